@@ -1,0 +1,207 @@
+/*
+ * smki.h -- C ABI of libsmki, an MI355X (gfx950) implementation of the
+ * per-scan map update of Bayesian spatial kernel smoothing for dense semantic
+ * mapping (S-BKI; Gan, Zhang, Grizzle, Eustice, Ghaffari, arXiv 1909.04631).
+ *
+ * Conventions for every entry point
+ *   - Pointers marked "device" are HIP device pointers (e.g. from a torch
+ *     tensor on cuda:N); "host" pointers are read before the call returns.
+ *     Arrays of points are row-major float32 [n][3] in metres, 4-byte aligned.
+ *   - The caller owns every input and output buffer and keeps it valid until
+ *     the map's stream has reached the enqueued work (the same rule as torch).
+ *   - A map owns its own device memory (block hash, concentration pool,
+ *     scratch); smki_destroy_map frees it.  A map is not thread-safe: use one
+ *     host thread and one stream per map.
+ *   - No exception or abort crosses the ABI.  Errors detectable on the host
+ *     return immediately, enqueue nothing and leave the map unchanged.
+ *     Errors found by device validation (bad label, non-finite coordinate,
+ *     voxel index outside [-2^20, 2^20), more than 2^20 free samples on one
+ *     beam) are detected before any concentration is written, so a failed
+ *     insert also leaves the map unchanged.
+ *   - Every real parameter is binary32; labels are int32 class ids in
+ *     [0, K), or -1 for "drop this hit and its beam".
+ */
+#ifndef SMKI_H
+#define SMKI_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t smki_status;
+#define SMKI_OK 0
+#define SMKI_E_INVALID_ARG (-1)  /* bad pointer, size or parameter (host-checked) */
+#define SMKI_E_OOM (-2)          /* device allocation failed */
+#define SMKI_E_CAPACITY (-3)     /* a configured limit would be exceeded */
+#define SMKI_E_DEVICE (-4)       /* HIP runtime error */
+#define SMKI_E_BAD_INPUT (-5)    /* device-detected bad label or non-finite coordinate */
+#define SMKI_E_RANGE (-6)        /* voxel index outside [-2^20, 2^20) or beam too long */
+
+typedef struct smki_map smki_map;
+
+/* Optional tuning; pass NULL for defaults. */
+typedef struct smki_options {
+  int64_t initial_blocks;   /* initial pool capacity in blocks (0: 4096); grows on demand */
+  int32_t unit_budget;      /* candidate rows per lane per gather work unit (0: 2048) */
+  float part_fraction;      /* expected largest per-lane share of a staged box (0: 0.5) */
+} smki_options;
+
+/* Counters of the last insert (smki_last_scan_stats). */
+typedef struct smki_scan_stats {
+  int64_t n_hits;           /* labelled hits kept (label != -1) */
+  int64_t n_free;           /* free-space samples generated */
+  int64_t n_point_blocks;   /* map blocks holding at least one training row */
+  int64_t n_target_blocks;  /* blocks examined (within reach of a row block) */
+  int64_t n_new_blocks;     /* blocks allocated by this insert */
+  int64_t n_units;          /* gather work units launched */
+  int64_t n_updated_voxels; /* voxels with at least one row within l */
+  int64_t n_pairs;          /* (voxel, row) pairs with distance < l */
+} smki_scan_stats;
+
+const char *smki_status_string(smki_status s);
+
+/*
+ * Create an empty semantic map (Sec. III-IV of the paper).
+ *   res         voxel edge in metres (> 0); voxel (i,j,k) has its centroid at
+ *               ((i+1/2) res, (j+1/2) res, (k+1/2) res) -- the query points of
+ *               Eq. (7) are the grid centroids (Sec. IV, after Eq. (8)).
+ *   block_size  voxels per block edge: 4, 8, 16 or 32 (blocks group the grid
+ *               as in Sec. IV; allocation granularity).
+ *   l, sigma0   length-scale (> 0) and scale (> 0) of the sparse kernel, Eq. (8).
+ *   K           classes (2..255), free class included.
+ *   alpha0      Dirichlet prior concentration of every class (> 0), Sec. III.
+ *   free_class  class id given to free-space samples, in [0, K).
+ * Every voxel of a new map holds alpha0 in every class.
+ */
+smki_status smki_create_map(float res, int32_t block_size, float l, float sigma0, int32_t K,
+                            float alpha0, int32_t free_class, const smki_options *opt,
+                            smki_map **out);
+smki_status smki_destroy_map(smki_map *m);
+
+/* Stream (a hipStream_t, e.g. torch.cuda.current_stream().cuda_stream) on which
+ * the map enqueues its work; NULL = the default stream. */
+smki_status smki_set_stream(smki_map *m, void *hip_stream);
+
+/*
+ * Insert one labelled scan: Eq. (7) with the kernel of Eq. (8), applied at
+ * every voxel centroid and added to the map (the recursive update of Sec. IV).
+ * The training rows are the hits with label != -1 and, for each of them, the
+ * free-space samples interpolated along the beam from origin to hit (Sec. III):
+ * positions origin + ((j*free_step)/L) * (hit - origin), j = 1..ceil(L/free_step)-1,
+ * binary32 arithmetic, labelled free_class.  free_step <= 0: no free samples.
+ *   xyz    device float32 [n][3], label device int32 [n], origin host float32 [3].
+ * Returns after the work is enqueued (it synchronises the stream internally
+ * to size its launches).
+ */
+smki_status smki_insert_scan(smki_map *m, const float *xyz, const int32_t *label, int64_t n,
+                             const float *origin, float free_step);
+
+/*
+ * Insert S scans in one pass: rows offsets[s]..offsets[s+1]-1 of xyz/label
+ * belong to scan s, whose beams start at origins[s].  Eq. (7) is additive over
+ * training rows, so the result equals S sequential inserts up to float32
+ * summation order.  offsets host int64 [S+1] (offsets[0] = 0, non-decreasing),
+ * origins host float32 [S][3].
+ */
+smki_status smki_insert_scans(smki_map *m, const float *xyz, const int32_t *label,
+                              const int64_t *offsets, const float *origins, int32_t S,
+                              float free_step);
+
+/*
+ * Read voxels (Sec. III, Eq. (3)-(4), reused for S-BKI in Sec. IV):
+ *   ijk    device int32 [M][3] voxel indices;
+ *   alpha  device float32 [M][K]  concentrations (nullable);
+ *   mean   device float32 [M][K]  alpha / sum(alpha)                (nullable);
+ *   var    device float32 [M][K]  mean (1 - mean) / (sum(alpha)+1)  (nullable);
+ *   label  device int32 [M]       argmax of alpha, lowest index on ties (nullable);
+ *   p_occ  device float32 [M]     1 - mean of the free class (nullable).
+ * Voxels never updated read alpha0 in every class.
+ */
+smki_status smki_query(smki_map *m, const int32_t *ijk, int64_t M, float *alpha, float *mean,
+                       float *var, int32_t *label, float *p_occ);
+
+/* Number of allocated blocks. */
+smki_status smki_num_blocks(smki_map *m, int64_t *n_blocks);
+
+/*
+ * Checkpoint: *n_blocks (host) receives the number of blocks.  If block_ijk
+ * and alpha are non-NULL and capacity >= *n_blocks, writes the blocks in
+ * ascending key order: block_ijk device int32 [n][3] (block coordinates:
+ * voxel index >> log2(block_size)), alpha device float32 [n][K][B^3]
+ * (class-major; voxel (x,y,z) of a block at (x*B + y)*B + z).
+ */
+smki_status smki_export(smki_map *m, int64_t capacity, int64_t *n_blocks, int32_t *block_ijk,
+                        float *alpha);
+/* Replace the map's contents with n exported blocks (device arrays as above). */
+smki_status smki_import(smki_map *m, int64_t n, const int32_t *block_ijk, const float *alpha);
+
+smki_status smki_last_scan_stats(smki_map *m, smki_scan_stats *out);
+
+/* Wait for the map's stream; returns a deferred device error if one occurred. */
+smki_status smki_sync(smki_map *m);
+
+/*
+ * The free-space samples of one scan alone (Sec. III; same binary32 recipe as
+ * the insert).  Two calls: with out_xyz == NULL only *n_out (host) is set;
+ * then out_xyz device float32 [n_out][3] and out_parent device int64 [n_out]
+ * (nullable; index of the source hit) are filled in (hit, j) order.
+ *   K is used to validate the labels.  Synchronous on hip_stream.
+ */
+smki_status smki_free_samples(const float *xyz, const int32_t *label, int64_t n, const float *origin,
+                              float free_step, int32_t K, void *hip_stream, int64_t *n_out,
+                              float *out_xyz, int64_t *out_parent);
+
+/*
+ * The voxel-cell table of a set of rows (the bucketing step of the update):
+ * rows are keyed by voxel index floor(x / res) (binary32 division) and radix
+ * sorted.  Two calls: with cell_keys == NULL only *n_cells (host) is set; then
+ *   cell_keys  device uint64 [n_cells] packed voxel index
+ *              ((i + 2^20) << 42) | ((j + 2^20) << 21) | (k + 2^20),
+ *   cell_start device int32 [n_cells], cell_count device int32 [n_cells],
+ *   order      device int32 [n] (nullable): row ids in sorted order, so rows
+ *              order[cell_start[c] .. cell_start[c]+cell_count[c]-1] are cell c's.
+ * Cells appear in the library's sort order (block-major).  Synchronous.
+ */
+smki_status smki_bucket_cells(const float *xyz, int64_t n, float res, int32_t block_size,
+                              void *hip_stream, int64_t *n_cells, uint64_t *cell_keys,
+                              int32_t *cell_start, int32_t *cell_count, int32_t *order);
+
+/*
+ * Differentiable form (an extension; the paper tunes l and sigma0 by hand and
+ * names hyper-parameter optimisation as future work, Sec. VI).  Stateless:
+ * explicit training rows (hits and free samples) and labelled query points.
+ *   alpha_q[h][k] = alpha0 + sum_t sigma0 f(|x_t - x_h| / l) [y_t = k]   (Eq. (7)-(8))
+ *   loss = -(1/H) sum_h log(alpha_q[h][y_h] / sum_k alpha_q[h][k])
+ *   train_xyz device float32 [n_train][3], train_label device int32 [n_train],
+ *   query_xyz device float32 [n_query][3], query_label device int32 [n_query],
+ *   loss device float32 [1]; alpha_q device float32 [n_query][K] (nullable).
+ * workspace: device scratch of smki_loss_workspace_bytes(...) bytes, or NULL to
+ * let the call allocate its own.
+ */
+size_t smki_loss_workspace_bytes(int64_t n_train, int64_t n_query, int32_t K);
+smki_status smki_loss_forward(const float *train_xyz, const int32_t *train_label, int64_t n_train,
+                              const float *query_xyz, const int32_t *query_label, int64_t n_query,
+                              float l, float sigma0, float alpha0, int32_t K, void *hip_stream,
+                              void *workspace, size_t workspace_bytes, float *loss,
+                              float *alpha_q);
+/*
+ * Gradient of loss * grad_loss (grad_loss device float32 [1]) with respect to
+ * l, sigma0 (device float32 [1] each, nullable), the training coordinates
+ * (device float32 [n_train][3], nullable) and the query coordinates (device
+ * float32 [n_query][3], nullable).  alpha_q is the forward's output.  Kernel
+ * weights are recomputed, not stored.
+ */
+smki_status smki_loss_backward(const float *train_xyz, const int32_t *train_label, int64_t n_train,
+                               const float *query_xyz, const int32_t *query_label, int64_t n_query,
+                               float l, float sigma0, float alpha0, int32_t K, void *hip_stream,
+                               void *workspace, size_t workspace_bytes, const float *alpha_q,
+                               const float *grad_loss, float *grad_l, float *grad_sigma0,
+                               float *grad_train_xyz, float *grad_query_xyz);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SMKI_H */

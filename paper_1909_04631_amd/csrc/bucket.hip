@@ -1,0 +1,540 @@
+// Training-set construction and spatial bucketing.
+//
+// Rows of the training set (Sec. III and IV of Gan et al., arXiv 1909.04631):
+// every labelled hit, plus free-space points interpolated along its beam and
+// labelled with the free class.  The free-sample positions and the voxel index
+// of every row follow a binary32 contract (each operation rounded once, no
+// fused multiply-add), so that cell keys are bit-reproducible.
+//
+// Bucketing: rows are keyed by (map block, voxel inside the block) over a dense
+// grid of the blocks that the scan's bounding box covers, radix sorted, and
+// stored as float4 records (x, y, z relative to the exact centre of the row's
+// own block; label bits).  A per-block prefix table of B^3 + 1 entries maps
+// any voxel range inside a block to a contiguous row range.
+#include "smki_bucket.h"
+
+#pragma clang fp contract(off)
+
+// Correctly rounded binary32 division and square root: the double-precision
+// result rounded once to binary32 is the correctly rounded binary32 result
+// (53 >= 2*24 + 2, so the double rounding is innocuous).
+__device__ __forceinline__ float div_rn(float a, float b) { return (float)((double)a / (double)b); }
+__device__ __forceinline__ float sqrt_rn(float a) { return (float)sqrt((double)a); }
+
+// ---------------------------------------------------------------------------
+// binary32 beam arithmetic (reading of the paper's free-space sampling):
+//   v = p - o ; L = sqrt((vx*vx + vy*vy) + vz*vz) ; n = ceil(L/s) - 1 ;
+//   q_j = o + (((float)j * s) / L) * v
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ float beam_len(float px, float py, float pz, float ox, float oy,
+                                          float oz, float* vx, float* vy, float* vz) {
+  *vx = px - ox;
+  *vy = py - oy;
+  *vz = pz - oz;
+  const float xx = *vx * *vx, yy = *vy * *vy, zz = *vz * *vz;
+  const float a = xx + yy;
+  const float L2 = a + zz;
+  return sqrt_rn(L2);
+}
+
+__device__ __forceinline__ int voxel_index(float x, float res, int32_t* out) {
+  float q = div_rn(x, res);
+  float f = floorf(q);
+  if (!(f >= -(float)SMKI_COORD_LIM && f < (float)SMKI_COORD_LIM)) return 0;
+  *out = (int32_t)f;
+  return 1;
+}
+
+__device__ __forceinline__ bool finite3(float x, float y, float z) {
+  return isfinite(x) && isfinite(y) && isfinite(z);
+}
+
+// Which scan a hit belongs to (scan_off has S+1 entries, S >= 1).
+__device__ __forceinline__ int32_t scan_of(const int64_t* scan_off, int32_t S, int64_t i) {
+  int32_t lo = 0, hi = S - 1;
+  while (lo < hi) {
+    int32_t mid = (lo + hi + 1) >> 1;
+    if (scan_off[mid] <= i) lo = mid; else hi = mid - 1;
+  }
+  return lo;
+}
+
+// Per hit: validation, kept flag, number of free samples, voxel bounding box.
+__global__ void k_count(const float* __restrict__ xyz, const int32_t* __restrict__ label,
+                        int64_t n, const int64_t* __restrict__ scan_off,
+                        const float* __restrict__ origins, int32_t S, float res, float step,
+                        int32_t K, int64_t* __restrict__ nfree, int32_t* __restrict__ kept,
+                        int32_t* __restrict__ bbox, uint32_t* __restrict__ err) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  int32_t lo[3] = {INT32_MAX, INT32_MAX, INT32_MAX};
+  int32_t hi[3] = {INT32_MIN, INT32_MIN, INT32_MIN};
+  if (i < n) {
+    const int32_t y = label[i];
+    const float px = xyz[3 * i], py = xyz[3 * i + 1], pz = xyz[3 * i + 2];
+    uint32_t e = 0;
+    int64_t c = 0;
+    int32_t k = 0;
+    if (y < -1 || y >= K) e |= DEVERR_LABEL;
+    if (!finite3(px, py, pz)) e |= DEVERR_NONFINITE;
+    if (e == 0 && y != -1) {
+      k = 1;
+      int32_t v[3];
+      if (!voxel_index(px, res, &v[0]) || !voxel_index(py, res, &v[1]) ||
+          !voxel_index(pz, res, &v[2])) {
+        e |= DEVERR_RANGE;
+      } else {
+        for (int a = 0; a < 3; ++a) { lo[a] = v[a]; hi[a] = v[a]; }
+      }
+      if (step > 0.0f) {
+        const int32_t s = scan_of(scan_off, S, i);
+        const float ox = origins[3 * s], oy = origins[3 * s + 1], oz = origins[3 * s + 2];
+        float vx, vy, vz;
+        const float L = beam_len(px, py, pz, ox, oy, oz, &vx, &vy, &vz);
+        if (L > 0.0f) {
+          const float cf = ceilf(div_rn(L, step));
+          if (!(cf - 1.0f <= (float)SMKI_MAX_SAMPLES_PER_RAY)) e |= DEVERR_RAY;
+          else c = (int64_t)cf - 1;
+        }
+        if (c > 0) {
+          int32_t vo[3];
+          if (voxel_index(ox, res, &vo[0]) && voxel_index(oy, res, &vo[1]) &&
+              voxel_index(oz, res, &vo[2])) {
+            for (int a = 0; a < 3; ++a) { lo[a] = min(lo[a], vo[a]); hi[a] = max(hi[a], vo[a]); }
+          } else {
+            e |= DEVERR_RANGE;
+          }
+        }
+      }
+    }
+    nfree[i] = e ? 0 : c;
+    kept[i] = e ? 0 : k;
+    if (e) atomicOr(err, e);
+  }
+  // workgroup reduction of the bounding box, then one atomic per workgroup
+  __shared__ int32_t slo[3][256], shi[3][256];
+  for (int a = 0; a < 3; ++a) { slo[a][threadIdx.x] = lo[a]; shi[a][threadIdx.x] = hi[a]; }
+  __syncthreads();
+  for (int o = blockDim.x / 2; o > 0; o >>= 1) {
+    if ((int)threadIdx.x < o) {
+      for (int a = 0; a < 3; ++a) {
+        slo[a][threadIdx.x] = min(slo[a][threadIdx.x], slo[a][threadIdx.x + o]);
+        shi[a][threadIdx.x] = max(shi[a][threadIdx.x], shi[a][threadIdx.x + o]);
+      }
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    for (int a = 0; a < 3; ++a) {
+      if (slo[a][0] != INT32_MAX) atomicMin(&bbox[a], slo[a][0]);
+      if (shi[a][0] != INT32_MIN) atomicMax(&bbox[3 + a], shi[a][0]);
+    }
+  }
+}
+
+__device__ __forceinline__ void block_of(const BucketGeom& g, const int32_t v[3], int32_t b[3],
+                                         int32_t l[3]) {
+  for (int a = 0; a < 3; ++a) {
+    b[a] = v[a] >> g.log2B;             // floor division (arithmetic shift)
+    l[a] = v[a] - b[a] * g.B;
+  }
+}
+
+template <typename KeyT>
+__device__ __forceinline__ KeyT make_key(const BucketGeom& g, const int32_t b[3],
+                                         const int32_t l[3]) {
+  const int64_t lin = ((int64_t)(b[0] - g.blo[0]) * g.nb[1] + (b[1] - g.blo[1])) * g.nb[2] +
+                      (b[2] - g.blo[2]);
+  const int64_t loc = ((int64_t)l[0] << (2 * g.log2B)) | ((int64_t)l[1] << g.log2B) | l[2];
+  return (KeyT)(((uint64_t)lin << (3 * g.log2B)) | (uint64_t)loc);
+}
+
+// Record of a row: coordinates relative to the exact centre ((b + 1/2) B res) of
+// its own block, computed in double and rounded once; label bits in .w.
+__device__ __forceinline__ float4 make_record(const BucketGeom& g, float x, float y, float z,
+                                              const int32_t b[3], int32_t label) {
+  const double r = (double)g.res, hb = 0.5 * (double)g.B;
+  float4 o;
+  o.x = (float)((double)x - ((double)(b[0] * g.B) + hb) * r);
+  o.y = (float)((double)y - ((double)(b[1] * g.B) + hb) * r);
+  o.z = (float)((double)z - ((double)(b[2] * g.B) + hb) * r);
+  o.w = __int_as_float(label);
+  return o;
+}
+
+__device__ __forceinline__ bool in_grid(const BucketGeom& g, const int32_t b[3]) {
+  return b[0] >= g.blo[0] && b[0] < g.blo[0] + g.nb[0] && b[1] >= g.blo[1] &&
+         b[1] < g.blo[1] + g.nb[1] && b[2] >= g.blo[2] && b[2] < g.blo[2] + g.nb[2];
+}
+
+// Kept hits -> (key, index) and records (unsorted).
+template <typename KeyT>
+__global__ void k_hit_keys(const float* __restrict__ xyz, const int32_t* __restrict__ label,
+                           int64_t n, const int32_t* __restrict__ kept,
+                           const int32_t* __restrict__ kpos, BucketGeom g,
+                           KeyT* __restrict__ keys, uint32_t* __restrict__ idx,
+                           float4* __restrict__ rec, uint32_t* __restrict__ err) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n || !kept[i]) return;
+  const float px = xyz[3 * i], py = xyz[3 * i + 1], pz = xyz[3 * i + 2];
+  int32_t v[3], b[3], l[3];
+  voxel_index(px, g.res, &v[0]);
+  voxel_index(py, g.res, &v[1]);
+  voxel_index(pz, g.res, &v[2]);
+  block_of(g, v, b, l);
+  const int32_t w = kpos[i];
+  if (!in_grid(g, b)) { atomicOr(err, DEVERR_RANGE); keys[w] = (KeyT)0; idx[w] = w; rec[w] = make_float4(0, 0, 0, 0); return; }
+  keys[w] = make_key<KeyT>(g, b, l);
+  idx[w] = (uint32_t)w;
+  rec[w] = make_record(g, px, py, pz, b, label[i]);
+}
+
+// Free sample f -> its beam (largest i with off[i] <= f), its position, key and record.
+template <typename KeyT>
+__global__ void k_free_keys(const float* __restrict__ xyz, int64_t n,
+                            const int64_t* __restrict__ off, int64_t nf,
+                            const int64_t* __restrict__ scan_off,
+                            const float* __restrict__ origins, int32_t S, float step,
+                            int32_t free_class, BucketGeom g, KeyT* __restrict__ keys,
+                            uint32_t* __restrict__ idx, float4* __restrict__ rec,
+                            int64_t* __restrict__ parent, uint32_t* __restrict__ err) {
+  const int64_t f = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (f >= nf) return;
+  int64_t lo = 0, hi = n - 1;
+  while (lo < hi) {
+    int64_t mid = (lo + hi + 1) >> 1;
+    if (off[mid] <= f) lo = mid; else hi = mid - 1;
+  }
+  const int64_t i = lo;
+  const int64_t j = f - off[i] + 1;
+  const int32_t s = scan_of(scan_off, S, i);
+  const float ox = origins[3 * s], oy = origins[3 * s + 1], oz = origins[3 * s + 2];
+  float vx, vy, vz;
+  const float L = beam_len(xyz[3 * i], xyz[3 * i + 1], xyz[3 * i + 2], ox, oy, oz, &vx, &vy, &vz);
+  const float t = (float)j * step;
+  const float w = div_rn(t, L);
+  const float mx = w * vx, my = w * vy, mz = w * vz;
+  const float qx = ox + mx, qy = oy + my, qz = oz + mz;
+  if (parent) parent[f] = i;
+  if (!keys) {  // positions only (the free-sample entry point)
+    rec[f] = make_float4(qx, qy, qz, 0.0f);
+    return;
+  }
+  int32_t v[3], b[3], l[3];
+  if (!voxel_index(qx, g.res, &v[0]) || !voxel_index(qy, g.res, &v[1]) ||
+      !voxel_index(qz, g.res, &v[2])) {
+    atomicOr(err, DEVERR_RANGE);
+    keys[f] = (KeyT)0; idx[f] = (uint32_t)f; rec[f] = make_float4(0, 0, 0, 0);
+    return;
+  }
+  block_of(g, v, b, l);
+  if (!in_grid(g, b)) { atomicOr(err, DEVERR_RANGE); keys[f] = (KeyT)0; idx[f] = (uint32_t)f; rec[f] = make_float4(0, 0, 0, 0); return; }
+  keys[f] = make_key<KeyT>(g, b, l);
+  idx[f] = (uint32_t)f;
+  rec[f] = make_record(g, qx, qy, qz, b, free_class);
+}
+
+// Explicit training rows (differentiable form, tests): keys and records.
+template <typename KeyT>
+__global__ void k_row_keys(const float* __restrict__ xyz, const int32_t* __restrict__ label,
+                           int64_t n, BucketGeom g, KeyT* __restrict__ keys,
+                           uint32_t* __restrict__ idx, float4* __restrict__ rec,
+                           uint32_t* __restrict__ err) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const float px = xyz[3 * i], py = xyz[3 * i + 1], pz = xyz[3 * i + 2];
+  int32_t v[3], b[3], l[3];
+  if (!finite3(px, py, pz) || !voxel_index(px, g.res, &v[0]) || !voxel_index(py, g.res, &v[1]) ||
+      !voxel_index(pz, g.res, &v[2])) {
+    atomicOr(err, DEVERR_RANGE);
+    keys[i] = (KeyT)0; idx[i] = (uint32_t)i; rec[i] = make_float4(0, 0, 0, 0);
+    return;
+  }
+  block_of(g, v, b, l);
+  if (!in_grid(g, b)) { atomicOr(err, DEVERR_RANGE); keys[i] = (KeyT)0; idx[i] = (uint32_t)i; rec[i] = make_float4(0, 0, 0, 0); return; }
+  keys[i] = make_key<KeyT>(g, b, l);
+  idx[i] = (uint32_t)i;
+  rec[i] = make_record(g, px, py, pz, b, label ? label[i] : 0);
+}
+
+// Sorted records: out[i] = rec[idx[i]].
+__global__ void k_permute_rec(const float4* __restrict__ rec, const uint32_t* __restrict__ idx,
+                              int64_t n, float4* __restrict__ out) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) out[i] = rec[idx[i]];
+}
+
+template <typename KeyT>
+__global__ void k_block_flags(const KeyT* __restrict__ keys, int64_t n, int shift,
+                              int32_t* __restrict__ flag) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  flag[i] = (i == 0 || (uint64_t)(keys[i] >> shift) != (uint64_t)(keys[i - 1] >> shift)) ? 1 : 0;
+}
+
+// After the scan of the block-start flags: slot of every row's block, the
+// dense grid -> slot index, each slot's grid position, and the prefix tables.
+template <typename KeyT>
+__global__ void k_block_tables(const KeyT* __restrict__ keys, int64_t n, int log2B3,
+                               const int32_t* __restrict__ flag, const int32_t* __restrict__ slot_excl,
+                               int32_t* __restrict__ dense, int32_t* __restrict__ slot_lin,
+                               int32_t* __restrict__ prefix) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int32_t B3 = 1 << log2B3;
+  const uint64_t key = (uint64_t)keys[i];
+  const int64_t blk = (int64_t)(key >> log2B3);
+  const int32_t c = (int32_t)(key & (uint64_t)(B3 - 1));
+  const int32_t slot = slot_excl[i] + flag[i] - 1;
+  int32_t* P = prefix + (int64_t)slot * (B3 + 1);
+  const bool first = flag[i] != 0;
+  if (first) {
+    dense[blk] = slot;
+    slot_lin[slot] = (int32_t)blk;
+  }
+  const int32_t prev = first ? -1 : (int32_t)((uint64_t)keys[i - 1] & (uint64_t)(B3 - 1));
+  if (c != prev)
+    for (int32_t cc = prev + 1; cc <= c; ++cc) P[cc] = (int32_t)i;
+  const bool last = (i == n - 1) || ((uint64_t)keys[i + 1] >> log2B3) != (uint64_t)blk;
+  if (last)
+    for (int32_t cc = c + 1; cc <= B3; ++cc) P[cc] = (int32_t)(i + 1);
+}
+
+__global__ void k_fill_i32(int32_t* p, int64_t n, int32_t v) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+
+// ---------------------------------------------------------------------------
+// host-side launchers
+// ---------------------------------------------------------------------------
+static inline unsigned nblk(int64_t n, int t) { return (unsigned)ceil_div_i64(n > 0 ? n : 1, t); }
+
+hipError_t launch_count(const float* xyz, const int32_t* label, int64_t n, const int64_t* scan_off,
+                        const float* origins, int32_t S, float res, float step, int32_t K,
+                        int64_t* nfree, int32_t* kept, int32_t* bbox, uint32_t* err,
+                        hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_count, dim3(nblk(n, 256)), dim3(256), 0, st, xyz, label, n, scan_off,
+                     origins, S, res, step, K, nfree, kept, bbox, err);
+  return hipGetLastError();
+}
+
+hipError_t launch_fill_i32(int32_t* p, int64_t n, int32_t v, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_fill_i32, dim3(nblk(n, 256)), dim3(256), 0, st, p, n, v);
+  return hipGetLastError();
+}
+
+hipError_t launch_free_positions(const float* xyz, int64_t n, const int64_t* off, int64_t nf,
+                                 const int64_t* scan_off, const float* origins, int32_t S,
+                                 float step, float4* out, int64_t* parent, hipStream_t st) {
+  if (nf <= 0) return hipSuccess;
+  BucketGeom g{};
+  hipLaunchKernelGGL(k_free_keys<uint32_t>, dim3(nblk(nf, 256)), dim3(256), 0, st, xyz, n, off,
+                     nf, scan_off, origins, S, step, 0, g, (uint32_t*)nullptr,
+                     (uint32_t*)nullptr, out, parent, (uint32_t*)nullptr);
+  return hipGetLastError();
+}
+
+// Keys, sort, records and block tables of one point set.
+template <typename KeyT>
+static hipError_t finish_set(PointSet& ps, KeyT* keys, uint32_t* idx, KeyT* akeys, uint32_t* aidx,
+                             float4* rec_unsorted, const BucketGeom& g, int key_bits,
+                             BucketScratch& scr, hipStream_t st) {
+  const int64_t n = ps.n;
+  if (n <= 0) return hipSuccess;
+  hipError_t e;
+  if (sizeof(KeyT) == 4)
+    e = radix_sort_u32((uint32_t*)keys, idx, (uint32_t*)akeys, aidx, n, key_bits, scr.sort_tmp, st);
+  else
+    e = radix_sort_u64((uint64_t*)keys, idx, (uint64_t*)akeys, aidx, n, key_bits, scr.sort_tmp, st);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_permute_rec, dim3(nblk(n, 256)), dim3(256), 0, st, rec_unsorted, idx, n,
+                     ps.pts);
+  const int log2B3 = 3 * g.log2B;
+  hipLaunchKernelGGL(k_block_flags<KeyT>, dim3(nblk(n, 256)), dim3(256), 0, st, keys, n, log2B3,
+                     scr.flag);
+  e = scan_excl_i32(scr.flag, scr.slot_excl, n, ps.d_nslots, scr.scan_tmp, st);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_block_tables<KeyT>, dim3(nblk(n, 256)), dim3(256), 0, st, keys, n, log2B3,
+                     scr.flag, scr.slot_excl, ps.dense, ps.slot_lin, ps.prefix);
+  return hipGetLastError();
+}
+
+hipError_t bucket_hits(const float* xyz, const int32_t* label, int64_t n, const int32_t* kept,
+                       const int32_t* kpos, const BucketGeom& g, PointSet& ps, BucketScratch& scr,
+                       uint32_t* err, hipStream_t st) {
+  hipError_t e = launch_fill_i32(ps.dense, g.n_blocks, -1, st);
+  if (e != hipSuccess || ps.n <= 0) return e;
+  if (g.key_bits <= 32) {
+    hipLaunchKernelGGL(k_hit_keys<uint32_t>, dim3(nblk(n, 256)), dim3(256), 0, st, xyz, label, n,
+                       kept, kpos, g, (uint32_t*)scr.keys, scr.idx, scr.rec, err);
+    return finish_set<uint32_t>(ps, (uint32_t*)scr.keys, scr.idx, (uint32_t*)scr.akeys, scr.aidx,
+                                scr.rec, g, g.key_bits, scr, st);
+  }
+  hipLaunchKernelGGL(k_hit_keys<uint64_t>, dim3(nblk(n, 256)), dim3(256), 0, st, xyz, label, n,
+                     kept, kpos, g, (uint64_t*)scr.keys, scr.idx, scr.rec, err);
+  return finish_set<uint64_t>(ps, (uint64_t*)scr.keys, scr.idx, (uint64_t*)scr.akeys, scr.aidx,
+                              scr.rec, g, g.key_bits, scr, st);
+}
+
+hipError_t bucket_frees(const float* xyz, int64_t n, const int64_t* off, const int64_t* scan_off,
+                        const float* origins, int32_t S, float step, int32_t free_class,
+                        const BucketGeom& g, PointSet& ps, BucketScratch& scr, uint32_t* err,
+                        hipStream_t st) {
+  hipError_t e = launch_fill_i32(ps.dense, g.n_blocks, -1, st);
+  if (e != hipSuccess || ps.n <= 0) return e;
+  const int64_t nf = ps.n;
+  if (g.key_bits <= 32) {
+    hipLaunchKernelGGL(k_free_keys<uint32_t>, dim3(nblk(nf, 256)), dim3(256), 0, st, xyz, n, off,
+                       nf, scan_off, origins, S, step, free_class, g, (uint32_t*)scr.keys,
+                       scr.idx, scr.rec, (int64_t*)nullptr, err);
+    return finish_set<uint32_t>(ps, (uint32_t*)scr.keys, scr.idx, (uint32_t*)scr.akeys, scr.aidx,
+                                scr.rec, g, g.key_bits, scr, st);
+  }
+  hipLaunchKernelGGL(k_free_keys<uint64_t>, dim3(nblk(nf, 256)), dim3(256), 0, st, xyz, n, off,
+                     nf, scan_off, origins, S, step, free_class, g, (uint64_t*)scr.keys, scr.idx,
+                     scr.rec, (int64_t*)nullptr, err);
+  return finish_set<uint64_t>(ps, (uint64_t*)scr.keys, scr.idx, (uint64_t*)scr.akeys, scr.aidx,
+                              scr.rec, g, g.key_bits, scr, st);
+}
+
+hipError_t bucket_rows(const float* xyz, const int32_t* label, int64_t n, const BucketGeom& g,
+                       PointSet& ps, BucketScratch& scr, uint32_t* err, hipStream_t st) {
+  hipError_t e = launch_fill_i32(ps.dense, g.n_blocks, -1, st);
+  if (e != hipSuccess || n <= 0) return e;
+  if (g.key_bits <= 32) {
+    hipLaunchKernelGGL(k_row_keys<uint32_t>, dim3(nblk(n, 256)), dim3(256), 0, st, xyz, label, n,
+                       g, (uint32_t*)scr.keys, scr.idx, scr.rec, err);
+    return finish_set<uint32_t>(ps, (uint32_t*)scr.keys, scr.idx, (uint32_t*)scr.akeys, scr.aidx,
+                                scr.rec, g, g.key_bits, scr, st);
+  }
+  hipLaunchKernelGGL(k_row_keys<uint64_t>, dim3(nblk(n, 256)), dim3(256), 0, st, xyz, label, n, g,
+                     (uint64_t*)scr.keys, scr.idx, scr.rec, err);
+  return finish_set<uint64_t>(ps, (uint64_t*)scr.keys, scr.idx, (uint64_t*)scr.akeys, scr.aidx,
+                              scr.rec, g, g.key_bits, scr, st);
+}
+
+// ---------------------------------------------------------------------------
+// cell table of a sorted row set (the bucketing entry point)
+// ---------------------------------------------------------------------------
+template <typename KeyT>
+__global__ void k_cell_flags(const KeyT* __restrict__ keys, int64_t n, int32_t* __restrict__ flag) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) flag[i] = (i == 0 || keys[i] != keys[i - 1]) ? 1 : 0;
+}
+
+template <typename KeyT>
+__global__ void k_cell_starts(const KeyT* __restrict__ keys, int64_t n, BucketGeom g,
+                              const int32_t* __restrict__ flag, const int32_t* __restrict__ cpos,
+                              uint64_t* __restrict__ cell_keys, int32_t* __restrict__ cell_start) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n || !flag[i]) return;
+  const int l3 = 3 * g.log2B;
+  const uint64_t key = (uint64_t)keys[i];
+  int64_t lin = (int64_t)(key >> l3);
+  const int32_t loc = (int32_t)(key & ((1ull << l3) - 1));
+  const int32_t pz = (int32_t)(lin % g.nb[2]);
+  lin /= g.nb[2];
+  const int32_t py = (int32_t)(lin % g.nb[1]);
+  const int32_t px = (int32_t)(lin / g.nb[1]);
+  const int32_t B = g.B;
+  const int32_t vx = (px + g.blo[0]) * B + (loc >> (2 * g.log2B));
+  const int32_t vy = (py + g.blo[1]) * B + ((loc >> g.log2B) & (B - 1));
+  const int32_t vz = (pz + g.blo[2]) * B + (loc & (B - 1));
+  const int32_t c = cpos[i];
+  cell_start[c] = (int32_t)i;
+  cell_keys[c] = ((uint64_t)(int64_t)(vx + SMKI_COORD_LIM) << 42) |
+                 ((uint64_t)(int64_t)(vy + SMKI_COORD_LIM) << 21) |
+                 (uint64_t)(int64_t)(vz + SMKI_COORD_LIM);
+}
+
+__global__ void k_cell_counts(const int32_t* __restrict__ cell_start, int64_t ncells, int64_t n,
+                              int32_t* __restrict__ cell_count) {
+  const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= ncells) return;
+  const int64_t e = (c + 1 < ncells) ? cell_start[c + 1] : n;
+  cell_count[c] = (int32_t)(e - cell_start[c]);
+}
+
+__global__ void k_copy_order(const uint32_t* __restrict__ idx, int64_t n, int32_t* __restrict__ o) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) o[i] = (int32_t)idx[i];
+}
+
+// Sort rows by key (keys/idx filled by k_row_keys into scr), then count cells.
+hipError_t bucket_cells_sort(const float* xyz, int64_t n, const BucketGeom& g, BucketScratch& scr,
+                             uint32_t* err, int32_t* d_ncells, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  hipError_t e;
+  if (g.key_bits <= 32) {
+    hipLaunchKernelGGL(k_row_keys<uint32_t>, dim3(nblk(n, 256)), dim3(256), 0, st, xyz,
+                       (const int32_t*)nullptr, n, g, (uint32_t*)scr.keys, scr.idx, scr.rec, err);
+    e = radix_sort_u32((uint32_t*)scr.keys, scr.idx, (uint32_t*)scr.akeys, scr.aidx, n, g.key_bits,
+                       scr.sort_tmp, st);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_cell_flags<uint32_t>, dim3(nblk(n, 256)), dim3(256), 0, st,
+                       (const uint32_t*)scr.keys, n, scr.flag);
+  } else {
+    hipLaunchKernelGGL(k_row_keys<uint64_t>, dim3(nblk(n, 256)), dim3(256), 0, st, xyz,
+                       (const int32_t*)nullptr, n, g, (uint64_t*)scr.keys, scr.idx, scr.rec, err);
+    e = radix_sort_u64((uint64_t*)scr.keys, scr.idx, (uint64_t*)scr.akeys, scr.aidx, n, g.key_bits,
+                       scr.sort_tmp, st);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_cell_flags<uint64_t>, dim3(nblk(n, 256)), dim3(256), 0, st,
+                       (const uint64_t*)scr.keys, n, scr.flag);
+  }
+  return scan_excl_i32(scr.flag, scr.slot_excl, n, d_ncells, scr.scan_tmp, st);
+}
+
+hipError_t bucket_cells_table(int64_t n, int64_t ncells, const BucketGeom& g, BucketScratch& scr,
+                              uint64_t* cell_keys, int32_t* cell_start, int32_t* cell_count,
+                              int32_t* order, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  if (g.key_bits <= 32)
+    hipLaunchKernelGGL(k_cell_starts<uint32_t>, dim3(nblk(n, 256)), dim3(256), 0, st,
+                       (const uint32_t*)scr.keys, n, g, scr.flag, scr.slot_excl, cell_keys,
+                       cell_start);
+  else
+    hipLaunchKernelGGL(k_cell_starts<uint64_t>, dim3(nblk(n, 256)), dim3(256), 0, st,
+                       (const uint64_t*)scr.keys, n, g, scr.flag, scr.slot_excl, cell_keys,
+                       cell_start);
+  hipLaunchKernelGGL(k_cell_counts, dim3(nblk(ncells, 256)), dim3(256), 0, st, cell_start, ncells,
+                     n, cell_count);
+  if (order)
+    hipLaunchKernelGGL(k_copy_order, dim3(nblk(n, 256)), dim3(256), 0, st, scr.idx, n, order);
+  return hipGetLastError();
+}
+
+__global__ void k_free_xyz(const float* __restrict__ xyz, int64_t n, const int64_t* __restrict__ off,
+                           int64_t nf, const float* __restrict__ origin, float step,
+                           float* __restrict__ out, int64_t* __restrict__ parent) {
+  const int64_t f = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (f >= nf) return;
+  int64_t lo = 0, hi = n - 1;
+  while (lo < hi) {
+    int64_t mid = (lo + hi + 1) >> 1;
+    if (off[mid] <= f) lo = mid; else hi = mid - 1;
+  }
+  const int64_t i = lo;
+  const int64_t j = f - off[i] + 1;
+  float vx, vy, vz;
+  const float L = beam_len(xyz[3 * i], xyz[3 * i + 1], xyz[3 * i + 2], origin[0], origin[1],
+                           origin[2], &vx, &vy, &vz);
+  const float t = (float)j * step;
+  const float w = div_rn(t, L);
+  const float mx = w * vx, my = w * vy, mz = w * vz;
+  out[3 * f] = origin[0] + mx;
+  out[3 * f + 1] = origin[1] + my;
+  out[3 * f + 2] = origin[2] + mz;
+  if (parent) parent[f] = i;
+}
+
+hipError_t launch_free_xyz(const float* xyz, int64_t n, const int64_t* off, int64_t nf,
+                           const float* origin_dev, float step, float* out, int64_t* parent,
+                           hipStream_t st) {
+  if (nf <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_free_xyz, dim3(nblk(nf, 256)), dim3(256), 0, st, xyz, n, off, nf,
+                     origin_dev, step, out, parent);
+  return hipGetLastError();
+}

@@ -1,0 +1,172 @@
+// Persistent map: block hash, readout (Eq. 3-4), export / import.
+#include "smki_gather.h"
+
+namespace {
+
+inline unsigned nblk(int64_t n, int t) { return (unsigned)ceil_div_i64(n > 0 ? n : 1, t); }
+
+__device__ __forceinline__ int32_t hash_find(const MapDev& m, uint64_t key) {
+  uint64_t h = smki_mix64(key) & (uint64_t)(m.hcap - 1);
+  for (int64_t probe = 0; probe < m.hcap; ++probe) {
+    const uint64_t k = m.hkeys[h];
+    if (k == key) return m.hvals[h];
+    if (k == ~0ull) return -1;
+    h = (h + 1) & (uint64_t)(m.hcap - 1);
+  }
+  return -1;
+}
+
+__global__ void k_hash_clear(uint64_t* keys, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) keys[i] = ~0ull;
+}
+
+// Readout of Eq. (3)-(4): mean alpha/S, variance mean(1-mean)/(S+1), label =
+// argmax (lowest index on ties), occupancy = 1 - mean of the free class.
+__global__ void k_query(MapDev m, const int32_t* __restrict__ ijk, int64_t M,
+                        float* __restrict__ alpha, float* __restrict__ mean,
+                        float* __restrict__ var, int32_t* __restrict__ label,
+                        float* __restrict__ p_occ, int32_t free_class) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= M) return;
+  const int32_t vx = ijk[3 * i], vy = ijk[3 * i + 1], vz = ijk[3 * i + 2];
+  const int32_t bx = vx >> m.log2B, by = vy >> m.log2B, bz = vz >> m.log2B;
+  const int32_t B = m.B, B3 = B * B * B;
+  int32_t slot = -1;
+  if (vx >= -(1 << 20) && vx < (1 << 20) && vy >= -(1 << 20) && vy < (1 << 20) &&
+      vz >= -(1 << 20) && vz < (1 << 20))
+    slot = hash_find(m, smki_block_key(bx, by, bz));
+  const float* A = slot >= 0 ? m.alpha + (int64_t)slot * m.K * B3 +
+                                   ((vx - bx * B) * B + (vy - by * B)) * B + (vz - bz * B)
+                             : nullptr;
+  // moments in double: 1 - mean cancels when one class dominates
+  double S = 0.0;
+  int32_t best = 0;
+  float bestv = -1.0f;
+  for (int k = 0; k < m.K; ++k) {
+    const float a = A ? A[(int64_t)k * B3] : m.alpha0;
+    S += (double)a;
+    if (a > bestv) { bestv = a; best = k; }
+    if (alpha) alpha[i * m.K + k] = a;
+  }
+  if (mean || var) {
+    for (int k = 0; k < m.K; ++k) {
+      const double a = (double)(A ? A[(int64_t)k * B3] : m.alpha0);
+      const double e = a / S;
+      if (mean) mean[i * m.K + k] = (float)e;
+      if (var) var[i * m.K + k] = (float)(e * ((S - a) / S) / (S + 1.0));
+    }
+  }
+  if (label) label[i] = best;
+  if (p_occ) {
+    const double af = (double)(A ? A[(int64_t)free_class * B3] : m.alpha0);
+    p_occ[i] = (float)((S - af) / S);
+  }
+}
+
+__global__ void k_hash_insert_slots(MapDev m, int64_t slot0, int64_t n, uint32_t* err) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int32_t slot = (int32_t)(slot0 + i);
+  const uint64_t key = m.bkeys[slot];
+  uint64_t h = smki_mix64(key) & (uint64_t)(m.hcap - 1);
+  for (int64_t probe = 0; probe < m.hcap; ++probe) {
+    const unsigned long long old =
+        atomicCAS((unsigned long long*)&m.hkeys[h], ~0ull, (unsigned long long)key);
+    if (old == ~0ull || old == key) {
+      m.hvals[h] = slot;
+      return;
+    }
+    h = (h + 1) & (uint64_t)(m.hcap - 1);
+  }
+  atomicOr(err, DEVERR_HASH);
+}
+
+// out block b <- pool slot order[b]
+__global__ void k_gather_blocks(MapDev m, const uint32_t* __restrict__ order, int64_t n,
+                                float* __restrict__ out) {
+  const int64_t per = (int64_t)m.K * m.B * m.B * m.B;
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n * per) return;
+  const int64_t b = i / per, r = i % per;
+  out[i] = m.alpha[(int64_t)order[b] * per + r];
+}
+
+__global__ void k_keys_to_ijk(const uint64_t* __restrict__ keys, int64_t n, int32_t* ijk) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const uint64_t k = keys[i];
+  ijk[3 * i] = (int32_t)((k >> 42) & 0x1FFFFF) - (1 << 20);
+  ijk[3 * i + 1] = (int32_t)((k >> 21) & 0x1FFFFF) - (1 << 20);
+  ijk[3 * i + 2] = (int32_t)(k & 0x1FFFFF) - (1 << 20);
+}
+
+__global__ void k_ijk_to_keys(const int32_t* __restrict__ ijk, int64_t n, uint64_t* keys,
+                              uint32_t* err) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int32_t bx = ijk[3 * i], by = ijk[3 * i + 1], bz = ijk[3 * i + 2];
+  if (bx < -(1 << 20) || bx >= (1 << 20) || by < -(1 << 20) || by >= (1 << 20) ||
+      bz < -(1 << 20) || bz >= (1 << 20)) {
+    atomicOr(err, DEVERR_RANGE);
+    keys[i] = 0;
+    return;
+  }
+  keys[i] = smki_block_key(bx, by, bz);
+}
+
+__global__ void k_iota(uint32_t* p, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = (uint32_t)i;
+}
+
+}  // namespace
+
+hipError_t launch_query(const MapDev& m, const int32_t* ijk, int64_t M, float* alpha, float* mean,
+                        float* var, int32_t* label, float* p_occ, int32_t free_class,
+                        hipStream_t st) {
+  if (M <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_query, dim3(nblk(M, 256)), dim3(256), 0, st, m, ijk, M, alpha, mean, var,
+                     label, p_occ, free_class);
+  return hipGetLastError();
+}
+
+hipError_t launch_hash_clear(const MapDev& m, hipStream_t st) {
+  hipLaunchKernelGGL(k_hash_clear, dim3(nblk(m.hcap, 256)), dim3(256), 0, st, m.hkeys, m.hcap);
+  return hipGetLastError();
+}
+
+hipError_t launch_hash_insert_slots(const MapDev& m, int64_t slot0, int64_t n, uint32_t* err,
+                                    hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_hash_insert_slots, dim3(nblk(n, 256)), dim3(256), 0, st, m, slot0, n, err);
+  return hipGetLastError();
+}
+
+hipError_t launch_gather_blocks(const MapDev& m, const uint32_t* order, int64_t n,
+                                int32_t* /*unused*/, float* alpha_out, hipStream_t st) {
+  const int64_t tot = n * (int64_t)m.K * m.B * m.B * m.B;
+  if (tot <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_gather_blocks, dim3(nblk(tot, 256)), dim3(256), 0, st, m, order, n,
+                     alpha_out);
+  return hipGetLastError();
+}
+
+hipError_t launch_block_keys_to_ijk(const uint64_t* keys, int64_t n, int32_t* ijk, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_keys_to_ijk, dim3(nblk(n, 256)), dim3(256), 0, st, keys, n, ijk);
+  return hipGetLastError();
+}
+
+hipError_t launch_ijk_to_block_keys(const int32_t* ijk, int64_t n, uint64_t* keys, uint32_t* err,
+                                    hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_ijk_to_keys, dim3(nblk(n, 256)), dim3(256), 0, st, ijk, n, keys, err);
+  return hipGetLastError();
+}
+
+hipError_t launch_iota_u32(uint32_t* p, int64_t n, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_iota, dim3(nblk(n, 256)), dim3(256), 0, st, p, n);
+  return hipGetLastError();
+}

@@ -1,0 +1,147 @@
+// Stable least-significant-digit radix sort of (key, u32 value) pairs.
+//
+// One pass per digit of up to 8 bits: (1) per-tile digit histograms in LDS,
+// (2) an exclusive scan of the digit-major histogram table, (3) a stable
+// scatter in which each element's rank among equal digits inside its tile is
+// found with wave ballots (the peers of a lane are the lanes whose digit
+// agrees on every bit), then combined across the tile's waves and rounds in
+// element order.  Integer work only: bit-exact and run-to-run deterministic.
+#include "smki_internal.h"
+
+namespace {
+
+constexpr int RS_THREADS = 256;
+constexpr int RS_WAVES = RS_THREADS / SMKI_WAVE;
+constexpr int RS_ROUNDS = 16;
+constexpr int RS_TILE = RS_THREADS * RS_ROUNDS;  // 4096 elements per tile
+constexpr int RS_BINS = 256;
+
+template <typename K>
+__device__ __forceinline__ uint32_t digit_of(K key, int shift, uint32_t mask) {
+  return (uint32_t)(key >> shift) & mask;
+}
+
+template <typename K>
+__global__ void __launch_bounds__(RS_THREADS) k_hist(const K* __restrict__ keys, int64_t n,
+                                                     int shift, uint32_t mask, int64_t ntiles,
+                                                     uint32_t* __restrict__ hist) {
+  __shared__ uint32_t h[RS_BINS];
+  h[threadIdx.x] = 0;
+  __syncthreads();
+  const int64_t base = (int64_t)blockIdx.x * RS_TILE;
+#pragma unroll 4
+  for (int r = 0; r < RS_ROUNDS; ++r) {
+    int64_t i = base + (int64_t)r * RS_THREADS + threadIdx.x;
+    if (i < n) atomicAdd(&h[digit_of(keys[i], shift, mask)], 1u);
+  }
+  __syncthreads();
+  // digit-major layout: all tiles of digit 0, then digit 1, ...
+  hist[(int64_t)threadIdx.x * ntiles + blockIdx.x] = h[threadIdx.x];
+}
+
+template <typename K>
+__global__ void __launch_bounds__(RS_THREADS) k_scatter(const K* __restrict__ keys,
+                                                        const uint32_t* __restrict__ vals,
+                                                        K* __restrict__ okeys,
+                                                        uint32_t* __restrict__ ovals, int64_t n,
+                                                        int shift, uint32_t mask, int64_t ntiles,
+                                                        const uint32_t* __restrict__ offs) {
+  __shared__ uint32_t base_of[RS_BINS];
+  __shared__ uint32_t wcnt[RS_WAVES][RS_BINS];
+  const int tid = threadIdx.x;
+  const int lane = tid & (SMKI_WAVE - 1);
+  const int w = tid / SMKI_WAVE;
+  base_of[tid] = offs[(int64_t)tid * ntiles + blockIdx.x];
+#pragma unroll
+  for (int q = 0; q < RS_WAVES; ++q) wcnt[q][tid] = 0;
+  __syncthreads();
+  const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (SMKI_WAVE - lane));
+  const int64_t tile_base = (int64_t)blockIdx.x * RS_TILE;
+  for (int r = 0; r < RS_ROUNDS; ++r) {
+    const int64_t i = tile_base + (int64_t)r * RS_THREADS + tid;
+    const bool valid = i < n;
+    K key = valid ? keys[i] : (K)0;
+    uint32_t val = valid ? vals[i] : 0u;
+    uint32_t d = digit_of(key, shift, mask);
+    uint64_t peers = __ballot(valid);
+#pragma unroll
+    for (int b = 0; b < 8; ++b) {
+      const bool bit = (d >> b) & 1u;
+      const uint64_t m = __ballot(bit);
+      peers &= bit ? m : ~m;
+    }
+    const uint32_t rank = (uint32_t)__popcll(peers & lt_mask);
+    const uint32_t cnt = (uint32_t)__popcll(peers);
+    const bool leader = valid && ((peers & lt_mask) == 0);
+    if (leader) wcnt[w][d] = cnt;
+    __syncthreads();
+    if (valid) {
+      uint32_t pre = base_of[d];
+      for (int q = 0; q < w; ++q) pre += wcnt[q][d];
+      const uint32_t pos = pre + rank;
+      okeys[pos] = key;
+      ovals[pos] = val;
+    }
+    __syncthreads();
+    uint32_t add = 0;
+#pragma unroll
+    for (int q = 0; q < RS_WAVES; ++q) {
+      add += wcnt[q][tid];
+      wcnt[q][tid] = 0;
+    }
+    base_of[tid] += add;
+    __syncthreads();
+  }
+}
+
+template <typename K>
+hipError_t sort_impl(K* keys, uint32_t* vals, K* akeys, uint32_t* avals, int64_t n, int bits,
+                     void* tmp, hipStream_t st) {
+  if (n <= 1 || bits <= 0) return hipSuccess;
+  const int64_t ntiles = ceil_div_i64(n, RS_TILE);
+  uint32_t* hist = (uint32_t*)tmp;
+  void* scan_tmp = (void*)(hist + RS_BINS * ntiles + 64);
+  const int passes = (bits + 7) / 8;
+  const int dbits = (bits + passes - 1) / passes;
+  const uint32_t mask = (1u << dbits) - 1u;
+  K* src_k = keys;
+  uint32_t* src_v = vals;
+  K* dst_k = akeys;
+  uint32_t* dst_v = avals;
+  for (int p = 0; p < passes; ++p) {
+    const int shift = p * dbits;
+    hipLaunchKernelGGL(k_hist<K>, dim3((unsigned)ntiles), dim3(RS_THREADS), 0, st, src_k, n,
+                       shift, mask, ntiles, hist);
+    hipError_t e = scan_excl_i32((const int32_t*)hist, (int32_t*)hist, RS_BINS * ntiles,
+                                 (int32_t*)nullptr, scan_tmp, st);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_scatter<K>, dim3((unsigned)ntiles), dim3(RS_THREADS), 0, st, src_k,
+                       src_v, dst_k, dst_v, n, shift, mask, ntiles, (const uint32_t*)hist);
+    K* tk = src_k; src_k = dst_k; dst_k = tk;
+    uint32_t* tv = src_v; src_v = dst_v; dst_v = tv;
+  }
+  if (src_k != keys) {
+    hipError_t e = hipMemcpyAsync(keys, src_k, sizeof(K) * n, hipMemcpyDeviceToDevice, st);
+    if (e != hipSuccess) return e;
+    e = hipMemcpyAsync(vals, src_v, sizeof(uint32_t) * n, hipMemcpyDeviceToDevice, st);
+    if (e != hipSuccess) return e;
+  }
+  return hipGetLastError();
+}
+
+}  // namespace
+
+size_t radix_tmp_bytes(int64_t n) {
+  const int64_t ntiles = ceil_div_i64(n > 0 ? n : 1, RS_TILE);
+  return sizeof(uint32_t) * (RS_BINS * ntiles + 64) + scan_tmp_bytes(RS_BINS * ntiles) + 256;
+}
+
+hipError_t radix_sort_u32(uint32_t* keys, uint32_t* vals, uint32_t* ak, uint32_t* av, int64_t n,
+                          int bits, void* tmp, hipStream_t st) {
+  return sort_impl<uint32_t>(keys, vals, ak, av, n, bits, tmp, st);
+}
+
+hipError_t radix_sort_u64(uint64_t* keys, uint32_t* vals, uint64_t* ak, uint32_t* av, int64_t n,
+                          int bits, void* tmp, hipStream_t st) {
+  return sort_impl<uint64_t>(keys, vals, ak, av, n, bits, tmp, st);
+}

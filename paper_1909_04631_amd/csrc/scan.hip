@@ -1,0 +1,127 @@
+// Device-wide exclusive prefix sum (reduce, scan the tile sums, scan again).
+// Deterministic: integer sums only.
+#include "smki_internal.h"
+
+namespace {
+
+constexpr int SCAN_THREADS = 256;
+constexpr int SCAN_ITEMS = 8;
+constexpr int SCAN_TILE = SCAN_THREADS * SCAN_ITEMS;
+
+template <typename T>
+__device__ __forceinline__ T wave_incl_scan(T v) {
+  const int lane = threadIdx.x & (SMKI_WAVE - 1);
+#pragma unroll
+  for (int o = 1; o < SMKI_WAVE; o <<= 1) {
+    T u = __shfl_up(v, o, SMKI_WAVE);
+    if (lane >= o) v += u;
+  }
+  return v;
+}
+
+// exclusive scan of one value per thread across the workgroup; returns the
+// exclusive prefix, *block_total the sum.
+template <typename T>
+__device__ __forceinline__ T block_excl_scan(T v, T* block_total) {
+  __shared__ T wsum[SCAN_THREADS / SMKI_WAVE];
+  const int lane = threadIdx.x & (SMKI_WAVE - 1);
+  const int w = threadIdx.x / SMKI_WAVE;
+  T inc = wave_incl_scan(v);
+  if (lane == SMKI_WAVE - 1) wsum[w] = inc;
+  __syncthreads();
+  T off = 0, tot = 0;
+#pragma unroll
+  for (int i = 0; i < SCAN_THREADS / SMKI_WAVE; ++i) {
+    if (i < w) off += wsum[i];
+    tot += wsum[i];
+  }
+  __syncthreads();
+  *block_total = tot;
+  return off + inc - v;
+}
+
+template <typename T>
+__global__ void __launch_bounds__(SCAN_THREADS) k_tile_sums(const T* __restrict__ in, int64_t n,
+                                                            T* __restrict__ sums) {
+  const int64_t base = (int64_t)blockIdx.x * SCAN_TILE + (int64_t)threadIdx.x * SCAN_ITEMS;
+  T s = 0;
+#pragma unroll
+  for (int i = 0; i < SCAN_ITEMS; ++i)
+    if (base + i < n) s += in[base + i];
+  T tot;
+  block_excl_scan(s, &tot);
+  if (threadIdx.x == 0) sums[blockIdx.x] = tot;
+}
+
+template <typename T>
+__global__ void __launch_bounds__(SCAN_THREADS) k_tile_scan(const T* in, T* out, int64_t n,
+                                                            const T* __restrict__ tile_off,
+                                                            T* total) {
+  const int64_t base = (int64_t)blockIdx.x * SCAN_TILE + (int64_t)threadIdx.x * SCAN_ITEMS;
+  T v[SCAN_ITEMS];
+  T s = 0;
+#pragma unroll
+  for (int i = 0; i < SCAN_ITEMS; ++i) {
+    v[i] = (base + i < n) ? in[base + i] : (T)0;
+    s += v[i];
+  }
+  T tot;
+  T run = block_excl_scan(s, &tot) + (tile_off ? tile_off[blockIdx.x] : (T)0);
+#pragma unroll
+  for (int i = 0; i < SCAN_ITEMS; ++i) {
+    if (base + i < n) out[base + i] = run;
+    run += v[i];
+  }
+  if (total && blockIdx.x == gridDim.x - 1 && threadIdx.x == SCAN_THREADS - 1) *total = run;
+}
+
+template <typename T>
+__global__ void k_zero_total(T* total) { *total = 0; }
+
+template <typename T>
+size_t tmp_elems(int64_t n) {
+  size_t e = 0;
+  int64_t m = n;
+  while (m > SCAN_TILE) {
+    m = ceil_div_i64(m, SCAN_TILE);
+    e += (size_t)m + 1;
+  }
+  return e + 1;
+}
+
+template <typename T>
+hipError_t scan_impl(const T* in, T* out, int64_t n, T* total, T* tmp, hipStream_t st) {
+  if (n <= 0) {
+    if (total) hipLaunchKernelGGL(k_zero_total<T>, dim3(1), dim3(1), 0, st, total);
+    return hipGetLastError();
+  }
+  const int64_t tiles = ceil_div_i64(n, SCAN_TILE);
+  if (tiles == 1) {
+    hipLaunchKernelGGL(k_tile_scan<T>, dim3(1), dim3(SCAN_THREADS), 0, st, in, out, n,
+                       (const T*)nullptr, total);
+    return hipGetLastError();
+  }
+  T* sums = tmp;
+  T* rest = tmp + tiles + 1;
+  hipLaunchKernelGGL(k_tile_sums<T>, dim3((unsigned)tiles), dim3(SCAN_THREADS), 0, st, in, n,
+                     sums);
+  hipError_t e = scan_impl<T>(sums, sums, tiles, (T*)nullptr, rest, st);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_tile_scan<T>, dim3((unsigned)tiles), dim3(SCAN_THREADS), 0, st, in, out,
+                     n, (const T*)sums, total);
+  return hipGetLastError();
+}
+
+}  // namespace
+
+size_t scan_tmp_bytes(int64_t n) { return tmp_elems<int64_t>(n) * sizeof(int64_t) + 256; }
+
+hipError_t scan_excl_i64(const int64_t* in, int64_t* out, int64_t n, int64_t* total, void* tmp,
+                         hipStream_t st) {
+  return scan_impl<int64_t>(in, out, n, total, (int64_t*)tmp, st);
+}
+
+hipError_t scan_excl_i32(const int32_t* in, int32_t* out, int64_t n, int32_t* total, void* tmp,
+                         hipStream_t st) {
+  return scan_impl<int32_t>(in, out, n, total, (int32_t*)tmp, st);
+}

@@ -1,0 +1,881 @@
+// Host side of the C ABI declared in include/smki.h: the map object, argument
+// validation, workspace management and the per-insert launch sequence.
+#include <math.h>
+#include <string.h>
+
+#include <algorithm>
+#include <vector>
+
+#include "../../include/smki.h"
+#include "smki_gather.h"
+
+// ---------------------------------------------------------------------------
+// kernel polynomial: f(1 - s) = s^5 Q(s^2) for the sparse kernel of Eq. (8);
+// Q below is a weighted least-squares degree-7 fit in u = s^2 on [0, 1] (relative
+// error 7e-9) to the series  Q(u) = sum_{n>=2} (-1)^n (2n-2) (2 pi)^(2n) u^(n-2) / (3 (2n+1)!),
+// obtained by expanding cos and sin of 2 pi (1 - s) in Eq. (8).  Highest degree first.
+// ---------------------------------------------------------------------------
+static const double kQ[SMKI_POLY_N] = {
+    -0.006484397132806161, 0.07136417330604423, -0.4518001709419727, 2.02382364154106,
+    -6.405593664147021,    13.387587273598974,  -16.27748266990142,  8.658585806723543};
+
+int32_t smki_hip_error(hipError_t e) {
+  return e == hipErrorOutOfMemory ? SMKI_E_OOM : SMKI_E_DEVICE;
+}
+
+namespace {
+
+constexpr size_t kAlign = 256;
+
+// A growable device region carved into aligned sub-buffers per phase.
+struct Arena {
+  char* base = nullptr;
+  size_t cap = 0;
+  size_t used = 0;
+  hipError_t reserve(size_t bytes) {
+    used = 0;
+    if (bytes <= cap) return hipSuccess;
+    if (base) {
+      // work queued on any stream may still read the old region
+      hipError_t e = hipDeviceSynchronize();
+      if (e != hipSuccess) return e;
+      e = hipFree(base);
+      if (e != hipSuccess) return e;
+      base = nullptr;
+      cap = 0;
+    }
+    const size_t want = bytes + bytes / 4 + (1 << 20);
+    hipError_t e = hipMalloc((void**)&base, want);
+    if (e != hipSuccess) return e;
+    cap = want;
+    return hipSuccess;
+  }
+  template <typename T>
+  T* take(size_t n) {
+    size_t off = (used + kAlign - 1) / kAlign * kAlign;
+    used = off + std::max<size_t>(n, 1) * sizeof(T);
+    return (T*)(base + off);
+  }
+  void release() {
+    if (base) (void)hipFree(base);
+    base = nullptr;
+    cap = used = 0;
+  }
+};
+
+// Size of a sequence of aligned sub-buffers.
+struct Sizer {
+  size_t total = 0;
+  template <typename T>
+  void add(size_t n) {
+    total = (total + kAlign - 1) / kAlign * kAlign + std::max<size_t>(n, 1) * sizeof(T);
+  }
+};
+
+int ilog2(int32_t x) {
+  int r = 0;
+  while ((1 << r) < x) ++r;
+  return r;
+}
+
+int bits_for(int64_t n) {  // bits to represent values 0..n-1
+  int b = 0;
+  while (b < 62 && (int64_t(1) << b) < n) ++b;
+  return b;
+}
+
+bool finite_pos(float x) { return isfinite(x) && x > 0.0f; }
+
+}  // namespace
+
+struct smki_map {
+  float res, l, sigma0, alpha0;
+  int32_t K, B, log2B, free_class;
+  int32_t budget;
+  float part_frac;
+  int device = 0;
+  hipStream_t stream = nullptr;
+  // persistent device state
+  MapDev dev{};
+  int64_t pool_cap = 0;
+  int64_t n_blocks = 0;
+  uint32_t* d_err = nullptr;
+  unsigned long long* d_stats = nullptr;
+  StencilCol* d_cols = nullptr;
+  float coef[SMKI_POLY_N];
+  // workspaces
+  Arena a_hits, a_sets, a_tgts, a_misc;
+  // pinned host staging
+  int64_t* h_pin = nullptr;
+  smki_scan_stats last{};
+  bool stats_pending = false;
+  int64_t pending_nk = 0, pending_nf = 0;
+};
+
+// ---------------------------------------------------------------------------
+// helpers
+// ---------------------------------------------------------------------------
+namespace {
+
+smki_status status_of_err(uint32_t e) {
+  if (e & (DEVERR_LABEL | DEVERR_NONFINITE)) return SMKI_E_BAD_INPUT;
+  if (e & (DEVERR_RANGE | DEVERR_RAY)) return SMKI_E_RANGE;
+  if (e & DEVERR_HASH) return SMKI_E_CAPACITY;
+  return SMKI_E_DEVICE;
+}
+
+// Voxel stencil for centroid queries: every voxel cell that can hold a point
+// within l (plus a rounding margin, in voxel units) of the centroid of voxel 0.
+struct Stencil {
+  int32_t R = 0, D = 0;
+  std::vector<StencilCol> cols;
+};
+
+Stencil make_stencil(double lv, double margin) {
+  Stencil s;
+  const double L = lv + margin;
+  s.R = (int32_t)ceil(lv + 0.5 + margin) - 1;
+  if (s.R < 0) s.R = 0;
+  s.D = SMKI_TILE + 2 * s.R;
+  for (int dx = -s.R; dx <= s.R; ++dx)
+    for (int dy = -s.R; dy <= s.R; ++dy) {
+      const double ax = std::max(0.0, fabs((double)dx) - 0.5);
+      const double ay = std::max(0.0, fabs((double)dy) - 0.5);
+      const double rho2 = ax * ax + ay * ay;
+      if (!(rho2 < L * L)) continue;
+      int32_t h = (int32_t)ceil(0.5 + sqrt(L * L - rho2)) - 1;
+      h = std::min(std::max(h, 0), s.R);
+      s.cols.push_back(StencilCol{dx, dy, h, 0});
+    }
+  return s;
+}
+
+hipError_t sync_read(smki_map* m, const void* dev, size_t bytes, void* host) {
+  hipError_t e = hipMemcpyAsync(host, dev, bytes, hipMemcpyDeviceToHost, m->stream);
+  if (e != hipSuccess) return e;
+  return hipStreamSynchronize(m->stream);
+}
+
+smki_status ensure_pool(smki_map* m, int64_t need) {
+  if (need <= m->pool_cap) return SMKI_OK;
+  int64_t cap = std::max<int64_t>(need, m->pool_cap * 2);
+  const size_t per = (size_t)m->K * m->B * m->B * m->B;
+  float* na = nullptr;
+  uint64_t* nk = nullptr;
+  SMKI_HIP_TRY(hipMalloc((void**)&na, sizeof(float) * per * cap));
+  hipError_t e = hipMalloc((void**)&nk, sizeof(uint64_t) * cap);
+  if (e != hipSuccess) {
+    (void)hipFree(na);
+    return smki_hip_error(e);
+  }
+  if (m->n_blocks > 0) {
+    SMKI_HIP_TRY(hipMemcpyAsync(na, m->dev.alpha, sizeof(float) * per * m->n_blocks,
+                                hipMemcpyDeviceToDevice, m->stream));
+    SMKI_HIP_TRY(hipMemcpyAsync(nk, m->dev.bkeys, sizeof(uint64_t) * m->n_blocks,
+                                hipMemcpyDeviceToDevice, m->stream));
+  }
+  SMKI_HIP_TRY(hipStreamSynchronize(m->stream));
+  if (m->dev.alpha) (void)hipFree(m->dev.alpha);
+  if (m->dev.bkeys) (void)hipFree(m->dev.bkeys);
+  m->dev.alpha = na;
+  m->dev.bkeys = nk;
+  m->pool_cap = cap;
+  return SMKI_OK;
+}
+
+// Keep the block hash at most half full; rebuild it from the slot keys on growth.
+smki_status ensure_hash(smki_map* m, int64_t blocks) {
+  if (m->dev.hcap >= 2 * blocks && m->dev.hkeys) return SMKI_OK;
+  int64_t cap = std::max<int64_t>(m->dev.hcap, 1 << 14);
+  while (cap < 2 * blocks) cap *= 2;
+  uint64_t* hk = nullptr;
+  int32_t* hv = nullptr;
+  SMKI_HIP_TRY(hipMalloc((void**)&hk, sizeof(uint64_t) * cap));
+  hipError_t e = hipMalloc((void**)&hv, sizeof(int32_t) * cap);
+  if (e != hipSuccess) {
+    (void)hipFree(hk);
+    return smki_hip_error(e);
+  }
+  SMKI_HIP_TRY(hipStreamSynchronize(m->stream));
+  if (m->dev.hkeys) (void)hipFree(m->dev.hkeys);
+  if (m->dev.hvals) (void)hipFree(m->dev.hvals);
+  m->dev.hkeys = hk;
+  m->dev.hvals = hv;
+  m->dev.hcap = cap;
+  SMKI_HIP_TRY(launch_hash_clear(m->dev, m->stream));
+  SMKI_HIP_TRY(launch_hash_insert_slots(m->dev, 0, m->n_blocks, m->d_err, m->stream));
+  return SMKI_OK;
+}
+
+smki_status take_device_error(smki_map* m) {
+  uint32_t e = 0;
+  SMKI_HIP_TRY(sync_read(m, m->d_err, sizeof(uint32_t), &e));
+  if (e) {
+    SMKI_HIP_TRY(hipMemsetAsync(m->d_err, 0, sizeof(uint32_t), m->stream));
+    SMKI_HIP_TRY(hipStreamSynchronize(m->stream));
+    return status_of_err(e);
+  }
+  return SMKI_OK;
+}
+
+// Grid of blocks covering voxel box [vlo, vhi].
+BucketGeom make_geom(const smki_map* m, const int32_t vlo[3], const int32_t vhi[3]) {
+  BucketGeom g{};
+  g.res = m->res;
+  g.B = m->B;
+  g.log2B = m->log2B;
+  g.n_blocks = 1;
+  for (int a = 0; a < 3; ++a) {
+    const int32_t lo = vlo[a] >> m->log2B, hi = vhi[a] >> m->log2B;
+    g.blo[a] = lo;
+    g.nb[a] = hi - lo + 1;
+    g.n_blocks *= g.nb[a];
+  }
+  g.key_bits = std::max(1, bits_for(g.n_blocks) + 3 * m->log2B);
+  return g;
+}
+
+// ---------------------------------------------------------------------------
+// the insert (one or several scans)
+// ---------------------------------------------------------------------------
+smki_status insert_impl(smki_map* m, const float* xyz, const int32_t* label, int64_t n,
+                        const int64_t* offsets, const float* origins, int32_t S, float step) {
+  // host-side validation
+  if (!m || S < 1 || !offsets || !origins || n < 0 || (n > 0 && (!xyz || !label)))
+    return SMKI_E_INVALID_ARG;
+  if (!isfinite(step)) return SMKI_E_INVALID_ARG;
+  if (offsets[0] != 0 || offsets[S] != n) return SMKI_E_INVALID_ARG;
+  for (int32_t s = 0; s < S; ++s)
+    if (offsets[s + 1] < offsets[s]) return SMKI_E_INVALID_ARG;
+  for (int32_t s = 0; s < 3 * S; ++s) {
+    if (!isfinite(origins[s])) return SMKI_E_INVALID_ARG;
+    const float q = floorf((float)((double)origins[s] / (double)m->res));
+    if (!(q >= -(float)SMKI_COORD_LIM && q < (float)SMKI_COORD_LIM)) return SMKI_E_RANGE;
+  }
+  if (n > (int64_t)INT32_MAX / 2) return SMKI_E_CAPACITY;
+  smki_scan_stats st{};
+  m->last = st;
+  m->stats_pending = false;
+  if (n == 0) return SMKI_OK;
+  hipStream_t q = m->stream;
+  SMKI_HIP_TRY(hipSetDevice(m->device));
+
+  // ---- phase A: per-hit validation, free-sample counts, bounding box ----
+  Sizer za;
+  za.add<int64_t>(S + 1);
+  za.add<float>(3 * (size_t)S);
+  za.add<int64_t>(n);        // nfree
+  za.add<int64_t>(n);        // off
+  za.add<int32_t>(n);        // kept
+  za.add<int32_t>(n);        // kpos
+  za.add<int32_t>(8);        // bbox
+  za.add<int64_t>(4);        // scalars
+  za.add<char>(scan_tmp_bytes(n));
+  SMKI_HIP_TRY(m->a_hits.reserve(za.total));
+  Arena& A = m->a_hits;
+  int64_t* d_soff = A.take<int64_t>(S + 1);
+  float* d_org = A.take<float>(3 * (size_t)S);
+  int64_t* d_nfree = A.take<int64_t>(n);
+  int64_t* d_off = A.take<int64_t>(n);
+  int32_t* d_kept = A.take<int32_t>(n);
+  int32_t* d_kpos = A.take<int32_t>(n);
+  int32_t* d_bbox = A.take<int32_t>(8);
+  int64_t* d_sc = A.take<int64_t>(4);
+  void* d_stmp = A.take<char>(scan_tmp_bytes(n));
+  const int32_t bbox0[8] = {INT32_MAX, INT32_MAX, INT32_MAX, INT32_MIN, INT32_MIN, INT32_MIN, 0, 0};
+  SMKI_HIP_TRY(hipMemcpyAsync(d_soff, offsets, sizeof(int64_t) * (S + 1), hipMemcpyHostToDevice, q));
+  SMKI_HIP_TRY(hipMemcpyAsync(d_org, origins, sizeof(float) * 3 * S, hipMemcpyHostToDevice, q));
+  SMKI_HIP_TRY(hipMemcpyAsync(d_bbox, bbox0, sizeof(bbox0), hipMemcpyHostToDevice, q));
+  SMKI_HIP_TRY(hipMemsetAsync(d_sc, 0, sizeof(int64_t) * 4, q));
+  SMKI_HIP_TRY(launch_count(xyz, label, n, d_soff, d_org, S, m->res, step, m->K, d_nfree, d_kept,
+                            d_bbox, m->d_err, q));
+  SMKI_HIP_TRY(scan_excl_i64(d_nfree, d_off, n, d_sc, d_stmp, q));
+  SMKI_HIP_TRY(scan_excl_i32(d_kept, d_kpos, n, (int32_t*)(d_sc + 1), d_stmp, q));
+  // sync 1: counts, box, device validation
+  SMKI_HIP_TRY(hipMemcpyAsync(m->h_pin, d_sc, sizeof(int64_t) * 2, hipMemcpyDeviceToHost, q));
+  SMKI_HIP_TRY(hipMemcpyAsync(m->h_pin + 2, d_bbox, sizeof(int32_t) * 6, hipMemcpyDeviceToHost, q));
+  SMKI_HIP_TRY(hipMemcpyAsync(m->h_pin + 6, m->d_err, sizeof(uint32_t), hipMemcpyDeviceToHost, q));
+  SMKI_HIP_TRY(hipStreamSynchronize(q));
+  const int64_t nf = m->h_pin[0];
+  const int64_t nk = (int64_t)(int32_t)(m->h_pin[1] & 0xffffffff);
+  int32_t bb[6];
+  memcpy(bb, m->h_pin + 2, sizeof(bb));
+  const uint32_t derr = (uint32_t)(m->h_pin[6] & 0xffffffffu);
+  if (derr) {
+    SMKI_HIP_TRY(hipMemsetAsync(m->d_err, 0, sizeof(uint32_t), q));
+    SMKI_HIP_TRY(hipStreamSynchronize(q));
+    return status_of_err(derr);
+  }
+  m->last.n_hits = nk;
+  m->last.n_free = nf;
+  if (nk == 0) return SMKI_OK;
+  if (nk + nf > (int64_t)INT32_MAX - 1) return SMKI_E_CAPACITY;
+
+  // ---- geometry of this insert ----
+  int32_t vlo[3], vhi[3];
+  int64_t maxabs = 0;
+  for (int a = 0; a < 3; ++a) {
+    vlo[a] = std::max(bb[a] - 1, -SMKI_COORD_LIM);
+    vhi[a] = std::min(bb[3 + a] + 1, SMKI_COORD_LIM - 1);
+    maxabs = std::max<int64_t>(maxabs, std::max(std::abs((int64_t)vlo[a]), std::abs((int64_t)vhi[a])));
+  }
+  const BucketGeom g = make_geom(m, vlo, vhi);
+  if (g.n_blocks > (int64_t(1) << 28)) return SMKI_E_CAPACITY;
+  const double lv = (double)m->l / (double)m->res;
+  const double margin = std::max(1e-4, 4.0 * ldexp((double)maxabs + 1.0, -23));
+  const Stencil sten = make_stencil(lv, margin);
+  if (sten.D > SMKI_MAX_BOX) return SMKI_E_CAPACITY;
+  const int32_t DB = std::max<int32_t>(1, (sten.R + m->B - 1) / m->B);
+  int32_t eblo[3], enb[3];
+  int64_t n_ext = 1;
+  for (int a = 0; a < 3; ++a) {
+    eblo[a] = g.blo[a] - DB;
+    enb[a] = g.nb[a] + 2 * DB;
+    n_ext *= enb[a];
+  }
+  const int32_t B3 = m->B * m->B * m->B;
+
+  // ---- phase B: bucket hits and free samples; mark target blocks ----
+  const int64_t nmax = std::max(nk, nf);
+  const int64_t slots_h = std::min<int64_t>(nk, g.n_blocks);
+  const int64_t slots_f = std::min<int64_t>(std::max<int64_t>(nf, 1), g.n_blocks);
+  Sizer zb;
+  zb.add<float4>(nk);
+  zb.add<int32_t>(g.n_blocks);
+  zb.add<int32_t>(slots_h);
+  zb.add<int32_t>(slots_h * (B3 + 1));
+  zb.add<float4>(nf);
+  zb.add<int32_t>(g.n_blocks);
+  zb.add<int32_t>(slots_f);
+  zb.add<int32_t>(slots_f * (B3 + 1));
+  zb.add<int32_t>(8);
+  zb.add<uint64_t>(nmax);
+  zb.add<uint64_t>(nmax);
+  zb.add<uint32_t>(nmax);
+  zb.add<uint32_t>(nmax);
+  zb.add<float4>(nmax);
+  zb.add<int32_t>(nmax);
+  zb.add<int32_t>(nmax);
+  zb.add<char>(radix_tmp_bytes(nmax));
+  zb.add<char>(scan_tmp_bytes(std::max(nmax, n_ext)));
+  zb.add<int32_t>(n_ext);
+  zb.add<int32_t>(n_ext);
+  SMKI_HIP_TRY(m->a_sets.reserve(zb.total));
+  Arena& Bz = m->a_sets;
+  PointSet hs{}, fs{};
+  hs.n = nk;
+  hs.pts = Bz.take<float4>(nk);
+  hs.dense = Bz.take<int32_t>(g.n_blocks);
+  hs.slot_lin = Bz.take<int32_t>(slots_h);
+  hs.prefix = Bz.take<int32_t>(slots_h * (B3 + 1));
+  fs.n = nf;
+  fs.pts = Bz.take<float4>(nf);
+  fs.dense = Bz.take<int32_t>(g.n_blocks);
+  fs.slot_lin = Bz.take<int32_t>(slots_f);
+  fs.prefix = Bz.take<int32_t>(slots_f * (B3 + 1));
+  int32_t* d_si = Bz.take<int32_t>(8);
+  hs.d_nslots = d_si;
+  fs.d_nslots = d_si + 1;
+  int32_t* d_ntgt = d_si + 2;
+  BucketScratch scr{};
+  scr.keys = Bz.take<uint64_t>(nmax);
+  scr.akeys = Bz.take<uint64_t>(nmax);
+  scr.idx = Bz.take<uint32_t>(nmax);
+  scr.aidx = Bz.take<uint32_t>(nmax);
+  scr.rec = Bz.take<float4>(nmax);
+  scr.flag = Bz.take<int32_t>(nmax);
+  scr.slot_excl = Bz.take<int32_t>(nmax);
+  scr.sort_tmp = Bz.take<char>(radix_tmp_bytes(nmax));
+  scr.scan_tmp = Bz.take<char>(scan_tmp_bytes(std::max(nmax, n_ext)));
+  int32_t* d_mark = Bz.take<int32_t>(n_ext);
+  int32_t* d_mpos = Bz.take<int32_t>(n_ext);
+  SMKI_HIP_TRY(hipMemsetAsync(d_si, 0, sizeof(int32_t) * 8, q));
+  SMKI_HIP_TRY(bucket_hits(xyz, label, n, d_kept, d_kpos, g, hs, scr, m->d_err, q));
+  SMKI_HIP_TRY(bucket_frees(xyz, n, d_off, d_soff, d_org, S, step, m->free_class, g, fs, scr,
+                            m->d_err, q));
+  SMKI_HIP_TRY(hipMemsetAsync(d_mark, 0, sizeof(int32_t) * n_ext, q));
+  SMKI_HIP_TRY(launch_mark_targets(hs.slot_lin, hs.d_nslots, (int32_t)slots_h, g, eblo, enb, DB,
+                                   d_mark, q));
+  if (nf > 0)
+    SMKI_HIP_TRY(launch_mark_targets(fs.slot_lin, fs.d_nslots, (int32_t)slots_f, g, eblo, enb, DB,
+                                     d_mark, q));
+  SMKI_HIP_TRY(scan_excl_i32(d_mark, d_mpos, n_ext, d_ntgt, scr.scan_tmp, q));
+  // sync 2: number of target blocks
+  int32_t si[3];
+  SMKI_HIP_TRY(sync_read(m, d_si, sizeof(si), si));
+  const int32_t n_t = si[2];
+  m->last.n_point_blocks = (int64_t)si[0] + si[1];
+  m->last.n_target_blocks = n_t;
+
+  // ---- phase C: plan, allocate, gather ----
+  GatherArgs ga{};
+  ga.g = g;
+  for (int a = 0; a < 3; ++a) {
+    ga.eblo[a] = eblo[a];
+    ga.enb[a] = enb[a];
+  }
+  ga.R = sten.R;
+  ga.D = sten.D;
+  ga.nsub = m->B / SMKI_TILE;
+  ga.ncols = (int32_t)sten.cols.size();
+  SMKI_HIP_TRY(hipMemcpyAsync(m->d_cols, sten.cols.data(), sizeof(StencilCol) * sten.cols.size(),
+                              hipMemcpyHostToDevice, q));
+  ga.cols = m->d_cols;
+  ga.l2 = m->l * m->l;
+  ga.inv_l = 1.0f / m->l;
+  for (int i = 0; i < SMKI_POLY_N; ++i) ga.coef[i] = m->coef[i];
+  ga.K = m->K;
+  ga.free_class = m->free_class;
+  ga.pts[0] = fs.pts;
+  ga.dense[0] = fs.dense;
+  ga.prefix[0] = fs.prefix;
+  ga.pts[1] = hs.pts;
+  ga.dense[1] = hs.dense;
+  ga.prefix[1] = hs.prefix;
+  ga.budget = m->budget;
+  ga.stats = m->d_stats;
+  if (nf == 0) {  // an empty free set: every lookup misses
+    SMKI_HIP_TRY(launch_fill_i32(fs.dense, g.n_blocks, -1, q));
+  }
+  const int32_t nsub3 = ga.nsub * ga.nsub * ga.nsub;
+  const int64_t n_plan = (int64_t)n_t * nsub3;
+  Sizer zc;
+  zc.add<int32_t>(n_t);   // tgt_elin
+  zc.add<int32_t>(n_t);   // active
+  zc.add<int32_t>(n_t);   // tgt_slot
+  zc.add<int32_t>(n_t);   // is_new
+  zc.add<int32_t>(n_t);   // new_rank
+  zc.add<int4>(n_plan);
+  zc.add<int32_t>(n_plan);
+  zc.add<int32_t>(n_plan);
+  zc.add<int32_t>(n_plan);
+  zc.add<int32_t>(n_plan);
+  zc.add<int32_t>(8);
+  zc.add<char>(scan_tmp_bytes(std::max<int64_t>(n_plan, n_t)));
+  SMKI_HIP_TRY(m->a_tgts.reserve(zc.total));
+  Arena& C = m->a_tgts;
+  int32_t* d_tgt = C.take<int32_t>(n_t);
+  int32_t* d_active = C.take<int32_t>(n_t);
+  int32_t* d_tslot = C.take<int32_t>(n_t);
+  int32_t* d_isnew = C.take<int32_t>(n_t);
+  int32_t* d_rank = C.take<int32_t>(n_t);
+  int4* d_plan = C.take<int4>(n_plan);
+  int32_t* d_np = C.take<int32_t>(n_plan);
+  int32_t* d_ns = C.take<int32_t>(n_plan);
+  int32_t* d_uoff = C.take<int32_t>(n_plan);
+  int32_t* d_soff2 = C.take<int32_t>(n_plan);
+  int32_t* d_cnt = C.take<int32_t>(8);
+  void* d_ctmp = C.take<char>(scan_tmp_bytes(std::max<int64_t>(n_plan, n_t)));
+  ga.tgt_elin = d_tgt;
+  ga.tgt_slot = d_tslot;
+  ga.plan = d_plan;
+  SMKI_HIP_TRY(hipMemsetAsync(d_cnt, 0, sizeof(int32_t) * 8, q));
+  SMKI_HIP_TRY(hipMemsetAsync(d_active, 0, sizeof(int32_t) * std::max<int64_t>(n_t, 1), q));
+  SMKI_HIP_TRY(launch_list_targets(d_mark, d_mpos, n_ext, d_tgt, q));
+  SMKI_HIP_TRY(launch_plan(ga, n_t, m->part_frac, d_plan, d_active, q));
+  SMKI_HIP_TRY(launch_map_lookup(m->dev, ga, n_t, d_active, d_tslot, d_isnew, m->d_err, q));
+  SMKI_HIP_TRY(scan_excl_i32(d_isnew, d_rank, n_t, d_cnt, d_ctmp, q));
+  SMKI_HIP_TRY(launch_plan_counts(d_plan, n_plan, d_np, d_ns, q));
+  SMKI_HIP_TRY(scan_excl_i32(d_np, d_uoff, n_plan, d_cnt + 1, d_ctmp, q));
+  SMKI_HIP_TRY(scan_excl_i32(d_ns, d_soff2, n_plan, d_cnt + 2, d_ctmp, q));
+  // sync 3: new blocks, units, partial slots
+  int32_t cnt[3];
+  SMKI_HIP_TRY(sync_read(m, d_cnt, sizeof(cnt), cnt));
+  const int64_t n_new = cnt[0], n_units = cnt[1], n_split = cnt[2];
+  m->last.n_new_blocks = n_new;
+  m->last.n_units = n_units;
+  smki_status rc = ensure_pool(m, m->n_blocks + n_new);
+  if (rc != SMKI_OK) return rc;
+  rc = ensure_hash(m, m->n_blocks + n_new);
+  if (rc != SMKI_OK) return rc;
+  Sizer zd;
+  zd.add<int4>(n_units);
+  zd.add<float>((size_t)n_split * m->K * SMKI_WAVE);
+  zd.add<int32_t>((size_t)n_split * SMKI_WAVE);
+  SMKI_HIP_TRY(m->a_misc.reserve(zd.total));
+  int4* d_units = m->a_misc.take<int4>(n_units);
+  float* d_pacc = m->a_misc.take<float>((size_t)n_split * m->K * SMKI_WAVE);
+  int32_t* d_pcnt = m->a_misc.take<int32_t>((size_t)n_split * SMKI_WAVE);
+  SMKI_HIP_TRY(launch_assign_new(m->dev, ga, n_t, d_isnew, d_rank, m->n_blocks, d_tslot, m->d_err, q));
+  SMKI_HIP_TRY(launch_fill_alpha0(m->dev, m->n_blocks, n_new, q));
+  SMKI_HIP_TRY(launch_units(d_plan, d_uoff, d_soff2, n_plan, nsub3, d_units, q));
+  ga.units = d_units;
+  ga.alpha = m->dev.alpha;
+  ga.part_acc = d_pacc;
+  ga.part_cnt = d_pcnt;
+  SMKI_HIP_TRY(hipMemsetAsync(m->d_stats, 0, sizeof(unsigned long long) * 2, q));
+  SMKI_HIP_TRY(launch_gather(ga, n_units, q));
+  if (n_split > 0) SMKI_HIP_TRY(launch_merge(ga, n_plan, q));
+  SMKI_HIP_TRY(hipMemcpyAsync(m->h_pin + 8, m->d_stats, sizeof(unsigned long long) * 2,
+                              hipMemcpyDeviceToHost, q));
+  m->n_blocks += n_new;
+  m->stats_pending = true;
+  return SMKI_OK;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// C ABI
+// ---------------------------------------------------------------------------
+extern "C" {
+
+const char* smki_status_string(smki_status s) {
+  switch (s) {
+    case SMKI_OK: return "ok";
+    case SMKI_E_INVALID_ARG: return "invalid argument";
+    case SMKI_E_OOM: return "device out of memory";
+    case SMKI_E_CAPACITY: return "capacity exceeded";
+    case SMKI_E_DEVICE: return "HIP runtime error";
+    case SMKI_E_BAD_INPUT: return "bad input (label outside {-1..K-1} or non-finite coordinate)";
+    case SMKI_E_RANGE: return "voxel index outside [-2^20, 2^20) or too many samples on a beam";
+    default: return "unknown status";
+  }
+}
+
+smki_status smki_create_map(float res, int32_t block_size, float l, float sigma0, int32_t K,
+                            float alpha0, int32_t free_class, const smki_options* opt,
+                            smki_map** out) {
+  if (!out) return SMKI_E_INVALID_ARG;
+  *out = nullptr;
+  if (!finite_pos(res) || !finite_pos(l) || !finite_pos(sigma0) || !finite_pos(alpha0))
+    return SMKI_E_INVALID_ARG;
+  if (K < 2 || K > 255 || free_class < 0 || free_class >= K) return SMKI_E_INVALID_ARG;
+  if (block_size != 4 && block_size != 8 && block_size != 16 && block_size != 32)
+    return SMKI_E_INVALID_ARG;
+  if (opt && (opt->initial_blocks < 0 || opt->unit_budget < 0 || !(opt->part_fraction >= 0.0f) ||
+              opt->part_fraction > 1.0f))
+    return SMKI_E_INVALID_ARG;
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) return SMKI_E_DEVICE;
+  smki_map* m = new (std::nothrow) smki_map();
+  if (!m) return SMKI_E_OOM;
+  m->res = res;
+  m->l = l;
+  m->sigma0 = sigma0;
+  m->alpha0 = alpha0;
+  m->K = K;
+  m->B = block_size;
+  m->log2B = ilog2(block_size);
+  m->free_class = free_class;
+  m->budget = (opt && opt->unit_budget > 0) ? opt->unit_budget : 2048;
+  m->part_frac = (opt && opt->part_fraction > 0.0f) ? opt->part_fraction : 0.5f;
+  for (int i = 0; i < SMKI_POLY_N; ++i) m->coef[i] = (float)(kQ[i] * (double)sigma0);
+  (void)hipGetDevice(&m->device);
+  m->dev.K = K;
+  m->dev.B = block_size;
+  m->dev.log2B = m->log2B;
+  m->dev.alpha0 = alpha0;
+  smki_status rc = SMKI_OK;
+  if (hipMalloc((void**)&m->d_err, 64) != hipSuccess ||
+      hipMalloc((void**)&m->d_stats, 64) != hipSuccess ||
+      hipMalloc((void**)&m->d_cols, sizeof(StencilCol) * SMKI_MAX_COLS) != hipSuccess ||
+      hipHostMalloc((void**)&m->h_pin, 256, hipHostMallocDefault) != hipSuccess)
+    rc = SMKI_E_OOM;
+  if (rc == SMKI_OK && hipMemset(m->d_err, 0, 64) != hipSuccess) rc = SMKI_E_DEVICE;
+  if (rc == SMKI_OK) rc = ensure_pool(m, (opt && opt->initial_blocks > 0) ? opt->initial_blocks : 4096);
+  if (rc == SMKI_OK) rc = ensure_hash(m, 4096);
+  if (rc == SMKI_OK && hipStreamSynchronize(m->stream) != hipSuccess) rc = SMKI_E_DEVICE;
+  if (rc != SMKI_OK) {
+    smki_destroy_map(m);
+    return rc;
+  }
+  *out = m;
+  return SMKI_OK;
+}
+
+smki_status smki_destroy_map(smki_map* m) {
+  if (!m) return SMKI_E_INVALID_ARG;
+  (void)hipStreamSynchronize(m->stream);
+  if (m->dev.hkeys) (void)hipFree(m->dev.hkeys);
+  if (m->dev.hvals) (void)hipFree(m->dev.hvals);
+  if (m->dev.bkeys) (void)hipFree(m->dev.bkeys);
+  if (m->dev.alpha) (void)hipFree(m->dev.alpha);
+  if (m->d_err) (void)hipFree(m->d_err);
+  if (m->d_stats) (void)hipFree(m->d_stats);
+  if (m->d_cols) (void)hipFree(m->d_cols);
+  if (m->h_pin) (void)hipHostFree(m->h_pin);
+  m->a_hits.release();
+  m->a_sets.release();
+  m->a_tgts.release();
+  m->a_misc.release();
+  delete m;
+  return SMKI_OK;
+}
+
+smki_status smki_set_stream(smki_map* m, void* hip_stream) {
+  if (!m) return SMKI_E_INVALID_ARG;
+  m->stream = (hipStream_t)hip_stream;
+  return SMKI_OK;
+}
+
+smki_status smki_insert_scan(smki_map* m, const float* xyz, const int32_t* label, int64_t n,
+                             const float* origin, float free_step) {
+  if (!origin) return SMKI_E_INVALID_ARG;
+  const int64_t off[2] = {0, n};
+  return insert_impl(m, xyz, label, n, off, origin, 1, free_step);
+}
+
+smki_status smki_insert_scans(smki_map* m, const float* xyz, const int32_t* label,
+                              const int64_t* offsets, const float* origins, int32_t S,
+                              float free_step) {
+  if (!offsets || S < 1) return SMKI_E_INVALID_ARG;
+  return insert_impl(m, xyz, label, offsets[S], offsets, origins, S, free_step);
+}
+
+smki_status smki_query(smki_map* m, const int32_t* ijk, int64_t M, float* alpha, float* mean,
+                       float* var, int32_t* label, float* p_occ) {
+  if (!m || M < 0 || (M > 0 && !ijk)) return SMKI_E_INVALID_ARG;
+  SMKI_HIP_TRY(launch_query(m->dev, ijk, M, alpha, mean, var, label, p_occ, m->free_class,
+                            m->stream));
+  return SMKI_OK;
+}
+
+smki_status smki_num_blocks(smki_map* m, int64_t* n_blocks) {
+  if (!m || !n_blocks) return SMKI_E_INVALID_ARG;
+  *n_blocks = m->n_blocks;
+  return SMKI_OK;
+}
+
+smki_status smki_export(smki_map* m, int64_t capacity, int64_t* n_blocks, int32_t* block_ijk,
+                        float* alpha) {
+  if (!m || !n_blocks) return SMKI_E_INVALID_ARG;
+  *n_blocks = m->n_blocks;
+  if (!block_ijk && !alpha) return SMKI_OK;
+  if (capacity < m->n_blocks) return SMKI_E_CAPACITY;
+  const int64_t n = m->n_blocks;
+  if (n == 0) return SMKI_OK;
+  Sizer z;
+  z.add<uint64_t>(n);
+  z.add<uint64_t>(n);
+  z.add<uint32_t>(n);
+  z.add<uint32_t>(n);
+  z.add<char>(radix_tmp_bytes(n));
+  SMKI_HIP_TRY(m->a_misc.reserve(z.total));
+  uint64_t* k = m->a_misc.take<uint64_t>(n);
+  uint64_t* k2 = m->a_misc.take<uint64_t>(n);
+  uint32_t* o = m->a_misc.take<uint32_t>(n);
+  uint32_t* o2 = m->a_misc.take<uint32_t>(n);
+  void* tmp = m->a_misc.take<char>(radix_tmp_bytes(n));
+  SMKI_HIP_TRY(hipMemcpyAsync(k, m->dev.bkeys, sizeof(uint64_t) * n, hipMemcpyDeviceToDevice,
+                              m->stream));
+  SMKI_HIP_TRY(launch_iota_u32(o, n, m->stream));
+  SMKI_HIP_TRY(radix_sort_u64(k, o, k2, o2, n, 63, tmp, m->stream));
+  if (block_ijk) SMKI_HIP_TRY(launch_block_keys_to_ijk(k, n, block_ijk, m->stream));
+  if (alpha) SMKI_HIP_TRY(launch_gather_blocks(m->dev, o, n, nullptr, alpha, m->stream));
+  SMKI_HIP_TRY(hipStreamSynchronize(m->stream));
+  return SMKI_OK;
+}
+
+smki_status smki_import(smki_map* m, int64_t n, const int32_t* block_ijk, const float* alpha) {
+  if (!m || n < 0 || (n > 0 && (!block_ijk || !alpha))) return SMKI_E_INVALID_ARG;
+  smki_status rc = ensure_pool(m, std::max<int64_t>(n, 1));
+  if (rc != SMKI_OK) return rc;
+  const int64_t keep = m->n_blocks;
+  m->n_blocks = 0;  // the hash is rebuilt from the imported keys below
+  rc = ensure_hash(m, std::max<int64_t>(n, 1));
+  if (rc != SMKI_OK) { m->n_blocks = keep; return rc; }
+  const size_t per = (size_t)m->K * m->B * m->B * m->B;
+  SMKI_HIP_TRY(launch_ijk_to_block_keys(block_ijk, n, m->dev.bkeys, m->d_err, m->stream));
+  if (n > 0)
+    SMKI_HIP_TRY(hipMemcpyAsync(m->dev.alpha, alpha, sizeof(float) * per * n,
+                                hipMemcpyDeviceToDevice, m->stream));
+  SMKI_HIP_TRY(launch_hash_clear(m->dev, m->stream));
+  SMKI_HIP_TRY(launch_hash_insert_slots(m->dev, 0, n, m->d_err, m->stream));
+  m->n_blocks = n;
+  return take_device_error(m);
+}
+
+smki_status smki_last_scan_stats(smki_map* m, smki_scan_stats* out) {
+  if (!m || !out) return SMKI_E_INVALID_ARG;
+  if (m->stats_pending) {
+    SMKI_HIP_TRY(hipStreamSynchronize(m->stream));
+    const unsigned long long* s = (const unsigned long long*)(m->h_pin + 8);
+    m->last.n_updated_voxels = (int64_t)s[0];
+    m->last.n_pairs = (int64_t)s[1];
+    m->stats_pending = false;
+  }
+  *out = m->last;
+  return SMKI_OK;
+}
+
+smki_status smki_sync(smki_map* m) {
+  if (!m) return SMKI_E_INVALID_ARG;
+  SMKI_HIP_TRY(hipStreamSynchronize(m->stream));
+  return take_device_error(m);
+}
+
+smki_status smki_free_samples(const float* xyz, const int32_t* label, int64_t n, const float* origin,
+                              float free_step, int32_t K, void* hip_stream, int64_t* n_out,
+                              float* out_xyz, int64_t* out_parent) {
+  if (!n_out || !origin || n < 0 || (n > 0 && (!xyz || !label)) || K < 1 || K > 255 ||
+      !isfinite(free_step))
+    return SMKI_E_INVALID_ARG;
+  hipStream_t q = (hipStream_t)hip_stream;
+  *n_out = 0;
+  if (n == 0) return SMKI_OK;
+  Sizer z;
+  z.add<int64_t>(2);
+  z.add<float>(4);
+  z.add<int64_t>(n);
+  z.add<int64_t>(n);
+  z.add<int32_t>(n);
+  z.add<int32_t>(8);
+  z.add<uint32_t>(1);
+  z.add<int64_t>(2);
+  z.add<char>(scan_tmp_bytes(n));
+  char* base = nullptr;
+  SMKI_HIP_TRY(hipMallocAsync((void**)&base, z.total, q));
+  Arena A;
+  A.base = base;
+  A.cap = z.total;
+  int64_t* soff = A.take<int64_t>(2);
+  float* org = A.take<float>(4);
+  int64_t* nfree = A.take<int64_t>(n);
+  int64_t* off = A.take<int64_t>(n);
+  int32_t* kept = A.take<int32_t>(n);
+  int32_t* bbox = A.take<int32_t>(8);
+  uint32_t* err = A.take<uint32_t>(1);
+  int64_t* tot = A.take<int64_t>(2);
+  void* tmp = A.take<char>(scan_tmp_bytes(n));
+  const int64_t so[2] = {0, n};
+  const int32_t bbox0[8] = {INT32_MAX, INT32_MAX, INT32_MAX, INT32_MIN, INT32_MIN, INT32_MIN, 0, 0};
+  smki_status rc = SMKI_OK;
+  hipError_t e = hipMemcpyAsync(soff, so, sizeof(so), hipMemcpyHostToDevice, q);
+  if (e == hipSuccess) e = hipMemcpyAsync(org, origin, sizeof(float) * 3, hipMemcpyHostToDevice, q);
+  if (e == hipSuccess) e = hipMemcpyAsync(bbox, bbox0, sizeof(bbox0), hipMemcpyHostToDevice, q);
+  if (e == hipSuccess) e = hipMemsetAsync(err, 0, sizeof(uint32_t), q);
+  if (e == hipSuccess)
+    e = launch_count(xyz, label, n, soff, org, 1, 3.0e38f, free_step, K, nfree, kept, bbox, err, q);
+  if (e == hipSuccess) e = scan_excl_i64(nfree, off, n, tot, tmp, q);
+  int64_t h[2] = {0, 0};
+  uint32_t herr = 0;
+  if (e == hipSuccess) e = hipMemcpyAsync(h, tot, sizeof(int64_t), hipMemcpyDeviceToHost, q);
+  if (e == hipSuccess) e = hipMemcpyAsync(&herr, err, sizeof(uint32_t), hipMemcpyDeviceToHost, q);
+  if (e == hipSuccess) e = hipStreamSynchronize(q);
+  if (e != hipSuccess) rc = smki_hip_error(e);
+  // the resolution used above (3e38) only feeds an unused bounding box
+  if (rc == SMKI_OK && herr) rc = status_of_err(herr);
+  if (rc == SMKI_OK) {
+    *n_out = h[0];
+    if (out_xyz) {
+      e = launch_free_xyz(xyz, n, off, h[0], org, free_step, out_xyz, out_parent, q);
+      if (e == hipSuccess) e = hipStreamSynchronize(q);
+      if (e != hipSuccess) rc = smki_hip_error(e);
+    }
+  }
+  (void)hipFreeAsync(base, q);
+  (void)hipStreamSynchronize(q);
+  return rc;
+}
+
+smki_status smki_bucket_cells(const float* xyz, int64_t n, float res, int32_t block_size,
+                              void* hip_stream, int64_t* n_cells, uint64_t* cell_keys,
+                              int32_t* cell_start, int32_t* cell_count, int32_t* order) {
+  if (!n_cells || n < 0 || (n > 0 && !xyz) || !finite_pos(res) ||
+      (block_size != 4 && block_size != 8 && block_size != 16 && block_size != 32))
+    return SMKI_E_INVALID_ARG;
+  if (n > (int64_t)INT32_MAX / 2) return SMKI_E_CAPACITY;
+  hipStream_t q = (hipStream_t)hip_stream;
+  *n_cells = 0;
+  if (n == 0) return SMKI_OK;
+  // bounding box pass (labels are not needed: validate with an all-valid label)
+  smki_map tmp_map{};
+  tmp_map.res = res;
+  tmp_map.B = block_size;
+  tmp_map.log2B = ilog2(block_size);
+  Sizer z0;
+  z0.add<int32_t>(8);
+  z0.add<uint32_t>(1);
+  z0.add<int64_t>(n);
+  z0.add<int32_t>(n);
+  z0.add<int32_t>(n);
+  z0.add<int64_t>(2);
+  z0.add<float>(4);
+  char* base0 = nullptr;
+  SMKI_HIP_TRY(hipMallocAsync((void**)&base0, z0.total, q));
+  Arena A0;
+  A0.base = base0;
+  A0.cap = z0.total;
+  int32_t* bbox = A0.take<int32_t>(8);
+  uint32_t* err = A0.take<uint32_t>(1);
+  int64_t* nfree = A0.take<int64_t>(n);
+  int32_t* kept = A0.take<int32_t>(n);
+  int32_t* lab = A0.take<int32_t>(n);
+  int64_t* soff = A0.take<int64_t>(2);
+  float* org = A0.take<float>(4);
+  const int32_t bbox0[8] = {INT32_MAX, INT32_MAX, INT32_MAX, INT32_MIN, INT32_MIN, INT32_MIN, 0, 0};
+  const int64_t so[2] = {0, n};
+  const float o0[4] = {0, 0, 0, 0};
+  hipError_t e = hipMemcpyAsync(bbox, bbox0, sizeof(bbox0), hipMemcpyHostToDevice, q);
+  if (e == hipSuccess) e = hipMemcpyAsync(soff, so, sizeof(so), hipMemcpyHostToDevice, q);
+  if (e == hipSuccess) e = hipMemcpyAsync(org, o0, sizeof(o0), hipMemcpyHostToDevice, q);
+  if (e == hipSuccess) e = hipMemsetAsync(err, 0, sizeof(uint32_t), q);
+  if (e == hipSuccess) e = hipMemsetAsync(lab, 0, sizeof(int32_t) * n, q);
+  if (e == hipSuccess)
+    e = launch_count(xyz, lab, n, soff, org, 1, res, 0.0f, 1, nfree, kept, bbox, err, q);
+  int32_t hb[8];
+  uint32_t herr = 0;
+  if (e == hipSuccess) e = hipMemcpyAsync(hb, bbox, sizeof(hb), hipMemcpyDeviceToHost, q);
+  if (e == hipSuccess) e = hipMemcpyAsync(&herr, err, sizeof(uint32_t), hipMemcpyDeviceToHost, q);
+  if (e == hipSuccess) e = hipStreamSynchronize(q);
+  (void)hipFreeAsync(base0, q);
+  if (e != hipSuccess) return smki_hip_error(e);
+  if (herr) return status_of_err(herr);
+  const BucketGeom g = make_geom(&tmp_map, hb, hb + 3);
+  if (g.n_blocks > (int64_t(1) << 28)) return SMKI_E_CAPACITY;
+  Sizer z;
+  z.add<uint64_t>(n);
+  z.add<uint64_t>(n);
+  z.add<uint32_t>(n);
+  z.add<uint32_t>(n);
+  z.add<float4>(n);
+  z.add<int32_t>(n);
+  z.add<int32_t>(n);
+  z.add<char>(radix_tmp_bytes(n));
+  z.add<char>(scan_tmp_bytes(n));
+  z.add<int32_t>(2);
+  z.add<uint32_t>(1);
+  char* base = nullptr;
+  SMKI_HIP_TRY(hipMallocAsync((void**)&base, z.total, q));
+  Arena A;
+  A.base = base;
+  A.cap = z.total;
+  BucketScratch scr{};
+  scr.keys = A.take<uint64_t>(n);
+  scr.akeys = A.take<uint64_t>(n);
+  scr.idx = A.take<uint32_t>(n);
+  scr.aidx = A.take<uint32_t>(n);
+  scr.rec = A.take<float4>(n);
+  scr.flag = A.take<int32_t>(n);
+  scr.slot_excl = A.take<int32_t>(n);
+  scr.sort_tmp = A.take<char>(radix_tmp_bytes(n));
+  scr.scan_tmp = A.take<char>(scan_tmp_bytes(n));
+  int32_t* d_nc = A.take<int32_t>(2);
+  uint32_t* err2 = A.take<uint32_t>(1);
+  smki_status rc = SMKI_OK;
+  int32_t nc = 0;
+  e = hipMemsetAsync(d_nc, 0, sizeof(int32_t) * 2, q);
+  if (e == hipSuccess) e = hipMemsetAsync(err2, 0, sizeof(uint32_t), q);
+  if (e == hipSuccess) e = bucket_cells_sort(xyz, n, g, scr, err2, d_nc, q);
+  if (e == hipSuccess) e = hipMemcpyAsync(&nc, d_nc, sizeof(int32_t), hipMemcpyDeviceToHost, q);
+  if (e == hipSuccess) e = hipMemcpyAsync(&herr, err2, sizeof(uint32_t), hipMemcpyDeviceToHost, q);
+  if (e == hipSuccess) e = hipStreamSynchronize(q);
+  if (e != hipSuccess) rc = smki_hip_error(e);
+  if (rc == SMKI_OK && herr) rc = status_of_err(herr);
+  if (rc == SMKI_OK) {
+    *n_cells = nc;
+    if (cell_keys && cell_start && cell_count) {
+      e = bucket_cells_table(n, nc, g, scr, cell_keys, cell_start, cell_count, order, q);
+      if (e == hipSuccess) e = hipStreamSynchronize(q);
+      if (e != hipSuccess) rc = smki_hip_error(e);
+    }
+  }
+  (void)hipFreeAsync(base, q);
+  (void)hipStreamSynchronize(q);
+  return rc;
+}
+
+size_t smki_loss_workspace_bytes(int64_t n_train, int64_t n_query, int32_t K);
+
+}  // extern "C"

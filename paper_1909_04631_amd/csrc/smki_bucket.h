@@ -1,0 +1,66 @@
+// Bucketing structures shared by the HIP translation units (internal).
+#pragma once
+#include "smki_internal.h"
+
+#define SMKI_COORD_LIM (1 << 20)
+#define SMKI_MAX_SAMPLES_PER_RAY (1 << 20)
+
+// Dense grid of map blocks covering a bounding box of voxel indices.
+struct BucketGeom {
+  float res;        // voxel edge
+  int32_t B;        // voxels per block edge (power of two)
+  int32_t log2B;
+  int32_t blo[3];   // lowest block coordinate of the grid
+  int32_t nb[3];    // blocks per axis
+  int64_t n_blocks; // nb[0] * nb[1] * nb[2]
+  int32_t key_bits; // significant bits of a row key
+};
+
+// One sorted point set (hits, free samples, or explicit rows).
+struct PointSet {
+  int64_t n;          // rows
+  float4* pts;        // sorted records: xyz relative to the row's block corner, label bits
+  int32_t* dense;     // [n_blocks] grid block -> slot, -1 if the block holds no row
+  int32_t* slot_lin;  // [slots] grid linear index of each slot
+  int32_t* prefix;    // [slots][B^3 + 1] first row of each voxel of the block (absolute)
+  int32_t* d_nslots;  // device scalar: number of slots
+};
+
+// Scratch used while building a point set (capacity = rows of the set).
+struct BucketScratch {
+  void* keys;         // u32 or u64 keys
+  void* akeys;
+  uint32_t* idx;
+  uint32_t* aidx;
+  float4* rec;        // unsorted records
+  int32_t* flag;
+  int32_t* slot_excl;
+  void* sort_tmp;
+  void* scan_tmp;
+};
+
+hipError_t launch_count(const float* xyz, const int32_t* label, int64_t n, const int64_t* scan_off,
+                        const float* origins, int32_t S, float res, float step, int32_t K,
+                        int64_t* nfree, int32_t* kept, int32_t* bbox, uint32_t* err,
+                        hipStream_t st);
+hipError_t launch_fill_i32(int32_t* p, int64_t n, int32_t v, hipStream_t st);
+hipError_t launch_free_positions(const float* xyz, int64_t n, const int64_t* off, int64_t nf,
+                                 const int64_t* scan_off, const float* origins, int32_t S,
+                                 float step, float4* out, int64_t* parent, hipStream_t st);
+hipError_t bucket_hits(const float* xyz, const int32_t* label, int64_t n, const int32_t* kept,
+                       const int32_t* kpos, const BucketGeom& g, PointSet& ps, BucketScratch& scr,
+                       uint32_t* err, hipStream_t st);
+hipError_t bucket_frees(const float* xyz, int64_t n, const int64_t* off, const int64_t* scan_off,
+                        const float* origins, int32_t S, float step, int32_t free_class,
+                        const BucketGeom& g, PointSet& ps, BucketScratch& scr, uint32_t* err,
+                        hipStream_t st);
+hipError_t bucket_rows(const float* xyz, const int32_t* label, int64_t n, const BucketGeom& g,
+                       PointSet& ps, BucketScratch& scr, uint32_t* err, hipStream_t st);
+hipError_t bucket_cells_sort(const float* xyz, int64_t n, const BucketGeom& g, BucketScratch& scr,
+                             uint32_t* err, int32_t* d_ncells, hipStream_t st);
+hipError_t bucket_cells_table(int64_t n, int64_t ncells, const BucketGeom& g, BucketScratch& scr,
+                              uint64_t* cell_keys, int32_t* cell_start, int32_t* cell_count,
+                              int32_t* order, hipStream_t st);
+hipError_t launch_free_xyz(const float* xyz, int64_t n, const int64_t* off, int64_t nf,
+                           const float* origin_dev, float step, float* out, int64_t* parent,
+                           hipStream_t st);

@@ -1,0 +1,57 @@
+// Internal declarations shared by the HIP translation units of libsmki.
+// Not part of the public C ABI (that is include/smki.h).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include <stddef.h>
+
+#define SMKI_WAVE 64
+
+// ---------------------------------------------------------------------------
+// error plumbing
+// ---------------------------------------------------------------------------
+#define SMKI_HIP_TRY(expr)                                   \
+  do {                                                       \
+    hipError_t e__ = (expr);                                 \
+    if (e__ != hipSuccess) return smki_hip_error(e__);       \
+  } while (0)
+
+int32_t smki_hip_error(hipError_t e);
+
+// device error bits (sticky flag, OR-ed by kernels)
+enum : uint32_t {
+  DEVERR_LABEL = 1u << 0,      // label outside {-1, 0..K-1}
+  DEVERR_NONFINITE = 1u << 1,  // non-finite coordinate
+  DEVERR_RAY = 1u << 2,        // more than 2^20 free samples on one beam
+  DEVERR_RANGE = 1u << 3,      // voxel index outside [-2^20, 2^20)
+  DEVERR_HASH = 1u << 4,       // block hash full
+};
+
+// ---------------------------------------------------------------------------
+// scan / sort primitives (scan.hip, radix_sort.hip)
+// ---------------------------------------------------------------------------
+// exclusive prefix sum of n elements (in may equal out); *total (device,
+// nullable) receives the sum.  tmp must hold scan_tmp_bytes(n) bytes.
+size_t scan_tmp_bytes(int64_t n);
+hipError_t scan_excl_i64(const int64_t* in, int64_t* out, int64_t n, int64_t* total, void* tmp,
+                         hipStream_t st);
+hipError_t scan_excl_i32(const int32_t* in, int32_t* out, int64_t n, int32_t* total, void* tmp,
+                         hipStream_t st);
+
+// stable LSD radix sort of (key, value) pairs on the low `bits` bits of the
+// keys.  keys/vals are sorted in place; alt_* are scratch of the same size.
+size_t radix_tmp_bytes(int64_t n);
+hipError_t radix_sort_u32(uint32_t* keys, uint32_t* vals, uint32_t* alt_keys, uint32_t* alt_vals,
+                          int64_t n, int bits, void* tmp, hipStream_t st);
+hipError_t radix_sort_u64(uint64_t* keys, uint32_t* vals, uint64_t* alt_keys, uint32_t* alt_vals,
+                          int64_t n, int bits, void* tmp, hipStream_t st);
+
+// ---------------------------------------------------------------------------
+// small device helpers
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ int64_t floordiv_i64(int64_t a, int64_t b) {
+  int64_t q = a / b;
+  return (a % b != 0 && ((a < 0) != (b < 0))) ? q - 1 : q;
+}
+
+static inline int64_t ceil_div_i64(int64_t a, int64_t b) { return (a + b - 1) / b; }
