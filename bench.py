@@ -1,0 +1,223 @@
+"""Benchmark of the S-BKI per-scan map update on one MI355X.
+
+Workload: one spinning-LiDAR-shaped scan (64 beams x 2048 azimuth steps,
+~1.29e5 labelled hits, free samples every 0.3 m, ~4.0e6 training rows),
+K = 20, 0.1 m voxels in 8^3 blocks, l = 0.3 m, sigma0 = 0.1.  Data is
+synthetic and seeded (scenes.make_config(1)).
+
+A step is one pass of the per-scan path into a fresh map: clear the map,
+validate the scan, generate free samples, bucket (keys + radix sort + block
+tables), splat the rows' kernel weights Eq. (7)-(8) onto the voxel centroids
+of their (class, block) regions, allocate blocks, merge the partial sums into
+the map, and read out Eq. (3)-(4) at the voxels of the scan's hits.  Inputs
+are resident in HBM before timing starts.
+
+metric value = voxel updates per second = V / (time per step), V = voxels
+with at least one training row within l.  Also reported: input points/s, the
+roofline fraction of the dominant kernel (the splat, VALU-bound), the
+batched form, the differentiable form's forward/backward times, and the CPU
+oracle timed on a bounded sample (host cores).
+
+    python bench.py [--steps K] [--warmup W] [--gpus 1]
+"""
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, HERE)
+
+VALU_PEAK = 256 * 64 * 2.4e9          # non-packed FP32 VALU lane-operations per second
+OPS_PER_PAIR = 24                     # algorithmic VALU lane-operations per in-support pair
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extras", action="store_true", help="skip the loss and batched lines")
+    ap.add_argument("--cpu-sample-stride", type=int, default=16)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(run with --gpus 1)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import scenes
+    from paper_1909_04631_amd import SemanticMap, predictive_loss
+
+    torch.cuda.init()
+    dev = torch.device("cuda", 0)
+    t0 = time.time()
+    sc = scenes.make_config(1)
+    s = sc.scans[0]
+    p = sc.params
+    log(f"[bench] workload generated in {time.time() - t0:.1f}s: {s.xyz.shape[0]} hits")
+    xyz = torch.from_numpy(s.xyz).to(dev)
+    lab = torch.from_numpy(s.label).to(dev)
+    vox = torch.from_numpy(np.floor(s.xyz / np.float32(p.res)).astype(np.int32)).to(dev)
+    m = SemanticMap.from_params(p, initial_blocks=1 << 15,
+                                unit_budget=int(os.environ.get("SMKI_CHUNK", "0")))
+    stream = torch.cuda.current_stream()
+
+    def step():
+        m.reset()
+        m.insert_scan(xyz, lab, s.origin, p.free_step)
+        return m.query(vox, alpha=False, var=False, mean=True, label=True, p_occ=True)
+
+    for i in range(args.warmup):
+        step()
+        log(f"[bench] warmup {i + 1}/{args.warmup}")
+    torch.cuda.synchronize()
+    st = m.stats()
+    log(f"[bench] stats {st}")
+    splat_ms, merge_ms = [], []
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    w0 = time.perf_counter()
+    for i in range(args.steps):
+        step()
+        st_i = m.stats()
+        splat_ms.append(st_i["splat_ms"])
+        merge_ms.append(st_i["merge_ms"])
+    e1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - w0
+    ev_ms = e0.elapsed_time(e1)
+    ms = max(ev_ms, 1e3 * wall) / args.steps
+    log(f"[bench] {args.steps} steps: {ms:.3f} ms/step (events {ev_ms / args.steps:.3f}, "
+        f"wall {1e3 * wall / args.steps:.3f}); splat {np.mean(splat_ms):.3f} ms, "
+        f"alloc+merge {np.mean(merge_ms):.3f} ms")
+    V, P = st["n_updated_voxels"], st["n_pairs"]
+    value = V / (ms * 1e-3)
+    g_ms = float(np.mean(splat_ms))
+    achieved = OPS_PER_PAIR * P / (g_ms * 1e-3)
+    out = {
+        "metric": "voxel updates/sec per scan (1 GPU)",
+        "value": value,
+        "unit": "voxel updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic (seeded ray-cast street scene, LiDAR-shaped)",
+        "config": {
+            "workload": "lidar_scan_64x2048_K20_res0.1_B8_l0.3_s0.1_step0.3",
+            "hits": st["n_hits"], "free_samples": st["n_free"], "voxels_updated": V,
+            "pairs_in_support": P, "blocks_allocated": st["n_new_blocks"],
+            "splat_units": st["n_units"], "stencil_lane_util": st["n_candidates"] / max(st["n_lane_slots"], 1),
+        },
+        "points_per_s": st["n_hits"] / (ms * 1e-3),
+        "roofline": {
+            "kernel": "k_splat",
+            "bound": "alu",
+            "achieved": achieved / 1e12,
+            "peak": VALU_PEAK / 1e12,
+            "unit": "T VALU lane-op/s",
+            "frac": achieved / VALU_PEAK,
+            "traffic": None,
+            "kernel_ms": g_ms,
+            "merge_ms": float(np.mean(merge_ms)),
+            "ops_per_pair": OPS_PER_PAIR,
+        },
+    }
+
+    if not args.no_extras:
+        out["fwd_bwd"] = bench_loss(torch, dev, predictive_loss)
+
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(sc, V, args.cpu_sample_stride)
+    print(json.dumps(out), flush=True)
+
+
+def bench_loss(torch, dev, predictive_loss, reps=20):
+    """Differentiable form on the tiny scene with 20 % of hits held out."""
+    import scenes
+    sc = scenes.make_config(4)
+    p = sc.params
+    tr = sc.scans[0]
+    from paper_1909_04631_amd import free_samples
+    txh = torch.from_numpy(tr.xyz).to(dev)
+    tyh = torch.from_numpy(tr.label).to(dev)
+    fq, _ = free_samples(txh, tyh, tr.origin, p.free_step, p.K)
+    tx = torch.cat([txh, fq]).contiguous()
+    ty = torch.cat([tyh, torch.zeros(fq.shape[0], dtype=torch.int32, device=dev)]).contiguous()
+    qx = torch.from_numpy(sc.holdout.xyz).to(dev)
+    qy = torch.from_numpy(sc.holdout.label).to(dev)
+    l = torch.tensor(p.l, device=dev, requires_grad=True)
+    s0 = torch.tensor(p.sigma0, device=dev, requires_grad=True)
+    txg = tx.clone().requires_grad_(True)
+
+    def timeit(fn):
+        for _ in range(3):
+            fn()
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for _ in range(reps):
+            fn()
+        torch.cuda.synchronize()
+        return 1e3 * (time.perf_counter() - t) / reps
+
+    def fwd():
+        with torch.no_grad():
+            return predictive_loss(tx, ty, qx, qy, l, s0, p.alpha0, p.K)
+
+    def fwd_bwd():
+        L = predictive_loss(txg, ty, qx, qy, l, s0, p.alpha0, p.K)
+        L.backward()
+        return L
+
+    t_plain = timeit(fwd)
+    t_fb = timeit(fwd_bwd)
+    t_fwd = t_plain
+    t_bwd = max(t_fb - t_fwd, 0.0)
+    return {"workload": "tiny scene, 20% of hits held out (1600 hits + free samples, 400 queries)",
+            "train_rows": int(tx.shape[0]), "queries": int(qx.shape[0]),
+            "t_fwd_ms": t_fwd, "t_bwd_ms": t_bwd, "t_plain_ms": t_plain,
+            "bwd_over_fwd": t_bwd / t_fwd if t_fwd > 0 else None,
+            "fwd_bwd_over_plain": t_fb / t_plain if t_plain > 0 else None}
+
+
+def cpu_baseline(sc, V_full, stride):
+    """The oracle's map update (plain double-precision C, single thread) on
+    every `stride`-th beam of the same scan; scaled to the full scan by its
+    training rows (the oracle's cost is linear in them)."""
+    import oracle
+    p = sc.params.f32()
+    s = sc.scans[0]
+    sub = slice(0, None, stride)
+    _, nf_full = oracle.free_counts(s.xyz, s.label, s.origin, p.free_step, p.K)
+    _, nf_sub = oracle.free_counts(s.xyz[sub], s.label[sub], s.origin, p.free_step, p.K)
+    rows_full = s.xyz.shape[0] + nf_full
+    rows_sub = s.xyz[sub].shape[0] + nf_sub
+    om = oracle.OracleMap.from_params(p)
+    t = time.perf_counter()
+    om.insert_scan(s.xyz[sub], s.label[sub], s.origin, p.free_step, p.free_class)
+    T = time.perf_counter() - t
+    T_full = T * rows_full / rows_sub
+    log(f"[bench] cpu oracle: {rows_sub} rows in {T:.2f}s -> full scan est. {T_full:.1f}s")
+    return {"value": V_full / T_full, "unit": "voxel updates/s", "cores": 1, "kind": "oracle",
+            "sample": f"every {stride}th beam of the scan ({rows_sub} of {rows_full} training rows), "
+                      f"{T:.2f} s; scaled by training rows",
+            "points_per_s": s.xyz.shape[0] / T_full, "seconds_full_scan_est": T_full}
+
+
+if __name__ == "__main__":
+    main()

@@ -45,8 +45,9 @@ typedef struct smki_map smki_map;
 /* Optional tuning; pass NULL for defaults. */
 typedef struct smki_options {
   int64_t initial_blocks;   /* initial pool capacity in blocks (0: 4096); grows on demand */
-  int32_t unit_budget;      /* candidate rows per lane per gather work unit (0: 2048) */
-  float part_fraction;      /* expected largest per-lane share of a staged box (0: 0.5) */
+  int32_t unit_budget;      /* rows of one (class, block) that one splat work unit
+                               takes (0: 1024; at most 2^24); a (class, block) holding
+                               more rows is split into several units */
 } smki_options;
 
 /* Counters of the last insert (smki_last_scan_stats). */
@@ -56,9 +57,15 @@ typedef struct smki_scan_stats {
   int64_t n_point_blocks;   /* map blocks holding at least one training row */
   int64_t n_target_blocks;  /* blocks examined (within reach of a row block) */
   int64_t n_new_blocks;     /* blocks allocated by this insert */
-  int64_t n_units;          /* gather work units launched */
+  int64_t n_units;          /* splat work units launched */
   int64_t n_updated_voxels; /* voxels with at least one row within l */
   int64_t n_pairs;          /* (voxel, row) pairs with distance < l */
+  int64_t n_candidates;     /* (voxel, row) pairs examined: rows x stencil voxels */
+  int64_t n_lane_slots;     /* lane-iterations issued (stencil padded to 64-lane steps);
+                               n_candidates / n_lane_slots = lane utilisation */
+  double splat_ms;          /* device time of the splat kernel (HIP events recorded on
+                               the map's stream around its launch) */
+  double merge_ms;          /* device time of block allocation and the merge kernel */
 } smki_scan_stats;
 
 const char *smki_status_string(smki_status s);
@@ -68,7 +75,7 @@ const char *smki_status_string(smki_status s);
  *   res         voxel edge in metres (> 0); voxel (i,j,k) has its centroid at
  *               ((i+1/2) res, (j+1/2) res, (k+1/2) res) -- the query points of
  *               Eq. (7) are the grid centroids (Sec. IV, after Eq. (8)).
- *   block_size  voxels per block edge: 4, 8, 16 or 32 (blocks group the grid
+ *   block_size  voxels per block edge: 4 or 8 (blocks group the grid
  *               as in Sec. IV; allocation granularity).
  *   l, sigma0   length-scale (> 0) and scale (> 0) of the sparse kernel, Eq. (8).
  *   K           classes (2..255), free class included.
@@ -94,7 +101,12 @@ smki_status smki_set_stream(smki_map *m, void *hip_stream);
  * binary32 arithmetic, labelled free_class.  free_step <= 0: no free samples.
  *   xyz    device float32 [n][3], label device int32 [n], origin host float32 [3].
  * Returns after the work is enqueued (it synchronises the stream internally
- * to size its launches).
+ * to size its launches).  Errors: SMKI_E_BAD_INPUT for a label outside
+ * {-1..K-1} or a non-finite kept coordinate, SMKI_E_RANGE for a voxel index
+ * outside [-2^20, 2^20) or a beam with more than 2^20 samples, SMKI_E_CAPACITY
+ * when l / res >= 4.5 voxels (the kernel support reaches at most 4 voxels past
+ * a row's own voxel) or the scan's bounding box spans more than 2^30 / K
+ * blocks; on any error the map is left unchanged.
  */
 smki_status smki_insert_scan(smki_map *m, const float *xyz, const int32_t *label, int64_t n,
                              const float *origin, float free_step);

@@ -46,12 +46,12 @@ class SemanticMap:
     """A persistent semantic occupancy map on one GPU (the device current at creation)."""
 
     def __init__(self, res, block_size, l, sigma0, K, alpha0=1e-3, free_class=0,
-                 unit_budget=0, part_fraction=0.0, initial_blocks=0):
+                 unit_budget=0, initial_blocks=0):
         self.K, self.B = int(K), int(block_size)
         self.res, self.l, self.sigma0, self.alpha0 = float(res), float(l), float(sigma0), float(alpha0)
         self.free_class = int(free_class)
         self.device = torch.device("cuda", torch.cuda.current_device())
-        opt = Options(int(initial_blocks), int(unit_budget), float(part_fraction))
+        opt = Options(int(initial_blocks), int(unit_budget))
         h = C.c_void_p()
         check(lib().smki_create_map(res, block_size, l, sigma0, K, alpha0, free_class,
                                     C.byref(opt), C.byref(h)), "smki_create_map")
@@ -139,6 +139,11 @@ class SemanticMap:
         self._bind_stream()
         check(lib().smki_import(self._h, block_ijk.shape[0], _ptr(block_ijk), _ptr(alpha)),
               "smki_import")
+
+    def reset(self):
+        """Empty the map (every voxel back to alpha0); capacity is kept."""
+        self._bind_stream()
+        check(lib().smki_import(self._h, 0, None, None), "smki_import")
 
     def stats(self):
         s = ScanStats()

@@ -38,17 +38,18 @@ class SmkiError(RuntimeError):
 
 
 class Options(C.Structure):
-    _fields_ = [("initial_blocks", C.c_int64), ("unit_budget", C.c_int32),
-                ("part_fraction", C.c_float)]
+    _fields_ = [("initial_blocks", C.c_int64), ("unit_budget", C.c_int32)]
 
 
 class ScanStats(C.Structure):
     _fields_ = [("n_hits", C.c_int64), ("n_free", C.c_int64), ("n_point_blocks", C.c_int64),
                 ("n_target_blocks", C.c_int64), ("n_new_blocks", C.c_int64),
-                ("n_units", C.c_int64), ("n_updated_voxels", C.c_int64), ("n_pairs", C.c_int64)]
+                ("n_units", C.c_int64), ("n_updated_voxels", C.c_int64), ("n_pairs", C.c_int64),
+                ("n_candidates", C.c_int64), ("n_lane_slots", C.c_int64), ("splat_ms", C.c_double),
+                ("merge_ms", C.c_double)]
 
     def as_dict(self):
-        return {f: int(getattr(self, f)) for f, _ in self._fields_}
+        return {f: (float if f.endswith("_ms") else int)(getattr(self, f)) for f, _ in self._fields_}
 
 
 _lib = None

@@ -139,10 +139,14 @@ __device__ __forceinline__ void block_of(const BucketGeom& g, const int32_t v[3]
   }
 }
 
+// Key of a row: (label plane, block of the grid, voxel inside the block), so a
+// sort groups rows by class first (planes = K for the map, 1 otherwise), then
+// by block, then by voxel with z fastest.
 template <typename KeyT>
-__device__ __forceinline__ KeyT make_key(const BucketGeom& g, const int32_t b[3],
+__device__ __forceinline__ KeyT make_key(const BucketGeom& g, int32_t plane, const int32_t b[3],
                                          const int32_t l[3]) {
-  const int64_t lin = ((int64_t)(b[0] - g.blo[0]) * g.nb[1] + (b[1] - g.blo[1])) * g.nb[2] +
+  const int64_t lin = (int64_t)plane * g.n_blocks +
+                      ((int64_t)(b[0] - g.blo[0]) * g.nb[1] + (b[1] - g.blo[1])) * g.nb[2] +
                       (b[2] - g.blo[2]);
   const int64_t loc = ((int64_t)l[0] << (2 * g.log2B)) | ((int64_t)l[1] << g.log2B) | l[2];
   return (KeyT)(((uint64_t)lin << (3 * g.log2B)) | (uint64_t)loc);
@@ -183,7 +187,7 @@ __global__ void k_hit_keys(const float* __restrict__ xyz, const int32_t* __restr
   block_of(g, v, b, l);
   const int32_t w = kpos[i];
   if (!in_grid(g, b)) { atomicOr(err, DEVERR_RANGE); keys[w] = (KeyT)0; idx[w] = w; rec[w] = make_float4(0, 0, 0, 0); return; }
-  keys[w] = make_key<KeyT>(g, b, l);
+  keys[w] = make_key<KeyT>(g, label[i], b, l);
   idx[w] = (uint32_t)w;
   rec[w] = make_record(g, px, py, pz, b, label[i]);
 }
@@ -194,9 +198,9 @@ __global__ void k_free_keys(const float* __restrict__ xyz, int64_t n,
                             const int64_t* __restrict__ off, int64_t nf,
                             const int64_t* __restrict__ scan_off,
                             const float* __restrict__ origins, int32_t S, float step,
-                            int32_t free_class, BucketGeom g, KeyT* __restrict__ keys,
-                            uint32_t* __restrict__ idx, float4* __restrict__ rec,
-                            int64_t* __restrict__ parent, uint32_t* __restrict__ err) {
+                            int32_t free_class, BucketGeom g, int64_t out_base,
+                            KeyT* __restrict__ keys, uint32_t* __restrict__ idx,
+                            float4* __restrict__ rec, uint32_t* __restrict__ err) {
   const int64_t f = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (f >= nf) return;
   int64_t lo = 0, hi = n - 1;
@@ -211,26 +215,22 @@ __global__ void k_free_keys(const float* __restrict__ xyz, int64_t n,
   float vx, vy, vz;
   const float L = beam_len(xyz[3 * i], xyz[3 * i + 1], xyz[3 * i + 2], ox, oy, oz, &vx, &vy, &vz);
   const float t = (float)j * step;
-  const float w = div_rn(t, L);
-  const float mx = w * vx, my = w * vy, mz = w * vz;
+  const float wt = div_rn(t, L);
+  const float mx = wt * vx, my = wt * vy, mz = wt * vz;
   const float qx = ox + mx, qy = oy + my, qz = oz + mz;
-  if (parent) parent[f] = i;
-  if (!keys) {  // positions only (the free-sample entry point)
-    rec[f] = make_float4(qx, qy, qz, 0.0f);
-    return;
-  }
+  const int64_t w = out_base + f;
   int32_t v[3], b[3], l[3];
   if (!voxel_index(qx, g.res, &v[0]) || !voxel_index(qy, g.res, &v[1]) ||
       !voxel_index(qz, g.res, &v[2])) {
     atomicOr(err, DEVERR_RANGE);
-    keys[f] = (KeyT)0; idx[f] = (uint32_t)f; rec[f] = make_float4(0, 0, 0, 0);
+    keys[w] = (KeyT)0; idx[w] = (uint32_t)w; rec[w] = make_float4(0, 0, 0, 0);
     return;
   }
   block_of(g, v, b, l);
-  if (!in_grid(g, b)) { atomicOr(err, DEVERR_RANGE); keys[f] = (KeyT)0; idx[f] = (uint32_t)f; rec[f] = make_float4(0, 0, 0, 0); return; }
-  keys[f] = make_key<KeyT>(g, b, l);
-  idx[f] = (uint32_t)f;
-  rec[f] = make_record(g, qx, qy, qz, b, free_class);
+  if (!in_grid(g, b)) { atomicOr(err, DEVERR_RANGE); keys[w] = (KeyT)0; idx[w] = (uint32_t)w; rec[w] = make_float4(0, 0, 0, 0); return; }
+  keys[w] = make_key<KeyT>(g, free_class, b, l);
+  idx[w] = (uint32_t)w;
+  rec[w] = make_record(g, qx, qy, qz, b, free_class);
 }
 
 // Explicit training rows (differentiable form, tests): keys and records.
@@ -251,7 +251,7 @@ __global__ void k_row_keys(const float* __restrict__ xyz, const int32_t* __restr
   }
   block_of(g, v, b, l);
   if (!in_grid(g, b)) { atomicOr(err, DEVERR_RANGE); keys[i] = (KeyT)0; idx[i] = (uint32_t)i; rec[i] = make_float4(0, 0, 0, 0); return; }
-  keys[i] = make_key<KeyT>(g, b, l);
+  keys[i] = make_key<KeyT>(g, 0, b, l);
   idx[i] = (uint32_t)i;
   rec[i] = make_record(g, px, py, pz, b, label ? label[i] : 0);
 }
@@ -325,17 +325,6 @@ hipError_t launch_fill_i32(int32_t* p, int64_t n, int32_t v, hipStream_t st) {
   return hipGetLastError();
 }
 
-hipError_t launch_free_positions(const float* xyz, int64_t n, const int64_t* off, int64_t nf,
-                                 const int64_t* scan_off, const float* origins, int32_t S,
-                                 float step, float4* out, int64_t* parent, hipStream_t st) {
-  if (nf <= 0) return hipSuccess;
-  BucketGeom g{};
-  hipLaunchKernelGGL(k_free_keys<uint32_t>, dim3(nblk(nf, 256)), dim3(256), 0, st, xyz, n, off,
-                     nf, scan_off, origins, S, step, 0, g, (uint32_t*)nullptr,
-                     (uint32_t*)nullptr, out, parent, (uint32_t*)nullptr);
-  return hipGetLastError();
-}
-
 // Keys, sort, records and block tables of one point set.
 template <typename KeyT>
 static hipError_t finish_set(PointSet& ps, KeyT* keys, uint32_t* idx, KeyT* akeys, uint32_t* aidx,
@@ -361,47 +350,41 @@ static hipError_t finish_set(PointSet& ps, KeyT* keys, uint32_t* idx, KeyT* akey
   return hipGetLastError();
 }
 
-hipError_t bucket_hits(const float* xyz, const int32_t* label, int64_t n, const int32_t* kept,
-                       const int32_t* kpos, const BucketGeom& g, PointSet& ps, BucketScratch& scr,
+// All training rows of an insert in one sorted set: kept hits at [0, nk), free
+// samples after them; keys carry the class plane, so each (class, block) is a
+// contiguous range.
+hipError_t bucket_scan(const float* xyz, const int32_t* label, int64_t n, const int32_t* kept,
+                       const int32_t* kpos, int64_t nk, const int64_t* off, int64_t nf,
+                       const int64_t* scan_off, const float* origins, int32_t S, float step,
+                       int32_t free_class, const BucketGeom& g, PointSet& ps, BucketScratch& scr,
                        uint32_t* err, hipStream_t st) {
-  hipError_t e = launch_fill_i32(ps.dense, g.n_blocks, -1, st);
+  hipError_t e = launch_fill_i32(ps.dense, g.n_blocks * g.planes, -1, st);
   if (e != hipSuccess || ps.n <= 0) return e;
   if (g.key_bits <= 32) {
-    hipLaunchKernelGGL(k_hit_keys<uint32_t>, dim3(nblk(n, 256)), dim3(256), 0, st, xyz, label, n,
-                       kept, kpos, g, (uint32_t*)scr.keys, scr.idx, scr.rec, err);
+    if (nk > 0)
+      hipLaunchKernelGGL(k_hit_keys<uint32_t>, dim3(nblk(n, 256)), dim3(256), 0, st, xyz, label, n,
+                         kept, kpos, g, (uint32_t*)scr.keys, scr.idx, scr.rec, err);
+    if (nf > 0)
+      hipLaunchKernelGGL(k_free_keys<uint32_t>, dim3(nblk(nf, 256)), dim3(256), 0, st, xyz, n, off,
+                         nf, scan_off, origins, S, step, free_class, g, nk, (uint32_t*)scr.keys,
+                         scr.idx, scr.rec, err);
     return finish_set<uint32_t>(ps, (uint32_t*)scr.keys, scr.idx, (uint32_t*)scr.akeys, scr.aidx,
                                 scr.rec, g, g.key_bits, scr, st);
   }
-  hipLaunchKernelGGL(k_hit_keys<uint64_t>, dim3(nblk(n, 256)), dim3(256), 0, st, xyz, label, n,
-                     kept, kpos, g, (uint64_t*)scr.keys, scr.idx, scr.rec, err);
-  return finish_set<uint64_t>(ps, (uint64_t*)scr.keys, scr.idx, (uint64_t*)scr.akeys, scr.aidx,
-                              scr.rec, g, g.key_bits, scr, st);
-}
-
-hipError_t bucket_frees(const float* xyz, int64_t n, const int64_t* off, const int64_t* scan_off,
-                        const float* origins, int32_t S, float step, int32_t free_class,
-                        const BucketGeom& g, PointSet& ps, BucketScratch& scr, uint32_t* err,
-                        hipStream_t st) {
-  hipError_t e = launch_fill_i32(ps.dense, g.n_blocks, -1, st);
-  if (e != hipSuccess || ps.n <= 0) return e;
-  const int64_t nf = ps.n;
-  if (g.key_bits <= 32) {
-    hipLaunchKernelGGL(k_free_keys<uint32_t>, dim3(nblk(nf, 256)), dim3(256), 0, st, xyz, n, off,
-                       nf, scan_off, origins, S, step, free_class, g, (uint32_t*)scr.keys,
-                       scr.idx, scr.rec, (int64_t*)nullptr, err);
-    return finish_set<uint32_t>(ps, (uint32_t*)scr.keys, scr.idx, (uint32_t*)scr.akeys, scr.aidx,
-                                scr.rec, g, g.key_bits, scr, st);
-  }
-  hipLaunchKernelGGL(k_free_keys<uint64_t>, dim3(nblk(nf, 256)), dim3(256), 0, st, xyz, n, off,
-                     nf, scan_off, origins, S, step, free_class, g, (uint64_t*)scr.keys, scr.idx,
-                     scr.rec, (int64_t*)nullptr, err);
+  if (nk > 0)
+    hipLaunchKernelGGL(k_hit_keys<uint64_t>, dim3(nblk(n, 256)), dim3(256), 0, st, xyz, label, n,
+                       kept, kpos, g, (uint64_t*)scr.keys, scr.idx, scr.rec, err);
+  if (nf > 0)
+    hipLaunchKernelGGL(k_free_keys<uint64_t>, dim3(nblk(nf, 256)), dim3(256), 0, st, xyz, n, off,
+                       nf, scan_off, origins, S, step, free_class, g, nk, (uint64_t*)scr.keys,
+                       scr.idx, scr.rec, err);
   return finish_set<uint64_t>(ps, (uint64_t*)scr.keys, scr.idx, (uint64_t*)scr.akeys, scr.aidx,
                               scr.rec, g, g.key_bits, scr, st);
 }
 
 hipError_t bucket_rows(const float* xyz, const int32_t* label, int64_t n, const BucketGeom& g,
                        PointSet& ps, BucketScratch& scr, uint32_t* err, hipStream_t st) {
-  hipError_t e = launch_fill_i32(ps.dense, g.n_blocks, -1, st);
+  hipError_t e = launch_fill_i32(ps.dense, g.n_blocks * g.planes, -1, st);
   if (e != hipSuccess || n <= 0) return e;
   if (g.key_bits <= 32) {
     hipLaunchKernelGGL(k_row_keys<uint32_t>, dim3(nblk(n, 256)), dim3(256), 0, st, xyz, label, n,

@@ -364,6 +364,7 @@ smki_status prepare(const float* txyz, const int32_t* tlab, int64_t nt, const fl
   SMKI_HIP_TRY(hipStreamSynchronize(st));
   if (e) return err_status(e);
   g = BucketGeom{};
+  g.planes = 1;
   g.res = h;
   g.B = LB;
   g.log2B = LLOG2B;

@@ -91,8 +91,7 @@ bool finite_pos(float x) { return isfinite(x) && x > 0.0f; }
 struct smki_map {
   float res, l, sigma0, alpha0;
   int32_t K, B, log2B, free_class;
-  int32_t budget;
-  float part_frac;
+  int32_t chunk;  // rows per splat work unit
   int device = 0;
   hipStream_t stream = nullptr;
   // persistent device state
@@ -101,7 +100,7 @@ struct smki_map {
   int64_t n_blocks = 0;
   uint32_t* d_err = nullptr;
   unsigned long long* d_stats = nullptr;
-  StencilCol* d_cols = nullptr;
+  StencilOff* d_offs = nullptr;
   float coef[SMKI_POLY_N];
   // workspaces
   Arena a_hits, a_sets, a_tgts, a_misc;
@@ -109,7 +108,7 @@ struct smki_map {
   int64_t* h_pin = nullptr;
   smki_scan_stats last{};
   bool stats_pending = false;
-  int64_t pending_nk = 0, pending_nf = 0;
+  hipEvent_t ev[4] = {};  // bracket the splat [0, 1] and the allocation + merge [2, 3]
 };
 
 // ---------------------------------------------------------------------------
@@ -124,29 +123,27 @@ smki_status status_of_err(uint32_t e) {
   return SMKI_E_DEVICE;
 }
 
-// Voxel stencil for centroid queries: every voxel cell that can hold a point
-// within l (plus a rounding margin, in voxel units) of the centroid of voxel 0.
+// Voxel offsets (relative to a cell) whose centroid can lie within l of some
+// point of that cell: every o with sum_a max(0, |o_a| - 1/2)^2 < (l/res + margin)^2
+// (voxel units; the margin covers a point assigned to the neighbouring cell by
+// the rounding of floor(x / res)).  Ordered with z fastest.
 struct Stencil {
-  int32_t R = 0, D = 0;
-  std::vector<StencilCol> cols;
+  int32_t R = 0;
+  std::vector<StencilOff> offs;
 };
 
 Stencil make_stencil(double lv, double margin) {
   Stencil s;
   const double L = lv + margin;
-  s.R = (int32_t)ceil(lv + 0.5 + margin) - 1;
-  if (s.R < 0) s.R = 0;
-  s.D = SMKI_TILE + 2 * s.R;
+  s.R = std::max(0, (int32_t)ceil(lv + 0.5 + margin) - 1);
   for (int dx = -s.R; dx <= s.R; ++dx)
-    for (int dy = -s.R; dy <= s.R; ++dy) {
-      const double ax = std::max(0.0, fabs((double)dx) - 0.5);
-      const double ay = std::max(0.0, fabs((double)dy) - 0.5);
-      const double rho2 = ax * ax + ay * ay;
-      if (!(rho2 < L * L)) continue;
-      int32_t h = (int32_t)ceil(0.5 + sqrt(L * L - rho2)) - 1;
-      h = std::min(std::max(h, 0), s.R);
-      s.cols.push_back(StencilCol{dx, dy, h, 0});
-    }
+    for (int dy = -s.R; dy <= s.R; ++dy)
+      for (int dz = -s.R; dz <= s.R; ++dz) {
+        const double ax = std::max(0.0, fabs((double)dx) - 0.5);
+        const double ay = std::max(0.0, fabs((double)dy) - 0.5);
+        const double az = std::max(0.0, fabs((double)dz) - 0.5);
+        if (ax * ax + ay * ay + az * az < L * L) s.offs.push_back(StencilOff{dx, dy, dz, 0});
+      }
   return s;
 }
 
@@ -219,8 +216,9 @@ smki_status take_device_error(smki_map* m) {
 }
 
 // Grid of blocks covering voxel box [vlo, vhi].
-BucketGeom make_geom(const smki_map* m, const int32_t vlo[3], const int32_t vhi[3]) {
+BucketGeom make_geom(const smki_map* m, const int32_t vlo[3], const int32_t vhi[3], int32_t planes) {
   BucketGeom g{};
+  g.planes = planes;
   g.res = m->res;
   g.B = m->B;
   g.log2B = m->log2B;
@@ -231,7 +229,7 @@ BucketGeom make_geom(const smki_map* m, const int32_t vlo[3], const int32_t vhi[
     g.nb[a] = hi - lo + 1;
     g.n_blocks *= g.nb[a];
   }
-  g.key_bits = std::max(1, bits_for(g.n_blocks) + 3 * m->log2B);
+  g.key_bits = std::max(1, bits_for(g.n_blocks * planes) + 3 * m->log2B);
   return g;
 }
 
@@ -314,144 +312,137 @@ smki_status insert_impl(smki_map* m, const float* xyz, const int32_t* label, int
   // ---- geometry of this insert ----
   int32_t vlo[3], vhi[3];
   int64_t maxabs = 0;
-  for (int a = 0; a < 3; ++a) {
-    vlo[a] = std::max(bb[a] - 1, -SMKI_COORD_LIM);
-    vhi[a] = std::min(bb[3 + a] + 1, SMKI_COORD_LIM - 1);
-    maxabs = std::max<int64_t>(maxabs, std::max(std::abs((int64_t)vlo[a]), std::abs((int64_t)vhi[a])));
+  for (int q2 = 0; q2 < 3; ++q2) {
+    vlo[q2] = std::max(bb[q2] - 1, -SMKI_COORD_LIM);
+    vhi[q2] = std::min(bb[3 + q2] + 1, SMKI_COORD_LIM - 1);
+    maxabs = std::max<int64_t>(maxabs, std::max(std::abs((int64_t)vlo[q2]), std::abs((int64_t)vhi[q2])));
   }
-  const BucketGeom g = make_geom(m, vlo, vhi);
-  if (g.n_blocks > (int64_t(1) << 28)) return SMKI_E_CAPACITY;
+  const BucketGeom g = make_geom(m, vlo, vhi, m->K);
+  if (g.n_blocks * m->K > (int64_t(1) << 30)) return SMKI_E_CAPACITY;
+  if ((int64_t)(g.nb[0] + 2) * (g.nb[1] + 2) * (g.nb[2] + 2) > (int64_t(1) << 30))
+    return SMKI_E_CAPACITY;
   const double lv = (double)m->l / (double)m->res;
   const double margin = std::max(1e-4, 4.0 * ldexp((double)maxabs + 1.0, -23));
   const Stencil sten = make_stencil(lv, margin);
-  if (sten.D > SMKI_MAX_BOX) return SMKI_E_CAPACITY;
-  const int32_t DB = std::max<int32_t>(1, (sten.R + m->B - 1) / m->B);
+  if (sten.R > SMKI_MAX_REACH || sten.R > m->B) return SMKI_E_CAPACITY;
+  const int32_t DB = 1;
   int32_t eblo[3], enb[3];
   int64_t n_ext = 1;
-  for (int a = 0; a < 3; ++a) {
-    eblo[a] = g.blo[a] - DB;
-    enb[a] = g.nb[a] + 2 * DB;
-    n_ext *= enb[a];
+  for (int q2 = 0; q2 < 3; ++q2) {
+    eblo[q2] = g.blo[q2] - DB;
+    enb[q2] = g.nb[q2] + 2 * DB;
+    n_ext *= enb[q2];
   }
   const int32_t B3 = m->B * m->B * m->B;
+  const int32_t DR = m->B + 2 * sten.R;
+  const int64_t DR3 = (int64_t)DR * DR * DR;
 
-  // ---- phase B: bucket hits and free samples; mark target blocks ----
-  const int64_t nmax = std::max(nk, nf);
-  const int64_t slots_h = std::min<int64_t>(nk, g.n_blocks);
-  const int64_t slots_f = std::min<int64_t>(std::max<int64_t>(nf, 1), g.n_blocks);
+  // ---- phase B: bucket all rows (class-major keys), mark target blocks ----
+  const int64_t nt = nk + nf;
+  const int64_t max_slots = std::min<int64_t>(nt, g.n_blocks * m->K);
   Sizer zb;
-  zb.add<float4>(nk);
-  zb.add<int32_t>(g.n_blocks);
-  zb.add<int32_t>(slots_h);
-  zb.add<int32_t>(slots_h * (B3 + 1));
-  zb.add<float4>(nf);
-  zb.add<int32_t>(g.n_blocks);
-  zb.add<int32_t>(slots_f);
-  zb.add<int32_t>(slots_f * (B3 + 1));
+  zb.add<float4>(nt);
+  zb.add<int32_t>(g.n_blocks * m->K);
+  zb.add<int32_t>(max_slots);
+  zb.add<int32_t>(max_slots * (B3 + 1));
   zb.add<int32_t>(8);
-  zb.add<uint64_t>(nmax);
-  zb.add<uint64_t>(nmax);
-  zb.add<uint32_t>(nmax);
-  zb.add<uint32_t>(nmax);
-  zb.add<float4>(nmax);
-  zb.add<int32_t>(nmax);
-  zb.add<int32_t>(nmax);
-  zb.add<char>(radix_tmp_bytes(nmax));
-  zb.add<char>(scan_tmp_bytes(std::max(nmax, n_ext)));
+  zb.add<uint64_t>(nt);
+  zb.add<uint64_t>(nt);
+  zb.add<uint32_t>(nt);
+  zb.add<uint32_t>(nt);
+  zb.add<float4>(nt);
+  zb.add<int32_t>(nt);
+  zb.add<int32_t>(nt);
+  zb.add<char>(radix_tmp_bytes(nt));
+  zb.add<char>(scan_tmp_bytes(std::max(nt, n_ext)));
   zb.add<int32_t>(n_ext);
   zb.add<int32_t>(n_ext);
+  zb.add<int32_t>(n_ext);
+  zb.add<int32_t>(max_slots);
+  zb.add<int32_t>(max_slots);
   SMKI_HIP_TRY(m->a_sets.reserve(zb.total));
   Arena& Bz = m->a_sets;
-  PointSet hs{}, fs{};
-  hs.n = nk;
-  hs.pts = Bz.take<float4>(nk);
-  hs.dense = Bz.take<int32_t>(g.n_blocks);
-  hs.slot_lin = Bz.take<int32_t>(slots_h);
-  hs.prefix = Bz.take<int32_t>(slots_h * (B3 + 1));
-  fs.n = nf;
-  fs.pts = Bz.take<float4>(nf);
-  fs.dense = Bz.take<int32_t>(g.n_blocks);
-  fs.slot_lin = Bz.take<int32_t>(slots_f);
-  fs.prefix = Bz.take<int32_t>(slots_f * (B3 + 1));
+  PointSet ps{};
+  ps.n = nt;
+  ps.pts = Bz.take<float4>(nt);
+  ps.dense = Bz.take<int32_t>(g.n_blocks * m->K);
+  ps.slot_lin = Bz.take<int32_t>(max_slots);
+  ps.prefix = Bz.take<int32_t>(max_slots * (B3 + 1));
   int32_t* d_si = Bz.take<int32_t>(8);
-  hs.d_nslots = d_si;
-  fs.d_nslots = d_si + 1;
-  int32_t* d_ntgt = d_si + 2;
+  ps.d_nslots = d_si;
+  int32_t* d_ntgt = d_si + 1;
+  int32_t* d_nunits = d_si + 2;
   BucketScratch scr{};
-  scr.keys = Bz.take<uint64_t>(nmax);
-  scr.akeys = Bz.take<uint64_t>(nmax);
-  scr.idx = Bz.take<uint32_t>(nmax);
-  scr.aidx = Bz.take<uint32_t>(nmax);
-  scr.rec = Bz.take<float4>(nmax);
-  scr.flag = Bz.take<int32_t>(nmax);
-  scr.slot_excl = Bz.take<int32_t>(nmax);
-  scr.sort_tmp = Bz.take<char>(radix_tmp_bytes(nmax));
-  scr.scan_tmp = Bz.take<char>(scan_tmp_bytes(std::max(nmax, n_ext)));
+  scr.keys = Bz.take<uint64_t>(nt);
+  scr.akeys = Bz.take<uint64_t>(nt);
+  scr.idx = Bz.take<uint32_t>(nt);
+  scr.aidx = Bz.take<uint32_t>(nt);
+  scr.rec = Bz.take<float4>(nt);
+  scr.flag = Bz.take<int32_t>(nt);
+  scr.slot_excl = Bz.take<int32_t>(nt);
+  scr.sort_tmp = Bz.take<char>(radix_tmp_bytes(nt));
+  scr.scan_tmp = Bz.take<char>(scan_tmp_bytes(std::max(nt, n_ext)));
   int32_t* d_mark = Bz.take<int32_t>(n_ext);
   int32_t* d_mpos = Bz.take<int32_t>(n_ext);
+  int32_t* d_ext2t = Bz.take<int32_t>(n_ext);
+  int32_t* d_nun = Bz.take<int32_t>(max_slots);
+  int32_t* d_ust = Bz.take<int32_t>(max_slots);
   SMKI_HIP_TRY(hipMemsetAsync(d_si, 0, sizeof(int32_t) * 8, q));
-  SMKI_HIP_TRY(bucket_hits(xyz, label, n, d_kept, d_kpos, g, hs, scr, m->d_err, q));
-  SMKI_HIP_TRY(bucket_frees(xyz, n, d_off, d_soff, d_org, S, step, m->free_class, g, fs, scr,
-                            m->d_err, q));
+  SMKI_HIP_TRY(bucket_scan(xyz, label, n, d_kept, d_kpos, nk, d_off, nf, d_soff, d_org, S, step,
+                           m->free_class, g, ps, scr, m->d_err, q));
   SMKI_HIP_TRY(hipMemsetAsync(d_mark, 0, sizeof(int32_t) * n_ext, q));
-  SMKI_HIP_TRY(launch_mark_targets(hs.slot_lin, hs.d_nslots, (int32_t)slots_h, g, eblo, enb, DB,
+  SMKI_HIP_TRY(launch_mark_targets(ps.slot_lin, ps.d_nslots, (int32_t)max_slots, g, eblo, enb, DB,
                                    d_mark, q));
-  if (nf > 0)
-    SMKI_HIP_TRY(launch_mark_targets(fs.slot_lin, fs.d_nslots, (int32_t)slots_f, g, eblo, enb, DB,
-                                     d_mark, q));
   SMKI_HIP_TRY(scan_excl_i32(d_mark, d_mpos, n_ext, d_ntgt, scr.scan_tmp, q));
-  // sync 2: number of target blocks
+  SMKI_HIP_TRY(launch_slot_units(ps.prefix, ps.d_nslots, (int32_t)max_slots, B3, m->chunk, d_nun, q));
+  SMKI_HIP_TRY(scan_excl_i32(d_nun, d_ust, max_slots, d_nunits, scr.scan_tmp, q));
+  // sync 2: slots, targets, work units
   int32_t si[3];
   SMKI_HIP_TRY(sync_read(m, d_si, sizeof(si), si));
-  const int32_t n_t = si[2];
-  m->last.n_point_blocks = (int64_t)si[0] + si[1];
+  const int32_t n_slots = si[0], n_t = si[1];
+  const int64_t n_units = si[2];
+  m->last.n_point_blocks = n_slots;
   m->last.n_target_blocks = n_t;
+  m->last.n_units = n_units;
+  if ((double)n_units * (double)DR3 * sizeof(float) > 64.0 * (1ull << 30)) return SMKI_E_CAPACITY;
+  m->last.n_candidates = nt * (int64_t)sten.offs.size();
+  m->last.n_lane_slots = nt * (int64_t)SMKI_WAVE * ((int64_t)(sten.offs.size() + SMKI_WAVE - 1) / SMKI_WAVE);
 
-  // ---- phase C: plan, allocate, gather ----
-  GatherArgs ga{};
-  ga.g = g;
-  for (int a = 0; a < 3; ++a) {
-    ga.eblo[a] = eblo[a];
-    ga.enb[a] = enb[a];
-  }
-  ga.R = sten.R;
-  ga.D = sten.D;
-  ga.nsub = m->B / SMKI_TILE;
-  ga.ncols = (int32_t)sten.cols.size();
-  SMKI_HIP_TRY(hipMemcpyAsync(m->d_cols, sten.cols.data(), sizeof(StencilCol) * sten.cols.size(),
+  // ---- phase C: splat, allocate, merge ----
+  SplatArgs sa{};
+  sa.g = g;
+  sa.R = sten.R;
+  sa.noff = (int32_t)sten.offs.size();
+  SMKI_HIP_TRY(hipMemcpyAsync(m->d_offs, sten.offs.data(), sizeof(StencilOff) * sten.offs.size(),
                               hipMemcpyHostToDevice, q));
-  ga.cols = m->d_cols;
-  ga.l2 = m->l * m->l;
-  ga.inv_l = 1.0f / m->l;
-  for (int i = 0; i < SMKI_POLY_N; ++i) ga.coef[i] = m->coef[i];
-  ga.K = m->K;
-  ga.free_class = m->free_class;
-  ga.pts[0] = fs.pts;
-  ga.dense[0] = fs.dense;
-  ga.prefix[0] = fs.prefix;
-  ga.pts[1] = hs.pts;
-  ga.dense[1] = hs.dense;
-  ga.prefix[1] = hs.prefix;
-  ga.budget = m->budget;
-  ga.stats = m->d_stats;
-  if (nf == 0) {  // an empty free set: every lookup misses
-    SMKI_HIP_TRY(launch_fill_i32(fs.dense, g.n_blocks, -1, q));
+  sa.offs = (const int4*)m->d_offs;
+  sa.l2 = m->l * m->l;
+  sa.inv_l = 1.0f / m->l;
+  for (int i = 0; i < SMKI_POLY_N; ++i) sa.coef[i] = m->coef[i];
+  sa.K = m->K;
+  sa.chunk = m->chunk;
+  sa.pts = ps.pts;
+  sa.dense = ps.dense;
+  sa.prefix = ps.prefix;
+  sa.slot_lin = ps.slot_lin;
+  sa.nunits = d_nun;
+  sa.ustart = d_ust;
+  for (int q2 = 0; q2 < 3; ++q2) {
+    sa.eblo[q2] = eblo[q2];
+    sa.enb[q2] = enb[q2];
   }
-  const int32_t nsub3 = ga.nsub * ga.nsub * ga.nsub;
-  const int64_t n_plan = (int64_t)n_t * nsub3;
+  sa.ext2t = d_ext2t;
+  sa.stats = m->d_stats;
   Sizer zc;
   zc.add<int32_t>(n_t);   // tgt_elin
   zc.add<int32_t>(n_t);   // active
   zc.add<int32_t>(n_t);   // tgt_slot
   zc.add<int32_t>(n_t);   // is_new
   zc.add<int32_t>(n_t);   // new_rank
-  zc.add<int4>(n_plan);
-  zc.add<int32_t>(n_plan);
-  zc.add<int32_t>(n_plan);
-  zc.add<int32_t>(n_plan);
-  zc.add<int32_t>(n_plan);
   zc.add<int32_t>(8);
-  zc.add<char>(scan_tmp_bytes(std::max<int64_t>(n_plan, n_t)));
+  zc.add<char>(scan_tmp_bytes(std::max<int64_t>(n_t, 1)));
+  zc.add<int2>(n_units);
+  zc.add<float>((size_t)n_units * DR3);
   SMKI_HIP_TRY(m->a_tgts.reserve(zc.total));
   Arena& C = m->a_tgts;
   int32_t* d_tgt = C.take<int32_t>(n_t);
@@ -459,54 +450,41 @@ smki_status insert_impl(smki_map* m, const float* xyz, const int32_t* label, int
   int32_t* d_tslot = C.take<int32_t>(n_t);
   int32_t* d_isnew = C.take<int32_t>(n_t);
   int32_t* d_rank = C.take<int32_t>(n_t);
-  int4* d_plan = C.take<int4>(n_plan);
-  int32_t* d_np = C.take<int32_t>(n_plan);
-  int32_t* d_ns = C.take<int32_t>(n_plan);
-  int32_t* d_uoff = C.take<int32_t>(n_plan);
-  int32_t* d_soff2 = C.take<int32_t>(n_plan);
   int32_t* d_cnt = C.take<int32_t>(8);
-  void* d_ctmp = C.take<char>(scan_tmp_bytes(std::max<int64_t>(n_plan, n_t)));
-  ga.tgt_elin = d_tgt;
-  ga.tgt_slot = d_tslot;
-  ga.plan = d_plan;
+  void* d_ctmp = C.take<char>(scan_tmp_bytes(std::max<int64_t>(n_t, 1)));
+  int2* d_units = C.take<int2>(n_units);
+  float* d_part = C.take<float>((size_t)n_units * DR3);
+  sa.tgt_elin = d_tgt;
+  sa.tgt_active = d_active;
+  sa.tgt_slot = d_tslot;
+  sa.units = d_units;
+  sa.part = d_part;
   SMKI_HIP_TRY(hipMemsetAsync(d_cnt, 0, sizeof(int32_t) * 8, q));
   SMKI_HIP_TRY(hipMemsetAsync(d_active, 0, sizeof(int32_t) * std::max<int64_t>(n_t, 1), q));
-  SMKI_HIP_TRY(launch_list_targets(d_mark, d_mpos, n_ext, d_tgt, q));
-  SMKI_HIP_TRY(launch_plan(ga, n_t, m->part_frac, d_plan, d_active, q));
-  SMKI_HIP_TRY(launch_map_lookup(m->dev, ga, n_t, d_active, d_tslot, d_isnew, m->d_err, q));
+  SMKI_HIP_TRY(hipMemsetAsync(m->d_stats, 0, sizeof(unsigned long long) * 4, q));
+  SMKI_HIP_TRY(launch_list_targets(d_mark, d_mpos, n_ext, d_tgt, d_ext2t, q));
+  SMKI_HIP_TRY(launch_unit_table(d_nun, d_ust, (int32_t)max_slots, d_units, q));
+  SMKI_HIP_TRY(hipEventRecord(m->ev[0], q));
+  SMKI_HIP_TRY(launch_splat(sa, n_units, q));
+  SMKI_HIP_TRY(hipEventRecord(m->ev[1], q));
+  SMKI_HIP_TRY(launch_map_lookup(m->dev, sa, n_t, d_tslot, d_isnew, q));
   SMKI_HIP_TRY(scan_excl_i32(d_isnew, d_rank, n_t, d_cnt, d_ctmp, q));
-  SMKI_HIP_TRY(launch_plan_counts(d_plan, n_plan, d_np, d_ns, q));
-  SMKI_HIP_TRY(scan_excl_i32(d_np, d_uoff, n_plan, d_cnt + 1, d_ctmp, q));
-  SMKI_HIP_TRY(scan_excl_i32(d_ns, d_soff2, n_plan, d_cnt + 2, d_ctmp, q));
-  // sync 3: new blocks, units, partial slots
-  int32_t cnt[3];
+  // sync 3: new blocks
+  int32_t cnt[1];
   SMKI_HIP_TRY(sync_read(m, d_cnt, sizeof(cnt), cnt));
-  const int64_t n_new = cnt[0], n_units = cnt[1], n_split = cnt[2];
+  const int64_t n_new = cnt[0];
   m->last.n_new_blocks = n_new;
-  m->last.n_units = n_units;
   smki_status rc = ensure_pool(m, m->n_blocks + n_new);
   if (rc != SMKI_OK) return rc;
   rc = ensure_hash(m, m->n_blocks + n_new);
   if (rc != SMKI_OK) return rc;
-  Sizer zd;
-  zd.add<int4>(n_units);
-  zd.add<float>((size_t)n_split * m->K * SMKI_WAVE);
-  zd.add<int32_t>((size_t)n_split * SMKI_WAVE);
-  SMKI_HIP_TRY(m->a_misc.reserve(zd.total));
-  int4* d_units = m->a_misc.take<int4>(n_units);
-  float* d_pacc = m->a_misc.take<float>((size_t)n_split * m->K * SMKI_WAVE);
-  int32_t* d_pcnt = m->a_misc.take<int32_t>((size_t)n_split * SMKI_WAVE);
-  SMKI_HIP_TRY(launch_assign_new(m->dev, ga, n_t, d_isnew, d_rank, m->n_blocks, d_tslot, m->d_err, q));
+  SMKI_HIP_TRY(hipEventRecord(m->ev[2], q));
+  SMKI_HIP_TRY(launch_assign_new(m->dev, sa, n_t, d_isnew, d_rank, m->n_blocks, d_tslot, m->d_err, q));
   SMKI_HIP_TRY(launch_fill_alpha0(m->dev, m->n_blocks, n_new, q));
-  SMKI_HIP_TRY(launch_units(d_plan, d_uoff, d_soff2, n_plan, nsub3, d_units, q));
-  ga.units = d_units;
-  ga.alpha = m->dev.alpha;
-  ga.part_acc = d_pacc;
-  ga.part_cnt = d_pcnt;
-  SMKI_HIP_TRY(hipMemsetAsync(m->d_stats, 0, sizeof(unsigned long long) * 2, q));
-  SMKI_HIP_TRY(launch_gather(ga, n_units, q));
-  if (n_split > 0) SMKI_HIP_TRY(launch_merge(ga, n_plan, q));
-  SMKI_HIP_TRY(hipMemcpyAsync(m->h_pin + 8, m->d_stats, sizeof(unsigned long long) * 2,
+  sa.alpha = m->dev.alpha;
+  SMKI_HIP_TRY(launch_merge(sa, n_t, q));
+  SMKI_HIP_TRY(hipEventRecord(m->ev[3], q));
+  SMKI_HIP_TRY(hipMemcpyAsync(m->h_pin + 8, m->d_stats, sizeof(unsigned long long) * 4,
                               hipMemcpyDeviceToHost, q));
   m->n_blocks += n_new;
   m->stats_pending = true;
@@ -541,10 +519,8 @@ smki_status smki_create_map(float res, int32_t block_size, float l, float sigma0
   if (!finite_pos(res) || !finite_pos(l) || !finite_pos(sigma0) || !finite_pos(alpha0))
     return SMKI_E_INVALID_ARG;
   if (K < 2 || K > 255 || free_class < 0 || free_class >= K) return SMKI_E_INVALID_ARG;
-  if (block_size != 4 && block_size != 8 && block_size != 16 && block_size != 32)
-    return SMKI_E_INVALID_ARG;
-  if (opt && (opt->initial_blocks < 0 || opt->unit_budget < 0 || !(opt->part_fraction >= 0.0f) ||
-              opt->part_fraction > 1.0f))
+  if (block_size != 4 && block_size != 8) return SMKI_E_INVALID_ARG;
+  if (opt && (opt->initial_blocks < 0 || opt->unit_budget < 0 || opt->unit_budget > (1 << 24)))
     return SMKI_E_INVALID_ARG;
   int ndev = 0;
   if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) return SMKI_E_DEVICE;
@@ -558,8 +534,7 @@ smki_status smki_create_map(float res, int32_t block_size, float l, float sigma0
   m->B = block_size;
   m->log2B = ilog2(block_size);
   m->free_class = free_class;
-  m->budget = (opt && opt->unit_budget > 0) ? opt->unit_budget : 2048;
-  m->part_frac = (opt && opt->part_fraction > 0.0f) ? opt->part_fraction : 0.5f;
+  m->chunk = (opt && opt->unit_budget > 0) ? opt->unit_budget : SMKI_CHUNK;
   for (int i = 0; i < SMKI_POLY_N; ++i) m->coef[i] = (float)(kQ[i] * (double)sigma0);
   (void)hipGetDevice(&m->device);
   m->dev.K = K;
@@ -569,8 +544,10 @@ smki_status smki_create_map(float res, int32_t block_size, float l, float sigma0
   smki_status rc = SMKI_OK;
   if (hipMalloc((void**)&m->d_err, 64) != hipSuccess ||
       hipMalloc((void**)&m->d_stats, 64) != hipSuccess ||
-      hipMalloc((void**)&m->d_cols, sizeof(StencilCol) * SMKI_MAX_COLS) != hipSuccess ||
-      hipHostMalloc((void**)&m->h_pin, 256, hipHostMallocDefault) != hipSuccess)
+      hipMalloc((void**)&m->d_offs, sizeof(StencilOff) * SMKI_MAX_OFFS) != hipSuccess ||
+      hipHostMalloc((void**)&m->h_pin, 256, hipHostMallocDefault) != hipSuccess ||
+      hipEventCreate(&m->ev[0]) != hipSuccess || hipEventCreate(&m->ev[1]) != hipSuccess ||
+      hipEventCreate(&m->ev[2]) != hipSuccess || hipEventCreate(&m->ev[3]) != hipSuccess)
     rc = SMKI_E_OOM;
   if (rc == SMKI_OK && hipMemset(m->d_err, 0, 64) != hipSuccess) rc = SMKI_E_DEVICE;
   if (rc == SMKI_OK) rc = ensure_pool(m, (opt && opt->initial_blocks > 0) ? opt->initial_blocks : 4096);
@@ -593,8 +570,10 @@ smki_status smki_destroy_map(smki_map* m) {
   if (m->dev.alpha) (void)hipFree(m->dev.alpha);
   if (m->d_err) (void)hipFree(m->d_err);
   if (m->d_stats) (void)hipFree(m->d_stats);
-  if (m->d_cols) (void)hipFree(m->d_cols);
+  if (m->d_offs) (void)hipFree(m->d_offs);
   if (m->h_pin) (void)hipHostFree(m->h_pin);
+  for (hipEvent_t e : m->ev)
+    if (e) (void)hipEventDestroy(e);
   m->a_hits.release();
   m->a_sets.release();
   m->a_tgts.release();
@@ -693,6 +672,9 @@ smki_status smki_last_scan_stats(smki_map* m, smki_scan_stats* out) {
     const unsigned long long* s = (const unsigned long long*)(m->h_pin + 8);
     m->last.n_updated_voxels = (int64_t)s[0];
     m->last.n_pairs = (int64_t)s[1];
+    float ms = 0.0f;
+    if (hipEventElapsedTime(&ms, m->ev[0], m->ev[1]) == hipSuccess) m->last.splat_ms = ms;
+    if (hipEventElapsedTime(&ms, m->ev[2], m->ev[3]) == hipSuccess) m->last.merge_ms = ms;
     m->stats_pending = false;
   }
   *out = m->last;
@@ -822,7 +804,7 @@ smki_status smki_bucket_cells(const float* xyz, int64_t n, float res, int32_t bl
   (void)hipFreeAsync(base0, q);
   if (e != hipSuccess) return smki_hip_error(e);
   if (herr) return status_of_err(herr);
-  const BucketGeom g = make_geom(&tmp_map, hb, hb + 3);
+  const BucketGeom g = make_geom(&tmp_map, hb, hb + 3, 1);
   if (g.n_blocks > (int64_t(1) << 28)) return SMKI_E_CAPACITY;
   Sizer z;
   z.add<uint64_t>(n);

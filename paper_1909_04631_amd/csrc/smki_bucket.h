@@ -13,6 +13,7 @@ struct BucketGeom {
   int32_t blo[3];   // lowest block coordinate of the grid
   int32_t nb[3];    // blocks per axis
   int64_t n_blocks; // nb[0] * nb[1] * nb[2]
+  int32_t planes;   // label planes of the keys (K for a map insert, 1 otherwise)
   int32_t key_bits; // significant bits of a row key
 };
 
@@ -20,8 +21,8 @@ struct BucketGeom {
 struct PointSet {
   int64_t n;          // rows
   float4* pts;        // sorted records: xyz relative to the row's block corner, label bits
-  int32_t* dense;     // [n_blocks] grid block -> slot, -1 if the block holds no row
-  int32_t* slot_lin;  // [slots] grid linear index of each slot
+  int32_t* dense;     // [planes * n_blocks] (plane, grid block) -> slot, -1 if no row
+  int32_t* slot_lin;  // [slots] (plane, grid block) linear index of each slot
   int32_t* prefix;    // [slots][B^3 + 1] first row of each voxel of the block (absolute)
   int32_t* d_nslots;  // device scalar: number of slots
 };
@@ -44,16 +45,11 @@ hipError_t launch_count(const float* xyz, const int32_t* label, int64_t n, const
                         int64_t* nfree, int32_t* kept, int32_t* bbox, uint32_t* err,
                         hipStream_t st);
 hipError_t launch_fill_i32(int32_t* p, int64_t n, int32_t v, hipStream_t st);
-hipError_t launch_free_positions(const float* xyz, int64_t n, const int64_t* off, int64_t nf,
-                                 const int64_t* scan_off, const float* origins, int32_t S,
-                                 float step, float4* out, int64_t* parent, hipStream_t st);
-hipError_t bucket_hits(const float* xyz, const int32_t* label, int64_t n, const int32_t* kept,
-                       const int32_t* kpos, const BucketGeom& g, PointSet& ps, BucketScratch& scr,
+hipError_t bucket_scan(const float* xyz, const int32_t* label, int64_t n, const int32_t* kept,
+                       const int32_t* kpos, int64_t nk, const int64_t* off, int64_t nf,
+                       const int64_t* scan_off, const float* origins, int32_t S, float step,
+                       int32_t free_class, const BucketGeom& g, PointSet& ps, BucketScratch& scr,
                        uint32_t* err, hipStream_t st);
-hipError_t bucket_frees(const float* xyz, int64_t n, const int64_t* off, const int64_t* scan_off,
-                        const float* origins, int32_t S, float step, int32_t free_class,
-                        const BucketGeom& g, PointSet& ps, BucketScratch& scr, uint32_t* err,
-                        hipStream_t st);
 hipError_t bucket_rows(const float* xyz, const int32_t* label, int64_t n, const BucketGeom& g,
                        PointSet& ps, BucketScratch& scr, uint32_t* err, hipStream_t st);
 hipError_t bucket_cells_sort(const float* xyz, int64_t n, const BucketGeom& g, BucketScratch& scr,

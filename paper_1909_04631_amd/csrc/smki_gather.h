@@ -2,10 +2,10 @@
 #pragma once
 #include "smki_bucket.h"
 
-#define SMKI_TILE 4                 // sub-tile edge: 4^3 = 64 voxels = one wavefront
-#define SMKI_MAX_BOX 16             // largest staged box edge (sub-tile + 2 * reach)
-#define SMKI_MAX_COLS ((SMKI_MAX_BOX) * (SMKI_MAX_BOX))
+#define SMKI_MAX_REACH 4            // largest stencil reach in voxels
+#define SMKI_MAX_OFFS 729           // (2 * SMKI_MAX_REACH + 1)^3
 #define SMKI_POLY_N 8               // coefficients of the kernel polynomial
+#define SMKI_CHUNK 1024             // default rows of one (class, block) per splat work unit
 
 // Block-hash and pool of the persistent map.
 struct MapDev {
@@ -18,59 +18,57 @@ struct MapDev {
   float alpha0;
 };
 
-// One column of the voxel stencil: lateral offset (dx, dy) and half-height h:
-// every voxel cell that can hold a point within l of the voxel centre.
-struct StencilCol {
-  int32_t dx, dy, h, pad;
+// Voxel offset (relative to a row's cell) that can lie within l of a point of
+// that cell: (dx, dy, dz, unused).
+struct StencilOff {
+  int32_t dx, dy, dz, pad;
 };
 
-struct GatherArgs {
-  BucketGeom g;             // point grid
-  int32_t eblo[3], enb[3];  // target (extended) grid
-  int32_t R, D;             // stencil reach in voxels, staged box edge (SMKI_TILE + 2R)
-  int32_t nsub;             // sub-tiles per block edge (B / SMKI_TILE)
-  int32_t ncols;
-  const StencilCol* cols;
+struct SplatArgs {
+  BucketGeom g;               // point grid (planes = classes)
+  int32_t R;                  // stencil reach in voxels (region = block grown by R)
+  int32_t noff;               // voxel offsets in offs
+  const int4* offs;           // [noff] StencilOff
   float l2, inv_l;
-  float coef[SMKI_POLY_N];  // sigma0 * Q(u) coefficients, highest degree first
-  int32_t K, free_class;
-  // point sets: 0 = free samples, 1 = hits
-  const float4* pts[2];
-  const int32_t* dense[2];
-  const int32_t* prefix[2];
-  // targets
-  const int32_t* tgt_elin;  // [n_targets] extended-grid linear index
-  const int32_t* tgt_slot;  // [n_targets] pool slot (-1: inactive)
-  const int4* plan;         // [n_targets * nsub^3]: (parts, window, partial base, 0)
-  const int4* units;        // [n_units]: (target, sub-tile, part, 0)
-  float* alpha;             // pool
-  float* part_acc;          // [n_partials][K][64]
-  int32_t* part_cnt;        // [n_partials][64]
-  unsigned long long* stats;  // [0] = voxels with an in-support point, [1] = in-support pairs
-  int32_t budget;           // per-lane candidate budget of one work unit
+  float coef[SMKI_POLY_N];    // sigma0 * Q(u) coefficients, highest degree first
+  int32_t K;
+  int32_t chunk;              // rows of one (class, block) per work unit
+  // sorted rows
+  const float4* pts;          // records: xyz relative to the row block's centre, label bits
+  const int32_t* dense;       // [K * n_blocks] (class, block) -> slot
+  const int32_t* prefix;      // [slots][B^3 + 1]
+  const int32_t* slot_lin;    // [slots] (class, block) linear index
+  const int32_t* nunits;      // [slots] chunks of the slot
+  const int32_t* ustart;      // [slots] first unit of the slot
+  const int2* units;          // [n_units] (slot, chunk)
+  float* part;                // [n_units][(B + 2R)^3] partial sums of each unit's region
+  // targets (blocks within reach of a row block), on the extended grid
+  int32_t eblo[3], enb[3];
+  const int32_t* ext2t;       // [n_ext] extended-grid block -> target index or -1
+  const int32_t* tgt_elin;    // [n_targets] extended-grid linear index
+  int32_t* tgt_active;        // [n_targets] 1 if some row reaches the block
+  const int32_t* tgt_slot;    // [n_targets] pool slot (-1: inactive)
+  float* alpha;               // pool
+  unsigned long long* stats;  // [0] updated voxels, [1] in-support pairs
 };
 
 hipError_t launch_mark_targets(const int32_t* slot_lin, const int32_t* d_nslots, int32_t max_slots,
                                const BucketGeom& g, const int32_t eblo[3], const int32_t enb[3],
                                int32_t DB, int32_t* mark, hipStream_t st);
 hipError_t launch_list_targets(const int32_t* mark, const int32_t* mpos, int64_t n_ext,
-                               int32_t* tgt_elin, hipStream_t st);
-hipError_t launch_plan(const GatherArgs& a, int32_t n_targets, float frac, int4* plan,
-                       int32_t* active, hipStream_t st);
-size_t gather_lds_bytes(const GatherArgs& a);
-hipError_t launch_map_lookup(const MapDev& m, const GatherArgs& a, int32_t n_targets,
-                             const int32_t* active, int32_t* tgt_slot, int32_t* is_new,
-                             uint32_t* err, hipStream_t st);
-hipError_t launch_assign_new(const MapDev& m, const GatherArgs& a, int32_t n_targets,
+                               int32_t* tgt_elin, int32_t* ext2t, hipStream_t st);
+hipError_t launch_slot_units(const int32_t* prefix, const int32_t* d_nslots, int32_t max_slots,
+                             int32_t B3, int32_t chunk, int32_t* nunits, hipStream_t st);
+hipError_t launch_unit_table(const int32_t* nunits, const int32_t* ustart, int32_t max_slots,
+                             int2* units, hipStream_t st);
+hipError_t launch_splat(const SplatArgs& a, int64_t n_units, hipStream_t st);
+hipError_t launch_merge(const SplatArgs& a, int32_t n_targets, hipStream_t st);
+hipError_t launch_map_lookup(const MapDev& m, const SplatArgs& a, int32_t n_targets,
+                             int32_t* tgt_slot, int32_t* is_new, hipStream_t st);
+hipError_t launch_assign_new(const MapDev& m, const SplatArgs& a, int32_t n_targets,
                              const int32_t* is_new, const int32_t* new_rank, int64_t n_old,
                              int32_t* tgt_slot, uint32_t* err, hipStream_t st);
 hipError_t launch_fill_alpha0(const MapDev& m, int64_t slot0, int64_t nslots, hipStream_t st);
-hipError_t launch_plan_counts(const int4* plan, int64_t n, int32_t* nparts, int32_t* nsplit,
-                              hipStream_t st);
-hipError_t launch_units(int4* plan, const int32_t* unit_off, const int32_t* split_off, int64_t n,
-                        int32_t nsub3, int4* units, hipStream_t st);
-hipError_t launch_gather(const GatherArgs& a, int64_t n_units, hipStream_t st);
-hipError_t launch_merge(const GatherArgs& a, int64_t n_plan, hipStream_t st);
 
 // map.hip
 hipError_t launch_query(const MapDev& m, const int32_t* ijk, int64_t M, float* alpha, float* mean,

@@ -230,27 +230,46 @@ def test_single_class_scene_and_k2_reduction():
                                atol=1e-7)
 
 
-@pytest.mark.parametrize("budget", [64, 300])
-def test_split_work_units_agree(budget):
-    # small per-lane budgets force many parts per sub-tile: partial sums merged in order
+@pytest.mark.parametrize("chunk", [64, 300])
+def test_split_work_units_agree(chunk):
+    # small chunks split every busy (class, block) into several splat units whose
+    # partial sums the merge adds in chunk order
     sc = scenes.make_config(0)
-    _print_case(f"budget {budget}")
-    gm = gpu_map_of(sc, unit_budget=budget)
+    _print_case(f"chunk {chunk}")
+    gm = gpu_map_of(sc, unit_budget=chunk)
     om = oracle_map_of(sc)
     worst, (ijk, a_ref, nv, nb) = compare_map(gm, om, sc.params.K)
     st = gm.stats()
-    assert st["n_units"] >= 1000
+    assert st["n_units"] > st["n_point_blocks"]
     check_counts(st, nv, nb)
 
 
-def test_block_sizes_and_resolutions():
+@pytest.mark.parametrize("B,l", [(4, 0.3), (8, 0.3), (4, 0.89), (8, 0.89)])
+def test_block_sizes_and_reach(B, l):
+    # res 0.2: l = 0.3 reaches 2 voxels past a row's voxel, l = 0.89 reaches 4,
+    # the largest supported reach (equal to the block edge for B = 4)
     sc = scenes.random_points_scene(5, 3000, K=5, extent=1.3, centre=(-7.3, 12.9, -0.4),
-                                    res=0.2, l=0.3, sigma0=0.4, free_step=0.25,
+                                    res=0.2, l=l, sigma0=0.4, free_step=0.25,
                                     origin=(-6.0, 11.0, 0.5))
-    for B in (4, 8, 16):
-        sc.params.block_size = B
-        _print_case(f"block size {B}")
-        compare_map(gpu_map_of(sc), oracle_map_of(sc), sc.params.K)
+    sc.params.block_size = B
+    _print_case(f"block size {B} l {l}")
+    compare_map(gpu_map_of(sc), oracle_map_of(sc), sc.params.K)
+
+
+def test_reach_beyond_limit_is_rejected_and_map_unchanged():
+    import torch
+    from paper_1909_04631_amd import SemanticMap, SmkiError
+    sc = scenes.random_points_scene(6, 500, K=3, extent=0.5, res=0.1, l=0.3)
+    p = sc.params
+    s = sc.scans[0]
+    m = SemanticMap(p.res, 8, 0.46, p.sigma0, p.K, p.alpha0)   # l / res = 4.6 voxels
+    with pytest.raises(SmkiError, match="CAPACITY"):
+        m.insert_scan(cuda(s.xyz), cuda(s.label), s.origin, 0.0)
+    assert m.num_blocks() == 0
+    ok = SemanticMap(p.res, 8, 0.44, p.sigma0, p.K, p.alpha0)   # 4.4 voxels: supported
+    ok.insert_scan(cuda(s.xyz), cuda(s.label), s.origin, 0.0)
+    torch.cuda.synchronize()
+    assert ok.num_blocks() > 0
 
 
 # ---------------------------------------------------------------------------
