@@ -271,32 +271,75 @@ __global__ void k_block_flags(const KeyT* __restrict__ keys, int64_t n, int shif
   flag[i] = (i == 0 || (uint64_t)(keys[i] >> shift) != (uint64_t)(keys[i - 1] >> shift)) ? 1 : 0;
 }
 
-// After the scan of the block-start flags: slot of every row's block, the
-// dense grid -> slot index, each slot's grid position, and the prefix tables.
+// After the scan of the block-start flags: the first row of every slot, the
+// dense grid -> slot index and each slot's grid position.
+// The dense table is block-major: entry (block * planes + plane), so the
+// classes of one block share a cache line.
 template <typename KeyT>
-__global__ void k_block_tables(const KeyT* __restrict__ keys, int64_t n, int log2B3,
-                               const int32_t* __restrict__ flag, const int32_t* __restrict__ slot_excl,
-                               int32_t* __restrict__ dense, int32_t* __restrict__ slot_lin,
-                               int32_t* __restrict__ prefix) {
+__global__ void k_slot_heads(const KeyT* __restrict__ keys, int64_t n, int log2B3, int64_t n_blocks,
+                             int32_t planes, const int32_t* __restrict__ flag,
+                             const int32_t* __restrict__ slot_excl, int32_t* __restrict__ dense,
+                             int32_t* __restrict__ slot_lin, int32_t* __restrict__ head) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  const int32_t B3 = 1 << log2B3;
-  const uint64_t key = (uint64_t)keys[i];
-  const int64_t blk = (int64_t)(key >> log2B3);
-  const int32_t c = (int32_t)(key & (uint64_t)(B3 - 1));
-  const int32_t slot = slot_excl[i] + flag[i] - 1;
-  int32_t* P = prefix + (int64_t)slot * (B3 + 1);
-  const bool first = flag[i] != 0;
-  if (first) {
-    dense[blk] = slot;
-    slot_lin[slot] = (int32_t)blk;
+  if (i >= n || !flag[i]) return;
+  const int64_t blk = (int64_t)((uint64_t)keys[i] >> log2B3);   // plane * n_blocks + block
+  const int32_t slot = slot_excl[i];
+  dense[(blk % n_blocks) * planes + blk / n_blocks] = slot;
+  slot_lin[slot] = (int32_t)blk;
+  head[slot] = (int32_t)i;
+}
+
+// Per slot (grid-stride over slots): histogram of the rows' voxel cells in LDS,
+// then the exclusive scan -> prefix[slot][c] = first row of cell c, [B3] = end.
+template <typename KeyT, int LOG2B3>
+__global__ void __launch_bounds__(256) k_slot_prefix(const KeyT* __restrict__ keys, int64_t n,
+                                                     const int32_t* __restrict__ head,
+                                                     const int32_t* __restrict__ d_nslots,
+                                                     int32_t* __restrict__ prefix) {
+  constexpr int B3 = 1 << LOG2B3;
+  constexpr int PER = (B3 + 255) / 256;
+  __shared__ int32_t cnt[B3];
+  __shared__ int32_t wsum[256 / SMKI_WAVE];
+  const int32_t ns = *d_nslots;
+  const int tid = threadIdx.x;
+  for (int32_t s = blockIdx.x; s < ns; s += gridDim.x) {
+    const int32_t r0 = head[s];
+    const int32_t r1 = (s + 1 < ns) ? head[s + 1] : (int32_t)n;
+    for (int c = tid; c < B3; c += 256) cnt[c] = 0;
+    __syncthreads();
+    for (int32_t r = r0 + tid; r < r1; r += 256)
+      atomicAdd(&cnt[(uint32_t)((uint64_t)keys[r] & (uint64_t)(B3 - 1))], 1);
+    __syncthreads();
+    // exclusive scan of cnt: thread tid owns cells [tid * PER, tid * PER + PER)
+    int32_t loc[PER];
+    int32_t tot = 0;
+#pragma unroll
+    for (int j = 0; j < PER; ++j) {
+      const int c = tid * PER + j;
+      loc[j] = c < B3 ? cnt[c] : 0;
+      tot += loc[j];
+    }
+    int32_t inc = tot;   // inclusive scan over the wavefront
+#pragma unroll
+    for (int o = 1; o < SMKI_WAVE; o <<= 1) {
+      const int32_t v = __shfl_up(inc, o, SMKI_WAVE);
+      if ((tid & (SMKI_WAVE - 1)) >= o) inc += v;
+    }
+    if ((tid & (SMKI_WAVE - 1)) == SMKI_WAVE - 1) wsum[tid / SMKI_WAVE] = inc;
+    __syncthreads();
+    int32_t base = r0;
+    for (int w = 0; w < tid / SMKI_WAVE; ++w) base += wsum[w];
+    int32_t run = base + inc - tot;
+    int32_t* P = prefix + (int64_t)s * (B3 + 1);
+#pragma unroll
+    for (int j = 0; j < PER; ++j) {
+      const int c = tid * PER + j;
+      if (c < B3) P[c] = run;
+      run += loc[j];
+    }
+    if (tid == 0) P[B3] = r1;
+    __syncthreads();
   }
-  const int32_t prev = first ? -1 : (int32_t)((uint64_t)keys[i - 1] & (uint64_t)(B3 - 1));
-  if (c != prev)
-    for (int32_t cc = prev + 1; cc <= c; ++cc) P[cc] = (int32_t)i;
-  const bool last = (i == n - 1) || ((uint64_t)keys[i + 1] >> log2B3) != (uint64_t)blk;
-  if (last)
-    for (int32_t cc = c + 1; cc <= B3; ++cc) P[cc] = (int32_t)(i + 1);
 }
 
 __global__ void k_fill_i32(int32_t* p, int64_t n, int32_t v) {
@@ -345,8 +388,22 @@ static hipError_t finish_set(PointSet& ps, KeyT* keys, uint32_t* idx, KeyT* akey
                      scr.flag);
   e = scan_excl_i32(scr.flag, scr.slot_excl, n, ps.d_nslots, scr.scan_tmp, st);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_block_tables<KeyT>, dim3(nblk(n, 256)), dim3(256), 0, st, keys, n, log2B3,
-                     scr.flag, scr.slot_excl, ps.dense, ps.slot_lin, ps.prefix);
+  hipLaunchKernelGGL(k_slot_heads<KeyT>, dim3(nblk(n, 256)), dim3(256), 0, st, keys, n, log2B3,
+                     g.n_blocks, g.planes, scr.flag, scr.slot_excl, ps.dense, ps.slot_lin,
+                     scr.slot_head);
+  const unsigned grid = (unsigned)std::min<int64_t>(n, 8192);
+  switch (log2B3) {
+    case 6:
+      hipLaunchKernelGGL((k_slot_prefix<KeyT, 6>), dim3(grid), dim3(256), 0, st, keys, n,
+                         scr.slot_head, ps.d_nslots, ps.prefix);
+      break;
+    case 9:
+      hipLaunchKernelGGL((k_slot_prefix<KeyT, 9>), dim3(grid), dim3(256), 0, st, keys, n,
+                         scr.slot_head, ps.d_nslots, ps.prefix);
+      break;
+    default:
+      return hipErrorInvalidValue;
+  }
   return hipGetLastError();
 }
 

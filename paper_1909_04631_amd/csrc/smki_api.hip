@@ -353,6 +353,7 @@ smki_status insert_impl(smki_map* m, const float* xyz, const int32_t* label, int
   zb.add<float4>(nt);
   zb.add<int32_t>(nt);
   zb.add<int32_t>(nt);
+  zb.add<int32_t>(nt);
   zb.add<char>(radix_tmp_bytes(nt));
   zb.add<char>(scan_tmp_bytes(std::max(nt, n_ext)));
   zb.add<int32_t>(n_ext);
@@ -380,6 +381,7 @@ smki_status insert_impl(smki_map* m, const float* xyz, const int32_t* label, int
   scr.rec = Bz.take<float4>(nt);
   scr.flag = Bz.take<int32_t>(nt);
   scr.slot_excl = Bz.take<int32_t>(nt);
+  scr.slot_head = Bz.take<int32_t>(nt);
   scr.sort_tmp = Bz.take<char>(radix_tmp_bytes(nt));
   scr.scan_tmp = Bz.take<char>(scan_tmp_bytes(std::max(nt, n_ext)));
   int32_t* d_mark = Bz.take<int32_t>(n_ext);
@@ -443,6 +445,8 @@ smki_status insert_impl(smki_map* m, const float* xyz, const int32_t* label, int
   zc.add<char>(scan_tmp_bytes(std::max<int64_t>(n_t, 1)));
   zc.add<int2>(n_units);
   zc.add<float>((size_t)n_units * DR3);
+  zc.add<uint32_t>(n_units);
+  zc.add<int4>(n_slots);
   SMKI_HIP_TRY(m->a_tgts.reserve(zc.total));
   Arena& C = m->a_tgts;
   int32_t* d_tgt = C.take<int32_t>(n_t);
@@ -454,11 +458,16 @@ smki_status insert_impl(smki_map* m, const float* xyz, const int32_t* label, int
   void* d_ctmp = C.take<char>(scan_tmp_bytes(std::max<int64_t>(n_t, 1)));
   int2* d_units = C.take<int2>(n_units);
   float* d_part = C.take<float>((size_t)n_units * DR3);
+  uint32_t* d_umask = C.take<uint32_t>(n_units);
+  int4* d_sinfo = C.take<int4>(n_slots);
   sa.tgt_elin = d_tgt;
   sa.tgt_active = d_active;
   sa.tgt_slot = d_tslot;
   sa.units = d_units;
   sa.part = d_part;
+  sa.umask = d_umask;
+  sa.sinfo = d_sinfo;
+  sa.n_slots = n_slots;
   SMKI_HIP_TRY(hipMemsetAsync(d_cnt, 0, sizeof(int32_t) * 8, q));
   SMKI_HIP_TRY(hipMemsetAsync(d_active, 0, sizeof(int32_t) * std::max<int64_t>(n_t, 1), q));
   SMKI_HIP_TRY(hipMemsetAsync(m->d_stats, 0, sizeof(unsigned long long) * 4, q));
@@ -480,8 +489,9 @@ smki_status insert_impl(smki_map* m, const float* xyz, const int32_t* label, int
   if (rc != SMKI_OK) return rc;
   SMKI_HIP_TRY(hipEventRecord(m->ev[2], q));
   SMKI_HIP_TRY(launch_assign_new(m->dev, sa, n_t, d_isnew, d_rank, m->n_blocks, d_tslot, m->d_err, q));
-  SMKI_HIP_TRY(launch_fill_alpha0(m->dev, m->n_blocks, n_new, q));
   sa.alpha = m->dev.alpha;
+  sa.n_old = m->n_blocks;
+  sa.alpha0 = m->alpha0;
   SMKI_HIP_TRY(launch_merge(sa, n_t, q));
   SMKI_HIP_TRY(hipEventRecord(m->ev[3], q));
   SMKI_HIP_TRY(hipMemcpyAsync(m->h_pin + 8, m->d_stats, sizeof(unsigned long long) * 4,

@@ -21,7 +21,7 @@ struct BucketGeom {
 struct PointSet {
   int64_t n;          // rows
   float4* pts;        // sorted records: xyz relative to the row's block corner, label bits
-  int32_t* dense;     // [planes * n_blocks] (plane, grid block) -> slot, -1 if no row
+  int32_t* dense;     // [n_blocks * planes] (grid block, plane) -> slot, -1 if no row
   int32_t* slot_lin;  // [slots] (plane, grid block) linear index of each slot
   int32_t* prefix;    // [slots][B^3 + 1] first row of each voxel of the block (absolute)
   int32_t* d_nslots;  // device scalar: number of slots
@@ -36,6 +36,7 @@ struct BucketScratch {
   float4* rec;        // unsorted records
   int32_t* flag;
   int32_t* slot_excl;
+  int32_t* slot_head;  // first row of each slot (capacity = rows)
   void* sort_tmp;
   void* scan_tmp;
 };

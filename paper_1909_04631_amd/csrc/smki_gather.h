@@ -35,13 +35,18 @@ struct SplatArgs {
   int32_t chunk;              // rows of one (class, block) per work unit
   // sorted rows
   const float4* pts;          // records: xyz relative to the row block's centre, label bits
-  const int32_t* dense;       // [K * n_blocks] (class, block) -> slot
+  const int32_t* dense;       // [n_blocks * K] (block, class) -> slot
   const int32_t* prefix;      // [slots][B^3 + 1]
   const int32_t* slot_lin;    // [slots] (class, block) linear index
   const int32_t* nunits;      // [slots] chunks of the slot
   const int32_t* ustart;      // [slots] first unit of the slot
   const int2* units;          // [n_units] (slot, chunk)
-  float* part;                // [n_units][(B + 2R)^3] partial sums of each unit's region
+  float* part;                // [n_units][(B + 2R)^3] partial sums of each unit's region, by
+                              // piece: the region split into the 27 parts that fall in the
+                              // unit's block and its neighbours, each contiguous (x, y, z)
+  uint32_t* umask;            // [n_units] bit d: piece d is non-zero (and written)
+  int4* sinfo;                // [slots] (first unit, units, union of the units' masks, 0)
+  int32_t n_slots;
   // targets (blocks within reach of a row block), on the extended grid
   int32_t eblo[3], enb[3];
   const int32_t* ext2t;       // [n_ext] extended-grid block -> target index or -1
@@ -49,6 +54,8 @@ struct SplatArgs {
   int32_t* tgt_active;        // [n_targets] 1 if some row reaches the block
   const int32_t* tgt_slot;    // [n_targets] pool slot (-1: inactive)
   float* alpha;               // pool
+  int64_t n_old;              // pool slots in use before this insert (newer ones are fresh)
+  float alpha0;               // prior concentration written to fresh blocks
   unsigned long long* stats;  // [0] updated voxels, [1] in-support pairs
 };
 
@@ -68,7 +75,6 @@ hipError_t launch_map_lookup(const MapDev& m, const SplatArgs& a, int32_t n_targ
 hipError_t launch_assign_new(const MapDev& m, const SplatArgs& a, int32_t n_targets,
                              const int32_t* is_new, const int32_t* new_rank, int64_t n_old,
                              int32_t* tgt_slot, uint32_t* err, hipStream_t st);
-hipError_t launch_fill_alpha0(const MapDev& m, int64_t slot0, int64_t nslots, hipStream_t st);
 
 // map.hip
 hipError_t launch_query(const MapDev& m, const int32_t* ijk, int64_t M, float* alpha, float* mean,

@@ -116,6 +116,40 @@ struct Steps {
   static constexpr int NS = ((2 * R + 1) * (2 * R + 1) * (2 * R + 1) + SMKI_WAVE - 1) / SMKI_WAVE;
 };
 
+// The region of a (class, block) work unit, (B + 2R)^3 voxels, split into 27
+// pieces: piece p = (dx+1)*9 + (dy+1)*3 + (dz+1) holds the voxels that lie in
+// the block at offset (dx, dy, dz) from the unit's block.  Per axis a piece
+// spans R voxels (d = -1, region coordinates [0, R)), B (d = 0, [R, R+B)) or
+// R (d = +1, [R+B, 2R+B)).  Partial sums are stored piece after piece, each
+// piece contiguous with z fastest.
+template <int B, int R>
+struct Pieces {
+  static constexpr int ext(int d) { return d == 0 ? B : R; }
+  static constexpr int rstart(int d) { return d < 0 ? 0 : (d == 0 ? R : R + B); }
+  static constexpr int size(int p) { return ext(p / 9 - 1) * ext((p / 3) % 3 - 1) * ext(p % 3 - 1); }
+  static constexpr int base(int p) {
+    int b = 0;
+    for (int q = 0; q < p; ++q) b += size(q);
+    return b;
+  }
+};
+
+// Start of piece p inside a unit's partial sums (p known at run time).
+template <int B, int R>
+__device__ __forceinline__ int pbase(int p) {
+  const int px = p / 9, py = (p / 3) % 3, pz = p % 3;
+  // pieces before p: full x-layers, then y-rows of this layer, then z-cells of this row
+  constexpr int E[3] = {R, B, R};
+  constexpr int S2 = (2 * R + B) * (2 * R + B);   // one x-layer spans all (y, z): sum ey * ez
+  int b = 0;
+  for (int i = 0; i < px; ++i) b += E[i] * S2;
+  const int ex = E[px];
+  for (int i = 0; i < py; ++i) b += ex * E[i] * (2 * R + B);
+  const int ey = E[py];
+  for (int i = 0; i < pz; ++i) b += ex * ey * E[i];
+  return b;
+}
+
 template <int B, int R>
 __global__ void __launch_bounds__(SMKI_WAVE) k_splat(SplatArgs a) {
   constexpr int DR = B + 2 * R;                 // region edge (voxels)
@@ -193,25 +227,41 @@ __global__ void __launch_bounds__(SMKI_WAVE) k_splat(SplatArgs a) {
     __syncthreads();
   }
   __syncthreads();
+  // pieces that received a contribution
+  uint32_t touched = 0;
+  for (int i = lane; i < DR3; i += SMKI_WAVE) {
+    if (acc[i] != 0.0f) {
+      const int rx = i / (DR * DR), ry = (i / DR) % DR, rz = i % DR;
+      const int px = rx < R ? 0 : (rx < R + B ? 1 : 2);
+      const int py = ry < R ? 0 : (ry < R + B ? 1 : 2);
+      const int pz = rz < R ? 0 : (rz < R + B ? 1 : 2);
+      touched |= 1u << (px * 9 + py * 3 + pz);
+    }
+  }
+#pragma unroll
+  for (int o = SMKI_WAVE / 2; o > 0; o >>= 1) touched |= __shfl_xor(touched, o, SMKI_WAVE);
+  touched = __builtin_amdgcn_readfirstlane(touched);
+  if (lane == 0) a.umask[blockIdx.x] = touched;
+  // write the non-zero pieces
+  using PC = Pieces<B, R>;
   float* out = a.part + (int64_t)blockIdx.x * DR3;
-  for (int i = lane; i < DR3; i += SMKI_WAVE) out[i] = acc[i];
+#pragma unroll
+  for (int p = 0; p < 27; ++p) {
+    if (!((touched >> p) & 1u)) continue;
+    const int ex = PC::ext(p / 9 - 1), ey = PC::ext((p / 3) % 3 - 1), ez = PC::ext(p % 3 - 1);
+    const int sx = PC::rstart(p / 9 - 1), sy = PC::rstart((p / 3) % 3 - 1),
+              sz = PC::rstart(p % 3 - 1);
+    const int n = ex * ey * ez, b = PC::base(p);
+    for (int i = lane; i < n; i += SMKI_WAVE) {
+      const int lx = i / (ey * ez), ly = (i / ez) % ey, lz = i % ez;
+      out[b + i] = acc[((sx + lx) * DR + (sy + ly)) * DR + (sz + lz)];
+    }
+  }
   // which target blocks received a contribution
   const int32_t plane_lin = a.slot_lin[slot];
   const int32_t blin = plane_lin % a.g.n_blocks;
   int32_t pb[3];
   unlin3(blin, a.g.nb, pb);
-  uint32_t touched = 0;   // bit (dx+1)*9 + (dy+1)*3 + (dz+1) for DB = 1
-  for (int i = lane; i < DR3; i += SMKI_WAVE) {
-    if (acc[i] != 0.0f) {
-      const int vx = i / (DR * DR) - R, vy = (i / DR) % DR - R, vz = i % DR - R;
-      const int dx = vx < 0 ? -1 : (vx >= B ? 1 : 0);
-      const int dy = vy < 0 ? -1 : (vy >= B ? 1 : 0);
-      const int dz = vz < 0 ? -1 : (vz >= B ? 1 : 0);
-      touched |= 1u << ((dx + 1) * 9 + (dy + 1) * 3 + (dz + 1));
-    }
-  }
-#pragma unroll
-  for (int o = SMKI_WAVE / 2; o > 0; o >>= 1) touched |= __shfl_xor(touched, o, SMKI_WAVE);
   if (lane < 27 && ((touched >> lane) & 1u)) {
     const int dx = lane / 9 - 1, dy = (lane / 3) % 3 - 1, dz = lane % 3 - 1;
     const int64_t e = ((int64_t)(pb[0] + a.g.blo[0] - a.eblo[0] + dx) * a.enb[1] +
@@ -225,78 +275,207 @@ __global__ void __launch_bounds__(SMKI_WAVE) k_splat(SplatArgs a) {
 }
 
 // ---------------------------------------------------------------------------
-// merge: one workgroup of 256 threads per target block, 2 voxels per thread
+// merge
 // ---------------------------------------------------------------------------
+// Per slot: its units and the union of their non-zero pieces.
+__global__ void k_slot_info(SplatArgs a) {
+  const int32_t s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= a.n_slots) return;
+  const int32_t u0 = a.ustart[s], nu = a.nunits[s];
+  uint32_t m = 0;
+  for (int32_t w = u0; w < u0 + nu; ++w) m |= a.umask[w];
+  a.sinfo[s] = make_int4(u0, nu, (int32_t)m, 0);
+}
+
+// One workgroup per active target block, one thread per voxel.  Each thread
+// first lists, once, the neighbours whose regions cover its voxel and the
+// offset of its voxel in the corresponding piece.  The workgroup then looks up
+// the slots of the 27 neighbouring blocks for a group of classes into LDS (all
+// lookups in flight together) and lists the classes that have any.  A block
+// allocated by this insert gets alpha0 in the classes without contributions
+// (stores only).  For every listed class, each thread adds the pieces that
+// cover its voxel (fixed neighbour order, then chunk order; compensated), with
+// the first-chunk loads of all its candidates issued before summing; fresh
+// blocks are written alpha0 + sum, older blocks updated in place where the sum
+// is non-zero.
 template <int B, int R>
-__global__ void __launch_bounds__(256) k_merge(SplatArgs a, int32_t n_targets) {
+struct MergeShape {
+  static constexpr int B3 = B * B * B;
+  static constexpr int NT = B3;                       // threads per workgroup
+  static constexpr int CPG = 64;                      // classes per lookup group (one wavefront)
+  // neighbours whose region can cover one voxel: per axis 1, 2 (R > 0), or 3 (2R > B)
+  static constexpr int AX = R == 0 ? 1 : (2 * R > B ? 3 : 2);
+  static constexpr int MAXC = AX * AX * AX;
+};
+
+template <int B, int R>
+__global__ void __launch_bounds__(B * B * B) k_merge(SplatArgs a, int32_t n_targets) {
+  using S = MergeShape<B, R>;
   constexpr int DR = B + 2 * R;
   constexpr int DR3 = DR * DR * DR;
-  constexpr int B3 = B * B * B;
-  constexpr int VPT = (B3 + 255) / 256;
+  constexpr int B3 = S::B3, NT = S::NT, CPG = S::CPG, MAXC = S::MAXC, AX = S::AX;
+  __shared__ int4 ent[CPG * 27];      // [class][neighbour]: (first unit, units, union mask, -)
+  __shared__ int32_t cflag[CPG], clist[CPG], ncls_s;
+  __shared__ int32_t red[NT / SMKI_WAVE];
   const int32_t t = blockIdx.x;
   if (t >= n_targets || !a.tgt_active[t]) return;
+  const int tid = threadIdx.x;
   const int32_t mslot = a.tgt_slot[t];
+  const bool fresh = mslot >= a.n_old;
   int32_t bt[3];
   unlin3(a.tgt_elin[t], a.enb, bt);
-  for (int q = 0; q < 3; ++q) bt[q] += a.eblo[q];
+  int32_t pt[3];   // target block on the point grid
+  for (int q = 0; q < 3; ++q) pt[q] = bt[q] + a.eblo[q] - a.g.blo[q];
   float* A = a.alpha + (int64_t)mslot * a.K * B3;
-  bool upd[VPT];
+  const int vv[3] = {tid / (B * B), (tid / B) % B, tid % B};
+  // covering neighbours c, per axis: 0, -1 if v < R, +1 if v >= B - R (both only
+  // when 2R > B); the voxel is in piece p = 26 - c of the neighbour's region.
+  // Candidates in a fixed order: cidx = neighbour index or -1, coff = offset.
+  int cidx[MAXC], coff[MAXC];
 #pragma unroll
-  for (int j = 0; j < VPT; ++j) upd[j] = false;
-  for (int y = 0; y < a.K; ++y) {
-    float sum[VPT], comp[VPT];
+  for (int k = 0; k < MAXC; ++k) {
+    const int kk[3] = {k / (AX * AX), (k / AX) % AX, k % AX};
+    int c3[3], l3[3];
+    bool valid = true;
 #pragma unroll
-    for (int j = 0; j < VPT; ++j) sum[j] = comp[j] = 0.0f;
-    bool any = false;
-    for (int dx = -1; dx <= 1; ++dx)
-      for (int dy = -1; dy <= 1; ++dy)
-        for (int dz = -1; dz <= 1; ++dz) {
-          const int px = bt[0] + dx - a.g.blo[0], py = bt[1] + dy - a.g.blo[1],
-                    pz = bt[2] + dz - a.g.blo[2];
-          if (px < 0 || py < 0 || pz < 0 || px >= a.g.nb[0] || py >= a.g.nb[1] || pz >= a.g.nb[2])
-            continue;
-          const int32_t s = a.dense[(int64_t)y * a.g.n_blocks +
-                                    ((int64_t)px * a.g.nb[1] + py) * a.g.nb[2] + pz];
-          if (s < 0) continue;
-          const int32_t u0 = a.ustart[s], u1 = u0 + a.nunits[s];
-          any = true;
+    for (int q = 0; q < 3; ++q) {
+      int c = 0;
+      if (kk[q] == 1) {
+        if (AX == 2) {
+          c = vv[q] < R ? -1 : (vv[q] >= B - R ? 1 : 0);
+          valid = valid && c != 0;
+        } else {
+          c = -1;
+          valid = valid && vv[q] < R;
+        }
+      } else if (kk[q] == 2) {
+        c = 1;
+        valid = valid && vv[q] >= B - R;
+      }
+      c3[q] = c;
+      l3[q] = c > 0 ? vv[q] - (B - R) : vv[q];
+    }
+    const int ci = (c3[0] + 1) * 9 + (c3[1] + 1) * 3 + (c3[2] + 1);
+    const int ey = c3[1] == 0 ? B : R, ez = c3[2] == 0 ? B : R;
+    cidx[k] = valid ? ci : -1;
+    coff[k] = pbase<B, R>(26 - ci) + (l3[0] * ey + l3[1]) * ez + l3[2];
+  }
+  bool upd = false;
+  for (int y0 = 0; y0 < a.K; y0 += CPG) {
+    const int ny = min(CPG, a.K - y0);
+    if (tid < ny) cflag[tid] = 0;
+    __syncthreads();
+    for (int i = tid; i < 27 * ny; i += NT) {
+      const int d = i / ny, yc = i - d * ny;
+      const int px = pt[0] + d / 9 - 1, py = pt[1] + (d / 3) % 3 - 1, pz = pt[2] + d % 3 - 1;
+      int4 e = make_int4(0, 0, 0, 0);
+      if (px >= 0 && py >= 0 && pz >= 0 && px < a.g.nb[0] && py < a.g.nb[1] && pz < a.g.nb[2]) {
+        const int32_t s = a.dense[(((int64_t)px * a.g.nb[1] + py) * a.g.nb[2] + pz) * a.K + y0 + yc];
+        if (s >= 0) {
+          e = a.sinfo[s];
+          atomicOr(&cflag[yc], 1);
+        }
+      }
+      ent[yc * 27 + d] = e;
+    }
+    __syncthreads();
+    if (tid < SMKI_WAVE) {   // list the classes with contributions, in class order
+      const bool f = tid < ny && cflag[tid] != 0;
+      const uint64_t m = __ballot(f);
+      if (f) clist[__popcll(m & ((1ull << tid) - 1ull))] = tid;
+      if (tid == 0) ncls_s = __popcll(m);
+    }
+    __syncthreads();
+    const int ncls = ncls_s;
+    if (fresh) {
+      for (int yc = 0; yc < ny; ++yc)
+        if (!cflag[yc]) A[(int64_t)(y0 + yc) * B3 + tid] = a.alpha0;
+    }
+    if constexpr (MAXC > 8) {
+      // 2R > B (B = 4 with a reach of 3 or 4 voxels): up to 27 candidates,
+      // summed one at a time
+      for (int ic = 0; ic < ncls; ++ic) {
+        const int yc = clist[ic];
+        const int4* E = ent + yc * 27;
+        float sm = 0.0f, comp = 0.0f;
+        for (int k = 0; k < MAXC; ++k) {
+          if (cidx[k] < 0) continue;
+          const int4 e = E[cidx[k]];
+          const int p = 26 - cidx[k];
+          if (e.y == 0 || !((e.z >> p) & 1)) continue;
+          for (int32_t w = e.x; w < e.x + e.y; ++w) {
+            if (!((a.umask[w] >> p) & 1u)) continue;
+            const float yv = a.part[(int64_t)w * DR3 + coff[k]] - comp;
+            const float tv = sm + yv;
+            comp = (tv - sm) - yv;
+            sm = tv;
+          }
+        }
+        float* dst = A + (int64_t)(y0 + yc) * B3 + tid;
+        if (fresh) {
+          *dst = a.alpha0 + sm;
+        } else if (sm != 0.0f) {
+          *dst += sm;
+        }
+        upd = upd || sm != 0.0f;
+      }
+    } else {
+      for (int ic = 0; ic < ncls; ++ic) {
+        const int yc = clist[ic];
+        const int4* E = ent + yc * 27;
+        float first[MAXC];
+        int4 ek[MAXC];
 #pragma unroll
-          for (int j = 0; j < VPT; ++j) {
-            const int v = threadIdx.x + 256 * j;
-            if (v >= B3) continue;
-            // voxel v of the target block in the region of the neighbour block
-            const int rx = v / (B * B) - dx * B + R, ry = (v / B) % B - dy * B + R,
-                      rz = v % B - dz * B + R;
-            if (rx < 0 || ry < 0 || rz < 0 || rx >= DR || ry >= DR || rz >= DR) continue;
-            const int ri = (rx * DR + ry) * DR + rz;
-            for (int32_t w = u0; w < u1; ++w) {
-              const float yv = a.part[(int64_t)w * DR3 + ri] - comp[j];
-              const float tv = sum[j] + yv;
-              comp[j] = (tv - sum[j]) - yv;
-              sum[j] = tv;
+        for (int k = 0; k < MAXC; ++k) {
+          first[k] = 0.0f;
+          ek[k] = make_int4(0, 0, 0, 0);
+          if (cidx[k] >= 0) {
+            const int4 e = E[cidx[k]];
+            const int p = 26 - cidx[k];
+            if (e.y != 0 && ((e.z >> p) & 1)) {
+              ek[k] = e;
+              // a single-unit slot's union mask is the unit's own mask
+              if (e.y == 1 || ((a.umask[e.x] >> p) & 1u))
+                first[k] = a.part[(int64_t)e.x * DR3 + coff[k]];
             }
           }
         }
-    if (!any) continue;
+        float sm = 0.0f, comp = 0.0f;
 #pragma unroll
-    for (int j = 0; j < VPT; ++j) {
-      const int v = threadIdx.x + 256 * j;
-      if (v < B3 && sum[j] != 0.0f) {
-        A[(int64_t)y * B3 + v] += sum[j];
-        upd[j] = true;
+        for (int k = 0; k < MAXC; ++k) {
+          if (ek[k].y == 0) continue;
+          {
+            const float yv = first[k] - comp;
+            const float tv = sm + yv;
+            comp = (tv - sm) - yv;
+            sm = tv;
+          }
+          const int p = 26 - cidx[k];
+          for (int32_t w = ek[k].x + 1; w < ek[k].x + ek[k].y; ++w) {
+            if (!((a.umask[w] >> p) & 1u)) continue;
+            const float yv = a.part[(int64_t)w * DR3 + coff[k]] - comp;
+            const float tv = sm + yv;
+            comp = (tv - sm) - yv;
+            sm = tv;
+          }
+        }
+        float* dst = A + (int64_t)(y0 + yc) * B3 + tid;
+        if (fresh) {
+          *dst = a.alpha0 + sm;
+        } else if (sm != 0.0f) {
+          *dst += sm;
+        }
+        upd = upd || sm != 0.0f;
       }
     }
+    __syncthreads();
   }
-  int32_t nup = 0;
-#pragma unroll
-  for (int j = 0; j < VPT; ++j) nup += upd[j] ? 1 : 0;
-  __shared__ int32_t red[256 / SMKI_WAVE];
-  const int64_t wsum = wave_sum_i64(nup);
-  if ((threadIdx.x & (SMKI_WAVE - 1)) == 0) red[threadIdx.x / SMKI_WAVE] = (int32_t)wsum;
+  const int64_t wsum = wave_sum_i64(upd ? 1 : 0);
+  if ((tid & (SMKI_WAVE - 1)) == 0) red[tid / SMKI_WAVE] = (int32_t)wsum;
   __syncthreads();
-  if (threadIdx.x == 0) {
+  if (tid == 0) {
     int32_t tot = 0;
-    for (int i = 0; i < 256 / SMKI_WAVE; ++i) tot += red[i];
+    for (int i = 0; i < NT / SMKI_WAVE; ++i) tot += red[i];
     atomicAdd(&a.stats[0], (unsigned long long)tot);
   }
 }
@@ -351,11 +530,6 @@ __global__ void k_assign_new(MapDev m, SplatArgs a, int32_t n_targets,
   atomicOr(err, DEVERR_HASH);
 }
 
-__global__ void k_fill_alpha0(float* __restrict__ alpha, int64_t n, float a0) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) alpha[i] = a0;
-}
-
 template <int B, int R>
 hipError_t launch_splat_br(const SplatArgs& a, int64_t n_units, int32_t n_targets, bool merge,
                            hipStream_t st) {
@@ -363,9 +537,11 @@ hipError_t launch_splat_br(const SplatArgs& a, int64_t n_units, int32_t n_target
     if (n_units > 0)
       hipLaunchKernelGGL((k_splat<B, R>), dim3((unsigned)n_units), dim3(SMKI_WAVE), 0, st, a);
   } else {
+    if (a.n_slots > 0)
+      hipLaunchKernelGGL(k_slot_info, dim3(nblk(a.n_slots, 256)), dim3(256), 0, st, a);
     if (n_targets > 0)
-      hipLaunchKernelGGL((k_merge<B, R>), dim3((unsigned)n_targets), dim3(256), 0, st, a,
-                         n_targets);
+      hipLaunchKernelGGL((k_merge<B, R>), dim3((unsigned)n_targets), dim3(MergeShape<B, R>::NT), 0,
+                         st, a, n_targets);
   }
   return hipGetLastError();
 }
@@ -453,14 +629,5 @@ hipError_t launch_assign_new(const MapDev& m, const SplatArgs& a, int32_t n_targ
   if (n_targets <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_assign_new, dim3(nblk(n_targets, 256)), dim3(256), 0, st, m, a, n_targets,
                      is_new, new_rank, n_old, tgt_slot, err);
-  return hipGetLastError();
-}
-
-hipError_t launch_fill_alpha0(const MapDev& m, int64_t slot0, int64_t nslots, hipStream_t st) {
-  const int64_t per = (int64_t)m.K * m.B * m.B * m.B;
-  const int64_t n = nslots * per;
-  if (n <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_fill_alpha0, dim3(nblk(n, 256)), dim3(256), 0, st, m.alpha + slot0 * per,
-                     n, m.alpha0);
   return hipGetLastError();
 }
