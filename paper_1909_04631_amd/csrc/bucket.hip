@@ -165,6 +165,26 @@ __device__ __forceinline__ float4 make_record(const BucketGeom& g, float x, floa
   return o;
 }
 
+// Record of a map row: |u| per axis, u = x - (v + 1/2) res the row relative to
+// the centre of its voxel (double, rounded once), and in .w the row's cell
+// within its block and the octant of u:  (cell << 3) | (ux < 0) | (uy < 0) << 1
+// | (uz < 0) << 2.  The class is the row's plane in the key, not stored here.
+__device__ __forceinline__ float4 make_map_record(const BucketGeom& g, float x, float y, float z,
+                                                  const int32_t v[3], const int32_t l[3]) {
+  const double r = (double)g.res;
+  const double ux = (double)x - ((double)v[0] + 0.5) * r;
+  const double uy = (double)y - ((double)v[1] + 0.5) * r;
+  const double uz = (double)z - ((double)v[2] + 0.5) * r;
+  const int32_t cell = (l[0] << (2 * g.log2B)) | (l[1] << g.log2B) | l[2];
+  const int32_t oct = (ux < 0.0 ? 1 : 0) | (uy < 0.0 ? 2 : 0) | (uz < 0.0 ? 4 : 0);
+  float4 o;
+  o.x = (float)fabs(ux);
+  o.y = (float)fabs(uy);
+  o.z = (float)fabs(uz);
+  o.w = __int_as_float((cell << 3) | oct);
+  return o;
+}
+
 __device__ __forceinline__ bool in_grid(const BucketGeom& g, const int32_t b[3]) {
   return b[0] >= g.blo[0] && b[0] < g.blo[0] + g.nb[0] && b[1] >= g.blo[1] &&
          b[1] < g.blo[1] + g.nb[1] && b[2] >= g.blo[2] && b[2] < g.blo[2] + g.nb[2];
@@ -189,7 +209,7 @@ __global__ void k_hit_keys(const float* __restrict__ xyz, const int32_t* __restr
   if (!in_grid(g, b)) { atomicOr(err, DEVERR_RANGE); keys[w] = (KeyT)0; idx[w] = w; rec[w] = make_float4(0, 0, 0, 0); return; }
   keys[w] = make_key<KeyT>(g, label[i], b, l);
   idx[w] = (uint32_t)w;
-  rec[w] = make_record(g, px, py, pz, b, label[i]);
+  rec[w] = make_map_record(g, px, py, pz, v, l);
 }
 
 // Free sample f -> its beam (largest i with off[i] <= f), its position, key and record.
@@ -230,7 +250,7 @@ __global__ void k_free_keys(const float* __restrict__ xyz, int64_t n,
   if (!in_grid(g, b)) { atomicOr(err, DEVERR_RANGE); keys[w] = (KeyT)0; idx[w] = (uint32_t)w; rec[w] = make_float4(0, 0, 0, 0); return; }
   keys[w] = make_key<KeyT>(g, free_class, b, l);
   idx[w] = (uint32_t)w;
-  rec[w] = make_record(g, qx, qy, qz, b, free_class);
+  rec[w] = make_map_record(g, qx, qy, qz, v, l);
 }
 
 // Explicit training rows (differentiable form, tests): keys and records.

@@ -406,9 +406,6 @@ void release(char** own, hipStream_t st) {
 
 LossArgs make_args(const BucketGeom& g, const SetBufs& s, float l, float sigma0, float alpha0,
                    int32_t K, int64_t H) {
-  static const double kQ[SMKI_POLY_N] = {
-      -0.006484397132806161, 0.07136417330604423, -0.4518001709419727, 2.02382364154106,
-      -6.405593664147021,    13.387587273598974,  -16.27748266990142,  8.658585806723543};
   LossArgs a{};
   a.g = g;
   a.pts = s.ps.pts;
@@ -420,7 +417,7 @@ LossArgs make_args(const BucketGeom& g, const SetBufs& s, float l, float sigma0,
   a.inv_l = 1.0f / l;
   a.sigma0 = sigma0;
   a.alpha0 = alpha0;
-  for (int i = 0; i < SMKI_POLY_N; ++i) a.coef[i] = (float)(kQ[i] * (double)sigma0);
+  for (int i = 0; i < SMKI_POLY_N; ++i) a.coef[i] = (float)(kSmkiQ[i] * (double)sigma0);
   a.K = K;
   a.H = H;
   return a;

@@ -9,15 +9,6 @@
 #include "../../include/smki.h"
 #include "smki_gather.h"
 
-// ---------------------------------------------------------------------------
-// kernel polynomial: f(1 - s) = s^5 Q(s^2) for the sparse kernel of Eq. (8);
-// Q below is a weighted least-squares degree-7 fit in u = s^2 on [0, 1] (relative
-// error 7e-9) to the series  Q(u) = sum_{n>=2} (-1)^n (2n-2) (2 pi)^(2n) u^(n-2) / (3 (2n+1)!),
-// obtained by expanding cos and sin of 2 pi (1 - s) in Eq. (8).  Highest degree first.
-// ---------------------------------------------------------------------------
-static const double kQ[SMKI_POLY_N] = {
-    -0.006484397132806161, 0.07136417330604423, -0.4518001709419727, 2.02382364154106,
-    -6.405593664147021,    13.387587273598974,  -16.27748266990142,  8.658585806723543};
 
 int32_t smki_hip_error(hipError_t e) {
   return e == hipErrorOutOfMemory ? SMKI_E_OOM : SMKI_E_DEVICE;
@@ -123,10 +114,12 @@ smki_status status_of_err(uint32_t e) {
   return SMKI_E_DEVICE;
 }
 
-// Voxel offsets (relative to a cell) whose centroid can lie within l of some
-// point of that cell: every o with sum_a max(0, |o_a| - 1/2)^2 < (l/res + margin)^2
-// (voxel units; the margin covers a point assigned to the neighbouring cell by
-// the rounding of floor(x / res)).  Ordered with z fastest.
+// First-octant stencil: voxel offsets o (relative to a cell) whose centroid can
+// lie within l of some point in the (+,+,+) octant of that cell, i.e. with the
+// point at u in [0, 1/2]^3 (voxel units, relative to the cell centre):
+// sum_a dist(o_a, [0, 1/2])^2 < (l/res + margin)^2.  The margin covers a point
+// assigned to the neighbouring cell by the rounding of floor(x / res).  A point
+// in another octant uses the mirrored offsets.  Ordered with z fastest.
 struct Stencil {
   int32_t R = 0;
   std::vector<StencilOff> offs;
@@ -136,12 +129,11 @@ Stencil make_stencil(double lv, double margin) {
   Stencil s;
   const double L = lv + margin;
   s.R = std::max(0, (int32_t)ceil(lv + 0.5 + margin) - 1);
+  auto dist = [](int o) { return o >= 1 ? o - 0.5 : (o == 0 ? 0.0 : -(double)o); };
   for (int dx = -s.R; dx <= s.R; ++dx)
     for (int dy = -s.R; dy <= s.R; ++dy)
       for (int dz = -s.R; dz <= s.R; ++dz) {
-        const double ax = std::max(0.0, fabs((double)dx) - 0.5);
-        const double ay = std::max(0.0, fabs((double)dy) - 0.5);
-        const double az = std::max(0.0, fabs((double)dz) - 0.5);
+        const double ax = dist(dx), ay = dist(dy), az = dist(dz);
         if (ax * ax + ay * ay + az * az < L * L) s.offs.push_back(StencilOff{dx, dy, dz, 0});
       }
   return s;
@@ -545,7 +537,7 @@ smki_status smki_create_map(float res, int32_t block_size, float l, float sigma0
   m->log2B = ilog2(block_size);
   m->free_class = free_class;
   m->chunk = (opt && opt->unit_budget > 0) ? opt->unit_budget : SMKI_CHUNK;
-  for (int i = 0; i < SMKI_POLY_N; ++i) m->coef[i] = (float)(kQ[i] * (double)sigma0);
+  for (int i = 0; i < SMKI_POLY_N; ++i) m->coef[i] = (float)(kSmkiQ[i] * (double)sigma0);
   (void)hipGetDevice(&m->device);
   m->dev.K = K;
   m->dev.B = block_size;

@@ -4,8 +4,17 @@
 
 #define SMKI_MAX_REACH 4            // largest stencil reach in voxels
 #define SMKI_MAX_OFFS 729           // (2 * SMKI_MAX_REACH + 1)^3
-#define SMKI_POLY_N 8               // coefficients of the kernel polynomial
+#define SMKI_POLY_N 7               // coefficients of the kernel polynomial
 #define SMKI_CHUNK 1024             // default rows of one (class, block) per splat work unit
+
+// Sparse kernel of Eq. (8): f(1 - s) = s^5 Q(s^2) with s = 1 - d/l.  Q below is a
+// degree-6 relative least-squares fit in u = s^2 on [0, 1] to the series
+// Q(u) = sum_{n>=2} (-1)^n (2n-2) (2 pi)^(2n) u^(n-2) / (3 (2n+1)!), obtained by
+// expanding cos and sin of 2 pi (1 - s); fit error 2.6e-7 relative, 1.3e-6 when
+// evaluated in binary32 (kernel_poly.py derives it).  Highest degree first.
+static constexpr double kSmkiQ[SMKI_POLY_N] = {
+    0.04696689938778598, -0.41528081234338315, 1.9962683906096352, -6.394682424213184,
+    13.385465187748379,  -16.277320609426397,  8.658583627197082};
 
 // Block-hash and pool of the persistent map.
 struct MapDev {
@@ -34,7 +43,7 @@ struct SplatArgs {
   int32_t K;
   int32_t chunk;              // rows of one (class, block) per work unit
   // sorted rows
-  const float4* pts;          // records: xyz relative to the row block's centre, label bits
+  const float4* pts;          // records: |row - its voxel centre| per axis; (cell << 3 | octant) bits
   const int32_t* dense;       // [n_blocks * K] (block, class) -> slot
   const int32_t* prefix;      // [slots][B^3 + 1]
   const int32_t* slot_lin;    // [slots] (class, block) linear index

@@ -24,8 +24,9 @@
 //
 // Kernel evaluation: with s = 1 - r, f(1 - s) = s^5 Q(s^2) exactly (the Taylor
 // series of the sparse kernel about r = 1 has only odd powers from s^5 on);
-// Q is a degree-7 polynomial fit, which keeps f relatively accurate up to the
-// support edge where the direct formula cancels.
+// Q is a degree-6 polynomial fit (kernel_poly.py), which keeps f relatively
+// accurate (about 1.3e-6 in binary32) up to the support edge, where the direct
+// formula cancels.
 #include "smki_gather.h"
 
 namespace {
@@ -43,15 +44,6 @@ __device__ __forceinline__ void unlin3(int64_t lin, const int32_t n[3], int32_t 
   lin /= n[2];
   out[1] = (int32_t)(lin % n[1]);
   out[0] = (int32_t)(lin / n[1]);
-}
-
-// sigma0 f(r) from s = 1 - r: s^5 * (sigma0 Q)(s^2)
-__device__ __forceinline__ float kernel_weight(const float* c, float s) {
-  const float u = s * s;
-  float q = c[0];
-#pragma unroll
-  for (int i = 1; i < SMKI_POLY_N; ++i) q = fmaf(q, u, c[i]);
-  return (u * u) * (s * q);
 }
 
 // ---------------------------------------------------------------------------
@@ -110,10 +102,13 @@ __global__ void k_unit_table(const int32_t* __restrict__ nunits, const int32_t* 
 // ---------------------------------------------------------------------------
 // splat
 // ---------------------------------------------------------------------------
-// NS: steps of 64 voxel offsets, enough for any stencil of reach R.
+// NS: steps of 64 voxel offsets, enough for the first-octant stencil of any
+// l / res with reach R (its size is largest at l / res -> R + 1/2: 1, 23, 90,
+// 230, 471 offsets for R = 0..4).
 template <int R>
 struct Steps {
-  static constexpr int NS = ((2 * R + 1) * (2 * R + 1) * (2 * R + 1) + SMKI_WAVE - 1) / SMKI_WAVE;
+  static constexpr int MAXOFF = R == 0 ? 1 : R == 1 ? 23 : R == 2 ? 90 : R == 3 ? 230 : 471;
+  static constexpr int NS = (MAXOFF + SMKI_WAVE - 1) / SMKI_WAVE;
 };
 
 // The region of a (class, block) work unit, (B + 2R)^3 voxels, split into 27
@@ -164,68 +159,107 @@ __global__ void __launch_bounds__(SMKI_WAVE) k_splat(SplatArgs a) {
   const int32_t r0 = P[0] + u.y * a.chunk;
   const int32_t r1 = min(P[B3], r0 + a.chunk);
   for (int i = lane; i < DR3; i += SMKI_WAVE) acc[i] = 0.0f;
-  // per-lane offset data for each step: voxel-centre offset (in the frame of
-  // the row's cell, minus the block-centre shift) and region-index offset
+  // Per lane, for each step: one voxel offset o of the first-octant stencil
+  // (offsets whose centre can lie within l of a point in the (+,+,+) octant of
+  // its cell) as a centre offset in metres, and its region-index offset for
+  // each of the 8 octants: a row in octant (sx, sy, sz) reaches voxel
+  // cell + (sx ox, sy oy, sz oz), at the distance from |u| to o.
   float wx[NS], wy[NS], wz[NS];
-  int32_t wl[NS];
+  int32_t wl[8][NS];
   const float res = a.g.res;
 #pragma unroll
   for (int s = 0; s < NS; ++s) {
     const int o = s * SMKI_WAVE + lane;
+    int4 off = make_int4(0, 0, 0, 0);
     if (o < a.noff) {
-      const int4 off = a.offs[o];
-      wx[s] = ((float)off.x + (0.5f - 0.5f * B)) * res;
-      wy[s] = ((float)off.y + (0.5f - 0.5f * B)) * res;
-      wz[s] = ((float)off.z + (0.5f - 0.5f * B)) * res;
-      wl[s] = (off.x * DR + off.y) * DR + off.z;
+      off = a.offs[o];
+      wx[s] = (float)off.x * res;
+      wy[s] = (float)off.y * res;
+      wz[s] = (float)off.z * res;
     } else {
       wx[s] = wy[s] = wz[s] = 1.0e30f;   // never within l
-      wl[s] = 0;
     }
+#pragma unroll
+    for (int oc = 0; oc < 8; ++oc)
+      wl[oc][s] = ((oc & 1) ? -off.x : off.x) * DR * DR + ((oc & 2) ? -off.y : off.y) * DR +
+                  ((oc & 4) ? -off.z : off.z);
   }
   const int ns = (a.noff + SMKI_WAVE - 1) / SMKI_WAVE;
   __syncthreads();
-  // first cell holding row r0
-  int32_t lo = 0, hi = B3 - 1;
-  while (lo < hi) {
-    const int32_t mid = (lo + hi + 1) >> 1;
-    if (P[mid] <= r0) lo = mid; else hi = mid - 1;
-  }
   const float4* __restrict__ pts = a.pts;
-  int32_t npair = 0;
-  for (int32_t c = lo; c < B3; ++c) {
-    const int32_t c0 = max(P[c], r0), c1 = min(P[c + 1], r1);
-    if (c0 >= r1) break;
-    if (c0 >= c1) continue;
-    const int32_t cx = c / (B * B), cy = (c / B) % B, cz = c % B;
-    const float ux0 = (float)cx * res, uy0 = (float)cy * res, uz0 = (float)cz * res;
-    float sum[NS];
+  uint32_t npair = 0;
+  int32_t gkey = -1, gcb = 0;   // current (cell, octant) group and its region index
+  float sum[NS];
+#pragma unroll
+  for (int s = 0; s < NS; ++s) sum[s] = 0.0f;
+  // Lanes add their non-zero group sums to distinct LDS addresses (all reads of
+  // a flush first, then all writes).  The LDS executes one wavefront's reads
+  // and writes in issue order and the compiler keeps flushes in program order
+  // (signal fence), so every voxel sums its rows in row order.
+  auto flush = [&]() {
+    const int oc = gkey & 7;
+    __atomic_signal_fence(__ATOMIC_SEQ_CST);
+    switch (oc) {
+#define SMKI_FLUSH_CASE(OC)                                                  \
+  case OC: {                                                                 \
+    float old[NS];                                                           \
+    _Pragma("unroll") for (int s = 0; s < NS; ++s)                           \
+        old[s] = (s < ns && sum[s] != 0.0f) ? acc[gcb + wl[OC][s]] : 0.0f;   \
+    _Pragma("unroll") for (int s = 0; s < NS; ++s)                           \
+        if (s < ns && sum[s] != 0.0f) acc[gcb + wl[OC][s]] = old[s] + sum[s]; \
+    break;                                                                   \
+  }
+      SMKI_FLUSH_CASE(0) SMKI_FLUSH_CASE(1) SMKI_FLUSH_CASE(2) SMKI_FLUSH_CASE(3)
+      SMKI_FLUSH_CASE(4) SMKI_FLUSH_CASE(5) SMKI_FLUSH_CASE(6) SMKI_FLUSH_CASE(7)
+#undef SMKI_FLUSH_CASE
+    }
 #pragma unroll
     for (int s = 0; s < NS; ++s) sum[s] = 0.0f;
-    for (int32_t r = c0; r < c1; ++r) {
-      const float4 q = pts[r];
-      const float ux = q.x - ux0, uy = q.y - uy0, uz = q.z - uz0;
+  };
+  // Rows are staged 64 at a time in registers (lane i holds row base + i; the
+  // next batch is loaded while this one is processed) and broadcast with
+  // v_readlane: the record loads never wait on the LDS atomics.
+  auto load_batch = [&](int32_t base) {
+    const int32_t r = base + lane;
+    return r < r1 ? pts[r] : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+  };
+  float4 cur = load_batch(r0);
+  for (int32_t base = r0; base < r1; base += SMKI_WAVE) {
+    const float4 nxt = load_batch(base + SMKI_WAVE);
+    const int nb = min(SMKI_WAVE, r1 - base);
+    for (int j = 0; j < nb; ++j) {
+      const float qx = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(cur.x), j));
+      const float qy = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(cur.y), j));
+      const float qz = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(cur.z), j));
+      const int32_t key = __builtin_amdgcn_readlane(__float_as_int(cur.w), j);
+      if (key != gkey) {
+        if (gkey >= 0) flush();
+        gkey = key;
+        const int c = key >> 3;
+        gcb = ((c / (B * B) + R) * DR + ((c / B) % B + R)) * DR + (c % B + R);
+      }
 #pragma unroll
       for (int s = 0; s < NS; ++s) {
         if (s < ns) {
-          const float dx = ux - wx[s], dy = uy - wy[s], dz = uz - wz[s];
+          const float dx = qx - wx[s], dy = qy - wy[s], dz = qz - wz[s];
           const float d2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
-          if (d2 < a.l2) {
+          const bool in = d2 < a.l2;
+          npair += (uint32_t)__popcll(__ballot(in));
+          if (in) {
             const float d = __builtin_amdgcn_sqrtf(d2);
             const float sv = fmaxf(fmaf(-d, a.inv_l, 1.0f), 0.0f);
-            sum[s] += kernel_weight(a.coef, sv);
-            ++npair;
+            const float uu = sv * sv;
+            float qq = fmaf(a.coef[0], uu, a.coef[1]);
+#pragma unroll
+            for (int i = 2; i < SMKI_POLY_N; ++i) qq = fmaf(qq, uu, a.coef[i]);
+            sum[s] = fmaf(uu * uu, sv * qq, sum[s]);
           }
         }
       }
     }
-    const int32_t cb = ((cx + R) * DR + (cy + R)) * DR + (cz + R);
-#pragma unroll
-    for (int s = 0; s < NS; ++s)
-      if (s < ns && sum[s] != 0.0f) acc[cb + wl[s]] += sum[s];
-    // the next cell's lanes may own these addresses: keep the LDS order
-    __syncthreads();
+    cur = nxt;
   }
+  if (gkey >= 0) flush();
   __syncthreads();
   // pieces that received a contribution
   uint32_t touched = 0;
@@ -270,8 +304,7 @@ __global__ void __launch_bounds__(SMKI_WAVE) k_splat(SplatArgs a) {
     const int32_t t = a.ext2t[e];
     if (t >= 0) a.tgt_active[t] = 1;
   }
-  const int64_t np = wave_sum_i64((int64_t)npair);
-  if (lane == 0) atomicAdd(&a.stats[1], (unsigned long long)np);
+  if (lane == 0) atomicAdd(&a.stats[1], (unsigned long long)npair);
 }
 
 // ---------------------------------------------------------------------------
@@ -561,7 +594,10 @@ hipError_t launch_splat_b(const SplatArgs& a, int64_t n_units, int32_t n_targets
 
 hipError_t launch_splat_any(const SplatArgs& a, int64_t n_units, int32_t n_targets, bool merge,
                             hipStream_t st) {
-  if (a.noff > SMKI_WAVE * ((2 * a.R + 1) * (2 * a.R + 1) * (2 * a.R + 1) + SMKI_WAVE - 1) / SMKI_WAVE)
+  static const int kMaxOff[SMKI_MAX_REACH + 1] = {Steps<0>::MAXOFF, Steps<1>::MAXOFF,
+                                                  Steps<2>::MAXOFF, Steps<3>::MAXOFF,
+                                                  Steps<4>::MAXOFF};
+  if (a.R < 0 || a.R > SMKI_MAX_REACH || a.noff < 1 || a.noff > kMaxOff[a.R])
     return hipErrorInvalidValue;
   switch (a.g.B) {
     case 4: return launch_splat_b<4>(a, n_units, n_targets, merge, st);

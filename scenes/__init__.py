@@ -105,6 +105,25 @@ class World:
     def add_ellipsoid(self, c, radii, cls):
         self.ellipsoids.append((np.asarray(c, np.float64), np.asarray(radii, np.float64), int(cls)))
 
+    def near(self, o, radius: float) -> "World":
+        """The primitives that can be hit from o within `radius` (planes kept):
+        casting from o with tmax <= radius against this subset gives the same
+        result as against the whole world."""
+        o = np.asarray(o, np.float64)
+        w = World()
+        w.planes = list(self.planes)
+
+        def close(lo, hi):
+            q = np.clip(o, lo, hi)
+            return float(np.linalg.norm(q - o)) <= radius
+
+        w.boxes = [b for b in self.boxes if close(b[0], b[1])]
+        w.cyls = [c for c in self.cyls
+                  if close(np.array([c[0] - c[2], c[1] - c[2], c[3]]),
+                           np.array([c[0] + c[2], c[1] + c[2], c[4]]))]
+        w.ellipsoids = [e for e in self.ellipsoids if close(e[0] - e[1], e[0] + e[1])]
+        return w
+
     def cast(self, o: np.ndarray, d: np.ndarray, tmax: float = np.inf):
         """Nearest hit along rays o + t d (o [3] or [R,3], d [R,3] unit).
 
@@ -256,7 +275,8 @@ def _street_world(rng, length=120.0, n_classes=19):
     w = World()
     # class map (ids are only labels; which id goes to which primitive kind is arbitrary)
     ROAD, SIDEWALK, TERRAIN, BUILDING, CAR, POLE, VEG, TRUNK, SIGN, FENCE = 1, 2, 3, 4, 5, 6, 7, 8, 9, 10
-    extra = list(range(11, n_classes + 1))  # further vehicle / object classes
+    # further vehicle / object classes (with 10 classes, cars and signs stand in)
+    extra = list(range(11, n_classes + 1)) or [CAR, SIGN]
 
     def ground_cls(p):
         ay = np.abs(p[:, 1])
@@ -325,6 +345,7 @@ def _lidar_dirs(n_beams=64, n_az=2048, el_lo=-25.0, el_hi=3.0, yaw=0.0):
 
 def _lidar_returns(rng, world, origin, dirs, rmin=2.0, rmax=50.0, sigma=0.02, chunk=1 << 16):
     ts, cs = [], []
+    world = world.near(origin, rmax + 1.0)
     for i in range(0, dirs.shape[0], chunk):
         t, c = world.cast(origin, dirs[i:i + chunk], tmax=rmax + 1.0)
         ts.append(t)
@@ -384,8 +405,9 @@ def stereo_sequence_scene(seed: int = 2, n_scans: int = 100, width: int = 1242,
     for s in range(n_scans):
         origin = np.array([-0.5 * n_scans * step + s * step, 0.0, 1.65])
         t, c = [], []
+        ws = w.near(origin, zmax * 1.5)
         for i in range(0, dirs_u.shape[0], 1 << 16):
-            ti, ci = w.cast(origin, dirs_u[i:i + (1 << 16)], tmax=zmax * 1.5)
+            ti, ci = ws.cast(origin, dirs_u[i:i + (1 << 16)], tmax=zmax * 1.5)
             t.append(ti)
             c.append(ci)
         t = np.concatenate(t)
