@@ -46,8 +46,9 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-extras", action="store_true", help="skip the loss and batched lines")
-    ap.add_argument("--cpu-sample-stride", type=int, default=16)
+    ap.add_argument("--no-extras", action="store_true", help="skip the differentiable-form line")
+    ap.add_argument("--cpu-sample-stride", type=int, default=2)
+    ap.add_argument("--no-batched", action="store_true", help="skip the 64-scan batched line")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only copy a MIB-MiB device buffer 5 times (scale for HBM counters)")
     args = ap.parse_args()
@@ -150,8 +151,11 @@ def main():
         },
     }
 
+    out["roofline"]["traffic"] = splat_traffic()
     if not args.no_extras:
         out["fwd_bwd"] = bench_loss(torch, dev, predictive_loss)
+    if not args.no_batched:
+        out["batched"] = bench_batched(torch, dev, SemanticMap)
 
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(sc, V, args.cpu_sample_stride)
@@ -186,24 +190,101 @@ def bench_loss(torch, dev, predictive_loss, reps=20):
         torch.cuda.synchronize()
         return 1e3 * (time.perf_counter() - t) / reps
 
-    def fwd():
+    def plain():
         with torch.no_grad():
             return predictive_loss(tx, ty, qx, qy, l, s0, p.alpha0, p.K)
+
+    def fwd():
+        return predictive_loss(txg, ty, qx, qy, l, s0, p.alpha0, p.K)
 
     def fwd_bwd():
         L = predictive_loss(txg, ty, qx, qy, l, s0, p.alpha0, p.K)
         L.backward()
         return L
 
-    t_plain = timeit(fwd)
+    t_plain = timeit(plain)
+    t_fwd = timeit(fwd)
     t_fb = timeit(fwd_bwd)
-    t_fwd = t_plain
     t_bwd = max(t_fb - t_fwd, 0.0)
     return {"workload": "tiny scene, 20% of hits held out (1600 hits + free samples, 400 queries)",
             "train_rows": int(tx.shape[0]), "queries": int(qx.shape[0]),
             "t_fwd_ms": t_fwd, "t_bwd_ms": t_bwd, "t_plain_ms": t_plain,
             "bwd_over_fwd": t_bwd / t_fwd if t_fwd > 0 else None,
             "fwd_bwd_over_plain": t_fb / t_plain if t_plain > 0 else None}
+
+
+def splat_traffic():
+    """HBM bytes per k_splat launch on this workload from the committed counter
+    profile (FETCH_SIZE and WRITE_SIZE, each scaled by a 1 GiB copy measured the
+    same way), or None when the kernel source changed since it was taken."""
+    import hashlib
+    prof = os.path.join(HERE, "profiles", "k_splat_lidar_hbm_traffic.txt")
+    src = os.path.join(HERE, "paper_1909_04631_amd", "csrc", "splat.hip")
+    if not os.path.exists(prof):
+        return None
+    fields = {}
+    for line in open(prof):
+        if "=" in line and not line.startswith("#"):
+            k, v = line.split("=", 1)
+            fields[k.strip()] = v.strip()
+    digest = hashlib.sha256(open(src, "rb").read()).hexdigest()
+    if fields.get("splat_hip_sha256") != digest or "hbm_bytes_per_launch" not in fields:
+        return None
+    return float(fields["hbm_bytes_per_launch"])
+
+
+def bench_batched(torch, dev, SemanticMap):
+    """64 scans of a synthetic town (U[10k, 130k] hits each): one batched insert
+    beside 64 sequential inserts, both into a fresh map.  V = sum over scans of
+    each scan's updated voxels (from the sequential run)."""
+    import scenes
+    t0 = time.time()
+    sc = scenes.make_config(3)
+    p = sc.params
+    log(f"[bench] town generated in {time.time() - t0:.1f}s: {len(sc.scans)} scans")
+    xyz = [torch.from_numpy(s.xyz).to(dev) for s in sc.scans]
+    lab = [torch.from_numpy(s.label).to(dev) for s in sc.scans]
+    cat_xyz, cat_lab = torch.cat(xyz).contiguous(), torch.cat(lab).contiguous()
+    offs = [0]
+    for s in sc.scans:
+        offs.append(offs[-1] + s.xyz.shape[0])
+    origins = [s.origin for s in sc.scans]
+    m = SemanticMap.from_params(p, initial_blocks=1 << 18)
+
+    def sequential():
+        m.reset()
+        v = 0
+        for i, s in enumerate(sc.scans):
+            m.insert_scan(xyz[i], lab[i], s.origin, p.free_step)
+            v += m.stats()["n_updated_voxels"]
+        return v
+
+    def batched():
+        m.reset()
+        m.insert_scans(cat_xyz, cat_lab, offs, origins, p.free_step)
+
+    def timed(fn, reps):
+        r = None
+        for _ in range(1):
+            r = fn()
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for _ in range(reps):
+            r = fn()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t) / reps, r
+
+    t_seq, V = timed(sequential, 3)
+    t_bat, _ = timed(batched, 3)
+    st = m.stats()
+    log(f"[bench] batched: {t_bat * 1e3:.1f} ms vs sequential {t_seq * 1e3:.1f} ms")
+    return {"workload": "town_64_scans_K20_res0.2_B8_l0.3_s0.1_step0.3",
+            "hits": int(offs[-1]), "rows": int(st["n_hits"] + st["n_free"]),
+            "voxel_updates_sum_over_scans": int(V),
+            "t_batched_ms": t_bat * 1e3, "t_sequential_ms": t_seq * 1e3,
+            "batched_voxel_updates_per_s": V / t_bat, "sequential_voxel_updates_per_s": V / t_seq,
+            "speedup": t_seq / t_bat, "batched_splat_ms": st["splat_ms"],
+            "batched_merge_ms": st["merge_ms"]}
 
 
 def cpu_baseline(sc, V_full, stride):
