@@ -92,7 +92,6 @@ struct smki_map {
   uint32_t* d_err = nullptr;
   unsigned long long* d_stats = nullptr;
   StencilOff* d_offs = nullptr;
-  float coef[SMKI_POLY_N];
   // workspaces
   Arena a_hits, a_sets, a_tgts, a_misc;
   // pinned host staging
@@ -412,7 +411,8 @@ smki_status insert_impl(smki_map* m, const float* xyz, const int32_t* label, int
   sa.offs = (const int4*)m->d_offs;
   sa.l2 = m->l * m->l;
   sa.inv_l = 1.0f / m->l;
-  for (int i = 0; i < SMKI_POLY_N; ++i) sa.coef[i] = m->coef[i];
+  for (int i = 0; i < SMKI_POLY_N; ++i) sa.mcoef[i] = (float)(kSmkiQ[i] / kSmkiQ[0]);
+  sa.cscale = (float)(kSmkiQ[0] * (double)m->sigma0);
   sa.K = m->K;
   sa.chunk = m->chunk;
   sa.pts = ps.pts;
@@ -537,7 +537,6 @@ smki_status smki_create_map(float res, int32_t block_size, float l, float sigma0
   m->log2B = ilog2(block_size);
   m->free_class = free_class;
   m->chunk = (opt && opt->unit_budget > 0) ? opt->unit_budget : SMKI_CHUNK;
-  for (int i = 0; i < SMKI_POLY_N; ++i) m->coef[i] = (float)(kSmkiQ[i] * (double)sigma0);
   (void)hipGetDevice(&m->device);
   m->dev.K = K;
   m->dev.B = block_size;

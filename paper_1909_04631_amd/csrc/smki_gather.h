@@ -39,7 +39,8 @@ struct SplatArgs {
   int32_t noff;               // voxel offsets in offs
   const int4* offs;           // [noff] StencilOff
   float l2, inv_l;
-  float coef[SMKI_POLY_N];    // sigma0 * Q(u) coefficients, highest degree first
+  float mcoef[SMKI_POLY_N];   // Q / Q's leading coefficient (monic), highest degree first
+  float cscale;               // sigma0 * Q's leading coefficient
   int32_t K;
   int32_t chunk;              // rows of one (class, block) per work unit
   // sorted rows

@@ -26,7 +26,8 @@
 // series of the sparse kernel about r = 1 has only odd powers from s^5 on);
 // Q is a degree-6 polynomial fit (kernel_poly.py), which keeps f relatively
 // accurate (about 1.3e-6 in binary32) up to the support edge, where the direct
-// formula cancels.
+// formula cancels.  The splat evaluates Q divided by its leading coefficient
+// (monic) and applies sigma0 times that coefficient once per flushed sum.
 #include "smki_gather.h"
 
 namespace {
@@ -109,6 +110,8 @@ template <int R>
 struct Steps {
   static constexpr int MAXOFF = R == 0 ? 1 : R == 1 ? 23 : R == 2 ? 90 : R == 3 ? 230 : 471;
   static constexpr int NS = (MAXOFF + SMKI_WAVE - 1) / SMKI_WAVE;
+  // fewest steps a reach-R stencil can need (its size at l / res -> R - 1/2)
+  static constexpr int NSMIN = R <= 2 ? 1 : R == 3 ? 2 : 4;
 };
 
 // The region of a (class, block) work unit, (B + 2R)^3 voxels, split into 27
@@ -145,12 +148,13 @@ __device__ __forceinline__ int pbase(int p) {
   return b;
 }
 
-template <int B, int R>
+// NS = ceil(stencil size / 64), the steps each row takes (compiled per value
+// so that the steps of a row are independent straight-line code).
+template <int B, int R, int NS>
 __global__ void __launch_bounds__(SMKI_WAVE) k_splat(SplatArgs a) {
   constexpr int DR = B + 2 * R;                 // region edge (voxels)
   constexpr int DR3 = DR * DR * DR;
   constexpr int B3 = B * B * B;
-  constexpr int NS = Steps<R>::NS;
   __shared__ float acc[DR3];
   const int lane = threadIdx.x;
   const int2 u = a.units[blockIdx.x];
@@ -164,27 +168,31 @@ __global__ void __launch_bounds__(SMKI_WAVE) k_splat(SplatArgs a) {
   // its cell) as a centre offset in metres, and its region-index offset for
   // each of the 8 octants: a row in octant (sx, sy, sz) reaches voxel
   // cell + (sx ox, sy oy, sz oz), at the distance from |u| to o.
-  float wx[NS], wy[NS], wz[NS];
+  // The squared distance is evaluated as |q|^2 + |w|^2 - 2 q.w (q: the row's
+  // |u|, at most res sqrt(3)/2; w: the offset's centre): nw = -2 w, w2 = |w|^2.
+  float nwx[NS], nwy[NS], nwz[NS], w2[NS];
   int32_t wl[8][NS];
-  const float res = a.g.res;
+  const double res = (double)a.g.res;
 #pragma unroll
   for (int s = 0; s < NS; ++s) {
     const int o = s * SMKI_WAVE + lane;
     int4 off = make_int4(0, 0, 0, 0);
     if (o < a.noff) {
       off = a.offs[o];
-      wx[s] = (float)off.x * res;
-      wy[s] = (float)off.y * res;
-      wz[s] = (float)off.z * res;
+      const double x = off.x * res, y = off.y * res, z = off.z * res;
+      nwx[s] = (float)(-2.0 * x);
+      nwy[s] = (float)(-2.0 * y);
+      nwz[s] = (float)(-2.0 * z);
+      w2[s] = (float)(x * x + y * y + z * z);
     } else {
-      wx[s] = wy[s] = wz[s] = 1.0e30f;   // never within l
+      nwx[s] = nwy[s] = nwz[s] = 0.0f;
+      w2[s] = 1.0e30f;   // never within l
     }
 #pragma unroll
     for (int oc = 0; oc < 8; ++oc)
       wl[oc][s] = ((oc & 1) ? -off.x : off.x) * DR * DR + ((oc & 2) ? -off.y : off.y) * DR +
                   ((oc & 4) ? -off.z : off.z);
   }
-  const int ns = (a.noff + SMKI_WAVE - 1) / SMKI_WAVE;
   __syncthreads();
   const float4* __restrict__ pts = a.pts;
   uint32_t npair = 0;
@@ -204,9 +212,10 @@ __global__ void __launch_bounds__(SMKI_WAVE) k_splat(SplatArgs a) {
   case OC: {                                                                 \
     float old[NS];                                                           \
     _Pragma("unroll") for (int s = 0; s < NS; ++s)                           \
-        old[s] = (s < ns && sum[s] != 0.0f) ? acc[gcb + wl[OC][s]] : 0.0f;   \
+        old[s] = sum[s] != 0.0f ? acc[gcb + wl[OC][s]] : 0.0f;               \
     _Pragma("unroll") for (int s = 0; s < NS; ++s)                           \
-        if (s < ns && sum[s] != 0.0f) acc[gcb + wl[OC][s]] = old[s] + sum[s]; \
+        if (sum[s] != 0.0f)                                                  \
+          acc[gcb + wl[OC][s]] = fmaf(a.cscale, sum[s], old[s]);             \
     break;                                                                   \
   }
       SMKI_FLUSH_CASE(0) SMKI_FLUSH_CASE(1) SMKI_FLUSH_CASE(2) SMKI_FLUSH_CASE(3)
@@ -238,23 +247,22 @@ __global__ void __launch_bounds__(SMKI_WAVE) k_splat(SplatArgs a) {
         const int c = key >> 3;
         gcb = ((c / (B * B) + R) * DR + ((c / B) % B + R)) * DR + (c % B + R);
       }
+      const float q2 = fmaf(qx, qx, fmaf(qy, qy, qz * qz));
+      // Branch-free: every lane evaluates its pair; out of support (d >= l) the
+      // clamped s is forced to 0, which zeroes the weight s^5 Q(s^2).
 #pragma unroll
       for (int s = 0; s < NS; ++s) {
-        if (s < ns) {
-          const float dx = qx - wx[s], dy = qy - wy[s], dz = qz - wz[s];
-          const float d2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
-          const bool in = d2 < a.l2;
-          npair += (uint32_t)__popcll(__ballot(in));
-          if (in) {
-            const float d = __builtin_amdgcn_sqrtf(d2);
-            const float sv = fmaxf(fmaf(-d, a.inv_l, 1.0f), 0.0f);
-            const float uu = sv * sv;
-            float qq = fmaf(a.coef[0], uu, a.coef[1]);
+        // |d2| only guards rounding below 0 when the row sits on the voxel centre
+        const float d2 = fmaf(qz, nwz[s], fmaf(qy, nwy[s], fmaf(qx, nwx[s], q2 + w2[s])));
+        const bool in = d2 < a.l2;
+        npair += (uint32_t)__popcll(__ballot(in));
+        const float d = __builtin_amdgcn_sqrtf(fabsf(d2));
+        const float sv = in ? fmaf(-d, a.inv_l, 1.0f) : 0.0f;
+        const float uu = sv * sv;
+        float qq = uu + a.mcoef[1];
 #pragma unroll
-            for (int i = 2; i < SMKI_POLY_N; ++i) qq = fmaf(qq, uu, a.coef[i]);
-            sum[s] = fmaf(uu * uu, sv * qq, sum[s]);
-          }
-        }
+        for (int i = 2; i < SMKI_POLY_N; ++i) qq = fmaf(qq, uu, a.mcoef[i]);
+        sum[s] = fmaf(uu * uu, sv * qq, sum[s]);
       }
     }
     cur = nxt;
@@ -563,12 +571,26 @@ __global__ void k_assign_new(MapDev m, SplatArgs a, int32_t n_targets,
   atomicOr(err, DEVERR_HASH);
 }
 
+template <int B, int R, int NSV>
+hipError_t launch_splat_ns(const SplatArgs& a, int64_t n_units, int ns, hipStream_t st) {
+  if constexpr (NSV >= Steps<R>::NSMIN) {
+    if (ns == NSV) {
+      hipLaunchKernelGGL((k_splat<B, R, NSV>), dim3((unsigned)n_units), dim3(SMKI_WAVE), 0, st, a);
+      return hipGetLastError();
+    }
+    return launch_splat_ns<B, R, NSV - 1>(a, n_units, ns, st);
+  } else {
+    return hipErrorInvalidValue;
+  }
+}
+
 template <int B, int R>
 hipError_t launch_splat_br(const SplatArgs& a, int64_t n_units, int32_t n_targets, bool merge,
                            hipStream_t st) {
   if (!merge) {
     if (n_units > 0)
-      hipLaunchKernelGGL((k_splat<B, R>), dim3((unsigned)n_units), dim3(SMKI_WAVE), 0, st, a);
+      return launch_splat_ns<B, R, Steps<R>::NS>(a, n_units, (a.noff + SMKI_WAVE - 1) / SMKI_WAVE,
+                                                 st);
   } else {
     if (a.n_slots > 0)
       hipLaunchKernelGGL(k_slot_info, dim3(nblk(a.n_slots, 256)), dim3(256), 0, st, a);
