@@ -221,11 +221,25 @@ __global__ void k_free_keys(const float* __restrict__ xyz, int64_t n,
                             int32_t free_class, BucketGeom g, int64_t out_base,
                             KeyT* __restrict__ keys, uint32_t* __restrict__ idx,
                             float4* __restrict__ rec, uint32_t* __restrict__ err) {
-  const int64_t f = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  // The beams of this workgroup's samples: the first and last are found by two
+  // threads over all beams, every sample then searches only between them.
+  __shared__ int64_t span[2];
+  const int64_t f0 = (int64_t)blockIdx.x * blockDim.x;
+  const int64_t f = f0 + threadIdx.x;
+  if (threadIdx.x == 0 || threadIdx.x == blockDim.x - 1) {
+    const int64_t g = min(f, nf - 1);
+    int64_t lo = 0, hi = n - 1;
+    while (lo < hi) {
+      const int64_t mid = (lo + hi + 1) >> 1;
+      if (off[mid] <= g) lo = mid; else hi = mid - 1;
+    }
+    span[threadIdx.x == 0 ? 0 : 1] = lo;
+  }
+  __syncthreads();
   if (f >= nf) return;
-  int64_t lo = 0, hi = n - 1;
+  int64_t lo = span[0], hi = span[1];
   while (lo < hi) {
-    int64_t mid = (lo + hi + 1) >> 1;
+    const int64_t mid = (lo + hi + 1) >> 1;
     if (off[mid] <= f) lo = mid; else hi = mid - 1;
   }
   const int64_t i = lo;
@@ -299,8 +313,10 @@ template <typename KeyT>
 __global__ void k_slot_heads(const KeyT* __restrict__ keys, int64_t n, int log2B3, int64_t n_blocks,
                              int32_t planes, const int32_t* __restrict__ flag,
                              const int32_t* __restrict__ slot_excl, int32_t* __restrict__ dense,
-                             int32_t* __restrict__ slot_lin, int32_t* __restrict__ head) {
+                             int32_t* __restrict__ slot_lin, int32_t* __restrict__ head,
+                             const int32_t* __restrict__ d_nslots) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i == 0) head[*d_nslots] = (int32_t)n;
   if (i >= n || !flag[i]) return;
   const int64_t blk = (int64_t)((uint64_t)keys[i] >> log2B3);   // plane * n_blocks + block
   const int32_t slot = slot_excl[i];
@@ -410,16 +426,17 @@ static hipError_t finish_set(PointSet& ps, KeyT* keys, uint32_t* idx, KeyT* akey
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_slot_heads<KeyT>, dim3(nblk(n, 256)), dim3(256), 0, st, keys, n, log2B3,
                      g.n_blocks, g.planes, scr.flag, scr.slot_excl, ps.dense, ps.slot_lin,
-                     scr.slot_head);
+                     ps.head, ps.d_nslots);
+  if (!ps.prefix) return hipGetLastError();
   const unsigned grid = (unsigned)std::min<int64_t>(n, 8192);
   switch (log2B3) {
     case 6:
       hipLaunchKernelGGL((k_slot_prefix<KeyT, 6>), dim3(grid), dim3(256), 0, st, keys, n,
-                         scr.slot_head, ps.d_nslots, ps.prefix);
+                         ps.head, ps.d_nslots, ps.prefix);
       break;
     case 9:
       hipLaunchKernelGGL((k_slot_prefix<KeyT, 9>), dim3(grid), dim3(256), 0, st, keys, n,
-                         scr.slot_head, ps.d_nslots, ps.prefix);
+                         ps.head, ps.d_nslots, ps.prefix);
       break;
     default:
       return hipErrorInvalidValue;

@@ -294,7 +294,7 @@ void carve_set(Carve& c, SetBufs& s, int64_t n, int64_t nblocks_cap) {
   s.scr.rec = c.take<float4>(n);
   s.scr.flag = c.take<int32_t>(n);
   s.scr.slot_excl = c.take<int32_t>(n);
-  s.scr.slot_head = c.take<int32_t>(n);
+  s.ps.head = c.take<int32_t>(n + 1);
   s.scr.sort_tmp = c.take<char>(radix_tmp_bytes(n));
   s.scr.scan_tmp = c.take<char>(scan_tmp_bytes(n));
 }

@@ -324,7 +324,6 @@ smki_status insert_impl(smki_map* m, const float* xyz, const int32_t* label, int
     enb[q2] = g.nb[q2] + 2 * DB;
     n_ext *= enb[q2];
   }
-  const int32_t B3 = m->B * m->B * m->B;
   const int32_t DR = m->B + 2 * sten.R;
   const int64_t DR3 = (int64_t)DR * DR * DR;
 
@@ -335,7 +334,6 @@ smki_status insert_impl(smki_map* m, const float* xyz, const int32_t* label, int
   zb.add<float4>(nt);
   zb.add<int32_t>(g.n_blocks * m->K);
   zb.add<int32_t>(max_slots);
-  zb.add<int32_t>(max_slots * (B3 + 1));
   zb.add<int32_t>(8);
   zb.add<uint64_t>(nt);
   zb.add<uint64_t>(nt);
@@ -344,7 +342,7 @@ smki_status insert_impl(smki_map* m, const float* xyz, const int32_t* label, int
   zb.add<float4>(nt);
   zb.add<int32_t>(nt);
   zb.add<int32_t>(nt);
-  zb.add<int32_t>(nt);
+  zb.add<int32_t>(max_slots + 1);
   zb.add<char>(radix_tmp_bytes(nt));
   zb.add<char>(scan_tmp_bytes(std::max(nt, n_ext)));
   zb.add<int32_t>(n_ext);
@@ -359,7 +357,8 @@ smki_status insert_impl(smki_map* m, const float* xyz, const int32_t* label, int
   ps.pts = Bz.take<float4>(nt);
   ps.dense = Bz.take<int32_t>(g.n_blocks * m->K);
   ps.slot_lin = Bz.take<int32_t>(max_slots);
-  ps.prefix = Bz.take<int32_t>(max_slots * (B3 + 1));
+  ps.prefix = nullptr;   // the splat needs only the slot ranges
+  ps.head = Bz.take<int32_t>(max_slots + 1);
   int32_t* d_si = Bz.take<int32_t>(8);
   ps.d_nslots = d_si;
   int32_t* d_ntgt = d_si + 1;
@@ -372,7 +371,6 @@ smki_status insert_impl(smki_map* m, const float* xyz, const int32_t* label, int
   scr.rec = Bz.take<float4>(nt);
   scr.flag = Bz.take<int32_t>(nt);
   scr.slot_excl = Bz.take<int32_t>(nt);
-  scr.slot_head = Bz.take<int32_t>(nt);
   scr.sort_tmp = Bz.take<char>(radix_tmp_bytes(nt));
   scr.scan_tmp = Bz.take<char>(scan_tmp_bytes(std::max(nt, n_ext)));
   int32_t* d_mark = Bz.take<int32_t>(n_ext);
@@ -387,7 +385,7 @@ smki_status insert_impl(smki_map* m, const float* xyz, const int32_t* label, int
   SMKI_HIP_TRY(launch_mark_targets(ps.slot_lin, ps.d_nslots, (int32_t)max_slots, g, eblo, enb, DB,
                                    d_mark, q));
   SMKI_HIP_TRY(scan_excl_i32(d_mark, d_mpos, n_ext, d_ntgt, scr.scan_tmp, q));
-  SMKI_HIP_TRY(launch_slot_units(ps.prefix, ps.d_nslots, (int32_t)max_slots, B3, m->chunk, d_nun, q));
+  SMKI_HIP_TRY(launch_slot_units(ps.head, ps.d_nslots, (int32_t)max_slots, m->chunk, d_nun, q));
   SMKI_HIP_TRY(scan_excl_i32(d_nun, d_ust, max_slots, d_nunits, scr.scan_tmp, q));
   // sync 2: slots, targets, work units
   int32_t si[3];
@@ -417,7 +415,7 @@ smki_status insert_impl(smki_map* m, const float* xyz, const int32_t* label, int
   sa.chunk = m->chunk;
   sa.pts = ps.pts;
   sa.dense = ps.dense;
-  sa.prefix = ps.prefix;
+  sa.head = ps.head;
   sa.slot_lin = ps.slot_lin;
   sa.nunits = d_nun;
   sa.ustart = d_ust;

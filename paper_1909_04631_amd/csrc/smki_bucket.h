@@ -23,7 +23,9 @@ struct PointSet {
   float4* pts;        // sorted records: xyz relative to the row's block corner, label bits
   int32_t* dense;     // [n_blocks * planes] (grid block, plane) -> slot, -1 if no row
   int32_t* slot_lin;  // [slots] (plane, grid block) linear index of each slot
-  int32_t* prefix;    // [slots][B^3 + 1] first row of each voxel of the block (absolute)
+  int32_t* prefix;    // [slots][B^3 + 1] first row of each voxel of the block (absolute);
+                      // nullptr: not built (only the slot ranges in head)
+  int32_t* head;      // [slots + 1] first row of each slot; head[slots] = rows
   int32_t* d_nslots;  // device scalar: number of slots
 };
 
@@ -36,7 +38,6 @@ struct BucketScratch {
   float4* rec;        // unsorted records
   int32_t* flag;
   int32_t* slot_excl;
-  int32_t* slot_head;  // first row of each slot (capacity = rows)
   void* sort_tmp;
   void* scan_tmp;
 };

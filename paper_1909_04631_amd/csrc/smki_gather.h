@@ -46,7 +46,7 @@ struct SplatArgs {
   // sorted rows
   const float4* pts;          // records: |row - its voxel centre| per axis; (cell << 3 | octant) bits
   const int32_t* dense;       // [n_blocks * K] (block, class) -> slot
-  const int32_t* prefix;      // [slots][B^3 + 1]
+  const int32_t* head;        // [slots + 1] first row of each slot
   const int32_t* slot_lin;    // [slots] (class, block) linear index
   const int32_t* nunits;      // [slots] chunks of the slot
   const int32_t* ustart;      // [slots] first unit of the slot
@@ -74,8 +74,8 @@ hipError_t launch_mark_targets(const int32_t* slot_lin, const int32_t* d_nslots,
                                int32_t DB, int32_t* mark, hipStream_t st);
 hipError_t launch_list_targets(const int32_t* mark, const int32_t* mpos, int64_t n_ext,
                                int32_t* tgt_elin, int32_t* ext2t, hipStream_t st);
-hipError_t launch_slot_units(const int32_t* prefix, const int32_t* d_nslots, int32_t max_slots,
-                             int32_t B3, int32_t chunk, int32_t* nunits, hipStream_t st);
+hipError_t launch_slot_units(const int32_t* head, const int32_t* d_nslots, int32_t max_slots,
+                             int32_t chunk, int32_t* nunits, hipStream_t st);
 hipError_t launch_unit_table(const int32_t* nunits, const int32_t* ustart, int32_t max_slots,
                              int2* units, hipStream_t st);
 hipError_t launch_splat(const SplatArgs& a, int64_t n_units, hipStream_t st);

@@ -79,16 +79,12 @@ __global__ void k_list_targets(const int32_t* __restrict__ mark, const int32_t* 
 }
 
 // chunks of every (class, block) slot
-__global__ void k_slot_units(const int32_t* __restrict__ prefix, const int32_t* __restrict__ d_nslots,
-                             int32_t max_slots, int32_t B3, int32_t chunk,
-                             int32_t* __restrict__ nunits) {
+__global__ void k_slot_units(const int32_t* __restrict__ head, const int32_t* __restrict__ d_nslots,
+                             int32_t max_slots, int32_t chunk, int32_t* __restrict__ nunits) {
   const int32_t s = blockIdx.x * blockDim.x + threadIdx.x;
   if (s >= max_slots) return;
   int32_t u = 0;
-  if (s < *d_nslots) {
-    const int32_t* P = prefix + (int64_t)s * (B3 + 1);
-    u = (P[B3] - P[0] + chunk - 1) / chunk;
-  }
+  if (s < *d_nslots) u = (head[s + 1] - head[s] + chunk - 1) / chunk;
   nunits[s] = u;
 }
 
@@ -154,14 +150,12 @@ template <int B, int R, int NS>
 __global__ void __launch_bounds__(SMKI_WAVE) k_splat(SplatArgs a) {
   constexpr int DR = B + 2 * R;                 // region edge (voxels)
   constexpr int DR3 = DR * DR * DR;
-  constexpr int B3 = B * B * B;
   __shared__ float acc[DR3];
   const int lane = threadIdx.x;
   const int2 u = a.units[blockIdx.x];
   const int32_t slot = u.x;
-  const int32_t* P = a.prefix + (int64_t)slot * (B3 + 1);
-  const int32_t r0 = P[0] + u.y * a.chunk;
-  const int32_t r1 = min(P[B3], r0 + a.chunk);
+  const int32_t r0 = a.head[slot] + u.y * a.chunk;
+  const int32_t r1 = min(a.head[slot + 1], r0 + a.chunk);
   for (int i = lane; i < DR3; i += SMKI_WAVE) acc[i] = 0.0f;
   // Per lane, for each step: one voxel offset o of the first-octant stencil
   // (offsets whose centre can lie within l of a point in the (+,+,+) octant of
@@ -648,12 +642,12 @@ hipError_t launch_list_targets(const int32_t* mark, const int32_t* mpos, int64_t
   return hipGetLastError();
 }
 
-hipError_t launch_slot_units(const int32_t* prefix, const int32_t* d_nslots, int32_t max_slots,
-                             int32_t B3, int32_t chunk, int32_t* nunits, hipStream_t st) {
+hipError_t launch_slot_units(const int32_t* head, const int32_t* d_nslots, int32_t max_slots,
+                             int32_t chunk, int32_t* nunits, hipStream_t st) {
   if (max_slots <= 0) return hipSuccess;
   if (chunk <= 0) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(k_slot_units, dim3(nblk(max_slots, 256)), dim3(256), 0, st, prefix, d_nslots,
-                     max_slots, B3, chunk, nunits);
+  hipLaunchKernelGGL(k_slot_units, dim3(nblk(max_slots, 256)), dim3(256), 0, st, head, d_nslots,
+                     max_slots, chunk, nunits);
   return hipGetLastError();
 }
 
