@@ -150,13 +150,13 @@ template <int B, int R, int NS>
 __global__ void __launch_bounds__(SMKI_WAVE) k_splat(SplatArgs a) {
   constexpr int DR = B + 2 * R;                 // region edge (voxels)
   constexpr int DR3 = DR * DR * DR;
-  __shared__ float acc[DR3];
+  __shared__ float acc[DR3 + 1];   // + a dummy slot for pad lanes
   const int lane = threadIdx.x;
   const int2 u = a.units[blockIdx.x];
   const int32_t slot = u.x;
   const int32_t r0 = a.head[slot] + u.y * a.chunk;
   const int32_t r1 = min(a.head[slot + 1], r0 + a.chunk);
-  for (int i = lane; i < DR3; i += SMKI_WAVE) acc[i] = 0.0f;
+  for (int i = lane; i <= DR3; i += SMKI_WAVE) acc[i] = 0.0f;
   // Per lane, for each step: one voxel offset o of the first-octant stencil
   // (offsets whose centre can lie within l of a point in the (+,+,+) octant of
   // its cell) as a centre offset in metres, and its region-index offset for
@@ -166,11 +166,13 @@ __global__ void __launch_bounds__(SMKI_WAVE) k_splat(SplatArgs a) {
   // |u|, at most res sqrt(3)/2; w: the offset's centre): nw = -2 w, w2 = |w|^2.
   float nwx[NS], nwy[NS], nwz[NS], w2[NS];
   int32_t wl[8][NS];
+  bool pad[NS];
   const double res = (double)a.g.res;
 #pragma unroll
   for (int s = 0; s < NS; ++s) {
     const int o = s * SMKI_WAVE + lane;
     int4 off = make_int4(0, 0, 0, 0);
+    pad[s] = o >= a.noff;
     if (o < a.noff) {
       off = a.offs[o];
       const double x = off.x * res, y = off.y * res, z = off.z * res;
@@ -194,22 +196,26 @@ __global__ void __launch_bounds__(SMKI_WAVE) k_splat(SplatArgs a) {
   float sum[NS];
 #pragma unroll
   for (int s = 0; s < NS; ++s) sum[s] = 0.0f;
-  // Lanes add their non-zero group sums to distinct LDS addresses (all reads of
-  // a flush first, then all writes).  The LDS executes one wavefront's reads
-  // and writes in issue order and the compiler keeps flushes in program order
-  // (signal fence), so every voxel sums its rows in row order.
+  // Flush: every lane adds its group sum (0 included) to its voxel of the
+  // region, all reads of a flush first, then all writes; pad lanes (no stencil
+  // offset) use a dummy slot past the region.  Within one flush the lanes'
+  // addresses are distinct; the LDS executes one wavefront's reads and writes
+  // in issue order and the compiler keeps flushes in program order (signal
+  // fence), so every voxel sums its rows in row order.
   auto flush = [&]() {
     const int oc = gkey & 7;
+    int32_t base[NS];
+#pragma unroll
+    for (int s = 0; s < NS; ++s) base[s] = pad[s] ? DR3 : gcb;
     __atomic_signal_fence(__ATOMIC_SEQ_CST);
     switch (oc) {
 #define SMKI_FLUSH_CASE(OC)                                                  \
   case OC: {                                                                 \
     float old[NS];                                                           \
     _Pragma("unroll") for (int s = 0; s < NS; ++s)                           \
-        old[s] = sum[s] != 0.0f ? acc[gcb + wl[OC][s]] : 0.0f;               \
+        old[s] = acc[base[s] + wl[OC][s]];                                   \
     _Pragma("unroll") for (int s = 0; s < NS; ++s)                           \
-        if (sum[s] != 0.0f)                                                  \
-          acc[gcb + wl[OC][s]] = fmaf(a.cscale, sum[s], old[s]);             \
+        acc[base[s] + wl[OC][s]] = fmaf(a.cscale, sum[s], old[s]);           \
     break;                                                                   \
   }
       SMKI_FLUSH_CASE(0) SMKI_FLUSH_CASE(1) SMKI_FLUSH_CASE(2) SMKI_FLUSH_CASE(3)
@@ -219,17 +225,17 @@ __global__ void __launch_bounds__(SMKI_WAVE) k_splat(SplatArgs a) {
 #pragma unroll
     for (int s = 0; s < NS; ++s) sum[s] = 0.0f;
   };
-  // Rows are staged 64 at a time in registers (lane i holds row base + i; the
-  // next batch is loaded while this one is processed) and broadcast with
-  // v_readlane: the record loads never wait on the LDS atomics.
-  auto load_batch = [&](int32_t base) {
-    const int32_t r = base + lane;
-    return r < r1 ? pts[r] : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+  // Rows are staged 64 at a time in registers (lane i holds row base + i) and
+  // broadcast with v_readlane; two batches alternate so that one loads while
+  // the other is processed.
+  auto load_batch = [&](int32_t base) {   // unconditional: lanes past the end re-read row r1 - 1
+    return pts[min(base + lane, r1 - 1)];
   };
-  float4 cur = load_batch(r0);
-  for (int32_t base = r0; base < r1; base += SMKI_WAVE) {
-    const float4 nxt = load_batch(base + SMKI_WAVE);
+  auto process = [&](const float4& cur, int32_t base) {
     const int nb = min(SMKI_WAVE, r1 - base);
+    // Consume the batch once here, so that the only wait for its load (and not
+    // for the other batch's, issued later) sits before the row loop.
+    asm volatile("" ::"v"(cur.x), "v"(cur.y), "v"(cur.z), "v"(cur.w));
     for (int j = 0; j < nb; ++j) {
       const float qx = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(cur.x), j));
       const float qy = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(cur.y), j));
@@ -242,8 +248,8 @@ __global__ void __launch_bounds__(SMKI_WAVE) k_splat(SplatArgs a) {
         gcb = ((c / (B * B) + R) * DR + ((c / B) % B + R)) * DR + (c % B + R);
       }
       const float q2 = fmaf(qx, qx, fmaf(qy, qy, qz * qz));
-      // Branch-free: every lane evaluates its pair; out of support (d >= l) the
-      // clamped s is forced to 0, which zeroes the weight s^5 Q(s^2).
+      // Branch-free: every lane evaluates its pair; out of support (d >= l) s is
+      // forced to 0, which zeroes the weight s^5 Q(s^2).
 #pragma unroll
       for (int s = 0; s < NS; ++s) {
         // |d2| only guards rounding below 0 when the row sits on the voxel centre
@@ -259,7 +265,14 @@ __global__ void __launch_bounds__(SMKI_WAVE) k_splat(SplatArgs a) {
         sum[s] = fmaf(uu * uu, sv * qq, sum[s]);
       }
     }
-    cur = nxt;
+  };
+  float4 ba = load_batch(r0);
+  for (int32_t base = r0; base < r1; base += 2 * SMKI_WAVE) {
+    const float4 bb = load_batch(base + SMKI_WAVE);
+    process(ba, base);
+    if (base + SMKI_WAVE >= r1) break;
+    ba = load_batch(base + 2 * SMKI_WAVE);
+    process(bb, base + SMKI_WAVE);
   }
   if (gkey >= 0) flush();
   __syncthreads();
