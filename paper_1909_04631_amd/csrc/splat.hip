@@ -171,18 +171,15 @@ __global__ void __launch_bounds__(SMKI_WAVE) k_splat(SplatArgs a) {
 #pragma unroll
   for (int s = 0; s < NS; ++s) {
     const int o = s * SMKI_WAVE + lane;
-    int4 off = make_int4(0, 0, 0, 0);
     pad[s] = o >= a.noff;
-    if (o < a.noff) {
-      off = a.offs[o];
+    int4 off = a.offs[min(o, a.noff - 1)];   // unconditional load, pad lanes reset below
+    if (pad[s]) off = make_int4(0, 0, 0, 0);
+    {
       const double x = off.x * res, y = off.y * res, z = off.z * res;
       nwx[s] = (float)(-2.0 * x);
       nwy[s] = (float)(-2.0 * y);
       nwz[s] = (float)(-2.0 * z);
-      w2[s] = (float)(x * x + y * y + z * z);
-    } else {
-      nwx[s] = nwy[s] = nwz[s] = 0.0f;
-      w2[s] = 1.0e30f;   // never within l
+      w2[s] = pad[s] ? 1.0e30f : (float)(x * x + y * y + z * z);   // pad: never within l
     }
 #pragma unroll
     for (int oc = 0; oc < 8; ++oc)
@@ -278,6 +275,7 @@ __global__ void __launch_bounds__(SMKI_WAVE) k_splat(SplatArgs a) {
   __syncthreads();
   // pieces that received a contribution
   uint32_t touched = 0;
+#pragma unroll 4
   for (int i = lane; i < DR3; i += SMKI_WAVE) {
     if (acc[i] != 0.0f) {
       const int rx = i / (DR * DR), ry = (i / DR) % DR, rz = i % DR;
@@ -301,6 +299,7 @@ __global__ void __launch_bounds__(SMKI_WAVE) k_splat(SplatArgs a) {
     const int sx = PC::rstart(p / 9 - 1), sy = PC::rstart((p / 3) % 3 - 1),
               sz = PC::rstart(p % 3 - 1);
     const int n = ex * ey * ez, b = PC::base(p);
+#pragma unroll 4
     for (int i = lane; i < n; i += SMKI_WAVE) {
       const int lx = i / (ey * ez), ly = (i / ez) % ey, lz = i % ez;
       out[b + i] = acc[((sx + lx) * DR + (sy + ly)) * DR + (sz + lz)];
