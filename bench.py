@@ -152,6 +152,7 @@ def main():
     }
 
     out["roofline"]["traffic"] = splat_traffic()
+    out["scsm"] = bench_scsm(torch, m, xyz, lab, vox, s, p, SemanticMap, args.steps)
     if not args.no_extras:
         out["fwd_bwd"] = bench_loss(torch, dev, predictive_loss)
     if not args.no_batched:
@@ -211,6 +212,29 @@ def bench_loss(torch, dev, predictive_loss, reps=20):
             "t_fwd_ms": t_fwd, "t_bwd_ms": t_bwd, "t_plain_ms": t_plain,
             "bwd_over_fwd": t_bwd / t_fwd if t_fwd > 0 else None,
             "fwd_bwd_over_plain": t_fb / t_plain if t_plain > 0 else None}
+
+
+def bench_scsm(torch, m_bki, xyz, lab, vox, s, p, SemanticMap, steps):
+    """The counting model (Eq. 2) on the same scan and step (reset, insert, readout)."""
+    m = SemanticMap.from_params(p, initial_blocks=1 << 15, model="scsm")
+
+    def step():
+        m.reset()
+        m.insert_scan(xyz, lab, s.origin, p.free_step)
+        return m.query(vox, alpha=False, var=False, mean=True, label=True, p_occ=True)
+
+    for _ in range(3):
+        step()
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    for _ in range(steps):
+        step()
+    torch.cuda.synchronize()
+    ms = 1e3 * (time.perf_counter() - t) / steps
+    st = m.stats()
+    return {"model": "S-CSM (Eq. 2)", "ms_per_step": ms, "voxels_updated": st["n_updated_voxels"],
+            "voxel_updates_per_s": st["n_updated_voxels"] / (ms * 1e-3),
+            "points_per_s": st["n_hits"] / (ms * 1e-3)}
 
 
 def splat_traffic():

@@ -42,12 +42,21 @@ typedef int32_t smki_status;
 
 typedef struct smki_map smki_map;
 
-/* Optional tuning; pass NULL for defaults. */
+/* Map update model (smki_options.model). */
+#define SMKI_MODEL_SBKI 0  /* Bayesian spatial kernel inference, Sec. IV, Eq. (7)-(8) */
+#define SMKI_MODEL_SCSM 1  /* semantic counting sensor model, Sec. III, Eq. (2): a voxel
+                              adds the number of training rows of each class inside it
+                              (free-space samples included); exact while a voxel holds
+                              fewer than 2^24 rows of a class */
+
+/* Optional settings; pass NULL for defaults (all fields 0). */
 typedef struct smki_options {
   int64_t initial_blocks;   /* initial pool capacity in blocks (0: 4096); grows on demand */
   int32_t unit_budget;      /* rows of one (class, block) that one splat work unit
                                takes (0: 1024; at most 2^24); a (class, block) holding
                                more rows is split into several units */
+  int32_t model;            /* SMKI_MODEL_SBKI (default) or SMKI_MODEL_SCSM; l and sigma0
+                               are not used by the counting model */
 } smki_options;
 
 /* Counters of the last insert (smki_last_scan_stats). */

@@ -83,6 +83,7 @@ struct smki_map {
   float res, l, sigma0, alpha0;
   int32_t K, B, log2B, free_class;
   int32_t chunk;  // rows per splat work unit
+  int32_t model;  // SMKI_MODEL_SBKI or SMKI_MODEL_SCSM
   int device = 0;
   hipStream_t stream = nullptr;
   // persistent device state
@@ -225,6 +226,80 @@ BucketGeom make_geom(const smki_map* m, const int32_t vlo[3], const int32_t vhi[
 }
 
 // ---------------------------------------------------------------------------
+// counting-model insert (S-CSM): rows already bucketed; allocate the row blocks,
+// then add each (class, voxel) run length to alpha
+// ---------------------------------------------------------------------------
+smki_status insert_csm(smki_map* m, const BucketGeom& g, const PointSet& ps, int32_t n_slots,
+                       int32_t n_t, int64_t n_ext, const int32_t eblo[3], const int32_t enb[3],
+                       const int32_t* d_mark, const int32_t* d_mpos, int32_t* d_ext2t,
+                       hipStream_t q) {
+  const int32_t B3 = m->B * m->B * m->B;
+  SplatArgs sa{};
+  sa.g = g;
+  sa.K = m->K;
+  sa.pts = ps.pts;
+  sa.dense = ps.dense;
+  sa.head = ps.head;
+  sa.slot_lin = ps.slot_lin;
+  sa.n_slots = n_slots;
+  for (int q2 = 0; q2 < 3; ++q2) {
+    sa.eblo[q2] = eblo[q2];
+    sa.enb[q2] = enb[q2];
+  }
+  sa.ext2t = d_ext2t;
+  sa.stats = m->d_stats;
+  Sizer zc;
+  for (int i = 0; i < 5; ++i) zc.add<int32_t>(n_t);
+  zc.add<int32_t>(8);
+  zc.add<char>(scan_tmp_bytes(std::max<int64_t>(n_t, 1)));
+  zc.add<uint32_t>((size_t)n_t * (B3 / 32));
+  SMKI_HIP_TRY(m->a_tgts.reserve(zc.total));
+  Arena& C = m->a_tgts;
+  int32_t* d_tgt = C.take<int32_t>(n_t);
+  int32_t* d_active = C.take<int32_t>(n_t);
+  int32_t* d_tslot = C.take<int32_t>(n_t);
+  int32_t* d_isnew = C.take<int32_t>(n_t);
+  int32_t* d_rank = C.take<int32_t>(n_t);
+  int32_t* d_cnt = C.take<int32_t>(8);
+  void* d_ctmp = C.take<char>(scan_tmp_bytes(std::max<int64_t>(n_t, 1)));
+  uint32_t* d_vbits = C.take<uint32_t>((size_t)n_t * (B3 / 32));
+  sa.tgt_elin = d_tgt;
+  sa.tgt_active = d_active;
+  sa.tgt_slot = d_tslot;
+  SMKI_HIP_TRY(hipMemsetAsync(d_cnt, 0, sizeof(int32_t) * 8, q));
+  SMKI_HIP_TRY(hipMemsetAsync(d_vbits, 0, sizeof(uint32_t) * std::max<size_t>((size_t)n_t * (B3 / 32), 1), q));
+  SMKI_HIP_TRY(hipMemsetAsync(m->d_stats, 0, sizeof(unsigned long long) * 4, q));
+  SMKI_HIP_TRY(launch_list_targets(d_mark, d_mpos, n_ext, d_tgt, d_ext2t, q));
+  SMKI_HIP_TRY(launch_fill_i32(d_active, n_t, 1, q));   // every row block is updated
+  SMKI_HIP_TRY(hipEventRecord(m->ev[0], q));
+  SMKI_HIP_TRY(hipEventRecord(m->ev[1], q));
+  SMKI_HIP_TRY(launch_map_lookup(m->dev, sa, n_t, d_tslot, d_isnew, q));
+  SMKI_HIP_TRY(scan_excl_i32(d_isnew, d_rank, n_t, d_cnt, d_ctmp, q));
+  int32_t cnt[1];
+  SMKI_HIP_TRY(sync_read(m, d_cnt, sizeof(cnt), cnt));
+  const int64_t n_new = cnt[0];
+  m->last.n_new_blocks = n_new;
+  smki_status rc = ensure_pool(m, m->n_blocks + n_new);
+  if (rc != SMKI_OK) return rc;
+  rc = ensure_hash(m, m->n_blocks + n_new);
+  if (rc != SMKI_OK) return rc;
+  SMKI_HIP_TRY(hipEventRecord(m->ev[2], q));
+  SMKI_HIP_TRY(launch_assign_new(m->dev, sa, n_t, d_isnew, d_rank, m->n_blocks, d_tslot, m->d_err, q));
+  SMKI_HIP_TRY(launch_fill_alpha0(m->dev, m->n_blocks, n_new, q));
+  sa.alpha = m->dev.alpha;
+  SMKI_HIP_TRY(launch_csm_counts(sa, d_vbits, n_t, q));
+  SMKI_HIP_TRY(hipEventRecord(m->ev[3], q));
+  // in-support pairs of the counting model: every row counts once
+  const unsigned long long rows = (unsigned long long)ps.n;
+  SMKI_HIP_TRY(hipMemcpyAsync(m->d_stats + 1, &rows, sizeof(rows), hipMemcpyHostToDevice, q));
+  SMKI_HIP_TRY(hipMemcpyAsync(m->h_pin + 8, m->d_stats, sizeof(unsigned long long) * 4,
+                              hipMemcpyDeviceToHost, q));
+  m->n_blocks += n_new;
+  m->stats_pending = true;
+  return SMKI_OK;
+}
+
+// ---------------------------------------------------------------------------
 // the insert (one or several scans)
 // ---------------------------------------------------------------------------
 smki_status insert_impl(smki_map* m, const float* xyz, const int32_t* label, int64_t n,
@@ -312,11 +387,13 @@ smki_status insert_impl(smki_map* m, const float* xyz, const int32_t* label, int
   if (g.n_blocks * m->K > (int64_t(1) << 30)) return SMKI_E_CAPACITY;
   if ((int64_t)(g.nb[0] + 2) * (g.nb[1] + 2) * (g.nb[2] + 2) > (int64_t(1) << 30))
     return SMKI_E_CAPACITY;
+  const bool csm = m->model == SMKI_MODEL_SCSM;
   const double lv = (double)m->l / (double)m->res;
   const double margin = std::max(1e-4, 4.0 * ldexp((double)maxabs + 1.0, -23));
-  const Stencil sten = make_stencil(lv, margin);
-  if (sten.R > SMKI_MAX_REACH || sten.R > m->B) return SMKI_E_CAPACITY;
-  const int32_t DB = 1;
+  const Stencil sten = csm ? Stencil{} : make_stencil(lv, margin);
+  if (!csm && (sten.R > SMKI_MAX_REACH || sten.R > m->B)) return SMKI_E_CAPACITY;
+  // target blocks: the row blocks and their neighbours (S-BKI), the row blocks (S-CSM)
+  const int32_t DB = csm ? 0 : 1;
   int32_t eblo[3], enb[3];
   int64_t n_ext = 1;
   for (int q2 = 0; q2 < 3; ++q2) {
@@ -400,6 +477,7 @@ smki_status insert_impl(smki_map* m, const float* xyz, const int32_t* label, int
   m->last.n_lane_slots = nt * (int64_t)SMKI_WAVE * ((int64_t)(sten.offs.size() + SMKI_WAVE - 1) / SMKI_WAVE);
 
   // ---- phase C: splat, allocate, merge ----
+  if (csm) return insert_csm(m, g, ps, n_slots, n_t, n_ext, eblo, enb, d_mark, d_mpos, d_ext2t, q);
   SplatArgs sa{};
   sa.g = g;
   sa.R = sten.R;
@@ -520,7 +598,8 @@ smki_status smki_create_map(float res, int32_t block_size, float l, float sigma0
     return SMKI_E_INVALID_ARG;
   if (K < 2 || K > 255 || free_class < 0 || free_class >= K) return SMKI_E_INVALID_ARG;
   if (block_size != 4 && block_size != 8) return SMKI_E_INVALID_ARG;
-  if (opt && (opt->initial_blocks < 0 || opt->unit_budget < 0 || opt->unit_budget > (1 << 24)))
+  if (opt && (opt->initial_blocks < 0 || opt->unit_budget < 0 || opt->unit_budget > (1 << 24) ||
+              (opt->model != SMKI_MODEL_SBKI && opt->model != SMKI_MODEL_SCSM)))
     return SMKI_E_INVALID_ARG;
   int ndev = 0;
   if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) return SMKI_E_DEVICE;
@@ -535,6 +614,7 @@ smki_status smki_create_map(float res, int32_t block_size, float l, float sigma0
   m->log2B = ilog2(block_size);
   m->free_class = free_class;
   m->chunk = (opt && opt->unit_budget > 0) ? opt->unit_budget : SMKI_CHUNK;
+  m->model = opt ? opt->model : SMKI_MODEL_SBKI;
   (void)hipGetDevice(&m->device);
   m->dev.K = K;
   m->dev.B = block_size;

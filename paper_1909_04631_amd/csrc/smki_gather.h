@@ -86,6 +86,11 @@ hipError_t launch_assign_new(const MapDev& m, const SplatArgs& a, int32_t n_targ
                              const int32_t* is_new, const int32_t* new_rank, int64_t n_old,
                              int32_t* tgt_slot, uint32_t* err, hipStream_t st);
 
+// csm.hip: counting-model inserts
+hipError_t launch_csm_counts(const SplatArgs& a, uint32_t* vbits, int64_t n_targets,
+                             hipStream_t st);
+hipError_t launch_fill_alpha0(const MapDev& m, int64_t slot0, int64_t nslots, hipStream_t st);
+
 // map.hip
 hipError_t launch_query(const MapDev& m, const int32_t* ijk, int64_t M, float* alpha, float* mean,
                         float* var, int32_t* label, float* p_occ, int32_t free_class,
