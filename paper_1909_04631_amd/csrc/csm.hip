@@ -4,28 +4,35 @@
 //
 //   alpha_v^k = alpha0 + #{ rows t in voxel v with y_t = k }.
 //
-// Rows arrive bucketed by (class, block, voxel cell), so the rows of one
-// (class, voxel) are a run of equal cells inside their slot.  One wavefront per
-// slot finds the runs and adds each run's length to its voxel: every
-// (voxel, class) is written by exactly one lane, and the counts are integers,
-// so the result is exact and order-free.
+// Rows arrive sorted by (class, block, voxel cell), so the rows of one
+// (class, voxel) are a run of equal keys.  The last row of each run adds the
+// run's length to its voxel: every (voxel, class) is written by exactly one
+// thread, and the counts are integers, so the result is exact and order-free.
 #include "smki_gather.h"
 
 namespace {
 
 inline unsigned nblk(int64_t n, int t) { return (unsigned)ceil_div_i64(n > 0 ? n : 1, t); }
 
-__device__ __forceinline__ int32_t cell_of_row(const float4* __restrict__ pts, int32_t r) {
-  return __float_as_int(pts[r].w) >> 3;
-}
-
-template <int B>
-__global__ void __launch_bounds__(SMKI_WAVE) k_csm_counts(SplatArgs a, uint32_t* __restrict__ vbits) {
+// One thread per row; the last row of each run of equal keys (one class in one
+// voxel: keys are sorted by (class, block, voxel)) finds the run's first row by
+// binary search and adds the run length to that voxel's class.
+template <typename KeyT, int B>
+__global__ void k_csm_counts(SplatArgs a, const KeyT* __restrict__ keys, int64_t n,
+                             uint32_t* __restrict__ vbits) {
   constexpr int B3 = B * B * B;
-  const int32_t s = blockIdx.x;
-  if (s >= a.n_slots) return;
-  const int32_t r0 = a.head[s], r1 = a.head[s + 1];
-  const int32_t plane_lin = a.slot_lin[s];
+  constexpr int L3 = B == 8 ? 9 : 6;   // bits of the voxel cell in the key
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const KeyT k = keys[i];
+  if (i + 1 < n && keys[i + 1] == k) return;   // not the last row of its run
+  int64_t lo = 0, hi = i;                      // first row with this key
+  while (lo < hi) {
+    const int64_t mid = (lo + hi) >> 1;
+    if (keys[mid] < k) lo = mid + 1; else hi = mid;
+  }
+  const int32_t c = (int32_t)((uint64_t)k & (uint64_t)(B3 - 1));
+  const int64_t plane_lin = (int64_t)((uint64_t)k >> L3);
   const int32_t y = (int32_t)(plane_lin / a.g.n_blocks);
   const int64_t blin = plane_lin % a.g.n_blocks;
   const int32_t pz = (int32_t)(blin % a.g.nb[2]);
@@ -35,19 +42,8 @@ __global__ void __launch_bounds__(SMKI_WAVE) k_csm_counts(SplatArgs a, uint32_t*
                      (py + a.g.blo[1] - a.eblo[1])) * a.enb[2] + (pz + a.g.blo[2] - a.eblo[2]);
   const int32_t t = a.ext2t[e];
   const int32_t mslot = a.tgt_slot[t];
-  float* A = a.alpha + ((int64_t)mslot * a.K + y) * B3;
-  const float4* __restrict__ pts = a.pts;
-  for (int32_t r = r0 + (int32_t)threadIdx.x; r < r1; r += SMKI_WAVE) {
-    const int32_t c = cell_of_row(pts, r);
-    if (r > r0 && cell_of_row(pts, r - 1) == c) continue;   // not the first row of its run
-    int32_t lo = r, hi = r1 - 1;                             // last row of the run
-    while (lo < hi) {
-      const int32_t mid = (lo + hi + 1) >> 1;
-      if (cell_of_row(pts, mid) == c) lo = mid; else hi = mid - 1;
-    }
-    A[c] += (float)(lo - r + 1);
-    atomicOr(&vbits[(int64_t)t * (B3 / 32) + (c >> 5)], 1u << (c & 31));
-  }
+  a.alpha[((int64_t)mslot * a.K + y) * B3 + c] += (float)(i - lo + 1);
+  atomicOr(&vbits[(int64_t)t * (B3 / 32) + (c >> 5)], 1u << (c & 31));
 }
 
 // voxels with at least one row: popcount of the per-target voxel bits
@@ -68,21 +64,20 @@ __global__ void k_fill_f32(float* __restrict__ p, int64_t n, float v) {
 
 }  // namespace
 
-hipError_t launch_csm_counts(const SplatArgs& a, uint32_t* vbits, int64_t n_targets,
-                             hipStream_t st) {
-  if (a.n_slots <= 0) return hipSuccess;
-  switch (a.g.B) {
-    case 4:
-      hipLaunchKernelGGL(k_csm_counts<4>, dim3((unsigned)a.n_slots), dim3(SMKI_WAVE), 0, st, a,
-                         vbits);
-      break;
-    case 8:
-      hipLaunchKernelGGL(k_csm_counts<8>, dim3((unsigned)a.n_slots), dim3(SMKI_WAVE), 0, st, a,
-                         vbits);
-      break;
-    default:
-      return hipErrorInvalidValue;
-  }
+hipError_t launch_csm_counts(const SplatArgs& a, const void* keys, bool wide_keys, int64_t n,
+                             uint32_t* vbits, int64_t n_targets, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  const dim3 grid(nblk(n, 256)), block(256);
+  if (a.g.B == 8 && !wide_keys)
+    hipLaunchKernelGGL((k_csm_counts<uint32_t, 8>), grid, block, 0, st, a, (const uint32_t*)keys, n, vbits);
+  else if (a.g.B == 8)
+    hipLaunchKernelGGL((k_csm_counts<uint64_t, 8>), grid, block, 0, st, a, (const uint64_t*)keys, n, vbits);
+  else if (a.g.B == 4 && !wide_keys)
+    hipLaunchKernelGGL((k_csm_counts<uint32_t, 4>), grid, block, 0, st, a, (const uint32_t*)keys, n, vbits);
+  else if (a.g.B == 4)
+    hipLaunchKernelGGL((k_csm_counts<uint64_t, 4>), grid, block, 0, st, a, (const uint64_t*)keys, n, vbits);
+  else
+    return hipErrorInvalidValue;
   const int64_t nwords = n_targets * (int64_t)(a.g.B * a.g.B * a.g.B / 32);
   hipLaunchKernelGGL(k_csm_voxels, dim3(nblk(nwords, 256)), dim3(256), 0, st, vbits, nwords,
                      &a.stats[0]);

@@ -229,7 +229,8 @@ BucketGeom make_geom(const smki_map* m, const int32_t vlo[3], const int32_t vhi[
 // counting-model insert (S-CSM): rows already bucketed; allocate the row blocks,
 // then add each (class, voxel) run length to alpha
 // ---------------------------------------------------------------------------
-smki_status insert_csm(smki_map* m, const BucketGeom& g, const PointSet& ps, int32_t n_slots,
+smki_status insert_csm(smki_map* m, const BucketGeom& g, const PointSet& ps, const void* keys,
+                       int32_t n_slots,
                        int32_t n_t, int64_t n_ext, const int32_t eblo[3], const int32_t enb[3],
                        const int32_t* d_mark, const int32_t* d_mpos, int32_t* d_ext2t,
                        hipStream_t q) {
@@ -287,7 +288,7 @@ smki_status insert_csm(smki_map* m, const BucketGeom& g, const PointSet& ps, int
   SMKI_HIP_TRY(launch_assign_new(m->dev, sa, n_t, d_isnew, d_rank, m->n_blocks, d_tslot, m->d_err, q));
   SMKI_HIP_TRY(launch_fill_alpha0(m->dev, m->n_blocks, n_new, q));
   sa.alpha = m->dev.alpha;
-  SMKI_HIP_TRY(launch_csm_counts(sa, d_vbits, n_t, q));
+  SMKI_HIP_TRY(launch_csm_counts(sa, keys, g.key_bits > 32, ps.n, d_vbits, n_t, q));
   SMKI_HIP_TRY(hipEventRecord(m->ev[3], q));
   // in-support pairs of the counting model: every row counts once
   const unsigned long long rows = (unsigned long long)ps.n;
@@ -477,7 +478,8 @@ smki_status insert_impl(smki_map* m, const float* xyz, const int32_t* label, int
   m->last.n_lane_slots = nt * (int64_t)SMKI_WAVE * ((int64_t)(sten.offs.size() + SMKI_WAVE - 1) / SMKI_WAVE);
 
   // ---- phase C: splat, allocate, merge ----
-  if (csm) return insert_csm(m, g, ps, n_slots, n_t, n_ext, eblo, enb, d_mark, d_mpos, d_ext2t, q);
+  if (csm)
+    return insert_csm(m, g, ps, scr.keys, n_slots, n_t, n_ext, eblo, enb, d_mark, d_mpos, d_ext2t, q);
   SplatArgs sa{};
   sa.g = g;
   sa.R = sten.R;

@@ -87,8 +87,8 @@ hipError_t launch_assign_new(const MapDev& m, const SplatArgs& a, int32_t n_targ
                              int32_t* tgt_slot, uint32_t* err, hipStream_t st);
 
 // csm.hip: counting-model inserts
-hipError_t launch_csm_counts(const SplatArgs& a, uint32_t* vbits, int64_t n_targets,
-                             hipStream_t st);
+hipError_t launch_csm_counts(const SplatArgs& a, const void* keys, bool wide_keys, int64_t n,
+                             uint32_t* vbits, int64_t n_targets, hipStream_t st);
 hipError_t launch_fill_alpha0(const MapDev& m, int64_t slot0, int64_t nslots, hipStream_t st);
 
 // map.hip
