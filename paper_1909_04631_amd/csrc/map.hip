@@ -49,18 +49,19 @@ __global__ void k_query(MapDev m, const int32_t* __restrict__ ijk, int64_t M,
     if (a > bestv) { bestv = a; best = k; }
     if (alpha) alpha[i * m.K + k] = a;
   }
+  const double inv_s = 1.0 / S, inv_s1 = 1.0 / (S + 1.0);
   if (mean || var) {
     for (int k = 0; k < m.K; ++k) {
       const double a = (double)(A ? A[(int64_t)k * B3] : m.alpha0);
-      const double e = a / S;
+      const double e = a * inv_s;
       if (mean) mean[i * m.K + k] = (float)e;
-      if (var) var[i * m.K + k] = (float)(e * ((S - a) / S) / (S + 1.0));
+      if (var) var[i * m.K + k] = (float)(e * ((S - a) * inv_s) * inv_s1);
     }
   }
   if (label) label[i] = best;
   if (p_occ) {
     const double af = (double)(A ? A[(int64_t)free_class * B3] : m.alpha0);
-    p_occ[i] = (float)((S - af) / S);
+    p_occ[i] = (float)((S - af) * inv_s);
   }
 }
 
