@@ -66,6 +66,9 @@ typedef struct smki_scan_stats {
   int64_t n_point_blocks;   /* map blocks holding at least one training row */
   int64_t n_target_blocks;  /* blocks examined (within reach of a row block) */
   int64_t n_new_blocks;     /* blocks allocated by this insert */
+  int64_t n_new_class_blocks; /* class blocks (B^3 concentrations of one class in one
+                               block) allocated by this insert; a class no row ever
+                               reached in a block takes no memory and reads alpha0 */
   int64_t n_units;          /* splat work units launched */
   int64_t n_updated_voxels; /* voxels with at least one row within l */
   int64_t n_pairs;          /* (voxel, row) pairs with distance < l */

@@ -47,6 +47,7 @@ MODELS = {"sbki": 0, "scsm": 1}
 class ScanStats(C.Structure):
     _fields_ = [("n_hits", C.c_int64), ("n_free", C.c_int64), ("n_point_blocks", C.c_int64),
                 ("n_target_blocks", C.c_int64), ("n_new_blocks", C.c_int64),
+                ("n_new_class_blocks", C.c_int64),
                 ("n_units", C.c_int64), ("n_updated_voxels", C.c_int64), ("n_pairs", C.c_int64),
                 ("n_candidates", C.c_int64), ("n_lane_slots", C.c_int64), ("splat_ms", C.c_double),
                 ("merge_ms", C.c_double)]

@@ -42,7 +42,8 @@ __global__ void k_csm_counts(SplatArgs a, const KeyT* __restrict__ keys, int64_t
                      (py + a.g.blo[1] - a.eblo[1])) * a.enb[2] + (pz + a.g.blo[2] - a.eblo[2]);
   const int32_t t = a.ext2t[e];
   const int32_t mslot = a.tgt_slot[t];
-  a.alpha[((int64_t)mslot * a.K + y) * B3 + c] += (float)(i - lo + 1);
+  const int32_t cb = a.map.cslot[(int64_t)mslot * a.K + y];   // allocated: the class has rows here
+  a.map.calpha[(int64_t)cb * B3 + c] += (float)(i - lo + 1);
   atomicOr(&vbits[(int64_t)t * (B3 / 32) + (c >> 5)], 1u << (c & 31));
 }
 
@@ -84,11 +85,11 @@ hipError_t launch_csm_counts(const SplatArgs& a, const void* keys, bool wide_key
   return hipGetLastError();
 }
 
-hipError_t launch_fill_alpha0(const MapDev& m, int64_t slot0, int64_t nslots, hipStream_t st) {
-  const int64_t per = (int64_t)m.K * m.B * m.B * m.B;
-  const int64_t n = nslots * per;
+hipError_t launch_fill_calpha0(const MapDev& m, int64_t c0, int64_t nc, hipStream_t st) {
+  const int64_t per = (int64_t)m.B * m.B * m.B;
+  const int64_t n = nc * per;
   if (n <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_fill_f32, dim3(nblk(n, 256)), dim3(256), 0, st, m.alpha + slot0 * per, n,
+  hipLaunchKernelGGL(k_fill_f32, dim3(nblk(n, 256)), dim3(256), 0, st, m.calpha + c0 * per, n,
                      m.alpha0);
   return hipGetLastError();
 }

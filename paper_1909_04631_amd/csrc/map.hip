@@ -36,15 +36,18 @@ __global__ void k_query(MapDev m, const int32_t* __restrict__ ijk, int64_t M,
   if (vx >= -(1 << 20) && vx < (1 << 20) && vy >= -(1 << 20) && vy < (1 << 20) &&
       vz >= -(1 << 20) && vz < (1 << 20))
     slot = hash_find(m, smki_block_key(bx, by, bz));
-  const float* A = slot >= 0 ? m.alpha + (int64_t)slot * m.K * B3 +
-                                   ((vx - bx * B) * B + (vy - by * B)) * B + (vz - bz * B)
-                             : nullptr;
+  const int32_t* CS = slot >= 0 ? m.cslot + (int64_t)slot * m.K : nullptr;
+  const int32_t v = ((vx - bx * B) * B + (vy - by * B)) * B + (vz - bz * B);
+  auto alpha_of = [&](int k) -> float {   // classes without a class block hold alpha0
+    const int32_t cb = CS ? CS[k] : -1;
+    return cb >= 0 ? m.calpha[(int64_t)cb * B3 + v] : m.alpha0;
+  };
   // moments in double: 1 - mean cancels when one class dominates
   double S = 0.0;
   int32_t best = 0;
   float bestv = -1.0f;
   for (int k = 0; k < m.K; ++k) {
-    const float a = A ? A[(int64_t)k * B3] : m.alpha0;
+    const float a = alpha_of(k);
     S += (double)a;
     if (a > bestv) { bestv = a; best = k; }
     if (alpha) alpha[i * m.K + k] = a;
@@ -52,7 +55,7 @@ __global__ void k_query(MapDev m, const int32_t* __restrict__ ijk, int64_t M,
   const double inv_s = 1.0 / S, inv_s1 = 1.0 / (S + 1.0);
   if (mean || var) {
     for (int k = 0; k < m.K; ++k) {
-      const double a = (double)(A ? A[(int64_t)k * B3] : m.alpha0);
+      const double a = (double)alpha_of(k);
       const double e = a * inv_s;
       if (mean) mean[i * m.K + k] = (float)e;
       if (var) var[i * m.K + k] = (float)(e * ((S - a) * inv_s) * inv_s1);
@@ -60,7 +63,7 @@ __global__ void k_query(MapDev m, const int32_t* __restrict__ ijk, int64_t M,
   }
   if (label) label[i] = best;
   if (p_occ) {
-    const double af = (double)(A ? A[(int64_t)free_class * B3] : m.alpha0);
+    const double af = (double)alpha_of(free_class);
     p_occ[i] = (float)((S - af) * inv_s);
   }
 }
@@ -83,14 +86,42 @@ __global__ void k_hash_insert_slots(MapDev m, int64_t slot0, int64_t n, uint32_t
   atomicOr(err, DEVERR_HASH);
 }
 
-// out block b <- pool slot order[b]
+// out block b <- pool slot order[b], dense [K][B^3] (alpha0 where a class has no class block)
 __global__ void k_gather_blocks(MapDev m, const uint32_t* __restrict__ order, int64_t n,
                                 float* __restrict__ out) {
-  const int64_t per = (int64_t)m.K * m.B * m.B * m.B;
+  const int64_t B3 = (int64_t)m.B * m.B * m.B;
+  const int64_t per = (int64_t)m.K * B3;
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n * per) return;
-  const int64_t b = i / per, r = i % per;
-  out[i] = m.alpha[(int64_t)order[b] * per + r];
+  const int64_t b = i / per, r = i % per, k = r / B3, v = r % B3;
+  const int32_t cb = m.cslot[(int64_t)order[b] * m.K + k];
+  out[i] = cb >= 0 ? m.calpha[cb * B3 + v] : m.alpha0;
+}
+
+// import: flag[b][k] = 1 if any voxel of class k in input block b differs from alpha0
+__global__ void k_import_flags(MapDev m, const float* __restrict__ alpha, int64_t n,
+                               int32_t* __restrict__ flag) {
+  const int64_t B3 = (int64_t)m.B * m.B * m.B;
+  const int64_t bk = blockIdx.x;   // (block, class)
+  if (bk >= n * m.K) return;
+  int any = 0;
+  for (int64_t v = threadIdx.x; v < B3; v += blockDim.x) any |= alpha[bk * B3 + v] != m.alpha0;
+  any = __syncthreads_or(any);
+  if (threadIdx.x == 0) flag[bk] = any ? 1 : 0;
+}
+
+// import: (block b, class k) flagged -> class block c0 + pos[b][k]; others alpha0 (no block)
+__global__ void k_import_copy(MapDev m, const float* __restrict__ alpha, int64_t n,
+                              const int32_t* __restrict__ flag, const int32_t* __restrict__ pos,
+                              int64_t c0) {
+  const int64_t B3 = (int64_t)m.B * m.B * m.B;
+  const int64_t bk = blockIdx.x;
+  if (bk >= n * m.K) return;
+  const int32_t cb = flag[bk] ? (int32_t)(c0 + pos[bk]) : -1;
+  if (threadIdx.x == 0) m.cslot[bk] = cb;
+  if (cb < 0) return;
+  for (int64_t v = threadIdx.x; v < B3; v += blockDim.x)
+    m.calpha[(int64_t)cb * B3 + v] = alpha[bk * B3 + v];
 }
 
 __global__ void k_keys_to_ijk(const uint64_t* __restrict__ keys, int64_t n, int32_t* ijk) {
@@ -145,11 +176,27 @@ hipError_t launch_hash_insert_slots(const MapDev& m, int64_t slot0, int64_t n, u
 }
 
 hipError_t launch_gather_blocks(const MapDev& m, const uint32_t* order, int64_t n,
-                                int32_t* /*unused*/, float* alpha_out, hipStream_t st) {
+                                float* alpha_out, hipStream_t st) {
   const int64_t tot = n * (int64_t)m.K * m.B * m.B * m.B;
   if (tot <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_gather_blocks, dim3(nblk(tot, 256)), dim3(256), 0, st, m, order, n,
                      alpha_out);
+  return hipGetLastError();
+}
+
+hipError_t launch_import_flags(const MapDev& m, const float* alpha, int64_t n, int32_t* flag,
+                               hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_import_flags, dim3((unsigned)(n * m.K)), dim3(256), 0, st, m, alpha, n,
+                     flag);
+  return hipGetLastError();
+}
+
+hipError_t launch_import_copy(const MapDev& m, const float* alpha, int64_t n, const int32_t* flag,
+                              const int32_t* pos, int64_t c0, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_import_copy, dim3((unsigned)(n * m.K)), dim3(256), 0, st, m, alpha, n,
+                     flag, pos, c0);
   return hipGetLastError();
 }
 

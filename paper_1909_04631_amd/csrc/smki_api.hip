@@ -88,8 +88,10 @@ struct smki_map {
   hipStream_t stream = nullptr;
   // persistent device state
   MapDev dev{};
-  int64_t pool_cap = 0;
+  int64_t pool_cap = 0;      // blocks
   int64_t n_blocks = 0;
+  int64_t cpool_cap = 0;     // class blocks
+  int64_t n_cblocks = 0;
   uint32_t* d_err = nullptr;
   unsigned long long* d_stats = nullptr;
   StencilOff* d_offs = nullptr;
@@ -145,30 +147,47 @@ hipError_t sync_read(smki_map* m, const void* dev, size_t bytes, void* host) {
   return hipStreamSynchronize(m->stream);
 }
 
+// Grow the block arrays (keys, class-block table) to hold `need` blocks.
 smki_status ensure_pool(smki_map* m, int64_t need) {
   if (need <= m->pool_cap) return SMKI_OK;
-  int64_t cap = std::max<int64_t>(need, m->pool_cap * 2);
-  const size_t per = (size_t)m->K * m->B * m->B * m->B;
-  float* na = nullptr;
+  const int64_t cap = std::max<int64_t>(need, m->pool_cap * 2);
+  int32_t* ncs = nullptr;
   uint64_t* nk = nullptr;
-  SMKI_HIP_TRY(hipMalloc((void**)&na, sizeof(float) * per * cap));
+  SMKI_HIP_TRY(hipMalloc((void**)&ncs, sizeof(int32_t) * m->K * cap));
   hipError_t e = hipMalloc((void**)&nk, sizeof(uint64_t) * cap);
   if (e != hipSuccess) {
-    (void)hipFree(na);
+    (void)hipFree(ncs);
     return smki_hip_error(e);
   }
   if (m->n_blocks > 0) {
-    SMKI_HIP_TRY(hipMemcpyAsync(na, m->dev.alpha, sizeof(float) * per * m->n_blocks,
+    SMKI_HIP_TRY(hipMemcpyAsync(ncs, m->dev.cslot, sizeof(int32_t) * m->K * m->n_blocks,
                                 hipMemcpyDeviceToDevice, m->stream));
     SMKI_HIP_TRY(hipMemcpyAsync(nk, m->dev.bkeys, sizeof(uint64_t) * m->n_blocks,
                                 hipMemcpyDeviceToDevice, m->stream));
   }
   SMKI_HIP_TRY(hipStreamSynchronize(m->stream));
-  if (m->dev.alpha) (void)hipFree(m->dev.alpha);
+  if (m->dev.cslot) (void)hipFree(m->dev.cslot);
   if (m->dev.bkeys) (void)hipFree(m->dev.bkeys);
-  m->dev.alpha = na;
+  m->dev.cslot = ncs;
   m->dev.bkeys = nk;
   m->pool_cap = cap;
+  return SMKI_OK;
+}
+
+// Grow the class-block pool (B^3 floats each) to hold `need` class blocks.
+smki_status ensure_cpool(smki_map* m, int64_t need) {
+  if (need <= m->cpool_cap) return SMKI_OK;
+  const int64_t cap = std::max<int64_t>(need, m->cpool_cap * 2);
+  const size_t per = (size_t)m->B * m->B * m->B;
+  float* na = nullptr;
+  SMKI_HIP_TRY(hipMalloc((void**)&na, sizeof(float) * per * cap));
+  if (m->n_cblocks > 0)
+    SMKI_HIP_TRY(hipMemcpyAsync(na, m->dev.calpha, sizeof(float) * per * m->n_cblocks,
+                                hipMemcpyDeviceToDevice, m->stream));
+  SMKI_HIP_TRY(hipStreamSynchronize(m->stream));
+  if (m->dev.calpha) (void)hipFree(m->dev.calpha);
+  m->dev.calpha = na;
+  m->cpool_cap = cap;
   return SMKI_OK;
 }
 
@@ -230,11 +249,11 @@ BucketGeom make_geom(const smki_map* m, const int32_t vlo[3], const int32_t vhi[
 // then add each (class, voxel) run length to alpha
 // ---------------------------------------------------------------------------
 smki_status insert_csm(smki_map* m, const BucketGeom& g, const PointSet& ps, const void* keys,
-                       int32_t n_slots,
-                       int32_t n_t, int64_t n_ext, const int32_t eblo[3], const int32_t enb[3],
-                       const int32_t* d_mark, const int32_t* d_mpos, int32_t* d_ext2t,
-                       hipStream_t q) {
+                       int32_t n_slots, int32_t n_t, int64_t n_ext, const int32_t eblo[3],
+                       const int32_t enb[3], const int32_t* d_mark, const int32_t* d_mpos,
+                       int32_t* d_ext2t, hipStream_t q) {
   const int32_t B3 = m->B * m->B * m->B;
+  const int64_t ntk = (int64_t)n_t * m->K;
   SplatArgs sa{};
   sa.g = g;
   sa.K = m->K;
@@ -252,8 +271,9 @@ smki_status insert_csm(smki_map* m, const BucketGeom& g, const PointSet& ps, con
   Sizer zc;
   for (int i = 0; i < 5; ++i) zc.add<int32_t>(n_t);
   zc.add<int32_t>(8);
-  zc.add<char>(scan_tmp_bytes(std::max<int64_t>(n_t, 1)));
+  zc.add<char>(scan_tmp_bytes(std::max<int64_t>(ntk, 1)));
   zc.add<uint32_t>((size_t)n_t * (B3 / 32));
+  for (int i = 0; i < 3; ++i) zc.add<int32_t>(ntk);
   SMKI_HIP_TRY(m->a_tgts.reserve(zc.total));
   Arena& C = m->a_tgts;
   int32_t* d_tgt = C.take<int32_t>(n_t);
@@ -262,40 +282,55 @@ smki_status insert_csm(smki_map* m, const BucketGeom& g, const PointSet& ps, con
   int32_t* d_isnew = C.take<int32_t>(n_t);
   int32_t* d_rank = C.take<int32_t>(n_t);
   int32_t* d_cnt = C.take<int32_t>(8);
-  void* d_ctmp = C.take<char>(scan_tmp_bytes(std::max<int64_t>(n_t, 1)));
+  void* d_ctmp = C.take<char>(scan_tmp_bytes(std::max<int64_t>(ntk, 1)));
   uint32_t* d_vbits = C.take<uint32_t>((size_t)n_t * (B3 / 32));
+  int32_t* d_contrib = C.take<int32_t>(ntk);
+  int32_t* d_need = C.take<int32_t>(ntk);
+  int32_t* d_cpos = C.take<int32_t>(ntk);
   sa.tgt_elin = d_tgt;
   sa.tgt_active = d_active;
   sa.tgt_slot = d_tslot;
+  sa.contrib = d_contrib;
   SMKI_HIP_TRY(hipMemsetAsync(d_cnt, 0, sizeof(int32_t) * 8, q));
   SMKI_HIP_TRY(hipMemsetAsync(d_vbits, 0, sizeof(uint32_t) * std::max<size_t>((size_t)n_t * (B3 / 32), 1), q));
+  SMKI_HIP_TRY(hipMemsetAsync(d_contrib, 0, sizeof(int32_t) * std::max<int64_t>(ntk, 1), q));
   SMKI_HIP_TRY(hipMemsetAsync(m->d_stats, 0, sizeof(unsigned long long) * 4, q));
   SMKI_HIP_TRY(launch_list_targets(d_mark, d_mpos, n_ext, d_tgt, d_ext2t, q));
   SMKI_HIP_TRY(launch_fill_i32(d_active, n_t, 1, q));   // every row block is updated
+  SMKI_HIP_TRY(launch_contrib(sa, true, d_contrib, q));
   SMKI_HIP_TRY(hipEventRecord(m->ev[0], q));
   SMKI_HIP_TRY(hipEventRecord(m->ev[1], q));
   SMKI_HIP_TRY(launch_map_lookup(m->dev, sa, n_t, d_tslot, d_isnew, q));
   SMKI_HIP_TRY(scan_excl_i32(d_isnew, d_rank, n_t, d_cnt, d_ctmp, q));
-  int32_t cnt[1];
+  SMKI_HIP_TRY(launch_need(m->dev, n_t, d_contrib, d_isnew, d_tslot, d_need, q));
+  SMKI_HIP_TRY(scan_excl_i32(d_need, d_cpos, ntk, d_cnt + 1, d_ctmp, q));
+  int32_t cnt[2];
   SMKI_HIP_TRY(sync_read(m, d_cnt, sizeof(cnt), cnt));
-  const int64_t n_new = cnt[0];
+  const int64_t n_new = cnt[0], n_cnew = cnt[1];
   m->last.n_new_blocks = n_new;
   smki_status rc = ensure_pool(m, m->n_blocks + n_new);
   if (rc != SMKI_OK) return rc;
   rc = ensure_hash(m, m->n_blocks + n_new);
   if (rc != SMKI_OK) return rc;
+  rc = ensure_cpool(m, m->n_cblocks + n_cnew);
+  if (rc != SMKI_OK) return rc;
   SMKI_HIP_TRY(hipEventRecord(m->ev[2], q));
   SMKI_HIP_TRY(launch_assign_new(m->dev, sa, n_t, d_isnew, d_rank, m->n_blocks, d_tslot, m->d_err, q));
-  SMKI_HIP_TRY(launch_fill_alpha0(m->dev, m->n_blocks, n_new, q));
-  sa.alpha = m->dev.alpha;
+  SMKI_HIP_TRY(launch_assign_cblocks(m->dev, n_t, d_need, d_cpos, d_tslot, m->n_cblocks, q));
+  SMKI_HIP_TRY(launch_fill_calpha0(m->dev, m->n_cblocks, n_cnew, q));
+  sa.map = m->dev;
   SMKI_HIP_TRY(launch_csm_counts(sa, keys, g.key_bits > 32, ps.n, d_vbits, n_t, q));
   SMKI_HIP_TRY(hipEventRecord(m->ev[3], q));
-  // in-support pairs of the counting model: every row counts once
-  const unsigned long long rows = (unsigned long long)ps.n;
-  SMKI_HIP_TRY(hipMemcpyAsync(m->d_stats + 1, &rows, sizeof(rows), hipMemcpyHostToDevice, q));
+  // in-support pairs of the counting model: every row counts once (staged in
+  // pinned memory, which no later insert touches before this one has synchronised)
+  unsigned long long* h_rows = (unsigned long long*)(m->h_pin + 20);
+  *h_rows = (unsigned long long)ps.n;
+  SMKI_HIP_TRY(hipMemcpyAsync(m->d_stats + 1, h_rows, sizeof(*h_rows), hipMemcpyHostToDevice, q));
   SMKI_HIP_TRY(hipMemcpyAsync(m->h_pin + 8, m->d_stats, sizeof(unsigned long long) * 4,
                               hipMemcpyDeviceToHost, q));
   m->n_blocks += n_new;
+  m->n_cblocks += n_cnew;
+  m->last.n_new_class_blocks = n_cnew;
   m->stats_pending = true;
   return SMKI_OK;
 }
@@ -512,11 +547,13 @@ smki_status insert_impl(smki_map* m, const float* xyz, const int32_t* label, int
   zc.add<int32_t>(n_t);   // is_new
   zc.add<int32_t>(n_t);   // new_rank
   zc.add<int32_t>(8);
-  zc.add<char>(scan_tmp_bytes(std::max<int64_t>(n_t, 1)));
+  const int64_t ntk = (int64_t)n_t * m->K;
+  zc.add<char>(scan_tmp_bytes(std::max<int64_t>(ntk, 1)));
   zc.add<int2>(n_units);
   zc.add<float>((size_t)n_units * DR3);
   zc.add<uint32_t>(n_units);
   zc.add<int4>(n_slots);
+  for (int i = 0; i < 3; ++i) zc.add<int32_t>(ntk);
   SMKI_HIP_TRY(m->a_tgts.reserve(zc.total));
   Arena& C = m->a_tgts;
   int32_t* d_tgt = C.take<int32_t>(n_t);
@@ -525,11 +562,14 @@ smki_status insert_impl(smki_map* m, const float* xyz, const int32_t* label, int
   int32_t* d_isnew = C.take<int32_t>(n_t);
   int32_t* d_rank = C.take<int32_t>(n_t);
   int32_t* d_cnt = C.take<int32_t>(8);
-  void* d_ctmp = C.take<char>(scan_tmp_bytes(std::max<int64_t>(n_t, 1)));
+  void* d_ctmp = C.take<char>(scan_tmp_bytes(std::max<int64_t>(ntk, 1)));
   int2* d_units = C.take<int2>(n_units);
   float* d_part = C.take<float>((size_t)n_units * DR3);
   uint32_t* d_umask = C.take<uint32_t>(n_units);
   int4* d_sinfo = C.take<int4>(n_slots);
+  int32_t* d_contrib = C.take<int32_t>(ntk);
+  int32_t* d_need = C.take<int32_t>(ntk);
+  int32_t* d_cpos = C.take<int32_t>(ntk);
   sa.tgt_elin = d_tgt;
   sa.tgt_active = d_active;
   sa.tgt_slot = d_tslot;
@@ -538,35 +578,46 @@ smki_status insert_impl(smki_map* m, const float* xyz, const int32_t* label, int
   sa.umask = d_umask;
   sa.sinfo = d_sinfo;
   sa.n_slots = n_slots;
+  sa.contrib = d_contrib;
   SMKI_HIP_TRY(hipMemsetAsync(d_cnt, 0, sizeof(int32_t) * 8, q));
   SMKI_HIP_TRY(hipMemsetAsync(d_active, 0, sizeof(int32_t) * std::max<int64_t>(n_t, 1), q));
+  SMKI_HIP_TRY(hipMemsetAsync(d_contrib, 0, sizeof(int32_t) * std::max<int64_t>(ntk, 1), q));
   SMKI_HIP_TRY(hipMemsetAsync(m->d_stats, 0, sizeof(unsigned long long) * 4, q));
   SMKI_HIP_TRY(launch_list_targets(d_mark, d_mpos, n_ext, d_tgt, d_ext2t, q));
   SMKI_HIP_TRY(launch_unit_table(d_nun, d_ust, (int32_t)max_slots, d_units, q));
   SMKI_HIP_TRY(hipEventRecord(m->ev[0], q));
   SMKI_HIP_TRY(launch_splat(sa, n_units, q));
   SMKI_HIP_TRY(hipEventRecord(m->ev[1], q));
+  SMKI_HIP_TRY(launch_slot_info(sa, q));
+  SMKI_HIP_TRY(launch_contrib(sa, false, d_contrib, q));
   SMKI_HIP_TRY(launch_map_lookup(m->dev, sa, n_t, d_tslot, d_isnew, q));
   SMKI_HIP_TRY(scan_excl_i32(d_isnew, d_rank, n_t, d_cnt, d_ctmp, q));
-  // sync 3: new blocks
-  int32_t cnt[1];
+  SMKI_HIP_TRY(launch_need(m->dev, n_t, d_contrib, d_isnew, d_tslot, d_need, q));
+  SMKI_HIP_TRY(scan_excl_i32(d_need, d_cpos, ntk, d_cnt + 1, d_ctmp, q));
+  // sync 3: new blocks and class blocks
+  int32_t cnt[2];
   SMKI_HIP_TRY(sync_read(m, d_cnt, sizeof(cnt), cnt));
-  const int64_t n_new = cnt[0];
+  const int64_t n_new = cnt[0], n_cnew = cnt[1];
   m->last.n_new_blocks = n_new;
   smki_status rc = ensure_pool(m, m->n_blocks + n_new);
   if (rc != SMKI_OK) return rc;
   rc = ensure_hash(m, m->n_blocks + n_new);
   if (rc != SMKI_OK) return rc;
+  rc = ensure_cpool(m, m->n_cblocks + n_cnew);
+  if (rc != SMKI_OK) return rc;
   SMKI_HIP_TRY(hipEventRecord(m->ev[2], q));
   SMKI_HIP_TRY(launch_assign_new(m->dev, sa, n_t, d_isnew, d_rank, m->n_blocks, d_tslot, m->d_err, q));
-  sa.alpha = m->dev.alpha;
-  sa.n_old = m->n_blocks;
+  SMKI_HIP_TRY(launch_assign_cblocks(m->dev, n_t, d_need, d_cpos, d_tslot, m->n_cblocks, q));
+  sa.map = m->dev;
+  sa.n_cold = m->n_cblocks;
   sa.alpha0 = m->alpha0;
   SMKI_HIP_TRY(launch_merge(sa, n_t, q));
   SMKI_HIP_TRY(hipEventRecord(m->ev[3], q));
   SMKI_HIP_TRY(hipMemcpyAsync(m->h_pin + 8, m->d_stats, sizeof(unsigned long long) * 4,
                               hipMemcpyDeviceToHost, q));
   m->n_blocks += n_new;
+  m->n_cblocks += n_cnew;
+  m->last.n_new_class_blocks = n_cnew;
   m->stats_pending = true;
   return SMKI_OK;
 }
@@ -631,7 +682,9 @@ smki_status smki_create_map(float res, int32_t block_size, float l, float sigma0
       hipEventCreate(&m->ev[2]) != hipSuccess || hipEventCreate(&m->ev[3]) != hipSuccess)
     rc = SMKI_E_OOM;
   if (rc == SMKI_OK && hipMemset(m->d_err, 0, 64) != hipSuccess) rc = SMKI_E_DEVICE;
-  if (rc == SMKI_OK) rc = ensure_pool(m, (opt && opt->initial_blocks > 0) ? opt->initial_blocks : 4096);
+  const int64_t init_blocks = (opt && opt->initial_blocks > 0) ? opt->initial_blocks : 4096;
+  if (rc == SMKI_OK) rc = ensure_pool(m, init_blocks);
+  if (rc == SMKI_OK) rc = ensure_cpool(m, 2 * init_blocks);
   if (rc == SMKI_OK) rc = ensure_hash(m, 4096);
   if (rc == SMKI_OK && hipStreamSynchronize(m->stream) != hipSuccess) rc = SMKI_E_DEVICE;
   if (rc != SMKI_OK) {
@@ -648,7 +701,8 @@ smki_status smki_destroy_map(smki_map* m) {
   if (m->dev.hkeys) (void)hipFree(m->dev.hkeys);
   if (m->dev.hvals) (void)hipFree(m->dev.hvals);
   if (m->dev.bkeys) (void)hipFree(m->dev.bkeys);
-  if (m->dev.alpha) (void)hipFree(m->dev.alpha);
+  if (m->dev.cslot) (void)hipFree(m->dev.cslot);
+  if (m->dev.calpha) (void)hipFree(m->dev.calpha);
   if (m->d_err) (void)hipFree(m->d_err);
   if (m->d_stats) (void)hipFree(m->d_stats);
   if (m->d_offs) (void)hipFree(m->d_offs);
@@ -722,7 +776,7 @@ smki_status smki_export(smki_map* m, int64_t capacity, int64_t* n_blocks, int32_
   SMKI_HIP_TRY(launch_iota_u32(o, n, m->stream));
   SMKI_HIP_TRY(radix_sort_u64(k, o, k2, o2, n, 63, tmp, m->stream));
   if (block_ijk) SMKI_HIP_TRY(launch_block_keys_to_ijk(k, n, block_ijk, m->stream));
-  if (alpha) SMKI_HIP_TRY(launch_gather_blocks(m->dev, o, n, nullptr, alpha, m->stream));
+  if (alpha) SMKI_HIP_TRY(launch_gather_blocks(m->dev, o, n, alpha, m->stream));
   SMKI_HIP_TRY(hipStreamSynchronize(m->stream));
   return SMKI_OK;
 }
@@ -731,15 +785,33 @@ smki_status smki_import(smki_map* m, int64_t n, const int32_t* block_ijk, const 
   if (!m || n < 0 || (n > 0 && (!block_ijk || !alpha))) return SMKI_E_INVALID_ARG;
   smki_status rc = ensure_pool(m, std::max<int64_t>(n, 1));
   if (rc != SMKI_OK) return rc;
-  const int64_t keep = m->n_blocks;
-  m->n_blocks = 0;  // the hash is rebuilt from the imported keys below
+  m->n_blocks = 0;   // the hash and the class blocks are rebuilt from the input below
+  m->n_cblocks = 0;
   rc = ensure_hash(m, std::max<int64_t>(n, 1));
-  if (rc != SMKI_OK) { m->n_blocks = keep; return rc; }
-  const size_t per = (size_t)m->K * m->B * m->B * m->B;
-  SMKI_HIP_TRY(launch_ijk_to_block_keys(block_ijk, n, m->dev.bkeys, m->d_err, m->stream));
-  if (n > 0)
-    SMKI_HIP_TRY(hipMemcpyAsync(m->dev.alpha, alpha, sizeof(float) * per * n,
-                                hipMemcpyDeviceToDevice, m->stream));
+  if (rc != SMKI_OK) return rc;
+  if (n > 0) {
+    // class blocks only for (block, class) pairs holding a value other than alpha0
+    const int64_t nk = n * m->K;
+    Sizer z;
+    z.add<int32_t>(nk);
+    z.add<int32_t>(nk);
+    z.add<int32_t>(2);
+    z.add<char>(scan_tmp_bytes(nk));
+    SMKI_HIP_TRY(m->a_misc.reserve(z.total));
+    int32_t* flag = m->a_misc.take<int32_t>(nk);
+    int32_t* pos = m->a_misc.take<int32_t>(nk);
+    int32_t* tot = m->a_misc.take<int32_t>(2);
+    void* tmp = m->a_misc.take<char>(scan_tmp_bytes(nk));
+    SMKI_HIP_TRY(launch_ijk_to_block_keys(block_ijk, n, m->dev.bkeys, m->d_err, m->stream));
+    SMKI_HIP_TRY(launch_import_flags(m->dev, alpha, n, flag, m->stream));
+    SMKI_HIP_TRY(scan_excl_i32(flag, pos, nk, tot, tmp, m->stream));
+    int32_t nc = 0;
+    SMKI_HIP_TRY(sync_read(m, tot, sizeof(nc), &nc));
+    rc = ensure_cpool(m, nc);
+    if (rc != SMKI_OK) return rc;
+    SMKI_HIP_TRY(launch_import_copy(m->dev, alpha, n, flag, pos, 0, m->stream));
+    m->n_cblocks = nc;
+  }
   SMKI_HIP_TRY(launch_hash_clear(m->dev, m->stream));
   SMKI_HIP_TRY(launch_hash_insert_slots(m->dev, 0, n, m->d_err, m->stream));
   m->n_blocks = n;

@@ -16,13 +16,16 @@ static constexpr double kSmkiQ[SMKI_POLY_N] = {
     0.04696689938778598, -0.41528081234338315, 1.9962683906096352, -6.394682424213184,
     13.385465187748379,  -16.277320609426397,  8.658583627197082};
 
-// Block-hash and pool of the persistent map.
+// Block hash and pools of the persistent map.  A block holds, per class, either
+// nothing (every voxel at the prior alpha0) or one class block of B^3
+// concentrations: only classes that some row ever reached take memory.
 struct MapDev {
   uint64_t* hkeys;      // [hcap] block keys, ~0 = empty
   int32_t* hvals;       // [hcap] pool slot
   int64_t hcap;         // power of two
   uint64_t* bkeys;      // [pool_cap] key of each pool slot
-  float* alpha;         // [pool_cap][K][B^3]
+  int32_t* cslot;       // [pool_cap][K] class block of (block, class), -1: all alpha0
+  float* calpha;        // [cpool_cap][B^3] concentrations of the allocated class blocks
   int32_t K, B, log2B;
   float alpha0;
 };
@@ -63,9 +66,10 @@ struct SplatArgs {
   const int32_t* tgt_elin;    // [n_targets] extended-grid linear index
   int32_t* tgt_active;        // [n_targets] 1 if some row reaches the block
   const int32_t* tgt_slot;    // [n_targets] pool slot (-1: inactive)
-  float* alpha;               // pool
-  int64_t n_old;              // pool slots in use before this insert (newer ones are fresh)
-  float alpha0;               // prior concentration written to fresh blocks
+  const int32_t* contrib;     // [n_targets][K] 1: some row of the class reaches the block
+  MapDev map;
+  int64_t n_cold;             // class blocks in use before this insert (newer ones are fresh)
+  float alpha0;               // prior concentration written to fresh class blocks
   unsigned long long* stats;  // [0] updated voxels, [1] in-support pairs
 };
 
@@ -80,6 +84,17 @@ hipError_t launch_unit_table(const int32_t* nunits, const int32_t* ustart, int32
                              int2* units, hipStream_t st);
 hipError_t launch_splat(const SplatArgs& a, int64_t n_units, hipStream_t st);
 hipError_t launch_merge(const SplatArgs& a, int32_t n_targets, hipStream_t st);
+// class blocks: which (target, class) pairs receive rows, which need a new
+// class block, and their allocation (splat.hip)
+hipError_t launch_contrib(const SplatArgs& a, bool own_block_only, int32_t* contrib,
+                          hipStream_t st);
+hipError_t launch_need(const MapDev& m, int32_t n_targets, const int32_t* contrib,
+                       const int32_t* is_new, const int32_t* tgt_slot, int32_t* need,
+                       hipStream_t st);
+hipError_t launch_assign_cblocks(const MapDev& m, int32_t n_targets, const int32_t* need,
+                                 const int32_t* cpos, const int32_t* tgt_slot, int64_t n_cold,
+                                 hipStream_t st);
+hipError_t launch_slot_info(const SplatArgs& a, hipStream_t st);
 hipError_t launch_map_lookup(const MapDev& m, const SplatArgs& a, int32_t n_targets,
                              int32_t* tgt_slot, int32_t* is_new, hipStream_t st);
 hipError_t launch_assign_new(const MapDev& m, const SplatArgs& a, int32_t n_targets,
@@ -89,7 +104,7 @@ hipError_t launch_assign_new(const MapDev& m, const SplatArgs& a, int32_t n_targ
 // csm.hip: counting-model inserts
 hipError_t launch_csm_counts(const SplatArgs& a, const void* keys, bool wide_keys, int64_t n,
                              uint32_t* vbits, int64_t n_targets, hipStream_t st);
-hipError_t launch_fill_alpha0(const MapDev& m, int64_t slot0, int64_t nslots, hipStream_t st);
+hipError_t launch_fill_calpha0(const MapDev& m, int64_t c0, int64_t nc, hipStream_t st);
 
 // map.hip
 hipError_t launch_query(const MapDev& m, const int32_t* ijk, int64_t M, float* alpha, float* mean,
@@ -99,7 +114,13 @@ hipError_t launch_hash_clear(const MapDev& m, hipStream_t st);
 hipError_t launch_hash_insert_slots(const MapDev& m, int64_t slot0, int64_t n, uint32_t* err,
                                     hipStream_t st);
 hipError_t launch_gather_blocks(const MapDev& m, const uint32_t* order, int64_t n,
-                                int32_t* block_ijk, float* alpha_out, hipStream_t st);
+                                float* alpha_out, hipStream_t st);
+// import: flags of the (block, class) pairs holding any value other than alpha0,
+// then the copy of those into class blocks c0 + pos
+hipError_t launch_import_flags(const MapDev& m, const float* alpha, int64_t n, int32_t* flag,
+                               hipStream_t st);
+hipError_t launch_import_copy(const MapDev& m, const float* alpha, int64_t n, const int32_t* flag,
+                              const int32_t* pos, int64_t c0, hipStream_t st);
 hipError_t launch_block_keys_to_ijk(const uint64_t* keys, int64_t n, int32_t* ijk, hipStream_t st);
 hipError_t launch_ijk_to_block_keys(const int32_t* ijk, int64_t n, uint64_t* keys, uint32_t* err,
                                     hipStream_t st);

@@ -362,18 +362,16 @@ __global__ void __launch_bounds__(B * B * B) k_merge(SplatArgs a, int32_t n_targ
   constexpr int DR3 = DR * DR * DR;
   constexpr int B3 = S::B3, NT = S::NT, CPG = S::CPG, MAXC = S::MAXC, AX = S::AX;
   __shared__ int4 ent[CPG * 27];      // [class][neighbour]: (first unit, units, union mask, -)
-  __shared__ int32_t cflag[CPG], clist[CPG], ncls_s;
+  __shared__ int32_t cflag[CPG], clist[CPG], cblk[CPG], ncls_s;
   __shared__ int32_t red[NT / SMKI_WAVE];
   const int32_t t = blockIdx.x;
   if (t >= n_targets || !a.tgt_active[t]) return;
   const int tid = threadIdx.x;
   const int32_t mslot = a.tgt_slot[t];
-  const bool fresh = mslot >= a.n_old;
   int32_t bt[3];
   unlin3(a.tgt_elin[t], a.enb, bt);
   int32_t pt[3];   // target block on the point grid
   for (int q = 0; q < 3; ++q) pt[q] = bt[q] + a.eblo[q] - a.g.blo[q];
-  float* A = a.alpha + (int64_t)mslot * a.K * B3;
   const int vv[3] = {tid / (B * B), (tid / B) % B, tid % B};
   // covering neighbours c, per axis: 0, -1 if v < R, +1 if v >= B - R (both only
   // when 2R > B); the voxel is in piece p = 26 - c of the neighbour's region.
@@ -410,18 +408,18 @@ __global__ void __launch_bounds__(B * B * B) k_merge(SplatArgs a, int32_t n_targ
   bool upd = false;
   for (int y0 = 0; y0 < a.K; y0 += CPG) {
     const int ny = min(CPG, a.K - y0);
-    if (tid < ny) cflag[tid] = 0;
-    __syncthreads();
+    // classes whose rows reach this block, and their class blocks
+    if (tid < ny) {
+      cflag[tid] = a.contrib[(int64_t)t * a.K + y0 + tid];
+      cblk[tid] = a.map.cslot[(int64_t)mslot * a.K + y0 + tid];
+    }
     for (int i = tid; i < 27 * ny; i += NT) {
       const int d = i / ny, yc = i - d * ny;
       const int px = pt[0] + d / 9 - 1, py = pt[1] + (d / 3) % 3 - 1, pz = pt[2] + d % 3 - 1;
       int4 e = make_int4(0, 0, 0, 0);
       if (px >= 0 && py >= 0 && pz >= 0 && px < a.g.nb[0] && py < a.g.nb[1] && pz < a.g.nb[2]) {
         const int32_t s = a.dense[(((int64_t)px * a.g.nb[1] + py) * a.g.nb[2] + pz) * a.K + y0 + yc];
-        if (s >= 0) {
-          e = a.sinfo[s];
-          atomicOr(&cflag[yc], 1);
-        }
+        if (s >= 0) e = a.sinfo[s];
       }
       ent[yc * 27 + d] = e;
     }
@@ -434,10 +432,6 @@ __global__ void __launch_bounds__(B * B * B) k_merge(SplatArgs a, int32_t n_targ
     }
     __syncthreads();
     const int ncls = ncls_s;
-    if (fresh) {
-      for (int yc = 0; yc < ny; ++yc)
-        if (!cflag[yc]) A[(int64_t)(y0 + yc) * B3 + tid] = a.alpha0;
-    }
     if constexpr (MAXC > 8) {
       // 2R > B (B = 4 with a reach of 3 or 4 voxels): up to 27 candidates,
       // summed one at a time
@@ -458,9 +452,10 @@ __global__ void __launch_bounds__(B * B * B) k_merge(SplatArgs a, int32_t n_targ
             sm = tv;
           }
         }
-        float* dst = A + (int64_t)(y0 + yc) * B3 + tid;
-        if (fresh) {
-          *dst = a.alpha0 + sm;
+        const int32_t cb = cblk[yc];   // allocated for every class with rows reaching here
+        float* dst = a.map.calpha + (int64_t)cb * B3 + tid;
+        if (cb >= a.n_cold) {
+          *dst = a.alpha0 + sm;   // class block allocated by this insert: written whole
         } else if (sm != 0.0f) {
           *dst += sm;
         }
@@ -506,9 +501,10 @@ __global__ void __launch_bounds__(B * B * B) k_merge(SplatArgs a, int32_t n_targ
             sm = tv;
           }
         }
-        float* dst = A + (int64_t)(y0 + yc) * B3 + tid;
-        if (fresh) {
-          *dst = a.alpha0 + sm;
+        const int32_t cb = cblk[yc];   // allocated for every class with rows reaching here
+        float* dst = a.map.calpha + (int64_t)cb * B3 + tid;
+        if (cb >= a.n_cold) {
+          *dst = a.alpha0 + sm;   // class block allocated by this insert: written whole
         } else if (sm != 0.0f) {
           *dst += sm;
         }
@@ -525,6 +521,48 @@ __global__ void __launch_bounds__(B * B * B) k_merge(SplatArgs a, int32_t n_targ
     for (int i = 0; i < NT / SMKI_WAVE; ++i) tot += red[i];
     atomicAdd(&a.stats[0], (unsigned long long)tot);
   }
+}
+
+// (target, class) pairs that receive rows: from each slot's non-zero pieces (or
+// the slot's own block for the counting model); idempotent flag stores.
+__global__ void k_contrib(SplatArgs a, int32_t own_block_only, int32_t* __restrict__ contrib) {
+  const int32_t s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= a.n_slots) return;
+  const int32_t plane_lin = a.slot_lin[s];
+  const int32_t y = (int32_t)(plane_lin / a.g.n_blocks);
+  int32_t pb[3];
+  unlin3(plane_lin % a.g.n_blocks, a.g.nb, pb);
+  const uint32_t m = own_block_only ? (1u << 13) : (uint32_t)a.sinfo[s].z;
+  for (int p = 0; p < 27; ++p) {
+    if (!((m >> p) & 1u)) continue;
+    const int dx = p / 9 - 1, dy = (p / 3) % 3 - 1, dz = p % 3 - 1;
+    const int64_t e = ((int64_t)(pb[0] + a.g.blo[0] - a.eblo[0] + dx) * a.enb[1] +
+                       (pb[1] + a.g.blo[1] - a.eblo[1] + dy)) * a.enb[2] +
+                      (pb[2] + a.g.blo[2] - a.eblo[2] + dz);
+    const int32_t t = a.ext2t[e];
+    if (t >= 0) contrib[(int64_t)t * a.K + y] = 1;
+  }
+}
+
+// a class block is needed where rows arrive and the block has none for the class
+__global__ void k_need(MapDev m, int32_t n_targets, const int32_t* __restrict__ contrib,
+                       const int32_t* __restrict__ is_new, const int32_t* __restrict__ tgt_slot,
+                       int32_t* __restrict__ need) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= (int64_t)n_targets * m.K) return;
+  const int32_t t = (int32_t)(i / m.K), k = (int32_t)(i % m.K);
+  int32_t v = 0;
+  if (contrib[i]) v = (is_new[t] || m.cslot[(int64_t)tgt_slot[t] * m.K + k] < 0) ? 1 : 0;
+  need[i] = v;
+}
+
+__global__ void k_assign_cblocks(MapDev m, int32_t n_targets, const int32_t* __restrict__ need,
+                                 const int32_t* __restrict__ cpos,
+                                 const int32_t* __restrict__ tgt_slot, int64_t n_cold) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= (int64_t)n_targets * m.K || !need[i]) return;
+  const int32_t t = (int32_t)(i / m.K), k = (int32_t)(i % m.K);
+  m.cslot[(int64_t)tgt_slot[t] * m.K + k] = (int32_t)(n_cold + cpos[i]);
 }
 
 // map-slot lookup of the active targets; new blocks are marked for allocation
@@ -564,6 +602,7 @@ __global__ void k_assign_new(MapDev m, SplatArgs a, int32_t n_targets,
   const int32_t slot = (int32_t)(n_old + rank[t]);
   tgt_slot[t] = slot;
   m.bkeys[slot] = key;
+  for (int32_t k = 0; k < m.K; ++k) m.cslot[(int64_t)slot * m.K + k] = -1;
   uint64_t h = smki_mix64(key) & (uint64_t)(m.hcap - 1);
   for (int64_t probe = 0; probe < m.hcap; ++probe) {
     const unsigned long long old =
@@ -598,8 +637,6 @@ hipError_t launch_splat_br(const SplatArgs& a, int64_t n_units, int32_t n_target
       return launch_splat_ns<B, R, Steps<R>::NS>(a, n_units, (a.noff + SMKI_WAVE - 1) / SMKI_WAVE,
                                                  st);
   } else {
-    if (a.n_slots > 0)
-      hipLaunchKernelGGL(k_slot_info, dim3(nblk(a.n_slots, 256)), dim3(256), 0, st, a);
     if (n_targets > 0)
       hipLaunchKernelGGL((k_merge<B, R>), dim3((unsigned)n_targets), dim3(MergeShape<B, R>::NT), 0,
                          st, a, n_targets);
@@ -693,5 +730,39 @@ hipError_t launch_assign_new(const MapDev& m, const SplatArgs& a, int32_t n_targ
   if (n_targets <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_assign_new, dim3(nblk(n_targets, 256)), dim3(256), 0, st, m, a, n_targets,
                      is_new, new_rank, n_old, tgt_slot, err);
+  return hipGetLastError();
+}
+
+hipError_t launch_slot_info(const SplatArgs& a, hipStream_t st) {
+  if (a.n_slots <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_slot_info, dim3(nblk(a.n_slots, 256)), dim3(256), 0, st, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_contrib(const SplatArgs& a, bool own_block_only, int32_t* contrib,
+                          hipStream_t st) {
+  if (a.n_slots <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_contrib, dim3(nblk(a.n_slots, 256)), dim3(256), 0, st, a,
+                     own_block_only ? 1 : 0, contrib);
+  return hipGetLastError();
+}
+
+hipError_t launch_need(const MapDev& m, int32_t n_targets, const int32_t* contrib,
+                       const int32_t* is_new, const int32_t* tgt_slot, int32_t* need,
+                       hipStream_t st) {
+  const int64_t n = (int64_t)n_targets * m.K;
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_need, dim3(nblk(n, 256)), dim3(256), 0, st, m, n_targets, contrib, is_new,
+                     tgt_slot, need);
+  return hipGetLastError();
+}
+
+hipError_t launch_assign_cblocks(const MapDev& m, int32_t n_targets, const int32_t* need,
+                                 const int32_t* cpos, const int32_t* tgt_slot, int64_t n_cold,
+                                 hipStream_t st) {
+  const int64_t n = (int64_t)n_targets * m.K;
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_assign_cblocks, dim3(nblk(n, 256)), dim3(256), 0, st, m, n_targets, need,
+                     cpos, tgt_slot, n_cold);
   return hipGetLastError();
 }
