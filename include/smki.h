@@ -49,6 +49,12 @@ typedef struct smki_map smki_map;
                               (free-space samples included); exact while a voxel holds
                               fewer than 2^24 rows of a class */
 
+/* Training rows of a voxel (smki_options.selection). */
+#define SMKI_SELECT_EXACT 0        /* every row within l: Eq. (7) as written */
+#define SMKI_SELECT_FACE_BLOCKS 1  /* rows within l whose block is the voxel's own block or
+                                      one of the six sharing a face with it: the extended
+                                      block of the paper's implementation (Sec. IV) */
+
 /* Optional settings; pass NULL for defaults (all fields 0). */
 typedef struct smki_options {
   int64_t initial_blocks;   /* initial pool capacity in blocks (0: 4096); grows on demand */
@@ -57,6 +63,9 @@ typedef struct smki_options {
                                more rows is split into several units */
   int32_t model;            /* SMKI_MODEL_SBKI (default) or SMKI_MODEL_SCSM; l and sigma0
                                are not used by the counting model */
+  int32_t selection;        /* SMKI_SELECT_EXACT (default) or SMKI_SELECT_FACE_BLOCKS
+                               (S-BKI only); with face blocks, n_pairs still counts the
+                               pairs of the exact support */
 } smki_options;
 
 /* Counters of the last insert (smki_last_scan_stats). */

@@ -73,7 +73,7 @@ def lib():
                                           C.c_int32, i64p, f32p, i32p, i64p]
         L.oracle_map_create.restype = C.c_void_p
         L.oracle_map_create.argtypes = [C.c_int32, C.c_float, C.c_int32, C.c_float, C.c_float,
-                                        C.c_float, C.c_int32]
+                                        C.c_float, C.c_int32, C.c_int32]
         L.oracle_map_destroy.argtypes = [C.c_void_p]
         L.oracle_map_insert_training.argtypes = [C.c_void_p, f32p, i32p, C.c_int64]
         L.oracle_map_insert_scan.argtypes = [C.c_void_p, f32p, i32p, C.c_int64, f32p, C.c_float,
@@ -221,18 +221,22 @@ def alpha_at_voxels(train_xyz, train_label, ijk, res, K, l, sigma0, alpha0):
 
 class OracleMap:
     """Eq. (7) at every grid centroid, accumulated scan after scan (Sec. IV);
-    with scsm=True the counting model of Eq. (2) instead."""
+    with scsm=True the counting model of Eq. (2) instead.  face_blocks=True
+    restricts a voxel's training rows to its block and the six blocks sharing a
+    face with it (the extended block of the paper's implementation, Sec. IV)."""
 
-    def __init__(self, K, res, block_size, l, sigma0, alpha0, scsm=False):
+    def __init__(self, K, res, block_size, l, sigma0, alpha0, scsm=False, face_blocks=False):
         self.K = int(K)
         self._h = lib().oracle_map_create(K, C.c_float(res), block_size, C.c_float(l),
-                                          C.c_float(sigma0), C.c_float(alpha0), int(bool(scsm)))
+                                          C.c_float(sigma0), C.c_float(alpha0), int(bool(scsm)),
+                                          int(bool(face_blocks)))
         if not self._h:
             raise OracleError(E_ARG, "map_create")
 
     @classmethod
-    def from_params(cls, p, scsm=False):
-        return cls(p.K, p.res, p.block_size, p.l, p.sigma0, p.alpha0, scsm=scsm)
+    def from_params(cls, p, scsm=False, face_blocks=False):
+        return cls(p.K, p.res, p.block_size, p.l, p.sigma0, p.alpha0, scsm=scsm,
+                   face_blocks=face_blocks)
 
     def __del__(self):
         h = getattr(self, "_h", None)

@@ -378,7 +378,18 @@ typedef struct oracle_map {
     double *alpha;   /* rows * K */
     int64_t *nv, *nband;
     int scsm;        /* 1: S-CSM map (Eq. 2), 0: S-BKI map (Eq. 7) */
+    int face_blocks; /* 1: a voxel's training rows are those in its block and the six
+                        face-adjacent blocks (the extended block of Sec. IV's
+                        implementation notes), 0: every row (exact Eq. 7) */
 } oracle_map;
+
+/* floor(a / b) for b > 0 */
+static int64_t fdiv_floor(int64_t a, int64_t b)
+{
+    int64_t q = a / b;
+    if ((a % b != 0) && (a < 0)) --q;
+    return q;
+}
 
 static uint64_t mix64(uint64_t x)
 {
@@ -389,7 +400,7 @@ static uint64_t mix64(uint64_t x)
 }
 
 oracle_map *oracle_map_create(int32_t K, float res, int32_t block_size, float l, float sigma0,
-                              float alpha0, int32_t scsm)
+                              float alpha0, int32_t scsm, int32_t face_blocks)
 {
     if (K < 1 || !(res > 0) || !(l > 0) || block_size < 1) return NULL;
     oracle_map *m = (oracle_map *)calloc(1, sizeof(oracle_map));
@@ -398,6 +409,7 @@ oracle_map *oracle_map_create(int32_t K, float res, int32_t block_size, float l,
     m->res32 = res; m->l32 = l; m->sigma032 = sigma0; m->alpha032 = alpha0;
     m->res = res; m->l = l; m->sigma0 = sigma0; m->alpha0 = alpha0;
     m->scsm = scsm;
+    m->face_blocks = face_blocks;
     m->cap = 1 << 16;
     m->tab = (or_slot *)malloc(sizeof(or_slot) * m->cap);
     for (int64_t i = 0; i < m->cap; ++i) m->tab[i].key = UINT64_MAX;
@@ -493,6 +505,12 @@ int oracle_map_insert_training(oracle_map *m, const float *xyz, const int32_t *l
             continue;
         }
         const double x[3] = {p[0], p[1], p[2]};
+        /* block of the row's own voxel (for the extended-block selection) */
+        int32_t pv[3];
+        if (m->face_blocks) {
+            int rc = voxel_of(p, m->res32, pv);
+            if (rc) return rc;
+        }
         int64_t lo[3], hi[3];
         for (int a = 0; a < 3; ++a) {
             lo[a] = (int64_t)floor((x[a] - L) / res - 0.5) - 1;
@@ -506,6 +524,14 @@ int oracle_map_insert_training(oracle_map *m, const float *xyz, const int32_t *l
                 for (int64_t k = lo[2]; k <= hi[2]; ++k) {
                     double dz = x[2] - ((double)k + 0.5) * res;
                     double d2 = dx * dx + dy * dy + dz * dz;
+                    if (m->face_blocks) {
+                        /* the row must lie in the voxel's block or one sharing a face */
+                        const int64_t B = m->B;
+                        const int64_t db = llabs(fdiv_floor(pv[0], B) - fdiv_floor(i, B)) +
+                                           llabs(fdiv_floor(pv[1], B) - fdiv_floor(j, B)) +
+                                           llabs(fdiv_floor(pv[2], B) - fdiv_floor(k, B));
+                        if (db > 1) continue;
+                    }
                     int band = fabs(d2 / L2 - 1.0) <= 1e-5;
                     if (!(d2 < L2) && !band) continue;
                     int64_t r = map_row(m, pack_key(i, j, k));

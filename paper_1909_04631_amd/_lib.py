@@ -38,10 +38,12 @@ class SmkiError(RuntimeError):
 
 
 class Options(C.Structure):
-    _fields_ = [("initial_blocks", C.c_int64), ("unit_budget", C.c_int32), ("model", C.c_int32)]
+    _fields_ = [("initial_blocks", C.c_int64), ("unit_budget", C.c_int32), ("model", C.c_int32),
+                ("selection", C.c_int32)]
 
 
 MODELS = {"sbki": 0, "scsm": 1}
+SELECTIONS = {"exact": 0, "face_blocks": 1}
 
 
 class ScanStats(C.Structure):

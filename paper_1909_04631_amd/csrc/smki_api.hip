@@ -83,7 +83,8 @@ struct smki_map {
   float res, l, sigma0, alpha0;
   int32_t K, B, log2B, free_class;
   int32_t chunk;  // rows per splat work unit
-  int32_t model;  // SMKI_MODEL_SBKI or SMKI_MODEL_SCSM
+  int32_t model;      // SMKI_MODEL_SBKI or SMKI_MODEL_SCSM
+  int32_t selection;  // SMKI_SELECT_EXACT or SMKI_SELECT_FACE_BLOCKS
   int device = 0;
   hipStream_t stream = nullptr;
   // persistent device state
@@ -528,6 +529,12 @@ smki_status insert_impl(smki_map* m, const float* xyz, const int32_t* label, int
   sa.cscale = (float)(kSmkiQ[0] * (double)m->sigma0);
   sa.K = m->K;
   sa.chunk = m->chunk;
+  // piece p = (dx+1)*9 + (dy+1)*3 + (dz+1): all 27, or those with at most one dx, dy, dz != 0
+  sa.piece_mask = 0;
+  for (int p = 0; p < 27; ++p) {
+    const int nz = (p / 9 != 1) + ((p / 3) % 3 != 1) + (p % 3 != 1);
+    if (m->selection == SMKI_SELECT_EXACT || nz <= 1) sa.piece_mask |= 1u << p;
+  }
   sa.pts = ps.pts;
   sa.dense = ps.dense;
   sa.head = ps.head;
@@ -652,7 +659,8 @@ smki_status smki_create_map(float res, int32_t block_size, float l, float sigma0
   if (K < 2 || K > 255 || free_class < 0 || free_class >= K) return SMKI_E_INVALID_ARG;
   if (block_size != 4 && block_size != 8) return SMKI_E_INVALID_ARG;
   if (opt && (opt->initial_blocks < 0 || opt->unit_budget < 0 || opt->unit_budget > (1 << 24) ||
-              (opt->model != SMKI_MODEL_SBKI && opt->model != SMKI_MODEL_SCSM)))
+              (opt->model != SMKI_MODEL_SBKI && opt->model != SMKI_MODEL_SCSM) ||
+              (opt->selection != SMKI_SELECT_EXACT && opt->selection != SMKI_SELECT_FACE_BLOCKS)))
     return SMKI_E_INVALID_ARG;
   int ndev = 0;
   if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) return SMKI_E_DEVICE;
@@ -668,6 +676,7 @@ smki_status smki_create_map(float res, int32_t block_size, float l, float sigma0
   m->free_class = free_class;
   m->chunk = (opt && opt->unit_budget > 0) ? opt->unit_budget : SMKI_CHUNK;
   m->model = opt ? opt->model : SMKI_MODEL_SBKI;
+  m->selection = opt ? opt->selection : SMKI_SELECT_EXACT;
   (void)hipGetDevice(&m->device);
   m->dev.K = K;
   m->dev.B = block_size;

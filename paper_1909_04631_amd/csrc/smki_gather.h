@@ -58,6 +58,8 @@ struct SplatArgs {
                               // piece: the region split into the 27 parts that fall in the
                               // unit's block and its neighbours, each contiguous (x, y, z)
   uint32_t* umask;            // [n_units] bit d: piece d is non-zero (and written)
+  uint32_t piece_mask;        // pieces a unit may contribute (all 27, or the own block and
+                              // its 6 face neighbours for the extended-block selection)
   int4* sinfo;                // [slots] (first unit, units, union of the units' masks, 0)
   int32_t n_slots;
   // targets (blocks within reach of a row block), on the extended grid

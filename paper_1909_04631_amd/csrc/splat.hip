@@ -287,7 +287,7 @@ __global__ void __launch_bounds__(SMKI_WAVE) k_splat(SplatArgs a) {
   }
 #pragma unroll
   for (int o = SMKI_WAVE / 2; o > 0; o >>= 1) touched |= __shfl_xor(touched, o, SMKI_WAVE);
-  touched = __builtin_amdgcn_readfirstlane(touched);
+  touched = __builtin_amdgcn_readfirstlane(touched) & a.piece_mask;
   if (lane == 0) a.umask[blockIdx.x] = touched;
   // write the non-zero pieces
   using PC = Pieces<B, R>;

@@ -14,9 +14,9 @@ def cuda(a, dtype=None):
     return t.cuda()
 
 
-def oracle_map_of(scene, scans=None, scsm=False):
+def oracle_map_of(scene, scans=None, scsm=False, face_blocks=False):
     p = scene.params.f32()
-    m = oracle.OracleMap.from_params(p, scsm=scsm)
+    m = oracle.OracleMap.from_params(p, scsm=scsm, face_blocks=face_blocks)
     for s in (scene.scans if scans is None else scans):
         m.insert_scan(s.xyz, s.label, s.origin, p.free_step, p.free_class)
     return m

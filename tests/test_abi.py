@@ -50,7 +50,7 @@ def test_host_argument_checks_need_no_gpu(lib):
     assert lib.smki_create_map(0.1, 16, 0.3, 0.1, 4, 1e-3, 0, None, C.byref(h)) == -1
     assert lib.smki_create_map(0.1, 8, 0.3, 0.1, 4, 1e-3, 4, None, C.byref(h)) == -1
     assert lib.smki_create_map(0.1, 8, float("nan"), 0.1, 4, 1e-3, 0, None, C.byref(h)) == -1
-    for bad in (Options(-1, 0), Options(0, -1), Options(0, (1 << 24) + 1), Options(0, 0, 2)):
+    for bad in (Options(-1, 0), Options(0, -1), Options(0, (1 << 24) + 1), Options(0, 0, 2), Options(0, 0, 0, 2)):
         assert lib.smki_create_map(0.1, 8, 0.3, 0.1, 4, 1e-3, 0, C.byref(bad), C.byref(h)) == -1
     assert lib.smki_insert_scan(None, None, None, 0, None, 0.3) == -1
     assert lib.smki_query(None, None, 0, None, None, None, None, None) == -1

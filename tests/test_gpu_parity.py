@@ -296,3 +296,28 @@ def test_lidar_scan_full_size_sampled():
     err = rel_err(a, a_ref)
     print(f"lidar sampled max rel err {err.max():.2e}, max n_in {n_in.max()}", flush=True)
     assert err.max() <= ALPHA_RTOL
+
+
+# ---------------------------------------------------------------------------
+# the paper's extended-block selection (a voxel trains on rows of its block and
+# the six face-adjacent blocks)
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("B", [4, 8])
+def test_extended_block_selection_matches_the_oracle(B):
+    sc = scenes.make_config(0)
+    sc.params.block_size = B
+    _print_case(f"face blocks B={B}")
+    gm = gpu_map_of(sc, selection="face_blocks")
+    om = oracle_map_of(sc, face_blocks=True)
+    worst, (ijk, a_ref, nv, nb) = compare_map(gm, om, sc.params.K)
+    st = gm.stats()
+    v_strict = int((nv > 0).sum())
+    assert abs(st["n_updated_voxels"] - v_strict) <= int((nb > 0).sum())
+    # voxels the exact support reaches but the selection does not stay at alpha0
+    ex = oracle_map_of(sc)
+    ie, ae, nve, _ = ex.export()
+    dropped = np.array([tuple(v) not in set(map(tuple, ijk[nv > 0])) for v in ie]) & (nve > 0)
+    if dropped.any():
+        a = gm.query(cuda(ie[dropped].astype(np.int32)))["alpha"].cpu().numpy()
+        ref = om.lookup(ie[dropped])
+        assert rel_err(a, ref).max() <= ALPHA_RTOL

@@ -215,3 +215,63 @@ def test_table1_hyperparameters_are_what_the_street_workloads_use():
     for n in (1,):
         p = scenes.make_config(n).params
         assert (p.l, p.sigma0, p.alpha0, p.res) == (g["l_m"], g["sigma0"], g["alpha0"], g["res_m"])
+
+
+def test_extended_block_selection_single_hit_at_a_block_corner():
+    # The paper's implementation trains each block on its own rows and those of
+    # the six face-adjacent blocks (Sec. IV).  One hit on the centre of voxel
+    # (7, 7, 7), the corner voxel of block (0, 0, 0) with B = 8: of the 93 voxels
+    # in support, those whose block differs from (0, 0, 0) along two or three
+    # axes are not reached; the others keep exactly the exact-support value.
+    kw = dict(K=3, res=0.125, block_size=8, l=0.375, sigma0=1.0, alpha0=0.001)
+    hit = np.array([[(7 + 0.5) * 0.125] * 3], np.float32)
+    lab = np.array([1], np.int32)
+    exact = oracle.OracleMap(**kw)
+    face = oracle.OracleMap(**kw, face_blocks=True)
+    exact.insert_training(hit, lab)
+    face.insert_training(hit, lab)
+    ie, ae, nve, _ = exact.export()
+    i_f, af, nvf, _ = face.export()
+    D = ie - 7
+    off_axes = (D >= 1).sum(1)                     # axes on which the voxel left block 0
+    keep = (nve > 0) & (off_axes <= 1)
+    # expected count from the offsets alone: |D|^2 <= 8 and at most one axis with D >= 1
+    grid = np.stack(np.meshgrid(*[np.arange(-3, 4)] * 3, indexing="ij"), -1).reshape(-1, 3)
+    n2 = (grid ** 2).sum(1)
+    expect = int(((n2 <= 8) & ((grid >= 1).sum(1) <= 1)).sum())
+    assert int((nvf > 0).sum()) == expect == int(keep.sum())
+    got = {tuple(v): a for v, a, n in zip(i_f, af, nvf) if n > 0}
+    for v, a in zip(ie[keep], ae[keep]):
+        np.testing.assert_array_equal(got[tuple(v)], a)
+    # every voxel reached under the selection is reached without it, never with more
+    assert set(got) <= {tuple(v) for v, n in zip(ie, nve) if n > 0}
+
+
+def test_extended_block_selection_equals_exact_support_inside_blocks():
+    # Rows whose support stays inside their own block see no difference.
+    rng = np.random.default_rng(3)
+    centres = (rng.integers(-4, 4, size=(40, 3)) * 8 + 4).astype(np.float64)   # block centres (voxels)
+    xyz = ((centres + rng.uniform(-1.0, 1.0, size=centres.shape)) * 0.1).astype(np.float32)
+    lab = rng.integers(0, 3, size=40).astype(np.int32)
+    kw = dict(K=3, res=0.1, block_size=8, l=0.25, sigma0=0.7, alpha0=0.001)
+    exact, face = oracle.OracleMap(**kw), oracle.OracleMap(**kw, face_blocks=True)
+    exact.insert_training(xyz, lab)
+    face.insert_training(xyz, lab)
+    ie, ae, _, _ = exact.export()
+    i_f, af, _, _ = face.export()
+    np.testing.assert_array_equal(ie, i_f)
+    np.testing.assert_array_equal(ae, af)
+
+
+def test_extended_block_selection_is_a_lower_bound_on_a_scene():
+    sc = scenes.make_config(0)
+    p = sc.params.f32()
+    s = sc.scans[0]
+    exact = oracle.OracleMap.from_params(p)
+    face = oracle.OracleMap.from_params(p, face_blocks=True)
+    for m in (exact, face):
+        m.insert_scan(s.xyz[:500], s.label[:500], s.origin, p.free_step)
+    ie, ae, _, _ = exact.export()
+    af = face.lookup(ie)
+    assert np.all(af <= ae * (1 + 1e-15))
+    assert np.any(af < ae * (1 - 1e-6))          # the selection does drop rows here
