@@ -78,6 +78,8 @@ def lib():
         L.oracle_map_insert_training.argtypes = [C.c_void_p, f32p, i32p, C.c_int64]
         L.oracle_map_insert_scan.argtypes = [C.c_void_p, f32p, i32p, C.c_int64, f32p, C.c_float,
                                              C.c_int32]
+        L.oracle_map_insert_scan_soft.argtypes = [C.c_void_p, f32p, f32p, C.c_int64, f32p,
+                                                  C.c_float, C.c_int32]
         L.oracle_map_size.restype = C.c_int64
         L.oracle_map_size.argtypes = [C.c_void_p]
         L.oracle_map_export.argtypes = [C.c_void_p, i32p, f64p, i64p, i64p]
@@ -256,6 +258,20 @@ class OracleMap:
         _chk(lib().oracle_map_insert_scan(self._h, _p(xyz, C.c_float), _p(label, C.c_int32),
                                           xyz.shape[0], _p(o, C.c_float), C.c_float(free_step),
                                           free_class), "map_insert_scan")
+
+    def insert_scan_soft(self, xyz, probs, origin, free_step, free_class=0):
+        """One scan of soft measurements: probs[i] holds non-negative class
+        weights of hit i (all zero drops the hit and its beam); each positive
+        weight adds weight x kernel to its class (Sec. VI, linear pooling)."""
+        xyz = _f32x3(xyz)
+        probs = np.ascontiguousarray(probs, dtype=np.float32)
+        if probs.shape != (xyz.shape[0], self.K):
+            raise ValueError(f"probs must have shape [n, {self.K}]")
+        o = np.ascontiguousarray(origin, dtype=np.float32).reshape(3)
+        _chk(lib().oracle_map_insert_scan_soft(self._h, _p(xyz, C.c_float), _p(probs, C.c_float),
+                                               xyz.shape[0], _p(o, C.c_float),
+                                               C.c_float(free_step), free_class),
+             "map_insert_scan_soft")
 
     def __len__(self):
         return int(lib().oracle_map_size(self._h))

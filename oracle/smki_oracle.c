@@ -56,6 +56,10 @@
  *       only when every alpha^k > 1 (NaN otherwise); occupancy probability =
  *       1 - mean of the free class (the sum over the occupied classes).
  *   R12 the recursive update is plain addition.
+ *   R22 soft measurements (Sec. VI): a hit carries a vector of non-negative
+ *       class weights instead of one label and adds each class's weight
+ *       times the kernel (the linear-pooling form); weights are used as given,
+ *       without renormalisation, so a one-hot vector is the hard update.
  *   R14-R16 differentiable form: the loss is the mean negative log predictive
  *       probability  -log(alpha^{y}/S)  of held-out labelled points queried
  *       at their own (continuous) positions; every training row is an input
@@ -483,16 +487,24 @@ static int64_t map_row(oracle_map *m, uint64_t key)
 }
 
 /* Add one training set (rows already expanded: hits + free samples). */
-int oracle_map_insert_training(oracle_map *m, const float *xyz, const int32_t *label, int64_t n)
+/* Rows t = 0..n-1 with class label[t] and measurement weight w[t] (1 for every
+ * row when w is NULL): alpha^y += w sigma0 f(d / l) at every voxel centre
+ * within l (Eq. (7)), or alpha^y += w in the row's own cell (Eq. (2)).  A
+ * one-hot row has w = 1; a soft row contributes its class probability
+ * (reading R22). */
+static int insert_rows(oracle_map *m, const float *xyz, const int32_t *label, const double *w,
+                       int64_t n)
 {
     if (!m || n < 0) return OR_E_ARG;
     for (int64_t t = 0; t < n; ++t) {
         if (label[t] < 0 || label[t] >= m->K) return OR_E_INPUT;
         if (!finite3(xyz + 3 * t)) return OR_E_INPUT;
+        if (w && !(isfinite(w[t]) && w[t] >= 0.0)) return OR_E_INPUT;
     }
     const double res = m->res, L = m->l, L2 = L * L;
     for (int64_t t = 0; t < n; ++t) {
         const float *p = xyz + 3 * t;
+        const double wt = w ? w[t] : 1.0;
         if (m->scsm) {
             /* Eq. (2): the measurement counts in the cell it falls into. */
             int32_t v[3];
@@ -500,7 +512,7 @@ int oracle_map_insert_training(oracle_map *m, const float *xyz, const int32_t *l
             if (rc) return rc;
             int64_t r = map_row(m, pack_key(v[0], v[1], v[2]));
             if (r < 0) return OR_E_OOM;
-            m->alpha[r * m->K + label[t]] += 1.0;
+            m->alpha[r * m->K + label[t]] += wt;
             m->nv[r] += 1;
             continue;
         }
@@ -538,7 +550,7 @@ int oracle_map_insert_training(oracle_map *m, const float *xyz, const int32_t *l
                     if (r < 0) return OR_E_OOM;
                     if (band) m->nband[r] += 1;
                     if (!(d2 < L2)) continue;
-                    m->alpha[r * m->K + label[t]] += m->sigma0 * oracle_kernel_f(sqrt(d2) / L);
+                    m->alpha[r * m->K + label[t]] += wt * (m->sigma0 * oracle_kernel_f(sqrt(d2) / L));
                     m->nv[r] += 1;
                 }
             }
@@ -548,6 +560,60 @@ int oracle_map_insert_training(oracle_map *m, const float *xyz, const int32_t *l
 }
 
 /* One scan: its training set (hits + free samples) into the map. */
+int oracle_map_insert_training(oracle_map *m, const float *xyz, const int32_t *label, int64_t n)
+{
+    return insert_rows(m, xyz, label, NULL, n);
+}
+
+/* One scan of soft measurements (reading R22): probs[i][k] >= 0 is the weight
+ * of class k in hit i.  Every class with a positive weight gives the hit one
+ * training row of that class and weight; a hit whose weights are all zero is
+ * dropped with its beam (as label -1); the free samples of the other beams are
+ * one-hot free-class rows, exactly as for hard labels.  Negative or non-finite
+ * weights are input errors. */
+int oracle_map_insert_scan_soft(oracle_map *m, const float *xyz, const float *probs, int64_t n,
+                                const float *origin, float free_step, int32_t free_class)
+{
+    if (!m || n < 0 || (n > 0 && (!xyz || !probs)) || !origin) return OR_E_ARG;
+    if (free_class < 0 || free_class >= m->K) return OR_E_ARG;
+    const int32_t K = m->K;
+    int32_t *keep = (int32_t *)malloc(sizeof(int32_t) * (size_t)(n > 0 ? n : 1));
+    if (!keep) return OR_E_OOM;
+    int64_t nrows = 0;
+    for (int64_t i = 0; i < n; ++i) {
+        int any = 0;
+        for (int32_t k = 0; k < K; ++k) {
+            const float p = probs[i * K + k];
+            if (!(isfinite(p) && p >= 0.0f)) { free(keep); return OR_E_INPUT; }
+            if (p > 0.0f) { any = 1; ++nrows; }
+        }
+        keep[i] = any ? 0 : -1;   /* any class index marks a kept beam */
+    }
+    int64_t nf = 0;
+    int rc = oracle_free_counts(xyz, keep, n, origin, free_step, K, NULL, &nf);
+    if (rc) { free(keep); return rc; }
+    const int64_t nt = nrows + nf;
+    float *tx = (float *)malloc(sizeof(float) * 3 * (size_t)(nt > 0 ? nt : 1));
+    int32_t *ty = (int32_t *)malloc(sizeof(int32_t) * (size_t)(nt > 0 ? nt : 1));
+    double *tw = (double *)malloc(sizeof(double) * (size_t)(nt > 0 ? nt : 1));
+    if (!tx || !ty || !tw) { free(keep); free(tx); free(ty); free(tw); return OR_E_OOM; }
+    int64_t r = 0;
+    for (int64_t i = 0; i < n; ++i)
+        for (int32_t k = 0; k < K; ++k) {
+            const float p = probs[i * K + k];
+            if (!(p > 0.0f)) continue;
+            memcpy(tx + 3 * r, xyz + 3 * i, 3 * sizeof(float));
+            ty[r] = k;
+            tw[r] = (double)p;
+            ++r;
+        }
+    rc = oracle_free_samples(xyz, keep, n, origin, free_step, K, tx + 3 * r, NULL);
+    for (int64_t j = 0; j < nf; ++j) { ty[r + j] = free_class; tw[r + j] = 1.0; }
+    if (!rc) rc = insert_rows(m, tx, ty, tw, nt);
+    free(keep); free(tx); free(ty); free(tw);
+    return rc;
+}
+
 int oracle_map_insert_scan(oracle_map *m, const float *xyz, const int32_t *label, int64_t n,
                            const float *origin, float free_step, int32_t free_class)
 {
