@@ -68,7 +68,12 @@ def lib():
         L.oracle_alpha_at_voxels.argtypes = [f32p, i32p, C.c_int64, i32p, C.c_int64, C.c_float,
                                              C.c_int32, C.c_float, C.c_float, C.c_float, f64p,
                                              i64p, i64p]
+        L.oracle_alpha_at_voxels_w.argtypes = [f32p, i32p, f64p, C.c_int64, i32p, C.c_int64,
+                                               C.c_float, C.c_int32, C.c_float, C.c_float,
+                                               C.c_float, f64p, i64p, i64p]
         L.oracle_voxel_centres.argtypes = [i32p, C.c_int64, C.c_float, f64p]
+        L.oracle_training_set_soft.argtypes = [f32p, f32p, C.c_int64, f32p, C.c_float, C.c_int32,
+                                               C.c_int32, i64p, f32p, i32p, f64p]
         L.oracle_training_set.argtypes = [f32p, i32p, C.c_int64, f32p, C.c_float, C.c_int32,
                                           C.c_int32, i64p, f32p, i32p, i64p]
         L.oracle_map_create.restype = C.c_void_p
@@ -80,6 +85,10 @@ def lib():
                                              C.c_int32]
         L.oracle_map_insert_scan_soft.argtypes = [C.c_void_p, f32p, f32p, C.c_int64, f32p,
                                                   C.c_float, C.c_int32]
+        L.oracle_map_set_class_params.argtypes = [C.c_void_p, f32p, f32p]
+        L.oracle_loss_classes.argtypes = [f64p, i32p, C.c_int64, f64p, i32p, C.c_int64, C.c_int32,
+                                          f64p, f64p, C.c_double, f64p, f64p, f64p, f64p, f64p,
+                                          f64p]
         L.oracle_map_size.restype = C.c_int64
         L.oracle_map_size.argtypes = [C.c_void_p]
         L.oracle_map_export.argtypes = [C.c_void_p, i32p, f64p, i64p, i64p]
@@ -168,6 +177,29 @@ def training_set(xyz, label, origin, free_step, K, free_class=0):
     return tx, ty, par
 
 
+def training_set_soft(xyz, probs, origin, free_step, K, free_class=0):
+    """Rows of one scan of soft measurements: (xyz, class, weight) -- one row per
+    positive class weight of each hit, then the free samples (weight 1)."""
+    xyz = _f32x3(xyz)
+    probs = np.ascontiguousarray(probs, dtype=np.float32)
+    if probs.shape != (xyz.shape[0], K):
+        raise ValueError(f"probs must have shape [n, {K}]")
+    o = np.ascontiguousarray(origin, dtype=np.float32).reshape(3)
+    n_out = np.zeros(1, dtype=np.int64)
+    L = lib()
+    args = (_p(xyz, C.c_float), _p(probs, C.c_float), xyz.shape[0], _p(o, C.c_float),
+            C.c_float(free_step), K, free_class)
+    _chk(L.oracle_training_set_soft(*args, _p(n_out, C.c_int64), None, None, None),
+         "training_set_soft")
+    nt = int(n_out[0])
+    tx = np.zeros((nt, 3), dtype=np.float32)
+    ty = np.zeros(nt, dtype=np.int32)
+    tw = np.zeros(nt, dtype=np.float64)
+    _chk(L.oracle_training_set_soft(*args, _p(n_out, C.c_int64), _p(tx, C.c_float),
+                                    _p(ty, C.c_int32), _p(tw, C.c_double)), "training_set_soft")
+    return tx, ty, tw
+
+
 def voxel_coords(xyz, res):
     xyz = _f32x3(xyz)
     out = np.zeros((xyz.shape[0], 3), dtype=np.int32)
@@ -206,18 +238,28 @@ def alpha_at(train_xyz, train_label, query_xyz, K, l, sigma0, alpha0):
     return a, nin, nb
 
 
-def alpha_at_voxels(train_xyz, train_label, ijk, res, K, l, sigma0, alpha0):
-    """Eq. (7) at the centroids of voxels ijk: (alpha [Q,K], n_in [Q], n_band [Q])."""
+def alpha_at_voxels(train_xyz, train_label, ijk, res, K, l, sigma0, alpha0, weights=None):
+    """Eq. (7) at the centroids of voxels ijk: (alpha [Q,K], n_in [Q], n_band [Q]).
+    weights (float64 per row, optional): each row's kernel value is scaled by its
+    weight (soft measurements)."""
     tx, ty = _f32x3(train_xyz), _i32(train_label)
     v = np.ascontiguousarray(ijk, dtype=np.int32).reshape(-1, 3)
     nq = v.shape[0]
     a = np.zeros((nq, K), dtype=np.float64)
     nin = np.zeros(nq, dtype=np.int64)
     nb = np.zeros(nq, dtype=np.int64)
-    _chk(lib().oracle_alpha_at_voxels(_p(tx, C.c_float), _p(ty, C.c_int32), tx.shape[0],
-                                      _p(v, C.c_int32), nq, C.c_float(res), K, C.c_float(l),
-                                      C.c_float(sigma0), C.c_float(alpha0), _p(a, C.c_double),
-                                      _p(nin, C.c_int64), _p(nb, C.c_int64)), "alpha_at_voxels")
+    tail = (_p(v, C.c_int32), nq, C.c_float(res), K, C.c_float(l), C.c_float(sigma0),
+            C.c_float(alpha0), _p(a, C.c_double), _p(nin, C.c_int64), _p(nb, C.c_int64))
+    if weights is None:
+        _chk(lib().oracle_alpha_at_voxels(_p(tx, C.c_float), _p(ty, C.c_int32), tx.shape[0],
+                                          *tail), "alpha_at_voxels")
+    else:
+        w = np.ascontiguousarray(weights, dtype=np.float64).reshape(-1)
+        if w.shape[0] != tx.shape[0]:
+            raise ValueError("weights must hold one value per training row")
+        _chk(lib().oracle_alpha_at_voxels_w(_p(tx, C.c_float), _p(ty, C.c_int32),
+                                            _p(w, C.c_double), tx.shape[0], *tail),
+             "alpha_at_voxels_w")
     return a, nin, nb
 
 
@@ -258,6 +300,15 @@ class OracleMap:
         _chk(lib().oracle_map_insert_scan(self._h, _p(xyz, C.c_float), _p(label, C.c_int32),
                                           xyz.shape[0], _p(o, C.c_float), C.c_float(free_step),
                                           free_class), "map_insert_scan")
+
+    def set_class_params(self, l, sigma0):
+        """Per-class kernels (float32 [K] each): rows of class k use l[k], sigma0[k]."""
+        lk = np.ascontiguousarray(l, dtype=np.float32).reshape(-1)
+        sk = np.ascontiguousarray(sigma0, dtype=np.float32).reshape(-1)
+        if lk.shape[0] != self.K or sk.shape[0] != self.K:
+            raise ValueError(f"l and sigma0 must hold {self.K} values")
+        _chk(lib().oracle_map_set_class_params(self._h, _p(lk, C.c_float), _p(sk, C.c_float)),
+             "map_set_class_params")
 
     def insert_scan_soft(self, xyz, probs, origin, free_step, free_class=0):
         """One scan of soft measurements: probs[i] holds non-negative class
@@ -331,3 +382,32 @@ def loss(train_xyz, train_label, query_xyz, query_label, K, l, sigma0, alpha0):
                            _p(gs, C.c_double), _p(gt, C.c_double), _p(gq, C.c_double)), "loss")
     return {"loss": float(out[0]), "alpha_q": aq, "grad_l": float(gl[0]),
             "grad_sigma0": float(gs[0]), "grad_train": gt, "grad_query": gq}
+
+
+def loss_classes(train_xyz, train_label, query_xyz, query_label, K, l, sigma0, alpha0):
+    """Predictive loss with per-class kernels (l, sigma0: [K]) and its gradient.
+
+    Returns dict(loss, alpha_q [H,K], grad_l [K], grad_sigma0 [K], grad_train [N,3],
+    grad_query [H,3])."""
+    tx = np.ascontiguousarray(train_xyz, dtype=np.float64).reshape(-1, 3)
+    ty = _i32(train_label)
+    qx = np.ascontiguousarray(query_xyz, dtype=np.float64).reshape(-1, 3)
+    qy = _i32(query_label)
+    lk = np.ascontiguousarray(l, dtype=np.float64).reshape(-1)
+    sk = np.ascontiguousarray(sigma0, dtype=np.float64).reshape(-1)
+    if lk.shape[0] != K or sk.shape[0] != K:
+        raise ValueError(f"l and sigma0 must hold {K} values")
+    H, N = qx.shape[0], tx.shape[0]
+    out = np.zeros(1)
+    aq = np.zeros((H, K))
+    gl = np.zeros(K)
+    gs = np.zeros(K)
+    gt = np.zeros((N, 3))
+    gq = np.zeros((H, 3))
+    _chk(lib().oracle_loss_classes(_p(tx, C.c_double), _p(ty, C.c_int32), N, _p(qx, C.c_double),
+                                   _p(qy, C.c_int32), H, K, _p(lk, C.c_double),
+                                   _p(sk, C.c_double), float(alpha0), _p(out, C.c_double),
+                                   _p(aq, C.c_double), _p(gl, C.c_double), _p(gs, C.c_double),
+                                   _p(gt, C.c_double), _p(gq, C.c_double)), "loss_classes")
+    return {"loss": float(out[0]), "alpha_q": aq, "grad_l": gl, "grad_sigma0": gs,
+            "grad_train": gt, "grad_query": gq}

@@ -56,6 +56,9 @@
  *       only when every alpha^k > 1 (NaN otherwise); occupancy probability =
  *       1 - mean of the free class (the sum over the occupied classes).
  *   R12 the recursive update is plain addition.
+ *   R23 per-class kernel parameters (Sec. V-D and VI): rows of class k use
+ *       their own l_k and sigma0_k, alpha^k = alpha0 + sum_{y_t = k} sigma0_k
+ *       f(d / l_k); the loss takes the gradient per class.
  *   R22 soft measurements (Sec. VI): a hit carries a vector of non-negative
  *       class weights instead of one label and adds each class's weight
  *       times the kernel (the linear-pooling form); weights are used as given,
@@ -265,13 +268,17 @@ int oracle_pack_keys(const int32_t *ijk, int64_t n, uint64_t *keys)
  * with |d^2/l^2 - 1| <= 1e-5 (pairs whose in/out status can flip between a
  * binary32 and a double evaluation; their weight is below 1e-25 sigma0).
  * Every query sums its terms in training-point order. */
-int oracle_alpha_at(const float *train_xyz, const int32_t *train_label, int64_t n_train,
-                    const double *query_xyz, int64_t n_query, int32_t K, float l, float sigma0,
-                    float alpha0, double *alpha, int64_t *n_in, int64_t *n_band)
+/* Gather form of Eq. (7) with row weights w (NULL: every row weighs 1). */
+static int alpha_at_impl(const float *train_xyz, const int32_t *train_label, const double *w,
+                         int64_t n_train, const double *query_xyz, int64_t n_query, int32_t K,
+                         float l, float sigma0, float alpha0, double *alpha, int64_t *n_in,
+                         int64_t *n_band)
 {
     if (n_train < 0 || n_query < 0 || K < 1 || !(l > 0) || !alpha) return OR_E_ARG;
-    for (int64_t t = 0; t < n_train; ++t)
+    for (int64_t t = 0; t < n_train; ++t) {
         if (train_label[t] < 0 || train_label[t] >= K) return OR_E_INPUT;
+        if (w && !(isfinite(w[t]) && w[t] >= 0.0)) return OR_E_INPUT;
+    }
     const double L = l, S0 = sigma0, A0 = alpha0, L2 = L * L;
 #pragma omp parallel for schedule(dynamic, 16)
     for (int64_t q = 0; q < n_query; ++q) {
@@ -287,13 +294,21 @@ int oracle_alpha_at(const float *train_xyz, const int32_t *train_label, int64_t 
             if (fabs(d2 / L2 - 1.0) <= 1e-5) ++cband;
             if (!(d2 < L2)) continue;
             double d = sqrt(d2);
-            a[train_label[t]] += S0 * oracle_kernel_f(d / L);
+            a[train_label[t]] += (w ? w[t] : 1.0) * (S0 * oracle_kernel_f(d / L));
             ++cin;
         }
         if (n_in) n_in[q] = cin;
         if (n_band) n_band[q] = cband;
     }
     return OR_OK;
+}
+
+int oracle_alpha_at(const float *train_xyz, const int32_t *train_label, int64_t n_train,
+                    const double *query_xyz, int64_t n_query, int32_t K, float l, float sigma0,
+                    float alpha0, double *alpha, int64_t *n_in, int64_t *n_band)
+{
+    return alpha_at_impl(train_xyz, train_label, NULL, n_train, query_xyz, n_query, K, l, sigma0,
+                         alpha0, alpha, n_in, n_band);
 }
 
 /* Voxel centres ((i+1/2) res, ...) in double from the binary32 res (R6). */
@@ -316,6 +331,21 @@ int oracle_alpha_at_voxels(const float *train_xyz, const int32_t *train_label, i
     oracle_voxel_centres(ijk, n_query, res, c);
     int rc = oracle_alpha_at(train_xyz, train_label, n_train, c, n_query, K, l, sigma0, alpha0,
                              alpha, n_in, n_band);
+    free(c);
+    return rc;
+}
+
+/* The same with row weights (soft measurements, reading R22). */
+int oracle_alpha_at_voxels_w(const float *train_xyz, const int32_t *train_label,
+                             const double *train_w, int64_t n_train, const int32_t *ijk,
+                             int64_t n_query, float res, int32_t K, float l, float sigma0,
+                             float alpha0, double *alpha, int64_t *n_in, int64_t *n_band)
+{
+    double *c = (double *)malloc(sizeof(double) * 3 * (size_t)(n_query > 0 ? n_query : 1));
+    if (!c) return OR_E_OOM;
+    oracle_voxel_centres(ijk, n_query, res, c);
+    int rc = alpha_at_impl(train_xyz, train_label, train_w, n_train, c, n_query, K, l, sigma0,
+                           alpha0, alpha, n_in, n_band);
     free(c);
     return rc;
 }
@@ -385,6 +415,8 @@ typedef struct oracle_map {
     int face_blocks; /* 1: a voxel's training rows are those in its block and the six
                         face-adjacent blocks (the extended block of Sec. IV's
                         implementation notes), 0: every row (exact Eq. 7) */
+    double *lk, *s0k; /* [K] length-scale and scale of each class's kernel (reading R23);
+                         all equal to l and sigma0 unless set per class */
 } oracle_map;
 
 /* floor(a / b) for b > 0 */
@@ -422,14 +454,31 @@ oracle_map *oracle_map_create(int32_t K, float res, int32_t block_size, float l,
     m->alpha = (double *)malloc(sizeof(double) * m->rows * K);
     m->nv = (int64_t *)malloc(sizeof(int64_t) * m->rows);
     m->nband = (int64_t *)malloc(sizeof(int64_t) * m->rows);
-    if (!m->tab || !m->keys || !m->alpha || !m->nv || !m->nband) return NULL;
+    m->lk = (double *)malloc(sizeof(double) * K);
+    m->s0k = (double *)malloc(sizeof(double) * K);
+    if (!m->tab || !m->keys || !m->alpha || !m->nv || !m->nband || !m->lk || !m->s0k) return NULL;
+    for (int32_t k = 0; k < K; ++k) { m->lk[k] = m->l; m->s0k[k] = m->sigma0; }
     return m;
+}
+
+/* Per-class kernel parameters (reading R23): rows of class k use length-scale
+ * l[k] and scale sigma0[k] (binary32 inputs, promoted exactly), each finite and
+ * positive.  Applies to later inserts. */
+int oracle_map_set_class_params(oracle_map *m, const float *l, const float *sigma0)
+{
+    if (!m || !l || !sigma0) return OR_E_ARG;
+    for (int32_t k = 0; k < m->K; ++k)
+        if (!(isfinite(l[k]) && l[k] > 0.0f && isfinite(sigma0[k]) && sigma0[k] > 0.0f))
+            return OR_E_ARG;
+    for (int32_t k = 0; k < m->K; ++k) { m->lk[k] = l[k]; m->s0k[k] = sigma0[k]; }
+    return OR_OK;
 }
 
 void oracle_map_destroy(oracle_map *m)
 {
     if (!m) return;
     free(m->tab); free(m->keys); free(m->alpha); free(m->nv); free(m->nband);
+    free(m->lk); free(m->s0k);
     free(m);
 }
 
@@ -501,10 +550,12 @@ static int insert_rows(oracle_map *m, const float *xyz, const int32_t *label, co
         if (!finite3(xyz + 3 * t)) return OR_E_INPUT;
         if (w && !(isfinite(w[t]) && w[t] >= 0.0)) return OR_E_INPUT;
     }
-    const double res = m->res, L = m->l, L2 = L * L;
+    const double res = m->res;
     for (int64_t t = 0; t < n; ++t) {
         const float *p = xyz + 3 * t;
         const double wt = w ? w[t] : 1.0;
+        /* the kernel of the row's class */
+        const double L = m->lk[label[t]], L2 = L * L, S0 = m->s0k[label[t]];
         if (m->scsm) {
             /* Eq. (2): the measurement counts in the cell it falls into. */
             int32_t v[3];
@@ -550,7 +601,7 @@ static int insert_rows(oracle_map *m, const float *xyz, const int32_t *label, co
                     if (r < 0) return OR_E_OOM;
                     if (band) m->nband[r] += 1;
                     if (!(d2 < L2)) continue;
-                    m->alpha[r * m->K + label[t]] += wt * (m->sigma0 * oracle_kernel_f(sqrt(d2) / L));
+                    m->alpha[r * m->K + label[t]] += wt * (S0 * oracle_kernel_f(sqrt(d2) / L));
                     m->nv[r] += 1;
                 }
             }
@@ -565,19 +616,20 @@ int oracle_map_insert_training(oracle_map *m, const float *xyz, const int32_t *l
     return insert_rows(m, xyz, label, NULL, n);
 }
 
-/* One scan of soft measurements (reading R22): probs[i][k] >= 0 is the weight
- * of class k in hit i.  Every class with a positive weight gives the hit one
- * training row of that class and weight; a hit whose weights are all zero is
- * dropped with its beam (as label -1); the free samples of the other beams are
- * one-hot free-class rows, exactly as for hard labels.  Negative or non-finite
- * weights are input errors. */
-int oracle_map_insert_scan_soft(oracle_map *m, const float *xyz, const float *probs, int64_t n,
-                                const float *origin, float free_step, int32_t free_class)
+/* Training rows of one scan of soft measurements (reading R22): probs[i][k]
+ * >= 0 is the weight of class k in hit i.  Every class with a positive weight
+ * gives the hit one row of that class and weight (hits in input order, classes
+ * ascending); a hit whose weights are all zero is dropped with its beam (as
+ * label -1); then the free samples of the kept beams, free-class rows of
+ * weight 1.  Negative or non-finite weights are input errors.  Two calls: with
+ * out_xyz == NULL only *n_out is set. */
+int oracle_training_set_soft(const float *xyz, const float *probs, int64_t n, const float *origin,
+                             float free_step, int32_t K, int32_t free_class, int64_t *n_out,
+                             float *out_xyz, int32_t *out_label, double *out_w)
 {
-    if (!m || n < 0 || (n > 0 && (!xyz || !probs)) || !origin) return OR_E_ARG;
-    if (free_class < 0 || free_class >= m->K) return OR_E_ARG;
-    const int32_t K = m->K;
-    int32_t *keep = (int32_t *)malloc(sizeof(int32_t) * (size_t)(n > 0 ? n : 1));
+    if (n < 0 || !n_out || K < 1 || free_class < 0 || free_class >= K) return OR_E_ARG;
+    if (n > 0 && (!xyz || !probs)) return OR_E_ARG;
+    int32_t *keep = (int32_t *)calloc((size_t)(n > 0 ? n : 1), sizeof(int32_t));
     if (!keep) return OR_E_OOM;
     int64_t nrows = 0;
     for (int64_t i = 0; i < n; ++i) {
@@ -591,26 +643,46 @@ int oracle_map_insert_scan_soft(oracle_map *m, const float *xyz, const float *pr
     }
     int64_t nf = 0;
     int rc = oracle_free_counts(xyz, keep, n, origin, free_step, K, NULL, &nf);
-    if (rc) { free(keep); return rc; }
-    const int64_t nt = nrows + nf;
-    float *tx = (float *)malloc(sizeof(float) * 3 * (size_t)(nt > 0 ? nt : 1));
-    int32_t *ty = (int32_t *)malloc(sizeof(int32_t) * (size_t)(nt > 0 ? nt : 1));
-    double *tw = (double *)malloc(sizeof(double) * (size_t)(nt > 0 ? nt : 1));
-    if (!tx || !ty || !tw) { free(keep); free(tx); free(ty); free(tw); return OR_E_OOM; }
+    if (rc || !out_xyz) {
+        *n_out = nrows + nf;
+        free(keep);
+        return rc;
+    }
     int64_t r = 0;
     for (int64_t i = 0; i < n; ++i)
         for (int32_t k = 0; k < K; ++k) {
             const float p = probs[i * K + k];
             if (!(p > 0.0f)) continue;
-            memcpy(tx + 3 * r, xyz + 3 * i, 3 * sizeof(float));
-            ty[r] = k;
-            tw[r] = (double)p;
+            memcpy(out_xyz + 3 * r, xyz + 3 * i, 3 * sizeof(float));
+            out_label[r] = k;
+            out_w[r] = (double)p;
             ++r;
         }
-    rc = oracle_free_samples(xyz, keep, n, origin, free_step, K, tx + 3 * r, NULL);
-    for (int64_t j = 0; j < nf; ++j) { ty[r + j] = free_class; tw[r + j] = 1.0; }
+    rc = oracle_free_samples(xyz, keep, n, origin, free_step, K, out_xyz + 3 * r, NULL);
+    for (int64_t j = 0; j < nf; ++j) { out_label[r + j] = free_class; out_w[r + j] = 1.0; }
+    *n_out = nrows + nf;
+    free(keep);
+    return rc;
+}
+
+/* One scan of soft measurements: the rows above, inserted with their weights. */
+int oracle_map_insert_scan_soft(oracle_map *m, const float *xyz, const float *probs, int64_t n,
+                                const float *origin, float free_step, int32_t free_class)
+{
+    if (!m || n < 0 || (n > 0 && (!xyz || !probs)) || !origin) return OR_E_ARG;
+    if (free_class < 0 || free_class >= m->K) return OR_E_ARG;
+    int64_t nt = 0;
+    int rc = oracle_training_set_soft(xyz, probs, n, origin, free_step, m->K, free_class, &nt,
+                                      NULL, NULL, NULL);
+    if (rc) return rc;
+    float *tx = (float *)malloc(sizeof(float) * 3 * (size_t)(nt > 0 ? nt : 1));
+    int32_t *ty = (int32_t *)malloc(sizeof(int32_t) * (size_t)(nt > 0 ? nt : 1));
+    double *tw = (double *)malloc(sizeof(double) * (size_t)(nt > 0 ? nt : 1));
+    if (!tx || !ty || !tw) { free(tx); free(ty); free(tw); return OR_E_OOM; }
+    rc = oracle_training_set_soft(xyz, probs, n, origin, free_step, m->K, free_class, &nt, tx, ty,
+                                  tw);
     if (!rc) rc = insert_rows(m, tx, ty, tw, nt);
-    free(keep); free(tx); free(ty); free(tw);
+    free(tx); free(ty); free(tw);
     return rc;
 }
 
@@ -778,6 +850,82 @@ int oracle_loss(const double *train_xyz, const int32_t *train_label, int64_t n_t
     }
     if (grad_l) *grad_l = gl;
     if (grad_sigma0) *grad_sigma0 = gs;
+    if (!alpha_q) free(A);
+    free(G);
+    return OR_OK;
+}
+
+/* The predictive loss with per-class kernel parameters (reading R23):
+ * alpha_q[h][k] = alpha0 + sum_{t: y_t = k} sigma0[k] f(|x_t - x_h| / l[k]),
+ * loss = -(1/H) sum_h log(alpha_q[h][y_h] / S_h), and its gradient with respect
+ * to every l[k], sigma0[k] and coordinate, all pairs, double throughout. */
+int oracle_loss_classes(const double *train_xyz, const int32_t *train_label, int64_t n_train,
+                        const double *query_xyz, const int32_t *query_label, int64_t n_query,
+                        int32_t K, const double *l, const double *sigma0, double alpha0,
+                        double *loss, double *alpha_q, double *grad_l, double *grad_sigma0,
+                        double *grad_train, double *grad_query)
+{
+    if (n_train < 0 || n_query <= 0 || K < 1 || !l || !sigma0) return OR_E_ARG;
+    for (int32_t k = 0; k < K; ++k)
+        if (!(l[k] > 0) || !(sigma0[k] > 0)) return OR_E_ARG;
+    for (int64_t t = 0; t < n_train; ++t)
+        if (train_label[t] < 0 || train_label[t] >= K) return OR_E_INPUT;
+    for (int64_t h = 0; h < n_query; ++h)
+        if (query_label[h] < 0 || query_label[h] >= K) return OR_E_INPUT;
+    double *A = alpha_q ? alpha_q : (double *)malloc(sizeof(double) * n_query * K);
+    double *G = (double *)malloc(sizeof(double) * n_query * K);
+    if (!A || !G) { if (!alpha_q) free(A); free(G); return OR_E_OOM; }
+    const double H = (double)n_query;
+    double tot = 0.0;
+    for (int64_t h = 0; h < n_query; ++h) {
+        double *a = A + h * K;
+        for (int k = 0; k < K; ++k) a[k] = alpha0;
+        for (int64_t t = 0; t < n_train; ++t) {
+            const int32_t y = train_label[t];
+            double dx = train_xyz[3 * t] - query_xyz[3 * h];
+            double dy = train_xyz[3 * t + 1] - query_xyz[3 * h + 1];
+            double dz = train_xyz[3 * t + 2] - query_xyz[3 * h + 2];
+            double d2 = dx * dx + dy * dy + dz * dz;
+            if (!(d2 < l[y] * l[y])) continue;
+            a[y] += sigma0[y] * oracle_kernel_f(sqrt(d2) / l[y]);
+        }
+        double S = 0.0;
+        for (int k = 0; k < K; ++k) S += a[k];
+        tot += -log(a[query_label[h]] / S);
+        for (int k = 0; k < K; ++k)
+            G[h * K + k] = -((k == query_label[h] ? 1.0 / a[k] : 0.0) - 1.0 / S) / H;
+    }
+    if (loss) *loss = tot / H;
+    if (grad_l) memset(grad_l, 0, sizeof(double) * K);
+    if (grad_sigma0) memset(grad_sigma0, 0, sizeof(double) * K);
+    if (grad_train) memset(grad_train, 0, sizeof(double) * 3 * n_train);
+    if (grad_query) memset(grad_query, 0, sizeof(double) * 3 * n_query);
+    for (int64_t h = 0; h < n_query; ++h) {
+        for (int64_t t = 0; t < n_train; ++t) {
+            const int32_t y = train_label[t];
+            const double L = l[y], S0 = sigma0[y];
+            double dx = train_xyz[3 * t] - query_xyz[3 * h];
+            double dy = train_xyz[3 * t + 1] - query_xyz[3 * h + 1];
+            double dz = train_xyz[3 * t + 2] - query_xyz[3 * h + 2];
+            double d2 = dx * dx + dy * dy + dz * dz;
+            if (!(d2 < L * L)) continue;
+            double r = sqrt(d2) / L;
+            double g = G[h * K + y];
+            if (grad_sigma0) grad_sigma0[y] += g * oracle_kernel_f(r);
+            if (grad_l) grad_l[y] += g * S0 * oracle_kernel_df(r) * (-r / L);
+            double c = g * S0 * oracle_kernel_df_over_r(r) / (L * L);
+            if (grad_train) {
+                grad_train[3 * t] += c * dx;
+                grad_train[3 * t + 1] += c * dy;
+                grad_train[3 * t + 2] += c * dz;
+            }
+            if (grad_query) {
+                grad_query[3 * h] -= c * dx;
+                grad_query[3 * h + 1] -= c * dy;
+                grad_query[3 * h + 2] -= c * dz;
+            }
+        }
+    }
     if (!alpha_q) free(A);
     free(G);
     return OR_OK;

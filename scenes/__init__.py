@@ -526,6 +526,30 @@ def random_points_scene(seed: int, n: int, K: int = 4, extent: float = 1.0,
     return Scene("random", params, [Scan(xyz, lab, _f32(origin))], info={"seed": seed})
 
 
+def soft_measurements(label, K, seed=0, top=3, peak=3.0, dropped=0.02):
+    """Pseudo-probability vectors shaped like a semantic classifier's output, one
+    per hit: softmax of N(0, 1) logits with +peak on the hit's label, truncated
+    to its `top` largest entries (the rest 0, not renormalised), float32.  Hits
+    with label -1 and a `dropped` fraction of the others get all-zero rows.
+    Seeded; the free class (0) is never a measured class."""
+    rng = np.random.default_rng(seed)
+    lab = np.asarray(label)
+    n = lab.shape[0]
+    z = rng.standard_normal((n, K))
+    z[:, 0] = -np.inf                                   # a hit never measures free space
+    ok = lab >= 0
+    z[np.nonzero(ok)[0], lab[ok]] += peak
+    z -= z.max(axis=1, keepdims=True)
+    e = np.exp(z)
+    pr = e / e.sum(axis=1, keepdims=True)
+    if top < K:
+        cut = np.sort(pr, axis=1)[:, K - top][:, None]
+        pr = np.where(pr >= cut, pr, 0.0)
+    pr[~ok] = 0.0
+    pr[rng.random(n) < dropped] = 0.0
+    return pr.astype(np.float32)
+
+
 CONFIG_NAMES = ["tiny", "lidar", "stereo", "batched", "differentiable"]
 
 

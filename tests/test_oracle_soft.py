@@ -103,3 +103,42 @@ def test_negative_or_non_finite_weights_are_input_errors(bad):
     with pytest.raises(oracle.OracleError):
         m.insert_scan_soft(xyz, probs, (0.0, 0.0, 1.0), 0.3)
     assert len(m) == 0
+
+
+def test_weighted_gather_form_matches_brute_force_and_the_soft_map():
+    # The gather form with row weights against an all-pairs numpy evaluation
+    # (independent of the C code, f from the oracle), and against the map's soft
+    # insert of the same scan (scatter form) on a tiny scene.
+    sc = scenes.make_config(0)
+    p = sc.params.f32()
+    s = sc.scans[0]
+    sel = slice(0, 150)
+    probs = scenes.soft_measurements(s.label[sel], p.K, seed=2)
+    tx, ty, tw = oracle.training_set_soft(s.xyz[sel], probs, s.origin, p.free_step, p.K,
+                                          p.free_class)
+    # the rows: one per positive weight, in (hit, class) order, then weight-1 free rows
+    nz = np.nonzero(probs > 0)
+    nh = nz[0].shape[0]
+    np.testing.assert_array_equal(ty[:nh], nz[1])
+    np.testing.assert_array_equal(tw[:nh], probs[nz].astype(np.float64))
+    np.testing.assert_array_equal(tx[:nh], s.xyz[sel][nz[0]])
+    assert np.all(ty[nh:] == p.free_class) and np.all(tw[nh:] == 1.0)
+    kept = probs.sum(1) > 0
+    fx, _ = oracle.free_samples(s.xyz[sel], np.where(kept, 1, -1).astype(np.int32), s.origin,
+                                p.free_step, p.K)
+    np.testing.assert_array_equal(tx[nh:], fx)
+    m = oracle.OracleMap.from_params(p)
+    m.insert_scan_soft(s.xyz[sel], probs, s.origin, p.free_step, p.free_class)
+    ijk, a_map, _, _ = m.export()
+    rng = np.random.default_rng(0)
+    q = ijk[rng.choice(ijk.shape[0], 300, replace=False)]
+    a_g, _, _ = oracle.alpha_at_voxels(tx, ty, q, p.res, p.K, p.l, p.sigma0, p.alpha0, weights=tw)
+    np.testing.assert_allclose(a_g, m.lookup(q), rtol=1e-12)
+    c = (q.astype(np.float64) + 0.5) * np.float64(p.res)
+    d = np.linalg.norm(c[:, None, :] - tx.astype(np.float64)[None, :, :], axis=2)
+    L = np.float64(p.l)
+    kv = np.where(d < L, np.float64(p.sigma0) * oracle.kernel_f(np.minimum(d / L, 1.0)), 0.0)
+    a_bf = np.full((q.shape[0], p.K), np.float64(p.alpha0))
+    for k in range(p.K):
+        a_bf[:, k] += (kv[:, ty == k] * tw[ty == k][None, :]).sum(1)
+    np.testing.assert_allclose(a_g, a_bf, rtol=1e-12)
