@@ -47,6 +47,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true", help="skip the differentiable-form line")
+    ap.add_argument("--no-variants", action="store_true",
+                    help="skip the S-CSM, extended-block and soft-measurement lines")
     ap.add_argument("--cpu-sample-stride", type=int, default=2)
     ap.add_argument("--no-batched", action="store_true", help="skip the 64-scan batched line")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
@@ -152,8 +154,11 @@ def main():
     }
 
     out["roofline"]["traffic"] = splat_traffic()
-    out["scsm"] = bench_scsm(torch, m, xyz, lab, vox, s, p, SemanticMap, args.steps)
-    out["face_blocks"] = bench_face_blocks(torch, m, xyz, lab, vox, s, p, SemanticMap, args.steps)
+    if not args.no_variants:
+        out["scsm"] = bench_scsm(torch, m, xyz, lab, vox, s, p, SemanticMap, args.steps)
+        out["face_blocks"] = bench_face_blocks(torch, m, xyz, lab, vox, s, p, SemanticMap,
+                                               args.steps)
+        out["soft"] = bench_soft(torch, xyz, vox, s, p, SemanticMap, args.steps)
     if not args.no_extras:
         out["fwd_bwd"] = bench_loss(torch, dev, predictive_loss)
     if not args.no_batched:
@@ -236,6 +241,34 @@ def bench_scsm(torch, m_bki, xyz, lab, vox, s, p, SemanticMap, steps):
     return {"model": "S-CSM (Eq. 2)", "ms_per_step": ms, "voxels_updated": st["n_updated_voxels"],
             "voxel_updates_per_s": st["n_updated_voxels"] / (ms * 1e-3),
             "points_per_s": st["n_hits"] / (ms * 1e-3)}
+
+
+def bench_soft(torch, xyz, vox, s, p, SemanticMap, steps):
+    """Soft measurements (Sec. VI) on the same scan: every hit carries a
+    classifier-like weight vector truncated to its 3 largest classes."""
+    import scenes
+    probs = torch.from_numpy(scenes.soft_measurements(s.label, p.K, seed=1, top=3)).to(xyz.device)
+    m = SemanticMap.from_params(p, initial_blocks=1 << 15)
+
+    def step():
+        m.reset()
+        m.insert_scan_soft(xyz, probs, s.origin, p.free_step)
+        return m.query(vox, alpha=False, var=False, mean=True, label=True, p_occ=True)
+
+    for _ in range(3):
+        step()
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    for _ in range(steps):
+        step()
+    torch.cuda.synchronize()
+    ms = 1e3 * (time.perf_counter() - t) / steps
+    st = m.stats()
+    return {"measurements": "soft, top-3 class weights per hit", "ms_per_step": ms,
+            "hit_rows": st["n_hits"], "voxels_updated": st["n_updated_voxels"],
+            "voxel_updates_per_s": st["n_updated_voxels"] / (ms * 1e-3),
+            "pairs_in_support": st["n_pairs"], "splat_ms": st["splat_ms"],
+            "merge_ms": st["merge_ms"]}
 
 
 def bench_face_blocks(torch, m_exact, xyz, lab, vox, s, p, SemanticMap, steps):

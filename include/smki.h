@@ -70,7 +70,8 @@ typedef struct smki_options {
 
 /* Counters of the last insert (smki_last_scan_stats). */
 typedef struct smki_scan_stats {
-  int64_t n_hits;           /* labelled hits kept (label != -1) */
+  int64_t n_hits;           /* hit rows: labelled hits kept (label != -1); for soft
+                               measurements one per positive class weight */
   int64_t n_free;           /* free-space samples generated */
   int64_t n_point_blocks;   /* map blocks holding at least one training row */
   int64_t n_target_blocks;  /* blocks examined (within reach of a row block) */
@@ -109,6 +110,18 @@ smki_status smki_create_map(float res, int32_t block_size, float l, float sigma0
                             smki_map **out);
 smki_status smki_destroy_map(smki_map *m);
 
+/*
+ * Per-class kernels: rows of class k use length-scale l[k] and scale
+ * sigma0[k] in Eq. (7)-(8), alpha^k = alpha0 + sum_{y_t = k} sigma0[k]
+ * f(d / l[k]) (Sec. V-D and VI: the paper keeps both class-independent and
+ * names class-dependent values as the way to make them matter).  l and sigma0
+ * host float32 [K], each finite and > 0; they apply to later inserts (S-BKI
+ * only; the counting model has no kernel).  The stencil follows the largest
+ * l[k], so an insert returns SMKI_E_CAPACITY when max l[k] / res >= 4.5.
+ * Synchronises the map's stream.  Errors: SMKI_E_INVALID_ARG (map unchanged).
+ */
+smki_status smki_set_class_params(smki_map *m, const float *l, const float *sigma0);
+
 /* Stream (a hipStream_t, e.g. torch.cuda.current_stream().cuda_stream) on which
  * the map enqueues its work; NULL = the default stream. */
 smki_status smki_set_stream(smki_map *m, void *hip_stream);
@@ -131,6 +144,24 @@ smki_status smki_set_stream(smki_map *m, void *hip_stream);
  */
 smki_status smki_insert_scan(smki_map *m, const float *xyz, const int32_t *label, int64_t n,
                              const float *origin, float free_step);
+
+/*
+ * Insert one scan of soft measurements (Sec. VI: a classifier's pseudo-
+ * probability vector per hit instead of one label).  probs device float32
+ * [n][K], row i the class weights of hit i, each finite and >= 0.  Every
+ * class k with probs[i][k] > 0 adds probs[i][k] * sigma0 f(d / l) to its
+ * concentration at every voxel centroid within l (S-BKI), or probs[i][k] to
+ * the hit's own voxel (S-CSM) -- the linear-pooling form; the weights are
+ * used as given, without renormalisation, so a one-hot row is the
+ * smki_insert_scan update.  A row of zeros drops the hit and its beam (as
+ * label -1); the free-space samples of the other beams are free_class rows of
+ * weight 1.  xyz, origin, free_step and the errors are those of
+ * smki_insert_scan (a negative or non-finite weight: SMKI_E_BAD_INPUT), plus
+ * SMKI_E_CAPACITY when n * K > 2^30.  The scan statistics count one hit row
+ * per positive weight.
+ */
+smki_status smki_insert_scan_soft(smki_map *m, const float *xyz, const float *probs, int64_t n,
+                                  const float *origin, float free_step);
 
 /*
  * Insert S scans in one pass: rows offsets[s]..offsets[s+1]-1 of xyz/label
@@ -233,6 +264,33 @@ smki_status smki_loss_backward(const float *train_xyz, const int32_t *train_labe
                                void *workspace, size_t workspace_bytes, const float *alpha_q,
                                const float *grad_loss, float *grad_l, float *grad_sigma0,
                                float *grad_train_xyz, float *grad_query_xyz);
+
+/*
+ * The same loss with per-class kernels (the class-dependent l and sigma0 that
+ * Sec. V-D and VI point to):  alpha_q[h][k] = alpha0 + sum_{t: y_t = k}
+ * sigma0[k] f(|x_t - x_h| / l[k]).  l, sigma0 host float32 [K], each finite and
+ * > 0.  Other arguments as smki_loss_forward; the workspace size is
+ * smki_loss_workspace_bytes(n_train, n_query, K).
+ */
+smki_status smki_loss_forward_classes(const float *train_xyz, const int32_t *train_label,
+                                      int64_t n_train, const float *query_xyz,
+                                      const int32_t *query_label, int64_t n_query, const float *l,
+                                      const float *sigma0, float alpha0, int32_t K,
+                                      void *hip_stream, void *workspace, size_t workspace_bytes,
+                                      float *loss, float *alpha_q);
+/*
+ * Its gradient: grad_l and grad_sigma0 device float32 [K] (nullable) receive
+ * dloss/dl[k] and dloss/dsigma0[k]; coordinates as smki_loss_backward.  The
+ * per-class gradients are summed over queries in double, in a fixed order.
+ */
+smki_status smki_loss_backward_classes(const float *train_xyz, const int32_t *train_label,
+                                       int64_t n_train, const float *query_xyz,
+                                       const int32_t *query_label, int64_t n_query,
+                                       const float *l, const float *sigma0, float alpha0,
+                                       int32_t K, void *hip_stream, void *workspace,
+                                       size_t workspace_bytes, const float *alpha_q,
+                                       const float *grad_loss, float *grad_l, float *grad_sigma0,
+                                       float *grad_train_xyz, float *grad_query_xyz);
 
 #ifdef __cplusplus
 }

@@ -16,7 +16,8 @@ import torch
 from ._lib import MODELS, SELECTIONS, SmkiError, ScanStats, Options, check, lib
 
 __all__ = ["SemanticMap", "SmkiError", "free_samples", "bucket_cells", "loss_forward",
-           "loss_backward", "PredictiveLoss", "predictive_loss"]
+           "loss_backward", "PredictiveLoss", "predictive_loss", "loss_forward_classes",
+           "loss_backward_classes", "PredictiveLossClasses", "predictive_loss_classes"]
 
 
 def _ptr(t):
@@ -89,6 +90,26 @@ class SemanticMap:
         self._bind_stream()
         check(lib().smki_insert_scan(self._h, _ptr(xyz), _ptr(label), xyz.shape[0], _f3(origin),
                                      float(free_step)), "smki_insert_scan")
+
+    def set_class_params(self, l, sigma0):
+        """Per-class kernels: l, sigma0 sequences of K floats (see smki_set_class_params)."""
+        lk = [float(v) for v in l]
+        sk = [float(v) for v in sigma0]
+        if len(lk) != self.K or len(sk) != self.K:
+            raise ValueError(f"l and sigma0 must hold {self.K} values")
+        check(lib().smki_set_class_params(self._h, (C.c_float * self.K)(*lk),
+                                          (C.c_float * self.K)(*sk)), "smki_set_class_params")
+
+    def insert_scan_soft(self, xyz, probs, origin, free_step):
+        """One scan of soft measurements: probs [n, K] float32, the class weights
+        of each hit (Sec. VI); see smki_insert_scan_soft."""
+        xyz = _dev_tensor(xyz, torch.float32, (3,), "xyz")
+        probs = _dev_tensor(probs, torch.float32, (self.K,), "probs")
+        if probs.shape[0] != xyz.shape[0]:
+            raise ValueError("probs must have one row per hit")
+        self._bind_stream()
+        check(lib().smki_insert_scan_soft(self._h, _ptr(xyz), _ptr(probs), xyz.shape[0],
+                                          _f3(origin), float(free_step)), "smki_insert_scan_soft")
 
     def insert_scans(self, xyz, label, offsets, origins, free_step):
         xyz = _dev_tensor(xyz, torch.float32, (3,), "xyz")
@@ -199,4 +220,6 @@ def bucket_cells(xyz, res, block_size):
     return keys, start, count, order
 
 
-from .loss import PredictiveLoss, loss_backward, loss_forward, predictive_loss  # noqa: E402
+from .loss import (PredictiveLoss, PredictiveLossClasses, loss_backward,  # noqa: E402
+                   loss_backward_classes, loss_forward, loss_forward_classes, predictive_loss,
+                   predictive_loss_classes)

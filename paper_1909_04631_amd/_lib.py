@@ -18,10 +18,11 @@ STATUS_NAMES = {
 
 # every symbol include/smki.h declares
 EXPORTED = [
-    "smki_status_string", "smki_create_map", "smki_destroy_map", "smki_set_stream",
-    "smki_insert_scan", "smki_insert_scans", "smki_query", "smki_num_blocks", "smki_export",
-    "smki_import", "smki_last_scan_stats", "smki_sync", "smki_free_samples", "smki_bucket_cells",
+    "smki_status_string", "smki_create_map", "smki_destroy_map", "smki_set_class_params",
+    "smki_set_stream", "smki_insert_scan", "smki_insert_scan_soft", "smki_insert_scans",
+    "smki_query", "smki_num_blocks", "smki_export", "smki_import", "smki_last_scan_stats", "smki_sync", "smki_free_samples", "smki_bucket_cells",
     "smki_loss_workspace_bytes", "smki_loss_forward", "smki_loss_backward",
+    "smki_loss_forward_classes", "smki_loss_backward_classes",
 ]
 
 
@@ -78,8 +79,12 @@ def lib():
     L.smki_destroy_map.argtypes = [vp]
     L.smki_set_stream.restype = st
     L.smki_set_stream.argtypes = [vp, vp]
+    L.smki_set_class_params.restype = st
+    L.smki_set_class_params.argtypes = [vp, C.POINTER(C.c_float), C.POINTER(C.c_float)]
     L.smki_insert_scan.restype = st
     L.smki_insert_scan.argtypes = [vp, vp, vp, i64, C.POINTER(C.c_float), f]
+    L.smki_insert_scan_soft.restype = st
+    L.smki_insert_scan_soft.argtypes = [vp, vp, vp, i64, C.POINTER(C.c_float), f]
     L.smki_insert_scans.restype = st
     L.smki_insert_scans.argtypes = [vp, vp, vp, C.POINTER(C.c_int64), C.POINTER(C.c_float), i32, f]
     L.smki_query.restype = st
@@ -107,6 +112,13 @@ def lib():
     L.smki_loss_backward.restype = st
     L.smki_loss_backward.argtypes = [vp, vp, i64, vp, vp, i64, f, f, f, i32, vp, vp, C.c_size_t,
                                      vp, vp, vp, vp, vp, vp]
+    fp = C.POINTER(C.c_float)
+    L.smki_loss_forward_classes.restype = st
+    L.smki_loss_forward_classes.argtypes = [vp, vp, i64, vp, vp, i64, fp, fp, f, i32, vp, vp,
+                                            C.c_size_t, vp, vp]
+    L.smki_loss_backward_classes.restype = st
+    L.smki_loss_backward_classes.argtypes = [vp, vp, i64, vp, vp, i64, fp, fp, f, i32, vp, vp,
+                                             C.c_size_t, vp, vp, vp, vp, vp, vp]
     _lib = L
     return L
 

@@ -59,25 +59,37 @@ __device__ __forceinline__ int32_t scan_of(const int64_t* scan_off, int32_t S, i
   return lo;
 }
 
-// Per hit: validation, kept flag, number of free samples, voxel bounding box.
+// Per hit: validation, hit rows (kept: 1 for a labelled hit; for soft weights
+// the number of classes with a positive weight), number of free samples of a
+// kept hit, voxel bounding box.  probs (nullable) replaces label: [n][K]
+// weights, each finite and >= 0; all zero drops the hit and its beam.
 __global__ void k_count(const float* __restrict__ xyz, const int32_t* __restrict__ label,
-                        int64_t n, const int64_t* __restrict__ scan_off,
-                        const float* __restrict__ origins, int32_t S, float res, float step,
-                        int32_t K, int64_t* __restrict__ nfree, int32_t* __restrict__ kept,
-                        int32_t* __restrict__ bbox, uint32_t* __restrict__ err) {
+                        const float* __restrict__ probs, int64_t n,
+                        const int64_t* __restrict__ scan_off, const float* __restrict__ origins,
+                        int32_t S, float res, float step, int32_t K, int64_t* __restrict__ nfree,
+                        int32_t* __restrict__ kept, int32_t* __restrict__ bbox,
+                        uint32_t* __restrict__ err) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   int32_t lo[3] = {INT32_MAX, INT32_MAX, INT32_MAX};
   int32_t hi[3] = {INT32_MIN, INT32_MIN, INT32_MIN};
   if (i < n) {
-    const int32_t y = label[i];
     const float px = xyz[3 * i], py = xyz[3 * i + 1], pz = xyz[3 * i + 2];
     uint32_t e = 0;
     int64_t c = 0;
     int32_t k = 0;
-    if (y < -1 || y >= K) e |= DEVERR_LABEL;
+    if (probs) {
+      for (int32_t j = 0; j < K; ++j) {
+        const float w = probs[i * K + j];
+        if (!(isfinite(w) && w >= 0.0f)) e |= DEVERR_LABEL;
+        k += w > 0.0f ? 1 : 0;
+      }
+    } else {
+      const int32_t y = label[i];
+      if (y < -1 || y >= K) e |= DEVERR_LABEL;
+      k = y != -1 ? 1 : 0;
+    }
     if (!finite3(px, py, pz)) e |= DEVERR_NONFINITE;
-    if (e == 0 && y != -1) {
-      k = 1;
+    if (e == 0 && k > 0) {
       int32_t v[3];
       if (!voxel_index(px, res, &v[0]) || !voxel_index(py, res, &v[1]) ||
           !voxel_index(pz, res, &v[2])) {
@@ -190,13 +202,16 @@ __device__ __forceinline__ bool in_grid(const BucketGeom& g, const int32_t b[3])
          b[1] < g.blo[1] + g.nb[1] && b[2] >= g.blo[2] && b[2] < g.blo[2] + g.nb[2];
 }
 
-// Kept hits -> (key, index) and records (unsorted).
+// Kept hits -> (key, index) and records (unsorted), at rows kpos[i]...  With
+// soft weights (probs non-null) a hit gives one row per class of positive
+// weight, in class order, and wt[row] = that weight.
 template <typename KeyT>
 __global__ void k_hit_keys(const float* __restrict__ xyz, const int32_t* __restrict__ label,
-                           int64_t n, const int32_t* __restrict__ kept,
-                           const int32_t* __restrict__ kpos, BucketGeom g,
-                           KeyT* __restrict__ keys, uint32_t* __restrict__ idx,
-                           float4* __restrict__ rec, uint32_t* __restrict__ err) {
+                           const float* __restrict__ probs, int32_t K, int64_t n,
+                           const int32_t* __restrict__ kept, const int32_t* __restrict__ kpos,
+                           BucketGeom g, KeyT* __restrict__ keys, uint32_t* __restrict__ idx,
+                           float4* __restrict__ rec, float* __restrict__ wt,
+                           uint32_t* __restrict__ err) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n || !kept[i]) return;
   const float px = xyz[3 * i], py = xyz[3 * i + 1], pz = xyz[3 * i + 2];
@@ -205,11 +220,32 @@ __global__ void k_hit_keys(const float* __restrict__ xyz, const int32_t* __restr
   voxel_index(py, g.res, &v[1]);
   voxel_index(pz, g.res, &v[2]);
   block_of(g, v, b, l);
-  const int32_t w = kpos[i];
-  if (!in_grid(g, b)) { atomicOr(err, DEVERR_RANGE); keys[w] = (KeyT)0; idx[w] = w; rec[w] = make_float4(0, 0, 0, 0); return; }
-  keys[w] = make_key<KeyT>(g, label[i], b, l);
-  idx[w] = (uint32_t)w;
-  rec[w] = make_map_record(g, px, py, pz, v, l);
+  int32_t w = kpos[i];
+  const int32_t rows = kept[i];
+  if (!in_grid(g, b)) {
+    atomicOr(err, DEVERR_RANGE);
+    for (int32_t r = 0; r < rows; ++r, ++w) {
+      keys[w] = (KeyT)0; idx[w] = (uint32_t)w; rec[w] = make_float4(0, 0, 0, 0);
+      if (wt) wt[w] = 0.0f;
+    }
+    return;
+  }
+  const float4 r4 = make_map_record(g, px, py, pz, v, l);
+  if (!probs) {
+    keys[w] = make_key<KeyT>(g, label[i], b, l);
+    idx[w] = (uint32_t)w;
+    rec[w] = r4;
+    return;
+  }
+  for (int32_t k = 0; k < K; ++k) {
+    const float p = probs[i * K + k];
+    if (!(p > 0.0f)) continue;
+    keys[w] = make_key<KeyT>(g, k, b, l);
+    idx[w] = (uint32_t)w;
+    rec[w] = r4;
+    wt[w] = p;
+    ++w;
+  }
 }
 
 // Free sample f -> its beam (largest i with off[i] <= f), its position, key and record.
@@ -220,7 +256,8 @@ __global__ void k_free_keys(const float* __restrict__ xyz, int64_t n,
                             const float* __restrict__ origins, int32_t S, float step,
                             int32_t free_class, BucketGeom g, int64_t out_base,
                             KeyT* __restrict__ keys, uint32_t* __restrict__ idx,
-                            float4* __restrict__ rec, uint32_t* __restrict__ err) {
+                            float4* __restrict__ rec, float* __restrict__ wrow,
+                            uint32_t* __restrict__ err) {
   // The beams of this workgroup's samples: the first and last are found by two
   // threads over all beams, every sample then searches only between them.
   __shared__ int64_t span[2];
@@ -258,13 +295,20 @@ __global__ void k_free_keys(const float* __restrict__ xyz, int64_t n,
       !voxel_index(qz, g.res, &v[2])) {
     atomicOr(err, DEVERR_RANGE);
     keys[w] = (KeyT)0; idx[w] = (uint32_t)w; rec[w] = make_float4(0, 0, 0, 0);
+    if (wrow) wrow[w] = 0.0f;
     return;
   }
   block_of(g, v, b, l);
-  if (!in_grid(g, b)) { atomicOr(err, DEVERR_RANGE); keys[w] = (KeyT)0; idx[w] = (uint32_t)w; rec[w] = make_float4(0, 0, 0, 0); return; }
+  if (!in_grid(g, b)) {
+    atomicOr(err, DEVERR_RANGE);
+    keys[w] = (KeyT)0; idx[w] = (uint32_t)w; rec[w] = make_float4(0, 0, 0, 0);
+    if (wrow) wrow[w] = 0.0f;
+    return;
+  }
   keys[w] = make_key<KeyT>(g, free_class, b, l);
   idx[w] = (uint32_t)w;
   rec[w] = make_map_record(g, qx, qy, qz, v, l);
+  if (wrow) wrow[w] = 1.0f;
 }
 
 // Explicit training rows (differentiable form, tests): keys and records.
@@ -290,11 +334,15 @@ __global__ void k_row_keys(const float* __restrict__ xyz, const int32_t* __restr
   rec[i] = make_record(g, px, py, pz, b, label ? label[i] : 0);
 }
 
-// Sorted records: out[i] = rec[idx[i]].
-__global__ void k_permute_rec(const float4* __restrict__ rec, const uint32_t* __restrict__ idx,
-                              int64_t n, float4* __restrict__ out) {
+// Sorted records: out[i] = rec[idx[i]] (and the weights alike when present).
+__global__ void k_permute_rec(const float4* __restrict__ rec, const float* __restrict__ wt,
+                              const uint32_t* __restrict__ idx, int64_t n,
+                              float4* __restrict__ out, float* __restrict__ wout) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) out[i] = rec[idx[i]];
+  if (i >= n) return;
+  const uint32_t j = idx[i];
+  out[i] = rec[j];
+  if (wt) wout[i] = wt[j];
 }
 
 template <typename KeyT>
@@ -388,13 +436,13 @@ __global__ void k_fill_i32(int32_t* p, int64_t n, int32_t v) {
 // ---------------------------------------------------------------------------
 static inline unsigned nblk(int64_t n, int t) { return (unsigned)ceil_div_i64(n > 0 ? n : 1, t); }
 
-hipError_t launch_count(const float* xyz, const int32_t* label, int64_t n, const int64_t* scan_off,
-                        const float* origins, int32_t S, float res, float step, int32_t K,
-                        int64_t* nfree, int32_t* kept, int32_t* bbox, uint32_t* err,
-                        hipStream_t st) {
+hipError_t launch_count(const float* xyz, const int32_t* label, const float* probs, int64_t n,
+                        const int64_t* scan_off, const float* origins, int32_t S, float res,
+                        float step, int32_t K, int64_t* nfree, int32_t* kept, int32_t* bbox,
+                        uint32_t* err, hipStream_t st) {
   if (n <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_count, dim3(nblk(n, 256)), dim3(256), 0, st, xyz, label, n, scan_off,
-                     origins, S, res, step, K, nfree, kept, bbox, err);
+  hipLaunchKernelGGL(k_count, dim3(nblk(n, 256)), dim3(256), 0, st, xyz, label, probs, n,
+                     scan_off, origins, S, res, step, K, nfree, kept, bbox, err);
   return hipGetLastError();
 }
 
@@ -417,8 +465,8 @@ static hipError_t finish_set(PointSet& ps, KeyT* keys, uint32_t* idx, KeyT* akey
   else
     e = radix_sort_u64((uint64_t*)keys, idx, (uint64_t*)akeys, aidx, n, key_bits, scr.sort_tmp, st);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_permute_rec, dim3(nblk(n, 256)), dim3(256), 0, st, rec_unsorted, idx, n,
-                     ps.pts);
+  hipLaunchKernelGGL(k_permute_rec, dim3(nblk(n, 256)), dim3(256), 0, st, rec_unsorted,
+                     (const float*)scr.wt, idx, n, ps.pts, ps.wts);
   const int log2B3 = 3 * g.log2B;
   hipLaunchKernelGGL(k_block_flags<KeyT>, dim3(nblk(n, 256)), dim3(256), 0, st, keys, n, log2B3,
                      scr.flag);
@@ -447,7 +495,8 @@ static hipError_t finish_set(PointSet& ps, KeyT* keys, uint32_t* idx, KeyT* akey
 // All training rows of an insert in one sorted set: kept hits at [0, nk), free
 // samples after them; keys carry the class plane, so each (class, block) is a
 // contiguous range.
-hipError_t bucket_scan(const float* xyz, const int32_t* label, int64_t n, const int32_t* kept,
+hipError_t bucket_scan(const float* xyz, const int32_t* label, const float* probs, int32_t K,
+                       int64_t n, const int32_t* kept,
                        const int32_t* kpos, int64_t nk, const int64_t* off, int64_t nf,
                        const int64_t* scan_off, const float* origins, int32_t S, float step,
                        int32_t free_class, const BucketGeom& g, PointSet& ps, BucketScratch& scr,
@@ -456,22 +505,22 @@ hipError_t bucket_scan(const float* xyz, const int32_t* label, int64_t n, const 
   if (e != hipSuccess || ps.n <= 0) return e;
   if (g.key_bits <= 32) {
     if (nk > 0)
-      hipLaunchKernelGGL(k_hit_keys<uint32_t>, dim3(nblk(n, 256)), dim3(256), 0, st, xyz, label, n,
-                         kept, kpos, g, (uint32_t*)scr.keys, scr.idx, scr.rec, err);
+      hipLaunchKernelGGL(k_hit_keys<uint32_t>, dim3(nblk(n, 256)), dim3(256), 0, st, xyz, label, probs,
+                         K, n, kept, kpos, g, (uint32_t*)scr.keys, scr.idx, scr.rec, scr.wt, err);
     if (nf > 0)
       hipLaunchKernelGGL(k_free_keys<uint32_t>, dim3(nblk(nf, 256)), dim3(256), 0, st, xyz, n, off,
                          nf, scan_off, origins, S, step, free_class, g, nk, (uint32_t*)scr.keys,
-                         scr.idx, scr.rec, err);
+                         scr.idx, scr.rec, scr.wt, err);
     return finish_set<uint32_t>(ps, (uint32_t*)scr.keys, scr.idx, (uint32_t*)scr.akeys, scr.aidx,
                                 scr.rec, g, g.key_bits, scr, st);
   }
   if (nk > 0)
-    hipLaunchKernelGGL(k_hit_keys<uint64_t>, dim3(nblk(n, 256)), dim3(256), 0, st, xyz, label, n,
-                       kept, kpos, g, (uint64_t*)scr.keys, scr.idx, scr.rec, err);
+    hipLaunchKernelGGL(k_hit_keys<uint64_t>, dim3(nblk(n, 256)), dim3(256), 0, st, xyz, label, probs,
+                       K, n, kept, kpos, g, (uint64_t*)scr.keys, scr.idx, scr.rec, scr.wt, err);
   if (nf > 0)
     hipLaunchKernelGGL(k_free_keys<uint64_t>, dim3(nblk(nf, 256)), dim3(256), 0, st, xyz, n, off,
                        nf, scan_off, origins, S, step, free_class, g, nk, (uint64_t*)scr.keys,
-                       scr.idx, scr.rec, err);
+                       scr.idx, scr.rec, scr.wt, err);
   return finish_set<uint64_t>(ps, (uint64_t*)scr.keys, scr.idx, (uint64_t*)scr.akeys, scr.aidx,
                               scr.rec, g, g.key_bits, scr, st);
 }

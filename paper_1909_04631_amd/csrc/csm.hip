@@ -8,6 +8,7 @@
 // (class, voxel) are a run of equal keys.  The last row of each run adds the
 // run's length to its voxel: every (voxel, class) is written by exactly one
 // thread, and the counts are integers, so the result is exact and order-free.
+// With soft measurements (Sec. VI) a row counts its class weight instead of 1.
 #include "smki_gather.h"
 
 namespace {
@@ -43,7 +44,13 @@ __global__ void k_csm_counts(SplatArgs a, const KeyT* __restrict__ keys, int64_t
   const int32_t t = a.ext2t[e];
   const int32_t mslot = a.tgt_slot[t];
   const int32_t cb = a.map.cslot[(int64_t)mslot * a.K + y];   // allocated: the class has rows here
-  a.map.calpha[(int64_t)cb * B3 + c] += (float)(i - lo + 1);
+  float add = (float)(i - lo + 1);
+  if (a.wts) {   // soft measurements: the run's weights, summed in row order in double
+    double sw = 0.0;
+    for (int64_t r = lo; r <= i; ++r) sw += (double)a.wts[r];
+    add = (float)sw;
+  }
+  a.map.calpha[(int64_t)cb * B3 + c] += add;
   atomicOr(&vbits[(int64_t)t * (B3 / 32) + (c >> 5)], 1u << (c & 31));
 }
 

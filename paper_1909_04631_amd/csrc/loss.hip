@@ -42,9 +42,11 @@ struct LossArgs {
   const int32_t* prefix;
   const int32_t* sidx;   // sorted position -> original row of the walked set
   float l, l2, inv_l, sigma0, alpha0;
-  float coef[SMKI_POLY_N];  // sigma0 * Q
+  float coef[SMKI_POLY_N];  // sigma0 * Q (per-class form: Q, the class's sigma0 applied apart)
   int32_t K;
   int64_t H;
+  const float4* cls;        // per-class form: [K] (l^2, 1/l, sigma0, l) of each class's kernel;
+                            // l, l2 and inv_l above then hold the largest l (the search cut)
 };
 
 __device__ __forceinline__ float kernel_weight(const float* c, float s) {
@@ -243,6 +245,116 @@ __global__ void k_train_grad(LossArgs a, const float* __restrict__ txyz,
   grad_t[3 * t + 2] = gz;
 }
 
+// ---------------------------------------------------------------------------
+// per-class kernels: rows of class k use l_k and sigma0_k,
+//   alpha_h^k = alpha0 + sum_{y_t = k} sigma0_k f(|x_t - x_h| / l_k),
+//   dloss/dl_k      = sum over pairs with y_t = k  G_{h,k} sigma0_k f'(r) (-r/l_k)
+//   dloss/dsigma0_k = sum over pairs with y_t = k  G_{h,k} f(r)
+// per query into dl[h][k], ds[h][k] (double), then summed per class in a fixed order.
+// ---------------------------------------------------------------------------
+__global__ void k_alpha_q_pc(LossArgs a, const float* __restrict__ qxyz,
+                             float* __restrict__ alpha_q) {
+  const int64_t h = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (h >= a.H) return;
+  float* A = alpha_q + h * a.K;
+  for (int k = 0; k < a.K; ++k) A[k] = a.alpha0;
+  for_neighbours(a, qxyz[3 * h], qxyz[3 * h + 1], qxyz[3 * h + 2],
+                 [&](const float4& p, float, float, float, float d2, int32_t) {
+                   const int32_t y = __float_as_int(p.w);
+                   const float4 c = a.cls[y];
+                   if (!(d2 < c.x)) return;
+                   const float d = __builtin_sqrtf(d2);
+                   const float s = fmaxf(fmaf(-d, c.y, 1.0f), 0.0f);
+                   A[y] += c.z * kernel_weight(a.coef, s);
+                 });
+}
+
+__global__ void k_query_grad_pc(LossArgs a, const float* __restrict__ qxyz,
+                                const int32_t* __restrict__ qlab, const float* __restrict__ inv_s,
+                                const float* __restrict__ inv_ay, const float* __restrict__ gscale,
+                                float* __restrict__ grad_q, double* __restrict__ dl,
+                                double* __restrict__ ds) {
+  const int64_t h = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (h >= a.H) return;
+  const float gH = gscale[0] / (float)a.H;
+  const int32_t yh = qlab[h];
+  const float is = inv_s[h], ia = inv_ay[h];
+  double* DL = dl + h * a.K;
+  double* DS = ds + h * a.K;
+  for (int k = 0; k < a.K; ++k) {
+    DL[k] = 0.0;
+    DS[k] = 0.0;
+  }
+  float gx = 0.f, gy = 0.f, gz = 0.f;
+  for_neighbours(a, qxyz[3 * h], qxyz[3 * h + 1], qxyz[3 * h + 2],
+                 [&](const float4& p, float dx, float dy, float dz, float d2, int32_t) {
+                   const int32_t yt = __float_as_int(p.w);
+                   const float4 c = a.cls[yt];
+                   if (!(d2 < c.x)) return;
+                   const float G = -gH * ((yt == yh ? ia : 0.0f) - is);
+                   const float d = __builtin_sqrtf(d2);
+                   const float r = d * c.y;
+                   const float s = fmaxf(1.0f - r, 0.0f);
+                   const float gr = c.z * dfdr_over_r(s);          // sigma0_k f'(r)/r
+                   const float cc = G * gr * (c.y * c.y);          // coefficient of (x_t - x_h)
+                   gx -= cc * dx;
+                   gy -= cc * dy;
+                   gz -= cc * dz;
+                   DL[yt] += (double)(-G * gr * r * r * c.y);     // G sigma0_k f'(r) (-r/l_k)
+                   DS[yt] += (double)(G * kernel_weight(a.coef, s));
+                 });
+  if (grad_q) {
+    grad_q[3 * h] = gx;
+    grad_q[3 * h + 1] = gy;
+    grad_q[3 * h + 2] = gz;
+  }
+}
+
+__global__ void k_train_grad_pc(LossArgs a, const float* __restrict__ txyz,
+                                const int32_t* __restrict__ tlab, int64_t n_train,
+                                const int32_t* __restrict__ qlab, const float* __restrict__ inv_s,
+                                const float* __restrict__ inv_ay, const float* __restrict__ gscale,
+                                float* __restrict__ grad_t) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= n_train) return;
+  const float gH = gscale[0] / (float)a.H;
+  const int32_t yt = tlab[t];
+  const float4 c = a.cls[yt];
+  float gx = 0.f, gy = 0.f, gz = 0.f;
+  const float il2 = c.y * c.y;
+  for_neighbours(a, txyz[3 * t], txyz[3 * t + 1], txyz[3 * t + 2],
+                 [&](const float4&, float dx, float dy, float dz, float d2, int32_t j) {
+                   if (!(d2 < c.x)) return;
+                   const int32_t h = a.sidx[j];
+                   const float G = -gH * ((yt == qlab[h] ? inv_ay[h] : 0.0f) - inv_s[h]);
+                   const float d = __builtin_sqrtf(d2);
+                   const float s = fmaxf(fmaf(-d, c.y, 1.0f), 0.0f);
+                   const float cc = G * c.z * dfdr_over_r(s) * il2;
+                   gx -= cc * dx;
+                   gy -= cc * dy;
+                   gz -= cc * dz;
+                 });
+  grad_t[3 * t] = gx;
+  grad_t[3 * t + 1] = gy;
+  grad_t[3 * t + 2] = gz;
+}
+
+// out[k] = sum_h v[h][k] (one workgroup per class, fixed order)
+__global__ void __launch_bounds__(256) k_colsum_f64(const double* __restrict__ v, int64_t H,
+                                                    int32_t K, float* __restrict__ out) {
+  __shared__ double part[256];
+  const int32_t k = blockIdx.x;
+  double s = 0.0;
+  for (int64_t h = threadIdx.x; h < H; h += 256) s += v[h * K + k];
+  part[threadIdx.x] = s;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if ((int)threadIdx.x < o) part[threadIdx.x] += part[threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[k] = (float)part[0];
+}
+
 __global__ void __launch_bounds__(256) k_sum_f64(const double* __restrict__ v, int64_t n,
                                                  float* __restrict__ out) {
   __shared__ double part[256];
@@ -282,6 +394,8 @@ struct SetBufs {
 void carve_set(Carve& c, SetBufs& s, int64_t n, int64_t nblocks_cap) {
   const int64_t slots = std::min<int64_t>(n, nblocks_cap);
   s.ps.n = n;
+  s.ps.wts = nullptr;   // every training row of the loss weighs 1
+  s.scr.wt = nullptr;
   s.ps.pts = c.take<float4>(n);
   s.ps.dense = c.take<int32_t>(nblocks_cap);
   s.ps.slot_lin = c.take<int32_t>(slots);
@@ -308,9 +422,14 @@ struct LossBufs {
   float* inv_ay;
   double* dsig;
   double* dl;
+  double* dlk;   // [H][K] per-class form
+  double* dsk;   // [H][K]
+  float4* cls;   // [K] per-class form: class kernels (in the header)
 };
 
-constexpr size_t kHdr = 512;  // bounding box and error word, ahead of the carved buffers
+// bounding box and error word (first 512 bytes) and the per-class kernel table
+// (up to 255 float4), ahead of the carved buffers
+constexpr size_t kHdr = 512 + 256 * sizeof(float4);
 
 // Buffers after the header, for a grid of nblocks blocks (nullptr base: size only).
 size_t carve_body(char* base, LossBufs& b, int64_t nt, int64_t nq, int32_t K, int64_t nblocks) {
@@ -320,6 +439,8 @@ size_t carve_body(char* base, LossBufs& b, int64_t nt, int64_t nq, int32_t K, in
   b.inv_ay = c.take<float>(nq);
   b.dsig = c.take<double>(nq);
   b.dl = c.take<double>(nq);
+  b.dlk = c.take<double>((size_t)nq * K);
+  b.dsk = c.take<double>((size_t)nq * K);
   carve_set(c, b.tr, nt, nblocks);
   carve_set(c, b.qu, nq, nblocks);
   return c.used + kAl;
@@ -336,10 +457,12 @@ char* align_up(char* p) { return (char*)(((uintptr_t)p + kAl - 1) / kAl * kAl); 
 // Validate both sets and size the grid (synchronous); then carve the body from
 // the caller's workspace or a fresh allocation, and bucket the training rows
 // (and the queries if both_sets).
+// h_cls (nullable): per-class kernel table, copied into the header before the
+// synchronisation (so the host array may go out of scope after the call).
 smki_status prepare(const float* txyz, const int32_t* tlab, int64_t nt, const float* qxyz,
                     const int32_t* qlab, int64_t nq, float l, int32_t K, bool both_sets,
                     char* ws, size_t ws_bytes, char** own, LossBufs& b, BucketGeom& g,
-                    hipStream_t st) {
+                    hipStream_t st, const float4* h_cls = nullptr) {
   const float h = (float)((double)l * (1.0 + 1.0 / 1024.0));
   char* hdr = ws ? align_up(ws) : nullptr;
   if (ws && ws_bytes < kHdr + kAl) return SMKI_E_CAPACITY;
@@ -349,6 +472,9 @@ smki_status prepare(const float* txyz, const int32_t* tlab, int64_t nt, const fl
   }
   b.bbox = (int32_t*)hdr;
   b.err = (uint32_t*)(hdr + 64);
+  b.cls = (float4*)(hdr + 512);
+  if (h_cls)
+    SMKI_HIP_TRY(hipMemcpyAsync(b.cls, h_cls, sizeof(float4) * K, hipMemcpyHostToDevice, st));
   const int32_t bbox0[8] = {INT32_MAX, INT32_MAX, INT32_MAX, INT32_MIN, INT32_MIN, INT32_MIN, 0, 0};
   SMKI_HIP_TRY(hipMemcpyAsync(b.bbox, bbox0, sizeof(bbox0), hipMemcpyHostToDevice, st));
   SMKI_HIP_TRY(hipMemsetAsync(b.err, 0, sizeof(uint32_t) * 4, st));
@@ -493,6 +619,103 @@ extern "C" smki_status smki_loss_backward(const float* txyz, const int32_t* tlab
     if (grad_train && nt > 0) {
       const LossArgs at = make_args(g, b.qu, l, sigma0, alpha0, K, nq);
       hipLaunchKernelGGL(k_train_grad, dim3(nblk(nt, 64)), dim3(64), 0, st, at, txyz, tlab, nt,
+                         qlab, (const float*)b.inv_s, (const float*)b.inv_ay, grad_loss,
+                         grad_train);
+    }
+    if (hipGetLastError() != hipSuccess) rc = SMKI_E_DEVICE;
+  }
+  release(own, st);
+  return rc;
+}
+
+// ---------------------------------------------------------------------------
+// per-class kernels (l_k, sigma0_k per class)
+// ---------------------------------------------------------------------------
+namespace {
+
+// Host table of the class kernels and the largest l; false if a value is invalid.
+bool class_table(const float* l, const float* sigma0, int32_t K, float4* t, float* lmax) {
+  if (!l || !sigma0 || K < 2 || K > 255) return false;
+  *lmax = 0.0f;
+  for (int32_t k = 0; k < K; ++k) {
+    if (!(std::isfinite(l[k]) && l[k] > 0) || !(std::isfinite(sigma0[k]) && sigma0[k] > 0))
+      return false;
+    t[k] = make_float4(l[k] * l[k], 1.0f / l[k], sigma0[k], l[k]);
+    *lmax = std::max(*lmax, l[k]);
+  }
+  return true;
+}
+
+LossArgs make_args_pc(const BucketGeom& g, const SetBufs& s, float lmax, const float4* cls,
+                      float alpha0, int32_t K, int64_t H) {
+  LossArgs a = make_args(g, s, lmax, 1.0f, alpha0, K, H);   // coef = Q: sigma0_k applied per row
+  a.cls = cls;
+  return a;
+}
+
+}  // namespace
+
+extern "C" smki_status smki_loss_forward_classes(const float* txyz, const int32_t* tlab,
+                                                 int64_t nt, const float* qxyz,
+                                                 const int32_t* qlab, int64_t nq, const float* l,
+                                                 const float* sigma0, float alpha0, int32_t K,
+                                                 void* hip_stream, void* workspace,
+                                                 size_t ws_bytes, float* loss, float* alpha_q) {
+  float4 tab[256];
+  float lmax = 0.0f;
+  if (!class_table(l, sigma0, K, tab, &lmax) || bad_params(nt, nq, lmax, 1.0f, alpha0, K) ||
+      !qxyz || !qlab || !loss || (nt > 0 && (!txyz || !tlab)))
+    return SMKI_E_INVALID_ARG;
+  hipStream_t st = (hipStream_t)hip_stream;
+  char* own[2] = {nullptr, nullptr};
+  LossBufs b{};
+  BucketGeom g{};
+  smki_status rc = prepare(txyz, tlab, nt, qxyz, qlab, nq, lmax, K, false, (char*)workspace,
+                           ws_bytes, own, b, g, st, tab);
+  if (rc == SMKI_OK) {
+    const LossArgs a = make_args_pc(g, b.tr, lmax, b.cls, alpha0, K, nq);
+    float* A = alpha_q ? alpha_q : b.alpha_q;
+    hipLaunchKernelGGL(k_alpha_q_pc, dim3(nblk(nq, 64)), dim3(64), 0, st, a, qxyz, A);
+    hipLaunchKernelGGL(k_loss_value, dim3(1), dim3(256), 0, st, (const float*)A, qlab, nq, K, loss);
+    if (hipGetLastError() != hipSuccess) rc = SMKI_E_DEVICE;
+  }
+  release(own, st);
+  return rc;
+}
+
+extern "C" smki_status smki_loss_backward_classes(
+    const float* txyz, const int32_t* tlab, int64_t nt, const float* qxyz, const int32_t* qlab,
+    int64_t nq, const float* l, const float* sigma0, float alpha0, int32_t K, void* hip_stream,
+    void* workspace, size_t ws_bytes, const float* alpha_q, const float* grad_loss, float* grad_l,
+    float* grad_sigma0, float* grad_train, float* grad_query) {
+  float4 tab[256];
+  float lmax = 0.0f;
+  if (!class_table(l, sigma0, K, tab, &lmax) || bad_params(nt, nq, lmax, 1.0f, alpha0, K) ||
+      !qxyz || !qlab || !alpha_q || !grad_loss || (nt > 0 && (!txyz || !tlab)))
+    return SMKI_E_INVALID_ARG;
+  hipStream_t st = (hipStream_t)hip_stream;
+  char* own[2] = {nullptr, nullptr};
+  LossBufs b{};
+  BucketGeom g{};
+  smki_status rc = prepare(txyz, tlab, nt, qxyz, qlab, nq, lmax, K, grad_train != nullptr,
+                           (char*)workspace, ws_bytes, own, b, g, st, tab);
+  if (rc == SMKI_OK) {
+    // 1/S and 1/alpha_y per query (the single-kernel sigma0 share is not used here)
+    hipLaunchKernelGGL(k_prep, dim3(nblk(nq, 256)), dim3(256), 0, st, alpha_q, qlab, nq, K, alpha0,
+                       1.0f, grad_loss, b.inv_s, b.inv_ay, b.dsig);
+    const LossArgs aq = make_args_pc(g, b.tr, lmax, b.cls, alpha0, K, nq);
+    hipLaunchKernelGGL(k_query_grad_pc, dim3(nblk(nq, 64)), dim3(64), 0, st, aq, qxyz, qlab,
+                       (const float*)b.inv_s, (const float*)b.inv_ay, grad_loss, grad_query,
+                       b.dlk, b.dsk);
+    if (grad_l)
+      hipLaunchKernelGGL(k_colsum_f64, dim3(K), dim3(256), 0, st, (const double*)b.dlk, nq, K,
+                         grad_l);
+    if (grad_sigma0)
+      hipLaunchKernelGGL(k_colsum_f64, dim3(K), dim3(256), 0, st, (const double*)b.dsk, nq, K,
+                         grad_sigma0);
+    if (grad_train && nt > 0) {
+      const LossArgs at = make_args_pc(g, b.qu, lmax, b.cls, alpha0, K, nq);
+      hipLaunchKernelGGL(k_train_grad_pc, dim3(nblk(nt, 64)), dim3(64), 0, st, at, txyz, tlab, nt,
                          qlab, (const float*)b.inv_s, (const float*)b.inv_ay, grad_loss,
                          grad_train);
     }

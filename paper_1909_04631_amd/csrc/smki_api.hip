@@ -96,6 +96,9 @@ struct smki_map {
   uint32_t* d_err = nullptr;
   unsigned long long* d_stats = nullptr;
   StencilOff* d_offs = nullptr;
+  // kernel of each class (l_k, sigma0_k; all l and sigma0 unless set per class)
+  std::vector<float> lk, s0k;
+  float4* d_cls = nullptr;  // [K] (l^2, 1/l, sigma0 * Q's leading coefficient, l)
   // workspaces
   Arena a_hits, a_sets, a_tgts, a_misc;
   // pinned host staging
@@ -216,6 +219,24 @@ smki_status ensure_hash(smki_map* m, int64_t blocks) {
   return SMKI_OK;
 }
 
+// Device table of the class kernels (synchronous: no insert in flight reads it).
+smki_status upload_class_params(smki_map* m) {
+  std::vector<float4> t(m->K);
+  for (int32_t k = 0; k < m->K; ++k) {
+    const float l = m->lk[k];
+    t[k] = make_float4(l * l, 1.0f / l, (float)(kSmkiQ[0] * (double)m->s0k[k]), l);
+  }
+  SMKI_HIP_TRY(hipStreamSynchronize(m->stream));
+  SMKI_HIP_TRY(hipMemcpy(m->d_cls, t.data(), sizeof(float4) * m->K, hipMemcpyHostToDevice));
+  return SMKI_OK;
+}
+
+float max_class_l(const smki_map* m) {
+  float l = 0.0f;
+  for (float v : m->lk) l = std::max(l, v);
+  return l;
+}
+
 smki_status take_device_error(smki_map* m) {
   uint32_t e = 0;
   SMKI_HIP_TRY(sync_read(m, m->d_err, sizeof(uint32_t), &e));
@@ -259,6 +280,7 @@ smki_status insert_csm(smki_map* m, const BucketGeom& g, const PointSet& ps, con
   sa.g = g;
   sa.K = m->K;
   sa.pts = ps.pts;
+  sa.wts = ps.wts;
   sa.dense = ps.dense;
   sa.head = ps.head;
   sa.slot_lin = ps.slot_lin;
@@ -339,10 +361,13 @@ smki_status insert_csm(smki_map* m, const BucketGeom& g, const PointSet& ps, con
 // ---------------------------------------------------------------------------
 // the insert (one or several scans)
 // ---------------------------------------------------------------------------
-smki_status insert_impl(smki_map* m, const float* xyz, const int32_t* label, int64_t n,
-                        const int64_t* offsets, const float* origins, int32_t S, float step) {
+// label (one class per hit) or probs (soft: [n][K] class weights per hit), not both
+smki_status insert_impl(smki_map* m, const float* xyz, const int32_t* label, const float* probs,
+                        int64_t n, const int64_t* offsets, const float* origins, int32_t S,
+                        float step) {
   // host-side validation
-  if (!m || S < 1 || !offsets || !origins || n < 0 || (n > 0 && (!xyz || !label)))
+  if (!m || S < 1 || !offsets || !origins || n < 0 ||
+      (n > 0 && (!xyz || (label == nullptr) == (probs == nullptr))))
     return SMKI_E_INVALID_ARG;
   if (!isfinite(step)) return SMKI_E_INVALID_ARG;
   if (offsets[0] != 0 || offsets[S] != n) return SMKI_E_INVALID_ARG;
@@ -354,6 +379,8 @@ smki_status insert_impl(smki_map* m, const float* xyz, const int32_t* label, int
     if (!(q >= -(float)SMKI_COORD_LIM && q < (float)SMKI_COORD_LIM)) return SMKI_E_RANGE;
   }
   if (n > (int64_t)INT32_MAX / 2) return SMKI_E_CAPACITY;
+  // soft: up to K hit rows per hit, counted in int32
+  if (probs && n * (int64_t)m->K > (int64_t)INT32_MAX / 2) return SMKI_E_CAPACITY;
   smki_scan_stats st{};
   m->last = st;
   m->stats_pending = false;
@@ -388,8 +415,8 @@ smki_status insert_impl(smki_map* m, const float* xyz, const int32_t* label, int
   SMKI_HIP_TRY(hipMemcpyAsync(d_org, origins, sizeof(float) * 3 * S, hipMemcpyHostToDevice, q));
   SMKI_HIP_TRY(hipMemcpyAsync(d_bbox, bbox0, sizeof(bbox0), hipMemcpyHostToDevice, q));
   SMKI_HIP_TRY(hipMemsetAsync(d_sc, 0, sizeof(int64_t) * 4, q));
-  SMKI_HIP_TRY(launch_count(xyz, label, n, d_soff, d_org, S, m->res, step, m->K, d_nfree, d_kept,
-                            d_bbox, m->d_err, q));
+  SMKI_HIP_TRY(launch_count(xyz, label, probs, n, d_soff, d_org, S, m->res, step, m->K, d_nfree,
+                            d_kept, d_bbox, m->d_err, q));
   SMKI_HIP_TRY(scan_excl_i64(d_nfree, d_off, n, d_sc, d_stmp, q));
   SMKI_HIP_TRY(scan_excl_i32(d_kept, d_kpos, n, (int32_t*)(d_sc + 1), d_stmp, q));
   // sync 1: counts, box, device validation
@@ -425,7 +452,7 @@ smki_status insert_impl(smki_map* m, const float* xyz, const int32_t* label, int
   if ((int64_t)(g.nb[0] + 2) * (g.nb[1] + 2) * (g.nb[2] + 2) > (int64_t(1) << 30))
     return SMKI_E_CAPACITY;
   const bool csm = m->model == SMKI_MODEL_SCSM;
-  const double lv = (double)m->l / (double)m->res;
+  const double lv = (double)max_class_l(m) / (double)m->res;   // the stencil of the widest kernel
   const double margin = std::max(1e-4, 4.0 * ldexp((double)maxabs + 1.0, -23));
   const Stencil sten = csm ? Stencil{} : make_stencil(lv, margin);
   if (!csm && (sten.R > SMKI_MAX_REACH || sten.R > m->B)) return SMKI_E_CAPACITY;
@@ -464,6 +491,10 @@ smki_status insert_impl(smki_map* m, const float* xyz, const int32_t* label, int
   zb.add<int32_t>(n_ext);
   zb.add<int32_t>(max_slots);
   zb.add<int32_t>(max_slots);
+  if (probs) {
+    zb.add<float>(nt);   // row weights, sorted
+    zb.add<float>(nt);   // unsorted
+  }
   SMKI_HIP_TRY(m->a_sets.reserve(zb.total));
   Arena& Bz = m->a_sets;
   PointSet ps{};
@@ -492,9 +523,11 @@ smki_status insert_impl(smki_map* m, const float* xyz, const int32_t* label, int
   int32_t* d_ext2t = Bz.take<int32_t>(n_ext);
   int32_t* d_nun = Bz.take<int32_t>(max_slots);
   int32_t* d_ust = Bz.take<int32_t>(max_slots);
+  ps.wts = probs ? Bz.take<float>(nt) : nullptr;
+  scr.wt = probs ? Bz.take<float>(nt) : nullptr;
   SMKI_HIP_TRY(hipMemsetAsync(d_si, 0, sizeof(int32_t) * 8, q));
-  SMKI_HIP_TRY(bucket_scan(xyz, label, n, d_kept, d_kpos, nk, d_off, nf, d_soff, d_org, S, step,
-                           m->free_class, g, ps, scr, m->d_err, q));
+  SMKI_HIP_TRY(bucket_scan(xyz, label, probs, m->K, n, d_kept, d_kpos, nk, d_off, nf, d_soff,
+                           d_org, S, step, m->free_class, g, ps, scr, m->d_err, q));
   SMKI_HIP_TRY(hipMemsetAsync(d_mark, 0, sizeof(int32_t) * n_ext, q));
   SMKI_HIP_TRY(launch_mark_targets(ps.slot_lin, ps.d_nslots, (int32_t)max_slots, g, eblo, enb, DB,
                                    d_mark, q));
@@ -523,10 +556,8 @@ smki_status insert_impl(smki_map* m, const float* xyz, const int32_t* label, int
   SMKI_HIP_TRY(hipMemcpyAsync(m->d_offs, sten.offs.data(), sizeof(StencilOff) * sten.offs.size(),
                               hipMemcpyHostToDevice, q));
   sa.offs = (const int4*)m->d_offs;
-  sa.l2 = m->l * m->l;
-  sa.inv_l = 1.0f / m->l;
+  sa.cls = m->d_cls;
   for (int i = 0; i < SMKI_POLY_N; ++i) sa.mcoef[i] = (float)(kSmkiQ[i] / kSmkiQ[0]);
-  sa.cscale = (float)(kSmkiQ[0] * (double)m->sigma0);
   sa.K = m->K;
   sa.chunk = m->chunk;
   // piece p = (dx+1)*9 + (dy+1)*3 + (dz+1): all 27, or those with at most one dx, dy, dz != 0
@@ -536,6 +567,7 @@ smki_status insert_impl(smki_map* m, const float* xyz, const int32_t* label, int
     if (m->selection == SMKI_SELECT_EXACT || nz <= 1) sa.piece_mask |= 1u << p;
   }
   sa.pts = ps.pts;
+  sa.wts = ps.wts;
   sa.dense = ps.dense;
   sa.head = ps.head;
   sa.slot_lin = ps.slot_lin;
@@ -686,11 +718,17 @@ smki_status smki_create_map(float res, int32_t block_size, float l, float sigma0
   if (hipMalloc((void**)&m->d_err, 64) != hipSuccess ||
       hipMalloc((void**)&m->d_stats, 64) != hipSuccess ||
       hipMalloc((void**)&m->d_offs, sizeof(StencilOff) * SMKI_MAX_OFFS) != hipSuccess ||
+      hipMalloc((void**)&m->d_cls, sizeof(float4) * K) != hipSuccess ||
       hipHostMalloc((void**)&m->h_pin, 256, hipHostMallocDefault) != hipSuccess ||
       hipEventCreate(&m->ev[0]) != hipSuccess || hipEventCreate(&m->ev[1]) != hipSuccess ||
       hipEventCreate(&m->ev[2]) != hipSuccess || hipEventCreate(&m->ev[3]) != hipSuccess)
     rc = SMKI_E_OOM;
   if (rc == SMKI_OK && hipMemset(m->d_err, 0, 64) != hipSuccess) rc = SMKI_E_DEVICE;
+  if (rc == SMKI_OK) {
+    m->lk.assign(K, l);
+    m->s0k.assign(K, sigma0);
+    rc = upload_class_params(m);
+  }
   const int64_t init_blocks = (opt && opt->initial_blocks > 0) ? opt->initial_blocks : 4096;
   if (rc == SMKI_OK) rc = ensure_pool(m, init_blocks);
   if (rc == SMKI_OK) rc = ensure_cpool(m, 2 * init_blocks);
@@ -715,6 +753,7 @@ smki_status smki_destroy_map(smki_map* m) {
   if (m->d_err) (void)hipFree(m->d_err);
   if (m->d_stats) (void)hipFree(m->d_stats);
   if (m->d_offs) (void)hipFree(m->d_offs);
+  if (m->d_cls) (void)hipFree(m->d_cls);
   if (m->h_pin) (void)hipHostFree(m->h_pin);
   for (hipEvent_t e : m->ev)
     if (e) (void)hipEventDestroy(e);
@@ -724,6 +763,16 @@ smki_status smki_destroy_map(smki_map* m) {
   m->a_misc.release();
   delete m;
   return SMKI_OK;
+}
+
+smki_status smki_set_class_params(smki_map* m, const float* l, const float* sigma0) {
+  if (!m || !l || !sigma0) return SMKI_E_INVALID_ARG;
+  for (int32_t k = 0; k < m->K; ++k)
+    if (!finite_pos(l[k]) || !finite_pos(sigma0[k])) return SMKI_E_INVALID_ARG;
+  SMKI_HIP_TRY(hipSetDevice(m->device));
+  m->lk.assign(l, l + m->K);
+  m->s0k.assign(sigma0, sigma0 + m->K);
+  return upload_class_params(m);
 }
 
 smki_status smki_set_stream(smki_map* m, void* hip_stream) {
@@ -736,14 +785,21 @@ smki_status smki_insert_scan(smki_map* m, const float* xyz, const int32_t* label
                              const float* origin, float free_step) {
   if (!origin) return SMKI_E_INVALID_ARG;
   const int64_t off[2] = {0, n};
-  return insert_impl(m, xyz, label, n, off, origin, 1, free_step);
+  return insert_impl(m, xyz, label, nullptr, n, off, origin, 1, free_step);
+}
+
+smki_status smki_insert_scan_soft(smki_map* m, const float* xyz, const float* probs, int64_t n,
+                                  const float* origin, float free_step) {
+  if (!origin) return SMKI_E_INVALID_ARG;
+  const int64_t off[2] = {0, n};
+  return insert_impl(m, xyz, nullptr, probs, n, off, origin, 1, free_step);
 }
 
 smki_status smki_insert_scans(smki_map* m, const float* xyz, const int32_t* label,
                               const int64_t* offsets, const float* origins, int32_t S,
                               float free_step) {
   if (!offsets || S < 1) return SMKI_E_INVALID_ARG;
-  return insert_impl(m, xyz, label, offsets[S], offsets, origins, S, free_step);
+  return insert_impl(m, xyz, label, nullptr, offsets[S], offsets, origins, S, free_step);
 }
 
 smki_status smki_query(smki_map* m, const int32_t* ijk, int64_t M, float* alpha, float* mean,
@@ -890,7 +946,8 @@ smki_status smki_free_samples(const float* xyz, const int32_t* label, int64_t n,
   if (e == hipSuccess) e = hipMemcpyAsync(bbox, bbox0, sizeof(bbox0), hipMemcpyHostToDevice, q);
   if (e == hipSuccess) e = hipMemsetAsync(err, 0, sizeof(uint32_t), q);
   if (e == hipSuccess)
-    e = launch_count(xyz, label, n, soff, org, 1, 3.0e38f, free_step, K, nfree, kept, bbox, err, q);
+    e = launch_count(xyz, label, nullptr, n, soff, org, 1, 3.0e38f, free_step, K, nfree, kept,
+                     bbox, err, q);
   if (e == hipSuccess) e = scan_excl_i64(nfree, off, n, tot, tmp, q);
   int64_t h[2] = {0, 0};
   uint32_t herr = 0;
@@ -957,7 +1014,7 @@ smki_status smki_bucket_cells(const float* xyz, int64_t n, float res, int32_t bl
   if (e == hipSuccess) e = hipMemsetAsync(err, 0, sizeof(uint32_t), q);
   if (e == hipSuccess) e = hipMemsetAsync(lab, 0, sizeof(int32_t) * n, q);
   if (e == hipSuccess)
-    e = launch_count(xyz, lab, n, soff, org, 1, res, 0.0f, 1, nfree, kept, bbox, err, q);
+    e = launch_count(xyz, lab, nullptr, n, soff, org, 1, res, 0.0f, 1, nfree, kept, bbox, err, q);
   int32_t hb[8];
   uint32_t herr = 0;
   if (e == hipSuccess) e = hipMemcpyAsync(hb, bbox, sizeof(hb), hipMemcpyDeviceToHost, q);

@@ -21,6 +21,7 @@ struct BucketGeom {
 struct PointSet {
   int64_t n;          // rows
   float4* pts;        // sorted records: xyz relative to the row's block corner, label bits
+  float* wts;         // sorted row weights (soft measurements); nullptr: every row weighs 1
   int32_t* dense;     // [n_blocks * planes] (grid block, plane) -> slot, -1 if no row
   int32_t* slot_lin;  // [slots] (plane, grid block) linear index of each slot
   int32_t* prefix;    // [slots][B^3 + 1] first row of each voxel of the block (absolute);
@@ -36,18 +37,20 @@ struct BucketScratch {
   uint32_t* idx;
   uint32_t* aidx;
   float4* rec;        // unsorted records
+  float* wt;          // unsorted row weights, or nullptr (then PointSet::wts is not written)
   int32_t* flag;
   int32_t* slot_excl;
   void* sort_tmp;
   void* scan_tmp;
 };
 
-hipError_t launch_count(const float* xyz, const int32_t* label, int64_t n, const int64_t* scan_off,
-                        const float* origins, int32_t S, float res, float step, int32_t K,
-                        int64_t* nfree, int32_t* kept, int32_t* bbox, uint32_t* err,
-                        hipStream_t st);
+hipError_t launch_count(const float* xyz, const int32_t* label, const float* probs, int64_t n,
+                        const int64_t* scan_off, const float* origins, int32_t S, float res,
+                        float step, int32_t K, int64_t* nfree, int32_t* kept, int32_t* bbox,
+                        uint32_t* err, hipStream_t st);
 hipError_t launch_fill_i32(int32_t* p, int64_t n, int32_t v, hipStream_t st);
-hipError_t bucket_scan(const float* xyz, const int32_t* label, int64_t n, const int32_t* kept,
+hipError_t bucket_scan(const float* xyz, const int32_t* label, const float* probs, int32_t K,
+                       int64_t n, const int32_t* kept,
                        const int32_t* kpos, int64_t nk, const int64_t* off, int64_t nf,
                        const int64_t* scan_off, const float* origins, int32_t S, float step,
                        int32_t free_class, const BucketGeom& g, PointSet& ps, BucketScratch& scr,

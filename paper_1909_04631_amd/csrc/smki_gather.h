@@ -41,13 +41,14 @@ struct SplatArgs {
   int32_t R;                  // stencil reach in voxels (region = block grown by R)
   int32_t noff;               // voxel offsets in offs
   const int4* offs;           // [noff] StencilOff
-  float l2, inv_l;
+  const float4* cls;          // [K] kernel of each class: (l^2, 1/l, sigma0 * Q's leading
+                              // coefficient, l); the stencil covers the largest l
   float mcoef[SMKI_POLY_N];   // Q / Q's leading coefficient (monic), highest degree first
-  float cscale;               // sigma0 * Q's leading coefficient
   int32_t K;
   int32_t chunk;              // rows of one (class, block) per work unit
   // sorted rows
   const float4* pts;          // records: |row - its voxel centre| per axis; (cell << 3 | octant) bits
+  const float* wts;           // row weights (soft measurements), nullptr: every row weighs 1
   const int32_t* dense;       // [n_blocks * K] (block, class) -> slot
   const int32_t* head;        // [slots + 1] first row of each slot
   const int32_t* slot_lin;    // [slots] (class, block) linear index

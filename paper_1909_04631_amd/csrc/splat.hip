@@ -145,8 +145,9 @@ __device__ __forceinline__ int pbase(int p) {
 }
 
 // NS = ceil(stencil size / 64), the steps each row takes (compiled per value
-// so that the steps of a row are independent straight-line code).
-template <int B, int R, int NS>
+// so that the steps of a row are independent straight-line code).  W: rows carry
+// a weight (soft measurements) that scales their kernel values.
+template <int B, int R, int NS, bool W>
 __global__ void __launch_bounds__(SMKI_WAVE) k_splat(SplatArgs a) {
   constexpr int DR = B + 2 * R;                 // region edge (voxels)
   constexpr int DR3 = DR * DR * DR;
@@ -156,6 +157,9 @@ __global__ void __launch_bounds__(SMKI_WAVE) k_splat(SplatArgs a) {
   const int32_t slot = u.x;
   const int32_t r0 = a.head[slot] + u.y * a.chunk;
   const int32_t r1 = min(a.head[slot + 1], r0 + a.chunk);
+  const int32_t plane_lin = a.slot_lin[slot];
+  const float4 kc = a.cls[plane_lin / a.g.n_blocks];   // the kernel of the unit's class
+  const float l2 = kc.x, inv_l = kc.y, cscale = kc.z;
   for (int i = lane; i <= DR3; i += SMKI_WAVE) acc[i] = 0.0f;
   // Per lane, for each step: one voxel offset o of the first-octant stencil
   // (offsets whose centre can lie within l of a point in the (+,+,+) octant of
@@ -212,7 +216,7 @@ __global__ void __launch_bounds__(SMKI_WAVE) k_splat(SplatArgs a) {
     _Pragma("unroll") for (int s = 0; s < NS; ++s)                           \
         old[s] = acc[base[s] + wl[OC][s]];                                   \
     _Pragma("unroll") for (int s = 0; s < NS; ++s)                           \
-        acc[base[s] + wl[OC][s]] = fmaf(a.cscale, sum[s], old[s]);           \
+        acc[base[s] + wl[OC][s]] = fmaf(cscale, sum[s], old[s]);             \
     break;                                                                   \
   }
       SMKI_FLUSH_CASE(0) SMKI_FLUSH_CASE(1) SMKI_FLUSH_CASE(2) SMKI_FLUSH_CASE(3)
@@ -225,19 +229,31 @@ __global__ void __launch_bounds__(SMKI_WAVE) k_splat(SplatArgs a) {
   // Rows are staged 64 at a time in registers (lane i holds row base + i) and
   // broadcast with v_readlane; two batches alternate so that one loads while
   // the other is processed.
-  auto load_batch = [&](int32_t base) {   // unconditional: lanes past the end re-read row r1 - 1
-    return pts[min(base + lane, r1 - 1)];
+  // A batch: the rows' records and (W) their weights.
+  struct Batch {
+    float4 r;
+    float w;
   };
-  auto process = [&](const float4& cur, int32_t base) {
+  auto load_batch = [&](int32_t base) {   // unconditional: lanes past the end re-read row r1 - 1
+    const int32_t row = min(base + lane, r1 - 1);
+    Batch b;
+    b.r = pts[row];
+    b.w = W ? a.wts[row] : 1.0f;
+    return b;
+  };
+  auto process = [&](const Batch& bt, int32_t base) {
     const int nb = min(SMKI_WAVE, r1 - base);
+    const float4& cur = bt.r;
     // Consume the batch once here, so that the only wait for its load (and not
     // for the other batch's, issued later) sits before the row loop.
     asm volatile("" ::"v"(cur.x), "v"(cur.y), "v"(cur.z), "v"(cur.w));
+    if (W) asm volatile("" ::"v"(bt.w));
     for (int j = 0; j < nb; ++j) {
       const float qx = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(cur.x), j));
       const float qy = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(cur.y), j));
       const float qz = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(cur.z), j));
       const int32_t key = __builtin_amdgcn_readlane(__float_as_int(cur.w), j);
+      const float wr = W ? __int_as_float(__builtin_amdgcn_readlane(__float_as_int(bt.w), j)) : 1.0f;
       if (key != gkey) {
         if (gkey >= 0) flush();
         gkey = key;
@@ -251,21 +267,24 @@ __global__ void __launch_bounds__(SMKI_WAVE) k_splat(SplatArgs a) {
       for (int s = 0; s < NS; ++s) {
         // |d2| only guards rounding below 0 when the row sits on the voxel centre
         const float d2 = fmaf(qz, nwz[s], fmaf(qy, nwy[s], fmaf(qx, nwx[s], q2 + w2[s])));
-        const bool in = d2 < a.l2;
+        const bool in = d2 < l2;
         npair += (uint32_t)__popcll(__ballot(in));
         const float d = __builtin_amdgcn_sqrtf(fabsf(d2));
-        const float sv = in ? fmaf(-d, a.inv_l, 1.0f) : 0.0f;
+        const float sv = in ? fmaf(-d, inv_l, 1.0f) : 0.0f;
         const float uu = sv * sv;
         float qq = uu + a.mcoef[1];
 #pragma unroll
         for (int i = 2; i < SMKI_POLY_N; ++i) qq = fmaf(qq, uu, a.mcoef[i]);
-        sum[s] = fmaf(uu * uu, sv * qq, sum[s]);
+        if (W)
+          sum[s] = fmaf(uu * uu, (sv * wr) * qq, sum[s]);
+        else
+          sum[s] = fmaf(uu * uu, sv * qq, sum[s]);
       }
     }
   };
-  float4 ba = load_batch(r0);
+  Batch ba = load_batch(r0);
   for (int32_t base = r0; base < r1; base += 2 * SMKI_WAVE) {
-    const float4 bb = load_batch(base + SMKI_WAVE);
+    const Batch bb = load_batch(base + SMKI_WAVE);
     process(ba, base);
     if (base + SMKI_WAVE >= r1) break;
     ba = load_batch(base + 2 * SMKI_WAVE);
@@ -306,7 +325,6 @@ __global__ void __launch_bounds__(SMKI_WAVE) k_splat(SplatArgs a) {
     }
   }
   // which target blocks received a contribution
-  const int32_t plane_lin = a.slot_lin[slot];
   const int32_t blin = plane_lin % a.g.n_blocks;
   int32_t pb[3];
   unlin3(blin, a.g.nb, pb);
@@ -620,7 +638,12 @@ template <int B, int R, int NSV>
 hipError_t launch_splat_ns(const SplatArgs& a, int64_t n_units, int ns, hipStream_t st) {
   if constexpr (NSV >= Steps<R>::NSMIN) {
     if (ns == NSV) {
-      hipLaunchKernelGGL((k_splat<B, R, NSV>), dim3((unsigned)n_units), dim3(SMKI_WAVE), 0, st, a);
+      if (a.wts)
+        hipLaunchKernelGGL((k_splat<B, R, NSV, true>), dim3((unsigned)n_units), dim3(SMKI_WAVE), 0,
+                           st, a);
+      else
+        hipLaunchKernelGGL((k_splat<B, R, NSV, false>), dim3((unsigned)n_units), dim3(SMKI_WAVE),
+                           0, st, a);
       return hipGetLastError();
     }
     return launch_splat_ns<B, R, NSV - 1>(a, n_units, ns, st);

@@ -1,6 +1,7 @@
 """Differentiable form: predictive loss of held-out labels and its adjoint.
 
-Binding of smki_loss_forward / smki_loss_backward (argument marshalling only).
+Binding of smki_loss_forward / smki_loss_backward and their per-class forms
+(argument marshalling only).
 The backward recomputes kernel weights in the library; it stores nothing per
 pair.  l and sigma0 are taken as 0-d tensors (or floats) so that gradient
 descent on them can run through autograd.
@@ -56,6 +57,80 @@ def loss_backward(train_xyz, train_label, query_xyz, query_label, l, sigma0, alp
                                    _stream(), None, 0, _ptr(alpha_q.contiguous()), _ptr(g),
                                    _ptr(gl), _ptr(gs), _ptr(gt), _ptr(gq)), "smki_loss_backward")
     return gl, gs, gt, gq
+
+
+def _class_params(l, sigma0, K):
+    lk = [float(v) for v in (l.detach().reshape(-1).cpu().tolist() if torch.is_tensor(l) else l)]
+    sk = [float(v) for v in (sigma0.detach().reshape(-1).cpu().tolist() if torch.is_tensor(sigma0)
+                             else sigma0)]
+    if len(lk) != K or len(sk) != K:
+        raise ValueError(f"per-class l and sigma0 must hold K = {K} values")
+    return (C.c_float * K)(*lk), (C.c_float * K)(*sk)
+
+
+def loss_forward_classes(train_xyz, train_label, query_xyz, query_label, l, sigma0, alpha0, K):
+    """Per-class kernels (l, sigma0: K values each): (loss [1], alpha_q [H, K])."""
+    tx, ty = _rows(train_xyz, train_label, "train")
+    qx, qy = _rows(query_xyz, query_label, "query")
+    lk, sk = _class_params(l, sigma0, int(K))
+    loss = torch.empty((1,), dtype=torch.float32, device=qx.device)
+    aq = torch.empty((qx.shape[0], int(K)), dtype=torch.float32, device=qx.device)
+    check(lib().smki_loss_forward_classes(_ptr(tx), _ptr(ty), tx.shape[0], _ptr(qx), _ptr(qy),
+                                          qx.shape[0], lk, sk, float(alpha0), int(K), _stream(),
+                                          None, 0, _ptr(loss), _ptr(aq)),
+          "smki_loss_forward_classes")
+    return loss, aq
+
+
+def loss_backward_classes(train_xyz, train_label, query_xyz, query_label, l, sigma0, alpha0, K,
+                          alpha_q, grad_loss, need_train=True, need_query=True):
+    """(grad_l [K], grad_sigma0 [K], grad_train [N,3] or None, grad_query [H,3] or None)."""
+    tx, ty = _rows(train_xyz, train_label, "train")
+    qx, qy = _rows(query_xyz, query_label, "query")
+    lk, sk = _class_params(l, sigma0, int(K))
+    dev = qx.device
+    gl = torch.empty((int(K),), dtype=torch.float32, device=dev)
+    gs = torch.empty((int(K),), dtype=torch.float32, device=dev)
+    gt = torch.empty((tx.shape[0], 3), dtype=torch.float32, device=dev) if need_train else None
+    gq = torch.empty((qx.shape[0], 3), dtype=torch.float32, device=dev) if need_query else None
+    g = grad_loss.reshape(1).to(torch.float32).contiguous()
+    check(lib().smki_loss_backward_classes(_ptr(tx), _ptr(ty), tx.shape[0], _ptr(qx), _ptr(qy),
+                                           qx.shape[0], lk, sk, float(alpha0), int(K), _stream(),
+                                           None, 0, _ptr(alpha_q.contiguous()), _ptr(g), _ptr(gl),
+                                           _ptr(gs), _ptr(gt), _ptr(gq)),
+          "smki_loss_backward_classes")
+    return gl, gs, gt, gq
+
+
+class PredictiveLossClasses(torch.autograd.Function):
+    """The predictive loss with per-class kernels: l, sigma0 tensors of K values."""
+
+    @staticmethod
+    def forward(ctx, train_xyz, query_xyz, l, sigma0, train_label, query_label, alpha0, K):
+        loss, aq = loss_forward_classes(train_xyz, train_label, query_xyz, query_label, l, sigma0,
+                                        alpha0, K)
+        ctx.save_for_backward(train_xyz, query_xyz, train_label, query_label, aq, l, sigma0)
+        ctx.hp = (float(alpha0), int(K))
+        return loss.reshape(())
+
+    @staticmethod
+    def backward(ctx, grad):
+        tx, qx, ty, qy, aq, l, sigma0 = ctx.saved_tensors
+        a0, K = ctx.hp
+        gl, gs, gt, gq = loss_backward_classes(tx, ty, qx, qy, l, sigma0, a0, K, aq, grad,
+                                               need_train=ctx.needs_input_grad[0],
+                                               need_query=ctx.needs_input_grad[1])
+        return gt, gq, gl.reshape(l.shape), gs.reshape(sigma0.shape), None, None, None, None
+
+
+def predictive_loss_classes(train_xyz, train_label, query_xyz, query_label, l, sigma0, alpha0, K):
+    """l, sigma0: tensors of K values (per-class kernels), differentiable."""
+    if not torch.is_tensor(l):
+        l = torch.tensor(l, dtype=torch.float32, device=query_xyz.device)
+    if not torch.is_tensor(sigma0):
+        sigma0 = torch.tensor(sigma0, dtype=torch.float32, device=query_xyz.device)
+    return PredictiveLossClasses.apply(train_xyz, query_xyz, l, sigma0, train_label, query_label,
+                                       alpha0, K)
 
 
 class PredictiveLoss(torch.autograd.Function):
