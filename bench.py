@@ -159,6 +159,7 @@ def main():
         out["face_blocks"] = bench_face_blocks(torch, m, xyz, lab, vox, s, p, SemanticMap,
                                                args.steps)
         out["soft"] = bench_soft(torch, xyz, vox, s, p, SemanticMap, args.steps)
+        out["per_class"] = bench_per_class(torch, xyz, lab, vox, s, p, SemanticMap, args.steps)
     if not args.no_extras:
         out["fwd_bwd"] = bench_loss(torch, dev, predictive_loss)
     if not args.no_batched:
@@ -266,6 +267,37 @@ def bench_soft(torch, xyz, vox, s, p, SemanticMap, steps):
     st = m.stats()
     return {"measurements": "soft, top-3 class weights per hit", "ms_per_step": ms,
             "hit_rows": st["n_hits"], "voxels_updated": st["n_updated_voxels"],
+            "voxel_updates_per_s": st["n_updated_voxels"] / (ms * 1e-3),
+            "pairs_in_support": st["n_pairs"], "splat_ms": st["splat_ms"],
+            "merge_ms": st["merge_ms"]}
+
+
+def bench_per_class(torch, xyz, lab, vox, s, p, SemanticMap, steps):
+    """Per-class kernels on the same scan: l_k from 0.2 to 0.3 m and sigma0_k
+    from 0.05 to 0.2 (seeded); the stencil follows the largest l_k."""
+    rng = np.random.default_rng(20)
+    lk = rng.choice([0.2, 0.25, 0.3], p.K).tolist()
+    lk[p.free_class] = 0.3
+    sk = rng.choice([0.05, 0.1, 0.2], p.K).tolist()
+    m = SemanticMap.from_params(p, initial_blocks=1 << 15)
+    m.set_class_params(lk, sk)
+
+    def step():
+        m.reset()
+        m.insert_scan(xyz, lab, s.origin, p.free_step)
+        return m.query(vox, alpha=False, var=False, mean=True, label=True, p_occ=True)
+
+    for _ in range(3):
+        step()
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    for _ in range(steps):
+        step()
+    torch.cuda.synchronize()
+    ms = 1e3 * (time.perf_counter() - t) / steps
+    st = m.stats()
+    return {"kernels": "per class, l_k in {0.2, 0.25, 0.3}, sigma0_k in {0.05, 0.1, 0.2}",
+            "ms_per_step": ms, "voxels_updated": st["n_updated_voxels"],
             "voxel_updates_per_s": st["n_updated_voxels"] / (ms * 1e-3),
             "pairs_in_support": st["n_pairs"], "splat_ms": st["splat_ms"],
             "merge_ms": st["merge_ms"]}

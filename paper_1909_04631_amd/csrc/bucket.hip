@@ -135,10 +135,11 @@ __global__ void k_count(const float* __restrict__ xyz, const int32_t* __restrict
     }
     __syncthreads();
   }
-  if (threadIdx.x == 0) {
+  if (threadIdx.x == 0) {   // spread over copies: workgroups rarely contend on one address
+    int32_t* bb = bbox + (blockIdx.x % SMKI_BBOX_COPIES) * 8;
     for (int a = 0; a < 3; ++a) {
-      if (slo[a][0] != INT32_MAX) atomicMin(&bbox[a], slo[a][0]);
-      if (shi[a][0] != INT32_MIN) atomicMax(&bbox[3 + a], shi[a][0]);
+      if (slo[a][0] != INT32_MAX) atomicMin(&bb[a], slo[a][0]);
+      if (shi[a][0] != INT32_MIN) atomicMax(&bb[3 + a], shi[a][0]);
     }
   }
 }

@@ -62,7 +62,8 @@ __global__ void k_csm_voxels(const uint32_t* __restrict__ vbits, int64_t nwords,
   int v = c;
 #pragma unroll
   for (int o = SMKI_WAVE / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, SMKI_WAVE);
-  if ((threadIdx.x & (SMKI_WAVE - 1)) == 0 && v) atomicAdd(out, (unsigned long long)v);
+  if ((threadIdx.x & (SMKI_WAVE - 1)) == 0 && v)
+    atomicAdd(&out[(blockIdx.x % SMKI_STAT_COPIES) * 4], (unsigned long long)v);
 }
 
 __global__ void k_fill_f32(float* __restrict__ p, int64_t n, float v) {

@@ -75,6 +75,40 @@ __global__ void __launch_bounds__(SCAN_THREADS) k_tile_scan(const T* in, T* out,
   if (total && blockIdx.x == gridDim.x - 1 && threadIdx.x == SCAN_THREADS - 1) *total = run;
 }
 
+// The same with each tile's offset computed by the workgroup itself as the sum
+// of the preceding tile sums (for few tiles: saves the launch that scans them).
+template <typename T>
+__global__ void __launch_bounds__(SCAN_THREADS) k_tile_scan_direct(const T* in, T* out, int64_t n,
+                                                                   const T* __restrict__ sums,
+                                                                   T* total) {
+  __shared__ T part[SCAN_THREADS / SMKI_WAVE];
+  T pre = 0;
+  for (int64_t i = threadIdx.x; i < (int64_t)blockIdx.x; i += SCAN_THREADS) pre += sums[i];
+#pragma unroll
+  for (int o = SMKI_WAVE / 2; o > 0; o >>= 1) pre += __shfl_xor(pre, o, SMKI_WAVE);
+  if ((threadIdx.x & (SMKI_WAVE - 1)) == 0) part[threadIdx.x / SMKI_WAVE] = pre;
+  __syncthreads();
+  T off = 0;
+#pragma unroll
+  for (int i = 0; i < SCAN_THREADS / SMKI_WAVE; ++i) off += part[i];
+  const int64_t base = (int64_t)blockIdx.x * SCAN_TILE + (int64_t)threadIdx.x * SCAN_ITEMS;
+  T v[SCAN_ITEMS];
+  T s = 0;
+#pragma unroll
+  for (int i = 0; i < SCAN_ITEMS; ++i) {
+    v[i] = (base + i < n) ? in[base + i] : (T)0;
+    s += v[i];
+  }
+  T tot;
+  T run = block_excl_scan(s, &tot) + off;
+#pragma unroll
+  for (int i = 0; i < SCAN_ITEMS; ++i) {
+    if (base + i < n) out[base + i] = run;
+    run += v[i];
+  }
+  if (total && blockIdx.x == gridDim.x - 1 && threadIdx.x == SCAN_THREADS - 1) *total = run;
+}
+
 template <typename T>
 __global__ void k_zero_total(T* total) { *total = 0; }
 
@@ -105,6 +139,11 @@ hipError_t scan_impl(const T* in, T* out, int64_t n, T* total, T* tmp, hipStream
   T* rest = tmp + tiles + 1;
   hipLaunchKernelGGL(k_tile_sums<T>, dim3((unsigned)tiles), dim3(SCAN_THREADS), 0, st, in, n,
                      sums);
+  if (tiles <= 512) {   // up to 512 tile sums: every workgroup adds its predecessors' itself
+    hipLaunchKernelGGL(k_tile_scan_direct<T>, dim3((unsigned)tiles), dim3(SCAN_THREADS), 0, st, in,
+                       out, n, (const T*)sums, total);
+    return hipGetLastError();
+  }
   hipError_t e = scan_impl<T>(sums, sums, tiles, (T*)nullptr, rest, st);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_tile_scan<T>, dim3((unsigned)tiles), dim3(SCAN_THREADS), 0, st, in, out,

@@ -77,6 +77,28 @@ int bits_for(int64_t n) {  // bits to represent values 0..n-1
 
 bool finite_pos(float x) { return isfinite(x) && x > 0.0f; }
 
+// Bounding-box accumulators of k_count: initial values of every copy, and the
+// reduction of the copies read back (min xyz, max xyz).
+void bbox_init(int32_t* h) {
+  for (int c = 0; c < SMKI_BBOX_COPIES; ++c)
+    for (int a = 0; a < 8; ++a) h[c * 8 + a] = a < 3 ? INT32_MAX : (a < 6 ? INT32_MIN : 0);
+}
+void bbox_reduce(const int32_t* h, int32_t out[6]) {
+  for (int a = 0; a < 3; ++a) {
+    out[a] = INT32_MAX;
+    out[3 + a] = INT32_MIN;
+  }
+  for (int c = 0; c < SMKI_BBOX_COPIES; ++c)
+    for (int a = 0; a < 3; ++a) {
+      out[a] = std::min(out[a], h[c * 8 + a]);
+      out[3 + a] = std::max(out[3 + a], h[c * 8 + 3 + a]);
+    }
+}
+constexpr size_t kBboxInts = 8 * SMKI_BBOX_COPIES;
+constexpr size_t kStatBytes = sizeof(unsigned long long) * 4 * SMKI_STAT_COPIES;
+// Pinned staging (int64 words): [0, 2) counts, [6] error word, [20] row count,
+// [128, 256) bounding-box copies, [256, 512) counter copies.
+
 }  // namespace
 
 struct smki_map {
@@ -96,6 +118,8 @@ struct smki_map {
   uint32_t* d_err = nullptr;
   unsigned long long* d_stats = nullptr;
   StencilOff* d_offs = nullptr;
+  std::vector<StencilOff> dev_offs;      // the stencil now in d_offs
+  int32_t dev_R = -1;
   // kernel of each class (l_k, sigma0_k; all l and sigma0 unless set per class)
   std::vector<float> lk, s0k;
   float4* d_cls = nullptr;  // [K] (l^2, 1/l, sigma0 * Q's leading coefficient, l)
@@ -317,7 +341,7 @@ smki_status insert_csm(smki_map* m, const BucketGeom& g, const PointSet& ps, con
   SMKI_HIP_TRY(hipMemsetAsync(d_cnt, 0, sizeof(int32_t) * 8, q));
   SMKI_HIP_TRY(hipMemsetAsync(d_vbits, 0, sizeof(uint32_t) * std::max<size_t>((size_t)n_t * (B3 / 32), 1), q));
   SMKI_HIP_TRY(hipMemsetAsync(d_contrib, 0, sizeof(int32_t) * std::max<int64_t>(ntk, 1), q));
-  SMKI_HIP_TRY(hipMemsetAsync(m->d_stats, 0, sizeof(unsigned long long) * 4, q));
+  SMKI_HIP_TRY(hipMemsetAsync(m->d_stats, 0, kStatBytes, q));
   SMKI_HIP_TRY(launch_list_targets(d_mark, d_mpos, n_ext, d_tgt, d_ext2t, q));
   SMKI_HIP_TRY(launch_fill_i32(d_active, n_t, 1, q));   // every row block is updated
   SMKI_HIP_TRY(launch_contrib(sa, true, d_contrib, q));
@@ -349,7 +373,7 @@ smki_status insert_csm(smki_map* m, const BucketGeom& g, const PointSet& ps, con
   unsigned long long* h_rows = (unsigned long long*)(m->h_pin + 20);
   *h_rows = (unsigned long long)ps.n;
   SMKI_HIP_TRY(hipMemcpyAsync(m->d_stats + 1, h_rows, sizeof(*h_rows), hipMemcpyHostToDevice, q));
-  SMKI_HIP_TRY(hipMemcpyAsync(m->h_pin + 8, m->d_stats, sizeof(unsigned long long) * 4,
+  SMKI_HIP_TRY(hipMemcpyAsync(m->h_pin + 256, m->d_stats, kStatBytes,
                               hipMemcpyDeviceToHost, q));
   m->n_blocks += n_new;
   m->n_cblocks += n_cnew;
@@ -396,7 +420,7 @@ smki_status insert_impl(smki_map* m, const float* xyz, const int32_t* label, con
   za.add<int64_t>(n);        // off
   za.add<int32_t>(n);        // kept
   za.add<int32_t>(n);        // kpos
-  za.add<int32_t>(8);        // bbox
+  za.add<int32_t>(kBboxInts); // bbox copies
   za.add<int64_t>(4);        // scalars
   za.add<char>(scan_tmp_bytes(n));
   SMKI_HIP_TRY(m->a_hits.reserve(za.total));
@@ -407,13 +431,14 @@ smki_status insert_impl(smki_map* m, const float* xyz, const int32_t* label, con
   int64_t* d_off = A.take<int64_t>(n);
   int32_t* d_kept = A.take<int32_t>(n);
   int32_t* d_kpos = A.take<int32_t>(n);
-  int32_t* d_bbox = A.take<int32_t>(8);
+  int32_t* d_bbox = A.take<int32_t>(kBboxInts);
   int64_t* d_sc = A.take<int64_t>(4);
   void* d_stmp = A.take<char>(scan_tmp_bytes(n));
-  const int32_t bbox0[8] = {INT32_MAX, INT32_MAX, INT32_MAX, INT32_MIN, INT32_MIN, INT32_MIN, 0, 0};
+  int32_t* h_bbox = (int32_t*)(m->h_pin + 128);   // pinned: [SMKI_BBOX_COPIES][8]
+  bbox_init(h_bbox);
   SMKI_HIP_TRY(hipMemcpyAsync(d_soff, offsets, sizeof(int64_t) * (S + 1), hipMemcpyHostToDevice, q));
   SMKI_HIP_TRY(hipMemcpyAsync(d_org, origins, sizeof(float) * 3 * S, hipMemcpyHostToDevice, q));
-  SMKI_HIP_TRY(hipMemcpyAsync(d_bbox, bbox0, sizeof(bbox0), hipMemcpyHostToDevice, q));
+  SMKI_HIP_TRY(hipMemcpyAsync(d_bbox, h_bbox, sizeof(int32_t) * kBboxInts, hipMemcpyHostToDevice, q));
   SMKI_HIP_TRY(hipMemsetAsync(d_sc, 0, sizeof(int64_t) * 4, q));
   SMKI_HIP_TRY(launch_count(xyz, label, probs, n, d_soff, d_org, S, m->res, step, m->K, d_nfree,
                             d_kept, d_bbox, m->d_err, q));
@@ -421,13 +446,13 @@ smki_status insert_impl(smki_map* m, const float* xyz, const int32_t* label, con
   SMKI_HIP_TRY(scan_excl_i32(d_kept, d_kpos, n, (int32_t*)(d_sc + 1), d_stmp, q));
   // sync 1: counts, box, device validation
   SMKI_HIP_TRY(hipMemcpyAsync(m->h_pin, d_sc, sizeof(int64_t) * 2, hipMemcpyDeviceToHost, q));
-  SMKI_HIP_TRY(hipMemcpyAsync(m->h_pin + 2, d_bbox, sizeof(int32_t) * 6, hipMemcpyDeviceToHost, q));
+  SMKI_HIP_TRY(hipMemcpyAsync(h_bbox, d_bbox, sizeof(int32_t) * kBboxInts, hipMemcpyDeviceToHost, q));
   SMKI_HIP_TRY(hipMemcpyAsync(m->h_pin + 6, m->d_err, sizeof(uint32_t), hipMemcpyDeviceToHost, q));
   SMKI_HIP_TRY(hipStreamSynchronize(q));
   const int64_t nf = m->h_pin[0];
   const int64_t nk = (int64_t)(int32_t)(m->h_pin[1] & 0xffffffff);
   int32_t bb[6];
-  memcpy(bb, m->h_pin + 2, sizeof(bb));
+  bbox_reduce(h_bbox, bb);
   const uint32_t derr = (uint32_t)(m->h_pin[6] & 0xffffffffu);
   if (derr) {
     SMKI_HIP_TRY(hipMemsetAsync(m->d_err, 0, sizeof(uint32_t), q));
@@ -553,8 +578,15 @@ smki_status insert_impl(smki_map* m, const float* xyz, const int32_t* label, con
   sa.g = g;
   sa.R = sten.R;
   sa.noff = (int32_t)sten.offs.size();
-  SMKI_HIP_TRY(hipMemcpyAsync(m->d_offs, sten.offs.data(), sizeof(StencilOff) * sten.offs.size(),
-                              hipMemcpyHostToDevice, q));
+  // the stencil changes only with l / res (or the rounding margin)
+  if (sten.R != m->dev_R || sten.offs.size() != m->dev_offs.size() ||
+      memcmp(sten.offs.data(), m->dev_offs.data(), sizeof(StencilOff) * sten.offs.size()) != 0) {
+    SMKI_HIP_TRY(hipStreamSynchronize(q));   // no insert in flight reads the old stencil
+    SMKI_HIP_TRY(hipMemcpy(m->d_offs, sten.offs.data(), sizeof(StencilOff) * sten.offs.size(),
+                           hipMemcpyHostToDevice));
+    m->dev_offs = sten.offs;
+    m->dev_R = sten.R;
+  }
   sa.offs = (const int4*)m->d_offs;
   sa.cls = m->d_cls;
   for (int i = 0; i < SMKI_POLY_N; ++i) sa.mcoef[i] = (float)(kSmkiQ[i] / kSmkiQ[0]);
@@ -588,7 +620,7 @@ smki_status insert_impl(smki_map* m, const float* xyz, const int32_t* label, con
   zc.add<int32_t>(8);
   const int64_t ntk = (int64_t)n_t * m->K;
   zc.add<char>(scan_tmp_bytes(std::max<int64_t>(ntk, 1)));
-  zc.add<int2>(n_units);
+  zc.add<int4>(n_units);
   zc.add<float>((size_t)n_units * DR3);
   zc.add<uint32_t>(n_units);
   zc.add<int4>(n_slots);
@@ -602,7 +634,7 @@ smki_status insert_impl(smki_map* m, const float* xyz, const int32_t* label, con
   int32_t* d_rank = C.take<int32_t>(n_t);
   int32_t* d_cnt = C.take<int32_t>(8);
   void* d_ctmp = C.take<char>(scan_tmp_bytes(std::max<int64_t>(ntk, 1)));
-  int2* d_units = C.take<int2>(n_units);
+  int4* d_units = C.take<int4>(n_units);
   float* d_part = C.take<float>((size_t)n_units * DR3);
   uint32_t* d_umask = C.take<uint32_t>(n_units);
   int4* d_sinfo = C.take<int4>(n_slots);
@@ -621,9 +653,10 @@ smki_status insert_impl(smki_map* m, const float* xyz, const int32_t* label, con
   SMKI_HIP_TRY(hipMemsetAsync(d_cnt, 0, sizeof(int32_t) * 8, q));
   SMKI_HIP_TRY(hipMemsetAsync(d_active, 0, sizeof(int32_t) * std::max<int64_t>(n_t, 1), q));
   SMKI_HIP_TRY(hipMemsetAsync(d_contrib, 0, sizeof(int32_t) * std::max<int64_t>(ntk, 1), q));
-  SMKI_HIP_TRY(hipMemsetAsync(m->d_stats, 0, sizeof(unsigned long long) * 4, q));
+  SMKI_HIP_TRY(hipMemsetAsync(m->d_stats, 0, kStatBytes, q));
   SMKI_HIP_TRY(launch_list_targets(d_mark, d_mpos, n_ext, d_tgt, d_ext2t, q));
-  SMKI_HIP_TRY(launch_unit_table(d_nun, d_ust, (int32_t)max_slots, d_units, q));
+  SMKI_HIP_TRY(launch_unit_table(d_nun, d_ust, ps.head, ps.slot_lin, g.n_blocks, m->chunk,
+                                 (int32_t)max_slots, d_units, q));
   SMKI_HIP_TRY(hipEventRecord(m->ev[0], q));
   SMKI_HIP_TRY(launch_splat(sa, n_units, q));
   SMKI_HIP_TRY(hipEventRecord(m->ev[1], q));
@@ -652,7 +685,7 @@ smki_status insert_impl(smki_map* m, const float* xyz, const int32_t* label, con
   sa.alpha0 = m->alpha0;
   SMKI_HIP_TRY(launch_merge(sa, n_t, q));
   SMKI_HIP_TRY(hipEventRecord(m->ev[3], q));
-  SMKI_HIP_TRY(hipMemcpyAsync(m->h_pin + 8, m->d_stats, sizeof(unsigned long long) * 4,
+  SMKI_HIP_TRY(hipMemcpyAsync(m->h_pin + 256, m->d_stats, kStatBytes,
                               hipMemcpyDeviceToHost, q));
   m->n_blocks += n_new;
   m->n_cblocks += n_cnew;
@@ -716,10 +749,10 @@ smki_status smki_create_map(float res, int32_t block_size, float l, float sigma0
   m->dev.alpha0 = alpha0;
   smki_status rc = SMKI_OK;
   if (hipMalloc((void**)&m->d_err, 64) != hipSuccess ||
-      hipMalloc((void**)&m->d_stats, 64) != hipSuccess ||
+      hipMalloc((void**)&m->d_stats, kStatBytes) != hipSuccess ||
       hipMalloc((void**)&m->d_offs, sizeof(StencilOff) * SMKI_MAX_OFFS) != hipSuccess ||
       hipMalloc((void**)&m->d_cls, sizeof(float4) * K) != hipSuccess ||
-      hipHostMalloc((void**)&m->h_pin, 256, hipHostMallocDefault) != hipSuccess ||
+      hipHostMalloc((void**)&m->h_pin, 8192, hipHostMallocDefault) != hipSuccess ||
       hipEventCreate(&m->ev[0]) != hipSuccess || hipEventCreate(&m->ev[1]) != hipSuccess ||
       hipEventCreate(&m->ev[2]) != hipSuccess || hipEventCreate(&m->ev[3]) != hipSuccess)
     rc = SMKI_E_OOM;
@@ -887,7 +920,11 @@ smki_status smki_last_scan_stats(smki_map* m, smki_scan_stats* out) {
   if (!m || !out) return SMKI_E_INVALID_ARG;
   if (m->stats_pending) {
     SMKI_HIP_TRY(hipStreamSynchronize(m->stream));
-    const unsigned long long* s = (const unsigned long long*)(m->h_pin + 8);
+    // the counters' copies, summed
+    const unsigned long long* c = (const unsigned long long*)(m->h_pin + 256);
+    unsigned long long s[4] = {0, 0, 0, 0};
+    for (int k = 0; k < SMKI_STAT_COPIES; ++k)
+      for (int i = 0; i < 4; ++i) s[i] += c[k * 4 + i];
     m->last.n_updated_voxels = (int64_t)s[0];
     m->last.n_pairs = (int64_t)s[1];
     float ms = 0.0f;
@@ -920,7 +957,7 @@ smki_status smki_free_samples(const float* xyz, const int32_t* label, int64_t n,
   z.add<int64_t>(n);
   z.add<int64_t>(n);
   z.add<int32_t>(n);
-  z.add<int32_t>(8);
+  z.add<int32_t>(kBboxInts);
   z.add<uint32_t>(1);
   z.add<int64_t>(2);
   z.add<char>(scan_tmp_bytes(n));
@@ -934,16 +971,18 @@ smki_status smki_free_samples(const float* xyz, const int32_t* label, int64_t n,
   int64_t* nfree = A.take<int64_t>(n);
   int64_t* off = A.take<int64_t>(n);
   int32_t* kept = A.take<int32_t>(n);
-  int32_t* bbox = A.take<int32_t>(8);
+  int32_t* bbox = A.take<int32_t>(kBboxInts);
   uint32_t* err = A.take<uint32_t>(1);
   int64_t* tot = A.take<int64_t>(2);
   void* tmp = A.take<char>(scan_tmp_bytes(n));
   const int64_t so[2] = {0, n};
-  const int32_t bbox0[8] = {INT32_MAX, INT32_MAX, INT32_MAX, INT32_MIN, INT32_MIN, INT32_MIN, 0, 0};
+  std::vector<int32_t> bbox0(kBboxInts);
+  bbox_init(bbox0.data());
   smki_status rc = SMKI_OK;
   hipError_t e = hipMemcpyAsync(soff, so, sizeof(so), hipMemcpyHostToDevice, q);
   if (e == hipSuccess) e = hipMemcpyAsync(org, origin, sizeof(float) * 3, hipMemcpyHostToDevice, q);
-  if (e == hipSuccess) e = hipMemcpyAsync(bbox, bbox0, sizeof(bbox0), hipMemcpyHostToDevice, q);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(bbox, bbox0.data(), sizeof(int32_t) * kBboxInts, hipMemcpyHostToDevice, q);
   if (e == hipSuccess) e = hipMemsetAsync(err, 0, sizeof(uint32_t), q);
   if (e == hipSuccess)
     e = launch_count(xyz, label, nullptr, n, soff, org, 1, 3.0e38f, free_step, K, nfree, kept,
@@ -986,7 +1025,7 @@ smki_status smki_bucket_cells(const float* xyz, int64_t n, float res, int32_t bl
   tmp_map.B = block_size;
   tmp_map.log2B = ilog2(block_size);
   Sizer z0;
-  z0.add<int32_t>(8);
+  z0.add<int32_t>(kBboxInts);
   z0.add<uint32_t>(1);
   z0.add<int64_t>(n);
   z0.add<int32_t>(n);
@@ -998,31 +1037,35 @@ smki_status smki_bucket_cells(const float* xyz, int64_t n, float res, int32_t bl
   Arena A0;
   A0.base = base0;
   A0.cap = z0.total;
-  int32_t* bbox = A0.take<int32_t>(8);
+  int32_t* bbox = A0.take<int32_t>(kBboxInts);
   uint32_t* err = A0.take<uint32_t>(1);
   int64_t* nfree = A0.take<int64_t>(n);
   int32_t* kept = A0.take<int32_t>(n);
   int32_t* lab = A0.take<int32_t>(n);
   int64_t* soff = A0.take<int64_t>(2);
   float* org = A0.take<float>(4);
-  const int32_t bbox0[8] = {INT32_MAX, INT32_MAX, INT32_MAX, INT32_MIN, INT32_MIN, INT32_MIN, 0, 0};
+  std::vector<int32_t> bbox0(kBboxInts), hbb(kBboxInts);
+  bbox_init(bbox0.data());
   const int64_t so[2] = {0, n};
   const float o0[4] = {0, 0, 0, 0};
-  hipError_t e = hipMemcpyAsync(bbox, bbox0, sizeof(bbox0), hipMemcpyHostToDevice, q);
+  hipError_t e =
+      hipMemcpyAsync(bbox, bbox0.data(), sizeof(int32_t) * kBboxInts, hipMemcpyHostToDevice, q);
   if (e == hipSuccess) e = hipMemcpyAsync(soff, so, sizeof(so), hipMemcpyHostToDevice, q);
   if (e == hipSuccess) e = hipMemcpyAsync(org, o0, sizeof(o0), hipMemcpyHostToDevice, q);
   if (e == hipSuccess) e = hipMemsetAsync(err, 0, sizeof(uint32_t), q);
   if (e == hipSuccess) e = hipMemsetAsync(lab, 0, sizeof(int32_t) * n, q);
   if (e == hipSuccess)
     e = launch_count(xyz, lab, nullptr, n, soff, org, 1, res, 0.0f, 1, nfree, kept, bbox, err, q);
-  int32_t hb[8];
+  int32_t hb[6];
   uint32_t herr = 0;
-  if (e == hipSuccess) e = hipMemcpyAsync(hb, bbox, sizeof(hb), hipMemcpyDeviceToHost, q);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(hbb.data(), bbox, sizeof(int32_t) * kBboxInts, hipMemcpyDeviceToHost, q);
   if (e == hipSuccess) e = hipMemcpyAsync(&herr, err, sizeof(uint32_t), hipMemcpyDeviceToHost, q);
   if (e == hipSuccess) e = hipStreamSynchronize(q);
   (void)hipFreeAsync(base0, q);
   if (e != hipSuccess) return smki_hip_error(e);
   if (herr) return status_of_err(herr);
+  bbox_reduce(hbb.data(), hb);
   const BucketGeom g = make_geom(&tmp_map, hb, hb + 3, 1);
   if (g.n_blocks > (int64_t(1) << 28)) return SMKI_E_CAPACITY;
   Sizer z;

@@ -4,6 +4,7 @@
 
 #define SMKI_COORD_LIM (1 << 20)
 #define SMKI_MAX_SAMPLES_PER_RAY (1 << 20)
+#define SMKI_BBOX_COPIES 32   // bounding-box accumulators (workgroup b updates copy b % 32)
 
 // Dense grid of map blocks covering a bounding box of voxel indices.
 struct BucketGeom {
@@ -44,6 +45,8 @@ struct BucketScratch {
   void* scan_tmp;
 };
 
+// bbox: [SMKI_BBOX_COPIES][8] (min x, y, z, max x, y, z, -, -), every copy
+// initialised to (INT32_MAX x3, INT32_MIN x3); the caller reduces the copies.
 hipError_t launch_count(const float* xyz, const int32_t* label, const float* probs, int64_t n,
                         const int64_t* scan_off, const float* origins, int32_t S, float res,
                         float step, int32_t K, int64_t* nfree, int32_t* kept, int32_t* bbox,

@@ -6,6 +6,7 @@
 #define SMKI_MAX_OFFS 729           // (2 * SMKI_MAX_REACH + 1)^3
 #define SMKI_POLY_N 7               // coefficients of the kernel polynomial
 #define SMKI_CHUNK 1024             // default rows of one (class, block) per splat work unit
+#define SMKI_STAT_COPIES 64         // copies of the insert counters (spread the atomics)
 
 // Sparse kernel of Eq. (8): f(1 - s) = s^5 Q(s^2) with s = 1 - d/l.  Q below is a
 // degree-6 relative least-squares fit in u = s^2 on [0, 1] to the series
@@ -54,7 +55,7 @@ struct SplatArgs {
   const int32_t* slot_lin;    // [slots] (class, block) linear index
   const int32_t* nunits;      // [slots] chunks of the slot
   const int32_t* ustart;      // [slots] first unit of the slot
-  const int2* units;          // [n_units] (slot, chunk)
+  const int4* units;          // [n_units] (first row, end row, slot, class)
   float* part;                // [n_units][(B + 2R)^3] partial sums of each unit's region, by
                               // piece: the region split into the 27 parts that fall in the
                               // unit's block and its neighbours, each contiguous (x, y, z)
@@ -67,13 +68,14 @@ struct SplatArgs {
   int32_t eblo[3], enb[3];
   const int32_t* ext2t;       // [n_ext] extended-grid block -> target index or -1
   const int32_t* tgt_elin;    // [n_targets] extended-grid linear index
-  int32_t* tgt_active;        // [n_targets] 1 if some row reaches the block
+  int32_t* tgt_active;        // [n_targets] 1 if some row reaches the block (set by k_contrib)
   const int32_t* tgt_slot;    // [n_targets] pool slot (-1: inactive)
   const int32_t* contrib;     // [n_targets][K] 1: some row of the class reaches the block
   MapDev map;
   int64_t n_cold;             // class blocks in use before this insert (newer ones are fresh)
   float alpha0;               // prior concentration written to fresh class blocks
-  unsigned long long* stats;  // [0] updated voxels, [1] in-support pairs
+  unsigned long long* stats;  // [SMKI_STAT_COPIES][4]: [0] updated voxels, [1] in-support pairs;
+                              // workgroup b adds to copy b % SMKI_STAT_COPIES
 };
 
 hipError_t launch_mark_targets(const int32_t* slot_lin, const int32_t* d_nslots, int32_t max_slots,
@@ -83,8 +85,9 @@ hipError_t launch_list_targets(const int32_t* mark, const int32_t* mpos, int64_t
                                int32_t* tgt_elin, int32_t* ext2t, hipStream_t st);
 hipError_t launch_slot_units(const int32_t* head, const int32_t* d_nslots, int32_t max_slots,
                              int32_t chunk, int32_t* nunits, hipStream_t st);
-hipError_t launch_unit_table(const int32_t* nunits, const int32_t* ustart, int32_t max_slots,
-                             int2* units, hipStream_t st);
+hipError_t launch_unit_table(const int32_t* nunits, const int32_t* ustart, const int32_t* head,
+                             const int32_t* slot_lin, int64_t n_blocks, int32_t chunk,
+                             int32_t max_slots, int4* units, hipStream_t st);
 hipError_t launch_splat(const SplatArgs& a, int64_t n_units, hipStream_t st);
 hipError_t launch_merge(const SplatArgs& a, int32_t n_targets, hipStream_t st);
 // class blocks: which (target, class) pairs receive rows, which need a new

@@ -88,12 +88,21 @@ __global__ void k_slot_units(const int32_t* __restrict__ head, const int32_t* __
   nunits[s] = u;
 }
 
+// Work units of every slot: (first row, end row, slot, class), chunk rows each.
 __global__ void k_unit_table(const int32_t* __restrict__ nunits, const int32_t* __restrict__ ustart,
-                             int32_t max_slots, int2* __restrict__ units) {
+                             const int32_t* __restrict__ head, const int32_t* __restrict__ slot_lin,
+                             int64_t n_blocks, int32_t chunk, int32_t max_slots,
+                             int4* __restrict__ units) {
   const int32_t s = blockIdx.x * blockDim.x + threadIdx.x;
   if (s >= max_slots) return;
-  const int32_t n = nunits[s], b = ustart[s];
-  for (int32_t k = 0; k < n; ++k) units[b + k] = make_int2(s, k);
+  const int32_t n = nunits[s];
+  if (n == 0) return;
+  const int32_t b = ustart[s], h0 = head[s], h1 = head[s + 1];
+  const int32_t plane = (int32_t)(slot_lin[s] / n_blocks);
+  for (int32_t k = 0; k < n; ++k) {
+    const int32_t r0 = h0 + k * chunk;
+    units[b + k] = make_int4(r0, min(h1, r0 + chunk), s, plane);
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -151,16 +160,15 @@ template <int B, int R, int NS, bool W>
 __global__ void __launch_bounds__(SMKI_WAVE) k_splat(SplatArgs a) {
   constexpr int DR = B + 2 * R;                 // region edge (voxels)
   constexpr int DR3 = DR * DR * DR;
-  __shared__ float acc[DR3 + 1];   // + a dummy slot for pad lanes
+  constexpr int NACC4 = (DR3 + 1 + 3) / 4;
+  __shared__ float4 acc4[NACC4];   // the region + a dummy slot for pad lanes
+  float* acc = (float*)acc4;
   const int lane = threadIdx.x;
-  const int2 u = a.units[blockIdx.x];
-  const int32_t slot = u.x;
-  const int32_t r0 = a.head[slot] + u.y * a.chunk;
-  const int32_t r1 = min(a.head[slot + 1], r0 + a.chunk);
-  const int32_t plane_lin = a.slot_lin[slot];
-  const float4 kc = a.cls[plane_lin / a.g.n_blocks];   // the kernel of the unit's class
+  const int4 u = a.units[blockIdx.x];   // (first row, end row, slot, class)
+  const int32_t r0 = u.x, r1 = u.y;
+  const float4 kc = a.cls[u.w];         // the kernel of the unit's class
   const float l2 = kc.x, inv_l = kc.y, cscale = kc.z;
-  for (int i = lane; i <= DR3; i += SMKI_WAVE) acc[i] = 0.0f;
+  for (int i = lane; i < NACC4; i += SMKI_WAVE) acc4[i] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
   // Per lane, for each step: one voxel offset o of the first-octant stencil
   // (offsets whose centre can lie within l of a point in the (+,+,+) octant of
   // its cell) as a centre offset in metres, and its region-index offset for
@@ -207,7 +215,8 @@ __global__ void __launch_bounds__(SMKI_WAVE) k_splat(SplatArgs a) {
     const int oc = gkey & 7;
     int32_t base[NS];
 #pragma unroll
-    for (int s = 0; s < NS; ++s) base[s] = pad[s] ? DR3 : gcb;
+    // only the last step has pad lanes (NS = ceil(stencil size / 64))
+    for (int s = 0; s < NS; ++s) base[s] = (s == NS - 1 && pad[s]) ? DR3 : gcb;
     __atomic_signal_fence(__ATOMIC_SEQ_CST);
     switch (oc) {
 #define SMKI_FLUSH_CASE(OC)                                                  \
@@ -292,51 +301,46 @@ __global__ void __launch_bounds__(SMKI_WAVE) k_splat(SplatArgs a) {
   }
   if (gkey >= 0) flush();
   __syncthreads();
-  // pieces that received a contribution
-  uint32_t touched = 0;
-#pragma unroll 4
-  for (int i = lane; i < DR3; i += SMKI_WAVE) {
-    if (acc[i] != 0.0f) {
-      const int rx = i / (DR * DR), ry = (i / DR) % DR, rz = i % DR;
-      const int px = rx < R ? 0 : (rx < R + B ? 1 : 2);
-      const int py = ry < R ? 0 : (ry < R + B ? 1 : 2);
-      const int pz = rz < R ? 0 : (rz < R + B ? 1 : 2);
-      touched |= 1u << (px * 9 + py * 3 + pz);
-    }
-  }
-#pragma unroll
-  for (int o = SMKI_WAVE / 2; o > 0; o >>= 1) touched |= __shfl_xor(touched, o, SMKI_WAVE);
-  touched = __builtin_amdgcn_readfirstlane(touched) & a.piece_mask;
-  if (lane == 0) a.umask[blockIdx.x] = touched;
-  // write the non-zero pieces
+  // Write out the pieces that received a contribution (and that the selection
+  // keeps): per piece, every lane reads its elements into registers, the
+  // wavefront votes on any non-zero value, and a non-zero piece is stored
+  // contiguously.  Piece geometry is compile-time, so the index arithmetic
+  // folds to constants.
   using PC = Pieces<B, R>;
   float* out = a.part + (int64_t)blockIdx.x * DR3;
+  constexpr int MAXPER = (B * B * B + SMKI_WAVE - 1) / SMKI_WAVE;   // the largest piece is the block
+  uint32_t touched = 0;
 #pragma unroll
   for (int p = 0; p < 27; ++p) {
-    if (!((touched >> p) & 1u)) continue;
+    if (!((a.piece_mask >> p) & 1u)) continue;
     const int ex = PC::ext(p / 9 - 1), ey = PC::ext((p / 3) % 3 - 1), ez = PC::ext(p % 3 - 1);
     const int sx = PC::rstart(p / 9 - 1), sy = PC::rstart((p / 3) % 3 - 1),
               sz = PC::rstart(p % 3 - 1);
     const int n = ex * ey * ez, b = PC::base(p);
-#pragma unroll 4
-    for (int i = lane; i < n; i += SMKI_WAVE) {
-      const int lx = i / (ey * ez), ly = (i / ez) % ey, lz = i % ez;
-      out[b + i] = acc[((sx + lx) * DR + (sy + ly)) * DR + (sz + lz)];
+    const int per = (n + SMKI_WAVE - 1) / SMKI_WAVE;
+    float v[MAXPER];
+    bool nz = false;
+#pragma unroll
+    for (int k = 0; k < MAXPER; ++k) {
+      v[k] = 0.0f;
+      const int i = lane + k * SMKI_WAVE;
+      if (k < per && i < n) {
+        const int lx = i / (ey * ez), ly = (i / ez) % ey, lz = i % ez;
+        v[k] = acc[((sx + lx) * DR + (sy + ly)) * DR + (sz + lz)];
+        nz = nz || v[k] != 0.0f;
+      }
+    }
+    if (__ballot(nz) == 0) continue;
+    touched |= 1u << p;
+#pragma unroll
+    for (int k = 0; k < MAXPER; ++k) {
+      const int i = lane + k * SMKI_WAVE;
+      if (k < per && i < n) out[b + i] = v[k];
     }
   }
-  // which target blocks received a contribution
-  const int32_t blin = plane_lin % a.g.n_blocks;
-  int32_t pb[3];
-  unlin3(blin, a.g.nb, pb);
-  if (lane < 27 && ((touched >> lane) & 1u)) {
-    const int dx = lane / 9 - 1, dy = (lane / 3) % 3 - 1, dz = lane % 3 - 1;
-    const int64_t e = ((int64_t)(pb[0] + a.g.blo[0] - a.eblo[0] + dx) * a.enb[1] +
-                       (pb[1] + a.g.blo[1] - a.eblo[1] + dy)) * a.enb[2] +
-                      (pb[2] + a.g.blo[2] - a.eblo[2] + dz);
-    const int32_t t = a.ext2t[e];
-    if (t >= 0) a.tgt_active[t] = 1;
-  }
-  if (lane == 0) atomicAdd(&a.stats[1], (unsigned long long)npair);
+  if (lane == 0) a.umask[blockIdx.x] = touched;
+  if (lane == 0)
+    atomicAdd(&a.stats[(blockIdx.x % SMKI_STAT_COPIES) * 4 + 1], (unsigned long long)npair);
 }
 
 // ---------------------------------------------------------------------------
@@ -356,30 +360,80 @@ __global__ void k_slot_info(SplatArgs a) {
 // first lists, once, the neighbours whose regions cover its voxel and the
 // offset of its voxel in the corresponding piece.  The workgroup then looks up
 // the slots of the 27 neighbouring blocks for a group of classes into LDS (all
-// lookups in flight together) and lists the classes that have any.  A block
-// allocated by this insert gets alpha0 in the classes without contributions
-// (stores only).  For every listed class, each thread adds the pieces that
-// cover its voxel (fixed neighbour order, then chunk order; compensated), with
-// the first-chunk loads of all its candidates issued before summing; fresh
-// blocks are written alpha0 + sum, older blocks updated in place where the sum
-// is non-zero.
+// lookups in flight together), keeping for each neighbour only whether its
+// units wrote the piece that lies in this block, and lists the classes that
+// have any.  For every listed class, each thread adds the pieces that cover its
+// voxel (fixed neighbour order, then chunk order; compensated), with the
+// first-chunk loads of all its candidates issued before summing; blocks
+// allocated by this insert are written alpha0 + sum, older blocks updated in
+// place where the sum is non-zero.  The per-thread state is kept small (packed
+// candidates, slot entries re-read from LDS) so that 8 wavefronts fit per SIMD.
 template <int B, int R>
 struct MergeShape {
   static constexpr int B3 = B * B * B;
   static constexpr int NT = B3;                       // threads per workgroup
-  static constexpr int CPG = 64;                      // classes per lookup group (one wavefront)
+  static constexpr int CPG = 32;                      // classes per lookup group
   // neighbours whose region can cover one voxel: per axis 1, 2 (R > 0), or 3 (2R > B)
   static constexpr int AX = R == 0 ? 1 : (2 * R > B ? 3 : 2);
   static constexpr int MAXC = AX * AX * AX;
 };
 
+// Candidate k of voxel vv (coordinates in the target block): the neighbour c
+// (per axis 0, -1 if v < R, +1 if v >= B - R; both only when 2R > B) whose
+// region covers the voxel, which lies in piece 26 - c of that region.  Packed
+// as (neighbour index << 16) | offset of the voxel in the region's pieces, or
+// -1 when the candidate does not apply to this voxel.
 template <int B, int R>
-__global__ void __launch_bounds__(B * B * B) k_merge(SplatArgs a, int32_t n_targets) {
+__device__ __forceinline__ int merge_candidate(const int vv[3], int k) {
+  constexpr int AX = MergeShape<B, R>::AX;
+  const int kk[3] = {k / (AX * AX), (k / AX) % AX, k % AX};
+  int c3[3], l3[3];
+  bool valid = true;
+#pragma unroll
+  for (int q = 0; q < 3; ++q) {
+    int c = 0;
+    if (kk[q] == 1) {
+      if (AX == 2) {
+        c = vv[q] < R ? -1 : (vv[q] >= B - R ? 1 : 0);
+        valid = valid && c != 0;
+      } else {
+        c = -1;
+        valid = valid && vv[q] < R;
+      }
+    } else if (kk[q] == 2) {
+      c = 1;
+      valid = valid && vv[q] >= B - R;
+    }
+    c3[q] = c;
+    l3[q] = c > 0 ? vv[q] - (B - R) : vv[q];
+  }
+  const int ci = (c3[0] + 1) * 9 + (c3[1] + 1) * 3 + (c3[2] + 1);
+  const int ey = c3[1] == 0 ? B : R, ez = c3[2] == 0 ? B : R;
+  const int off = pbase<B, R>(26 - ci) + (l3[0] * ey + l3[1]) * ez + l3[2];
+  return valid ? (ci << 16) | off : -1;
+}
+
+// Compensated (Kahan) step.
+__device__ __forceinline__ void kahan_add(float& sm, float& comp, float v) {
+  const float yv = v - comp;
+  const float tv = sm + yv;
+  comp = (tv - sm) - yv;
+  sm = tv;
+}
+
+// B = 8: 64 registers per lane, so that four 8-wavefront blocks fit per CU
+// (the kernel waits on memory; more blocks in flight hide more of it).
+template <int B, int R>
+__global__ void __launch_bounds__(B * B * B)
+    __attribute__((amdgpu_waves_per_eu(B == 8 ? 8 : 1, 8))) k_merge(SplatArgs a, int32_t n_targets) {
   using S = MergeShape<B, R>;
   constexpr int DR = B + 2 * R;
   constexpr int DR3 = DR * DR * DR;
-  constexpr int B3 = S::B3, NT = S::NT, CPG = S::CPG, MAXC = S::MAXC, AX = S::AX;
-  __shared__ int4 ent[CPG * 27];      // [class][neighbour]: (first unit, units, union mask, -)
+  constexpr int B3 = S::B3, NT = S::NT, CPG = S::CPG, MAXC = S::MAXC;
+  // [class][neighbour d]: (first unit, units) of the neighbour's slot if some
+  // unit of it wrote piece 26 - d (the part of its region inside this block),
+  // else (0, 0)
+  __shared__ int2 ent[CPG * 27];
   __shared__ int32_t cflag[CPG], clist[CPG], cblk[CPG], ncls_s;
   __shared__ int32_t red[NT / SMKI_WAVE];
   const int32_t t = blockIdx.x;
@@ -391,38 +445,9 @@ __global__ void __launch_bounds__(B * B * B) k_merge(SplatArgs a, int32_t n_targ
   int32_t pt[3];   // target block on the point grid
   for (int q = 0; q < 3; ++q) pt[q] = bt[q] + a.eblo[q] - a.g.blo[q];
   const int vv[3] = {tid / (B * B), (tid / B) % B, tid % B};
-  // covering neighbours c, per axis: 0, -1 if v < R, +1 if v >= B - R (both only
-  // when 2R > B); the voxel is in piece p = 26 - c of the neighbour's region.
-  // Candidates in a fixed order: cidx = neighbour index or -1, coff = offset.
-  int cidx[MAXC], coff[MAXC];
+  int pk[MAXC];   // candidates, in a fixed order
 #pragma unroll
-  for (int k = 0; k < MAXC; ++k) {
-    const int kk[3] = {k / (AX * AX), (k / AX) % AX, k % AX};
-    int c3[3], l3[3];
-    bool valid = true;
-#pragma unroll
-    for (int q = 0; q < 3; ++q) {
-      int c = 0;
-      if (kk[q] == 1) {
-        if (AX == 2) {
-          c = vv[q] < R ? -1 : (vv[q] >= B - R ? 1 : 0);
-          valid = valid && c != 0;
-        } else {
-          c = -1;
-          valid = valid && vv[q] < R;
-        }
-      } else if (kk[q] == 2) {
-        c = 1;
-        valid = valid && vv[q] >= B - R;
-      }
-      c3[q] = c;
-      l3[q] = c > 0 ? vv[q] - (B - R) : vv[q];
-    }
-    const int ci = (c3[0] + 1) * 9 + (c3[1] + 1) * 3 + (c3[2] + 1);
-    const int ey = c3[1] == 0 ? B : R, ez = c3[2] == 0 ? B : R;
-    cidx[k] = valid ? ci : -1;
-    coff[k] = pbase<B, R>(26 - ci) + (l3[0] * ey + l3[1]) * ez + l3[2];
-  }
+  for (int k = 0; k < MAXC; ++k) pk[k] = merge_candidate<B, R>(vv, k);
   bool upd = false;
   for (int y0 = 0; y0 < a.K; y0 += CPG) {
     const int ny = min(CPG, a.K - y0);
@@ -434,12 +459,15 @@ __global__ void __launch_bounds__(B * B * B) k_merge(SplatArgs a, int32_t n_targ
     for (int i = tid; i < 27 * ny; i += NT) {
       const int d = i / ny, yc = i - d * ny;
       const int px = pt[0] + d / 9 - 1, py = pt[1] + (d / 3) % 3 - 1, pz = pt[2] + d % 3 - 1;
-      int4 e = make_int4(0, 0, 0, 0);
+      int2 e2 = make_int2(0, 0);
       if (px >= 0 && py >= 0 && pz >= 0 && px < a.g.nb[0] && py < a.g.nb[1] && pz < a.g.nb[2]) {
         const int32_t s = a.dense[(((int64_t)px * a.g.nb[1] + py) * a.g.nb[2] + pz) * a.K + y0 + yc];
-        if (s >= 0) e = a.sinfo[s];
+        if (s >= 0) {
+          const int4 e = a.sinfo[s];
+          if ((e.z >> (26 - d)) & 1) e2 = make_int2(e.x, e.y);
+        }
       }
-      ent[yc * 27 + d] = e;
+      ent[yc * 27 + d] = e2;
     }
     __syncthreads();
     if (tid < SMKI_WAVE) {   // list the classes with contributions, in class order
@@ -450,84 +478,56 @@ __global__ void __launch_bounds__(B * B * B) k_merge(SplatArgs a, int32_t n_targ
     }
     __syncthreads();
     const int ncls = ncls_s;
-    if constexpr (MAXC > 8) {
-      // 2R > B (B = 4 with a reach of 3 or 4 voxels): up to 27 candidates,
-      // summed one at a time
-      for (int ic = 0; ic < ncls; ++ic) {
-        const int yc = clist[ic];
-        const int4* E = ent + yc * 27;
-        float sm = 0.0f, comp = 0.0f;
+    for (int ic = 0; ic < ncls; ++ic) {
+      const int yc = clist[ic];
+      const int2* E = ent + yc * 27;
+      float sm = 0.0f, comp = 0.0f;
+      if constexpr (MAXC > 8) {
+        // 2R > B (B = 4 with a reach of 3 or 4 voxels): up to 27 candidates,
+        // summed one at a time
         for (int k = 0; k < MAXC; ++k) {
-          if (cidx[k] < 0) continue;
-          const int4 e = E[cidx[k]];
-          const int p = 26 - cidx[k];
-          if (e.y == 0 || !((e.z >> p) & 1)) continue;
-          for (int32_t w = e.x; w < e.x + e.y; ++w) {
-            if (!((a.umask[w] >> p) & 1u)) continue;
-            const float yv = a.part[(int64_t)w * DR3 + coff[k]] - comp;
-            const float tv = sm + yv;
-            comp = (tv - sm) - yv;
-            sm = tv;
-          }
+          if (pk[k] < 0) continue;
+          const int ci = pk[k] >> 16;
+          const int2 e = E[ci];
+          const int p = 26 - ci;
+          for (int32_t w = e.x; w < e.x + e.y; ++w)
+            if ((a.umask[w] >> p) & 1u)
+              kahan_add(sm, comp, a.part[(int64_t)w * DR3 + (pk[k] & 0xffff)]);
         }
-        const int32_t cb = cblk[yc];   // allocated for every class with rows reaching here
-        float* dst = a.map.calpha + (int64_t)cb * B3 + tid;
-        if (cb >= a.n_cold) {
-          *dst = a.alpha0 + sm;   // class block allocated by this insert: written whole
-        } else if (sm != 0.0f) {
-          *dst += sm;
-        }
-        upd = upd || sm != 0.0f;
-      }
-    } else {
-      for (int ic = 0; ic < ncls; ++ic) {
-        const int yc = clist[ic];
-        const int4* E = ent + yc * 27;
+      } else {
+        // the first unit of every candidate: all loads in flight together
         float first[MAXC];
-        int4 ek[MAXC];
 #pragma unroll
         for (int k = 0; k < MAXC; ++k) {
           first[k] = 0.0f;
-          ek[k] = make_int4(0, 0, 0, 0);
-          if (cidx[k] >= 0) {
-            const int4 e = E[cidx[k]];
-            const int p = 26 - cidx[k];
-            if (e.y != 0 && ((e.z >> p) & 1)) {
-              ek[k] = e;
-              // a single-unit slot's union mask is the unit's own mask
-              if (e.y == 1 || ((a.umask[e.x] >> p) & 1u))
-                first[k] = a.part[(int64_t)e.x * DR3 + coff[k]];
-            }
+          if (pk[k] >= 0) {
+            const int ci = pk[k] >> 16;
+            const int2 e = E[ci];
+            // a single-unit slot's union mask is the unit's own mask
+            if (e.y == 1 || (e.y > 1 && ((a.umask[e.x] >> (26 - ci)) & 1u)))
+              first[k] = a.part[(int64_t)e.x * DR3 + (pk[k] & 0xffff)];
           }
         }
-        float sm = 0.0f, comp = 0.0f;
 #pragma unroll
         for (int k = 0; k < MAXC; ++k) {
-          if (ek[k].y == 0) continue;
-          {
-            const float yv = first[k] - comp;
-            const float tv = sm + yv;
-            comp = (tv - sm) - yv;
-            sm = tv;
-          }
-          const int p = 26 - cidx[k];
-          for (int32_t w = ek[k].x + 1; w < ek[k].x + ek[k].y; ++w) {
-            if (!((a.umask[w] >> p) & 1u)) continue;
-            const float yv = a.part[(int64_t)w * DR3 + coff[k]] - comp;
-            const float tv = sm + yv;
-            comp = (tv - sm) - yv;
-            sm = tv;
-          }
+          if (pk[k] < 0) continue;
+          const int ci = pk[k] >> 16;
+          const int2 e = E[ci];
+          if (e.y == 0) continue;
+          kahan_add(sm, comp, first[k]);
+          for (int32_t w = e.x + 1; w < e.x + e.y; ++w)
+            if ((a.umask[w] >> (26 - ci)) & 1u)
+              kahan_add(sm, comp, a.part[(int64_t)w * DR3 + (pk[k] & 0xffff)]);
         }
-        const int32_t cb = cblk[yc];   // allocated for every class with rows reaching here
-        float* dst = a.map.calpha + (int64_t)cb * B3 + tid;
-        if (cb >= a.n_cold) {
-          *dst = a.alpha0 + sm;   // class block allocated by this insert: written whole
-        } else if (sm != 0.0f) {
-          *dst += sm;
-        }
-        upd = upd || sm != 0.0f;
       }
+      const int32_t cb = cblk[yc];   // allocated for every class with rows reaching here
+      float* dst = a.map.calpha + (int64_t)cb * B3 + tid;
+      if (cb >= a.n_cold) {
+        *dst = a.alpha0 + sm;   // class block allocated by this insert: written whole
+      } else if (sm != 0.0f) {
+        *dst += sm;
+      }
+      upd = upd || sm != 0.0f;
     }
     __syncthreads();
   }
@@ -537,7 +537,7 @@ __global__ void __launch_bounds__(B * B * B) k_merge(SplatArgs a, int32_t n_targ
   if (tid == 0) {
     int32_t tot = 0;
     for (int i = 0; i < NT / SMKI_WAVE; ++i) tot += red[i];
-    atomicAdd(&a.stats[0], (unsigned long long)tot);
+    atomicAdd(&a.stats[(blockIdx.x % SMKI_STAT_COPIES) * 4], (unsigned long long)tot);
   }
 }
 
@@ -558,7 +558,10 @@ __global__ void k_contrib(SplatArgs a, int32_t own_block_only, int32_t* __restri
                        (pb[1] + a.g.blo[1] - a.eblo[1] + dy)) * a.enb[2] +
                       (pb[2] + a.g.blo[2] - a.eblo[2] + dz);
     const int32_t t = a.ext2t[e];
-    if (t >= 0) contrib[(int64_t)t * a.K + y] = 1;
+    if (t >= 0) {
+      contrib[(int64_t)t * a.K + y] = 1;
+      a.tgt_active[t] = 1;   // some row reaches the block
+    }
   }
 }
 
@@ -723,11 +726,12 @@ hipError_t launch_slot_units(const int32_t* head, const int32_t* d_nslots, int32
   return hipGetLastError();
 }
 
-hipError_t launch_unit_table(const int32_t* nunits, const int32_t* ustart, int32_t max_slots,
-                             int2* units, hipStream_t st) {
+hipError_t launch_unit_table(const int32_t* nunits, const int32_t* ustart, const int32_t* head,
+                             const int32_t* slot_lin, int64_t n_blocks, int32_t chunk,
+                             int32_t max_slots, int4* units, hipStream_t st) {
   if (max_slots <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_unit_table, dim3(nblk(max_slots, 256)), dim3(256), 0, st, nunits, ustart,
-                     max_slots, units);
+                     head, slot_lin, n_blocks, chunk, max_slots, units);
   return hipGetLastError();
 }
 
