@@ -205,16 +205,25 @@ __device__ __forceinline__ bool in_grid(const BucketGeom& g, const int32_t b[3])
 
 // Kept hits -> (key, index) and records (unsorted), at rows kpos[i]...  With
 // soft weights (probs non-null) a hit gives one row per class of positive
-// weight, in class order, and wt[row] = that weight.
+// weight, in class order, and wt[row] = that weight.  Also, for the free-sample
+// kernel (workgroups of FREE_WG samples): wgbeam[b] = the beam that holds free
+// sample b FREE_WG (each such sample lies in exactly one beam's range).
+constexpr int FREE_WG = 256;
 template <typename KeyT>
 __global__ void k_hit_keys(const float* __restrict__ xyz, const int32_t* __restrict__ label,
                            const float* __restrict__ probs, int32_t K, int64_t n,
                            const int32_t* __restrict__ kept, const int32_t* __restrict__ kpos,
-                           BucketGeom g, KeyT* __restrict__ keys, uint32_t* __restrict__ idx,
-                           float4* __restrict__ rec, float* __restrict__ wt,
-                           uint32_t* __restrict__ err) {
+                           const int64_t* __restrict__ off, int64_t nf,
+                           int32_t* __restrict__ wgbeam, BucketGeom g, KeyT* __restrict__ keys,
+                           uint32_t* __restrict__ idx, float4* __restrict__ rec,
+                           float* __restrict__ wt, uint32_t* __restrict__ err) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n || !kept[i]) return;
+  if (i >= n) return;
+  if (nf > 0) {
+    const int64_t a0 = off[i], a1 = i + 1 < n ? off[i + 1] : nf;
+    for (int64_t b = (a0 + FREE_WG - 1) / FREE_WG; b * FREE_WG < a1; ++b) wgbeam[b] = (int32_t)i;
+  }
+  if (!kept[i]) return;
   const float px = xyz[3 * i], py = xyz[3 * i + 1], pz = xyz[3 * i + 2];
   int32_t v[3], b[3], l[3];
   voxel_index(px, g.res, &v[0]);
@@ -258,24 +267,14 @@ __global__ void k_free_keys(const float* __restrict__ xyz, int64_t n,
                             int32_t free_class, BucketGeom g, int64_t out_base,
                             KeyT* __restrict__ keys, uint32_t* __restrict__ idx,
                             float4* __restrict__ rec, float* __restrict__ wrow,
-                            uint32_t* __restrict__ err) {
-  // The beams of this workgroup's samples: the first and last are found by two
-  // threads over all beams, every sample then searches only between them.
-  __shared__ int64_t span[2];
-  const int64_t f0 = (int64_t)blockIdx.x * blockDim.x;
-  const int64_t f = f0 + threadIdx.x;
-  if (threadIdx.x == 0 || threadIdx.x == blockDim.x - 1) {
-    const int64_t g = min(f, nf - 1);
-    int64_t lo = 0, hi = n - 1;
-    while (lo < hi) {
-      const int64_t mid = (lo + hi + 1) >> 1;
-      if (off[mid] <= g) lo = mid; else hi = mid - 1;
-    }
-    span[threadIdx.x == 0 ? 0 : 1] = lo;
-  }
-  __syncthreads();
+                            const int32_t* __restrict__ wgbeam, uint32_t* __restrict__ err) {
+  // The beams of this workgroup's samples lie between the beam of its first
+  // sample and the beam of the next workgroup's first sample (wgbeam, written
+  // by k_hit_keys); every sample searches only between them.
+  const int64_t f = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (f >= nf) return;
-  int64_t lo = span[0], hi = span[1];
+  int64_t lo = wgbeam[blockIdx.x];
+  int64_t hi = blockIdx.x + 1 < gridDim.x ? wgbeam[blockIdx.x + 1] : n - 1;
   while (lo < hi) {
     const int64_t mid = (lo + hi + 1) >> 1;
     if (off[mid] <= f) lo = mid; else hi = mid - 1;
@@ -461,13 +460,19 @@ static hipError_t finish_set(PointSet& ps, KeyT* keys, uint32_t* idx, KeyT* akey
   const int64_t n = ps.n;
   if (n <= 0) return hipSuccess;
   hipError_t e;
+  // the last radix pass gathers the records (and weights) into sorted order
+  const SortPayload pl{rec_unsorted, ps.pts, scr.wt, ps.wts};
+  const SortPayload* plp = n > 1 ? &pl : nullptr;
   if (sizeof(KeyT) == 4)
-    e = radix_sort_u32((uint32_t*)keys, idx, (uint32_t*)akeys, aidx, n, key_bits, scr.sort_tmp, st);
+    e = radix_sort_u32((uint32_t*)keys, idx, (uint32_t*)akeys, aidx, n, key_bits, scr.sort_tmp, st,
+                       plp);
   else
-    e = radix_sort_u64((uint64_t*)keys, idx, (uint64_t*)akeys, aidx, n, key_bits, scr.sort_tmp, st);
+    e = radix_sort_u64((uint64_t*)keys, idx, (uint64_t*)akeys, aidx, n, key_bits, scr.sort_tmp, st,
+                       plp);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_permute_rec, dim3(nblk(n, 256)), dim3(256), 0, st, rec_unsorted,
-                     (const float*)scr.wt, idx, n, ps.pts, ps.wts);
+  if (!plp)
+    hipLaunchKernelGGL(k_permute_rec, dim3(nblk(n, 256)), dim3(256), 0, st, rec_unsorted,
+                       (const float*)scr.wt, idx, n, ps.pts, ps.wts);
   const int log2B3 = 3 * g.log2B;
   hipLaunchKernelGGL(k_block_flags<KeyT>, dim3(nblk(n, 256)), dim3(256), 0, st, keys, n, log2B3,
                      scr.flag);
@@ -493,38 +498,44 @@ static hipError_t finish_set(PointSet& ps, KeyT* keys, uint32_t* idx, KeyT* akey
   return hipGetLastError();
 }
 
+template <typename KeyT>
+static hipError_t bucket_scan_t(const float* xyz, const int32_t* label, const float* probs,
+                                int32_t K, int64_t n, const int32_t* kept, const int32_t* kpos,
+                                int64_t nk, const int64_t* off, int64_t nf, int32_t* wgbeam,
+                                const int64_t* scan_off, const float* origins, int32_t S,
+                                float step, int32_t free_class, const BucketGeom& g, PointSet& ps,
+                                BucketScratch& scr, uint32_t* err, hipStream_t st) {
+  if (nk > 0)
+    hipLaunchKernelGGL(k_hit_keys<KeyT>, dim3(nblk(n, 256)), dim3(256), 0, st, xyz, label, probs,
+                       K, n, kept, kpos, off, nf, wgbeam, g, (KeyT*)scr.keys, scr.idx, scr.rec,
+                       scr.wt, err);
+  if (nf > 0)
+    hipLaunchKernelGGL(k_free_keys<KeyT>, dim3(nblk(nf, FREE_WG)), dim3(FREE_WG), 0, st, xyz, n,
+                       off, nf, scan_off, origins, S, step, free_class, g, nk, (KeyT*)scr.keys,
+                       scr.idx, scr.rec, scr.wt, (const int32_t*)wgbeam, err);
+  return finish_set<KeyT>(ps, (KeyT*)scr.keys, scr.idx, (KeyT*)scr.akeys, scr.aidx, scr.rec, g,
+                          g.key_bits, scr, st);
+}
+
 // All training rows of an insert in one sorted set: kept hits at [0, nk), free
 // samples after them; keys carry the class plane, so each (class, block) is a
-// contiguous range.
+// contiguous range.  wgbeam: scratch of free_sample_workgroups(nf) entries.
 hipError_t bucket_scan(const float* xyz, const int32_t* label, const float* probs, int32_t K,
-                       int64_t n, const int32_t* kept,
-                       const int32_t* kpos, int64_t nk, const int64_t* off, int64_t nf,
-                       const int64_t* scan_off, const float* origins, int32_t S, float step,
-                       int32_t free_class, const BucketGeom& g, PointSet& ps, BucketScratch& scr,
-                       uint32_t* err, hipStream_t st) {
+                       int64_t n, const int32_t* kept, const int32_t* kpos, int64_t nk,
+                       const int64_t* off, int64_t nf, int32_t* wgbeam, const int64_t* scan_off,
+                       const float* origins, int32_t S, float step, int32_t free_class,
+                       const BucketGeom& g, PointSet& ps, BucketScratch& scr, uint32_t* err,
+                       hipStream_t st) {
   hipError_t e = launch_fill_i32(ps.dense, g.n_blocks * g.planes, -1, st);
   if (e != hipSuccess || ps.n <= 0) return e;
-  if (g.key_bits <= 32) {
-    if (nk > 0)
-      hipLaunchKernelGGL(k_hit_keys<uint32_t>, dim3(nblk(n, 256)), dim3(256), 0, st, xyz, label, probs,
-                         K, n, kept, kpos, g, (uint32_t*)scr.keys, scr.idx, scr.rec, scr.wt, err);
-    if (nf > 0)
-      hipLaunchKernelGGL(k_free_keys<uint32_t>, dim3(nblk(nf, 256)), dim3(256), 0, st, xyz, n, off,
-                         nf, scan_off, origins, S, step, free_class, g, nk, (uint32_t*)scr.keys,
-                         scr.idx, scr.rec, scr.wt, err);
-    return finish_set<uint32_t>(ps, (uint32_t*)scr.keys, scr.idx, (uint32_t*)scr.akeys, scr.aidx,
-                                scr.rec, g, g.key_bits, scr, st);
-  }
-  if (nk > 0)
-    hipLaunchKernelGGL(k_hit_keys<uint64_t>, dim3(nblk(n, 256)), dim3(256), 0, st, xyz, label, probs,
-                       K, n, kept, kpos, g, (uint64_t*)scr.keys, scr.idx, scr.rec, scr.wt, err);
-  if (nf > 0)
-    hipLaunchKernelGGL(k_free_keys<uint64_t>, dim3(nblk(nf, 256)), dim3(256), 0, st, xyz, n, off,
-                       nf, scan_off, origins, S, step, free_class, g, nk, (uint64_t*)scr.keys,
-                       scr.idx, scr.rec, scr.wt, err);
-  return finish_set<uint64_t>(ps, (uint64_t*)scr.keys, scr.idx, (uint64_t*)scr.akeys, scr.aidx,
-                              scr.rec, g, g.key_bits, scr, st);
+  if (g.key_bits <= 32)
+    return bucket_scan_t<uint32_t>(xyz, label, probs, K, n, kept, kpos, nk, off, nf, wgbeam,
+                                   scan_off, origins, S, step, free_class, g, ps, scr, err, st);
+  return bucket_scan_t<uint64_t>(xyz, label, probs, K, n, kept, kpos, nk, off, nf, wgbeam,
+                                 scan_off, origins, S, step, free_class, g, ps, scr, err, st);
 }
+
+int64_t free_sample_workgroups(int64_t nf) { return nf > 0 ? ceil_div_i64(nf, FREE_WG) : 1; }
 
 hipError_t bucket_rows(const float* xyz, const int32_t* label, int64_t n, const BucketGeom& g,
                        PointSet& ps, BucketScratch& scr, uint32_t* err, hipStream_t st) {

@@ -39,13 +39,15 @@ __global__ void __launch_bounds__(RS_THREADS) k_hist(const K* __restrict__ keys,
   hist[(int64_t)threadIdx.x * ntiles + blockIdx.x] = h[threadIdx.x];
 }
 
+// pl.rec_in (last pass only, optional): also gather the records by value.
 template <typename K>
 __global__ void __launch_bounds__(RS_THREADS) k_scatter(const K* __restrict__ keys,
                                                         const uint32_t* __restrict__ vals,
                                                         K* __restrict__ okeys,
                                                         uint32_t* __restrict__ ovals, int64_t n,
                                                         int shift, uint32_t mask, int64_t ntiles,
-                                                        const uint32_t* __restrict__ offs) {
+                                                        const uint32_t* __restrict__ offs,
+                                                        SortPayload pl) {
   __shared__ uint32_t base_of[RS_BINS];
   __shared__ uint32_t wcnt[RS_WAVES][RS_BINS];
   const int tid = threadIdx.x;
@@ -81,6 +83,10 @@ __global__ void __launch_bounds__(RS_THREADS) k_scatter(const K* __restrict__ ke
       const uint32_t pos = pre + rank;
       okeys[pos] = key;
       ovals[pos] = val;
+      if (pl.rec_in) {
+        pl.rec_out[pos] = pl.rec_in[val];
+        if (pl.w_in) pl.w_out[pos] = pl.w_in[val];
+      }
     }
     __syncthreads();
     uint32_t add = 0;
@@ -96,7 +102,7 @@ __global__ void __launch_bounds__(RS_THREADS) k_scatter(const K* __restrict__ ke
 
 template <typename K>
 hipError_t sort_impl(K* keys, uint32_t* vals, K* akeys, uint32_t* avals, int64_t n, int bits,
-                     void* tmp, hipStream_t st) {
+                     void* tmp, hipStream_t st, const SortPayload* pl) {
   if (n <= 1 || bits <= 0) return hipSuccess;
   const int64_t ntiles = ceil_div_i64(n, RS_TILE);
   uint32_t* hist = (uint32_t*)tmp;
@@ -115,8 +121,10 @@ hipError_t sort_impl(K* keys, uint32_t* vals, K* akeys, uint32_t* avals, int64_t
     hipError_t e = scan_excl_i32((const int32_t*)hist, (int32_t*)hist, RS_BINS * ntiles,
                                  (int32_t*)nullptr, scan_tmp, st);
     if (e != hipSuccess) return e;
+    const SortPayload none{};
     hipLaunchKernelGGL(k_scatter<K>, dim3((unsigned)ntiles), dim3(RS_THREADS), 0, st, src_k,
-                       src_v, dst_k, dst_v, n, shift, mask, ntiles, (const uint32_t*)hist);
+                       src_v, dst_k, dst_v, n, shift, mask, ntiles, (const uint32_t*)hist,
+                       (p == passes - 1 && pl) ? *pl : none);
     K* tk = src_k; src_k = dst_k; dst_k = tk;
     uint32_t* tv = src_v; src_v = dst_v; dst_v = tv;
   }
@@ -137,11 +145,11 @@ size_t radix_tmp_bytes(int64_t n) {
 }
 
 hipError_t radix_sort_u32(uint32_t* keys, uint32_t* vals, uint32_t* ak, uint32_t* av, int64_t n,
-                          int bits, void* tmp, hipStream_t st) {
-  return sort_impl<uint32_t>(keys, vals, ak, av, n, bits, tmp, st);
+                          int bits, void* tmp, hipStream_t st, const SortPayload* pl) {
+  return sort_impl<uint32_t>(keys, vals, ak, av, n, bits, tmp, st, pl);
 }
 
 hipError_t radix_sort_u64(uint64_t* keys, uint32_t* vals, uint64_t* ak, uint32_t* av, int64_t n,
-                          int bits, void* tmp, hipStream_t st) {
-  return sort_impl<uint64_t>(keys, vals, ak, av, n, bits, tmp, st);
+                          int bits, void* tmp, hipStream_t st, const SortPayload* pl) {
+  return sort_impl<uint64_t>(keys, vals, ak, av, n, bits, tmp, st, pl);
 }

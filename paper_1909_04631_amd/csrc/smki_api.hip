@@ -520,6 +520,7 @@ smki_status insert_impl(smki_map* m, const float* xyz, const int32_t* label, con
     zb.add<float>(nt);   // row weights, sorted
     zb.add<float>(nt);   // unsorted
   }
+  zb.add<int32_t>(free_sample_workgroups(nf));
   SMKI_HIP_TRY(m->a_sets.reserve(zb.total));
   Arena& Bz = m->a_sets;
   PointSet ps{};
@@ -550,9 +551,10 @@ smki_status insert_impl(smki_map* m, const float* xyz, const int32_t* label, con
   int32_t* d_ust = Bz.take<int32_t>(max_slots);
   ps.wts = probs ? Bz.take<float>(nt) : nullptr;
   scr.wt = probs ? Bz.take<float>(nt) : nullptr;
+  int32_t* d_wgbeam = Bz.take<int32_t>(free_sample_workgroups(nf));
   SMKI_HIP_TRY(hipMemsetAsync(d_si, 0, sizeof(int32_t) * 8, q));
-  SMKI_HIP_TRY(bucket_scan(xyz, label, probs, m->K, n, d_kept, d_kpos, nk, d_off, nf, d_soff,
-                           d_org, S, step, m->free_class, g, ps, scr, m->d_err, q));
+  SMKI_HIP_TRY(bucket_scan(xyz, label, probs, m->K, n, d_kept, d_kpos, nk, d_off, nf, d_wgbeam,
+                           d_soff, d_org, S, step, m->free_class, g, ps, scr, m->d_err, q));
   SMKI_HIP_TRY(hipMemsetAsync(d_mark, 0, sizeof(int32_t) * n_ext, q));
   SMKI_HIP_TRY(launch_mark_targets(ps.slot_lin, ps.d_nslots, (int32_t)max_slots, g, eblo, enb, DB,
                                    d_mark, q));

@@ -53,11 +53,13 @@ hipError_t launch_count(const float* xyz, const int32_t* label, const float* pro
                         uint32_t* err, hipStream_t st);
 hipError_t launch_fill_i32(int32_t* p, int64_t n, int32_t v, hipStream_t st);
 hipError_t bucket_scan(const float* xyz, const int32_t* label, const float* probs, int32_t K,
-                       int64_t n, const int32_t* kept,
-                       const int32_t* kpos, int64_t nk, const int64_t* off, int64_t nf,
-                       const int64_t* scan_off, const float* origins, int32_t S, float step,
-                       int32_t free_class, const BucketGeom& g, PointSet& ps, BucketScratch& scr,
-                       uint32_t* err, hipStream_t st);
+                       int64_t n, const int32_t* kept, const int32_t* kpos, int64_t nk,
+                       const int64_t* off, int64_t nf, int32_t* wgbeam, const int64_t* scan_off,
+                       const float* origins, int32_t S, float step, int32_t free_class,
+                       const BucketGeom& g, PointSet& ps, BucketScratch& scr, uint32_t* err,
+                       hipStream_t st);
+// entries of bucket_scan's wgbeam scratch for nf free samples
+int64_t free_sample_workgroups(int64_t nf);
 hipError_t bucket_rows(const float* xyz, const int32_t* label, int64_t n, const BucketGeom& g,
                        PointSet& ps, BucketScratch& scr, uint32_t* err, hipStream_t st);
 hipError_t bucket_cells_sort(const float* xyz, int64_t n, const BucketGeom& g, BucketScratch& scr,

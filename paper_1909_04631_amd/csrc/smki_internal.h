@@ -40,11 +40,21 @@ hipError_t scan_excl_i32(const int32_t* in, int32_t* out, int64_t n, int32_t* to
 
 // stable LSD radix sort of (key, value) pairs on the low `bits` bits of the
 // keys.  keys/vals are sorted in place; alt_* are scratch of the same size.
+// With a payload (n > 1), the last pass also writes rec_out[i] = rec_in[value
+// of sorted element i] (and w_out alike when w_in is set).
+struct SortPayload {
+  const float4* rec_in;
+  float4* rec_out;
+  const float* w_in;
+  float* w_out;
+};
 size_t radix_tmp_bytes(int64_t n);
 hipError_t radix_sort_u32(uint32_t* keys, uint32_t* vals, uint32_t* alt_keys, uint32_t* alt_vals,
-                          int64_t n, int bits, void* tmp, hipStream_t st);
+                          int64_t n, int bits, void* tmp, hipStream_t st,
+                          const SortPayload* payload = nullptr);
 hipError_t radix_sort_u64(uint64_t* keys, uint32_t* vals, uint64_t* alt_keys, uint32_t* alt_vals,
-                          int64_t n, int bits, void* tmp, hipStream_t st);
+                          int64_t n, int bits, void* tmp, hipStream_t st,
+                          const SortPayload* payload = nullptr);
 
 // ---------------------------------------------------------------------------
 // small device helpers

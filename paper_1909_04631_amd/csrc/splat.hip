@@ -257,6 +257,8 @@ __global__ void __launch_bounds__(SMKI_WAVE) k_splat(SplatArgs a) {
     // for the other batch's, issued later) sits before the row loop.
     asm volatile("" ::"v"(cur.x), "v"(cur.y), "v"(cur.z), "v"(cur.w));
     if (W) asm volatile("" ::"v"(bt.w));
+    // |q|^2 of every row of the batch, once per lane
+    const float q2l = fmaf(cur.x, cur.x, fmaf(cur.y, cur.y, cur.z * cur.z));
     for (int j = 0; j < nb; ++j) {
       const float qx = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(cur.x), j));
       const float qy = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(cur.y), j));
@@ -269,9 +271,10 @@ __global__ void __launch_bounds__(SMKI_WAVE) k_splat(SplatArgs a) {
         const int c = key >> 3;
         gcb = ((c / (B * B) + R) * DR + ((c / B) % B + R)) * DR + (c % B + R);
       }
-      const float q2 = fmaf(qx, qx, fmaf(qy, qy, qz * qz));
-      // Branch-free: every lane evaluates its pair; out of support (d >= l) s is
-      // forced to 0, which zeroes the weight s^5 Q(s^2).
+      const float q2 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(q2l), j));
+      // Branch-free: every lane evaluates its pair; s = 1 - d/l clamped to [0, 1]
+      // (the clamp is free on the fused multiply-add) is 0 out of support, which
+      // zeroes the weight s^5 Q(s^2).
 #pragma unroll
       for (int s = 0; s < NS; ++s) {
         // |d2| only guards rounding below 0 when the row sits on the voxel centre
@@ -279,7 +282,7 @@ __global__ void __launch_bounds__(SMKI_WAVE) k_splat(SplatArgs a) {
         const bool in = d2 < l2;
         npair += (uint32_t)__popcll(__ballot(in));
         const float d = __builtin_amdgcn_sqrtf(fabsf(d2));
-        const float sv = in ? fmaf(-d, inv_l, 1.0f) : 0.0f;
+        const float sv = __builtin_amdgcn_fmed3f(fmaf(-d, inv_l, 1.0f), 0.0f, 1.0f);
         const float uu = sv * sv;
         float qq = uu + a.mcoef[1];
 #pragma unroll
@@ -456,18 +459,32 @@ __global__ void __launch_bounds__(B * B * B)
       cflag[tid] = a.contrib[(int64_t)t * a.K + y0 + tid];
       cblk[tid] = a.map.cslot[(int64_t)mslot * a.K + y0 + tid];
     }
-    for (int i = tid; i < 27 * ny; i += NT) {
-      const int d = i / ny, yc = i - d * ny;
-      const int px = pt[0] + d / 9 - 1, py = pt[1] + (d / 3) % 3 - 1, pz = pt[2] + d % 3 - 1;
-      int2 e2 = make_int2(0, 0);
-      if (px >= 0 && py >= 0 && pz >= 0 && px < a.g.nb[0] && py < a.g.nb[1] && pz < a.g.nb[2]) {
-        const int32_t s = a.dense[(((int64_t)px * a.g.nb[1] + py) * a.g.nb[2] + pz) * a.K + y0 + yc];
-        if (s >= 0) {
-          const int4 e = a.sinfo[s];
-          if ((e.z >> (26 - d)) & 1) e2 = make_int2(e.x, e.y);
+    // two lookups per thread and round, their loads in flight together
+    for (int i0 = tid; i0 < 27 * ny; i0 += 2 * NT) {
+      int32_t sl[2];
+#pragma unroll
+      for (int j = 0; j < 2; ++j) {
+        const int i = i0 + j * NT;
+        sl[j] = -1;
+        if (i < 27 * ny) {
+          const int d = i / ny, yc = i - d * ny;
+          const int px = pt[0] + d / 9 - 1, py = pt[1] + (d / 3) % 3 - 1, pz = pt[2] + d % 3 - 1;
+          if (px >= 0 && py >= 0 && pz >= 0 && px < a.g.nb[0] && py < a.g.nb[1] && pz < a.g.nb[2])
+            sl[j] = a.dense[(((int64_t)px * a.g.nb[1] + py) * a.g.nb[2] + pz) * a.K + y0 + yc];
         }
       }
-      ent[yc * 27 + d] = e2;
+#pragma unroll
+      for (int j = 0; j < 2; ++j) {
+        const int i = i0 + j * NT;
+        if (i >= 27 * ny) continue;
+        const int d = i / ny, yc = i - d * ny;
+        int2 e2 = make_int2(0, 0);
+        if (sl[j] >= 0) {
+          const int4 e = a.sinfo[sl[j]];
+          if ((e.z >> (26 - d)) & 1) e2 = make_int2(e.x, e.y);
+        }
+        ent[yc * 27 + d] = e2;
+      }
     }
     __syncthreads();
     if (tid < SMKI_WAVE) {   // list the classes with contributions, in class order
