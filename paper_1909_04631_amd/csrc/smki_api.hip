@@ -648,6 +648,7 @@ smki_status insert_impl(smki_map* m, const float* xyz, const int32_t* label, con
   sa.tgt_slot = d_tslot;
   sa.units = d_units;
   sa.part = d_part;
+  sa.part_elems = n_units * DR3;
   sa.umask = d_umask;
   sa.sinfo = d_sinfo;
   sa.n_slots = n_slots;

@@ -56,6 +56,7 @@ struct SplatArgs {
   const int32_t* nunits;      // [slots] chunks of the slot
   const int32_t* ustart;      // [slots] first unit of the slot
   const int4* units;          // [n_units] (first row, end row, slot, class)
+  int64_t part_elems;         // n_units (B + 2R)^3
   float* part;                // [n_units][(B + 2R)^3] partial sums of each unit's region, by
                               // piece: the region split into the 27 parts that fall in the
                               // unit's block and its neighbours, each contiguous (x, y, z)

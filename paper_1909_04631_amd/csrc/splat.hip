@@ -416,6 +416,16 @@ __device__ __forceinline__ int merge_candidate(const int vv[3], int k) {
   return valid ? (ci << 16) | off : -1;
 }
 
+// Partial sum at element off of unit w's region.  Below 4 GiB of partial sums
+// (WIDE false) the address is a 32-bit byte offset from the buffer base, so
+// that a load takes one address register instead of two.
+template <int DR3, bool WIDE>
+__device__ __forceinline__ float part_at(const float* part, int32_t w, int32_t off) {
+  if (WIDE) return part[(int64_t)w * DR3 + off];
+  const uint32_t byte = ((uint32_t)w * (uint32_t)DR3 + (uint32_t)off) * 4u;
+  return *(const float*)((const char*)part + byte);
+}
+
 // Compensated (Kahan) step.
 __device__ __forceinline__ void kahan_add(float& sm, float& comp, float v) {
   const float yv = v - comp;
@@ -424,11 +434,8 @@ __device__ __forceinline__ void kahan_add(float& sm, float& comp, float v) {
   sm = tv;
 }
 
-// B = 8: 64 registers per lane, so that four 8-wavefront blocks fit per CU
-// (the kernel waits on memory; more blocks in flight hide more of it).
-template <int B, int R>
-__global__ void __launch_bounds__(B * B * B)
-    __attribute__((amdgpu_waves_per_eu(B == 8 ? 8 : 1, 8))) k_merge(SplatArgs a, int32_t n_targets) {
+template <int B, int R, bool WIDE>
+__global__ void __launch_bounds__(B * B * B) k_merge(SplatArgs a, int32_t n_targets) {
   using S = MergeShape<B, R>;
   constexpr int DR = B + 2 * R;
   constexpr int DR3 = DR * DR * DR;
@@ -509,7 +516,7 @@ __global__ void __launch_bounds__(B * B * B)
           const int p = 26 - ci;
           for (int32_t w = e.x; w < e.x + e.y; ++w)
             if ((a.umask[w] >> p) & 1u)
-              kahan_add(sm, comp, a.part[(int64_t)w * DR3 + (pk[k] & 0xffff)]);
+              kahan_add(sm, comp, part_at<DR3, WIDE>(a.part, w, pk[k] & 0xffff));
         }
       } else {
         // the first unit of every candidate: all loads in flight together
@@ -522,7 +529,7 @@ __global__ void __launch_bounds__(B * B * B)
             const int2 e = E[ci];
             // a single-unit slot's union mask is the unit's own mask
             if (e.y == 1 || (e.y > 1 && ((a.umask[e.x] >> (26 - ci)) & 1u)))
-              first[k] = a.part[(int64_t)e.x * DR3 + (pk[k] & 0xffff)];
+              first[k] = part_at<DR3, WIDE>(a.part, e.x, pk[k] & 0xffff);
           }
         }
 #pragma unroll
@@ -534,7 +541,7 @@ __global__ void __launch_bounds__(B * B * B)
           kahan_add(sm, comp, first[k]);
           for (int32_t w = e.x + 1; w < e.x + e.y; ++w)
             if ((a.umask[w] >> (26 - ci)) & 1u)
-              kahan_add(sm, comp, a.part[(int64_t)w * DR3 + (pk[k] & 0xffff)]);
+              kahan_add(sm, comp, part_at<DR3, WIDE>(a.part, w, pk[k] & 0xffff));
         }
       }
       const int32_t cb = cblk[yc];   // allocated for every class with rows reaching here
@@ -680,9 +687,14 @@ hipError_t launch_splat_br(const SplatArgs& a, int64_t n_units, int32_t n_target
       return launch_splat_ns<B, R, Steps<R>::NS>(a, n_units, (a.noff + SMKI_WAVE - 1) / SMKI_WAVE,
                                                  st);
   } else {
-    if (n_targets > 0)
-      hipLaunchKernelGGL((k_merge<B, R>), dim3((unsigned)n_targets), dim3(MergeShape<B, R>::NT), 0,
-                         st, a, n_targets);
+    if (n_targets > 0) {
+      if (a.part_elems * sizeof(float) <= (int64_t(1) << 32))
+        hipLaunchKernelGGL((k_merge<B, R, false>), dim3((unsigned)n_targets),
+                           dim3(MergeShape<B, R>::NT), 0, st, a, n_targets);
+      else
+        hipLaunchKernelGGL((k_merge<B, R, true>), dim3((unsigned)n_targets),
+                           dim3(MergeShape<B, R>::NT), 0, st, a, n_targets);
+    }
   }
   return hipGetLastError();
 }
