@@ -40,6 +40,10 @@ __global__ void __launch_bounds__(RS_THREADS) k_hist(const K* __restrict__ keys,
 }
 
 // pl.rec_in (last pass only, optional): also gather the records by value.
+// Every thread loads its RS_ROUNDS elements of the tile up front (one memory
+// latency instead of one per round); the rounds then rank and scatter them in
+// element order.  Per-wave digit counts alternate between two buffers, so a
+// round needs two barriers.
 template <typename K>
 __global__ void __launch_bounds__(RS_THREADS) k_scatter(const K* __restrict__ keys,
                                                         const uint32_t* __restrict__ vals,
@@ -49,54 +53,71 @@ __global__ void __launch_bounds__(RS_THREADS) k_scatter(const K* __restrict__ ke
                                                         const uint32_t* __restrict__ offs,
                                                         SortPayload pl) {
   __shared__ uint32_t base_of[RS_BINS];
-  __shared__ uint32_t wcnt[RS_WAVES][RS_BINS];
+  __shared__ uint32_t wcnt[2][RS_WAVES][RS_BINS];
   const int tid = threadIdx.x;
   const int lane = tid & (SMKI_WAVE - 1);
   const int w = tid / SMKI_WAVE;
   base_of[tid] = offs[(int64_t)tid * ntiles + blockIdx.x];
 #pragma unroll
-  for (int q = 0; q < RS_WAVES; ++q) wcnt[q][tid] = 0;
-  __syncthreads();
+  for (int q = 0; q < RS_WAVES; ++q) {
+    wcnt[0][q][tid] = 0;
+    wcnt[1][q][tid] = 0;
+  }
   const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (SMKI_WAVE - lane));
   const int64_t tile_base = (int64_t)blockIdx.x * RS_TILE;
+  K key[RS_ROUNDS];
+  uint32_t val[RS_ROUNDS];
+#pragma unroll
   for (int r = 0; r < RS_ROUNDS; ++r) {
     const int64_t i = tile_base + (int64_t)r * RS_THREADS + tid;
+    key[r] = i < n ? keys[i] : (K)0;
+    val[r] = i < n ? vals[i] : 0u;
+  }
+  __syncthreads();
+#pragma unroll
+  for (int r = 0; r < RS_ROUNDS; ++r) {
+    const int b = r & 1;
+    const int64_t i = tile_base + (int64_t)r * RS_THREADS + tid;
     const bool valid = i < n;
-    K key = valid ? keys[i] : (K)0;
-    uint32_t val = valid ? vals[i] : 0u;
-    uint32_t d = digit_of(key, shift, mask);
+    const uint32_t d = digit_of(key[r], shift, mask);
     uint64_t peers = __ballot(valid);
 #pragma unroll
-    for (int b = 0; b < 8; ++b) {
-      const bool bit = (d >> b) & 1u;
+    for (int bit_i = 0; bit_i < 8; ++bit_i) {
+      const bool bit = (d >> bit_i) & 1u;
       const uint64_t m = __ballot(bit);
       peers &= bit ? m : ~m;
     }
     const uint32_t rank = (uint32_t)__popcll(peers & lt_mask);
     const uint32_t cnt = (uint32_t)__popcll(peers);
     const bool leader = valid && ((peers & lt_mask) == 0);
-    if (leader) wcnt[w][d] = cnt;
+    float4 rv = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+    float wv = 0.0f;
+    if (pl.rec_in && valid) {   // gather early: the load overlaps the ranking
+      rv = pl.rec_in[val[r]];
+      if (pl.w_in) wv = pl.w_in[val[r]];
+    }
+    if (leader) wcnt[b][w][d] = cnt;
     __syncthreads();
     if (valid) {
       uint32_t pre = base_of[d];
-      for (int q = 0; q < w; ++q) pre += wcnt[q][d];
+      for (int q = 0; q < w; ++q) pre += wcnt[b][q][d];
       const uint32_t pos = pre + rank;
-      okeys[pos] = key;
-      ovals[pos] = val;
+      okeys[pos] = key[r];
+      ovals[pos] = val[r];
       if (pl.rec_in) {
-        pl.rec_out[pos] = pl.rec_in[val];
-        if (pl.w_in) pl.w_out[pos] = pl.w_in[val];
+        pl.rec_out[pos] = rv;
+        if (pl.w_in) pl.w_out[pos] = wv;
       }
     }
     __syncthreads();
+    // bin tid: advance past this round's elements, clear this round's counts
     uint32_t add = 0;
 #pragma unroll
     for (int q = 0; q < RS_WAVES; ++q) {
-      add += wcnt[q][tid];
-      wcnt[q][tid] = 0;
+      add += wcnt[b][q][tid];
+      wcnt[b][q][tid] = 0;
     }
     base_of[tid] += add;
-    __syncthreads();
   }
 }
 
