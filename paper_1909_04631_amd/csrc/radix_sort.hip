@@ -39,11 +39,16 @@ __global__ void __launch_bounds__(RS_THREADS) k_hist(const K* __restrict__ keys,
   hist[(int64_t)threadIdx.x * ntiles + blockIdx.x] = h[threadIdx.x];
 }
 
+// Stable scatter of one tile (RS_TILE elements, one workgroup):
+//   1. the tile's digit counts come from the scanned histogram table (entry
+//      (digit, tile) minus the next entry), their exclusive scan gives each
+//      digit's first index inside the tile, and the table entry itself the
+//      digit's first global position;
+//   2. every thread loads its RS_ROUNDS elements, and the rounds rank them in
+//      element order (wave ballots over the digit bits, per-wave counts in LDS);
+//   3. the elements are placed in LDS in digit order, then written out by
+//      consecutive threads, so the stores of each digit's run are contiguous.
 // pl.rec_in (last pass only, optional): also gather the records by value.
-// Every thread loads its RS_ROUNDS elements of the tile up front (one memory
-// latency instead of one per round); the rounds then rank and scatter them in
-// element order.  Per-wave digit counts alternate between two buffers, so a
-// round needs two barriers.
 template <typename K>
 __global__ void __launch_bounds__(RS_THREADS) k_scatter(const K* __restrict__ keys,
                                                         const uint32_t* __restrict__ vals,
@@ -52,19 +57,44 @@ __global__ void __launch_bounds__(RS_THREADS) k_scatter(const K* __restrict__ ke
                                                         int shift, uint32_t mask, int64_t ntiles,
                                                         const uint32_t* __restrict__ offs,
                                                         SortPayload pl) {
-  __shared__ uint32_t base_of[RS_BINS];
+  __shared__ uint32_t gbase[RS_BINS];    // first global position of the tile's digit-d elements
+  __shared__ uint32_t lstart[RS_BINS];   // first index of digit d inside the tile
+  __shared__ uint32_t run_of[RS_BINS];   // digit-d elements ranked so far
   __shared__ uint32_t wcnt[2][RS_WAVES][RS_BINS];
+  __shared__ uint32_t wsum[RS_WAVES];
+  __shared__ K skey[RS_TILE];
+  __shared__ uint32_t sval[RS_TILE];
   const int tid = threadIdx.x;
   const int lane = tid & (SMKI_WAVE - 1);
   const int w = tid / SMKI_WAVE;
-  base_of[tid] = offs[(int64_t)tid * ntiles + blockIdx.x];
-#pragma unroll
-  for (int q = 0; q < RS_WAVES; ++q) {
-    wcnt[0][q][tid] = 0;
-    wcnt[1][q][tid] = 0;
-  }
-  const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (SMKI_WAVE - lane));
   const int64_t tile_base = (int64_t)blockIdx.x * RS_TILE;
+  // 1. digit counts of the tile and their exclusive scan (bin tid)
+  {
+    const int64_t e = (int64_t)tid * ntiles + blockIdx.x;
+    const uint32_t g0 = offs[e];
+    const uint32_t g1 = e + 1 < (int64_t)RS_BINS * ntiles ? offs[e + 1] : (uint32_t)n;
+    const uint32_t c = g1 - g0;
+    gbase[tid] = g0;
+    uint32_t inc = c;
+#pragma unroll
+    for (int o = 1; o < SMKI_WAVE; o <<= 1) {
+      const uint32_t u = __shfl_up(inc, o, SMKI_WAVE);
+      if (lane >= o) inc += u;
+    }
+    if (lane == SMKI_WAVE - 1) wsum[w] = inc;
+    run_of[tid] = 0;
+#pragma unroll
+    for (int q = 0; q < RS_WAVES; ++q) {
+      wcnt[0][q][tid] = 0;
+      wcnt[1][q][tid] = 0;
+    }
+    __syncthreads();
+    uint32_t pre = 0;
+    for (int q = 0; q < w; ++q) pre += wsum[q];
+    lstart[tid] = pre + inc - c;
+  }
+  // 2. load and rank
+  const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (SMKI_WAVE - lane));
   K key[RS_ROUNDS];
   uint32_t val[RS_ROUNDS];
 #pragma unroll
@@ -74,11 +104,11 @@ __global__ void __launch_bounds__(RS_THREADS) k_scatter(const K* __restrict__ ke
     val[r] = i < n ? vals[i] : 0u;
   }
   __syncthreads();
+  uint32_t lidx[RS_ROUNDS];
 #pragma unroll
   for (int r = 0; r < RS_ROUNDS; ++r) {
     const int b = r & 1;
-    const int64_t i = tile_base + (int64_t)r * RS_THREADS + tid;
-    const bool valid = i < n;
+    const bool valid = tile_base + (int64_t)r * RS_THREADS + tid < n;
     const uint32_t d = digit_of(key[r], shift, mask);
     uint64_t peers = __ballot(valid);
 #pragma unroll
@@ -90,24 +120,13 @@ __global__ void __launch_bounds__(RS_THREADS) k_scatter(const K* __restrict__ ke
     const uint32_t rank = (uint32_t)__popcll(peers & lt_mask);
     const uint32_t cnt = (uint32_t)__popcll(peers);
     const bool leader = valid && ((peers & lt_mask) == 0);
-    float4 rv = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
-    float wv = 0.0f;
-    if (pl.rec_in && valid) {   // gather early: the load overlaps the ranking
-      rv = pl.rec_in[val[r]];
-      if (pl.w_in) wv = pl.w_in[val[r]];
-    }
     if (leader) wcnt[b][w][d] = cnt;
     __syncthreads();
+    lidx[r] = 0;
     if (valid) {
-      uint32_t pre = base_of[d];
+      uint32_t pre = lstart[d] + run_of[d];
       for (int q = 0; q < w; ++q) pre += wcnt[b][q][d];
-      const uint32_t pos = pre + rank;
-      okeys[pos] = key[r];
-      ovals[pos] = val[r];
-      if (pl.rec_in) {
-        pl.rec_out[pos] = rv;
-        if (pl.w_in) pl.w_out[pos] = wv;
-      }
+      lidx[r] = pre + rank;
     }
     __syncthreads();
     // bin tid: advance past this round's elements, clear this round's counts
@@ -117,7 +136,29 @@ __global__ void __launch_bounds__(RS_THREADS) k_scatter(const K* __restrict__ ke
       add += wcnt[b][q][tid];
       wcnt[b][q][tid] = 0;
     }
-    base_of[tid] += add;
+    run_of[tid] += add;
+  }
+  // 3. place in digit order, then write out contiguously
+#pragma unroll
+  for (int r = 0; r < RS_ROUNDS; ++r) {
+    if (tile_base + (int64_t)r * RS_THREADS + tid < n) {
+      skey[lidx[r]] = key[r];
+      sval[lidx[r]] = val[r];
+    }
+  }
+  __syncthreads();
+  const int tile_n = (int)min((int64_t)RS_TILE, n - tile_base);
+  for (int j = tid; j < tile_n; j += RS_THREADS) {
+    const K k = skey[j];
+    const uint32_t v = sval[j];
+    const uint32_t d = digit_of(k, shift, mask);
+    const uint32_t pos = gbase[d] + ((uint32_t)j - lstart[d]);
+    okeys[pos] = k;
+    ovals[pos] = v;
+    if (pl.rec_in) {
+      pl.rec_out[pos] = pl.rec_in[v];
+      if (pl.w_in) pl.w_out[pos] = pl.w_in[v];
+    }
   }
 }
 
