@@ -122,6 +122,16 @@ smki_status smki_destroy_map(smki_map *m);
  */
 smki_status smki_set_class_params(smki_map *m, const float *l, const float *sigma0);
 
+/*
+ * Kernel times of the last inserts, oldest first (synchronises the map's
+ * stream): splat_ms[i] the accumulation of Eq. (7)-(8) (HIP events around the
+ * splat), merge_ms[i] the allocation of new blocks and the merge into the map.
+ * The map keeps the times of its last 64 inserts; *count receives how many
+ * were written (at most max).  splat_ms, merge_ms host float32 [max].
+ */
+smki_status smki_kernel_times(smki_map *m, int32_t max, float *splat_ms, float *merge_ms,
+                              int32_t *count);
+
 /* Stream (a hipStream_t, e.g. torch.cuda.current_stream().cuda_stream) on which
  * the map enqueues its work; NULL = the default stream. */
 smki_status smki_set_stream(smki_map *m, void *hip_stream);
@@ -199,7 +209,9 @@ smki_status smki_num_blocks(smki_map *m, int64_t *n_blocks);
  */
 smki_status smki_export(smki_map *m, int64_t capacity, int64_t *n_blocks, int32_t *block_ijk,
                         float *alpha);
-/* Replace the map's contents with n exported blocks (device arrays as above). */
+/* Replace the map's contents with n exported blocks (device arrays as above).
+ * n = 0 empties the map (capacity is kept) without synchronising the stream;
+ * n > 0 synchronises it once to size the class blocks. */
 smki_status smki_import(smki_map *m, int64_t n, const int32_t *block_ijk, const float *alpha);
 
 smki_status smki_last_scan_stats(smki_map *m, smki_scan_stats *out);

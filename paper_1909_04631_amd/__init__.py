@@ -179,6 +179,14 @@ class SemanticMap:
         check(lib().smki_last_scan_stats(self._h, C.byref(s)), "smki_last_scan_stats")
         return s.as_dict()
 
+    def kernel_times(self, last=64):
+        """(splat_ms, merge_ms) lists of the last inserts, oldest first."""
+        sp = (C.c_float * last)()
+        mg = (C.c_float * last)()
+        n = C.c_int32(0)
+        check(lib().smki_kernel_times(self._h, int(last), sp, mg, C.byref(n)), "smki_kernel_times")
+        return list(sp[:n.value]), list(mg[:n.value])
+
     def sync(self):
         check(lib().smki_sync(self._h), "smki_sync")
 

@@ -20,7 +20,7 @@ STATUS_NAMES = {
 EXPORTED = [
     "smki_status_string", "smki_create_map", "smki_destroy_map", "smki_set_class_params",
     "smki_set_stream", "smki_insert_scan", "smki_insert_scan_soft", "smki_insert_scans",
-    "smki_query", "smki_num_blocks", "smki_export", "smki_import", "smki_last_scan_stats", "smki_sync", "smki_free_samples", "smki_bucket_cells",
+    "smki_query", "smki_num_blocks", "smki_export", "smki_import", "smki_kernel_times", "smki_last_scan_stats", "smki_sync", "smki_free_samples", "smki_bucket_cells",
     "smki_loss_workspace_bytes", "smki_loss_forward", "smki_loss_backward",
     "smki_loss_forward_classes", "smki_loss_backward_classes",
 ]
@@ -79,6 +79,9 @@ def lib():
     L.smki_destroy_map.argtypes = [vp]
     L.smki_set_stream.restype = st
     L.smki_set_stream.argtypes = [vp, vp]
+    L.smki_kernel_times.restype = st
+    L.smki_kernel_times.argtypes = [vp, i32, C.POINTER(C.c_float), C.POINTER(C.c_float),
+                                    C.POINTER(C.c_int32)]
     L.smki_set_class_params.restype = st
     L.smki_set_class_params.argtypes = [vp, C.POINTER(C.c_float), C.POINTER(C.c_float)]
     L.smki_insert_scan.restype = st

@@ -127,9 +127,15 @@ struct smki_map {
   Arena a_hits, a_sets, a_tgts, a_misc;
   // pinned host staging
   int64_t* h_pin = nullptr;
+  char* h_hdr = nullptr;   // pinned staging of an insert's first-phase header
+  size_t h_hdr_cap = 0;
   smki_scan_stats last{};
   bool stats_pending = false;
-  hipEvent_t ev[4] = {};  // bracket the splat [0, 1] and the allocation + merge [2, 3]
+  // per insert: events around the splat [0, 1] and the allocation + merge [2, 3],
+  // kept for the last SMKI_TIMING_RING inserts; ev points at the current set
+  hipEvent_t evr[SMKI_TIMING_RING][4] = {};
+  hipEvent_t* ev = evr[0];
+  int64_t n_timed = 0;    // inserts that recorded a set
 };
 
 // ---------------------------------------------------------------------------
@@ -323,28 +329,30 @@ smki_status insert_csm(smki_map* m, const BucketGeom& g, const PointSet& ps, con
   for (int i = 0; i < 3; ++i) zc.add<int32_t>(ntk);
   SMKI_HIP_TRY(m->a_tgts.reserve(zc.total));
   Arena& C = m->a_tgts;
+  // cleared together: counts, voxel bits, contribution flags
+  int32_t* d_cnt = C.take<int32_t>(8);
+  uint32_t* d_vbits = C.take<uint32_t>((size_t)n_t * (B3 / 32));
+  int32_t* d_contrib = C.take<int32_t>(ntk);
   int32_t* d_tgt = C.take<int32_t>(n_t);
   int32_t* d_active = C.take<int32_t>(n_t);
   int32_t* d_tslot = C.take<int32_t>(n_t);
   int32_t* d_isnew = C.take<int32_t>(n_t);
   int32_t* d_rank = C.take<int32_t>(n_t);
-  int32_t* d_cnt = C.take<int32_t>(8);
   void* d_ctmp = C.take<char>(scan_tmp_bytes(std::max<int64_t>(ntk, 1)));
-  uint32_t* d_vbits = C.take<uint32_t>((size_t)n_t * (B3 / 32));
-  int32_t* d_contrib = C.take<int32_t>(ntk);
   int32_t* d_need = C.take<int32_t>(ntk);
   int32_t* d_cpos = C.take<int32_t>(ntk);
   sa.tgt_elin = d_tgt;
   sa.tgt_active = d_active;
   sa.tgt_slot = d_tslot;
   sa.contrib = d_contrib;
-  SMKI_HIP_TRY(hipMemsetAsync(d_cnt, 0, sizeof(int32_t) * 8, q));
-  SMKI_HIP_TRY(hipMemsetAsync(d_vbits, 0, sizeof(uint32_t) * std::max<size_t>((size_t)n_t * (B3 / 32), 1), q));
-  SMKI_HIP_TRY(hipMemsetAsync(d_contrib, 0, sizeof(int32_t) * std::max<int64_t>(ntk, 1), q));
+  SMKI_HIP_TRY(hipMemsetAsync(d_cnt, 0,
+                              (size_t)((char*)(d_contrib + std::max<int64_t>(ntk, 1)) - (char*)d_cnt),
+                              q));
   SMKI_HIP_TRY(hipMemsetAsync(m->d_stats, 0, kStatBytes, q));
   SMKI_HIP_TRY(launch_list_targets(d_mark, d_mpos, n_ext, d_tgt, d_ext2t, q));
   SMKI_HIP_TRY(launch_fill_i32(d_active, n_t, 1, q));   // every row block is updated
   SMKI_HIP_TRY(launch_contrib(sa, true, d_contrib, q));
+  m->ev = m->evr[m->n_timed++ % SMKI_TIMING_RING];
   SMKI_HIP_TRY(hipEventRecord(m->ev[0], q));
   SMKI_HIP_TRY(hipEventRecord(m->ev[1], q));
   SMKI_HIP_TRY(launch_map_lookup(m->dev, sa, n_t, d_tslot, d_isnew, q));
@@ -413,52 +421,58 @@ smki_status insert_impl(smki_map* m, const float* xyz, const int32_t* label, con
   SMKI_HIP_TRY(hipSetDevice(m->device));
 
   // ---- phase A: per-hit validation, free-sample counts, bounding box ----
+  // A header, uploaded in one copy from pinned memory and read back in one:
+  // [0, 32) counts (zeroed), [32, 36) error word of this phase (zeroed),
+  // [64, 64 + 4 kBboxInts) bounding-box copies, then the scan offsets and origins.
+  constexpr size_t kHdrBox = 64, kHdrTail = 64 + sizeof(int32_t) * kBboxInts;
+  const size_t hdr_bytes = kHdrTail + sizeof(int64_t) * (S + 1) + sizeof(float) * 3 * S;
+  if (hdr_bytes > m->h_hdr_cap) {
+    SMKI_HIP_TRY(hipStreamSynchronize(q));   // the old staging may still be read
+    if (m->h_hdr) (void)hipHostFree(m->h_hdr);
+    m->h_hdr = nullptr;
+    m->h_hdr_cap = 0;
+    SMKI_HIP_TRY(hipHostMalloc((void**)&m->h_hdr, hdr_bytes, hipHostMallocDefault));
+    m->h_hdr_cap = hdr_bytes;
+  }
+  char* hh = m->h_hdr;
+  memset(hh, 0, kHdrBox);
+  bbox_init((int32_t*)(hh + kHdrBox));
+  memcpy(hh + kHdrTail, offsets, sizeof(int64_t) * (S + 1));
+  memcpy(hh + kHdrTail + sizeof(int64_t) * (S + 1), origins, sizeof(float) * 3 * S);
   Sizer za;
-  za.add<int64_t>(S + 1);
-  za.add<float>(3 * (size_t)S);
+  za.add<char>(hdr_bytes);
   za.add<int64_t>(n);        // nfree
   za.add<int64_t>(n);        // off
   za.add<int32_t>(n);        // kept
   za.add<int32_t>(n);        // kpos
-  za.add<int32_t>(kBboxInts); // bbox copies
-  za.add<int64_t>(4);        // scalars
   za.add<char>(scan_tmp_bytes(n));
   SMKI_HIP_TRY(m->a_hits.reserve(za.total));
   Arena& A = m->a_hits;
-  int64_t* d_soff = A.take<int64_t>(S + 1);
-  float* d_org = A.take<float>(3 * (size_t)S);
+  char* d_hdr = A.take<char>(hdr_bytes);
+  int64_t* d_sc = (int64_t*)d_hdr;
+  uint32_t* d_err0 = (uint32_t*)(d_hdr + 32);
+  int32_t* d_bbox = (int32_t*)(d_hdr + kHdrBox);
+  int64_t* d_soff = (int64_t*)(d_hdr + kHdrTail);
+  float* d_org = (float*)(d_hdr + kHdrTail + sizeof(int64_t) * (S + 1));
   int64_t* d_nfree = A.take<int64_t>(n);
   int64_t* d_off = A.take<int64_t>(n);
   int32_t* d_kept = A.take<int32_t>(n);
   int32_t* d_kpos = A.take<int32_t>(n);
-  int32_t* d_bbox = A.take<int32_t>(kBboxInts);
-  int64_t* d_sc = A.take<int64_t>(4);
   void* d_stmp = A.take<char>(scan_tmp_bytes(n));
-  int32_t* h_bbox = (int32_t*)(m->h_pin + 128);   // pinned: [SMKI_BBOX_COPIES][8]
-  bbox_init(h_bbox);
-  SMKI_HIP_TRY(hipMemcpyAsync(d_soff, offsets, sizeof(int64_t) * (S + 1), hipMemcpyHostToDevice, q));
-  SMKI_HIP_TRY(hipMemcpyAsync(d_org, origins, sizeof(float) * 3 * S, hipMemcpyHostToDevice, q));
-  SMKI_HIP_TRY(hipMemcpyAsync(d_bbox, h_bbox, sizeof(int32_t) * kBboxInts, hipMemcpyHostToDevice, q));
-  SMKI_HIP_TRY(hipMemsetAsync(d_sc, 0, sizeof(int64_t) * 4, q));
+  SMKI_HIP_TRY(hipMemcpyAsync(d_hdr, hh, hdr_bytes, hipMemcpyHostToDevice, q));
   SMKI_HIP_TRY(launch_count(xyz, label, probs, n, d_soff, d_org, S, m->res, step, m->K, d_nfree,
-                            d_kept, d_bbox, m->d_err, q));
+                            d_kept, d_bbox, d_err0, q));
   SMKI_HIP_TRY(scan_excl_i64(d_nfree, d_off, n, d_sc, d_stmp, q));
   SMKI_HIP_TRY(scan_excl_i32(d_kept, d_kpos, n, (int32_t*)(d_sc + 1), d_stmp, q));
-  // sync 1: counts, box, device validation
-  SMKI_HIP_TRY(hipMemcpyAsync(m->h_pin, d_sc, sizeof(int64_t) * 2, hipMemcpyDeviceToHost, q));
-  SMKI_HIP_TRY(hipMemcpyAsync(h_bbox, d_bbox, sizeof(int32_t) * kBboxInts, hipMemcpyDeviceToHost, q));
-  SMKI_HIP_TRY(hipMemcpyAsync(m->h_pin + 6, m->d_err, sizeof(uint32_t), hipMemcpyDeviceToHost, q));
+  // sync 1: counts, error word and box in one copy
+  SMKI_HIP_TRY(hipMemcpyAsync(hh, d_hdr, kHdrTail, hipMemcpyDeviceToHost, q));
   SMKI_HIP_TRY(hipStreamSynchronize(q));
-  const int64_t nf = m->h_pin[0];
-  const int64_t nk = (int64_t)(int32_t)(m->h_pin[1] & 0xffffffff);
+  const int64_t nf = ((const int64_t*)hh)[0];
+  const int64_t nk = (int64_t)((const int32_t*)hh)[2];
   int32_t bb[6];
-  bbox_reduce(h_bbox, bb);
-  const uint32_t derr = (uint32_t)(m->h_pin[6] & 0xffffffffu);
-  if (derr) {
-    SMKI_HIP_TRY(hipMemsetAsync(m->d_err, 0, sizeof(uint32_t), q));
-    SMKI_HIP_TRY(hipStreamSynchronize(q));
-    return status_of_err(derr);
-  }
+  bbox_reduce((const int32_t*)(hh + kHdrBox), bb);
+  const uint32_t derr = *(const uint32_t*)(hh + 32);
+  if (derr) return status_of_err(derr);
   m->last.n_hits = nk;
   m->last.n_free = nf;
   if (nk == 0) return SMKI_OK;
@@ -530,10 +544,6 @@ smki_status insert_impl(smki_map* m, const float* xyz, const int32_t* label, con
   ps.slot_lin = Bz.take<int32_t>(max_slots);
   ps.prefix = nullptr;   // the splat needs only the slot ranges
   ps.head = Bz.take<int32_t>(max_slots + 1);
-  int32_t* d_si = Bz.take<int32_t>(8);
-  ps.d_nslots = d_si;
-  int32_t* d_ntgt = d_si + 1;
-  int32_t* d_nunits = d_si + 2;
   BucketScratch scr{};
   scr.keys = Bz.take<uint64_t>(nt);
   scr.akeys = Bz.take<uint64_t>(nt);
@@ -544,6 +554,10 @@ smki_status insert_impl(smki_map* m, const float* xyz, const int32_t* label, con
   scr.slot_excl = Bz.take<int32_t>(nt);
   scr.sort_tmp = Bz.take<char>(radix_tmp_bytes(nt));
   scr.scan_tmp = Bz.take<char>(scan_tmp_bytes(std::max(nt, n_ext)));
+  int32_t* d_si = Bz.take<int32_t>(8);   // counts; cleared with the target marks below
+  ps.d_nslots = d_si;
+  int32_t* d_ntgt = d_si + 1;
+  int32_t* d_nunits = d_si + 2;
   int32_t* d_mark = Bz.take<int32_t>(n_ext);
   int32_t* d_mpos = Bz.take<int32_t>(n_ext);
   int32_t* d_ext2t = Bz.take<int32_t>(n_ext);
@@ -552,10 +566,9 @@ smki_status insert_impl(smki_map* m, const float* xyz, const int32_t* label, con
   ps.wts = probs ? Bz.take<float>(nt) : nullptr;
   scr.wt = probs ? Bz.take<float>(nt) : nullptr;
   int32_t* d_wgbeam = Bz.take<int32_t>(free_sample_workgroups(nf));
-  SMKI_HIP_TRY(hipMemsetAsync(d_si, 0, sizeof(int32_t) * 8, q));
+  SMKI_HIP_TRY(hipMemsetAsync(d_si, 0, (size_t)((char*)(d_mark + n_ext) - (char*)d_si), q));
   SMKI_HIP_TRY(bucket_scan(xyz, label, probs, m->K, n, d_kept, d_kpos, nk, d_off, nf, d_wgbeam,
                            d_soff, d_org, S, step, m->free_class, g, ps, scr, m->d_err, q));
-  SMKI_HIP_TRY(hipMemsetAsync(d_mark, 0, sizeof(int32_t) * n_ext, q));
   SMKI_HIP_TRY(launch_mark_targets(ps.slot_lin, ps.d_nslots, (int32_t)max_slots, g, eblo, enb, DB,
                                    d_mark, q));
   SMKI_HIP_TRY(scan_excl_i32(d_mark, d_mpos, n_ext, d_ntgt, scr.scan_tmp, q));
@@ -629,18 +642,19 @@ smki_status insert_impl(smki_map* m, const float* xyz, const int32_t* label, con
   for (int i = 0; i < 3; ++i) zc.add<int32_t>(ntk);
   SMKI_HIP_TRY(m->a_tgts.reserve(zc.total));
   Arena& C = m->a_tgts;
-  int32_t* d_tgt = C.take<int32_t>(n_t);
+  // cleared together: counts, active flags, contribution flags
+  int32_t* d_cnt = C.take<int32_t>(8);
   int32_t* d_active = C.take<int32_t>(n_t);
+  int32_t* d_contrib = C.take<int32_t>(ntk);
+  int32_t* d_tgt = C.take<int32_t>(n_t);
   int32_t* d_tslot = C.take<int32_t>(n_t);
   int32_t* d_isnew = C.take<int32_t>(n_t);
   int32_t* d_rank = C.take<int32_t>(n_t);
-  int32_t* d_cnt = C.take<int32_t>(8);
   void* d_ctmp = C.take<char>(scan_tmp_bytes(std::max<int64_t>(ntk, 1)));
   int4* d_units = C.take<int4>(n_units);
   float* d_part = C.take<float>((size_t)n_units * DR3);
   uint32_t* d_umask = C.take<uint32_t>(n_units);
   int4* d_sinfo = C.take<int4>(n_slots);
-  int32_t* d_contrib = C.take<int32_t>(ntk);
   int32_t* d_need = C.take<int32_t>(ntk);
   int32_t* d_cpos = C.take<int32_t>(ntk);
   sa.tgt_elin = d_tgt;
@@ -653,13 +667,14 @@ smki_status insert_impl(smki_map* m, const float* xyz, const int32_t* label, con
   sa.sinfo = d_sinfo;
   sa.n_slots = n_slots;
   sa.contrib = d_contrib;
-  SMKI_HIP_TRY(hipMemsetAsync(d_cnt, 0, sizeof(int32_t) * 8, q));
-  SMKI_HIP_TRY(hipMemsetAsync(d_active, 0, sizeof(int32_t) * std::max<int64_t>(n_t, 1), q));
-  SMKI_HIP_TRY(hipMemsetAsync(d_contrib, 0, sizeof(int32_t) * std::max<int64_t>(ntk, 1), q));
+  SMKI_HIP_TRY(hipMemsetAsync(d_cnt, 0,
+                              (size_t)((char*)(d_contrib + std::max<int64_t>(ntk, 1)) - (char*)d_cnt),
+                              q));
   SMKI_HIP_TRY(hipMemsetAsync(m->d_stats, 0, kStatBytes, q));
   SMKI_HIP_TRY(launch_list_targets(d_mark, d_mpos, n_ext, d_tgt, d_ext2t, q));
   SMKI_HIP_TRY(launch_unit_table(d_nun, d_ust, ps.head, ps.slot_lin, g.n_blocks, m->chunk,
                                  (int32_t)max_slots, d_units, q));
+  m->ev = m->evr[m->n_timed++ % SMKI_TIMING_RING];
   SMKI_HIP_TRY(hipEventRecord(m->ev[0], q));
   SMKI_HIP_TRY(launch_splat(sa, n_units, q));
   SMKI_HIP_TRY(hipEventRecord(m->ev[1], q));
@@ -755,10 +770,11 @@ smki_status smki_create_map(float res, int32_t block_size, float l, float sigma0
       hipMalloc((void**)&m->d_stats, kStatBytes) != hipSuccess ||
       hipMalloc((void**)&m->d_offs, sizeof(StencilOff) * SMKI_MAX_OFFS) != hipSuccess ||
       hipMalloc((void**)&m->d_cls, sizeof(float4) * K) != hipSuccess ||
-      hipHostMalloc((void**)&m->h_pin, 8192, hipHostMallocDefault) != hipSuccess ||
-      hipEventCreate(&m->ev[0]) != hipSuccess || hipEventCreate(&m->ev[1]) != hipSuccess ||
-      hipEventCreate(&m->ev[2]) != hipSuccess || hipEventCreate(&m->ev[3]) != hipSuccess)
+      hipHostMalloc((void**)&m->h_pin, 8192, hipHostMallocDefault) != hipSuccess)
     rc = SMKI_E_OOM;
+  for (int i = 0; rc == SMKI_OK && i < SMKI_TIMING_RING; ++i)
+    for (int j = 0; j < 4; ++j)
+      if (hipEventCreate(&m->evr[i][j]) != hipSuccess) rc = SMKI_E_OOM;
   if (rc == SMKI_OK && hipMemset(m->d_err, 0, 64) != hipSuccess) rc = SMKI_E_DEVICE;
   if (rc == SMKI_OK) {
     m->lk.assign(K, l);
@@ -791,8 +807,10 @@ smki_status smki_destroy_map(smki_map* m) {
   if (m->d_offs) (void)hipFree(m->d_offs);
   if (m->d_cls) (void)hipFree(m->d_cls);
   if (m->h_pin) (void)hipHostFree(m->h_pin);
-  for (hipEvent_t e : m->ev)
-    if (e) (void)hipEventDestroy(e);
+  if (m->h_hdr) (void)hipHostFree(m->h_hdr);
+  for (auto& set : m->evr)
+    for (hipEvent_t e : set)
+      if (e) (void)hipEventDestroy(e);
   m->a_hits.release();
   m->a_sets.release();
   m->a_tgts.release();
@@ -916,6 +934,7 @@ smki_status smki_import(smki_map* m, int64_t n, const int32_t* block_ijk, const 
   SMKI_HIP_TRY(launch_hash_clear(m->dev, m->stream));
   SMKI_HIP_TRY(launch_hash_insert_slots(m->dev, 0, n, m->d_err, m->stream));
   m->n_blocks = n;
+  if (n == 0) return SMKI_OK;   // emptying the map: nothing to check, no synchronisation
   return take_device_error(m);
 }
 
@@ -936,6 +955,21 @@ smki_status smki_last_scan_stats(smki_map* m, smki_scan_stats* out) {
     m->stats_pending = false;
   }
   *out = m->last;
+  return SMKI_OK;
+}
+
+smki_status smki_kernel_times(smki_map* m, int32_t max, float* splat_ms, float* merge_ms,
+                              int32_t* count) {
+  if (!m || max < 0 || !count || (max > 0 && (!splat_ms || !merge_ms))) return SMKI_E_INVALID_ARG;
+  SMKI_HIP_TRY(hipStreamSynchronize(m->stream));
+  const int64_t have = std::min<int64_t>(m->n_timed, SMKI_TIMING_RING);
+  const int64_t k = std::min<int64_t>(have, max);
+  for (int64_t i = 0; i < k; ++i) {   // oldest first
+    hipEvent_t* e = m->evr[(m->n_timed - k + i) % SMKI_TIMING_RING];
+    SMKI_HIP_TRY(hipEventElapsedTime(&splat_ms[i], e[0], e[1]));
+    SMKI_HIP_TRY(hipEventElapsedTime(&merge_ms[i], e[2], e[3]));
+  }
+  *count = (int32_t)k;
   return SMKI_OK;
 }
 

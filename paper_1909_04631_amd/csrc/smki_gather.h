@@ -7,6 +7,7 @@
 #define SMKI_POLY_N 7               // coefficients of the kernel polynomial
 #define SMKI_CHUNK 1024             // default rows of one (class, block) per splat work unit
 #define SMKI_STAT_COPIES 64         // copies of the insert counters (spread the atomics)
+#define SMKI_TIMING_RING 64         // inserts whose kernel times are kept
 
 // Sparse kernel of Eq. (8): f(1 - s) = s^5 Q(s^2) with s = 1 - d/l.  Q below is a
 // degree-6 relative least-squares fit in u = s^2 on [0, 1] to the series

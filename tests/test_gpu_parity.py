@@ -321,3 +321,22 @@ def test_extended_block_selection_matches_the_oracle(B):
         a = gm.query(cuda(ie[dropped].astype(np.int32)))["alpha"].cpu().numpy()
         ref = om.lookup(ie[dropped])
         assert rel_err(a, ref).max() <= ALPHA_RTOL
+
+
+def test_kernel_times_and_reset():
+    import torch
+    sc = scenes.make_config(0)
+    p = sc.params
+    s = sc.scans[0]
+    _print_case("kernel times and reset")
+    gm = gpu_map_of(sc)
+    for _ in range(2):
+        gm.insert_scan(cuda(s.xyz), cuda(s.label), s.origin, p.free_step)
+    sp, mg = gm.kernel_times(10)
+    assert len(sp) == len(mg) == 3 and min(sp) > 0 and min(mg) > 0
+    assert len(gm.kernel_times(2)[0]) == 2
+    gm.reset()                      # empties the map without synchronising
+    assert gm.num_blocks() == 0
+    gm.insert_scan(cuda(s.xyz), cuda(s.label), s.origin, p.free_step)
+    torch.cuda.synchronize()
+    compare_map(gm, oracle_map_of(sc), p.K)
