@@ -155,7 +155,7 @@ smki_status status_of_err(uint32_t e) {
 // point at u in [0, 1/2]^3 (voxel units, relative to the cell centre):
 // sum_a dist(o_a, [0, 1/2])^2 < (l/res + margin)^2.  The margin covers a point
 // assigned to the neighbouring cell by the rounding of floor(x / res).  A point
-// in another octant uses the mirrored offsets.  Ordered with z fastest.
+// in another octant uses the mirrored offsets.  Ordered by that distance.
 struct Stencil {
   int32_t R = 0;
   std::vector<StencilOff> offs;
@@ -172,6 +172,14 @@ Stencil make_stencil(double lv, double margin) {
         const double ax = dist(dx), ay = dist(dy), az = dist(dz);
         if (ax * ax + ay * ay + az * az < L * L) s.offs.push_back(StencilOff{dx, dy, dz, 0});
       }
+  // nearest first: the splat's last step then holds the offsets that a row can
+  // reach least often, and is skipped for rows that reach none of them
+  auto key = [&](const StencilOff& o) {
+    const double ax = dist(o.dx), ay = dist(o.dy), az = dist(o.dz);
+    return ax * ax + ay * ay + az * az;
+  };
+  std::stable_sort(s.offs.begin(), s.offs.end(),
+                   [&](const StencilOff& a, const StencilOff& b) { return key(a) < key(b); });
   return s;
 }
 

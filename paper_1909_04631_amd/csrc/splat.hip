@@ -280,7 +280,11 @@ __global__ void __launch_bounds__(SMKI_WAVE) k_splat(SplatArgs a) {
         // |d2| only guards rounding below 0 when the row sits on the voxel centre
         const float d2 = fmaf(qz, nwz[s], fmaf(qy, nwy[s], fmaf(qx, nwx[s], q2 + w2[s])));
         const bool in = d2 < l2;
-        npair += (uint32_t)__popcll(__ballot(in));
+        const uint64_t inm = __ballot(in);
+        npair += (uint32_t)__popcll(inm);
+        // the last step holds the farthest offsets (the stencil is ordered by
+        // distance): a row that reaches none of them skips it
+        if (NS > 1 && s == NS - 1 && inm == 0) continue;
         const float d = __builtin_amdgcn_sqrtf(fabsf(d2));
         const float sv = __builtin_amdgcn_fmed3f(fmaf(-d, inv_l, 1.0f), 0.0f, 1.0f);
         const float uu = sv * sv;
