@@ -162,6 +162,32 @@ def test_recursive_update_and_batched_equal_the_oracle():
     compare_map(gb, om, p.K)
 
 
+def test_batched_many_small_scans_with_empty_ones():
+    # 400 scans of 0..9 hits each, every one from its own origin: the per-hit
+    # scan lookup, empty scans, and a first-phase header larger than usual
+    import torch
+    from paper_1909_04631_amd import SemanticMap
+    sc = scenes.make_config(0)
+    s = sc.scans[0]
+    p = sc.params
+    rng = np.random.default_rng(9)
+    sizes = rng.integers(0, 10, size=400)
+    sizes[::37] = 0
+    offs = np.concatenate([[0], np.cumsum(sizes)])
+    n = int(offs[-1])
+    xyz, lab = s.xyz[:n], s.label[:n]
+    origins = (s.origin + rng.uniform(-0.3, 0.3, size=(400, 3))).astype(np.float32)
+    scans = [scenes.Scan(xyz[offs[i]:offs[i + 1]], lab[offs[i]:offs[i + 1]], origins[i])
+             for i in range(400)]
+    _print_case(f"400 small scans, {n} hits")
+    om = oracle_map_of(sc, scans=scans)
+    gb = SemanticMap.from_params(p)
+    gb.insert_scans(cuda(xyz), cuda(lab), [int(o) for o in offs], [tuple(o) for o in origins],
+                    p.free_step)
+    torch.cuda.synchronize()
+    compare_map(gb, om, p.K)
+
+
 def test_invalid_input_leaves_map_unchanged():
     import torch
     from paper_1909_04631_amd import SmkiError
