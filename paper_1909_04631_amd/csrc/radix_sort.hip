@@ -1,11 +1,12 @@
 // Stable least-significant-digit radix sort of (key, u32 value) pairs.
 //
-// One pass per digit of up to 8 bits: (1) per-tile digit histograms in LDS,
-// (2) an exclusive scan of the digit-major histogram table, (3) a stable
-// scatter in which each element's rank among equal digits inside its tile is
-// found with wave ballots (the peers of a lane are the lanes whose digit
-// agrees on every bit), then combined across the tile's waves and rounds in
-// element order.  Integer work only: bit-exact and run-to-run deterministic.
+// One pass per digit of up to 8 bits: (1) per-tile digit histograms, (2) an
+// exclusive scan of the digit-major histogram table, (3) a stable scatter.  In
+// both kernels a wavefront takes 1024 consecutive elements of its tile and
+// groups equal digits with wave ballots (the peers of a lane are the lanes
+// whose digit agrees on every bit); its running digit counts live in its own
+// LDS row, so rounds need no barrier.  Integer work only: bit-exact and
+// run-to-run deterministic.
 #include "smki_internal.h"
 
 namespace {
@@ -13,6 +14,7 @@ namespace {
 constexpr int RS_THREADS = 256;
 constexpr int RS_WAVES = RS_THREADS / SMKI_WAVE;
 constexpr int RS_ROUNDS = 16;
+constexpr int RS_SPAN = RS_ROUNDS * SMKI_WAVE;   // 1024 consecutive elements per wavefront
 constexpr int RS_TILE = RS_THREADS * RS_ROUNDS;  // 4096 elements per tile
 constexpr int RS_BINS = 256;
 
@@ -21,31 +23,110 @@ __device__ __forceinline__ uint32_t digit_of(K key, int shift, uint32_t mask) {
   return (uint32_t)(key >> shift) & mask;
 }
 
+// Lanes of the wavefront that hold a valid element with digit d (dbits bits).
+__device__ __forceinline__ uint64_t digit_peers(uint32_t d, bool valid, int dbits) {
+  uint64_t peers = __ballot(valid);
+  for (int b = 0; b < dbits; ++b) {
+    const bool bit = (d >> b) & 1u;
+    const uint64_t m = __ballot(bit);
+    peers &= bit ? m : ~m;
+  }
+  return peers;
+}
+
+// Element layout of a tile: wavefront w holds elements [w RS_SPAN, (w+1) RS_SPAN),
+// round r of it the 64 elements from w RS_SPAN + 64 r, lane i the i-th of them;
+// so (wavefront, round, lane) is element order.
+__device__ __forceinline__ int64_t elem_index(int64_t tile_base, int w, int r, int lane) {
+  return tile_base + (int64_t)w * RS_SPAN + (int64_t)r * SMKI_WAVE + lane;
+}
+
+// Per-tile digit counts.  Each wavefront counts its span into its own LDS row:
+// per round, the lowest lane of every group of equal digits adds the group's
+// size (the groups' digits are distinct, so no two lanes write one word, and a
+// wavefront's LDS accesses execute in issue order).
 template <typename K>
 __global__ void __launch_bounds__(RS_THREADS) k_hist(const K* __restrict__ keys, int64_t n,
-                                                     int shift, uint32_t mask, int64_t ntiles,
+                                                     int shift, int dbits, int64_t ntiles,
                                                      uint32_t* __restrict__ hist) {
-  __shared__ uint32_t h[RS_BINS];
-  h[threadIdx.x] = 0;
-  __syncthreads();
-  const int64_t base = (int64_t)blockIdx.x * RS_TILE;
-#pragma unroll 4
+  __shared__ uint32_t wh[RS_WAVES][RS_BINS];
+  const int tid = threadIdx.x, lane = tid & (SMKI_WAVE - 1), w = tid / SMKI_WAVE;
+  const uint32_t mask = (1u << dbits) - 1u;
+  const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (SMKI_WAVE - lane));
+  const int64_t tile_base = (int64_t)blockIdx.x * RS_TILE;
+#pragma unroll
+  for (int q = 0; q < RS_WAVES; ++q) wh[q][tid] = 0;
+  K key[RS_ROUNDS];
+#pragma unroll
   for (int r = 0; r < RS_ROUNDS; ++r) {
-    int64_t i = base + (int64_t)r * RS_THREADS + threadIdx.x;
-    if (i < n) atomicAdd(&h[digit_of(keys[i], shift, mask)], 1u);
+    const int64_t i = elem_index(tile_base, w, r, lane);
+    key[r] = i < n ? keys[i] : (K)0;
   }
   __syncthreads();
+#pragma unroll
+  for (int r = 0; r < RS_ROUNDS; ++r) {
+    const bool valid = elem_index(tile_base, w, r, lane) < n;
+    const uint32_t d = digit_of(key[r], shift, mask);
+    const uint64_t peers = digit_peers(d, valid, dbits);
+    if (valid && (peers & lt_mask) == 0) wh[w][d] += (uint32_t)__popcll(peers);
+    __atomic_signal_fence(__ATOMIC_SEQ_CST);
+  }
+  __syncthreads();
+  uint32_t c = 0;
+#pragma unroll
+  for (int q = 0; q < RS_WAVES; ++q) c += wh[q][tid];
   // digit-major layout: all tiles of digit 0, then digit 1, ...
-  hist[(int64_t)threadIdx.x * ntiles + blockIdx.x] = h[threadIdx.x];
+  hist[(int64_t)tid * ntiles + blockIdx.x] = c;
+}
+
+// Last pass with records: a thread gathers the records (and weights) of eight
+// of the tile's sorted elements before storing any of them.
+template <typename K, bool WT>
+__device__ __forceinline__ void write_records(const K* skey, const uint32_t* sval,
+                                              const uint32_t* gbase, const uint32_t* lstart,
+                                              int tile_n, int shift, uint32_t mask,
+                                              K* __restrict__ okeys, uint32_t* __restrict__ ovals,
+                                              const SortPayload& pl) {
+  constexpr int G = 8;
+  const int tid = threadIdx.x;
+#pragma unroll
+  for (int j0 = 0; j0 < RS_TILE; j0 += G * RS_THREADS) {
+    // Unconditional: a thread past the tile's end takes its last element again
+    // and stores the same values to the same place.
+    float rx[G], ry[G], rz[G], rw[G], wv[G];   // (component arrays stay in registers)
+    K kk[G];
+    uint32_t vv[G], pos[G];
+#pragma unroll
+    for (int g = 0; g < G; ++g) {
+      const int j = min(j0 + g * RS_THREADS + tid, tile_n - 1);
+      kk[g] = skey[j];
+      vv[g] = sval[j];
+      const float4 r = pl.rec_in[vv[g]];
+      rx[g] = r.x;
+      ry[g] = r.y;
+      rz[g] = r.z;
+      rw[g] = r.w;
+      wv[g] = WT ? pl.w_in[vv[g]] : 0.0f;
+      const uint32_t d = digit_of(kk[g], shift, mask);
+      pos[g] = gbase[d] + ((uint32_t)j - lstart[d]);
+    }
+#pragma unroll
+    for (int g = 0; g < G; ++g) {
+      okeys[pos[g]] = kk[g];
+      ovals[pos[g]] = vv[g];
+      pl.rec_out[pos[g]] = make_float4(rx[g], ry[g], rz[g], rw[g]);
+      if (WT) pl.w_out[pos[g]] = wv[g];
+    }
+  }
 }
 
 // Stable scatter of one tile (RS_TILE elements, one workgroup):
-//   1. the tile's digit counts come from the scanned histogram table (entry
-//      (digit, tile) minus the next entry), their exclusive scan gives each
-//      digit's first index inside the tile, and the table entry itself the
-//      digit's first global position;
-//   2. every thread loads its RS_ROUNDS elements, and the rounds rank them in
-//      element order (wave ballots over the digit bits, per-wave counts in LDS);
+//   1. every wavefront loads its span and ranks each element among the equal
+//      digits of its span (wave ballots; per-wavefront running counts in LDS,
+//      no barrier between rounds);
+//   2. per digit, the tile's count and each wavefront's first index inside the
+//      tile (exclusive scans over wavefronts, then over digits); the scanned
+//      histogram table gives the digit's first global position;
 //   3. the elements are placed in LDS in digit order, then written out by
 //      consecutive threads, so the stores of each digit's run are contiguous.
 // pl.rec_in (last pass only, optional): also gather the records by value.
@@ -54,27 +135,53 @@ __global__ void __launch_bounds__(RS_THREADS) k_scatter(const K* __restrict__ ke
                                                         const uint32_t* __restrict__ vals,
                                                         K* __restrict__ okeys,
                                                         uint32_t* __restrict__ ovals, int64_t n,
-                                                        int shift, uint32_t mask, int64_t ntiles,
+                                                        int shift, int dbits, int64_t ntiles,
                                                         const uint32_t* __restrict__ offs,
                                                         SortPayload pl) {
   __shared__ uint32_t gbase[RS_BINS];    // first global position of the tile's digit-d elements
   __shared__ uint32_t lstart[RS_BINS];   // first index of digit d inside the tile
-  __shared__ uint32_t run_of[RS_BINS];   // digit-d elements ranked so far
-  __shared__ uint32_t wcnt[2][RS_WAVES][RS_BINS];
+  __shared__ uint32_t wh[RS_WAVES][RS_BINS];   // per wavefront: digit counts, then first index
   __shared__ uint32_t wsum[RS_WAVES];
   __shared__ K skey[RS_TILE];
   __shared__ uint32_t sval[RS_TILE];
-  const int tid = threadIdx.x;
-  const int lane = tid & (SMKI_WAVE - 1);
-  const int w = tid / SMKI_WAVE;
+  const int tid = threadIdx.x, lane = tid & (SMKI_WAVE - 1), w = tid / SMKI_WAVE;
+  const uint32_t mask = (1u << dbits) - 1u;
+  const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (SMKI_WAVE - lane));
   const int64_t tile_base = (int64_t)blockIdx.x * RS_TILE;
-  // 1. digit counts of the tile and their exclusive scan (bin tid)
+  gbase[tid] = offs[(int64_t)tid * ntiles + blockIdx.x];
+#pragma unroll
+  for (int q = 0; q < RS_WAVES; ++q) wh[q][tid] = 0;
+  K key[RS_ROUNDS];
+  uint32_t val[RS_ROUNDS];
+#pragma unroll
+  for (int r = 0; r < RS_ROUNDS; ++r) {
+    const int64_t i = elem_index(tile_base, w, r, lane);
+    key[r] = i < n ? keys[i] : (K)0;
+    val[r] = i < n ? vals[i] : 0u;
+  }
+  __syncthreads();
+  // 1. rank inside the wavefront's span
+  uint32_t lrank[RS_ROUNDS];
+#pragma unroll
+  for (int r = 0; r < RS_ROUNDS; ++r) {
+    const bool valid = elem_index(tile_base, w, r, lane) < n;
+    const uint32_t d = digit_of(key[r], shift, mask);
+    const uint64_t peers = digit_peers(d, valid, dbits);
+    const uint32_t before = wh[w][d];
+    lrank[r] = before + (uint32_t)__popcll(peers & lt_mask);
+    if (valid && (peers & lt_mask) == 0) wh[w][d] = before + (uint32_t)__popcll(peers);
+    __atomic_signal_fence(__ATOMIC_SEQ_CST);
+  }
+  __syncthreads();
+  // 2. digit tid: the wavefronts' counts, the tile's count and its first index
   {
-    const int64_t e = (int64_t)tid * ntiles + blockIdx.x;
-    const uint32_t g0 = offs[e];
-    const uint32_t g1 = e + 1 < (int64_t)RS_BINS * ntiles ? offs[e + 1] : (uint32_t)n;
-    const uint32_t c = g1 - g0;
-    gbase[tid] = g0;
+    uint32_t pw[RS_WAVES];
+    uint32_t c = 0;
+#pragma unroll
+    for (int q = 0; q < RS_WAVES; ++q) {
+      pw[q] = c;
+      c += wh[q][tid];
+    }
     uint32_t inc = c;
 #pragma unroll
     for (int o = 1; o < SMKI_WAVE; o <<= 1) {
@@ -82,84 +189,42 @@ __global__ void __launch_bounds__(RS_THREADS) k_scatter(const K* __restrict__ ke
       if (lane >= o) inc += u;
     }
     if (lane == SMKI_WAVE - 1) wsum[w] = inc;
-    run_of[tid] = 0;
-#pragma unroll
-    for (int q = 0; q < RS_WAVES; ++q) {
-      wcnt[0][q][tid] = 0;
-      wcnt[1][q][tid] = 0;
-    }
     __syncthreads();
     uint32_t pre = 0;
     for (int q = 0; q < w; ++q) pre += wsum[q];
-    lstart[tid] = pre + inc - c;
-  }
-  // 2. load and rank
-  const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (SMKI_WAVE - lane));
-  K key[RS_ROUNDS];
-  uint32_t val[RS_ROUNDS];
+    const uint32_t ls = pre + inc - c;
+    lstart[tid] = ls;
+    // column tid of wh is read and rewritten by thread tid only
 #pragma unroll
-  for (int r = 0; r < RS_ROUNDS; ++r) {
-    const int64_t i = tile_base + (int64_t)r * RS_THREADS + tid;
-    key[r] = i < n ? keys[i] : (K)0;
-    val[r] = i < n ? vals[i] : 0u;
+    for (int q = 0; q < RS_WAVES; ++q) wh[q][tid] = ls + pw[q];
   }
   __syncthreads();
-  uint32_t lidx[RS_ROUNDS];
-#pragma unroll
-  for (int r = 0; r < RS_ROUNDS; ++r) {
-    const int b = r & 1;
-    const bool valid = tile_base + (int64_t)r * RS_THREADS + tid < n;
-    const uint32_t d = digit_of(key[r], shift, mask);
-    uint64_t peers = __ballot(valid);
-#pragma unroll
-    for (int bit_i = 0; bit_i < 8; ++bit_i) {
-      const bool bit = (d >> bit_i) & 1u;
-      const uint64_t m = __ballot(bit);
-      peers &= bit ? m : ~m;
-    }
-    const uint32_t rank = (uint32_t)__popcll(peers & lt_mask);
-    const uint32_t cnt = (uint32_t)__popcll(peers);
-    const bool leader = valid && ((peers & lt_mask) == 0);
-    if (leader) wcnt[b][w][d] = cnt;
-    __syncthreads();
-    lidx[r] = 0;
-    if (valid) {
-      uint32_t pre = lstart[d] + run_of[d];
-      for (int q = 0; q < w; ++q) pre += wcnt[b][q][d];
-      lidx[r] = pre + rank;
-    }
-    __syncthreads();
-    // bin tid: advance past this round's elements, clear this round's counts
-    uint32_t add = 0;
-#pragma unroll
-    for (int q = 0; q < RS_WAVES; ++q) {
-      add += wcnt[b][q][tid];
-      wcnt[b][q][tid] = 0;
-    }
-    run_of[tid] += add;
-  }
   // 3. place in digit order, then write out contiguously
 #pragma unroll
   for (int r = 0; r < RS_ROUNDS; ++r) {
-    if (tile_base + (int64_t)r * RS_THREADS + tid < n) {
-      skey[lidx[r]] = key[r];
-      sval[lidx[r]] = val[r];
+    if (elem_index(tile_base, w, r, lane) < n) {
+      const uint32_t p = wh[w][digit_of(key[r], shift, mask)] + lrank[r];
+      skey[p] = key[r];
+      sval[p] = val[r];
     }
   }
   __syncthreads();
   const int tile_n = (int)min((int64_t)RS_TILE, n - tile_base);
-  for (int j = tid; j < tile_n; j += RS_THREADS) {
-    const K k = skey[j];
-    const uint32_t v = sval[j];
-    const uint32_t d = digit_of(k, shift, mask);
-    const uint32_t pos = gbase[d] + ((uint32_t)j - lstart[d]);
-    okeys[pos] = k;
-    ovals[pos] = v;
-    if (pl.rec_in) {
-      pl.rec_out[pos] = pl.rec_in[v];
-      if (pl.w_in) pl.w_out[pos] = pl.w_in[v];
+  if (!pl.rec_in) {
+#pragma unroll 4
+    for (int j = tid; j < tile_n; j += RS_THREADS) {
+      const K k = skey[j];
+      const uint32_t d = digit_of(k, shift, mask);
+      const uint32_t pos = gbase[d] + ((uint32_t)j - lstart[d]);
+      okeys[pos] = k;
+      ovals[pos] = sval[j];
     }
+    return;
   }
+  if (pl.w_in)
+    write_records<K, true>(skey, sval, gbase, lstart, tile_n, shift, mask, okeys, ovals, pl);
+  else
+    write_records<K, false>(skey, sval, gbase, lstart, tile_n, shift, mask, okeys, ovals, pl);
 }
 
 template <typename K>
@@ -171,7 +236,6 @@ hipError_t sort_impl(K* keys, uint32_t* vals, K* akeys, uint32_t* avals, int64_t
   void* scan_tmp = (void*)(hist + RS_BINS * ntiles + 64);
   const int passes = (bits + 7) / 8;
   const int dbits = (bits + passes - 1) / passes;
-  const uint32_t mask = (1u << dbits) - 1u;
   K* src_k = keys;
   uint32_t* src_v = vals;
   K* dst_k = akeys;
@@ -179,13 +243,13 @@ hipError_t sort_impl(K* keys, uint32_t* vals, K* akeys, uint32_t* avals, int64_t
   for (int p = 0; p < passes; ++p) {
     const int shift = p * dbits;
     hipLaunchKernelGGL(k_hist<K>, dim3((unsigned)ntiles), dim3(RS_THREADS), 0, st, src_k, n,
-                       shift, mask, ntiles, hist);
+                       shift, dbits, ntiles, hist);
     hipError_t e = scan_excl_i32((const int32_t*)hist, (int32_t*)hist, RS_BINS * ntiles,
                                  (int32_t*)nullptr, scan_tmp, st);
     if (e != hipSuccess) return e;
     const SortPayload none{};
     hipLaunchKernelGGL(k_scatter<K>, dim3((unsigned)ntiles), dim3(RS_THREADS), 0, st, src_k,
-                       src_v, dst_k, dst_v, n, shift, mask, ntiles, (const uint32_t*)hist,
+                       src_v, dst_k, dst_v, n, shift, dbits, ntiles, (const uint32_t*)hist,
                        (p == passes - 1 && pl) ? *pl : none);
     K* tk = src_k; src_k = dst_k; dst_k = tk;
     uint32_t* tv = src_v; src_v = dst_v; dst_v = tv;
