@@ -345,32 +345,84 @@ __global__ void k_permute_rec(const float4* __restrict__ rec, const float* __res
   if (wt) wout[i] = wt[j];
 }
 
+// Slots: the runs of sorted rows that share (plane, block) = key >> log2B3.
+// A row heads a slot when its block differs from the previous row's.  Tiles of
+// HT rows (one workgroup; wavefront w takes rows [w HS, (w+1) HS) of it, 64 per
+// round) first count their heads; after the scan of the counts, they give
+// their heads consecutive slot numbers in row order with wave ballots.
+constexpr int HT_THREADS = 256;
+constexpr int HT_ROUNDS = 16;
+constexpr int HS = HT_ROUNDS * SMKI_WAVE;      // rows per wavefront
+constexpr int HT = HT_THREADS * HT_ROUNDS;     // rows per tile
+
 template <typename KeyT>
-__global__ void k_block_flags(const KeyT* __restrict__ keys, int64_t n, int shift,
-                              int32_t* __restrict__ flag) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  flag[i] = (i == 0 || (uint64_t)(keys[i] >> shift) != (uint64_t)(keys[i - 1] >> shift)) ? 1 : 0;
+__device__ __forceinline__ bool heads_slot(const KeyT* __restrict__ keys, int64_t i, int64_t n,
+                                           int shift) {
+  if (i >= n) return false;
+  return i == 0 || (uint64_t)(keys[i] >> shift) != (uint64_t)(keys[i - 1] >> shift);
 }
 
-// After the scan of the block-start flags: the first row of every slot, the
-// dense grid -> slot index and each slot's grid position.
-// The dense table is block-major: entry (block * planes + plane), so the
-// classes of one block share a cache line.
 template <typename KeyT>
-__global__ void k_slot_heads(const KeyT* __restrict__ keys, int64_t n, int log2B3, int64_t n_blocks,
-                             int32_t planes, const int32_t* __restrict__ flag,
-                             const int32_t* __restrict__ slot_excl, int32_t* __restrict__ dense,
-                             int32_t* __restrict__ slot_lin, int32_t* __restrict__ head,
-                             const int32_t* __restrict__ d_nslots) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i == 0) head[*d_nslots] = (int32_t)n;
-  if (i >= n || !flag[i]) return;
-  const int64_t blk = (int64_t)((uint64_t)keys[i] >> log2B3);   // plane * n_blocks + block
-  const int32_t slot = slot_excl[i];
-  dense[(blk % n_blocks) * planes + blk / n_blocks] = slot;
-  slot_lin[slot] = (int32_t)blk;
-  head[slot] = (int32_t)i;
+__global__ void __launch_bounds__(HT_THREADS) k_head_counts(const KeyT* __restrict__ keys,
+                                                            int64_t n, int shift,
+                                                            int32_t* __restrict__ tcount) {
+  __shared__ int32_t wc[HT_THREADS / SMKI_WAVE];
+  const int lane = threadIdx.x & (SMKI_WAVE - 1), w = threadIdx.x / SMKI_WAVE;
+  const int64_t base = (int64_t)blockIdx.x * HT + (int64_t)w * HS + lane;
+  int32_t c = 0;
+#pragma unroll 4
+  for (int r = 0; r < HT_ROUNDS; ++r)
+    c += (int32_t)__popcll(__ballot(heads_slot(keys, base + r * SMKI_WAVE, n, shift)));
+  if (lane == 0) wc[w] = c;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int32_t t = 0;
+    for (int q = 0; q < HT_THREADS / SMKI_WAVE; ++q) t += wc[q];
+    tcount[blockIdx.x] = t;
+  }
+}
+
+// After the scan of the tile counts (tstart, total in *d_nslots): the first
+// row of every slot, the dense grid -> slot index and each slot's grid
+// position.  The dense table is block-major: entry (block * planes + plane),
+// so the classes of one block share a cache line.
+template <typename KeyT>
+__global__ void __launch_bounds__(HT_THREADS) k_slot_heads(const KeyT* __restrict__ keys,
+                                                           int64_t n, int log2B3, int64_t n_blocks,
+                                                           int32_t planes,
+                                                           const int32_t* __restrict__ tstart,
+                                                           int32_t* __restrict__ dense,
+                                                           int32_t* __restrict__ slot_lin,
+                                                           int32_t* __restrict__ head,
+                                                           const int32_t* __restrict__ d_nslots) {
+  __shared__ int32_t wc[HT_THREADS / SMKI_WAVE];
+  const int lane = threadIdx.x & (SMKI_WAVE - 1), w = threadIdx.x / SMKI_WAVE;
+  const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (SMKI_WAVE - lane));
+  const int64_t base = (int64_t)blockIdx.x * HT + (int64_t)w * HS + lane;
+  if (blockIdx.x == 0 && threadIdx.x == 0) head[*d_nslots] = (int32_t)n;
+  uint64_t hb[HT_ROUNDS];
+  int32_t c = 0;
+#pragma unroll
+  for (int r = 0; r < HT_ROUNDS; ++r) {
+    hb[r] = __ballot(heads_slot(keys, base + r * SMKI_WAVE, n, log2B3));
+    c += (int32_t)__popcll(hb[r]);
+  }
+  if (lane == 0) wc[w] = c;
+  __syncthreads();
+  int32_t slot = tstart[blockIdx.x];
+  for (int q = 0; q < w; ++q) slot += wc[q];
+#pragma unroll
+  for (int r = 0; r < HT_ROUNDS; ++r) {
+    if ((hb[r] >> lane) & 1ull) {
+      const int64_t i = base + r * SMKI_WAVE;
+      const int64_t blk = (int64_t)((uint64_t)keys[i] >> log2B3);   // plane * n_blocks + block
+      const int32_t sl = slot + (int32_t)__popcll(hb[r] & lt_mask);
+      dense[(blk % n_blocks) * planes + blk / n_blocks] = sl;
+      slot_lin[sl] = (int32_t)blk;
+      head[sl] = (int32_t)i;
+    }
+    slot += (int32_t)__popcll(hb[r]);
+  }
 }
 
 // Per slot (grid-stride over slots): histogram of the rows' voxel cells in LDS,
@@ -474,13 +526,15 @@ static hipError_t finish_set(PointSet& ps, KeyT* keys, uint32_t* idx, KeyT* akey
     hipLaunchKernelGGL(k_permute_rec, dim3(nblk(n, 256)), dim3(256), 0, st, rec_unsorted,
                        (const float*)scr.wt, idx, n, ps.pts, ps.wts);
   const int log2B3 = 3 * g.log2B;
-  hipLaunchKernelGGL(k_block_flags<KeyT>, dim3(nblk(n, 256)), dim3(256), 0, st, keys, n, log2B3,
-                     scr.flag);
-  e = scan_excl_i32(scr.flag, scr.slot_excl, n, ps.d_nslots, scr.scan_tmp, st);
+  // slot heads: per-tile counts (in scr.flag), their scan (scr.slot_excl), numbering
+  const int64_t ntiles = ceil_div_i64(n, HT);
+  hipLaunchKernelGGL(k_head_counts<KeyT>, dim3((unsigned)ntiles), dim3(HT_THREADS), 0, st, keys, n,
+                     log2B3, scr.flag);
+  e = scan_excl_i32(scr.flag, scr.slot_excl, ntiles, ps.d_nslots, scr.scan_tmp, st);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_slot_heads<KeyT>, dim3(nblk(n, 256)), dim3(256), 0, st, keys, n, log2B3,
-                     g.n_blocks, g.planes, scr.flag, scr.slot_excl, ps.dense, ps.slot_lin,
-                     ps.head, ps.d_nslots);
+  hipLaunchKernelGGL(k_slot_heads<KeyT>, dim3((unsigned)ntiles), dim3(HT_THREADS), 0, st, keys, n,
+                     log2B3, g.n_blocks, g.planes, scr.slot_excl, ps.dense, ps.slot_lin, ps.head,
+                     ps.d_nslots);
   if (!ps.prefix) return hipGetLastError();
   const unsigned grid = (unsigned)std::min<int64_t>(n, 8192);
   switch (log2B3) {

@@ -23,48 +23,77 @@ __global__ void k_hash_clear(uint64_t* keys, int64_t n) {
 
 // Readout of Eq. (3)-(4): mean alpha/S, variance mean(1-mean)/(S+1), label =
 // argmax (lowest index on ties), occupancy = 1 - mean of the free class.
-__global__ void k_query(MapDev m, const int32_t* __restrict__ ijk, int64_t M,
-                        float* __restrict__ alpha, float* __restrict__ mean,
-                        float* __restrict__ var, int32_t* __restrict__ label,
-                        float* __restrict__ p_occ, int32_t free_class) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= M) return;
-  const int32_t vx = ijk[3 * i], vy = ijk[3 * i + 1], vz = ijk[3 * i + 2];
-  const int32_t bx = vx >> m.log2B, by = vy >> m.log2B, bz = vz >> m.log2B;
-  const int32_t B = m.B, B3 = B * B * B;
-  int32_t slot = -1;
-  if (vx >= -(1 << 20) && vx < (1 << 20) && vy >= -(1 << 20) && vy < (1 << 20) &&
-      vz >= -(1 << 20) && vz < (1 << 20))
-    slot = hash_find(m, smki_block_key(bx, by, bz));
-  const int32_t* CS = slot >= 0 ? m.cslot + (int64_t)slot * m.K : nullptr;
-  const int32_t v = ((vx - bx * B) * B + (vy - by * B)) * B + (vz - bz * B);
-  auto alpha_of = [&](int k) -> float {   // classes without a class block hold alpha0
-    const int32_t cb = CS ? CS[k] : -1;
-    return cb >= 0 ? m.calpha[(int64_t)cb * B3 + v] : m.alpha0;
-  };
-  // moments in double: 1 - mean cancels when one class dominates
-  double S = 0.0;
-  int32_t best = 0;
-  float bestv = -1.0f;
-  for (int k = 0; k < m.K; ++k) {
-    const float a = alpha_of(k);
-    S += (double)a;
-    if (a > bestv) { bestv = a; best = k; }
-    if (alpha) alpha[i * m.K + k] = a;
+// SEG consecutive lanes serve one query (SEG >= K, or SEG = 64 with several
+// classes per lane): every lane finds the query's block, loads its classes'
+// alpha, and the segment reduces the sum, the free class's alpha and the
+// argmax with shuffles; per-class outputs are stored by consecutive lanes.
+template <int SEG>
+__global__ void __launch_bounds__(256) k_query(MapDev m, const int32_t* __restrict__ ijk,
+                                               int64_t M, float* __restrict__ alpha,
+                                               float* __restrict__ mean, float* __restrict__ var,
+                                               int32_t* __restrict__ label,
+                                               float* __restrict__ p_occ, int32_t free_class) {
+  constexpr int MAXC = SEG == 64 ? 4 : 1;   // classes per lane (K <= 255)
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t i = t / SEG;
+  const int kl = (int)(t % SEG);
+  const bool live = i < M;   // whole segments are live or not; shuffles stay inside a segment
+  const int32_t K = m.K, B = m.B, B3 = B * B * B;
+  int32_t slot = -1, v = 0;
+  if (live) {
+    const int32_t vx = ijk[3 * i], vy = ijk[3 * i + 1], vz = ijk[3 * i + 2];
+    const int32_t bx = vx >> m.log2B, by = vy >> m.log2B, bz = vz >> m.log2B;
+    if (vx >= -(1 << 20) && vx < (1 << 20) && vy >= -(1 << 20) && vy < (1 << 20) &&
+        vz >= -(1 << 20) && vz < (1 << 20))
+      slot = hash_find(m, smki_block_key(bx, by, bz));
+    v = ((vx - bx * B) * B + (vy - by * B)) * B + (vz - bz * B);
   }
-  const double inv_s = 1.0 / S, inv_s1 = 1.0 / (S + 1.0);
-  if (mean || var) {
-    for (int k = 0; k < m.K; ++k) {
-      const double a = (double)alpha_of(k);
-      const double e = a * inv_s;
-      if (mean) mean[i * m.K + k] = (float)e;
-      if (var) var[i * m.K + k] = (float)(e * ((S - a) * inv_s) * inv_s1);
+  // this lane's classes kl, kl + SEG, ...; classes without a class block hold alpha0
+  float a[MAXC];
+  double S = 0.0, af = 0.0;
+  float bestv = -1.0f;
+  int32_t best = 0;
+#pragma unroll
+  for (int j = 0; j < MAXC; ++j) {
+    const int k = kl + j * SEG;
+    a[j] = 0.0f;
+    if (live && k < K) {
+      const int32_t cb = slot >= 0 ? m.cslot[(int64_t)slot * K + k] : -1;
+      a[j] = cb >= 0 ? m.calpha[(int64_t)cb * B3 + v] : m.alpha0;
+      S += (double)a[j];
+      if (k == free_class) af = (double)a[j];
+      if (a[j] > bestv) {
+        bestv = a[j];
+        best = k;
+      }
     }
   }
-  if (label) label[i] = best;
-  if (p_occ) {
-    const double af = (double)alpha_of(free_class);
-    p_occ[i] = (float)((S - af) * inv_s);
+  // moments in double: 1 - mean cancels when one class dominates
+#pragma unroll
+  for (int o = 1; o < SEG; o <<= 1) {
+    S += __shfl_xor(S, o, SEG);
+    af += __shfl_xor(af, o, SEG);
+    const float ov = __shfl_xor(bestv, o, SEG);
+    const int32_t ok = __shfl_xor(best, o, SEG);
+    if (ov > bestv || (ov == bestv && ok < best)) {
+      bestv = ov;
+      best = ok;
+    }
+  }
+  if (!live) return;
+  const double inv_s = 1.0 / S, inv_s1 = 1.0 / (S + 1.0);
+#pragma unroll
+  for (int j = 0; j < MAXC; ++j) {
+    const int k = kl + j * SEG;
+    if (k >= K) continue;
+    if (alpha) alpha[i * K + k] = a[j];
+    const double e = (double)a[j] * inv_s;
+    if (mean) mean[i * K + k] = (float)e;
+    if (var) var[i * K + k] = (float)(e * ((S - (double)a[j]) * inv_s) * inv_s1);
+  }
+  if (kl == 0) {
+    if (label) label[i] = best;
+    if (p_occ) p_occ[i] = (float)((S - af) * inv_s);
   }
 }
 
@@ -158,8 +187,26 @@ hipError_t launch_query(const MapDev& m, const int32_t* ijk, int64_t M, float* a
                         float* var, int32_t* label, float* p_occ, int32_t free_class,
                         hipStream_t st) {
   if (M <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_query, dim3(nblk(M, 256)), dim3(256), 0, st, m, ijk, M, alpha, mean, var,
-                     label, p_occ, free_class);
+  const int seg = m.K <= 8 ? 8 : m.K <= 16 ? 16 : m.K <= 32 ? 32 : 64;
+  const unsigned grid = nblk(M * seg, 256);
+  switch (seg) {
+    case 8:
+      hipLaunchKernelGGL(k_query<8>, dim3(grid), dim3(256), 0, st, m, ijk, M, alpha, mean, var,
+                         label, p_occ, free_class);
+      break;
+    case 16:
+      hipLaunchKernelGGL(k_query<16>, dim3(grid), dim3(256), 0, st, m, ijk, M, alpha, mean, var,
+                         label, p_occ, free_class);
+      break;
+    case 32:
+      hipLaunchKernelGGL(k_query<32>, dim3(grid), dim3(256), 0, st, m, ijk, M, alpha, mean, var,
+                         label, p_occ, free_class);
+      break;
+    default:
+      hipLaunchKernelGGL(k_query<64>, dim3(grid), dim3(256), 0, st, m, ijk, M, alpha, mean, var,
+                         label, p_occ, free_class);
+      break;
+  }
   return hipGetLastError();
 }
 

@@ -1,7 +1,8 @@
 // Stable least-significant-digit radix sort of (key, u32 value) pairs.
 //
-// One pass per digit of up to 8 bits: (1) per-tile digit histograms, (2) an
-// exclusive scan of the digit-major histogram table, (3) a stable scatter.  In
+// One pass per digit of up to 8 bits: (1) per-tile digit histograms, (2) per
+// digit, an exclusive scan of its tile counts and its total, (3) a stable
+// scatter, which adds the totals of the smaller digits itself.  In
 // both kernels a wavefront takes 1024 consecutive elements of its tile and
 // groups equal digits with wave ballots (the peers of a lane are the lanes
 // whose digit agrees on every bit); its running digit counts live in its own
@@ -79,6 +80,38 @@ __global__ void __launch_bounds__(RS_THREADS) k_hist(const K* __restrict__ keys,
   hist[(int64_t)tid * ntiles + blockIdx.x] = c;
 }
 
+// Per digit (one workgroup each): exclusive scan, in place, of the digit's
+// row of the digit-major table (its count in every tile), and the digit's
+// total.  Thread i takes a run of consecutive tiles: its sum, a scan of the
+// sums over the workgroup, then the run is rewritten as running prefixes.
+__global__ void __launch_bounds__(RS_THREADS) k_digit_scan(uint32_t* __restrict__ hist,
+                                                           int64_t ntiles,
+                                                           uint32_t* __restrict__ total) {
+  __shared__ uint32_t wsum[RS_WAVES];
+  const int tid = threadIdx.x, lane = tid & (SMKI_WAVE - 1), w = tid / SMKI_WAVE;
+  uint32_t* row = hist + (int64_t)blockIdx.x * ntiles;
+  const int64_t run_len = (ntiles + RS_THREADS - 1) / RS_THREADS;
+  const int64_t b0 = min((int64_t)tid * run_len, ntiles), b1 = min(b0 + run_len, ntiles);
+  uint32_t sum = 0;
+  for (int64_t i = b0; i < b1; ++i) sum += row[i];
+  uint32_t inc = sum;
+#pragma unroll
+  for (int o = 1; o < SMKI_WAVE; o <<= 1) {
+    const uint32_t u = __shfl_up(inc, o, SMKI_WAVE);
+    if (lane >= o) inc += u;
+  }
+  if (lane == SMKI_WAVE - 1) wsum[w] = inc;
+  __syncthreads();
+  uint32_t run = inc - sum;
+  for (int q = 0; q < w; ++q) run += wsum[q];
+  for (int64_t i = b0; i < b1; ++i) {
+    const uint32_t c = row[i];
+    row[i] = run;
+    run += c;
+  }
+  if (tid == RS_THREADS - 1) total[blockIdx.x] = run;
+}
+
 // Last pass with records: a thread gathers the records (and weights) of eight
 // of the tile's sorted elements before storing any of them.
 template <typename K, bool WT>
@@ -137,18 +170,20 @@ __global__ void __launch_bounds__(RS_THREADS) k_scatter(const K* __restrict__ ke
                                                         uint32_t* __restrict__ ovals, int64_t n,
                                                         int shift, int dbits, int64_t ntiles,
                                                         const uint32_t* __restrict__ offs,
+                                                        const uint32_t* __restrict__ total,
                                                         SortPayload pl) {
   __shared__ uint32_t gbase[RS_BINS];    // first global position of the tile's digit-d elements
   __shared__ uint32_t lstart[RS_BINS];   // first index of digit d inside the tile
   __shared__ uint32_t wh[RS_WAVES][RS_BINS];   // per wavefront: digit counts, then first index
-  __shared__ uint32_t wsum[RS_WAVES];
+  __shared__ uint32_t wsum[2][RS_WAVES];
   __shared__ K skey[RS_TILE];
   __shared__ uint32_t sval[RS_TILE];
   const int tid = threadIdx.x, lane = tid & (SMKI_WAVE - 1), w = tid / SMKI_WAVE;
   const uint32_t mask = (1u << dbits) - 1u;
   const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (SMKI_WAVE - lane));
   const int64_t tile_base = (int64_t)blockIdx.x * RS_TILE;
-  gbase[tid] = offs[(int64_t)tid * ntiles + blockIdx.x];
+  const uint32_t in_digit = offs[(int64_t)tid * ntiles + blockIdx.x];   // earlier tiles' digit-tid count
+  const uint32_t dtot = total[tid];
 #pragma unroll
   for (int q = 0; q < RS_WAVES; ++q) wh[q][tid] = 0;
   K key[RS_ROUNDS];
@@ -174,6 +209,8 @@ __global__ void __launch_bounds__(RS_THREADS) k_scatter(const K* __restrict__ ke
   }
   __syncthreads();
   // 2. digit tid: the wavefronts' counts, the tile's count and its first index
+  //    inside the tile; the digit's first global position (the totals of the
+  //    smaller digits plus the digit's count in earlier tiles)
   {
     uint32_t pw[RS_WAVES];
     uint32_t c = 0;
@@ -182,18 +219,29 @@ __global__ void __launch_bounds__(RS_THREADS) k_scatter(const K* __restrict__ ke
       pw[q] = c;
       c += wh[q][tid];
     }
-    uint32_t inc = c;
+    uint32_t inc = c, incg = dtot;
 #pragma unroll
     for (int o = 1; o < SMKI_WAVE; o <<= 1) {
       const uint32_t u = __shfl_up(inc, o, SMKI_WAVE);
-      if (lane >= o) inc += u;
+      const uint32_t ug = __shfl_up(incg, o, SMKI_WAVE);
+      if (lane >= o) {
+        inc += u;
+        incg += ug;
+      }
     }
-    if (lane == SMKI_WAVE - 1) wsum[w] = inc;
+    if (lane == SMKI_WAVE - 1) {
+      wsum[0][w] = inc;
+      wsum[1][w] = incg;
+    }
     __syncthreads();
-    uint32_t pre = 0;
-    for (int q = 0; q < w; ++q) pre += wsum[q];
+    uint32_t pre = 0, preg = 0;
+    for (int q = 0; q < w; ++q) {
+      pre += wsum[0][q];
+      preg += wsum[1][q];
+    }
     const uint32_t ls = pre + inc - c;
     lstart[tid] = ls;
+    gbase[tid] = preg + incg - dtot + in_digit;
     // column tid of wh is read and rewritten by thread tid only
 #pragma unroll
     for (int q = 0; q < RS_WAVES; ++q) wh[q][tid] = ls + pw[q];
@@ -233,7 +281,7 @@ hipError_t sort_impl(K* keys, uint32_t* vals, K* akeys, uint32_t* avals, int64_t
   if (n <= 1 || bits <= 0) return hipSuccess;
   const int64_t ntiles = ceil_div_i64(n, RS_TILE);
   uint32_t* hist = (uint32_t*)tmp;
-  void* scan_tmp = (void*)(hist + RS_BINS * ntiles + 64);
+  uint32_t* total = hist + RS_BINS * ntiles;   // RS_BINS digit totals
   const int passes = (bits + 7) / 8;
   const int dbits = (bits + passes - 1) / passes;
   K* src_k = keys;
@@ -244,13 +292,11 @@ hipError_t sort_impl(K* keys, uint32_t* vals, K* akeys, uint32_t* avals, int64_t
     const int shift = p * dbits;
     hipLaunchKernelGGL(k_hist<K>, dim3((unsigned)ntiles), dim3(RS_THREADS), 0, st, src_k, n,
                        shift, dbits, ntiles, hist);
-    hipError_t e = scan_excl_i32((const int32_t*)hist, (int32_t*)hist, RS_BINS * ntiles,
-                                 (int32_t*)nullptr, scan_tmp, st);
-    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_digit_scan, dim3(RS_BINS), dim3(RS_THREADS), 0, st, hist, ntiles, total);
     const SortPayload none{};
     hipLaunchKernelGGL(k_scatter<K>, dim3((unsigned)ntiles), dim3(RS_THREADS), 0, st, src_k,
                        src_v, dst_k, dst_v, n, shift, dbits, ntiles, (const uint32_t*)hist,
-                       (p == passes - 1 && pl) ? *pl : none);
+                       (const uint32_t*)total, (p == passes - 1 && pl) ? *pl : none);
     K* tk = src_k; src_k = dst_k; dst_k = tk;
     uint32_t* tv = src_v; src_v = dst_v; dst_v = tv;
   }
@@ -267,7 +313,7 @@ hipError_t sort_impl(K* keys, uint32_t* vals, K* akeys, uint32_t* avals, int64_t
 
 size_t radix_tmp_bytes(int64_t n) {
   const int64_t ntiles = ceil_div_i64(n > 0 ? n : 1, RS_TILE);
-  return sizeof(uint32_t) * (RS_BINS * ntiles + 64) + scan_tmp_bytes(RS_BINS * ntiles) + 256;
+  return sizeof(uint32_t) * RS_BINS * (ntiles + 1) + 256;   // tile counts, digit totals
 }
 
 hipError_t radix_sort_u32(uint32_t* keys, uint32_t* vals, uint32_t* ak, uint32_t* av, int64_t n,

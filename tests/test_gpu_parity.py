@@ -135,6 +135,42 @@ def test_tiny_scene_alpha_counts_and_readout():
     assert np.all(a_far == np.float32(sc.params.alpha0))
 
 
+@pytest.mark.parametrize("K", [3, 12, 40, 150])
+def test_readout_at_several_class_counts(K):
+    # the readout serves a query with K lanes (K <= 32) or 64 lanes holding
+    # several classes each; labels spread over all K classes, the free class last
+    import dataclasses
+    sc = scenes.make_config(0)
+    rng = np.random.default_rng(K)
+    p = dataclasses.replace(sc.params, K=K, free_class=K - 1)
+    scans = []
+    for s in sc.scans:
+        lab = rng.integers(0, K, size=s.label.shape[0]).astype(np.int32)
+        lab[s.label < 0] = -1
+        scans.append(scenes.Scan(s.xyz, lab, s.origin))
+    sck = dataclasses.replace(sc, params=p, scans=scans)
+    _print_case(f"readout K={K}")
+    om = oracle_map_of(sck)
+    gm = gpu_map_of(sck)
+    ijk, a_ref, _, _ = om.export()
+    q = np.concatenate([ijk[::3], sc.query_ijk[::5]]).astype(np.int32)
+    out = gm.query(cuda(q))
+    a_o = om.lookup(q)
+    ref = oracle.readout(a_o, free_class=K - 1)
+    assert rel_err(out["alpha"].cpu().numpy(), a_o).max() <= ALPHA_RTOL
+    np.testing.assert_allclose(out["mean"].cpu().numpy(), ref["mean"], rtol=2e-5, atol=1e-7)
+    np.testing.assert_allclose(out["var"].cpu().numpy(), ref["var"], rtol=5e-5, atol=1e-9)
+    np.testing.assert_allclose(out["p_occ"].cpu().numpy(), ref["p_occ"], rtol=2e-5, atol=1e-6)
+    lab = out["label"].cpu().numpy()
+    srt = np.sort(a_o, axis=1)
+    clear = (srt[:, -1] - srt[:, -2]) > 4 * ALPHA_RTOL * srt[:, -1]
+    assert clear.sum() > 0
+    assert np.array_equal(lab[clear], ref["label"][clear])
+    # where every class holds alpha0 the label is class 0 (lowest index on ties)
+    unreached = np.all(a_o == a_o[:, :1], axis=1)
+    assert np.all(lab[unreached] == 0)
+
+
 def test_deterministic_across_runs():
     sc = scenes.make_config(0)
     _print_case("determinism")
