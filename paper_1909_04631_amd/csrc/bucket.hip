@@ -498,6 +498,29 @@ hipError_t launch_count(const float* xyz, const int32_t* label, const float* pro
   return hipGetLastError();
 }
 
+// Three ranges in one launch: z0[0, n0) = 0, z1[0, n1) = 0, f[0, nf) = fv.
+__global__ void k_clear3(int32_t* __restrict__ z0, int64_t n0, int32_t* __restrict__ z1, int64_t n1,
+                         int32_t* __restrict__ f, int64_t nf, int32_t fv) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n0 + n1 + nf; i += stride) {
+    if (i < n0)
+      z0[i] = 0;
+    else if (i < n0 + n1)
+      z1[i - n0] = 0;
+    else
+      f[i - n0 - n1] = fv;
+  }
+}
+
+hipError_t launch_clear3(int32_t* z0, int64_t n0, int32_t* z1, int64_t n1, int32_t* f, int64_t nf,
+                         int32_t fv, hipStream_t st) {
+  const int64_t n = n0 + n1 + nf;
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_clear3, dim3((unsigned)std::min<int64_t>(nblk(n, 256), 4096)), dim3(256), 0,
+                     st, z0, n0, z1, n1, f, nf, fv);
+  return hipGetLastError();
+}
+
 hipError_t launch_fill_i32(int32_t* p, int64_t n, int32_t v, hipStream_t st) {
   if (n <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_fill_i32, dim3(nblk(n, 256)), dim3(256), 0, st, p, n, v);
@@ -580,8 +603,7 @@ hipError_t bucket_scan(const float* xyz, const int32_t* label, const float* prob
                        const float* origins, int32_t S, float step, int32_t free_class,
                        const BucketGeom& g, PointSet& ps, BucketScratch& scr, uint32_t* err,
                        hipStream_t st) {
-  hipError_t e = launch_fill_i32(ps.dense, g.n_blocks * g.planes, -1, st);
-  if (e != hipSuccess || ps.n <= 0) return e;
+  if (ps.n <= 0) return hipSuccess;
   if (g.key_bits <= 32)
     return bucket_scan_t<uint32_t>(xyz, label, probs, K, n, kept, kpos, nk, off, nf, wgbeam,
                                    scan_off, origins, S, step, free_class, g, ps, scr, err, st);

@@ -378,8 +378,8 @@ smki_status insert_csm(smki_map* m, const BucketGeom& g, const PointSet& ps, con
   rc = ensure_cpool(m, m->n_cblocks + n_cnew);
   if (rc != SMKI_OK) return rc;
   SMKI_HIP_TRY(hipEventRecord(m->ev[2], q));
-  SMKI_HIP_TRY(launch_assign_new(m->dev, sa, n_t, d_isnew, d_rank, m->n_blocks, d_tslot, m->d_err, q));
-  SMKI_HIP_TRY(launch_assign_cblocks(m->dev, n_t, d_need, d_cpos, d_tslot, m->n_cblocks, q));
+  SMKI_HIP_TRY(launch_assign(m->dev, sa, n_t, d_isnew, d_rank, m->n_blocks, d_tslot, d_need,
+                             d_cpos, m->n_cblocks, m->d_err, q));
   SMKI_HIP_TRY(launch_fill_calpha0(m->dev, m->n_cblocks, n_cnew, q));
   sa.map = m->dev;
   SMKI_HIP_TRY(launch_csm_counts(sa, keys, g.key_bits > 32, ps.n, d_vbits, n_t, q));
@@ -574,7 +574,11 @@ smki_status insert_impl(smki_map* m, const float* xyz, const int32_t* label, con
   ps.wts = probs ? Bz.take<float>(nt) : nullptr;
   scr.wt = probs ? Bz.take<float>(nt) : nullptr;
   int32_t* d_wgbeam = Bz.take<int32_t>(free_sample_workgroups(nf));
-  SMKI_HIP_TRY(hipMemsetAsync(d_si, 0, (size_t)((char*)(d_mark + n_ext) - (char*)d_si), q));
+  // one launch clears the counts and target marks, the insert counters, and the
+  // dense slot table
+  SMKI_HIP_TRY(launch_clear3(d_si, (int64_t)(d_mark + n_ext - d_si), (int32_t*)m->d_stats,
+                             (int64_t)(kStatBytes / sizeof(int32_t)), ps.dense,
+                             g.n_blocks * m->K, -1, q));
   SMKI_HIP_TRY(bucket_scan(xyz, label, probs, m->K, n, d_kept, d_kpos, nk, d_off, nf, d_wgbeam,
                            d_soff, d_org, S, step, m->free_class, g, ps, scr, m->d_err, q));
   SMKI_HIP_TRY(launch_mark_targets(ps.slot_lin, ps.d_nslots, (int32_t)max_slots, g, eblo, enb, DB,
@@ -675,17 +679,18 @@ smki_status insert_impl(smki_map* m, const float* xyz, const int32_t* label, con
   sa.sinfo = d_sinfo;
   sa.n_slots = n_slots;
   sa.contrib = d_contrib;
-  SMKI_HIP_TRY(hipMemsetAsync(d_cnt, 0,
-                              (size_t)((char*)(d_contrib + std::max<int64_t>(ntk, 1)) - (char*)d_cnt),
-                              q));
-  SMKI_HIP_TRY(hipMemsetAsync(m->d_stats, 0, kStatBytes, q));
-  SMKI_HIP_TRY(launch_list_targets(d_mark, d_mpos, n_ext, d_tgt, d_ext2t, q));
+  // the splat first (its counters were cleared before the bucketing); what
+  // only the later kernels read is prepared while it runs
   SMKI_HIP_TRY(launch_unit_table(d_nun, d_ust, ps.head, ps.slot_lin, g.n_blocks, m->chunk,
                                  (int32_t)max_slots, d_units, q));
   m->ev = m->evr[m->n_timed++ % SMKI_TIMING_RING];
   SMKI_HIP_TRY(hipEventRecord(m->ev[0], q));
   SMKI_HIP_TRY(launch_splat(sa, n_units, q));
   SMKI_HIP_TRY(hipEventRecord(m->ev[1], q));
+  SMKI_HIP_TRY(hipMemsetAsync(d_cnt, 0,
+                              (size_t)((char*)(d_contrib + std::max<int64_t>(ntk, 1)) - (char*)d_cnt),
+                              q));
+  SMKI_HIP_TRY(launch_list_targets(d_mark, d_mpos, n_ext, d_tgt, d_ext2t, q));
   SMKI_HIP_TRY(launch_slot_info(sa, q));
   SMKI_HIP_TRY(launch_contrib(sa, false, d_contrib, q));
   SMKI_HIP_TRY(launch_map_lookup(m->dev, sa, n_t, d_tslot, d_isnew, q));
@@ -704,8 +709,8 @@ smki_status insert_impl(smki_map* m, const float* xyz, const int32_t* label, con
   rc = ensure_cpool(m, m->n_cblocks + n_cnew);
   if (rc != SMKI_OK) return rc;
   SMKI_HIP_TRY(hipEventRecord(m->ev[2], q));
-  SMKI_HIP_TRY(launch_assign_new(m->dev, sa, n_t, d_isnew, d_rank, m->n_blocks, d_tslot, m->d_err, q));
-  SMKI_HIP_TRY(launch_assign_cblocks(m->dev, n_t, d_need, d_cpos, d_tslot, m->n_cblocks, q));
+  SMKI_HIP_TRY(launch_assign(m->dev, sa, n_t, d_isnew, d_rank, m->n_blocks, d_tslot, d_need,
+                             d_cpos, m->n_cblocks, m->d_err, q));
   sa.map = m->dev;
   sa.n_cold = m->n_cblocks;
   sa.alpha0 = m->alpha0;

@@ -52,6 +52,11 @@ hipError_t launch_count(const float* xyz, const int32_t* label, const float* pro
                         float step, int32_t K, int64_t* nfree, int32_t* kept, int32_t* bbox,
                         uint32_t* err, hipStream_t st);
 hipError_t launch_fill_i32(int32_t* p, int64_t n, int32_t v, hipStream_t st);
+// z0[0, n0) = 0, z1[0, n1) = 0, f[0, nf) = fv, in one launch
+hipError_t launch_clear3(int32_t* z0, int64_t n0, int32_t* z1, int64_t n1, int32_t* f, int64_t nf,
+                         int32_t fv, hipStream_t st);
+// The rows of one insert, keyed, sorted and grouped into slots; ps.dense must
+// hold -1 on entry (the caller clears it with its other buffers).
 hipError_t bucket_scan(const float* xyz, const int32_t* label, const float* probs, int32_t K,
                        int64_t n, const int32_t* kept, const int32_t* kpos, int64_t nk,
                        const int64_t* off, int64_t nf, int32_t* wgbeam, const int64_t* scan_off,

@@ -99,15 +99,14 @@ hipError_t launch_contrib(const SplatArgs& a, bool own_block_only, int32_t* cont
 hipError_t launch_need(const MapDev& m, int32_t n_targets, const int32_t* contrib,
                        const int32_t* is_new, const int32_t* tgt_slot, int32_t* need,
                        hipStream_t st);
-hipError_t launch_assign_cblocks(const MapDev& m, int32_t n_targets, const int32_t* need,
-                                 const int32_t* cpos, const int32_t* tgt_slot, int64_t n_cold,
-                                 hipStream_t st);
 hipError_t launch_slot_info(const SplatArgs& a, hipStream_t st);
 hipError_t launch_map_lookup(const MapDev& m, const SplatArgs& a, int32_t n_targets,
                              int32_t* tgt_slot, int32_t* is_new, hipStream_t st);
-hipError_t launch_assign_new(const MapDev& m, const SplatArgs& a, int32_t n_targets,
-                             const int32_t* is_new, const int32_t* new_rank, int64_t n_old,
-                             int32_t* tgt_slot, uint32_t* err, hipStream_t st);
+// new map blocks (slot, key, hash entry) and class blocks, in one launch
+hipError_t launch_assign(const MapDev& m, const SplatArgs& a, int32_t n_targets,
+                         const int32_t* is_new, const int32_t* new_rank, int64_t n_old,
+                         int32_t* tgt_slot, const int32_t* need, const int32_t* cpos,
+                         int64_t n_cold, uint32_t* err, hipStream_t st);
 
 // csm.hip: counting-model inserts
 hipError_t launch_csm_counts(const SplatArgs& a, const void* keys, bool wide_keys, int64_t n,

@@ -605,15 +605,6 @@ __global__ void k_need(MapDev m, int32_t n_targets, const int32_t* __restrict__ 
   need[i] = v;
 }
 
-__global__ void k_assign_cblocks(MapDev m, int32_t n_targets, const int32_t* __restrict__ need,
-                                 const int32_t* __restrict__ cpos,
-                                 const int32_t* __restrict__ tgt_slot, int64_t n_cold) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= (int64_t)n_targets * m.K || !need[i]) return;
-  const int32_t t = (int32_t)(i / m.K), k = (int32_t)(i % m.K);
-  m.cslot[(int64_t)tgt_slot[t] * m.K + k] = (int32_t)(n_cold + cpos[i]);
-}
-
 // map-slot lookup of the active targets; new blocks are marked for allocation
 __global__ void k_map_lookup(MapDev m, SplatArgs a, int32_t n_targets,
                              int32_t* __restrict__ tgt_slot, int32_t* __restrict__ is_new) {
@@ -639,19 +630,28 @@ __global__ void k_map_lookup(MapDev m, SplatArgs a, int32_t n_targets,
   is_new[t] = slot < 0 ? 1 : 0;
 }
 
-__global__ void k_assign_new(MapDev m, SplatArgs a, int32_t n_targets,
-                             const int32_t* __restrict__ is_new, const int32_t* __restrict__ rank,
-                             int64_t n_old, int32_t* __restrict__ tgt_slot,
-                             uint32_t* __restrict__ err) {
-  const int32_t t = blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= n_targets || !is_new[t]) return;
+// Allocation, one thread per (target, class): a new target block takes map
+// slot n_old + its rank (the class-0 thread records its key and inserts it in
+// the hash), and its class slots start empty; a (target, class) pair that
+// needs a class block takes class block n_cold + its rank.
+__global__ void k_assign(MapDev m, SplatArgs a, int32_t n_targets,
+                         const int32_t* __restrict__ is_new, const int32_t* __restrict__ rank,
+                         int64_t n_old, int32_t* __restrict__ tgt_slot,
+                         const int32_t* __restrict__ need, const int32_t* __restrict__ cpos,
+                         int64_t n_cold, uint32_t* __restrict__ err) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= (int64_t)n_targets * m.K) return;
+  const int32_t t = (int32_t)(i / m.K), k = (int32_t)(i % m.K);
+  const bool fresh = is_new[t] != 0;
+  const int32_t slot = fresh ? (int32_t)(n_old + rank[t]) : tgt_slot[t];
+  if (fresh || need[i])
+    m.cslot[(int64_t)slot * m.K + k] = need[i] ? (int32_t)(n_cold + cpos[i]) : -1;
+  if (!fresh || k != 0) return;
   int32_t bt[3];
   unlin3(a.tgt_elin[t], a.enb, bt);
   const uint64_t key = smki_block_key(bt[0] + a.eblo[0], bt[1] + a.eblo[1], bt[2] + a.eblo[2]);
-  const int32_t slot = (int32_t)(n_old + rank[t]);
   tgt_slot[t] = slot;
   m.bkeys[slot] = key;
-  for (int32_t k = 0; k < m.K; ++k) m.cslot[(int64_t)slot * m.K + k] = -1;
   uint64_t h = smki_mix64(key) & (uint64_t)(m.hcap - 1);
   for (int64_t probe = 0; probe < m.hcap; ++probe) {
     const unsigned long long old =
@@ -784,12 +784,14 @@ hipError_t launch_map_lookup(const MapDev& m, const SplatArgs& a, int32_t n_targ
   return hipGetLastError();
 }
 
-hipError_t launch_assign_new(const MapDev& m, const SplatArgs& a, int32_t n_targets,
-                             const int32_t* is_new, const int32_t* new_rank, int64_t n_old,
-                             int32_t* tgt_slot, uint32_t* err, hipStream_t st) {
-  if (n_targets <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_assign_new, dim3(nblk(n_targets, 256)), dim3(256), 0, st, m, a, n_targets,
-                     is_new, new_rank, n_old, tgt_slot, err);
+hipError_t launch_assign(const MapDev& m, const SplatArgs& a, int32_t n_targets,
+                         const int32_t* is_new, const int32_t* new_rank, int64_t n_old,
+                         int32_t* tgt_slot, const int32_t* need, const int32_t* cpos,
+                         int64_t n_cold, uint32_t* err, hipStream_t st) {
+  const int64_t n = (int64_t)n_targets * m.K;
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_assign, dim3(nblk(n, 256)), dim3(256), 0, st, m, a, n_targets, is_new,
+                     new_rank, n_old, tgt_slot, need, cpos, n_cold, err);
   return hipGetLastError();
 }
 
@@ -817,12 +819,3 @@ hipError_t launch_need(const MapDev& m, int32_t n_targets, const int32_t* contri
   return hipGetLastError();
 }
 
-hipError_t launch_assign_cblocks(const MapDev& m, int32_t n_targets, const int32_t* need,
-                                 const int32_t* cpos, const int32_t* tgt_slot, int64_t n_cold,
-                                 hipStream_t st) {
-  const int64_t n = (int64_t)n_targets * m.K;
-  if (n <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_assign_cblocks, dim3(nblk(n, 256)), dim3(256), 0, st, m, n_targets, need,
-                     cpos, tgt_slot, n_cold);
-  return hipGetLastError();
-}
