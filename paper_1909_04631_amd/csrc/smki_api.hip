@@ -4,6 +4,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <chrono>
 #include <vector>
 
 #include "../../include/smki.h"
@@ -183,10 +184,23 @@ Stencil make_stencil(double lv, double margin) {
   return s;
 }
 
+// Wait for the stream by polling its status: the insert's waits are short,
+// and a blocking wait resumes the host only after an interrupt.  Waits longer
+// than 2 ms fall back to the blocking wait.
+hipError_t stream_wait(hipStream_t q) {
+  const auto t0 = std::chrono::steady_clock::now();
+  for (;;) {
+    const hipError_t e = hipStreamQuery(q);
+    if (e != hipErrorNotReady) return e;
+    if (std::chrono::steady_clock::now() - t0 > std::chrono::milliseconds(2))
+      return hipStreamSynchronize(q);
+  }
+}
+
 hipError_t sync_read(smki_map* m, const void* dev, size_t bytes, void* host) {
   hipError_t e = hipMemcpyAsync(host, dev, bytes, hipMemcpyDeviceToHost, m->stream);
   if (e != hipSuccess) return e;
-  return hipStreamSynchronize(m->stream);
+  return stream_wait(m->stream);
 }
 
 // Grow the block arrays (keys, class-block table) to hold `need` blocks.
@@ -474,7 +488,7 @@ smki_status insert_impl(smki_map* m, const float* xyz, const int32_t* label, con
   SMKI_HIP_TRY(scan_excl_i32(d_kept, d_kpos, n, (int32_t*)(d_sc + 1), d_stmp, q));
   // sync 1: counts, error word and box in one copy
   SMKI_HIP_TRY(hipMemcpyAsync(hh, d_hdr, kHdrTail, hipMemcpyDeviceToHost, q));
-  SMKI_HIP_TRY(hipStreamSynchronize(q));
+  SMKI_HIP_TRY(stream_wait(q));
   const int64_t nf = ((const int64_t*)hh)[0];
   const int64_t nk = (int64_t)((const int32_t*)hh)[2];
   int32_t bb[6];
