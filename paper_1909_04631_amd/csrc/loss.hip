@@ -488,7 +488,7 @@ smki_status prepare(const float* txyz, const int32_t* tlab, int64_t nt, const fl
   uint32_t e = 0;
   SMKI_HIP_TRY(hipMemcpyAsync(hb, b.bbox, sizeof(hb), hipMemcpyDeviceToHost, st));
   SMKI_HIP_TRY(hipMemcpyAsync(&e, b.err, sizeof(uint32_t), hipMemcpyDeviceToHost, st));
-  SMKI_HIP_TRY(hipStreamSynchronize(st));
+  SMKI_HIP_TRY(stream_wait(st));
   if (e) return err_status(e);
   g = BucketGeom{};
   g.planes = 1;

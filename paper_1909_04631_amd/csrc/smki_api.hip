@@ -15,6 +15,19 @@ int32_t smki_hip_error(hipError_t e) {
   return e == hipErrorOutOfMemory ? SMKI_E_OOM : SMKI_E_DEVICE;
 }
 
+// Wait for the stream by polling its status: the insert's waits are short,
+// and a blocking wait resumes the host only after an interrupt.  Waits longer
+// than 2 ms fall back to the blocking wait.
+hipError_t stream_wait(hipStream_t q) {
+  const auto t0 = std::chrono::steady_clock::now();
+  for (;;) {
+    const hipError_t e = hipStreamQuery(q);
+    if (e != hipErrorNotReady) return e;
+    if (std::chrono::steady_clock::now() - t0 > std::chrono::milliseconds(2))
+      return hipStreamSynchronize(q);
+  }
+}
+
 namespace {
 
 constexpr size_t kAlign = 256;
@@ -182,19 +195,6 @@ Stencil make_stencil(double lv, double margin) {
   std::stable_sort(s.offs.begin(), s.offs.end(),
                    [&](const StencilOff& a, const StencilOff& b) { return key(a) < key(b); });
   return s;
-}
-
-// Wait for the stream by polling its status: the insert's waits are short,
-// and a blocking wait resumes the host only after an interrupt.  Waits longer
-// than 2 ms fall back to the blocking wait.
-hipError_t stream_wait(hipStream_t q) {
-  const auto t0 = std::chrono::steady_clock::now();
-  for (;;) {
-    const hipError_t e = hipStreamQuery(q);
-    if (e != hipErrorNotReady) return e;
-    if (std::chrono::steady_clock::now() - t0 > std::chrono::milliseconds(2))
-      return hipStreamSynchronize(q);
-  }
 }
 
 hipError_t sync_read(smki_map* m, const void* dev, size_t bytes, void* host) {

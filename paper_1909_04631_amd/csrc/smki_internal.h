@@ -65,3 +65,6 @@ __device__ __forceinline__ int64_t floordiv_i64(int64_t a, int64_t b) {
 }
 
 static inline int64_t ceil_div_i64(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
+// Wait until the stream's work is done, polling (blocking after 2 ms).
+hipError_t stream_wait(hipStream_t q);
