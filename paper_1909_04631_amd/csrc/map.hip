@@ -23,17 +23,19 @@ __global__ void k_hash_clear(uint64_t* keys, int64_t n) {
 
 // Readout of Eq. (3)-(4): mean alpha/S, variance mean(1-mean)/(S+1), label =
 // argmax (lowest index on ties), occupancy = 1 - mean of the free class.
-// SEG consecutive lanes serve one query (SEG >= K, or SEG = 64 with several
-// classes per lane): every lane finds the query's block, loads its classes'
-// alpha, and the segment reduces the sum, the free class's alpha and the
-// argmax with shuffles; per-class outputs are stored by consecutive lanes.
+// SEG consecutive lanes serve one query, lane kl holding classes kl, kl + SEG,
+// ... (at most 8; SEG >= K / 8): every lane finds the query's block and loads
+// its classes' alpha (all loads in flight together), and the segment reduces
+// the sum, the free class's alpha and the argmax with shuffles.  Few lanes per
+// query keep the number of wavefronts, each waiting on the same chain of
+// dependent loads, small.
 template <int SEG>
 __global__ void __launch_bounds__(256) k_query(MapDev m, const int32_t* __restrict__ ijk,
                                                int64_t M, float* __restrict__ alpha,
                                                float* __restrict__ mean, float* __restrict__ var,
                                                int32_t* __restrict__ label,
                                                float* __restrict__ p_occ, int32_t free_class) {
-  constexpr int MAXC = SEG == 64 ? 4 : 1;   // classes per lane (K <= 255)
+  constexpr int MAXC = 8;   // classes per lane
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int64_t i = t / SEG;
   const int kl = (int)(t % SEG);
@@ -49,17 +51,23 @@ __global__ void __launch_bounds__(256) k_query(MapDev m, const int32_t* __restri
     v = ((vx - bx * B) * B + (vy - by * B)) * B + (vz - bz * B);
   }
   // this lane's classes kl, kl + SEG, ...; classes without a class block hold alpha0
+  // (all class-slot loads, then all alpha loads: each set in flight together)
+  int32_t cb[MAXC];
+#pragma unroll
+  for (int j = 0; j < MAXC; ++j) {
+    const int k = kl + j * SEG;
+    cb[j] = (live && k < K && slot >= 0) ? m.cslot[(int64_t)slot * K + k] : -1;
+  }
   float a[MAXC];
+#pragma unroll
+  for (int j = 0; j < MAXC; ++j) a[j] = cb[j] >= 0 ? m.calpha[(int64_t)cb[j] * B3 + v] : m.alpha0;
   double S = 0.0, af = 0.0;
   float bestv = -1.0f;
   int32_t best = 0;
 #pragma unroll
   for (int j = 0; j < MAXC; ++j) {
     const int k = kl + j * SEG;
-    a[j] = 0.0f;
     if (live && k < K) {
-      const int32_t cb = slot >= 0 ? m.cslot[(int64_t)slot * K + k] : -1;
-      a[j] = cb >= 0 ? m.calpha[(int64_t)cb * B3 + v] : m.alpha0;
       S += (double)a[j];
       if (k == free_class) af = (double)a[j];
       if (a[j] > bestv) {
@@ -187,9 +195,14 @@ hipError_t launch_query(const MapDev& m, const int32_t* ijk, int64_t M, float* a
                         float* var, int32_t* label, float* p_occ, int32_t free_class,
                         hipStream_t st) {
   if (M <= 0) return hipSuccess;
-  const int seg = m.K <= 8 ? 8 : m.K <= 16 ? 16 : m.K <= 32 ? 32 : 64;
+  // K <= 255: at most 8 classes per lane
+  const int seg = m.K <= 32 ? 4 : m.K <= 64 ? 8 : m.K <= 128 ? 16 : 32;
   const unsigned grid = nblk(M * seg, 256);
   switch (seg) {
+    case 4:
+      hipLaunchKernelGGL(k_query<4>, dim3(grid), dim3(256), 0, st, m, ijk, M, alpha, mean, var,
+                         label, p_occ, free_class);
+      break;
     case 8:
       hipLaunchKernelGGL(k_query<8>, dim3(grid), dim3(256), 0, st, m, ijk, M, alpha, mean, var,
                          label, p_occ, free_class);
@@ -198,12 +211,8 @@ hipError_t launch_query(const MapDev& m, const int32_t* ijk, int64_t M, float* a
       hipLaunchKernelGGL(k_query<16>, dim3(grid), dim3(256), 0, st, m, ijk, M, alpha, mean, var,
                          label, p_occ, free_class);
       break;
-    case 32:
-      hipLaunchKernelGGL(k_query<32>, dim3(grid), dim3(256), 0, st, m, ijk, M, alpha, mean, var,
-                         label, p_occ, free_class);
-      break;
     default:
-      hipLaunchKernelGGL(k_query<64>, dim3(grid), dim3(256), 0, st, m, ijk, M, alpha, mean, var,
+      hipLaunchKernelGGL(k_query<32>, dim3(grid), dim3(256), 0, st, m, ijk, M, alpha, mean, var,
                          label, p_occ, free_class);
       break;
   }

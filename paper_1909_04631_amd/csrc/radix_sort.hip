@@ -1,6 +1,6 @@
 // Stable least-significant-digit radix sort of (key, u32 value) pairs.
 //
-// One pass per digit of up to 8 bits: (1) per-tile digit histograms, (2) per
+// One pass per digit of up to 9 bits: (1) per-tile digit histograms, (2) per
 // digit, an exclusive scan of its tile counts and its total, (3) a stable
 // scatter, which adds the totals of the smaller digits itself.  In
 // both kernels a wavefront takes 1024 consecutive elements of its tile and
@@ -17,7 +17,8 @@ constexpr int RS_WAVES = RS_THREADS / SMKI_WAVE;
 constexpr int RS_ROUNDS = 16;
 constexpr int RS_SPAN = RS_ROUNDS * SMKI_WAVE;   // 1024 consecutive elements per wavefront
 constexpr int RS_TILE = RS_THREADS * RS_ROUNDS;  // 4096 elements per tile
-constexpr int RS_BINS = 256;
+constexpr int RS_MAXBITS = 9;                   // digits of up to 9 bits
+constexpr int RS_MAXBINS = 1 << RS_MAXBITS;
 
 template <typename K>
 __device__ __forceinline__ uint32_t digit_of(K key, int shift, uint32_t mask) {
@@ -46,17 +47,20 @@ __device__ __forceinline__ int64_t elem_index(int64_t tile_base, int w, int r, i
 // per round, the lowest lane of every group of equal digits adds the group's
 // size (the groups' digits are distinct, so no two lanes write one word, and a
 // wavefront's LDS accesses execute in issue order).
-template <typename K>
+template <typename K, int NB>
 __global__ void __launch_bounds__(RS_THREADS) k_hist(const K* __restrict__ keys, int64_t n,
                                                      int shift, int dbits, int64_t ntiles,
                                                      uint32_t* __restrict__ hist) {
-  __shared__ uint32_t wh[RS_WAVES][RS_BINS];
+  constexpr int DPT = NB / RS_THREADS;   // digits per thread
+  __shared__ uint32_t wh[RS_WAVES][NB];
   const int tid = threadIdx.x, lane = tid & (SMKI_WAVE - 1), w = tid / SMKI_WAVE;
   const uint32_t mask = (1u << dbits) - 1u;
   const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (SMKI_WAVE - lane));
   const int64_t tile_base = (int64_t)blockIdx.x * RS_TILE;
 #pragma unroll
-  for (int q = 0; q < RS_WAVES; ++q) wh[q][tid] = 0;
+  for (int q = 0; q < RS_WAVES; ++q)
+#pragma unroll
+    for (int j = 0; j < DPT; ++j) wh[q][tid * DPT + j] = 0;
   K key[RS_ROUNDS];
 #pragma unroll
   for (int r = 0; r < RS_ROUNDS; ++r) {
@@ -73,11 +77,16 @@ __global__ void __launch_bounds__(RS_THREADS) k_hist(const K* __restrict__ keys,
     __atomic_signal_fence(__ATOMIC_SEQ_CST);
   }
   __syncthreads();
-  uint32_t c = 0;
-#pragma unroll
-  for (int q = 0; q < RS_WAVES; ++q) c += wh[q][tid];
   // digit-major layout: all tiles of digit 0, then digit 1, ...
-  hist[(int64_t)tid * ntiles + blockIdx.x] = c;
+#pragma unroll
+  for (int j = 0; j < DPT; ++j) {
+    const int d = tid * DPT + j;
+    if (d > (int)mask) continue;
+    uint32_t c = 0;
+#pragma unroll
+    for (int q = 0; q < RS_WAVES; ++q) c += wh[q][d];
+    hist[(int64_t)d * ntiles + blockIdx.x] = c;
+  }
 }
 
 // Per digit (one workgroup each): exclusive scan, in place, of the digit's
@@ -163,7 +172,7 @@ __device__ __forceinline__ void write_records(const K* skey, const uint32_t* sva
 //   3. the elements are placed in LDS in digit order, then written out by
 //      consecutive threads, so the stores of each digit's run are contiguous.
 // pl.rec_in (last pass only, optional): also gather the records by value.
-template <typename K>
+template <typename K, int NB>
 __global__ void __launch_bounds__(RS_THREADS) k_scatter(const K* __restrict__ keys,
                                                         const uint32_t* __restrict__ vals,
                                                         K* __restrict__ okeys,
@@ -172,9 +181,10 @@ __global__ void __launch_bounds__(RS_THREADS) k_scatter(const K* __restrict__ ke
                                                         const uint32_t* __restrict__ offs,
                                                         const uint32_t* __restrict__ total,
                                                         SortPayload pl) {
-  __shared__ uint32_t gbase[RS_BINS];    // first global position of the tile's digit-d elements
-  __shared__ uint32_t lstart[RS_BINS];   // first index of digit d inside the tile
-  __shared__ uint32_t wh[RS_WAVES][RS_BINS];   // per wavefront: digit counts, then first index
+  constexpr int DPT = NB / RS_THREADS;   // digits per thread: tid * DPT + j
+  __shared__ uint32_t gbase[NB];    // first global position of the tile's digit-d elements
+  __shared__ uint32_t lstart[NB];   // first index of digit d inside the tile
+  __shared__ uint32_t wh[RS_WAVES][NB];   // per wavefront: digit counts, then first index
   __shared__ uint32_t wsum[2][RS_WAVES];
   __shared__ K skey[RS_TILE];
   __shared__ uint32_t sval[RS_TILE];
@@ -182,10 +192,18 @@ __global__ void __launch_bounds__(RS_THREADS) k_scatter(const K* __restrict__ ke
   const uint32_t mask = (1u << dbits) - 1u;
   const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (SMKI_WAVE - lane));
   const int64_t tile_base = (int64_t)blockIdx.x * RS_TILE;
-  const uint32_t in_digit = offs[(int64_t)tid * ntiles + blockIdx.x];   // earlier tiles' digit-tid count
-  const uint32_t dtot = total[tid];
+  uint32_t in_digit[DPT], dtot[DPT];   // earlier tiles' count of the digit, its total
 #pragma unroll
-  for (int q = 0; q < RS_WAVES; ++q) wh[q][tid] = 0;
+  for (int j = 0; j < DPT; ++j) {
+    const int d = tid * DPT + j;
+    const bool real = d <= (int)mask;
+    in_digit[j] = real ? offs[(int64_t)d * ntiles + blockIdx.x] : 0u;
+    dtot[j] = real ? total[d] : 0u;
+  }
+#pragma unroll
+  for (int q = 0; q < RS_WAVES; ++q)
+#pragma unroll
+    for (int j = 0; j < DPT; ++j) wh[q][tid * DPT + j] = 0;
   K key[RS_ROUNDS];
   uint32_t val[RS_ROUNDS];
 #pragma unroll
@@ -208,18 +226,24 @@ __global__ void __launch_bounds__(RS_THREADS) k_scatter(const K* __restrict__ ke
     __atomic_signal_fence(__ATOMIC_SEQ_CST);
   }
   __syncthreads();
-  // 2. digit tid: the wavefronts' counts, the tile's count and its first index
-  //    inside the tile; the digit's first global position (the totals of the
-  //    smaller digits plus the digit's count in earlier tiles)
+  // 2. digits of thread tid: the wavefronts' counts, the tile's count and its
+  //    first index inside the tile; the digit's first global position (the
+  //    totals of the smaller digits plus the digit's count in earlier tiles)
   {
-    uint32_t pw[RS_WAVES];
-    uint32_t c = 0;
+    uint32_t pw[DPT][RS_WAVES], c[DPT];
+    uint32_t csum = 0, gsum = 0;
 #pragma unroll
-    for (int q = 0; q < RS_WAVES; ++q) {
-      pw[q] = c;
-      c += wh[q][tid];
+    for (int j = 0; j < DPT; ++j) {
+      c[j] = 0;
+#pragma unroll
+      for (int q = 0; q < RS_WAVES; ++q) {
+        pw[j][q] = c[j];
+        c[j] += wh[q][tid * DPT + j];
+      }
+      csum += c[j];
+      gsum += dtot[j];
     }
-    uint32_t inc = c, incg = dtot;
+    uint32_t inc = csum, incg = gsum;
 #pragma unroll
     for (int o = 1; o < SMKI_WAVE; o <<= 1) {
       const uint32_t u = __shfl_up(inc, o, SMKI_WAVE);
@@ -234,17 +258,22 @@ __global__ void __launch_bounds__(RS_THREADS) k_scatter(const K* __restrict__ ke
       wsum[1][w] = incg;
     }
     __syncthreads();
-    uint32_t pre = 0, preg = 0;
+    uint32_t ls = inc - csum, lg = incg - gsum;
     for (int q = 0; q < w; ++q) {
-      pre += wsum[0][q];
-      preg += wsum[1][q];
+      ls += wsum[0][q];
+      lg += wsum[1][q];
     }
-    const uint32_t ls = pre + inc - c;
-    lstart[tid] = ls;
-    gbase[tid] = preg + incg - dtot + in_digit;
-    // column tid of wh is read and rewritten by thread tid only
+    // the digits of thread tid are read and rewritten by thread tid only
 #pragma unroll
-    for (int q = 0; q < RS_WAVES; ++q) wh[q][tid] = ls + pw[q];
+    for (int j = 0; j < DPT; ++j) {
+      const int d = tid * DPT + j;
+      lstart[d] = ls;
+      gbase[d] = lg + in_digit[j];
+#pragma unroll
+      for (int q = 0; q < RS_WAVES; ++q) wh[q][d] = ls + pw[j][q];
+      ls += c[j];
+      lg += dtot[j];
+    }
   }
   __syncthreads();
   // 3. place in digit order, then write out contiguously
@@ -275,14 +304,29 @@ __global__ void __launch_bounds__(RS_THREADS) k_scatter(const K* __restrict__ ke
     write_records<K, false>(skey, sval, gbase, lstart, tile_n, shift, mask, okeys, ovals, pl);
 }
 
+template <typename K, int NB>
+void launch_pass(const K* sk, const uint32_t* sv, K* dk, uint32_t* dv, int64_t n, int shift,
+                 int dbits, int64_t ntiles, uint32_t* hist, uint32_t* total, const SortPayload& pl,
+                 hipStream_t st) {
+  hipLaunchKernelGGL((k_hist<K, NB>), dim3((unsigned)ntiles), dim3(RS_THREADS), 0, st, sk, n,
+                     shift, dbits, ntiles, hist);
+  hipLaunchKernelGGL(k_digit_scan, dim3(1u << dbits), dim3(RS_THREADS), 0, st, hist, ntiles,
+                     total);
+  hipLaunchKernelGGL((k_scatter<K, NB>), dim3((unsigned)ntiles), dim3(RS_THREADS), 0, st, sk, sv,
+                     dk, dv, n, shift, dbits, ntiles, (const uint32_t*)hist,
+                     (const uint32_t*)total, pl);
+}
+
 template <typename K>
 hipError_t sort_impl(K* keys, uint32_t* vals, K* akeys, uint32_t* avals, int64_t n, int bits,
                      void* tmp, hipStream_t st, const SortPayload* pl) {
   if (n <= 1 || bits <= 0) return hipSuccess;
   const int64_t ntiles = ceil_div_i64(n, RS_TILE);
   uint32_t* hist = (uint32_t*)tmp;
-  uint32_t* total = hist + RS_BINS * ntiles;   // RS_BINS digit totals
-  const int passes = (bits + 7) / 8;
+  uint32_t* total = hist + RS_MAXBINS * ntiles;   // digit totals
+  // fewest passes of at most 9 bits, the bits spread evenly over them; digits
+  // of 8 bits or fewer use the 256-bin kernels (smaller LDS footprint)
+  const int passes = (bits + RS_MAXBITS - 1) / RS_MAXBITS;
   const int dbits = (bits + passes - 1) / passes;
   K* src_k = keys;
   uint32_t* src_v = vals;
@@ -290,13 +334,12 @@ hipError_t sort_impl(K* keys, uint32_t* vals, K* akeys, uint32_t* avals, int64_t
   uint32_t* dst_v = avals;
   for (int p = 0; p < passes; ++p) {
     const int shift = p * dbits;
-    hipLaunchKernelGGL(k_hist<K>, dim3((unsigned)ntiles), dim3(RS_THREADS), 0, st, src_k, n,
-                       shift, dbits, ntiles, hist);
-    hipLaunchKernelGGL(k_digit_scan, dim3(RS_BINS), dim3(RS_THREADS), 0, st, hist, ntiles, total);
     const SortPayload none{};
-    hipLaunchKernelGGL(k_scatter<K>, dim3((unsigned)ntiles), dim3(RS_THREADS), 0, st, src_k,
-                       src_v, dst_k, dst_v, n, shift, dbits, ntiles, (const uint32_t*)hist,
-                       (const uint32_t*)total, (p == passes - 1 && pl) ? *pl : none);
+    const SortPayload& pp = (p == passes - 1 && pl) ? *pl : none;
+    if (dbits <= 8)
+      launch_pass<K, 256>(src_k, src_v, dst_k, dst_v, n, shift, dbits, ntiles, hist, total, pp, st);
+    else
+      launch_pass<K, 512>(src_k, src_v, dst_k, dst_v, n, shift, dbits, ntiles, hist, total, pp, st);
     K* tk = src_k; src_k = dst_k; dst_k = tk;
     uint32_t* tv = src_v; src_v = dst_v; dst_v = tv;
   }
@@ -313,7 +356,7 @@ hipError_t sort_impl(K* keys, uint32_t* vals, K* akeys, uint32_t* avals, int64_t
 
 size_t radix_tmp_bytes(int64_t n) {
   const int64_t ntiles = ceil_div_i64(n > 0 ? n : 1, RS_TILE);
-  return sizeof(uint32_t) * RS_BINS * (ntiles + 1) + 256;   // tile counts, digit totals
+  return sizeof(uint32_t) * RS_MAXBINS * (ntiles + 1) + 256;   // tile counts, digit totals
 }
 
 hipError_t radix_sort_u32(uint32_t* keys, uint32_t* vals, uint32_t* ak, uint32_t* av, int64_t n,

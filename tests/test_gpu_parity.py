@@ -337,11 +337,20 @@ def test_reach_beyond_limit_is_rejected_and_map_unchanged():
 # ---------------------------------------------------------------------------
 # full-size LiDAR scan: sampled voxels by brute force, counts by the oracle
 # ---------------------------------------------------------------------------
-def test_lidar_scan_full_size_sampled():
+@pytest.mark.parametrize("K", [20, 2])
+def test_lidar_scan_full_size_sampled(K):
+    # K = 20: 29-bit row keys, four 8-bit radix passes; K = 2: 26-bit keys,
+    # three 9-bit passes
+    import dataclasses
     sc = scenes.make_config(1)
+    if K != sc.params.K:
+        s0 = sc.scans[0]
+        lab = np.where(s0.label < 0, s0.label, s0.label % K).astype(np.int32)
+        sc = dataclasses.replace(sc, params=dataclasses.replace(sc.params, K=K),
+                                 scans=[scenes.Scan(s0.xyz, lab, s0.origin)])
     p = sc.params.f32()
     s = sc.scans[0]
-    _print_case(f"lidar full size n={s.xyz.shape[0]}")
+    _print_case(f"lidar full size n={s.xyz.shape[0]} K={K}")
     gm = gpu_map_of(sc)
     st = gm.stats()
     print("lidar stats", st, flush=True)
