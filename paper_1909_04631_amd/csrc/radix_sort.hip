@@ -2,11 +2,11 @@
 //
 // One pass per digit of up to 9 bits: (1) per-tile digit histograms, (2) per
 // digit, an exclusive scan of its tile counts and its total, (3) a stable
-// scatter, which adds the totals of the smaller digits itself.  In
-// both kernels a wavefront takes 1024 consecutive elements of its tile and
-// groups equal digits with wave ballots (the peers of a lane are the lanes
-// whose digit agrees on every bit); its running digit counts live in its own
-// LDS row, so rounds need no barrier.  Integer work only: bit-exact and
+// scatter, which adds the totals of the smaller digits itself.  In the
+// scatter a wavefront takes 1024 consecutive elements of its tile and groups
+// equal digits with wave ballots (the peers of a lane are the lanes whose
+// digit agrees on every bit); its running digit counts live in its own LDS
+// row, so rounds need no barrier.  Integer work only: bit-exact and
 // run-to-run deterministic.
 #include "smki_internal.h"
 
@@ -43,24 +43,23 @@ __device__ __forceinline__ int64_t elem_index(int64_t tile_base, int w, int r, i
   return tile_base + (int64_t)w * RS_SPAN + (int64_t)r * SMKI_WAVE + lane;
 }
 
-// Per-tile digit counts.  Each wavefront counts its span into its own LDS row:
-// per round, the lowest lane of every group of equal digits adds the group's
-// size (the groups' digits are distinct, so no two lanes write one word, and a
-// wavefront's LDS accesses execute in issue order).
+// Per-tile digit counts: every element adds 1 to its digit's counter with an
+// LDS atomic (integer counts: the order of the adds does not matter).  Lane l
+// uses copy l % NC of the counters, rows padded by one word, so that the lanes
+// of one wavefront with equal digits neither hit one address nor one bank;
+// the copies are summed at the end.
 template <typename K, int NB>
 __global__ void __launch_bounds__(RS_THREADS) k_hist(const K* __restrict__ keys, int64_t n,
                                                      int shift, int dbits, int64_t ntiles,
                                                      uint32_t* __restrict__ hist) {
+  constexpr int NC = 16;         // counter copies
+  constexpr int STR = NB + 1;    // padded row of one copy
   constexpr int DPT = NB / RS_THREADS;   // digits per thread
-  __shared__ uint32_t wh[RS_WAVES][NB];
+  __shared__ uint32_t h[NC * STR];
   const int tid = threadIdx.x, lane = tid & (SMKI_WAVE - 1), w = tid / SMKI_WAVE;
   const uint32_t mask = (1u << dbits) - 1u;
-  const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (SMKI_WAVE - lane));
   const int64_t tile_base = (int64_t)blockIdx.x * RS_TILE;
-#pragma unroll
-  for (int q = 0; q < RS_WAVES; ++q)
-#pragma unroll
-    for (int j = 0; j < DPT; ++j) wh[q][tid * DPT + j] = 0;
+  for (int i = tid; i < NC * STR; i += RS_THREADS) h[i] = 0;
   K key[RS_ROUNDS];
 #pragma unroll
   for (int r = 0; r < RS_ROUNDS; ++r) {
@@ -68,14 +67,10 @@ __global__ void __launch_bounds__(RS_THREADS) k_hist(const K* __restrict__ keys,
     key[r] = i < n ? keys[i] : (K)0;
   }
   __syncthreads();
+  uint32_t* hc = h + (lane % NC) * STR;
 #pragma unroll
-  for (int r = 0; r < RS_ROUNDS; ++r) {
-    const bool valid = elem_index(tile_base, w, r, lane) < n;
-    const uint32_t d = digit_of(key[r], shift, mask);
-    const uint64_t peers = digit_peers(d, valid, dbits);
-    if (valid && (peers & lt_mask) == 0) wh[w][d] += (uint32_t)__popcll(peers);
-    __atomic_signal_fence(__ATOMIC_SEQ_CST);
-  }
+  for (int r = 0; r < RS_ROUNDS; ++r)
+    if (elem_index(tile_base, w, r, lane) < n) atomicAdd(&hc[digit_of(key[r], shift, mask)], 1u);
   __syncthreads();
   // digit-major layout: all tiles of digit 0, then digit 1, ...
 #pragma unroll
@@ -84,7 +79,7 @@ __global__ void __launch_bounds__(RS_THREADS) k_hist(const K* __restrict__ keys,
     if (d > (int)mask) continue;
     uint32_t c = 0;
 #pragma unroll
-    for (int q = 0; q < RS_WAVES; ++q) c += wh[q][d];
+    for (int q = 0; q < NC; ++q) c += h[q * STR + d];
     hist[(int64_t)d * ntiles + blockIdx.x] = c;
   }
 }
