@@ -64,7 +64,8 @@ struct SplatArgs {
   uint32_t* umask;            // [n_units] bit d: piece d is non-zero (and written)
   uint32_t piece_mask;        // pieces a unit may contribute (all 27, or the own block and
                               // its 6 face neighbours for the extended-block selection)
-  int4* sinfo;                // [slots] (first unit, units, union of the units' masks, 0)
+  int4* sinfo;                // [slots] (first unit, units, union of the units' masks,
+                              // the first unit's mask)
   int32_t n_slots;
   // targets (blocks within reach of a row block), on the extended grid
   int32_t eblo[3], enb[3];

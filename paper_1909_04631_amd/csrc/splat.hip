@@ -353,14 +353,15 @@ __global__ void __launch_bounds__(SMKI_WAVE) k_splat(SplatArgs a) {
 // ---------------------------------------------------------------------------
 // merge
 // ---------------------------------------------------------------------------
-// Per slot: its units and the union of their non-zero pieces.
+// Per slot: its units, the union of their non-zero pieces, and the first
+// unit's own pieces.
 __global__ void k_slot_info(SplatArgs a) {
   const int32_t s = blockIdx.x * blockDim.x + threadIdx.x;
   if (s >= a.n_slots) return;
   const int32_t u0 = a.ustart[s], nu = a.nunits[s];
   uint32_t m = 0;
   for (int32_t w = u0; w < u0 + nu; ++w) m |= a.umask[w];
-  a.sinfo[s] = make_int4(u0, nu, (int32_t)m, 0);
+  a.sinfo[s] = make_int4(u0, nu, (int32_t)m, nu > 0 ? (int32_t)a.umask[u0] : 0);
 }
 
 // One workgroup per active target block, one thread per voxel.  Each thread
@@ -446,7 +447,7 @@ __global__ void __launch_bounds__(B * B * B) k_merge(SplatArgs a, int32_t n_targ
   constexpr int B3 = S::B3, NT = S::NT, CPG = S::CPG, MAXC = S::MAXC;
   // [class][neighbour d]: (first unit, units) of the neighbour's slot if some
   // unit of it wrote piece 26 - d (the part of its region inside this block),
-  // else (0, 0)
+  // else (0, 0); units negated when the first unit did not write the piece
   __shared__ int2 ent[CPG * 27];
   __shared__ int32_t cflag[CPG], clist[CPG], cblk[CPG], ncls_s;
   __shared__ int32_t red[NT / SMKI_WAVE];
@@ -492,7 +493,7 @@ __global__ void __launch_bounds__(B * B * B) k_merge(SplatArgs a, int32_t n_targ
         int2 e2 = make_int2(0, 0);
         if (sl[j] >= 0) {
           const int4 e = a.sinfo[sl[j]];
-          if ((e.z >> (26 - d)) & 1) e2 = make_int2(e.x, e.y);
+          if ((e.z >> (26 - d)) & 1) e2 = make_int2(e.x, ((e.w >> (26 - d)) & 1) ? e.y : -e.y);
         }
         ent[yc * 27 + d] = e2;
       }
@@ -518,12 +519,13 @@ __global__ void __launch_bounds__(B * B * B) k_merge(SplatArgs a, int32_t n_targ
           const int ci = pk[k] >> 16;
           const int2 e = E[ci];
           const int p = 26 - ci;
-          for (int32_t w = e.x; w < e.x + e.y; ++w)
+          for (int32_t w = e.x; w < e.x + abs(e.y); ++w)
             if ((a.umask[w] >> p) & 1u)
               kahan_add(sm, comp, part_at<DR3, WIDE>(a.part, w, pk[k] & 0xffff));
         }
       } else {
-        // the first unit of every candidate: all loads in flight together
+        // the first unit of every candidate: all loads in flight together (the
+        // entry says whether the first unit wrote the piece: no mask load here)
         float first[MAXC];
 #pragma unroll
         for (int k = 0; k < MAXC; ++k) {
@@ -531,9 +533,7 @@ __global__ void __launch_bounds__(B * B * B) k_merge(SplatArgs a, int32_t n_targ
           if (pk[k] >= 0) {
             const int ci = pk[k] >> 16;
             const int2 e = E[ci];
-            // a single-unit slot's union mask is the unit's own mask
-            if (e.y == 1 || (e.y > 1 && ((a.umask[e.x] >> (26 - ci)) & 1u)))
-              first[k] = part_at<DR3, WIDE>(a.part, e.x, pk[k] & 0xffff);
+            if (e.y > 0) first[k] = part_at<DR3, WIDE>(a.part, e.x, pk[k] & 0xffff);
           }
         }
 #pragma unroll
@@ -543,7 +543,7 @@ __global__ void __launch_bounds__(B * B * B) k_merge(SplatArgs a, int32_t n_targ
           const int2 e = E[ci];
           if (e.y == 0) continue;
           kahan_add(sm, comp, first[k]);
-          for (int32_t w = e.x + 1; w < e.x + e.y; ++w)
+          for (int32_t w = e.x + 1; w < e.x + abs(e.y); ++w)
             if ((a.umask[w] >> (26 - ci)) & 1u)
               kahan_add(sm, comp, part_at<DR3, WIDE>(a.part, w, pk[k] & 0xffff));
         }
