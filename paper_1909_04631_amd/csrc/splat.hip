@@ -16,11 +16,12 @@
 //           the cell changes.  Every lane owns distinct LDS addresses, so the
 //           sum order of every voxel is the row order: run-to-run identical.
 //           The region is written out as the chunk's partial sums.
-//   merge   One workgroup per target block: for every class and every
-//           neighbouring (class, block) whose region covers a voxel, add the
-//           partial sums of its chunks in chunk order (compensated), then add
-//           the total to the voxel's concentration: one exclusive write per
-//           (voxel, class).
+//   merge   One workgroup per target block: for every class, add in double
+//           the partial sums that the neighbouring (class, block) regions
+//           covering a voxel hold for it (first chunks in a fixed neighbour
+//           order, then the later chunks in chunk order), then add the total
+//           to the voxel's concentration: one exclusive write per (voxel,
+//           class).
 //
 // Kernel evaluation: with s = 1 - r, f(1 - s) = s^5 Q(s^2) exactly (the Taylor
 // series of the sparse kernel about r = 1 has only odd powers from s^5 on);
@@ -370,9 +371,10 @@ __global__ void k_slot_info(SplatArgs a) {
 // the slots of the 27 neighbouring blocks for a group of classes into LDS (all
 // lookups in flight together), keeping for each neighbour only whether its
 // units wrote the piece that lies in this block, and lists the classes that
-// have any.  For every listed class, each thread adds the pieces that cover its
-// voxel (fixed neighbour order, then chunk order; compensated), with the
-// first-chunk loads of all its candidates issued before summing; blocks
+// have any.  For every listed class, each thread adds, in double, the pieces
+// that cover its voxel: the first chunks of all its candidates (loads issued
+// together, in the fixed neighbour order), then the later chunks of multi-chunk
+// slots eight at a time; blocks
 // allocated by this insert are written alpha0 + sum, older blocks updated in
 // place where the sum is non-zero.  The per-thread state is kept small (packed
 // candidates, slot entries re-read from LDS) so that 8 wavefronts fit per SIMD.
@@ -439,8 +441,10 @@ __device__ __forceinline__ void kahan_add(float& sm, float& comp, float v) {
   sm = tv;
 }
 
+// (B = 8 up to reach 3: at most 64 registers, eight wavefronts per SIMD)
 template <int B, int R, bool WIDE>
-__global__ void __launch_bounds__(B * B * B) k_merge(SplatArgs a, int32_t n_targets) {
+__global__ void __launch_bounds__(B * B * B, (B == 8 && R <= 3 && !WIDE) ? 8 : 1)
+k_merge(SplatArgs a, int32_t n_targets) {
   using S = MergeShape<B, R>;
   constexpr int DR = B + 2 * R;
   constexpr int DR3 = DR * DR * DR;
@@ -524,29 +528,48 @@ __global__ void __launch_bounds__(B * B * B) k_merge(SplatArgs a, int32_t n_targ
               kahan_add(sm, comp, part_at<DR3, WIDE>(a.part, w, pk[k] & 0xffff));
         }
       } else {
-        // the first unit of every candidate: all loads in flight together (the
-        // entry says whether the first unit wrote the piece: no mask load here)
+        // Branch-free over the candidates: every candidate loads (an absent one
+        // reads element 0 of the buffer and discards it) and the sum is kept in
+        // double; then the later units of multi-unit slots, eight at a time
+        // (their masks, then their pieces, each set of loads in flight together).
         float first[MAXC];
+        bool more = false;
 #pragma unroll
         for (int k = 0; k < MAXC; ++k) {
-          first[k] = 0.0f;
-          if (pk[k] >= 0) {
+          const int pkk = pk[k];
+          const int2 e = E[pkk >= 0 ? (pkk >> 16) : 13];
+          const bool ld = pkk >= 0 && e.y > 0;
+          const float v = part_at<DR3, WIDE>(a.part, ld ? e.x : 0, ld ? (pkk & 0xffff) : 0);
+          first[k] = ld ? v : 0.0f;
+          more = more || (pkk >= 0 && (e.y > 1 || e.y < -1));
+        }
+        double sd = 0.0;
+#pragma unroll
+        for (int k = 0; k < MAXC; ++k) sd += (double)first[k];
+        if (more) {
+#pragma unroll
+          for (int k = 0; k < MAXC; ++k) {
+            if (pk[k] < 0) continue;
             const int ci = pk[k] >> 16;
             const int2 e = E[ci];
-            if (e.y > 0) first[k] = part_at<DR3, WIDE>(a.part, e.x, pk[k] & 0xffff);
+            const int32_t w1 = e.x + abs(e.y);
+            for (int32_t w0 = e.x + 1; w0 < w1; w0 += 8) {
+              uint32_t mk[8];
+#pragma unroll
+              for (int j = 0; j < 8; ++j) mk[j] = w0 + j < w1 ? a.umask[w0 + j] : 0u;
+              float v[8];
+#pragma unroll
+              for (int j = 0; j < 8; ++j) {
+                const bool has = (mk[j] >> (26 - ci)) & 1u;
+                const float x = part_at<DR3, WIDE>(a.part, has ? w0 + j : 0, has ? (pk[k] & 0xffff) : 0);
+                v[j] = has ? x : 0.0f;
+              }
+#pragma unroll
+              for (int j = 0; j < 8; ++j) sd += (double)v[j];
+            }
           }
         }
-#pragma unroll
-        for (int k = 0; k < MAXC; ++k) {
-          if (pk[k] < 0) continue;
-          const int ci = pk[k] >> 16;
-          const int2 e = E[ci];
-          if (e.y == 0) continue;
-          kahan_add(sm, comp, first[k]);
-          for (int32_t w = e.x + 1; w < e.x + abs(e.y); ++w)
-            if ((a.umask[w] >> (26 - ci)) & 1u)
-              kahan_add(sm, comp, part_at<DR3, WIDE>(a.part, w, pk[k] & 0xffff));
-        }
+        sm = (float)sd;
       }
       const int32_t cb = cblk[yc];   // allocated for every class with rows reaching here
       float* dst = a.map.calpha + (int64_t)cb * B3 + tid;
