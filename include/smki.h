@@ -59,7 +59,7 @@ typedef struct smki_map smki_map;
 typedef struct smki_options {
   int64_t initial_blocks;   /* initial pool capacity in blocks (0: 4096); grows on demand */
   int32_t unit_budget;      /* rows of one (class, block) that one splat work unit
-                               takes (0: 1024; at most 2^24); a (class, block) holding
+                               takes (0: 512; at most 2^24); a (class, block) holding
                                more rows is split into several units */
   int32_t model;            /* SMKI_MODEL_SBKI (default) or SMKI_MODEL_SCSM; l and sigma0
                                are not used by the counting model */

@@ -5,7 +5,7 @@
 #define SMKI_MAX_REACH 4            // largest stencil reach in voxels
 #define SMKI_MAX_OFFS 729           // (2 * SMKI_MAX_REACH + 1)^3
 #define SMKI_POLY_N 7               // coefficients of the kernel polynomial
-#define SMKI_CHUNK 1024             // default rows of one (class, block) per splat work unit
+#define SMKI_CHUNK 512              // default rows of one (class, block) per splat work unit
 #define SMKI_STAT_COPIES 64         // copies of the insert counters (spread the atomics)
 #define SMKI_TIMING_RING 64         // inserts whose kernel times are kept
 
