@@ -664,6 +664,7 @@ smki_status insert_impl(smki_map* m, const float* xyz, const int32_t* label, con
   zc.add<int4>(n_units);
   zc.add<float>((size_t)n_units * DR3);
   zc.add<uint32_t>(n_units);
+  zc.add<int32_t>(n_units);   // splat launch order
   zc.add<int4>(n_slots);
   for (int i = 0; i < 3; ++i) zc.add<int32_t>(ntk);
   SMKI_HIP_TRY(m->a_tgts.reserve(zc.total));
@@ -680,6 +681,7 @@ smki_status insert_impl(smki_map* m, const float* xyz, const int32_t* label, con
   int4* d_units = C.take<int4>(n_units);
   float* d_part = C.take<float>((size_t)n_units * DR3);
   uint32_t* d_umask = C.take<uint32_t>(n_units);
+  int32_t* d_uorder = C.take<int32_t>(n_units);
   int4* d_sinfo = C.take<int4>(n_slots);
   int32_t* d_need = C.take<int32_t>(ntk);
   int32_t* d_cpos = C.take<int32_t>(ntk);
@@ -687,6 +689,7 @@ smki_status insert_impl(smki_map* m, const float* xyz, const int32_t* label, con
   sa.tgt_active = d_active;
   sa.tgt_slot = d_tslot;
   sa.units = d_units;
+  sa.uorder = d_uorder;
   sa.part = d_part;
   sa.part_elems = n_units * DR3;
   sa.umask = d_umask;
@@ -696,7 +699,7 @@ smki_status insert_impl(smki_map* m, const float* xyz, const int32_t* label, con
   // the splat first (its counters were cleared before the bucketing); what
   // only the later kernels read is prepared while it runs
   SMKI_HIP_TRY(launch_unit_table(d_nun, d_ust, ps.head, ps.slot_lin, g.n_blocks, m->chunk,
-                                 (int32_t)max_slots, d_units, q));
+                                 (int32_t)max_slots, ps.d_nslots, d_nunits, d_units, d_uorder, q));
   m->ev = m->evr[m->n_timed++ % SMKI_TIMING_RING];
   SMKI_HIP_TRY(hipEventRecord(m->ev[0], q));
   SMKI_HIP_TRY(launch_splat(sa, n_units, q));

@@ -57,6 +57,7 @@ struct SplatArgs {
   const int32_t* nunits;      // [slots] chunks of the slot
   const int32_t* ustart;      // [slots] first unit of the slot
   const int4* units;          // [n_units] (first row, end row, slot, class)
+  const int32_t* uorder;      // [n_units] unit of splat workgroup b (nullable: b itself)
   int64_t part_elems;         // n_units (B + 2R)^3
   float* part;                // [n_units][(B + 2R)^3] partial sums of each unit's region, by
                               // piece: the region split into the 27 parts that fall in the
@@ -88,9 +89,11 @@ hipError_t launch_list_targets(const int32_t* mark, const int32_t* mpos, int64_t
                                int32_t* tgt_elin, int32_t* ext2t, hipStream_t st);
 hipError_t launch_slot_units(const int32_t* head, const int32_t* d_nslots, int32_t max_slots,
                              int32_t chunk, int32_t* nunits, hipStream_t st);
+// units of every slot, and (order, nullable) the splat's launch order
 hipError_t launch_unit_table(const int32_t* nunits, const int32_t* ustart, const int32_t* head,
                              const int32_t* slot_lin, int64_t n_blocks, int32_t chunk,
-                             int32_t max_slots, int4* units, hipStream_t st);
+                             int32_t max_slots, const int32_t* d_nslots, const int32_t* d_nunits,
+                             int4* units, int32_t* order, hipStream_t st);
 hipError_t launch_splat(const SplatArgs& a, int64_t n_units, hipStream_t st);
 hipError_t launch_merge(const SplatArgs& a, int32_t n_targets, hipStream_t st);
 // class blocks: which (target, class) pairs receive rows, which need a new

@@ -90,10 +90,16 @@ __global__ void k_slot_units(const int32_t* __restrict__ head, const int32_t* __
 }
 
 // Work units of every slot: (first row, end row, slot, class), chunk rows each.
+// order (optional): the splat's launch order, longest first: the slots'
+// full-chunk units (slot s's k-th at ustart[s] - s + k, since every slot before
+// it has one last unit), then every slot's last unit (at F + s, F = units -
+// slots).  A late long unit would leave the rest of the GPU idle at the end.
 __global__ void k_unit_table(const int32_t* __restrict__ nunits, const int32_t* __restrict__ ustart,
                              const int32_t* __restrict__ head, const int32_t* __restrict__ slot_lin,
                              int64_t n_blocks, int32_t chunk, int32_t max_slots,
-                             int4* __restrict__ units) {
+                             const int32_t* __restrict__ d_nslots,
+                             const int32_t* __restrict__ d_nunits, int4* __restrict__ units,
+                             int32_t* __restrict__ order) {
   const int32_t s = blockIdx.x * blockDim.x + threadIdx.x;
   if (s >= max_slots) return;
   const int32_t n = nunits[s];
@@ -103,6 +109,7 @@ __global__ void k_unit_table(const int32_t* __restrict__ nunits, const int32_t* 
   for (int32_t k = 0; k < n; ++k) {
     const int32_t r0 = h0 + k * chunk;
     units[b + k] = make_int4(r0, min(h1, r0 + chunk), s, plane);
+    if (order) order[k + 1 < n ? b - s + k : (*d_nunits - *d_nslots) + s] = b + k;
   }
 }
 
@@ -165,7 +172,8 @@ __global__ void __launch_bounds__(SMKI_WAVE) k_splat(SplatArgs a) {
   __shared__ float4 acc4[NACC4];   // the region + a dummy slot for pad lanes
   float* acc = (float*)acc4;
   const int lane = threadIdx.x;
-  const int4 u = a.units[blockIdx.x];   // (first row, end row, slot, class)
+  const int32_t uid = a.uorder ? a.uorder[blockIdx.x] : (int32_t)blockIdx.x;
+  const int4 u = a.units[uid];   // (first row, end row, slot, class)
   const int32_t r0 = u.x, r1 = u.y;
   const float4 kc = a.cls[u.w];         // the kernel of the unit's class
   const float l2 = kc.x, inv_l = kc.y, cscale = kc.z;
@@ -315,7 +323,7 @@ __global__ void __launch_bounds__(SMKI_WAVE) k_splat(SplatArgs a) {
   // contiguously.  Piece geometry is compile-time, so the index arithmetic
   // folds to constants.
   using PC = Pieces<B, R>;
-  float* out = a.part + (int64_t)blockIdx.x * DR3;
+  float* out = a.part + (int64_t)uid * DR3;
   constexpr int MAXPER = (B * B * B + SMKI_WAVE - 1) / SMKI_WAVE;   // the largest piece is the block
   uint32_t touched = 0;
 #pragma unroll
@@ -346,7 +354,7 @@ __global__ void __launch_bounds__(SMKI_WAVE) k_splat(SplatArgs a) {
       if (k < per && i < n) out[b + i] = v[k];
     }
   }
-  if (lane == 0) a.umask[blockIdx.x] = touched;
+  if (lane == 0) a.umask[uid] = touched;
   if (lane == 0)
     atomicAdd(&a.stats[(blockIdx.x % SMKI_STAT_COPIES) * 4 + 1], (unsigned long long)npair);
 }
@@ -784,10 +792,11 @@ hipError_t launch_slot_units(const int32_t* head, const int32_t* d_nslots, int32
 
 hipError_t launch_unit_table(const int32_t* nunits, const int32_t* ustart, const int32_t* head,
                              const int32_t* slot_lin, int64_t n_blocks, int32_t chunk,
-                             int32_t max_slots, int4* units, hipStream_t st) {
+                             int32_t max_slots, const int32_t* d_nslots, const int32_t* d_nunits,
+                             int4* units, int32_t* order, hipStream_t st) {
   if (max_slots <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_unit_table, dim3(nblk(max_slots, 256)), dim3(256), 0, st, nunits, ustart,
-                     head, slot_lin, n_blocks, chunk, max_slots, units);
+                     head, slot_lin, n_blocks, chunk, max_slots, d_nslots, d_nunits, units, order);
   return hipGetLastError();
 }
 
