@@ -100,13 +100,15 @@ __global__ void k_unit_table(const int32_t* __restrict__ nunits, const int32_t* 
                              const int32_t* __restrict__ d_nslots,
                              const int32_t* __restrict__ d_nunits, int4* __restrict__ units,
                              int32_t* __restrict__ order) {
-  const int32_t s = blockIdx.x * blockDim.x + threadIdx.x;
+  // eight threads per slot, taking its units k = j, j + 8, ...
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int32_t s = (int32_t)(t >> 3);
   if (s >= max_slots) return;
   const int32_t n = nunits[s];
   if (n == 0) return;
   const int32_t b = ustart[s], h0 = head[s], h1 = head[s + 1];
   const int32_t plane = (int32_t)(slot_lin[s] / n_blocks);
-  for (int32_t k = 0; k < n; ++k) {
+  for (int32_t k = (int32_t)(t & 7); k < n; k += 8) {
     const int32_t r0 = h0 + k * chunk;
     units[b + k] = make_int4(r0, min(h1, r0 + chunk), s, plane);
     if (order) order[k + 1 < n ? b - s + k : (*d_nunits - *d_nslots) + s] = b + k;
@@ -364,13 +366,19 @@ __global__ void __launch_bounds__(SMKI_WAVE) k_splat(SplatArgs a) {
 // ---------------------------------------------------------------------------
 // Per slot: its units, the union of their non-zero pieces, and the first
 // unit's own pieces.
+// Eight threads per slot (one 8-lane group of a wavefront, active or exited
+// together) OR the masks of units j, j + 8, ...
 __global__ void k_slot_info(SplatArgs a) {
-  const int32_t s = blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int32_t s = (int32_t)(t >> 3), j = (int32_t)(t & 7);
   if (s >= a.n_slots) return;
   const int32_t u0 = a.ustart[s], nu = a.nunits[s];
   uint32_t m = 0;
-  for (int32_t w = u0; w < u0 + nu; ++w) m |= a.umask[w];
-  a.sinfo[s] = make_int4(u0, nu, (int32_t)m, nu > 0 ? (int32_t)a.umask[u0] : 0);
+  for (int32_t w = u0 + j; w < u0 + nu; w += 8) m |= a.umask[w];
+  m |= __shfl_xor(m, 1, 8);
+  m |= __shfl_xor(m, 2, 8);
+  m |= __shfl_xor(m, 4, 8);
+  if (j == 0) a.sinfo[s] = make_int4(u0, nu, (int32_t)m, nu > 0 ? (int32_t)a.umask[u0] : 0);
 }
 
 // One workgroup per active target block, one thread per voxel.  Each thread
@@ -795,8 +803,9 @@ hipError_t launch_unit_table(const int32_t* nunits, const int32_t* ustart, const
                              int32_t max_slots, const int32_t* d_nslots, const int32_t* d_nunits,
                              int4* units, int32_t* order, hipStream_t st) {
   if (max_slots <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_unit_table, dim3(nblk(max_slots, 256)), dim3(256), 0, st, nunits, ustart,
-                     head, slot_lin, n_blocks, chunk, max_slots, d_nslots, d_nunits, units, order);
+  hipLaunchKernelGGL(k_unit_table, dim3(nblk((int64_t)max_slots * 8, 256)), dim3(256), 0, st,
+                     nunits, ustart, head, slot_lin, n_blocks, chunk, max_slots, d_nslots, d_nunits,
+                     units, order);
   return hipGetLastError();
 }
 
@@ -829,7 +838,7 @@ hipError_t launch_assign(const MapDev& m, const SplatArgs& a, int32_t n_targets,
 
 hipError_t launch_slot_info(const SplatArgs& a, hipStream_t st) {
   if (a.n_slots <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_slot_info, dim3(nblk(a.n_slots, 256)), dim3(256), 0, st, a);
+  hipLaunchKernelGGL(k_slot_info, dim3(nblk((int64_t)a.n_slots * 8, 256)), dim3(256), 0, st, a);
   return hipGetLastError();
 }
 
