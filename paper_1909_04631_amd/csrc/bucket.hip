@@ -535,9 +535,10 @@ static hipError_t finish_set(PointSet& ps, KeyT* keys, uint32_t* idx, KeyT* akey
   const int64_t n = ps.n;
   if (n <= 0) return hipSuccess;
   hipError_t e;
-  // the last radix pass gathers the records (and weights) into sorted order
+  // the last radix pass gathers the records (and weights) into sorted order,
+  // if the set keeps sorted records; else they are read through the permutation
   const SortPayload pl{rec_unsorted, ps.pts, scr.wt, ps.wts};
-  const SortPayload* plp = n > 1 ? &pl : nullptr;
+  const SortPayload* plp = (n > 1 && ps.pts) ? &pl : nullptr;
   if (sizeof(KeyT) == 4)
     e = radix_sort_u32((uint32_t*)keys, idx, (uint32_t*)akeys, aidx, n, key_bits, scr.sort_tmp, st,
                        plp);
@@ -545,9 +546,10 @@ static hipError_t finish_set(PointSet& ps, KeyT* keys, uint32_t* idx, KeyT* akey
     e = radix_sort_u64((uint64_t*)keys, idx, (uint64_t*)akeys, aidx, n, key_bits, scr.sort_tmp, st,
                        plp);
   if (e != hipSuccess) return e;
-  if (!plp)
+  if (!plp && ps.pts)
     hipLaunchKernelGGL(k_permute_rec, dim3(nblk(n, 256)), dim3(256), 0, st, rec_unsorted,
                        (const float*)scr.wt, idx, n, ps.pts, ps.wts);
+  ps.perm = idx;
   const int log2B3 = 3 * g.log2B;
   // slot heads: per-tile counts (in scr.flag), their scan (scr.slot_excl), numbering
   const int64_t ntiles = ceil_div_i64(n, HT);

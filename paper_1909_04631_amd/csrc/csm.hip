@@ -47,7 +47,7 @@ __global__ void k_csm_counts(SplatArgs a, const KeyT* __restrict__ keys, int64_t
   float add = (float)(i - lo + 1);
   if (a.wts) {   // soft measurements: the run's weights, summed in row order in double
     double sw = 0.0;
-    for (int64_t r = lo; r <= i; ++r) sw += (double)a.wts[r];
+    for (int64_t r = lo; r <= i; ++r) sw += (double)a.wts[a.perm ? a.perm[r] : r];
     add = (float)sw;
   }
   a.map.calpha[(int64_t)cb * B3 + c] += add;

@@ -322,7 +322,8 @@ BucketGeom make_geom(const smki_map* m, const int32_t vlo[3], const int32_t vhi[
 // counting-model insert (S-CSM): rows already bucketed; allocate the row blocks,
 // then add each (class, voxel) run length to alpha
 // ---------------------------------------------------------------------------
-smki_status insert_csm(smki_map* m, const BucketGeom& g, const PointSet& ps, const void* keys,
+smki_status insert_csm(smki_map* m, const BucketGeom& g, const PointSet& ps,
+                       const float* wts_unsorted, const void* keys,
                        int32_t n_slots, int32_t n_t, int64_t n_ext, const int32_t eblo[3],
                        const int32_t enb[3], const int32_t* d_mark, const int32_t* d_mpos,
                        int32_t* d_ext2t, hipStream_t q) {
@@ -331,8 +332,9 @@ smki_status insert_csm(smki_map* m, const BucketGeom& g, const PointSet& ps, con
   SplatArgs sa{};
   sa.g = g;
   sa.K = m->K;
-  sa.pts = ps.pts;
-  sa.wts = ps.wts;
+  sa.pts = nullptr;   // the counting model reads no records
+  sa.wts = wts_unsorted;
+  sa.perm = ps.perm;
   sa.dense = ps.dense;
   sa.head = ps.head;
   sa.slot_lin = ps.slot_lin;
@@ -533,7 +535,6 @@ smki_status insert_impl(smki_map* m, const float* xyz, const int32_t* label, con
   const int64_t nt = nk + nf;
   const int64_t max_slots = std::min<int64_t>(nt, g.n_blocks * m->K);
   Sizer zb;
-  zb.add<float4>(nt);
   zb.add<int32_t>(g.n_blocks * m->K);
   zb.add<int32_t>(max_slots);
   zb.add<int32_t>(8);
@@ -552,16 +553,13 @@ smki_status insert_impl(smki_map* m, const float* xyz, const int32_t* label, con
   zb.add<int32_t>(n_ext);
   zb.add<int32_t>(max_slots);
   zb.add<int32_t>(max_slots);
-  if (probs) {
-    zb.add<float>(nt);   // row weights, sorted
-    zb.add<float>(nt);   // unsorted
-  }
+  if (probs) zb.add<float>(nt);   // row weights (read through the permutation)
   zb.add<int32_t>(free_sample_workgroups(nf));
   SMKI_HIP_TRY(m->a_sets.reserve(zb.total));
   Arena& Bz = m->a_sets;
   PointSet ps{};
   ps.n = nt;
-  ps.pts = Bz.take<float4>(nt);
+  ps.pts = nullptr;   // records stay unsorted: the splat reads them through the permutation
   ps.dense = Bz.take<int32_t>(g.n_blocks * m->K);
   ps.slot_lin = Bz.take<int32_t>(max_slots);
   ps.prefix = nullptr;   // the splat needs only the slot ranges
@@ -585,7 +583,7 @@ smki_status insert_impl(smki_map* m, const float* xyz, const int32_t* label, con
   int32_t* d_ext2t = Bz.take<int32_t>(n_ext);
   int32_t* d_nun = Bz.take<int32_t>(max_slots);
   int32_t* d_ust = Bz.take<int32_t>(max_slots);
-  ps.wts = probs ? Bz.take<float>(nt) : nullptr;
+  ps.wts = nullptr;
   scr.wt = probs ? Bz.take<float>(nt) : nullptr;
   int32_t* d_wgbeam = Bz.take<int32_t>(free_sample_workgroups(nf));
   // one launch clears the counts and target marks, the insert counters, and the
@@ -614,7 +612,8 @@ smki_status insert_impl(smki_map* m, const float* xyz, const int32_t* label, con
 
   // ---- phase C: splat, allocate, merge ----
   if (csm)
-    return insert_csm(m, g, ps, scr.keys, n_slots, n_t, n_ext, eblo, enb, d_mark, d_mpos, d_ext2t, q);
+    return insert_csm(m, g, ps, scr.wt, scr.keys, n_slots, n_t, n_ext, eblo, enb, d_mark, d_mpos,
+                      d_ext2t, q);
   SplatArgs sa{};
   sa.g = g;
   sa.R = sten.R;
@@ -639,8 +638,9 @@ smki_status insert_impl(smki_map* m, const float* xyz, const int32_t* label, con
     const int nz = (p / 9 != 1) + ((p / 3) % 3 != 1) + (p % 3 != 1);
     if (m->selection == SMKI_SELECT_EXACT || nz <= 1) sa.piece_mask |= 1u << p;
   }
-  sa.pts = ps.pts;
-  sa.wts = ps.wts;
+  sa.pts = scr.rec;   // unsorted records and weights, read through the permutation
+  sa.wts = scr.wt;
+  sa.perm = ps.perm;
   sa.dense = ps.dense;
   sa.head = ps.head;
   sa.slot_lin = ps.slot_lin;

@@ -21,8 +21,11 @@ struct BucketGeom {
 // One sorted point set (hits, free samples, or explicit rows).
 struct PointSet {
   int64_t n;          // rows
-  float4* pts;        // sorted records: xyz relative to the row's block corner, label bits
+  float4* pts;        // sorted records: xyz relative to the row's block corner, label bits;
+                      // nullptr: not gathered (read them through perm instead)
   float* wts;         // sorted row weights (soft measurements); nullptr: every row weighs 1
+                      // (or, with pts nullptr, not gathered)
+  const uint32_t* perm;   // after bucketing: sorted row -> row of the unsorted records
   int32_t* dense;     // [n_blocks * planes] (grid block, plane) -> slot, -1 if no row
   int32_t* slot_lin;  // [slots] (plane, grid block) linear index of each slot
   int32_t* prefix;    // [slots][B^3 + 1] first row of each voxel of the block (absolute);

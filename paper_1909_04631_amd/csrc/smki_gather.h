@@ -51,6 +51,7 @@ struct SplatArgs {
   // sorted rows
   const float4* pts;          // records: |row - its voxel centre| per axis; (cell << 3 | octant) bits
   const float* wts;           // row weights (soft measurements), nullptr: every row weighs 1
+  const uint32_t* perm;       // sorted row -> index into pts / wts (nullptr: pts is sorted)
   const int32_t* dense;       // [n_blocks * K] (block, class) -> slot
   const int32_t* head;        // [slots + 1] first row of each slot
   const int32_t* slot_lin;    // [slots] (class, block) linear index

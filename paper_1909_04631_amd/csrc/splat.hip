@@ -254,11 +254,17 @@ __global__ void __launch_bounds__(SMKI_WAVE) k_splat(SplatArgs a) {
     float4 r;
     float w;
   };
-  auto load_batch = [&](int32_t base) {   // unconditional: lanes past the end re-read row r1 - 1
+  // A batch's rows are found through the permutation (sorted row -> record):
+  // its indices are loaded one batch before its records.  Unconditional: lanes
+  // past the end re-read row r1 - 1.
+  auto load_index = [&](int32_t base) -> int32_t {
     const int32_t row = min(base + lane, r1 - 1);
+    return a.perm ? (int32_t)a.perm[row] : row;
+  };
+  auto load_batch = [&](int32_t v) {
     Batch b;
-    b.r = pts[row];
-    b.w = W ? a.wts[row] : 1.0f;
+    b.r = pts[v];
+    b.w = W ? a.wts[v] : 1.0f;
     return b;
   };
   auto process = [&](const Batch& bt, int32_t base) {
@@ -309,12 +315,15 @@ __global__ void __launch_bounds__(SMKI_WAVE) k_splat(SplatArgs a) {
       }
     }
   };
-  Batch ba = load_batch(r0);
+  Batch ba = load_batch(load_index(r0));
+  int32_t vb = load_index(r0 + SMKI_WAVE);
   for (int32_t base = r0; base < r1; base += 2 * SMKI_WAVE) {
-    const Batch bb = load_batch(base + SMKI_WAVE);
+    const Batch bb = load_batch(vb);
+    const int32_t va = load_index(base + 2 * SMKI_WAVE);
     process(ba, base);
     if (base + SMKI_WAVE >= r1) break;
-    ba = load_batch(base + 2 * SMKI_WAVE);
+    ba = load_batch(va);
+    vb = load_index(base + 3 * SMKI_WAVE);
     process(bb, base + SMKI_WAVE);
   }
   if (gkey >= 0) flush();
