@@ -1,5 +1,7 @@
 // Device-wide exclusive prefix sum (reduce, scan the tile sums, scan again).
 // Deterministic: integer sums only.
+#include <algorithm>
+
 #include "smki_internal.h"
 
 namespace {
@@ -109,6 +111,75 @@ __global__ void __launch_bounds__(SCAN_THREADS) k_tile_scan_direct(const T* in, 
   if (total && blockIdx.x == gridDim.x - 1 && threadIdx.x == SCAN_THREADS - 1) *total = run;
 }
 
+// Two independent scans in the same two launches (each of at most 512 tiles):
+// workgroups [0, ta) take the first array's tiles, the rest the second's.
+template <typename T>
+__device__ __forceinline__ void tile_sum(const T* __restrict__ in, int64_t n, T* __restrict__ sums,
+                                         int64_t tile) {
+  const int64_t base = tile * SCAN_TILE + (int64_t)threadIdx.x * SCAN_ITEMS;
+  T s = 0;
+#pragma unroll
+  for (int i = 0; i < SCAN_ITEMS; ++i)
+    if (base + i < n) s += in[base + i];
+  T tot;
+  block_excl_scan(s, &tot);
+  if (threadIdx.x == 0) sums[tile] = tot;
+}
+
+template <typename T>
+__device__ __forceinline__ void tile_scan_direct(const T* in, T* out, int64_t n,
+                                                 const T* __restrict__ sums, T* total,
+                                                 int64_t tile, int64_t ntiles) {
+  __shared__ T part[SCAN_THREADS / SMKI_WAVE];
+  T pre = 0;
+  for (int64_t i = threadIdx.x; i < tile; i += SCAN_THREADS) pre += sums[i];
+#pragma unroll
+  for (int o = SMKI_WAVE / 2; o > 0; o >>= 1) pre += __shfl_xor(pre, o, SMKI_WAVE);
+  if ((threadIdx.x & (SMKI_WAVE - 1)) == 0) part[threadIdx.x / SMKI_WAVE] = pre;
+  __syncthreads();
+  T off = 0;
+#pragma unroll
+  for (int i = 0; i < SCAN_THREADS / SMKI_WAVE; ++i) off += part[i];
+  const int64_t base = tile * SCAN_TILE + (int64_t)threadIdx.x * SCAN_ITEMS;
+  T v[SCAN_ITEMS];
+  T s = 0;
+#pragma unroll
+  for (int i = 0; i < SCAN_ITEMS; ++i) {
+    v[i] = (base + i < n) ? in[base + i] : (T)0;
+    s += v[i];
+  }
+  T tot;
+  T run = block_excl_scan(s, &tot) + off;
+#pragma unroll
+  for (int i = 0; i < SCAN_ITEMS; ++i) {
+    if (base + i < n) out[base + i] = run;
+    run += v[i];
+  }
+  if (total && tile == ntiles - 1 && threadIdx.x == SCAN_THREADS - 1) *total = run;
+}
+
+template <typename TA, typename TB>
+__global__ void __launch_bounds__(SCAN_THREADS) k_tile_sums_pair(const TA* __restrict__ ina,
+                                                                 int64_t na, TA* __restrict__ sa,
+                                                                 int64_t ta,
+                                                                 const TB* __restrict__ inb,
+                                                                 int64_t nb, TB* __restrict__ sb) {
+  if ((int64_t)blockIdx.x < ta)
+    tile_sum<TA>(ina, na, sa, blockIdx.x);
+  else
+    tile_sum<TB>(inb, nb, sb, (int64_t)blockIdx.x - ta);
+}
+
+template <typename TA, typename TB>
+__global__ void __launch_bounds__(SCAN_THREADS) k_tile_scan_direct_pair(
+    const TA* ina, TA* outa, int64_t na, const TA* __restrict__ sa, TA* tota, int64_t ta,
+    const TB* inb, TB* outb, int64_t nb, const TB* __restrict__ sb, TB* totb, int64_t tb) {
+  if ((int64_t)blockIdx.x < ta)
+    tile_scan_direct<TA>(ina, outa, na, sa, tota, blockIdx.x, ta);
+  else
+    tile_scan_direct<TB>(inb, outb, nb, sb, totb, (int64_t)blockIdx.x - ta, tb);
+}
+
 template <typename T>
 __global__ void k_zero_total(T* total) { *total = 0; }
 
@@ -151,9 +222,44 @@ hipError_t scan_impl(const T* in, T* out, int64_t n, T* total, T* tmp, hipStream
   return hipGetLastError();
 }
 
+constexpr int64_t kPairTiles = 512;   // per array, for the two-launch pair scan
+
+template <typename TA, typename TB>
+hipError_t scan_pair_impl(const TA* ina, TA* outa, int64_t na, TA* tota, const TB* inb, TB* outb,
+                          int64_t nb, TB* totb, void* tmp, hipStream_t st) {
+  const int64_t ta = ceil_div_i64(na, SCAN_TILE), tb = ceil_div_i64(nb, SCAN_TILE);
+  if (na <= 0 || nb <= 0 || ta > kPairTiles || tb > kPairTiles) {
+    hipError_t e = scan_impl<TA>(ina, outa, na, tota, (TA*)tmp, st);
+    if (e != hipSuccess) return e;
+    return scan_impl<TB>(inb, outb, nb, totb, (TB*)tmp, st);
+  }
+  TA* sa = (TA*)tmp;
+  TB* sb = (TB*)((char*)tmp + kPairTiles * sizeof(int64_t));
+  hipLaunchKernelGGL((k_tile_sums_pair<TA, TB>), dim3((unsigned)(ta + tb)), dim3(SCAN_THREADS), 0,
+                     st, ina, na, sa, ta, inb, nb, sb);
+  hipLaunchKernelGGL((k_tile_scan_direct_pair<TA, TB>), dim3((unsigned)(ta + tb)),
+                     dim3(SCAN_THREADS), 0, st, ina, outa, na, (const TA*)sa, tota, ta, inb, outb,
+                     nb, (const TB*)sb, totb, tb);
+  return hipGetLastError();
+}
+
 }  // namespace
 
-size_t scan_tmp_bytes(int64_t n) { return tmp_elems<int64_t>(n) * sizeof(int64_t) + 256; }
+size_t scan_tmp_bytes(int64_t n) {
+  return std::max<size_t>(tmp_elems<int64_t>(n), 2 * kPairTiles) * sizeof(int64_t) + 256;
+}
+
+hipError_t scan_excl_pair_i64_i32(const int64_t* ina, int64_t* outa, int64_t na, int64_t* tota,
+                                  const int32_t* inb, int32_t* outb, int64_t nb, int32_t* totb,
+                                  void* tmp, hipStream_t st) {
+  return scan_pair_impl<int64_t, int32_t>(ina, outa, na, tota, inb, outb, nb, totb, tmp, st);
+}
+
+hipError_t scan_excl_pair_i32(const int32_t* ina, int32_t* outa, int64_t na, int32_t* tota,
+                              const int32_t* inb, int32_t* outb, int64_t nb, int32_t* totb,
+                              void* tmp, hipStream_t st) {
+  return scan_pair_impl<int32_t, int32_t>(ina, outa, na, tota, inb, outb, nb, totb, tmp, st);
+}
 
 hipError_t scan_excl_i64(const int64_t* in, int64_t* out, int64_t n, int64_t* total, void* tmp,
                          hipStream_t st) {

@@ -380,9 +380,9 @@ smki_status insert_csm(smki_map* m, const BucketGeom& g, const PointSet& ps,
   SMKI_HIP_TRY(hipEventRecord(m->ev[0], q));
   SMKI_HIP_TRY(hipEventRecord(m->ev[1], q));
   SMKI_HIP_TRY(launch_map_lookup(m->dev, sa, n_t, d_tslot, d_isnew, q));
-  SMKI_HIP_TRY(scan_excl_i32(d_isnew, d_rank, n_t, d_cnt, d_ctmp, q));
   SMKI_HIP_TRY(launch_need(m->dev, n_t, d_contrib, d_isnew, d_tslot, d_need, q));
-  SMKI_HIP_TRY(scan_excl_i32(d_need, d_cpos, ntk, d_cnt + 1, d_ctmp, q));
+  SMKI_HIP_TRY(scan_excl_pair_i32(d_isnew, d_rank, n_t, d_cnt, d_need, d_cpos, ntk, d_cnt + 1,
+                                  d_ctmp, q));
   int32_t cnt[2];
   SMKI_HIP_TRY(sync_read(m, d_cnt, sizeof(cnt), cnt));
   const int64_t n_new = cnt[0], n_cnew = cnt[1];
@@ -486,8 +486,8 @@ smki_status insert_impl(smki_map* m, const float* xyz, const int32_t* label, con
   SMKI_HIP_TRY(hipMemcpyAsync(d_hdr, hh, hdr_bytes, hipMemcpyHostToDevice, q));
   SMKI_HIP_TRY(launch_count(xyz, label, probs, n, d_soff, d_org, S, m->res, step, m->K, d_nfree,
                             d_kept, d_bbox, d_err0, q));
-  SMKI_HIP_TRY(scan_excl_i64(d_nfree, d_off, n, d_sc, d_stmp, q));
-  SMKI_HIP_TRY(scan_excl_i32(d_kept, d_kpos, n, (int32_t*)(d_sc + 1), d_stmp, q));
+  SMKI_HIP_TRY(scan_excl_pair_i64_i32(d_nfree, d_off, n, d_sc, d_kept, d_kpos, n,
+                                      (int32_t*)(d_sc + 1), d_stmp, q));
   // sync 1: counts, error word and box in one copy
   SMKI_HIP_TRY(hipMemcpyAsync(hh, d_hdr, kHdrTail, hipMemcpyDeviceToHost, q));
   SMKI_HIP_TRY(stream_wait(q));
@@ -595,9 +595,9 @@ smki_status insert_impl(smki_map* m, const float* xyz, const int32_t* label, con
                            d_soff, d_org, S, step, m->free_class, g, ps, scr, m->d_err, q));
   SMKI_HIP_TRY(launch_mark_targets(ps.slot_lin, ps.d_nslots, (int32_t)max_slots, g, eblo, enb, DB,
                                    d_mark, q));
-  SMKI_HIP_TRY(scan_excl_i32(d_mark, d_mpos, n_ext, d_ntgt, scr.scan_tmp, q));
   SMKI_HIP_TRY(launch_slot_units(ps.head, ps.d_nslots, (int32_t)max_slots, m->chunk, d_nun, q));
-  SMKI_HIP_TRY(scan_excl_i32(d_nun, d_ust, max_slots, d_nunits, scr.scan_tmp, q));
+  SMKI_HIP_TRY(scan_excl_pair_i32(d_mark, d_mpos, n_ext, d_ntgt, d_nun, d_ust, max_slots, d_nunits,
+                                  scr.scan_tmp, q));
   // sync 2: slots, targets, work units
   int32_t si[3];
   SMKI_HIP_TRY(sync_read(m, d_si, sizeof(si), si));
@@ -711,9 +711,9 @@ smki_status insert_impl(smki_map* m, const float* xyz, const int32_t* label, con
   SMKI_HIP_TRY(launch_slot_info(sa, q));
   SMKI_HIP_TRY(launch_contrib(sa, false, d_contrib, q));
   SMKI_HIP_TRY(launch_map_lookup(m->dev, sa, n_t, d_tslot, d_isnew, q));
-  SMKI_HIP_TRY(scan_excl_i32(d_isnew, d_rank, n_t, d_cnt, d_ctmp, q));
   SMKI_HIP_TRY(launch_need(m->dev, n_t, d_contrib, d_isnew, d_tslot, d_need, q));
-  SMKI_HIP_TRY(scan_excl_i32(d_need, d_cpos, ntk, d_cnt + 1, d_ctmp, q));
+  SMKI_HIP_TRY(scan_excl_pair_i32(d_isnew, d_rank, n_t, d_cnt, d_need, d_cpos, ntk, d_cnt + 1,
+                                  d_ctmp, q));
   // sync 3: new blocks and class blocks
   int32_t cnt[2];
   SMKI_HIP_TRY(sync_read(m, d_cnt, sizeof(cnt), cnt));

@@ -37,6 +37,14 @@ hipError_t scan_excl_i64(const int64_t* in, int64_t* out, int64_t n, int64_t* to
                          hipStream_t st);
 hipError_t scan_excl_i32(const int32_t* in, int32_t* out, int64_t n, int32_t* total, void* tmp,
                          hipStream_t st);
+// two independent exclusive scans (the same contract each) sharing two launches
+// when each array has at most 512 tiles of 2048 elements; tmp as for the larger
+hipError_t scan_excl_pair_i64_i32(const int64_t* ina, int64_t* outa, int64_t na, int64_t* tota,
+                                  const int32_t* inb, int32_t* outb, int64_t nb, int32_t* totb,
+                                  void* tmp, hipStream_t st);
+hipError_t scan_excl_pair_i32(const int32_t* ina, int32_t* outa, int64_t na, int32_t* tota,
+                              const int32_t* inb, int32_t* outb, int64_t nb, int32_t* totb,
+                              void* tmp, hipStream_t st);
 
 // stable LSD radix sort of (key, value) pairs on the low `bits` bits of the
 // keys.  keys/vals are sorted in place; alt_* are scratch of the same size.
