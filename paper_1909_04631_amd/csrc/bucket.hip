@@ -215,7 +215,7 @@ __global__ void k_hit_keys(const float* __restrict__ xyz, const int32_t* __restr
                            const int32_t* __restrict__ kept, const int32_t* __restrict__ kpos,
                            const int64_t* __restrict__ off, int64_t nf,
                            int32_t* __restrict__ wgbeam, BucketGeom g, KeyT* __restrict__ keys,
-                           uint32_t* __restrict__ idx, float4* __restrict__ rec,
+                           float4* __restrict__ rec,
                            float* __restrict__ wt, uint32_t* __restrict__ err) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
@@ -235,7 +235,7 @@ __global__ void k_hit_keys(const float* __restrict__ xyz, const int32_t* __restr
   if (!in_grid(g, b)) {
     atomicOr(err, DEVERR_RANGE);
     for (int32_t r = 0; r < rows; ++r, ++w) {
-      keys[w] = (KeyT)0; idx[w] = (uint32_t)w; rec[w] = make_float4(0, 0, 0, 0);
+      keys[w] = (KeyT)0; rec[w] = make_float4(0, 0, 0, 0);
       if (wt) wt[w] = 0.0f;
     }
     return;
@@ -243,7 +243,6 @@ __global__ void k_hit_keys(const float* __restrict__ xyz, const int32_t* __restr
   const float4 r4 = make_map_record(g, px, py, pz, v, l);
   if (!probs) {
     keys[w] = make_key<KeyT>(g, label[i], b, l);
-    idx[w] = (uint32_t)w;
     rec[w] = r4;
     return;
   }
@@ -251,7 +250,6 @@ __global__ void k_hit_keys(const float* __restrict__ xyz, const int32_t* __restr
     const float p = probs[i * K + k];
     if (!(p > 0.0f)) continue;
     keys[w] = make_key<KeyT>(g, k, b, l);
-    idx[w] = (uint32_t)w;
     rec[w] = r4;
     wt[w] = p;
     ++w;
@@ -265,8 +263,7 @@ __global__ void k_free_keys(const float* __restrict__ xyz, int64_t n,
                             const int64_t* __restrict__ scan_off,
                             const float* __restrict__ origins, int32_t S, float step,
                             int32_t free_class, BucketGeom g, int64_t out_base,
-                            KeyT* __restrict__ keys, uint32_t* __restrict__ idx,
-                            float4* __restrict__ rec, float* __restrict__ wrow,
+                            KeyT* __restrict__ keys, float4* __restrict__ rec, float* __restrict__ wrow,
                             const int32_t* __restrict__ wgbeam, uint32_t* __restrict__ err) {
   // The beams of this workgroup's samples lie between the beam of its first
   // sample and the beam of the next workgroup's first sample (wgbeam, written
@@ -294,19 +291,18 @@ __global__ void k_free_keys(const float* __restrict__ xyz, int64_t n,
   if (!voxel_index(qx, g.res, &v[0]) || !voxel_index(qy, g.res, &v[1]) ||
       !voxel_index(qz, g.res, &v[2])) {
     atomicOr(err, DEVERR_RANGE);
-    keys[w] = (KeyT)0; idx[w] = (uint32_t)w; rec[w] = make_float4(0, 0, 0, 0);
+    keys[w] = (KeyT)0; rec[w] = make_float4(0, 0, 0, 0);
     if (wrow) wrow[w] = 0.0f;
     return;
   }
   block_of(g, v, b, l);
   if (!in_grid(g, b)) {
     atomicOr(err, DEVERR_RANGE);
-    keys[w] = (KeyT)0; idx[w] = (uint32_t)w; rec[w] = make_float4(0, 0, 0, 0);
+    keys[w] = (KeyT)0; rec[w] = make_float4(0, 0, 0, 0);
     if (wrow) wrow[w] = 0.0f;
     return;
   }
   keys[w] = make_key<KeyT>(g, free_class, b, l);
-  idx[w] = (uint32_t)w;
   rec[w] = make_map_record(g, qx, qy, qz, v, l);
   if (wrow) wrow[w] = 1.0f;
 }
@@ -529,22 +525,28 @@ hipError_t launch_fill_i32(int32_t* p, int64_t n, int32_t v, hipStream_t st) {
 
 // Keys, sort, records and block tables of one point set.
 template <typename KeyT>
+// idx_iota: idx was not written (row i's value is i): the first radix pass
+// takes the indices itself.
 static hipError_t finish_set(PointSet& ps, KeyT* keys, uint32_t* idx, KeyT* akeys, uint32_t* aidx,
                              float4* rec_unsorted, const BucketGeom& g, int key_bits,
-                             BucketScratch& scr, hipStream_t st) {
+                             BucketScratch& scr, hipStream_t st, bool idx_iota = false) {
   const int64_t n = ps.n;
   if (n <= 0) return hipSuccess;
   hipError_t e;
+  if (idx_iota && n == 1) {   // no radix pass: the single index by hand
+    e = hipMemsetAsync(idx, 0, sizeof(uint32_t), st);
+    if (e != hipSuccess) return e;
+  }
   // the last radix pass gathers the records (and weights) into sorted order,
   // if the set keeps sorted records; else they are read through the permutation
   const SortPayload pl{rec_unsorted, ps.pts, scr.wt, ps.wts};
   const SortPayload* plp = (n > 1 && ps.pts) ? &pl : nullptr;
   if (sizeof(KeyT) == 4)
     e = radix_sort_u32((uint32_t*)keys, idx, (uint32_t*)akeys, aidx, n, key_bits, scr.sort_tmp, st,
-                       plp);
+                       plp, idx_iota);
   else
     e = radix_sort_u64((uint64_t*)keys, idx, (uint64_t*)akeys, aidx, n, key_bits, scr.sort_tmp, st,
-                       plp);
+                       plp, idx_iota);
   if (e != hipSuccess) return e;
   if (!plp && ps.pts)
     hipLaunchKernelGGL(k_permute_rec, dim3(nblk(n, 256)), dim3(256), 0, st, rec_unsorted,
@@ -586,14 +588,13 @@ static hipError_t bucket_scan_t(const float* xyz, const int32_t* label, const fl
                                 BucketScratch& scr, uint32_t* err, hipStream_t st) {
   if (nk > 0)
     hipLaunchKernelGGL(k_hit_keys<KeyT>, dim3(nblk(n, 256)), dim3(256), 0, st, xyz, label, probs,
-                       K, n, kept, kpos, off, nf, wgbeam, g, (KeyT*)scr.keys, scr.idx, scr.rec,
-                       scr.wt, err);
+                       K, n, kept, kpos, off, nf, wgbeam, g, (KeyT*)scr.keys, scr.rec, scr.wt, err);
   if (nf > 0)
     hipLaunchKernelGGL(k_free_keys<KeyT>, dim3(nblk(nf, FREE_WG)), dim3(FREE_WG), 0, st, xyz, n,
                        off, nf, scan_off, origins, S, step, free_class, g, nk, (KeyT*)scr.keys,
-                       scr.idx, scr.rec, scr.wt, (const int32_t*)wgbeam, err);
+                       scr.rec, scr.wt, (const int32_t*)wgbeam, err);
   return finish_set<KeyT>(ps, (KeyT*)scr.keys, scr.idx, (KeyT*)scr.akeys, scr.aidx, scr.rec, g,
-                          g.key_bits, scr, st);
+                          g.key_bits, scr, st, true);
 }
 
 // All training rows of an insert in one sorted set: kept hits at [0, nk), free

@@ -175,7 +175,7 @@ __global__ void __launch_bounds__(RS_THREADS) k_scatter(const K* __restrict__ ke
                                                         int shift, int dbits, int64_t ntiles,
                                                         const uint32_t* __restrict__ offs,
                                                         const uint32_t* __restrict__ total,
-                                                        SortPayload pl) {
+                                                        SortPayload pl, int vals_iota) {
   constexpr int DPT = NB / RS_THREADS;   // digits per thread: tid * DPT + j
   __shared__ uint32_t gbase[NB];    // first global position of the tile's digit-d elements
   __shared__ uint32_t lstart[NB];   // first index of digit d inside the tile
@@ -205,7 +205,7 @@ __global__ void __launch_bounds__(RS_THREADS) k_scatter(const K* __restrict__ ke
   for (int r = 0; r < RS_ROUNDS; ++r) {
     const int64_t i = elem_index(tile_base, w, r, lane);
     key[r] = i < n ? keys[i] : (K)0;
-    val[r] = i < n ? vals[i] : 0u;
+    val[r] = vals_iota ? (uint32_t)i : (i < n ? vals[i] : 0u);
   }
   __syncthreads();
   // 1. rank inside the wavefront's span
@@ -302,19 +302,19 @@ __global__ void __launch_bounds__(RS_THREADS) k_scatter(const K* __restrict__ ke
 template <typename K, int NB>
 void launch_pass(const K* sk, const uint32_t* sv, K* dk, uint32_t* dv, int64_t n, int shift,
                  int dbits, int64_t ntiles, uint32_t* hist, uint32_t* total, const SortPayload& pl,
-                 hipStream_t st) {
+                 int vals_iota, hipStream_t st) {
   hipLaunchKernelGGL((k_hist<K, NB>), dim3((unsigned)ntiles), dim3(RS_THREADS), 0, st, sk, n,
                      shift, dbits, ntiles, hist);
   hipLaunchKernelGGL(k_digit_scan, dim3(1u << dbits), dim3(RS_THREADS), 0, st, hist, ntiles,
                      total);
   hipLaunchKernelGGL((k_scatter<K, NB>), dim3((unsigned)ntiles), dim3(RS_THREADS), 0, st, sk, sv,
                      dk, dv, n, shift, dbits, ntiles, (const uint32_t*)hist,
-                     (const uint32_t*)total, pl);
+                     (const uint32_t*)total, pl, vals_iota);
 }
 
 template <typename K>
 hipError_t sort_impl(K* keys, uint32_t* vals, K* akeys, uint32_t* avals, int64_t n, int bits,
-                     void* tmp, hipStream_t st, const SortPayload* pl) {
+                     void* tmp, hipStream_t st, const SortPayload* pl, bool vals_iota) {
   if (n <= 1 || bits <= 0) return hipSuccess;
   const int64_t ntiles = ceil_div_i64(n, RS_TILE);
   uint32_t* hist = (uint32_t*)tmp;
@@ -331,10 +331,13 @@ hipError_t sort_impl(K* keys, uint32_t* vals, K* akeys, uint32_t* avals, int64_t
     const int shift = p * dbits;
     const SortPayload none{};
     const SortPayload& pp = (p == passes - 1 && pl) ? *pl : none;
+    const int iota = (p == 0 && vals_iota) ? 1 : 0;
     if (dbits <= 8)
-      launch_pass<K, 256>(src_k, src_v, dst_k, dst_v, n, shift, dbits, ntiles, hist, total, pp, st);
+      launch_pass<K, 256>(src_k, src_v, dst_k, dst_v, n, shift, dbits, ntiles, hist, total, pp,
+                          iota, st);
     else
-      launch_pass<K, 512>(src_k, src_v, dst_k, dst_v, n, shift, dbits, ntiles, hist, total, pp, st);
+      launch_pass<K, 512>(src_k, src_v, dst_k, dst_v, n, shift, dbits, ntiles, hist, total, pp,
+                          iota, st);
     K* tk = src_k; src_k = dst_k; dst_k = tk;
     uint32_t* tv = src_v; src_v = dst_v; dst_v = tv;
   }
@@ -355,11 +358,13 @@ size_t radix_tmp_bytes(int64_t n) {
 }
 
 hipError_t radix_sort_u32(uint32_t* keys, uint32_t* vals, uint32_t* ak, uint32_t* av, int64_t n,
-                          int bits, void* tmp, hipStream_t st, const SortPayload* pl) {
-  return sort_impl<uint32_t>(keys, vals, ak, av, n, bits, tmp, st, pl);
+                          int bits, void* tmp, hipStream_t st, const SortPayload* pl,
+                          bool vals_iota) {
+  return sort_impl<uint32_t>(keys, vals, ak, av, n, bits, tmp, st, pl, vals_iota);
 }
 
 hipError_t radix_sort_u64(uint64_t* keys, uint32_t* vals, uint64_t* ak, uint32_t* av, int64_t n,
-                          int bits, void* tmp, hipStream_t st, const SortPayload* pl) {
-  return sort_impl<uint64_t>(keys, vals, ak, av, n, bits, tmp, st, pl);
+                          int bits, void* tmp, hipStream_t st, const SortPayload* pl,
+                          bool vals_iota) {
+  return sort_impl<uint64_t>(keys, vals, ak, av, n, bits, tmp, st, pl, vals_iota);
 }

@@ -57,12 +57,13 @@ struct SortPayload {
   float* w_out;
 };
 size_t radix_tmp_bytes(int64_t n);
+// vals_iota: vals holds nothing on entry; element i's value is i.
 hipError_t radix_sort_u32(uint32_t* keys, uint32_t* vals, uint32_t* alt_keys, uint32_t* alt_vals,
                           int64_t n, int bits, void* tmp, hipStream_t st,
-                          const SortPayload* payload = nullptr);
+                          const SortPayload* payload = nullptr, bool vals_iota = false);
 hipError_t radix_sort_u64(uint64_t* keys, uint32_t* vals, uint64_t* alt_keys, uint32_t* alt_vals,
                           int64_t n, int bits, void* tmp, hipStream_t st,
-                          const SortPayload* payload = nullptr);
+                          const SortPayload* payload = nullptr, bool vals_iota = false);
 
 // ---------------------------------------------------------------------------
 // small device helpers

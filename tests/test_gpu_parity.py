@@ -224,6 +224,21 @@ def test_batched_many_small_scans_with_empty_ones():
     compare_map(gb, om, p.K)
 
 
+def test_single_row_insert():
+    # one hit closer to the sensor than one free step: a single training row
+    # (the bucketing then runs no radix pass)
+    sc = scenes.make_config(0)
+    p = sc.params
+    xyz = np.array([[0.05, 0.02, 0.01]], np.float32)
+    lab = np.array([1], np.int32)
+    scan = scenes.Scan(xyz, lab, np.zeros(3, np.float32))
+    _print_case("single row")
+    om = oracle_map_of(sc, scans=[scan])
+    gm = gpu_map_of(sc, scans=[scan])
+    assert gm.stats()["n_free"] == 0
+    compare_map(gm, om, p.K)
+
+
 def test_invalid_input_leaves_map_unchanged():
     import torch
     from paper_1909_04631_amd import SmkiError
