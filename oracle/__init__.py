@@ -89,6 +89,7 @@ def lib():
         L.oracle_loss_classes.argtypes = [f64p, i32p, C.c_int64, f64p, i32p, C.c_int64, C.c_int32,
                                           f64p, f64p, C.c_double, f64p, f64p, f64p, f64p, f64p,
                                           f64p]
+        L.oracle_map_last_insert.argtypes = [C.c_void_p, i64p]
         L.oracle_map_size.restype = C.c_int64
         L.oracle_map_size.argtypes = [C.c_void_p]
         L.oracle_map_export.argtypes = [C.c_void_p, i32p, f64p, i64p, i64p]
@@ -99,6 +100,7 @@ def lib():
                                   C.c_double, C.c_double, C.c_double, f64p, f64p, f64p, f64p,
                                   f64p, f64p]
         L.oracle_num_threads.restype = C.c_int
+        L.oracle_set_num_threads.argtypes = [C.c_int]
         _lib = L
     return _lib
 
@@ -119,6 +121,11 @@ def _i32(a):
 
 def num_threads() -> int:
     return int(lib().oracle_num_threads())
+
+
+def set_num_threads(n: int) -> None:
+    """Threads of the map insert (its results do not depend on the count)."""
+    _chk(lib().oracle_set_num_threads(int(n)), "set_num_threads")
 
 
 def kernel_f(r) -> np.ndarray:
@@ -326,6 +333,14 @@ class OracleMap:
 
     def __len__(self):
         return int(lib().oracle_map_size(self._h))
+
+    def last_insert(self):
+        """Counters of the last insert: V (voxels with at least one row within
+        l; S-CSM: voxels holding a row), P (in-support pairs; S-CSM: rows), and
+        the voxels and pairs in the rounding band |d^2/l^2 - 1| <= 1e-5."""
+        out = np.zeros(4, dtype=np.int64)
+        _chk(lib().oracle_map_last_insert(self._h, _p(out, C.c_int64)), "map_last_insert")
+        return {"V": int(out[0]), "P": int(out[1]), "V_band": int(out[2]), "P_band": int(out[3])}
 
     def export(self):
         """(ijk int32 [V,3], alpha [V,K], n_in [V], n_band [V]) sorted by voxel key."""

@@ -417,6 +417,9 @@ typedef struct oracle_map {
                         implementation notes), 0: every row (exact Eq. 7) */
     double *lk, *s0k; /* [K] length-scale and scale of each class's kernel (reading R23);
                          all equal to l and sigma0 unless set per class */
+    int64_t *stamp;   /* per stored voxel: the last S-CSM insert that touched it */
+    int64_t stamp_now;
+    int64_t last[4];  /* counters of the last insert (oracle_map_last_insert) */
 } oracle_map;
 
 /* floor(a / b) for b > 0 */
@@ -434,6 +437,8 @@ static uint64_t mix64(uint64_t x)
     x ^= x >> 33;
     return x;
 }
+
+void oracle_map_destroy(oracle_map *m);
 
 oracle_map *oracle_map_create(int32_t K, float res, int32_t block_size, float l, float sigma0,
                               float alpha0, int32_t scsm, int32_t face_blocks)
@@ -454,9 +459,13 @@ oracle_map *oracle_map_create(int32_t K, float res, int32_t block_size, float l,
     m->alpha = (double *)malloc(sizeof(double) * m->rows * K);
     m->nv = (int64_t *)malloc(sizeof(int64_t) * m->rows);
     m->nband = (int64_t *)malloc(sizeof(int64_t) * m->rows);
+    m->stamp = (int64_t *)malloc(sizeof(int64_t) * m->rows);
     m->lk = (double *)malloc(sizeof(double) * K);
     m->s0k = (double *)malloc(sizeof(double) * K);
-    if (!m->tab || !m->keys || !m->alpha || !m->nv || !m->nband || !m->lk || !m->s0k) return NULL;
+    if (!m->tab || !m->keys || !m->alpha || !m->nv || !m->nband || !m->stamp || !m->lk || !m->s0k) {
+        oracle_map_destroy(m);
+        return NULL;
+    }
     for (int32_t k = 0; k < K; ++k) { m->lk[k] = m->l; m->s0k[k] = m->sigma0; }
     return m;
 }
@@ -478,7 +487,7 @@ void oracle_map_destroy(oracle_map *m)
 {
     if (!m) return;
     free(m->tab); free(m->keys); free(m->alpha); free(m->nv); free(m->nband);
-    free(m->lk); free(m->s0k);
+    free(m->stamp); free(m->lk); free(m->s0k);
     free(m);
 }
 
@@ -523,6 +532,9 @@ static int64_t map_row(oracle_map *m, uint64_t key)
         int64_t *b2 = (int64_t *)realloc(m->nband, sizeof(int64_t) * nr);
         if (!b2) return -1;
         m->nband = b2;
+        int64_t *s2 = (int64_t *)realloc(m->stamp, sizeof(int64_t) * nr);
+        if (!s2) return -1;
+        m->stamp = s2;
         m->rows = nr;
     }
     int64_t r = m->n++;
@@ -532,6 +544,7 @@ static int64_t map_row(oracle_map *m, uint64_t key)
     for (int k = 0; k < m->K; ++k) m->alpha[r * m->K + k] = m->alpha0;
     m->nv[r] = 0;
     m->nband[r] = 0;
+    m->stamp[r] = 0;
     return r;
 }
 
@@ -540,46 +553,137 @@ static int64_t map_row(oracle_map *m, uint64_t key)
  * row when w is NULL): alpha^y += w sigma0 f(d / l) at every voxel centre
  * within l (Eq. (7)), or alpha^y += w in the row's own cell (Eq. (2)).  A
  * one-hot row has w = 1; a soft row contributes its class probability
- * (reading R22). */
-static int insert_rows(oracle_map *m, const float *xyz, const int32_t *label, const double *w,
-                       int64_t n)
+ * (reading R22).
+ *
+ * Every row is validated before anything is written, so a failed insert leaves
+ * the map unchanged.  The S-BKI sum is split over square tiles of voxel columns
+ * (x, y) so that several threads can work at once; each tile adds, for each of
+ * its voxels, the terms of the rows in row order starting from the voxel's
+ * value before the insert, which is exactly the serial order: the result does
+ * not depend on the number of threads. */
+
+/* Box of voxel indices around the ball of radius L at x (widened by one voxel). */
+static void row_box(const double x[3], double L, double res, int64_t lo[3], int64_t hi[3])
 {
-    if (!m || n < 0) return OR_E_ARG;
-    for (int64_t t = 0; t < n; ++t) {
-        if (label[t] < 0 || label[t] >= m->K) return OR_E_INPUT;
-        if (!finite3(xyz + 3 * t)) return OR_E_INPUT;
-        if (w && !(isfinite(w[t]) && w[t] >= 0.0)) return OR_E_INPUT;
+    for (int a = 0; a < 3; ++a) {
+        lo[a] = (int64_t)floor((x[a] - L) / res - 0.5) - 1;
+        hi[a] = (int64_t)ceil((x[a] + L) / res - 0.5) + 1;
     }
+}
+
+/* The voxels one tile touches during one insert: packed key -> entry, each
+ * entry the running concentrations, the map's counts plus this insert's, and
+ * this insert's in-support and band counts. */
+typedef struct {
+    uint64_t *hk;      /* hash slots: key, UINT64_MAX empty */
+    int64_t *hv;       /* hash slots: entry */
+    int64_t hcap, n, cap;
+    uint64_t *key;     /* [cap] */
+    double *alpha;     /* [cap * K] */
+    int64_t *nv, *nb;  /* cumulative counts */
+    int64_t *snv, *snb;/* this insert's counts */
+} or_tile;
+
+static void tile_free(or_tile *t)
+{
+    free(t->hk); free(t->hv); free(t->key); free(t->alpha);
+    free(t->nv); free(t->nb); free(t->snv); free(t->snb);
+    memset(t, 0, sizeof(*t));
+}
+
+static int tile_grow_entries(or_tile *t, int32_t K)
+{
+    int64_t nc = t->cap ? 2 * t->cap : 256;
+    uint64_t *k2 = (uint64_t *)realloc(t->key, sizeof(uint64_t) * nc);
+    if (!k2) return OR_E_OOM;
+    t->key = k2;
+    double *a2 = (double *)realloc(t->alpha, sizeof(double) * nc * K);
+    if (!a2) return OR_E_OOM;
+    t->alpha = a2;
+    int64_t **arr[4] = {&t->nv, &t->nb, &t->snv, &t->snb};
+    for (int i = 0; i < 4; ++i) {
+        int64_t *q = (int64_t *)realloc(*arr[i], sizeof(int64_t) * nc);
+        if (!q) return OR_E_OOM;
+        *arr[i] = q;
+    }
+    t->cap = nc;
+    return OR_OK;
+}
+
+static int tile_grow_hash(or_tile *t)
+{
+    int64_t nc = t->hcap ? 2 * t->hcap : 512;
+    uint64_t *hk = (uint64_t *)malloc(sizeof(uint64_t) * nc);
+    int64_t *hv = (int64_t *)malloc(sizeof(int64_t) * nc);
+    if (!hk || !hv) { free(hk); free(hv); return OR_E_OOM; }
+    for (int64_t i = 0; i < nc; ++i) hk[i] = UINT64_MAX;
+    for (int64_t e = 0; e < t->n; ++e) {
+        uint64_t h = mix64(t->key[e]) & (uint64_t)(nc - 1);
+        while (hk[h] != UINT64_MAX) h = (h + 1) & (uint64_t)(nc - 1);
+        hk[h] = t->key[e];
+        hv[h] = e;
+    }
+    free(t->hk); free(t->hv);
+    t->hk = hk; t->hv = hv; t->hcap = nc;
+    return OR_OK;
+}
+
+/* Row of the stored map for a key, or -1 (read only). */
+static int64_t map_find(const oracle_map *m, uint64_t key)
+{
+    uint64_t h = mix64(key) & (uint64_t)(m->cap - 1);
+    while (m->tab[h].key != UINT64_MAX) {
+        if (m->tab[h].key == key) return m->tab[h].idx;
+        h = (h + 1) & (uint64_t)(m->cap - 1);
+    }
+    return -1;
+}
+
+/* Entry of a voxel in a tile, created from the map's current value (alpha0 and
+ * zero counts for a voxel the map does not store); -1 on allocation failure. */
+static int64_t tile_entry(or_tile *t, const oracle_map *m, uint64_t key)
+{
+    if (2 * (t->n + 1) > t->hcap && tile_grow_hash(t)) return -1;
+    uint64_t h = mix64(key) & (uint64_t)(t->hcap - 1);
+    while (t->hk[h] != UINT64_MAX) {
+        if (t->hk[h] == key) return t->hv[h];
+        h = (h + 1) & (uint64_t)(t->hcap - 1);
+    }
+    if (t->n == t->cap && tile_grow_entries(t, m->K)) return -1;
+    const int64_t e = t->n++;
+    t->hk[h] = key;
+    t->hv[h] = e;
+    t->key[e] = key;
+    const int64_t r = map_find(m, key);
+    for (int k = 0; k < m->K; ++k) t->alpha[e * m->K + k] = r < 0 ? m->alpha0 : m->alpha[r * m->K + k];
+    t->nv[e] = r < 0 ? 0 : m->nv[r];
+    t->nb[e] = r < 0 ? 0 : m->nband[r];
+    t->snv[e] = 0;
+    t->snb[e] = 0;
+    return e;
+}
+
+/* The terms of rows rows[0..nr) (ascending) for the voxels of columns
+ * i in [i0, i1], j in [j0, j1]. */
+static int tile_accumulate(or_tile *t, const oracle_map *m, const float *xyz,
+                           const int32_t *label, const double *w, const int64_t *rows,
+                           int64_t nr, int64_t i0, int64_t i1, int64_t j0, int64_t j1)
+{
     const double res = m->res;
-    for (int64_t t = 0; t < n; ++t) {
-        const float *p = xyz + 3 * t;
-        const double wt = w ? w[t] : 1.0;
-        /* the kernel of the row's class */
-        const double L = m->lk[label[t]], L2 = L * L, S0 = m->s0k[label[t]];
-        if (m->scsm) {
-            /* Eq. (2): the measurement counts in the cell it falls into. */
-            int32_t v[3];
-            int rc = voxel_of(p, m->res32, v);
-            if (rc) return rc;
-            int64_t r = map_row(m, pack_key(v[0], v[1], v[2]));
-            if (r < 0) return OR_E_OOM;
-            m->alpha[r * m->K + label[t]] += wt;
-            m->nv[r] += 1;
-            continue;
-        }
+    for (int64_t q = 0; q < nr; ++q) {
+        const int64_t t_ = rows[q];
+        const float *p = xyz + 3 * t_;
+        const double wt = w ? w[t_] : 1.0;
+        const double L = m->lk[label[t_]], L2 = L * L, S0 = m->s0k[label[t_]];
         const double x[3] = {p[0], p[1], p[2]};
-        /* block of the row's own voxel (for the extended-block selection) */
-        int32_t pv[3];
-        if (m->face_blocks) {
-            int rc = voxel_of(p, m->res32, pv);
-            if (rc) return rc;
-        }
+        int32_t pv[3] = {0, 0, 0};
+        if (m->face_blocks && voxel_of(p, m->res32, pv)) return OR_E_RANGE;
         int64_t lo[3], hi[3];
-        for (int a = 0; a < 3; ++a) {
-            lo[a] = (int64_t)floor((x[a] - L) / res - 0.5) - 1;
-            hi[a] = (int64_t)ceil((x[a] + L) / res - 0.5) + 1;
-            if (lo[a] < -OR_COORD_LIM || hi[a] >= OR_COORD_LIM) return OR_E_RANGE;
-        }
+        row_box(x, L, res, lo, hi);
+        if (lo[0] < i0) lo[0] = i0;
+        if (hi[0] > i1) hi[0] = i1;
+        if (lo[1] < j0) lo[1] = j0;
+        if (hi[1] > j1) hi[1] = j1;
         for (int64_t i = lo[0]; i <= hi[0]; ++i) {
             double dx = x[0] - ((double)i + 0.5) * res;
             for (int64_t j = lo[1]; j <= hi[1]; ++j) {
@@ -597,16 +701,149 @@ static int insert_rows(oracle_map *m, const float *xyz, const int32_t *label, co
                     }
                     int band = fabs(d2 / L2 - 1.0) <= 1e-5;
                     if (!(d2 < L2) && !band) continue;
-                    int64_t r = map_row(m, pack_key(i, j, k));
-                    if (r < 0) return OR_E_OOM;
-                    if (band) m->nband[r] += 1;
+                    int64_t e = tile_entry(t, m, pack_key(i, j, k));
+                    if (e < 0) return OR_E_OOM;
+                    if (band) { t->nb[e] += 1; t->snb[e] += 1; }
                     if (!(d2 < L2)) continue;
-                    m->alpha[r * m->K + label[t]] += wt * (S0 * oracle_kernel_f(sqrt(d2) / L));
-                    m->nv[r] += 1;
+                    t->alpha[e * m->K + label[t_]] += wt * (S0 * oracle_kernel_f(sqrt(d2) / L));
+                    t->nv[e] += 1;
+                    t->snv[e] += 1;
                 }
             }
         }
     }
+    return OR_OK;
+}
+
+static int insert_rows(oracle_map *m, const float *xyz, const int32_t *label, const double *w,
+                       int64_t n)
+{
+    if (!m || n < 0) return OR_E_ARG;
+    const double res = m->res;
+    memset(m->last, 0, sizeof(m->last));
+    for (int64_t t = 0; t < n; ++t) {
+        if (label[t] < 0 || label[t] >= m->K) return OR_E_INPUT;
+        if (!finite3(xyz + 3 * t)) return OR_E_INPUT;
+        if (w && !(isfinite(w[t]) && w[t] >= 0.0)) return OR_E_INPUT;
+        int32_t v[3];
+        int rc = voxel_of(xyz + 3 * t, m->res32, v);
+        if (rc) return rc;
+        if (!m->scsm) {
+            const double x[3] = {xyz[3 * t], xyz[3 * t + 1], xyz[3 * t + 2]};
+            int64_t lo[3], hi[3];
+            row_box(x, m->lk[label[t]], res, lo, hi);
+            for (int a = 0; a < 3; ++a)
+                if (lo[a] < -OR_COORD_LIM || hi[a] >= OR_COORD_LIM) return OR_E_RANGE;
+        }
+    }
+    if (n == 0) return OR_OK;
+    if (m->scsm) {
+        /* Eq. (2): each measurement counts in the cell it falls into. */
+        ++m->stamp_now;
+        for (int64_t t = 0; t < n; ++t) {
+            int32_t v[3];
+            (void)voxel_of(xyz + 3 * t, m->res32, v);
+            int64_t r = map_row(m, pack_key(v[0], v[1], v[2]));
+            if (r < 0) return OR_E_OOM;
+            m->alpha[r * m->K + label[t]] += w ? w[t] : 1.0;
+            m->nv[r] += 1;
+            if (m->stamp[r] != m->stamp_now) { m->stamp[r] = m->stamp_now; m->last[0] += 1; }
+            m->last[1] += 1;
+        }
+        return OR_OK;
+    }
+    /* tiles of W x W voxel columns covering the rows' boxes */
+    int64_t ti0 = INT64_MAX, ti1 = INT64_MIN, tj0 = INT64_MAX, tj1 = INT64_MIN;
+    int64_t W = 16;
+    int64_t vlo[2] = {INT64_MAX, INT64_MAX}, vhi[2] = {INT64_MIN, INT64_MIN};
+    for (int64_t t = 0; t < n; ++t) {
+        const double x[3] = {xyz[3 * t], xyz[3 * t + 1], xyz[3 * t + 2]};
+        int64_t lo[3], hi[3];
+        row_box(x, m->lk[label[t]], res, lo, hi);
+        for (int a = 0; a < 2; ++a) {
+            if (lo[a] < vlo[a]) vlo[a] = lo[a];
+            if (hi[a] > vhi[a]) vhi[a] = hi[a];
+        }
+    }
+    for (;;) {
+        ti0 = fdiv_floor(vlo[0], W); ti1 = fdiv_floor(vhi[0], W);
+        tj0 = fdiv_floor(vlo[1], W); tj1 = fdiv_floor(vhi[1], W);
+        if ((ti1 - ti0 + 1) * (tj1 - tj0 + 1) <= (1 << 20)) break;
+        W *= 2;
+    }
+    const int64_t nti = ti1 - ti0 + 1, ntj = tj1 - tj0 + 1, ntiles = nti * ntj;
+    int64_t *start = (int64_t *)calloc((size_t)ntiles + 1, sizeof(int64_t));
+    if (!start) return OR_E_OOM;
+    for (int64_t t = 0; t < n; ++t) {
+        const double x[3] = {xyz[3 * t], xyz[3 * t + 1], xyz[3 * t + 2]};
+        int64_t lo[3], hi[3];
+        row_box(x, m->lk[label[t]], res, lo, hi);
+        for (int64_t a = fdiv_floor(lo[0], W); a <= fdiv_floor(hi[0], W); ++a)
+            for (int64_t b = fdiv_floor(lo[1], W); b <= fdiv_floor(hi[1], W); ++b)
+                start[(a - ti0) * ntj + (b - tj0) + 1] += 1;
+    }
+    for (int64_t i = 0; i < ntiles; ++i) start[i + 1] += start[i];
+    int64_t *rows = (int64_t *)malloc(sizeof(int64_t) * (size_t)(start[ntiles] > 0 ? start[ntiles] : 1));
+    int64_t *cur = (int64_t *)malloc(sizeof(int64_t) * (size_t)ntiles);
+    or_tile *tiles = (or_tile *)calloc((size_t)ntiles, sizeof(or_tile));
+    int64_t *busy = (int64_t *)malloc(sizeof(int64_t) * (size_t)ntiles);
+    if (!rows || !cur || !tiles || !busy) {
+        free(start); free(rows); free(cur); free(tiles); free(busy);
+        return OR_E_OOM;
+    }
+    memcpy(cur, start, sizeof(int64_t) * (size_t)ntiles);
+    for (int64_t t = 0; t < n; ++t) {   /* each tile's rows in row order */
+        const double x[3] = {xyz[3 * t], xyz[3 * t + 1], xyz[3 * t + 2]};
+        int64_t lo[3], hi[3];
+        row_box(x, m->lk[label[t]], res, lo, hi);
+        for (int64_t a = fdiv_floor(lo[0], W); a <= fdiv_floor(hi[0], W); ++a)
+            for (int64_t b = fdiv_floor(lo[1], W); b <= fdiv_floor(hi[1], W); ++b)
+                rows[cur[(a - ti0) * ntj + (b - tj0)]++] = t;
+    }
+    int64_t nbusy = 0;
+    for (int64_t i = 0; i < ntiles; ++i)
+        if (start[i + 1] > start[i]) busy[nbusy++] = i;
+    int err = OR_OK;
+    #pragma omp parallel for schedule(dynamic, 1)
+    for (int64_t q = 0; q < nbusy; ++q) {
+        const int64_t i = busy[q];
+        const int64_t a = i / ntj + ti0, b = i % ntj + tj0;
+        int rc = tile_accumulate(&tiles[i], m, xyz, label, w, rows + start[i],
+                                 start[i + 1] - start[i], a * W, a * W + W - 1, b * W,
+                                 b * W + W - 1);
+        if (rc) {
+            #pragma omp critical
+            err = rc;
+        }
+    }
+    /* write back tile by tile (tiles own disjoint voxels) */
+    for (int64_t q = 0; q < nbusy && !err; ++q) {
+        or_tile *t = &tiles[busy[q]];
+        for (int64_t e = 0; e < t->n; ++e) {
+            int64_t r = map_row(m, t->key[e]);
+            if (r < 0) { err = OR_E_OOM; break; }
+            memcpy(m->alpha + r * m->K, t->alpha + e * m->K, sizeof(double) * m->K);
+            m->nv[r] = t->nv[e];
+            m->nband[r] = t->nb[e];
+            m->last[0] += t->snv[e] > 0;
+            m->last[1] += t->snv[e];
+            m->last[2] += t->snb[e] > 0;
+            m->last[3] += t->snb[e];
+        }
+    }
+    for (int64_t q = 0; q < nbusy; ++q) tile_free(&tiles[busy[q]]);
+    free(start); free(rows); free(cur); free(tiles); free(busy);
+    return err;
+}
+
+/* Counters of the last insert: [0] voxels with at least one in-support row
+ * (S-CSM: voxels holding at least one row), [1] in-support (voxel, row) pairs
+ * (S-CSM: rows), [2] voxels with a pair in the rounding band |d^2/l^2 - 1| <=
+ * 1e-5, [3] such pairs. */
+int oracle_map_last_insert(const oracle_map *m, int64_t *out)
+{
+    if (!m || !out) return OR_E_ARG;
+    memcpy(out, m->last, sizeof(m->last));
     return OR_OK;
 }
 
@@ -928,6 +1165,16 @@ int oracle_loss_classes(const double *train_xyz, const int32_t *train_label, int
     }
     if (!alpha_q) free(A);
     free(G);
+    return OR_OK;
+}
+
+/* Threads of the tile-parallel map insert (results do not depend on it). */
+int oracle_set_num_threads(int n)
+{
+    if (n < 1) return OR_E_ARG;
+#ifdef _OPENMP
+    omp_set_num_threads(n);
+#endif
     return OR_OK;
 }
 

@@ -275,3 +275,87 @@ def test_extended_block_selection_is_a_lower_bound_on_a_scene():
     af = face.lookup(ie)
     assert np.all(af <= ae * (1 + 1e-15))
     assert np.any(af < ae * (1 - 1e-6))          # the selection does drop rows here
+
+
+def test_voxel_key_format_worked_values():
+    # key = (i + 2^20) << 42 | (j + 2^20) << 21 | (k + 2^20): 21 bits per axis,
+    # biased by 2^20, written out here with Python integers
+    lim = 1 << 20
+    ijk = np.array([[0, 0, 0], [-lim, -lim, -lim], [lim - 1, lim - 1, lim - 1], [3, -7, 12],
+                    [-1, 0, 1], [lim - 1, -lim, 5]], np.int32)
+    want = [((int(i) + lim) << 42) | ((int(j) + lim) << 21) | (int(k) + lim) for i, j, k in ijk]
+    got = oracle.pack_keys(ijk)
+    assert [int(v) for v in got] == want
+    assert int(got[1]) == 0 and int(got[2]) == (1 << 63) - 1
+    # the key order is the lexicographic (i, j, k) order of the voxel indices
+    rng = np.random.default_rng(3)
+    v = rng.integers(-lim, lim, size=(500, 3)).astype(np.int32)
+    v[250:] = v[:250] + rng.integers(-1, 2, size=(250, 3))
+    v = np.clip(v, -lim, lim - 1).astype(np.int32)
+    lex = np.lexsort((v[:, 2], v[:, 1], v[:, 0]))
+    by_key = np.argsort(oracle.pack_keys(v), kind="stable")
+    assert np.array_equal(v[lex], v[by_key])
+
+
+def test_map_insert_does_not_depend_on_the_thread_count():
+    # the insert splits the voxels over column tiles; each voxel still sums its
+    # rows in row order, so any thread count gives the same bits
+    sc = scenes.random_points_scene(11, 4000, K=4, extent=6.0, res=0.1, l=0.3, free_step=0.2,
+                                    origin=(0.3, -0.2, 0.5))
+    p = sc.params.f32()
+    s = sc.scans[0]
+    out = []
+    for th in (1, 3, 8):
+        oracle.set_num_threads(th)
+        m = oracle.OracleMap.from_params(p)
+        m.insert_scan(s.xyz, s.label, s.origin, p.free_step, p.free_class)
+        m.insert_scan(s.xyz[::3], s.label[::3], (s.origin + np.float32(0.5)).astype(np.float32),
+                      p.free_step, p.free_class)
+        out.append(m.export())
+    oracle.set_num_threads(max(1, os.cpu_count() or 1))
+    for o in out[1:]:
+        for x, y in zip(out[0], o):
+            assert np.array_equal(x, y)
+
+
+def test_last_insert_counts_against_brute_force():
+    sc = scenes.random_points_scene(2, 80, K=3, extent=0.5, centre=(1.1, -2.3, 0.4))
+    p = sc.params.f32()
+    xyz, lab = sc.scans[0].xyz, sc.scans[0].label
+    m = oracle.OracleMap.from_params(p)
+    m.insert_training(xyz, lab)
+    vox = region_voxels(xyz, p.res, 4)
+    _, n_bf = brute_alpha_numpy(xyz, lab, vox, p.res, p.K, p.l, p.sigma0, p.alpha0)
+    c = m.last_insert()
+    assert c["V"] == int((n_bf > 0).sum()) and c["P"] == int(n_bf.sum())
+    # a second insert of half the rows: its own counts, not the map's totals
+    m.insert_training(xyz[:40], lab[:40])
+    _, n2 = brute_alpha_numpy(xyz[:40], lab[:40], vox, p.res, p.K, p.l, p.sigma0, p.alpha0)
+    c2 = m.last_insert()
+    assert c2["V"] == int((n2 > 0).sum()) and c2["P"] == int(n2.sum())
+    # the counting model counts rows and the voxels holding them
+    ms = oracle.OracleMap.from_params(p, scsm=True)
+    ms.insert_training(xyz, lab)
+    cs = ms.last_insert()
+    assert cs["P"] == xyz.shape[0]
+    assert cs["V"] == len({tuple(v) for v in oracle.voxel_coords(xyz, p.res)})
+
+
+def test_failed_insert_leaves_the_oracle_map_unchanged():
+    sc = scenes.random_points_scene(4, 200, K=3, extent=0.5)
+    p = sc.params.f32()
+    xyz, lab = sc.scans[0].xyz, sc.scans[0].label
+    m = oracle.OracleMap.from_params(p)
+    m.insert_training(xyz[:100], lab[:100])
+    before = m.export()
+    bad = lab[100:].copy()
+    bad[-1] = 7
+    with pytest.raises(oracle.OracleError):
+        m.insert_training(xyz[100:], bad)
+    far = xyz[100:].copy()
+    far[-1, 0] = 1.0e6          # voxel index beyond 2^20
+    with pytest.raises(oracle.OracleError):
+        m.insert_training(far, lab[100:])
+    after = m.export()
+    for x, y in zip(before, after):
+        assert np.array_equal(x, y)
