@@ -66,7 +66,13 @@ typedef struct smki_options {
   int32_t selection;        /* SMKI_SELECT_EXACT (default) or SMKI_SELECT_FACE_BLOCKS
                                (S-BKI only); with face blocks, n_pairs still counts the
                                pairs of the exact support */
+  int32_t flags;            /* bit set of SMKI_FLAG_* (0: none) */
 } smki_options;
+
+/* smki_options.flags */
+#define SMKI_FLAG_WIDE_OFFSETS 1  /* address the partial sums of an insert with 64-bit offsets
+                                     even when they take less than 4 GiB (the form used above
+                                     4 GiB; results are identical) */
 
 /* Counters of the last insert (smki_last_scan_stats). */
 typedef struct smki_scan_stats {
@@ -209,9 +215,13 @@ smki_status smki_num_blocks(smki_map *m, int64_t *n_blocks);
  */
 smki_status smki_export(smki_map *m, int64_t capacity, int64_t *n_blocks, int32_t *block_ijk,
                         float *alpha);
-/* Replace the map's contents with n exported blocks (device arrays as above).
- * n = 0 empties the map (capacity is kept) without synchronising the stream;
- * n > 0 synchronises it once to size the class blocks. */
+/* Replace the map's contents with n exported blocks (device arrays as above;
+ * block i of the input becomes the map's block i).  n = 0 empties the map
+ * (capacity is kept) without synchronising the stream; n > 0 validates the
+ * input on the device and synchronises once to read the result and size the
+ * class blocks.  Errors: SMKI_E_RANGE if a block's voxels leave
+ * [-2^20, 2^20), SMKI_E_BAD_INPUT if a block appears twice, SMKI_E_CAPACITY
+ * if n * K > 2^30, SMKI_E_OOM; on any error the map is left unchanged. */
 smki_status smki_import(smki_map *m, int64_t n, const int32_t *block_ijk, const float *alpha);
 
 smki_status smki_last_scan_stats(smki_map *m, smki_scan_stats *out);

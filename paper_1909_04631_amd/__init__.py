@@ -13,7 +13,7 @@ import ctypes as C
 
 import torch
 
-from ._lib import MODELS, SELECTIONS, SmkiError, ScanStats, Options, check, lib
+from ._lib import FLAG_WIDE_OFFSETS, MODELS, SELECTIONS, SmkiError, ScanStats, Options, check, lib
 
 __all__ = ["SemanticMap", "SmkiError", "free_samples", "bucket_cells", "loss_forward",
            "loss_backward", "PredictiveLoss", "predictive_loss", "loss_forward_classes",
@@ -47,10 +47,13 @@ class SemanticMap:
     """A persistent semantic occupancy map on one GPU (the device current at creation)."""
 
     def __init__(self, res, block_size, l, sigma0, K, alpha0=1e-3, free_class=0,
-                 unit_budget=0, initial_blocks=0, model="sbki", selection="exact"):
+                 unit_budget=0, initial_blocks=0, model="sbki", selection="exact",
+                 wide_offsets=False):
         """model: "sbki" (Eq. 7-8, the default) or "scsm" (counting model, Eq. 2).
         selection: "exact" (every row within l) or "face_blocks" (rows of the
-        voxel's block and its six face neighbours, the paper's extended block)."""
+        voxel's block and its six face neighbours, the paper's extended block).
+        wide_offsets: address partial sums with 64-bit offsets at any size
+        (SMKI_FLAG_WIDE_OFFSETS)."""
         if model not in MODELS:
             raise ValueError(f"model must be one of {sorted(MODELS)}")
         if selection not in SELECTIONS:
@@ -60,7 +63,8 @@ class SemanticMap:
         self.res, self.l, self.sigma0, self.alpha0 = float(res), float(l), float(sigma0), float(alpha0)
         self.free_class = int(free_class)
         self.device = torch.device("cuda", torch.cuda.current_device())
-        opt = Options(int(initial_blocks), int(unit_budget), MODELS[model], SELECTIONS[selection])
+        opt = Options(int(initial_blocks), int(unit_budget), MODELS[model], SELECTIONS[selection],
+                      FLAG_WIDE_OFFSETS if wide_offsets else 0)
         h = C.c_void_p()
         check(lib().smki_create_map(res, block_size, l, sigma0, K, alpha0, free_class,
                                     C.byref(opt), C.byref(h)), "smki_create_map")

@@ -40,7 +40,10 @@ class SmkiError(RuntimeError):
 
 class Options(C.Structure):
     _fields_ = [("initial_blocks", C.c_int64), ("unit_budget", C.c_int32), ("model", C.c_int32),
-                ("selection", C.c_int32)]
+                ("selection", C.c_int32), ("flags", C.c_int32)]
+
+
+FLAG_WIDE_OFFSETS = 1
 
 
 MODELS = {"sbki": 0, "scsm": 1}

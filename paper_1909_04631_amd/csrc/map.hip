@@ -170,18 +170,23 @@ __global__ void k_keys_to_ijk(const uint64_t* __restrict__ keys, int64_t n, int3
   ijk[3 * i + 2] = (int32_t)(k & 0x1FFFFF) - (1 << 20);
 }
 
-__global__ void k_ijk_to_keys(const int32_t* __restrict__ ijk, int64_t n, uint64_t* keys,
-                              uint32_t* err) {
+__global__ void k_ijk_to_keys(const int32_t* __restrict__ ijk, int64_t n, int32_t log2B,
+                              uint64_t* keys, uint32_t* err) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   const int32_t bx = ijk[3 * i], by = ijk[3 * i + 1], bz = ijk[3 * i + 2];
-  if (bx < -(1 << 20) || bx >= (1 << 20) || by < -(1 << 20) || by >= (1 << 20) ||
-      bz < -(1 << 20) || bz >= (1 << 20)) {
+  const int32_t lim = (1 << 20) >> log2B;   // the block's voxels stay in [-2^20, 2^20)
+  if (bx < -lim || bx >= lim || by < -lim || by >= lim || bz < -lim || bz >= lim) {
     atomicOr(err, DEVERR_RANGE);
     keys[i] = 0;
     return;
   }
   keys[i] = smki_block_key(bx, by, bz);
+}
+
+__global__ void k_adjacent_dups(const uint64_t* __restrict__ s, int64_t n, uint32_t* err) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i + 1 < n && s[i] == s[i + 1]) atomicOr(err, DEVERR_DUP);
 }
 
 __global__ void k_iota(uint32_t* p, int64_t n) {
@@ -262,10 +267,17 @@ hipError_t launch_block_keys_to_ijk(const uint64_t* keys, int64_t n, int32_t* ij
   return hipGetLastError();
 }
 
-hipError_t launch_ijk_to_block_keys(const int32_t* ijk, int64_t n, uint64_t* keys, uint32_t* err,
-                                    hipStream_t st) {
+hipError_t launch_ijk_to_block_keys(const int32_t* ijk, int64_t n, int32_t log2B, uint64_t* keys,
+                                    uint32_t* err, hipStream_t st) {
   if (n <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_ijk_to_keys, dim3(nblk(n, 256)), dim3(256), 0, st, ijk, n, keys, err);
+  hipLaunchKernelGGL(k_ijk_to_keys, dim3(nblk(n, 256)), dim3(256), 0, st, ijk, n, log2B, keys,
+                     err);
+  return hipGetLastError();
+}
+
+hipError_t launch_adjacent_dups(const uint64_t* sorted, int64_t n, uint32_t* err, hipStream_t st) {
+  if (n <= 1) return hipSuccess;
+  hipLaunchKernelGGL(k_adjacent_dups, dim3(nblk(n, 256)), dim3(256), 0, st, sorted, n, err);
   return hipGetLastError();
 }
 

@@ -121,6 +121,7 @@ struct smki_map {
   int32_t chunk;  // rows per splat work unit
   int32_t model;      // SMKI_MODEL_SBKI or SMKI_MODEL_SCSM
   int32_t selection;  // SMKI_SELECT_EXACT or SMKI_SELECT_FACE_BLOCKS
+  int32_t flags;      // SMKI_FLAG_*
   int device = 0;
   hipStream_t stream = nullptr;
   // persistent device state
@@ -158,7 +159,7 @@ struct smki_map {
 namespace {
 
 smki_status status_of_err(uint32_t e) {
-  if (e & (DEVERR_LABEL | DEVERR_NONFINITE)) return SMKI_E_BAD_INPUT;
+  if (e & (DEVERR_LABEL | DEVERR_NONFINITE | DEVERR_DUP)) return SMKI_E_BAD_INPUT;
   if (e & (DEVERR_RANGE | DEVERR_RAY)) return SMKI_E_RANGE;
   if (e & DEVERR_HASH) return SMKI_E_CAPACITY;
   return SMKI_E_DEVICE;
@@ -591,16 +592,20 @@ smki_status insert_impl(smki_map* m, const float* xyz, const int32_t* label, con
   SMKI_HIP_TRY(launch_clear3(d_si, (int64_t)(d_mark + n_ext - d_si), (int32_t*)m->d_stats,
                              (int64_t)(kStatBytes / sizeof(int32_t)), ps.dense,
                              g.n_blocks * m->K, -1, q));
+  // errors of the bucketing (a row's voxel index out of range) go to d_si[3],
+  // read with the counts below, before any concentration is written
   SMKI_HIP_TRY(bucket_scan(xyz, label, probs, m->K, n, d_kept, d_kpos, nk, d_off, nf, d_wgbeam,
-                           d_soff, d_org, S, step, m->free_class, g, ps, scr, m->d_err, q));
+                           d_soff, d_org, S, step, m->free_class, g, ps, scr,
+                           (uint32_t*)(d_si + 3), q));
   SMKI_HIP_TRY(launch_mark_targets(ps.slot_lin, ps.d_nslots, (int32_t)max_slots, g, eblo, enb, DB,
                                    d_mark, q));
   SMKI_HIP_TRY(launch_slot_units(ps.head, ps.d_nslots, (int32_t)max_slots, m->chunk, d_nun, q));
   SMKI_HIP_TRY(scan_excl_pair_i32(d_mark, d_mpos, n_ext, d_ntgt, d_nun, d_ust, max_slots, d_nunits,
                                   scr.scan_tmp, q));
-  // sync 2: slots, targets, work units
-  int32_t si[3];
+  // sync 2: slots, targets, work units, the bucketing's error word
+  int32_t si[4];
   SMKI_HIP_TRY(sync_read(m, d_si, sizeof(si), si));
+  if (si[3]) return status_of_err((uint32_t)si[3]);
   const int32_t n_slots = si[0], n_t = si[1];
   const int64_t n_units = si[2];
   m->last.n_point_blocks = n_slots;
@@ -692,6 +697,7 @@ smki_status insert_impl(smki_map* m, const float* xyz, const int32_t* label, con
   sa.uorder = d_uorder;
   sa.part = d_part;
   sa.part_elems = n_units * DR3;
+  sa.wide = (m->flags & SMKI_FLAG_WIDE_OFFSETS) ? 1 : 0;
   sa.umask = d_umask;
   sa.sinfo = d_sinfo;
   sa.n_slots = n_slots;
@@ -773,7 +779,8 @@ smki_status smki_create_map(float res, int32_t block_size, float l, float sigma0
   if (block_size != 4 && block_size != 8) return SMKI_E_INVALID_ARG;
   if (opt && (opt->initial_blocks < 0 || opt->unit_budget < 0 || opt->unit_budget > (1 << 24) ||
               (opt->model != SMKI_MODEL_SBKI && opt->model != SMKI_MODEL_SCSM) ||
-              (opt->selection != SMKI_SELECT_EXACT && opt->selection != SMKI_SELECT_FACE_BLOCKS)))
+              (opt->selection != SMKI_SELECT_EXACT && opt->selection != SMKI_SELECT_FACE_BLOCKS) ||
+              (opt->flags & ~SMKI_FLAG_WIDE_OFFSETS) != 0))
     return SMKI_E_INVALID_ARG;
   int ndev = 0;
   if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) return SMKI_E_DEVICE;
@@ -790,6 +797,7 @@ smki_status smki_create_map(float res, int32_t block_size, float l, float sigma0
   m->chunk = (opt && opt->unit_budget > 0) ? opt->unit_budget : SMKI_CHUNK;
   m->model = opt ? opt->model : SMKI_MODEL_SBKI;
   m->selection = opt ? opt->selection : SMKI_SELECT_EXACT;
+  m->flags = opt ? opt->flags : 0;
   (void)hipGetDevice(&m->device);
   m->dev.K = K;
   m->dev.B = block_size;
@@ -932,40 +940,73 @@ smki_status smki_export(smki_map* m, int64_t capacity, int64_t* n_blocks, int32_
 
 smki_status smki_import(smki_map* m, int64_t n, const int32_t* block_ijk, const float* alpha) {
   if (!m || n < 0 || (n > 0 && (!block_ijk || !alpha))) return SMKI_E_INVALID_ARG;
-  smki_status rc = ensure_pool(m, std::max<int64_t>(n, 1));
-  if (rc != SMKI_OK) return rc;
-  m->n_blocks = 0;   // the hash and the class blocks are rebuilt from the input below
-  m->n_cblocks = 0;
-  rc = ensure_hash(m, std::max<int64_t>(n, 1));
-  if (rc != SMKI_OK) return rc;
-  if (n > 0) {
-    // class blocks only for (block, class) pairs holding a value other than alpha0
-    const int64_t nk = n * m->K;
-    Sizer z;
-    z.add<int32_t>(nk);
-    z.add<int32_t>(nk);
-    z.add<int32_t>(2);
-    z.add<char>(scan_tmp_bytes(nk));
-    SMKI_HIP_TRY(m->a_misc.reserve(z.total));
-    int32_t* flag = m->a_misc.take<int32_t>(nk);
-    int32_t* pos = m->a_misc.take<int32_t>(nk);
-    int32_t* tot = m->a_misc.take<int32_t>(2);
-    void* tmp = m->a_misc.take<char>(scan_tmp_bytes(nk));
-    SMKI_HIP_TRY(launch_ijk_to_block_keys(block_ijk, n, m->dev.bkeys, m->d_err, m->stream));
-    SMKI_HIP_TRY(launch_import_flags(m->dev, alpha, n, flag, m->stream));
-    SMKI_HIP_TRY(scan_excl_i32(flag, pos, nk, tot, tmp, m->stream));
-    int32_t nc = 0;
-    SMKI_HIP_TRY(sync_read(m, tot, sizeof(nc), &nc));
-    rc = ensure_cpool(m, nc);
-    if (rc != SMKI_OK) return rc;
-    SMKI_HIP_TRY(launch_import_copy(m->dev, alpha, n, flag, pos, 0, m->stream));
-    m->n_cblocks = nc;
+  SMKI_HIP_TRY(hipSetDevice(m->device));
+  if (n == 0) {   // empty the map: no check, no synchronisation
+    SMKI_HIP_TRY(launch_hash_clear(m->dev, m->stream));
+    m->n_blocks = 0;
+    m->n_cblocks = 0;
+    return SMKI_OK;
   }
-  SMKI_HIP_TRY(launch_hash_clear(m->dev, m->stream));
-  SMKI_HIP_TRY(launch_hash_insert_slots(m->dev, 0, n, m->d_err, m->stream));
+  const int64_t nk = n * m->K;
+  if (nk > (int64_t)INT32_MAX / 2) return SMKI_E_CAPACITY;
+  // Validate and size everything in scratch first: the block keys (range
+  // checked), a sorted copy of them (duplicates), and the class blocks to keep
+  // (pairs holding a value other than alpha0).  The map is touched only after
+  // all of that succeeded, so a failed import leaves it unchanged.
+  Sizer z;
+  z.add<int32_t>(4);
+  z.add<uint64_t>(n);
+  z.add<uint64_t>(n);
+  z.add<uint64_t>(n);
+  z.add<uint32_t>(n);
+  z.add<uint32_t>(n);
+  z.add<char>(radix_tmp_bytes(n));
+  z.add<int32_t>(nk);
+  z.add<int32_t>(nk);
+  z.add<char>(scan_tmp_bytes(nk));
+  SMKI_HIP_TRY(m->a_misc.reserve(z.total));
+  Arena& Z = m->a_misc;
+  int32_t* hdr = Z.take<int32_t>(4);   // [0] error word, [1] class blocks
+  uint64_t* keys = Z.take<uint64_t>(n);
+  uint64_t* skeys = Z.take<uint64_t>(n);
+  uint64_t* k2 = Z.take<uint64_t>(n);
+  uint32_t* o = Z.take<uint32_t>(n);
+  uint32_t* o2 = Z.take<uint32_t>(n);
+  void* stmp = Z.take<char>(radix_tmp_bytes(n));
+  int32_t* flag = Z.take<int32_t>(nk);
+  int32_t* pos = Z.take<int32_t>(nk);
+  void* tmp = Z.take<char>(scan_tmp_bytes(nk));
+  hipStream_t q = m->stream;
+  SMKI_HIP_TRY(launch_fill_i32(hdr, 4, 0, q));
+  SMKI_HIP_TRY(launch_ijk_to_block_keys(block_ijk, n, m->log2B, keys, (uint32_t*)hdr, q));
+  SMKI_HIP_TRY(hipMemcpyAsync(skeys, keys, sizeof(uint64_t) * n, hipMemcpyDeviceToDevice, q));
+  SMKI_HIP_TRY(launch_iota_u32(o, n, q));
+  SMKI_HIP_TRY(radix_sort_u64(skeys, o, k2, o2, n, 63, stmp, q));
+  SMKI_HIP_TRY(launch_adjacent_dups(skeys, n, (uint32_t*)hdr, q));
+  SMKI_HIP_TRY(launch_import_flags(m->dev, alpha, n, flag, q));
+  SMKI_HIP_TRY(scan_excl_i32(flag, pos, nk, hdr + 1, tmp, q));
+  int32_t h[2];
+  SMKI_HIP_TRY(sync_read(m, hdr, sizeof(h), h));
+  if (h[0]) return status_of_err((uint32_t)h[0]);
+  const int64_t nc = h[1];
+  // capacity (growth keeps the current contents, so a failure here leaves the
+  // map as it was)
+  smki_status rc = ensure_pool(m, n);
+  if (rc != SMKI_OK) return rc;
+  rc = ensure_cpool(m, std::max<int64_t>(nc, 1));
+  if (rc != SMKI_OK) return rc;
+  rc = ensure_hash(m, n);
+  if (rc != SMKI_OK) return rc;
+  // commit: block i of the input is pool slot i
+  SMKI_HIP_TRY(hipMemcpyAsync(m->dev.bkeys, keys, sizeof(uint64_t) * n, hipMemcpyDeviceToDevice,
+                              q));
+  SMKI_HIP_TRY(launch_import_copy(m->dev, alpha, n, flag, pos, 0, q));
+  SMKI_HIP_TRY(launch_hash_clear(m->dev, q));
+  SMKI_HIP_TRY(launch_hash_insert_slots(m->dev, 0, n, m->d_err, q));
   m->n_blocks = n;
-  if (n == 0) return SMKI_OK;   // emptying the map: nothing to check, no synchronisation
-  return take_device_error(m);
+  m->n_cblocks = nc;
+  SMKI_HIP_TRY(stream_wait(q));
+  return SMKI_OK;
 }
 
 smki_status smki_last_scan_stats(smki_map* m, smki_scan_stats* out) {

@@ -60,6 +60,7 @@ struct SplatArgs {
   const int4* units;          // [n_units] (first row, end row, slot, class)
   const int32_t* uorder;      // [n_units] unit of splat workgroup b (nullable: b itself)
   int64_t part_elems;         // n_units (B + 2R)^3
+  int32_t wide;               // 1: 64-bit offsets into part even below 4 GiB
   float* part;                // [n_units][(B + 2R)^3] partial sums of each unit's region, by
                               // piece: the region split into the 27 parts that fall in the
                               // unit's block and its neighbours, each contiguous (x, y, z)
@@ -134,8 +135,11 @@ hipError_t launch_import_flags(const MapDev& m, const float* alpha, int64_t n, i
 hipError_t launch_import_copy(const MapDev& m, const float* alpha, int64_t n, const int32_t* flag,
                               const int32_t* pos, int64_t c0, hipStream_t st);
 hipError_t launch_block_keys_to_ijk(const uint64_t* keys, int64_t n, int32_t* ijk, hipStream_t st);
-hipError_t launch_ijk_to_block_keys(const int32_t* ijk, int64_t n, uint64_t* keys, uint32_t* err,
-                                    hipStream_t st);
+// block coordinates -> keys; a block whose voxels leave [-2^20, 2^20) flags DEVERR_RANGE
+hipError_t launch_ijk_to_block_keys(const int32_t* ijk, int64_t n, int32_t log2B, uint64_t* keys,
+                                    uint32_t* err, hipStream_t st);
+// DEVERR_DUP if two adjacent keys of a sorted array are equal
+hipError_t launch_adjacent_dups(const uint64_t* sorted, int64_t n, uint32_t* err, hipStream_t st);
 hipError_t launch_iota_u32(uint32_t* p, int64_t n, hipStream_t st);
 
 __host__ __device__ inline uint64_t smki_block_key(int32_t bx, int32_t by, int32_t bz) {

@@ -25,6 +25,7 @@ enum : uint32_t {
   DEVERR_RAY = 1u << 2,        // more than 2^20 free samples on one beam
   DEVERR_RANGE = 1u << 3,      // voxel index outside [-2^20, 2^20)
   DEVERR_HASH = 1u << 4,       // block hash full
+  DEVERR_DUP = 1u << 5,        // the same block twice in an import
 };
 
 // ---------------------------------------------------------------------------

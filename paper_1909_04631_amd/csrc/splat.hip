@@ -740,7 +740,7 @@ hipError_t launch_splat_br(const SplatArgs& a, int64_t n_units, int32_t n_target
                                                  st);
   } else {
     if (n_targets > 0) {
-      if (a.part_elems * sizeof(float) <= (int64_t(1) << 32))
+      if (!a.wide && a.part_elems * sizeof(float) <= (int64_t(1) << 32))
         hipLaunchKernelGGL((k_merge<B, R, false>), dim3((unsigned)n_targets),
                            dim3(MergeShape<B, R>::NT), 0, st, a, n_targets);
       else

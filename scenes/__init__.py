@@ -379,16 +379,46 @@ def lidar_scan_scene(seed: int = 1, flip: float = 0.10) -> Scene:
                  info={"seed": seed})
 
 
+_STEREO = {}   # the sequence being generated (read by forked workers)
+
+
+def _stereo_scan(s: int) -> Scan:
+    c = _STEREO
+    origin = np.array([c["x0"] + s * c["step"], 0.0, 1.65])
+    rng = np.random.default_rng([c["seed"], s])   # scan s is reproducible on its own
+    zmax = c["zmax"]
+    dirs_u, norms = c["dirs_u"], c["norms"]
+    ws = c["world"].near(origin, zmax * 1.5)
+    t, cl = [], []
+    for i in range(0, dirs_u.shape[0], 1 << 16):
+        ti, ci = ws.cast(origin, dirs_u[i:i + (1 << 16)], tmax=zmax * 1.5)
+        t.append(ti)
+        cl.append(ci)
+    t = np.concatenate(t)
+    cl = np.concatenate(cl)
+    with np.errstate(invalid="ignore"):
+        z = t / norms                      # depth along the optical axis
+        z = z + rng.normal(0.0, 1.0, size=z.shape) * 5e-4 * z * z
+    keep = np.isfinite(z) & (z > 0.5) & (z <= zmax) & (cl >= 0)
+    p = origin + (z[keep] * norms[keep])[:, None] * dirs_u[keep]
+    lab = _flip_labels(rng, cl[keep].astype(np.int32), c["flip"], 1, 10)
+    return Scan(_f32(p), lab, _f32(origin))
+
+
 def stereo_sequence_scene(seed: int = 2, n_scans: int = 100, width: int = 1242,
                           height: int = 375, focal: float = 720.0, zmax: float = 25.0,
-                          step: float = 1.0, flip: float = 0.10) -> Scene:
+                          step: float = 1.0, flip: float = 0.10, first: int = None,
+                          workers: int = 1) -> Scene:
     """Stereo-shaped dense scans along a street, one persistent map.
 
     Pinhole camera width x height, focal length `focal` px, centred principal
     point, 1.65 m high, looking along +x; depth from ray casting with noise
     sigma_z = 5e-4 z^2 (growing quadratically with depth), cut at 25 m;
     10 occupied classes + free (K = 11); `n_scans` poses 1 m apart along +x;
-    0.1 m voxels, l = 0.3, sigma0 = 0.1, free step 0.3 m.
+    0.1 m voxels, l = 0.3, sigma0 = 0.1, free step 0.3 m.  Only the first
+    `first` scans of the sequence are generated when it is given (each scan has
+    its own seeded generator, so they equal those of the whole sequence);
+    `workers` > 1 casts scans in forked worker processes.
     """
     rng = np.random.default_rng(seed)
     w = _street_world(rng, length=max(120.0, n_scans * step + 60.0), n_classes=10)
@@ -400,27 +430,20 @@ def stereo_sequence_scene(seed: int = 2, n_scans: int = 100, width: int = 1242,
     # camera frame (x right, y down, z forward) -> world (x forward, y left, z up)
     dirs = np.stack([cam[:, 2], -cam[:, 0], -cam[:, 1]], axis=1)
     norms = np.linalg.norm(dirs, axis=1)
-    dirs_u = dirs / norms[:, None]
-    scans = []
-    for s in range(n_scans):
-        origin = np.array([-0.5 * n_scans * step + s * step, 0.0, 1.65])
-        t, c = [], []
-        ws = w.near(origin, zmax * 1.5)
-        for i in range(0, dirs_u.shape[0], 1 << 16):
-            ti, ci = ws.cast(origin, dirs_u[i:i + (1 << 16)], tmax=zmax * 1.5)
-            t.append(ti)
-            c.append(ci)
-        t = np.concatenate(t)
-        c = np.concatenate(c)
-        z = t / norms                      # depth along the optical axis
-        z = z + rng.normal(0.0, 1.0, size=z.shape) * 5e-4 * z * z
-        keep = np.isfinite(z) & (z > 0.5) & (z <= zmax) & (c >= 0)
-        p = origin + (z[keep] * norms[keep])[:, None] * dirs_u[keep]
-        lab = _flip_labels(rng, c[keep].astype(np.int32), flip, 1, 10)
-        scans.append(Scan(_f32(p), lab, _f32(origin)))
+    _STEREO.clear()
+    _STEREO.update(world=w, dirs_u=dirs / norms[:, None], norms=norms, zmax=zmax, step=step,
+                   x0=-0.5 * n_scans * step, seed=seed, flip=flip)
+    todo = list(range(n_scans if first is None else min(first, n_scans)))
+    if workers > 1 and len(todo) > 1:
+        import multiprocessing as mp
+        with mp.get_context("fork").Pool(min(workers, len(todo))) as pool:
+            scans = pool.map(_stereo_scan, todo, chunksize=1)
+    else:
+        scans = [_stereo_scan(s) for s in todo]
+    _STEREO.clear()
     params = Params(res=0.1, block_size=8, l=0.3, sigma0=0.1, alpha0=0.001, K=11,
                     free_class=0, free_step=0.3)
-    return Scene("stereo", params, scans, info={"seed": seed})
+    return Scene("stereo", params, scans, info={"seed": seed, "n_scans": n_scans})
 
 
 def _town_world(rng, size=200.0, height=10.0):
