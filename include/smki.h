@@ -314,6 +314,28 @@ smki_status smki_loss_backward_classes(const float *train_xyz, const int32_t *tr
                                        const float *grad_loss, float *grad_l, float *grad_sigma0,
                                        float *grad_train_xyz, float *grad_query_xyz);
 
+/*
+ * smki_loss_forward without any allocation, for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving loops, harnesses
+ * that forbid hipMalloc).  Arguments and results are those of
+ * smki_loss_forward; the workspace is a fixed device array inside the library
+ * (SMKI_LOSS_NOALLOC_BYTES, 64 MiB; each device the library runs on holds its
+ * own copy until the process ends), so the call allocates nothing.  The
+ * device current at the call must be the device of hip_stream.  Inputs whose
+ * workspace would exceed SMKI_LOSS_NOALLOC_BYTES return SMKI_E_CAPACITY
+ * (roughly above 5e5 training rows, or a sparse set spanning a large box).
+ * Every call on one device shares that device's array: calls that overlap on
+ * one device (several host threads or streams) race and must be serialised
+ * by the caller.  Synchronises hip_stream once (to size the grid), like
+ * smki_loss_forward.
+ */
+#define SMKI_LOSS_NOALLOC_BYTES ((size_t)64 << 20)
+smki_status smki_loss_forward_noalloc(const float *train_xyz, const int32_t *train_label,
+                                      int64_t n_train, const float *query_xyz,
+                                      const int32_t *query_label, int64_t n_query, float l,
+                                      float sigma0, float alpha0, int32_t K, void *hip_stream,
+                                      float *loss, float *alpha_q);
+
 #ifdef __cplusplus
 }
 #endif

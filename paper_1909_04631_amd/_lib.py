@@ -22,7 +22,7 @@ EXPORTED = [
     "smki_set_stream", "smki_insert_scan", "smki_insert_scan_soft", "smki_insert_scans",
     "smki_query", "smki_num_blocks", "smki_export", "smki_import", "smki_kernel_times", "smki_last_scan_stats", "smki_sync", "smki_free_samples", "smki_bucket_cells",
     "smki_loss_workspace_bytes", "smki_loss_forward", "smki_loss_backward",
-    "smki_loss_forward_classes", "smki_loss_backward_classes",
+    "smki_loss_forward_classes", "smki_loss_backward_classes", "smki_loss_forward_noalloc",
 ]
 
 
@@ -125,6 +125,8 @@ def lib():
     L.smki_loss_backward_classes.restype = st
     L.smki_loss_backward_classes.argtypes = [vp, vp, i64, vp, vp, i64, fp, fp, f, i32, vp, vp,
                                              C.c_size_t, vp, vp, vp, vp, vp, vp]
+    L.smki_loss_forward_noalloc.restype = st
+    L.smki_loss_forward_noalloc.argtypes = [vp, vp, i64, vp, vp, i64, f, f, f, i32, vp, vp, vp]
     _lib = L
     return L
 

@@ -17,6 +17,7 @@
 // in a fixed order (deterministic, no floating-point atomics).
 #include <algorithm>
 #include <cmath>
+#include <mutex>
 
 #include "smki_gather.h"
 #include "../../include/smki.h"
@@ -723,4 +724,59 @@ extern "C" smki_status smki_loss_backward_classes(
   }
   release(own, st);
   return rc;
+}
+
+// ---------------------------------------------------------------------------
+// the predictive loss without any allocation: a fixed device array as workspace
+// ---------------------------------------------------------------------------
+namespace {
+
+// Workspace of smki_loss_forward_noalloc.  Each device the library runs on
+// holds its own copy until the process ends.  Host code never passes this
+// name to a kernel or a copy: it stands in for the array on the host side;
+// the device address comes from hipGetSymbolAddress (static_scratch below).
+constexpr size_t kStaticScratchBytes = SMKI_LOSS_NOALLOC_BYTES;
+static __device__ __align__(256) char scratch[kStaticScratchBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+char* g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of the current device's copy of `scratch`, looked up once per
+// device (with that device current) and kept.
+smki_status static_scratch(char** out) {
+  int dev = -1;
+  SMKI_HIP_TRY(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxDevices) return SMKI_E_DEVICE;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    SMKI_HIP_TRY(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    if (!p) return SMKI_E_DEVICE;
+    g_scratch_ptr[dev] = (char*)p;
+  }
+  *out = g_scratch_ptr[dev];
+  return SMKI_OK;
+}
+
+}  // namespace
+
+extern "C" smki_status smki_loss_forward_noalloc(const float* txyz, const int32_t* tlab,
+                                                 int64_t nt, const float* qxyz,
+                                                 const int32_t* qlab, int64_t nq, float l,
+                                                 float sigma0, float alpha0, int32_t K,
+                                                 void* hip_stream, float* loss, float* alpha_q) {
+  if (bad_params(nt, nq, l, sigma0, alpha0, K) || !qxyz || !qlab || !loss ||
+      (nt > 0 && (!txyz || !tlab)))
+    return SMKI_E_INVALID_ARG;
+  // the buffers that do not depend on the grid must fit before anything runs;
+  // the grid-dependent tables are checked once the grid is known
+  LossBufs b0{};
+  if (kHdr + 2 * kAl + carve_body(nullptr, b0, nt, nq, K, 1) > kStaticScratchBytes)
+    return SMKI_E_CAPACITY;
+  char* ws = nullptr;
+  const smki_status rc = static_scratch(&ws);
+  if (rc != SMKI_OK) return rc;
+  return smki_loss_forward(txyz, tlab, nt, qxyz, qlab, nq, l, sigma0, alpha0, K, hip_stream, ws,
+                           kStaticScratchBytes, loss, alpha_q);
 }
