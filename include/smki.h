@@ -41,6 +41,7 @@ typedef int32_t smki_status;
 #define SMKI_E_RANGE (-6)        /* voxel index outside [-2^20, 2^20) or beam too long */
 
 typedef struct smki_map smki_map;
+typedef struct smki_batch smki_batch;   /* a recorded batched insert (smki_batch_capture) */
 
 /* Map update model (smki_options.model). */
 #define SMKI_MODEL_SBKI 0  /* Bayesian spatial kernel inference, Sec. IV, Eq. (7)-(8) */
@@ -189,6 +190,39 @@ smki_status smki_insert_scan_soft(smki_map *m, const float *xyz, const float *pr
 smki_status smki_insert_scans(smki_map *m, const float *xyz, const int32_t *label,
                               const int64_t *offsets, const float *origins, int32_t S,
                               float free_step);
+
+/*
+ * Batched insert recorded as one HIP graph and replayed without any host
+ * synchronisation (Eq. (7) is additive over training rows, Sec. IV's recursive
+ * update, so S scans go in one pass as in smki_insert_scans).
+ *
+ * smki_batch_capture performs smki_insert_scans(m, xyz, label, offsets,
+ * origins, S, free_step) -- an ordinary insert, which updates the map and
+ * synchronises -- and then records the same insert for the same device buffers
+ * xyz / label, the same n = offsets[S], S and free_step into a graph in which
+ * every launch reads its counts from device memory.  Capacities are that
+ * insert's sizes grown by `margin` (0..16, e.g. 0.25): training rows, work
+ * units, the voxel box (grown by margin of its extent on every side), and room
+ * in the map's pools for that insert's new blocks once more.  S-BKI maps only.
+ *
+ * smki_batch_replay launches the graph on the map's stream: the insert of what
+ * xyz / label hold at the time it runs, with these scan offsets (host int64
+ * [S+1], offsets[S] = the captured n) and origins (host float32 [S][3]).  It
+ * returns once the graph is enqueued (it waits only for the previous replay of
+ * the same batch to finish).  A replay whose data needs more than the captured
+ * capacities, or whose rows leave the captured voxel box, writes nothing to
+ * the map; its error (SMKI_E_CAPACITY, SMKI_E_RANGE, SMKI_E_BAD_INPUT) is
+ * reported by the next smki_sync.  A replay returns SMKI_E_CAPACITY at once
+ * when the map's storage moved since the capture (an ordinary insert or an
+ * import grew it; smki_set_class_params also invalidates the recording):
+ * capture again.  smki_last_scan_stats reports the replay's counters (times
+ * are not recorded).  Destroy batches before their map.
+ */
+smki_status smki_batch_capture(smki_map *m, const float *xyz, const int32_t *label,
+                               const int64_t *offsets, const float *origins, int32_t S,
+                               float free_step, float margin, smki_batch **out);
+smki_status smki_batch_replay(smki_batch *b, const int64_t *offsets, const float *origins);
+smki_status smki_batch_destroy(smki_batch *b);
 
 /*
  * Read voxels (Sec. III, Eq. (3)-(4), reused for S-BKI in Sec. IV):

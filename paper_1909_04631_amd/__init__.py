@@ -43,6 +43,42 @@ def _f3(v):
     return a
 
 
+def _scan_tables(offsets, origins):
+    offs = [int(o) for o in offsets]
+    S = len(offs) - 1
+    org = [float(v) for o in origins for v in o]
+    if len(org) != 3 * S:
+        raise ValueError("origins must hold one (x, y, z) per scan")
+    return (C.c_int64 * (S + 1))(*offs), (C.c_float * (3 * S))(*org), S
+
+
+class Batch:
+    """A batched insert recorded as one HIP graph (smki_batch_capture).  The
+    tensors it was captured with stay referenced; replay() inserts their
+    current contents with the given scan offsets and origins, asynchronously."""
+
+    def __init__(self, m, h, keep, S):
+        self._m, self._h, self._keep, self.S = m, h, keep, S
+
+    def replay(self, offsets, origins):
+        offs, org, S = _scan_tables(offsets, origins)
+        if S != self.S:
+            raise ValueError(f"the batch was captured for {self.S} scans")
+        self._m._bind_stream()
+        check(lib().smki_batch_replay(self._h, offs, org), "smki_batch_replay")
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().smki_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
 class SemanticMap:
     """A persistent semantic occupancy map on one GPU (the device current at creation)."""
 
@@ -118,15 +154,24 @@ class SemanticMap:
     def insert_scans(self, xyz, label, offsets, origins, free_step):
         xyz = _dev_tensor(xyz, torch.float32, (3,), "xyz")
         label = _dev_tensor(label, torch.int32, (), "label")
-        offs = [int(o) for o in offsets]
-        S = len(offs) - 1
-        org = [float(v) for o in origins for v in o]
-        if len(org) != 3 * S:
-            raise ValueError("origins must hold one (x, y, z) per scan")
+        offs, org, S = _scan_tables(offsets, origins)
         self._bind_stream()
-        check(lib().smki_insert_scans(self._h, _ptr(xyz), _ptr(label), (C.c_int64 * (S + 1))(*offs),
-                                      (C.c_float * (3 * S))(*org), S, float(free_step)),
-              "smki_insert_scans")
+        check(lib().smki_insert_scans(self._h, _ptr(xyz), _ptr(label), offs, org, S,
+                                      float(free_step)), "smki_insert_scans")
+
+    def batch_capture(self, xyz, label, offsets, origins, free_step, margin=0.25):
+        """Insert S scans (as insert_scans) and record that insert as a HIP graph
+        for these tensors; returns a Batch whose replay() inserts what the
+        tensors hold then (see smki_batch_capture)."""
+        xyz = _dev_tensor(xyz, torch.float32, (3,), "xyz")
+        label = _dev_tensor(label, torch.int32, (), "label")
+        offs, org, S = _scan_tables(offsets, origins)
+        self._bind_stream()
+        h = C.c_void_p()
+        check(lib().smki_batch_capture(self._h, _ptr(xyz), _ptr(label), offs, org, S,
+                                       float(free_step), float(margin), C.byref(h)),
+              "smki_batch_capture")
+        return Batch(self, h, (xyz, label), S)
 
     def query(self, ijk, alpha=True, mean=True, var=True, label=True, p_occ=True):
         ijk = _dev_tensor(ijk, torch.int32, (3,), "ijk")

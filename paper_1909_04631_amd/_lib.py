@@ -23,6 +23,7 @@ EXPORTED = [
     "smki_query", "smki_num_blocks", "smki_export", "smki_import", "smki_kernel_times", "smki_last_scan_stats", "smki_sync", "smki_free_samples", "smki_bucket_cells",
     "smki_loss_workspace_bytes", "smki_loss_forward", "smki_loss_backward",
     "smki_loss_forward_classes", "smki_loss_backward_classes", "smki_loss_forward_noalloc",
+    "smki_batch_capture", "smki_batch_replay", "smki_batch_destroy",
 ]
 
 
@@ -125,6 +126,13 @@ def lib():
     L.smki_loss_backward_classes.restype = st
     L.smki_loss_backward_classes.argtypes = [vp, vp, i64, vp, vp, i64, fp, fp, f, i32, vp, vp,
                                              C.c_size_t, vp, vp, vp, vp, vp, vp]
+    L.smki_batch_capture.restype = st
+    L.smki_batch_capture.argtypes = [vp, vp, vp, C.POINTER(C.c_int64), C.POINTER(C.c_float), i32,
+                                     f, f, C.POINTER(vp)]
+    L.smki_batch_replay.restype = st
+    L.smki_batch_replay.argtypes = [vp, C.POINTER(C.c_int64), C.POINTER(C.c_float)]
+    L.smki_batch_destroy.restype = st
+    L.smki_batch_destroy.argtypes = [vp]
     L.smki_loss_forward_noalloc.restype = st
     L.smki_loss_forward_noalloc.argtypes = [vp, vp, i64, vp, vp, i64, f, f, f, i32, vp, vp, vp]
     _lib = L

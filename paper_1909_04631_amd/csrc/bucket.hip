@@ -209,18 +209,23 @@ __device__ __forceinline__ bool in_grid(const BucketGeom& g, const int32_t b[3])
 // kernel (workgroups of FREE_WG samples): wgbeam[b] = the beam that holds free
 // sample b FREE_WG (each such sample lies in exactly one beam's range).
 constexpr int FREE_WG = 256;
+// dcnt (device, nullable): row counts [total, hits, free samples] of the
+// insert, read here instead of nf (a capacity then).
 template <typename KeyT>
 __global__ void k_hit_keys(const float* __restrict__ xyz, const int32_t* __restrict__ label,
                            const float* __restrict__ probs, int32_t K, int64_t n,
                            const int32_t* __restrict__ kept, const int32_t* __restrict__ kpos,
-                           const int64_t* __restrict__ off, int64_t nf,
+                           const int64_t* __restrict__ off, int64_t nf_cap,
+                           const int64_t* __restrict__ dcnt,
                            int32_t* __restrict__ wgbeam, BucketGeom g, KeyT* __restrict__ keys,
                            float4* __restrict__ rec,
                            float* __restrict__ wt, uint32_t* __restrict__ err) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
+  const int64_t nf = dcnt ? dcnt[2] : nf_cap;
   if (nf > 0) {
-    const int64_t a0 = off[i], a1 = i + 1 < n ? off[i + 1] : nf;
+    // (clamped: a captured insert may hold fewer samples than its beams ask for)
+    const int64_t a0 = min(off[i], nf), a1 = min(i + 1 < n ? off[i + 1] : nf, nf);
     for (int64_t b = (a0 + FREE_WG - 1) / FREE_WG; b * FREE_WG < a1; ++b) wgbeam[b] = (int32_t)i;
   }
   if (!kept[i]) return;
@@ -259,19 +264,23 @@ __global__ void k_hit_keys(const float* __restrict__ xyz, const int32_t* __restr
 // Free sample f -> its beam (largest i with off[i] <= f), its position, key and record.
 template <typename KeyT>
 __global__ void k_free_keys(const float* __restrict__ xyz, int64_t n,
-                            const int64_t* __restrict__ off, int64_t nf,
+                            const int64_t* __restrict__ off, int64_t nf_cap,
+                            const int64_t* __restrict__ dcnt,
                             const int64_t* __restrict__ scan_off,
                             const float* __restrict__ origins, int32_t S, float step,
-                            int32_t free_class, BucketGeom g, int64_t out_base,
+                            int32_t free_class, BucketGeom g, int64_t out_base_h,
                             KeyT* __restrict__ keys, float4* __restrict__ rec, float* __restrict__ wrow,
                             const int32_t* __restrict__ wgbeam, uint32_t* __restrict__ err) {
   // The beams of this workgroup's samples lie between the beam of its first
   // sample and the beam of the next workgroup's first sample (wgbeam, written
   // by k_hit_keys); every sample searches only between them.
+  const int64_t nf = dcnt ? dcnt[2] : nf_cap;             // (launch sized for nf_cap)
+  const int64_t out_base = dcnt ? dcnt[1] : out_base_h;   // free samples follow the hits
+  const int64_t nwg = (nf + FREE_WG - 1) / FREE_WG;
   const int64_t f = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (f >= nf) return;
   int64_t lo = wgbeam[blockIdx.x];
-  int64_t hi = blockIdx.x + 1 < gridDim.x ? wgbeam[blockIdx.x + 1] : n - 1;
+  int64_t hi = (int64_t)blockIdx.x + 1 < nwg ? wgbeam[blockIdx.x + 1] : n - 1;
   while (lo < hi) {
     const int64_t mid = (lo + hi + 1) >> 1;
     if (off[mid] <= f) lo = mid; else hi = mid - 1;
@@ -354,14 +363,18 @@ constexpr int HT = HT_THREADS * HT_ROUNDS;     // rows per tile
 template <typename KeyT>
 __device__ __forceinline__ bool heads_slot(const KeyT* __restrict__ keys, int64_t i, int64_t n,
                                            int shift) {
+  // (n is the row count; launches past it see no heads)
   if (i >= n) return false;
   return i == 0 || (uint64_t)(keys[i] >> shift) != (uint64_t)(keys[i - 1] >> shift);
 }
 
 template <typename KeyT>
 __global__ void __launch_bounds__(HT_THREADS) k_head_counts(const KeyT* __restrict__ keys,
-                                                            int64_t n, int shift,
+                                                            int64_t ncap,
+                                                            const int64_t* __restrict__ dn,
+                                                            int shift,
                                                             int32_t* __restrict__ tcount) {
+  const int64_t n = eff_n(ncap, dn);
   __shared__ int32_t wc[HT_THREADS / SMKI_WAVE];
   const int lane = threadIdx.x & (SMKI_WAVE - 1), w = threadIdx.x / SMKI_WAVE;
   const int64_t base = (int64_t)blockIdx.x * HT + (int64_t)w * HS + lane;
@@ -384,13 +397,16 @@ __global__ void __launch_bounds__(HT_THREADS) k_head_counts(const KeyT* __restri
 // so the classes of one block share a cache line.
 template <typename KeyT>
 __global__ void __launch_bounds__(HT_THREADS) k_slot_heads(const KeyT* __restrict__ keys,
-                                                           int64_t n, int log2B3, int64_t n_blocks,
+                                                           int64_t ncap,
+                                                           const int64_t* __restrict__ dn,
+                                                           int log2B3, int64_t n_blocks,
                                                            int32_t planes,
                                                            const int32_t* __restrict__ tstart,
                                                            int32_t* __restrict__ dense,
                                                            int32_t* __restrict__ slot_lin,
                                                            int32_t* __restrict__ head,
                                                            const int32_t* __restrict__ d_nslots) {
+  const int64_t n = eff_n(ncap, dn);
   __shared__ int32_t wc[HT_THREADS / SMKI_WAVE];
   const int lane = threadIdx.x & (SMKI_WAVE - 1), w = threadIdx.x / SMKI_WAVE;
   const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (SMKI_WAVE - lane));
@@ -527,26 +543,28 @@ hipError_t launch_fill_i32(int32_t* p, int64_t n, int32_t v, hipStream_t st) {
 template <typename KeyT>
 // idx_iota: idx was not written (row i's value is i): the first radix pass
 // takes the indices itself.
+// dn (device, nullable): the row count; ps.n is then the capacity.
 static hipError_t finish_set(PointSet& ps, KeyT* keys, uint32_t* idx, KeyT* akeys, uint32_t* aidx,
                              float4* rec_unsorted, const BucketGeom& g, int key_bits,
-                             BucketScratch& scr, hipStream_t st, bool idx_iota = false) {
+                             BucketScratch& scr, hipStream_t st, bool idx_iota = false,
+                             const int64_t* dn = nullptr) {
   const int64_t n = ps.n;
   if (n <= 0) return hipSuccess;
   hipError_t e;
-  if (idx_iota && n == 1) {   // no radix pass: the single index by hand
+  if (idx_iota && n == 1 && !dn) {   // no radix pass: the single index by hand
     e = hipMemsetAsync(idx, 0, sizeof(uint32_t), st);
     if (e != hipSuccess) return e;
   }
   // the last radix pass gathers the records (and weights) into sorted order,
   // if the set keeps sorted records; else they are read through the permutation
   const SortPayload pl{rec_unsorted, ps.pts, scr.wt, ps.wts};
-  const SortPayload* plp = (n > 1 && ps.pts) ? &pl : nullptr;
+  const SortPayload* plp = (n > 1 && ps.pts && !dn) ? &pl : nullptr;
   if (sizeof(KeyT) == 4)
     e = radix_sort_u32((uint32_t*)keys, idx, (uint32_t*)akeys, aidx, n, key_bits, scr.sort_tmp, st,
-                       plp, idx_iota);
+                       plp, idx_iota, dn);
   else
     e = radix_sort_u64((uint64_t*)keys, idx, (uint64_t*)akeys, aidx, n, key_bits, scr.sort_tmp, st,
-                       plp, idx_iota);
+                       plp, idx_iota, dn);
   if (e != hipSuccess) return e;
   if (!plp && ps.pts)
     hipLaunchKernelGGL(k_permute_rec, dim3(nblk(n, 256)), dim3(256), 0, st, rec_unsorted,
@@ -556,13 +574,14 @@ static hipError_t finish_set(PointSet& ps, KeyT* keys, uint32_t* idx, KeyT* akey
   // slot heads: per-tile counts (in scr.flag), their scan (scr.slot_excl), numbering
   const int64_t ntiles = ceil_div_i64(n, HT);
   hipLaunchKernelGGL(k_head_counts<KeyT>, dim3((unsigned)ntiles), dim3(HT_THREADS), 0, st, keys, n,
-                     log2B3, scr.flag);
+                     dn, log2B3, scr.flag);
   e = scan_excl_i32(scr.flag, scr.slot_excl, ntiles, ps.d_nslots, scr.scan_tmp, st);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_slot_heads<KeyT>, dim3((unsigned)ntiles), dim3(HT_THREADS), 0, st, keys, n,
-                     log2B3, g.n_blocks, g.planes, scr.slot_excl, ps.dense, ps.slot_lin, ps.head,
-                     ps.d_nslots);
+                     dn, log2B3, g.n_blocks, g.planes, scr.slot_excl, ps.dense, ps.slot_lin,
+                     ps.head, ps.d_nslots);
   if (!ps.prefix) return hipGetLastError();
+  if (dn) return hipErrorInvalidValue;   // (per-cell tables are built for host counts only)
   const unsigned grid = (unsigned)std::min<int64_t>(n, 8192);
   switch (log2B3) {
     case 6:
@@ -585,16 +604,18 @@ static hipError_t bucket_scan_t(const float* xyz, const int32_t* label, const fl
                                 int64_t nk, const int64_t* off, int64_t nf, int32_t* wgbeam,
                                 const int64_t* scan_off, const float* origins, int32_t S,
                                 float step, int32_t free_class, const BucketGeom& g, PointSet& ps,
-                                BucketScratch& scr, uint32_t* err, hipStream_t st) {
-  if (nk > 0)
+                                BucketScratch& scr, uint32_t* err, hipStream_t st,
+                                const int64_t* dcnt) {
+  if (nk > 0 || dcnt)
     hipLaunchKernelGGL(k_hit_keys<KeyT>, dim3(nblk(n, 256)), dim3(256), 0, st, xyz, label, probs,
-                       K, n, kept, kpos, off, nf, wgbeam, g, (KeyT*)scr.keys, scr.rec, scr.wt, err);
+                       K, n, kept, kpos, off, nf, dcnt, wgbeam, g, (KeyT*)scr.keys, scr.rec,
+                       scr.wt, err);
   if (nf > 0)
     hipLaunchKernelGGL(k_free_keys<KeyT>, dim3(nblk(nf, FREE_WG)), dim3(FREE_WG), 0, st, xyz, n,
-                       off, nf, scan_off, origins, S, step, free_class, g, nk, (KeyT*)scr.keys,
-                       scr.rec, scr.wt, (const int32_t*)wgbeam, err);
+                       off, nf, dcnt, scan_off, origins, S, step, free_class, g, nk,
+                       (KeyT*)scr.keys, scr.rec, scr.wt, (const int32_t*)wgbeam, err);
   return finish_set<KeyT>(ps, (KeyT*)scr.keys, scr.idx, (KeyT*)scr.akeys, scr.aidx, scr.rec, g,
-                          g.key_bits, scr, st, true);
+                          g.key_bits, scr, st, true, dcnt);
 }
 
 // All training rows of an insert in one sorted set: kept hits at [0, nk), free
@@ -605,13 +626,15 @@ hipError_t bucket_scan(const float* xyz, const int32_t* label, const float* prob
                        const int64_t* off, int64_t nf, int32_t* wgbeam, const int64_t* scan_off,
                        const float* origins, int32_t S, float step, int32_t free_class,
                        const BucketGeom& g, PointSet& ps, BucketScratch& scr, uint32_t* err,
-                       hipStream_t st) {
+                       hipStream_t st, const int64_t* dcnt) {
   if (ps.n <= 0) return hipSuccess;
   if (g.key_bits <= 32)
     return bucket_scan_t<uint32_t>(xyz, label, probs, K, n, kept, kpos, nk, off, nf, wgbeam,
-                                   scan_off, origins, S, step, free_class, g, ps, scr, err, st);
+                                   scan_off, origins, S, step, free_class, g, ps, scr, err, st,
+                                   dcnt);
   return bucket_scan_t<uint64_t>(xyz, label, probs, K, n, kept, kpos, nk, off, nf, wgbeam,
-                                 scan_off, origins, S, step, free_class, g, ps, scr, err, st);
+                                 scan_off, origins, S, step, free_class, g, ps, scr, err, st,
+                                 dcnt);
 }
 
 int64_t free_sample_workgroups(int64_t nf) { return nf > 0 ? ceil_div_i64(nf, FREE_WG) : 1; }

@@ -194,7 +194,101 @@ __global__ void k_iota(uint32_t* p, int64_t n) {
   if (i < n) p[i] = (uint32_t)i;
 }
 
+// ---------------------------------------------------------------------------
+// captured inserts: device-side counts and checks (single small workgroups)
+// ---------------------------------------------------------------------------
+__global__ void k_batch_start(const int64_t* __restrict__ hdr, int64_t* __restrict__ counts,
+                              unsigned long long* __restrict__ stats) {
+  if (threadIdx.x == 0 && hdr[0]) {
+    counts[0] = hdr[1];
+    counts[1] = hdr[2];
+  }
+  for (int i = threadIdx.x; i < 4 * SMKI_STAT_COPIES; i += blockDim.x) stats[i] = 0ull;
+}
+
+__global__ void k_batch_rows(const int64_t* __restrict__ sc, int64_t cap_rows,
+                             int64_t* __restrict__ pc, uint32_t* __restrict__ err) {
+  const int64_t nf = sc[0];
+  const int64_t nk = (int64_t)((const int32_t*)(sc + 1))[0];
+  int64_t nt = nk + nf;
+  if (nt > cap_rows) {
+    atomicOr(err, DEVERR_CAPACITY);
+    nt = cap_rows;   // (hit rows never exceed cap_rows: it is at least the hits)
+  }
+  pc[0] = nt;
+  pc[1] = nk;
+  pc[2] = nt - nk;
+}
+
+__global__ void k_batch_units(const int32_t* __restrict__ d_nunits, int64_t cap_units,
+                              uint32_t* __restrict__ err) {
+  if (*d_nunits > cap_units) atomicOr(err, DEVERR_CAPACITY);
+}
+
+__global__ void k_batch_alloc_check(const int32_t* __restrict__ cnt,
+                                    const int64_t* __restrict__ counts, int64_t pool_cap,
+                                    int64_t cpool_cap, int64_t hcap, uint32_t* __restrict__ err) {
+  const int64_t nb = counts[0] + cnt[0], nc = counts[1] + cnt[1];
+  if (nb > pool_cap || nc > cpool_cap || 2 * nb > hcap) atomicOr(err, DEVERR_CAPACITY);
+}
+
+__global__ void k_batch_commit(const int32_t* __restrict__ cnt, int64_t* __restrict__ counts,
+                               const uint32_t* __restrict__ err, uint32_t* __restrict__ map_err,
+                               const int64_t* __restrict__ pc, const int32_t* __restrict__ si,
+                               int64_t* __restrict__ out) {
+  const uint32_t e = *err;
+  if (e == 0) {
+    counts[0] += cnt[0];
+    counts[1] += cnt[1];
+  } else {
+    atomicOr(map_err, e);
+  }
+  out[0] = e;
+  out[1] = e ? 0 : cnt[0];
+  out[2] = e ? 0 : cnt[1];
+  out[3] = pc[0];
+  out[4] = pc[1];
+  out[5] = pc[2];
+  out[6] = si[0];
+  out[7] = si[1];
+  out[8] = si[2];
+}
+
 }  // namespace
+
+hipError_t launch_batch_start(const int64_t* hdr, int64_t* counts, unsigned long long* stats,
+                              hipStream_t st) {
+  hipLaunchKernelGGL(k_batch_start, dim3(1), dim3(256), 0, st, hdr, counts, stats);
+  return hipGetLastError();
+}
+
+hipError_t launch_batch_rows(const int64_t* sc, int64_t cap_rows, int64_t* pc, uint32_t* err,
+                             hipStream_t st) {
+  hipLaunchKernelGGL(k_batch_rows, dim3(1), dim3(1), 0, st, sc, cap_rows, pc, err);
+  return hipGetLastError();
+}
+
+hipError_t launch_batch_units(const int32_t* d_nunits, int64_t cap_units, uint32_t* err,
+                              hipStream_t st) {
+  hipLaunchKernelGGL(k_batch_units, dim3(1), dim3(1), 0, st, d_nunits, cap_units, err);
+  return hipGetLastError();
+}
+
+hipError_t launch_batch_alloc_check(const int32_t* cnt, const int64_t* counts, int64_t pool_cap,
+                                    int64_t cpool_cap, int64_t hcap, uint32_t* err,
+                                    hipStream_t st) {
+  hipLaunchKernelGGL(k_batch_alloc_check, dim3(1), dim3(1), 0, st, cnt, counts, pool_cap,
+                     cpool_cap, hcap, err);
+  return hipGetLastError();
+}
+
+hipError_t launch_batch_commit(const int32_t* cnt, int64_t* counts, const uint32_t* err,
+                               uint32_t* map_err, const int64_t* pc, const int32_t* si,
+                               int64_t* out, hipStream_t st) {
+  hipLaunchKernelGGL(k_batch_commit, dim3(1), dim3(1), 0, st, cnt, counts, err, map_err, pc, si,
+                     out);
+  return hipGetLastError();
+}
 
 hipError_t launch_query(const MapDev& m, const int32_t* ijk, int64_t M, float* alpha, float* mean,
                         float* var, int32_t* label, float* p_occ, int32_t free_class,

@@ -49,9 +49,11 @@ __device__ __forceinline__ int64_t elem_index(int64_t tile_base, int w, int r, i
 // of one wavefront with equal digits neither hit one address nor one bank;
 // the copies are summed at the end.
 template <typename K, int NB>
-__global__ void __launch_bounds__(RS_THREADS) k_hist(const K* __restrict__ keys, int64_t n,
-                                                     int shift, int dbits, int64_t ntiles,
+__global__ void __launch_bounds__(RS_THREADS) k_hist(const K* __restrict__ keys, int64_t ncap,
+                                                     const int64_t* __restrict__ dn, int shift,
+                                                     int dbits, int64_t ntiles,
                                                      uint32_t* __restrict__ hist) {
+  const int64_t n = eff_n(ncap, dn);   // tiles past the count contribute zero counts
   constexpr int NC = 16;         // counter copies
   constexpr int STR = NB + 1;    // padded row of one copy
   constexpr int DPT = NB / RS_THREADS;   // digits per thread
@@ -171,11 +173,14 @@ template <typename K, int NB>
 __global__ void __launch_bounds__(RS_THREADS) k_scatter(const K* __restrict__ keys,
                                                         const uint32_t* __restrict__ vals,
                                                         K* __restrict__ okeys,
-                                                        uint32_t* __restrict__ ovals, int64_t n,
-                                                        int shift, int dbits, int64_t ntiles,
+                                                        uint32_t* __restrict__ ovals, int64_t ncap,
+                                                        const int64_t* __restrict__ dn, int shift,
+                                                        int dbits, int64_t ntiles,
                                                         const uint32_t* __restrict__ offs,
                                                         const uint32_t* __restrict__ total,
                                                         SortPayload pl, int vals_iota) {
+  const int64_t n = eff_n(ncap, dn);
+  if ((int64_t)blockIdx.x * RS_TILE >= n) return;   // a tile past the count (capacity launch)
   constexpr int DPT = NB / RS_THREADS;   // digits per thread: tid * DPT + j
   __shared__ uint32_t gbase[NB];    // first global position of the tile's digit-d elements
   __shared__ uint32_t lstart[NB];   // first index of digit d inside the tile
@@ -300,22 +305,26 @@ __global__ void __launch_bounds__(RS_THREADS) k_scatter(const K* __restrict__ ke
 }
 
 template <typename K, int NB>
-void launch_pass(const K* sk, const uint32_t* sv, K* dk, uint32_t* dv, int64_t n, int shift,
-                 int dbits, int64_t ntiles, uint32_t* hist, uint32_t* total, const SortPayload& pl,
-                 int vals_iota, hipStream_t st) {
-  hipLaunchKernelGGL((k_hist<K, NB>), dim3((unsigned)ntiles), dim3(RS_THREADS), 0, st, sk, n,
+void launch_pass(const K* sk, const uint32_t* sv, K* dk, uint32_t* dv, int64_t n,
+                 const int64_t* dn, int shift, int dbits, int64_t ntiles, uint32_t* hist,
+                 uint32_t* total, const SortPayload& pl, int vals_iota, hipStream_t st) {
+  hipLaunchKernelGGL((k_hist<K, NB>), dim3((unsigned)ntiles), dim3(RS_THREADS), 0, st, sk, n, dn,
                      shift, dbits, ntiles, hist);
   hipLaunchKernelGGL(k_digit_scan, dim3(1u << dbits), dim3(RS_THREADS), 0, st, hist, ntiles,
                      total);
   hipLaunchKernelGGL((k_scatter<K, NB>), dim3((unsigned)ntiles), dim3(RS_THREADS), 0, st, sk, sv,
-                     dk, dv, n, shift, dbits, ntiles, (const uint32_t*)hist,
+                     dk, dv, n, dn, shift, dbits, ntiles, (const uint32_t*)hist,
                      (const uint32_t*)total, pl, vals_iota);
 }
 
 template <typename K>
 hipError_t sort_impl(K* keys, uint32_t* vals, K* akeys, uint32_t* avals, int64_t n, int bits,
-                     void* tmp, hipStream_t st, const SortPayload* pl, bool vals_iota) {
-  if (n <= 1 || bits <= 0) return hipSuccess;
+                     void* tmp, hipStream_t st, const SortPayload* pl, bool vals_iota,
+                     const int64_t* dn) {
+  // with a device count the passes always run (the count is not known here);
+  // without one, one element or none needs no pass
+  if (n <= 0 || (!dn && n <= 1)) return hipSuccess;
+  if (bits <= 0) bits = 1;
   const int64_t ntiles = ceil_div_i64(n, RS_TILE);
   uint32_t* hist = (uint32_t*)tmp;
   uint32_t* total = hist + RS_MAXBINS * ntiles;   // digit totals
@@ -333,11 +342,11 @@ hipError_t sort_impl(K* keys, uint32_t* vals, K* akeys, uint32_t* avals, int64_t
     const SortPayload& pp = (p == passes - 1 && pl) ? *pl : none;
     const int iota = (p == 0 && vals_iota) ? 1 : 0;
     if (dbits <= 8)
-      launch_pass<K, 256>(src_k, src_v, dst_k, dst_v, n, shift, dbits, ntiles, hist, total, pp,
-                          iota, st);
+      launch_pass<K, 256>(src_k, src_v, dst_k, dst_v, n, dn, shift, dbits, ntiles, hist, total,
+                          pp, iota, st);
     else
-      launch_pass<K, 512>(src_k, src_v, dst_k, dst_v, n, shift, dbits, ntiles, hist, total, pp,
-                          iota, st);
+      launch_pass<K, 512>(src_k, src_v, dst_k, dst_v, n, dn, shift, dbits, ntiles, hist, total,
+                          pp, iota, st);
     K* tk = src_k; src_k = dst_k; dst_k = tk;
     uint32_t* tv = src_v; src_v = dst_v; dst_v = tv;
   }
@@ -359,12 +368,12 @@ size_t radix_tmp_bytes(int64_t n) {
 
 hipError_t radix_sort_u32(uint32_t* keys, uint32_t* vals, uint32_t* ak, uint32_t* av, int64_t n,
                           int bits, void* tmp, hipStream_t st, const SortPayload* pl,
-                          bool vals_iota) {
-  return sort_impl<uint32_t>(keys, vals, ak, av, n, bits, tmp, st, pl, vals_iota);
+                          bool vals_iota, const int64_t* dn) {
+  return sort_impl<uint32_t>(keys, vals, ak, av, n, bits, tmp, st, pl, vals_iota, dn);
 }
 
 hipError_t radix_sort_u64(uint64_t* keys, uint32_t* vals, uint64_t* ak, uint32_t* av, int64_t n,
                           int bits, void* tmp, hipStream_t st, const SortPayload* pl,
-                          bool vals_iota) {
-  return sort_impl<uint64_t>(keys, vals, ak, av, n, bits, tmp, st, pl, vals_iota);
+                          bool vals_iota, const int64_t* dn) {
+  return sort_impl<uint64_t>(keys, vals, ak, av, n, bits, tmp, st, pl, vals_iota, dn);
 }

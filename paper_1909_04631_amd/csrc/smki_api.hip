@@ -151,6 +151,14 @@ struct smki_map {
   hipEvent_t evr[SMKI_TIMING_RING][4] = {};
   hipEvent_t* ev = evr[0];
   int64_t n_timed = 0;    // inserts that recorded a set
+  // Captured inserts (smki_batch_*): the device copy of the block counts
+  // (dev.counts) is current after a replay, the host's (n_blocks, n_cblocks)
+  // until then; epoch changes whenever the map's storage moves (a captured
+  // graph holds its addresses).
+  bool host_counts_valid = true;
+  int64_t epoch = 0;
+  smki_batch* stats_batch = nullptr;   // the replay whose counters smki_last_scan_stats reports
+  int32_t last_vlo[3] = {0, 0, 0}, last_vhi[3] = {0, 0, 0};   // voxel box of the last insert
 };
 
 // ---------------------------------------------------------------------------
@@ -161,7 +169,7 @@ namespace {
 smki_status status_of_err(uint32_t e) {
   if (e & (DEVERR_LABEL | DEVERR_NONFINITE | DEVERR_DUP)) return SMKI_E_BAD_INPUT;
   if (e & (DEVERR_RANGE | DEVERR_RAY)) return SMKI_E_RANGE;
-  if (e & DEVERR_HASH) return SMKI_E_CAPACITY;
+  if (e & (DEVERR_HASH | DEVERR_CAPACITY)) return SMKI_E_CAPACITY;
   return SMKI_E_DEVICE;
 }
 
@@ -228,6 +236,7 @@ smki_status ensure_pool(smki_map* m, int64_t need) {
   m->dev.cslot = ncs;
   m->dev.bkeys = nk;
   m->pool_cap = cap;
+  ++m->epoch;
   return SMKI_OK;
 }
 
@@ -245,6 +254,7 @@ smki_status ensure_cpool(smki_map* m, int64_t need) {
   if (m->dev.calpha) (void)hipFree(m->dev.calpha);
   m->dev.calpha = na;
   m->cpool_cap = cap;
+  ++m->epoch;
   return SMKI_OK;
 }
 
@@ -267,6 +277,7 @@ smki_status ensure_hash(smki_map* m, int64_t blocks) {
   m->dev.hkeys = hk;
   m->dev.hvals = hv;
   m->dev.hcap = cap;
+  ++m->epoch;
   SMKI_HIP_TRY(launch_hash_clear(m->dev, m->stream));
   SMKI_HIP_TRY(launch_hash_insert_slots(m->dev, 0, m->n_blocks, m->d_err, m->stream));
   return SMKI_OK;
@@ -288,6 +299,18 @@ float max_class_l(const smki_map* m) {
   float l = 0.0f;
   for (float v : m->lk) l = std::max(l, v);
   return l;
+}
+
+// The block counts on the host, read back from the device after a replay of a
+// captured insert (synchronises the map's stream then).
+smki_status refresh_counts(smki_map* m) {
+  if (m->host_counts_valid) return SMKI_OK;
+  int64_t c[2];
+  SMKI_HIP_TRY(sync_read(m, m->dev.counts, sizeof(c), c));
+  m->n_blocks = c[0];
+  m->n_cblocks = c[1];
+  m->host_counts_valid = true;
+  return SMKI_OK;
 }
 
 smki_status take_device_error(smki_map* m) {
@@ -438,12 +461,15 @@ smki_status insert_impl(smki_map* m, const float* xyz, const int32_t* label, con
   if (n > (int64_t)INT32_MAX / 2) return SMKI_E_CAPACITY;
   // soft: up to K hit rows per hit, counted in int32
   if (probs && n * (int64_t)m->K > (int64_t)INT32_MAX / 2) return SMKI_E_CAPACITY;
+  SMKI_HIP_TRY(hipSetDevice(m->device));
+  smki_status rc0 = refresh_counts(m);
+  if (rc0 != SMKI_OK) return rc0;
   smki_scan_stats st{};
   m->last = st;
   m->stats_pending = false;
+  m->stats_batch = nullptr;
   if (n == 0) return SMKI_OK;
   hipStream_t q = m->stream;
-  SMKI_HIP_TRY(hipSetDevice(m->device));
 
   // ---- phase A: per-hit validation, free-sample counts, bounding box ----
   // A header, uploaded in one copy from pinned memory and read back in one:
@@ -512,6 +538,10 @@ smki_status insert_impl(smki_map* m, const float* xyz, const int32_t* label, con
     maxabs = std::max<int64_t>(maxabs, std::max(std::abs((int64_t)vlo[q2]), std::abs((int64_t)vhi[q2])));
   }
   const BucketGeom g = make_geom(m, vlo, vhi, m->K);
+  for (int q2 = 0; q2 < 3; ++q2) {
+    m->last_vlo[q2] = vlo[q2];
+    m->last_vhi[q2] = vhi[q2];
+  }
   if (g.n_blocks * m->K > (int64_t(1) << 30)) return SMKI_E_CAPACITY;
   if ((int64_t)(g.nb[0] + 2) * (g.nb[1] + 2) * (g.nb[2] + 2) > (int64_t(1) << 30))
     return SMKI_E_CAPACITY;
@@ -751,6 +781,303 @@ smki_status insert_impl(smki_map* m, const float* xyz, const int32_t* label, con
 }  // namespace
 
 // ---------------------------------------------------------------------------
+// captured batched insert: every launch sized for capacities fixed at capture,
+// every count read on the device, no host synchronisation (a HIP graph)
+// ---------------------------------------------------------------------------
+namespace {
+
+// Input header of a replay (pinned on the host, copied by the graph's first
+// node): [0, 32) int64 install-counts flag, blocks, class blocks; [32, 48) the
+// first phase's totals (zeroed); [48, 52) error word (zeroed); [64, ...) the
+// bounding-box copies; then the scan offsets and origins.
+constexpr size_t kBSc = 32, kBErr = 48, kBBox = 64;
+constexpr size_t kBTail = kBBox + sizeof(int32_t) * kBboxInts;
+constexpr int kBOut = 16;   // int64 results ahead of the counter copies in the output
+
+struct BatchBufs {
+  char* hdr;
+  int64_t *sc, *soff, *pc, *out;
+  uint32_t* err;
+  int32_t* bbox;
+  float* org;
+  unsigned long long* stats;
+  int64_t *nfree, *off;
+  int32_t *kept, *kpos, *wgbeam;
+  void *stmp_a, *sort_tmp, *scan_tmp, *ctmp;
+  int32_t *si, *mark, *mpos, *ext2t, *dense, *slot_lin, *head, *nun, *ust;
+  void *keys, *akeys;
+  uint32_t *idx, *aidx;
+  float4* rec;
+  int32_t *flag, *slot_excl;
+  int32_t *cnt, *active, *contrib, *tgt, *tslot, *isnew, *rank, *need, *cpos, *uorder;
+  int4 *units, *sinfo;
+  float* part;
+  uint32_t* umask;
+};
+
+}  // namespace
+
+struct smki_batch {
+  smki_map* m = nullptr;
+  int64_t epoch = -1;        // the map's storage epoch the graph was recorded for
+  const float* xyz = nullptr;
+  const int32_t* label = nullptr;
+  int64_t n = 0;
+  int32_t S = 0;
+  float step = 0.0f;
+  BucketGeom g{};            // the window: the sizing insert's voxel box, grown
+  int32_t eblo[3] = {0, 0, 0}, enb[3] = {0, 0, 0};
+  int64_t n_ext = 0;
+  Stencil sten;
+  int64_t cap_rows = 0, cap_slots = 0, cap_units = 0;
+  int64_t pool_cap = 0, cpool_cap = 0, hcap = 0;
+  size_t in_bytes = 0;
+  char* dbuf = nullptr;
+  char* h_in = nullptr;      // pinned input header
+  int64_t* h_out = nullptr;  // pinned results: kBOut int64, then the counter copies
+  StencilOff* d_offs = nullptr;
+  BatchBufs d{};
+  hipStream_t cs = nullptr;  // stream the graph is recorded on
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  hipEvent_t done = nullptr;
+  bool launched = false;
+};
+
+namespace {
+
+// Aligned sub-buffers carved from base (nullptr: sizes only).
+struct Carver {
+  char* base;
+  size_t used = 0;
+  template <typename T>
+  T* take(size_t k) {
+    size_t off = (used + kAlign - 1) / kAlign * kAlign;
+    used = off + std::max<size_t>(k, 1) * sizeof(T);
+    return base ? (T*)(base + off) : nullptr;
+  }
+};
+
+// Carve the batch's device buffers from base (nullptr: size only).
+size_t carve_batch(smki_batch* b, char* base) {
+  smki_map* m = b->m;
+  const int64_t n = std::max<int64_t>(b->n, 1), ne = b->n_ext, ntk = ne * m->K;
+  const int64_t R = b->cap_rows, NS = b->cap_slots, NU = b->cap_units;
+  const int64_t DR = m->B + 2 * b->sten.R, DR3 = DR * DR * DR;
+  const size_t kw = b->g.key_bits <= 32 ? 4 : 8;
+  Carver c{base};
+  BatchBufs& d = b->d;
+  d.hdr = c.take<char>(b->in_bytes);
+  d.sc = (int64_t*)(d.hdr ? d.hdr + kBSc : nullptr);
+  d.err = (uint32_t*)(d.hdr ? d.hdr + kBErr : nullptr);
+  d.bbox = (int32_t*)(d.hdr ? d.hdr + kBBox : nullptr);
+  d.soff = (int64_t*)(d.hdr ? d.hdr + kBTail : nullptr);
+  d.org = (float*)(d.hdr ? d.hdr + kBTail + sizeof(int64_t) * (b->S + 1) : nullptr);
+  d.pc = c.take<int64_t>(4);
+  d.out = c.take<int64_t>(kBOut + 4 * SMKI_STAT_COPIES);   // results, then the counter copies
+  d.stats = (unsigned long long*)(d.out ? d.out + kBOut : nullptr);
+  d.nfree = c.take<int64_t>(n);
+  d.off = c.take<int64_t>(n);
+  d.kept = c.take<int32_t>(n);
+  d.kpos = c.take<int32_t>(n);
+  d.stmp_a = c.take<char>(scan_tmp_bytes(n));
+  d.si = c.take<int32_t>(8);        // slots, targets, units; cleared with the marks
+  d.mark = c.take<int32_t>(ne);
+  d.mpos = c.take<int32_t>(ne);
+  d.ext2t = c.take<int32_t>(ne);
+  d.dense = c.take<int32_t>(b->g.n_blocks * m->K);
+  d.slot_lin = c.take<int32_t>(NS);
+  d.head = c.take<int32_t>(NS + 1);
+  d.nun = c.take<int32_t>(NS);
+  d.ust = c.take<int32_t>(NS);
+  d.keys = c.take<char>(kw * R);
+  d.akeys = c.take<char>(kw * R);
+  d.idx = c.take<uint32_t>(R);
+  d.aidx = c.take<uint32_t>(R);
+  d.rec = c.take<float4>(R);
+  d.flag = c.take<int32_t>(R);
+  d.slot_excl = c.take<int32_t>(R);
+  d.sort_tmp = c.take<char>(radix_tmp_bytes(R));
+  d.scan_tmp = c.take<char>(scan_tmp_bytes(std::max(std::max(R, ne), NS)));
+  d.wgbeam = c.take<int32_t>(free_sample_workgroups(R));
+  d.cnt = c.take<int32_t>(8);       // cnt, active, contrib: cleared together
+  d.active = c.take<int32_t>(ne);
+  d.contrib = c.take<int32_t>(ntk);
+  d.tgt = c.take<int32_t>(ne);
+  d.tslot = c.take<int32_t>(ne);
+  d.isnew = c.take<int32_t>(ne);
+  d.rank = c.take<int32_t>(ne);
+  d.ctmp = c.take<char>(scan_tmp_bytes(std::max<int64_t>(ntk, 1)));
+  d.units = c.take<int4>(NU);
+  d.part = c.take<float>((size_t)NU * DR3);
+  d.umask = c.take<uint32_t>(NU);
+  d.uorder = c.take<int32_t>(NU);
+  d.sinfo = c.take<int4>(NS);
+  d.need = c.take<int32_t>(ntk);
+  d.cpos = c.take<int32_t>(ntk);
+  return c.used;
+}
+
+// Fill the pinned input header of a replay.
+void batch_header(smki_batch* b, const int64_t* offsets, const float* origins) {
+  smki_map* m = b->m;
+  char* h = b->h_in;
+  memset(h, 0, kBBox);
+  int64_t* f = (int64_t*)h;
+  f[0] = m->host_counts_valid ? 1 : 0;   // else the device's counts are the current ones
+  f[1] = m->n_blocks;
+  f[2] = m->n_cblocks;
+  bbox_init((int32_t*)(h + kBBox));
+  memcpy(h + kBTail, offsets, sizeof(int64_t) * (b->S + 1));
+  memcpy(h + kBTail + sizeof(int64_t) * (b->S + 1), origins, sizeof(float) * 3 * b->S);
+}
+
+// The whole insert with device-resident counts (recorded into the graph).
+smki_status batch_enqueue(smki_batch* b, hipStream_t q) {
+  smki_map* m = b->m;
+  const BucketGeom& g = b->g;
+  BatchBufs& d = b->d;
+  const int64_t n = b->n, ne = b->n_ext, ntk = ne * m->K;
+  SMKI_HIP_TRY(hipMemcpyAsync(d.hdr, b->h_in, b->in_bytes, hipMemcpyHostToDevice, q));
+  SMKI_HIP_TRY(launch_batch_start((const int64_t*)d.hdr, m->dev.counts, d.stats, q));
+  SMKI_HIP_TRY(launch_clear3(d.si, (int64_t)(d.mark + ne - d.si), d.cnt,
+                             (int64_t)(d.contrib + ntk - d.cnt), d.dense, g.n_blocks * m->K, -1,
+                             q));
+  // first phase: validation, free-sample counts, their offsets
+  SMKI_HIP_TRY(launch_count(b->xyz, b->label, nullptr, n, d.soff, d.org, b->S, m->res, b->step,
+                            m->K, d.nfree, d.kept, d.bbox, d.err, q));
+  SMKI_HIP_TRY(scan_excl_pair_i64_i32(d.nfree, d.off, n, d.sc, d.kept, d.kpos, n,
+                                      (int32_t*)(d.sc + 1), d.stmp_a, q));
+  SMKI_HIP_TRY(launch_batch_rows(d.sc, b->cap_rows, d.pc, d.err, q));
+  // bucketing over the window's grid (rows outside it: SMKI_E_RANGE)
+  PointSet ps{};
+  ps.n = b->cap_rows;
+  ps.dense = d.dense;
+  ps.slot_lin = d.slot_lin;
+  ps.head = d.head;
+  ps.d_nslots = d.si;
+  BucketScratch scr{};
+  scr.keys = d.keys;
+  scr.akeys = d.akeys;
+  scr.idx = d.idx;
+  scr.aidx = d.aidx;
+  scr.rec = d.rec;
+  scr.flag = d.flag;
+  scr.slot_excl = d.slot_excl;
+  scr.sort_tmp = d.sort_tmp;
+  scr.scan_tmp = d.scan_tmp;
+  SMKI_HIP_TRY(bucket_scan(b->xyz, b->label, nullptr, m->K, n, d.kept, d.kpos, n, d.off,
+                           b->cap_rows, d.wgbeam, d.soff, d.org, b->S, b->step, m->free_class, g,
+                           ps, scr, d.err, q, d.pc));
+  SMKI_HIP_TRY(launch_mark_targets(ps.slot_lin, ps.d_nslots, (int32_t)b->cap_slots, g, b->eblo,
+                                   b->enb, 1, d.mark, q));
+  SMKI_HIP_TRY(launch_slot_units(ps.head, ps.d_nslots, (int32_t)b->cap_slots, m->chunk, d.nun, q));
+  SMKI_HIP_TRY(scan_excl_pair_i32(d.mark, d.mpos, ne, d.si + 1, d.nun, d.ust, b->cap_slots,
+                                  d.si + 2, d.scan_tmp, q));
+  SMKI_HIP_TRY(launch_batch_units(d.si + 2, b->cap_units, d.err, q));
+  // splat, allocation, merge
+  const Stencil& sten = b->sten;
+  const int64_t DR = m->B + 2 * sten.R;
+  SplatArgs sa{};
+  sa.g = g;
+  sa.R = sten.R;
+  sa.noff = (int32_t)sten.offs.size();
+  sa.offs = (const int4*)b->d_offs;
+  sa.cls = m->d_cls;
+  for (int i = 0; i < SMKI_POLY_N; ++i) sa.mcoef[i] = (float)(kSmkiQ[i] / kSmkiQ[0]);
+  sa.K = m->K;
+  sa.chunk = m->chunk;
+  sa.piece_mask = 0;
+  for (int p = 0; p < 27; ++p) {
+    const int nz = (p / 9 != 1) + ((p / 3) % 3 != 1) + (p % 3 != 1);
+    if (m->selection == SMKI_SELECT_EXACT || nz <= 1) sa.piece_mask |= 1u << p;
+  }
+  sa.pts = d.rec;
+  sa.wts = nullptr;
+  sa.perm = d.idx;
+  sa.dense = d.dense;
+  sa.head = d.head;
+  sa.slot_lin = d.slot_lin;
+  sa.nunits = d.nun;
+  sa.ustart = d.ust;
+  for (int a = 0; a < 3; ++a) {
+    sa.eblo[a] = b->eblo[a];
+    sa.enb[a] = b->enb[a];
+  }
+  sa.ext2t = d.ext2t;
+  sa.stats = d.stats;
+  sa.tgt_elin = d.tgt;
+  sa.tgt_active = d.active;
+  sa.tgt_slot = d.tslot;
+  sa.units = d.units;
+  sa.uorder = d.uorder;
+  sa.part = d.part;
+  sa.part_elems = b->cap_units * DR * DR * DR;
+  sa.wide = (m->flags & SMKI_FLAG_WIDE_OFFSETS) ? 1 : 0;
+  sa.umask = d.umask;
+  sa.sinfo = d.sinfo;
+  sa.n_slots = (int32_t)b->cap_slots;
+  sa.contrib = d.contrib;
+  sa.dn_slots = d.si;
+  sa.dn_targets = d.si + 1;
+  sa.dn_units = d.si + 2;
+  sa.abort_word = d.err;
+  sa.cap_units = (int32_t)b->cap_units;
+  SMKI_HIP_TRY(launch_unit_table(d.nun, d.ust, d.head, d.slot_lin, g.n_blocks, m->chunk,
+                                 (int32_t)b->cap_slots, ps.d_nslots, d.si + 2, d.units, d.uorder,
+                                 q, (int32_t)b->cap_units));
+  SMKI_HIP_TRY(launch_splat(sa, b->cap_units, q));
+  SMKI_HIP_TRY(launch_list_targets(d.mark, d.mpos, ne, d.tgt, d.ext2t, q));
+  SMKI_HIP_TRY(launch_slot_info(sa, q));
+  SMKI_HIP_TRY(launch_contrib(sa, false, d.contrib, q));
+  SMKI_HIP_TRY(launch_map_lookup(m->dev, sa, (int32_t)ne, d.tslot, d.isnew, q));
+  SMKI_HIP_TRY(launch_need(m->dev, (int32_t)ne, d.contrib, d.isnew, d.tslot, d.need, q, d.si + 1));
+  SMKI_HIP_TRY(scan_excl_pair_i32(d.isnew, d.rank, ne, d.cnt, d.need, d.cpos, ntk, d.cnt + 1,
+                                  d.ctmp, q));
+  SMKI_HIP_TRY(launch_batch_alloc_check(d.cnt, m->dev.counts, b->pool_cap, b->cpool_cap, b->hcap,
+                                        d.err, q));
+  SMKI_HIP_TRY(launch_assign(m->dev, sa, (int32_t)ne, d.isnew, d.rank, 0, d.tslot, d.need, d.cpos,
+                             0, m->d_err, q));
+  sa.map = m->dev;
+  sa.alpha0 = m->alpha0;
+  SMKI_HIP_TRY(launch_merge(sa, (int32_t)ne, q));
+  SMKI_HIP_TRY(launch_batch_commit(d.cnt, m->dev.counts, d.err, m->d_err, d.pc, d.si, d.out, q));
+  SMKI_HIP_TRY(hipMemcpyAsync(b->h_out, d.out, sizeof(int64_t) * (kBOut + 4 * SMKI_STAT_COPIES),
+                              hipMemcpyDeviceToHost, q));
+  return SMKI_OK;
+}
+
+void batch_release(smki_batch* b) {
+  if (!b) return;
+  if (b->launched && b->done) (void)hipEventSynchronize(b->done);
+  if (b->exec) (void)hipGraphExecDestroy(b->exec);
+  if (b->graph) (void)hipGraphDestroy(b->graph);
+  if (b->cs) (void)hipStreamDestroy(b->cs);
+  if (b->done) (void)hipEventDestroy(b->done);
+  if (b->dbuf) (void)hipFree(b->dbuf);
+  if (b->d_offs) (void)hipFree(b->d_offs);
+  if (b->h_in) (void)hipHostFree(b->h_in);
+  if (b->h_out) (void)hipHostFree(b->h_out);
+  if (b->m && b->m->stats_batch == b) b->m->stats_batch = nullptr;
+  delete b;
+}
+
+bool batch_inputs_ok(const smki_map* m, int64_t n, const int64_t* offsets, const float* origins,
+                     int32_t S) {
+  if (offsets[0] != 0 || offsets[S] != n) return false;
+  for (int32_t s = 0; s < S; ++s)
+    if (offsets[s + 1] < offsets[s]) return false;
+  for (int32_t s = 0; s < 3 * S; ++s) {
+    if (!isfinite(origins[s])) return false;
+    const float q = floorf((float)((double)origins[s] / (double)m->res));
+    if (!(q >= -(float)SMKI_COORD_LIM && q < (float)SMKI_COORD_LIM)) return false;
+  }
+  return true;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
 // C ABI
 // ---------------------------------------------------------------------------
 extern "C" {
@@ -808,12 +1135,15 @@ smki_status smki_create_map(float res, int32_t block_size, float l, float sigma0
       hipMalloc((void**)&m->d_stats, kStatBytes) != hipSuccess ||
       hipMalloc((void**)&m->d_offs, sizeof(StencilOff) * SMKI_MAX_OFFS) != hipSuccess ||
       hipMalloc((void**)&m->d_cls, sizeof(float4) * K) != hipSuccess ||
+      hipMalloc((void**)&m->dev.counts, sizeof(int64_t) * 2) != hipSuccess ||
       hipHostMalloc((void**)&m->h_pin, 8192, hipHostMallocDefault) != hipSuccess)
     rc = SMKI_E_OOM;
   for (int i = 0; rc == SMKI_OK && i < SMKI_TIMING_RING; ++i)
     for (int j = 0; j < 4; ++j)
       if (hipEventCreate(&m->evr[i][j]) != hipSuccess) rc = SMKI_E_OOM;
-  if (rc == SMKI_OK && hipMemset(m->d_err, 0, 64) != hipSuccess) rc = SMKI_E_DEVICE;
+  if (rc == SMKI_OK && (hipMemset(m->d_err, 0, 64) != hipSuccess ||
+                        hipMemset(m->dev.counts, 0, sizeof(int64_t) * 2) != hipSuccess))
+    rc = SMKI_E_DEVICE;
   if (rc == SMKI_OK) {
     m->lk.assign(K, l);
     m->s0k.assign(K, sigma0);
@@ -844,6 +1174,7 @@ smki_status smki_destroy_map(smki_map* m) {
   if (m->d_stats) (void)hipFree(m->d_stats);
   if (m->d_offs) (void)hipFree(m->d_offs);
   if (m->d_cls) (void)hipFree(m->d_cls);
+  if (m->dev.counts) (void)hipFree(m->dev.counts);
   if (m->h_pin) (void)hipHostFree(m->h_pin);
   if (m->h_hdr) (void)hipHostFree(m->h_hdr);
   for (auto& set : m->evr)
@@ -864,6 +1195,7 @@ smki_status smki_set_class_params(smki_map* m, const float* l, const float* sigm
   SMKI_HIP_TRY(hipSetDevice(m->device));
   m->lk.assign(l, l + m->K);
   m->s0k.assign(sigma0, sigma0 + m->K);
+  ++m->epoch;   // a captured insert was sized for the old kernels
   return upload_class_params(m);
 }
 
@@ -904,6 +1236,8 @@ smki_status smki_query(smki_map* m, const int32_t* ijk, int64_t M, float* alpha,
 
 smki_status smki_num_blocks(smki_map* m, int64_t* n_blocks) {
   if (!m || !n_blocks) return SMKI_E_INVALID_ARG;
+  const smki_status rc = refresh_counts(m);
+  if (rc != SMKI_OK) return rc;
   *n_blocks = m->n_blocks;
   return SMKI_OK;
 }
@@ -911,6 +1245,8 @@ smki_status smki_num_blocks(smki_map* m, int64_t* n_blocks) {
 smki_status smki_export(smki_map* m, int64_t capacity, int64_t* n_blocks, int32_t* block_ijk,
                         float* alpha) {
   if (!m || !n_blocks) return SMKI_E_INVALID_ARG;
+  const smki_status rc = refresh_counts(m);
+  if (rc != SMKI_OK) return rc;
   *n_blocks = m->n_blocks;
   if (!block_ijk && !alpha) return SMKI_OK;
   if (capacity < m->n_blocks) return SMKI_E_CAPACITY;
@@ -945,7 +1281,12 @@ smki_status smki_import(smki_map* m, int64_t n, const int32_t* block_ijk, const 
     SMKI_HIP_TRY(launch_hash_clear(m->dev, m->stream));
     m->n_blocks = 0;
     m->n_cblocks = 0;
+    m->host_counts_valid = true;   // (installed on the device by the next replay)
     return SMKI_OK;
+  }
+  {
+    const smki_status rc0 = refresh_counts(m);
+    if (rc0 != SMKI_OK) return rc0;
   }
   const int64_t nk = n * m->K;
   if (nk > (int64_t)INT32_MAX / 2) return SMKI_E_CAPACITY;
@@ -1011,6 +1352,30 @@ smki_status smki_import(smki_map* m, int64_t n, const int32_t* block_ijk, const 
 
 smki_status smki_last_scan_stats(smki_map* m, smki_scan_stats* out) {
   if (!m || !out) return SMKI_E_INVALID_ARG;
+  if (m->stats_pending && m->stats_batch) {   // the last insert was a replay
+    smki_batch* b = m->stats_batch;
+    SMKI_HIP_TRY(hipStreamSynchronize(m->stream));
+    const int64_t* o = b->h_out;
+    const unsigned long long* c = (const unsigned long long*)(o + kBOut);
+    unsigned long long s[4] = {0, 0, 0, 0};
+    for (int k = 0; k < SMKI_STAT_COPIES; ++k)
+      for (int i = 0; i < 4; ++i) s[i] += c[k * 4 + i];
+    smki_scan_stats st{};
+    st.n_hits = o[4];
+    st.n_free = o[5];
+    st.n_point_blocks = o[6];
+    st.n_target_blocks = o[7];
+    st.n_units = o[8];
+    st.n_new_blocks = o[1];
+    st.n_new_class_blocks = o[2];
+    st.n_updated_voxels = o[0] ? 0 : (int64_t)s[0];
+    st.n_pairs = (int64_t)s[1];
+    st.n_candidates = o[3] * (int64_t)b->sten.offs.size();
+    st.n_lane_slots =
+        o[3] * (int64_t)SMKI_WAVE * ((int64_t)(b->sten.offs.size() + SMKI_WAVE - 1) / SMKI_WAVE);
+    m->last = st;
+    m->stats_pending = false;
+  }
   if (m->stats_pending) {
     SMKI_HIP_TRY(hipStreamSynchronize(m->stream));
     // the counters' copies, summed
@@ -1047,6 +1412,8 @@ smki_status smki_kernel_times(smki_map* m, int32_t max, float* splat_ms, float* 
 smki_status smki_sync(smki_map* m) {
   if (!m) return SMKI_E_INVALID_ARG;
   SMKI_HIP_TRY(hipStreamSynchronize(m->stream));
+  const smki_status rc = refresh_counts(m);
+  if (rc != SMKI_OK) return rc;
   return take_device_error(m);
 }
 
@@ -1229,5 +1596,145 @@ smki_status smki_bucket_cells(const float* xyz, int64_t n, float res, int32_t bl
 }
 
 size_t smki_loss_workspace_bytes(int64_t n_train, int64_t n_query, int32_t K);
+
+smki_status smki_batch_capture(smki_map* m, const float* xyz, const int32_t* label,
+                               const int64_t* offsets, const float* origins, int32_t S,
+                               float free_step, float margin, smki_batch** out) {
+  if (!out) return SMKI_E_INVALID_ARG;
+  *out = nullptr;
+  if (!m || !offsets || !origins || S < 1 || !(margin >= 0.0f && margin <= 16.0f) ||
+      !isfinite(free_step) || offsets[S] < 1 || !xyz || !label)
+    return SMKI_E_INVALID_ARG;
+  if (m->model != SMKI_MODEL_SBKI) return SMKI_E_INVALID_ARG;
+  const int64_t n = offsets[S];
+  if (!batch_inputs_ok(m, n, offsets, origins, S)) return SMKI_E_INVALID_ARG;
+  // 1. the ordinary insert of these scans (it sizes everything)
+  smki_status rc = insert_impl(m, xyz, label, nullptr, n, offsets, origins, S, free_step);
+  if (rc != SMKI_OK) return rc;
+  const smki_scan_stats st = m->last;
+  if (st.n_hits == 0) return SMKI_E_INVALID_ARG;   // nothing to size the capture by
+  smki_batch* b = new (std::nothrow) smki_batch();
+  if (!b) return SMKI_E_OOM;
+  b->m = m;
+  b->xyz = xyz;
+  b->label = label;
+  b->n = n;
+  b->S = S;
+  b->step = free_step;
+  const double grow = 1.0 + (double)margin;
+  // 2. the window: the voxel box of that insert, grown by margin of its extent per side
+  int32_t wlo[3], whi[3];
+  int64_t maxabs = 0;
+  for (int a = 0; a < 3; ++a) {
+    const int64_t ext = (int64_t)m->last_vhi[a] - m->last_vlo[a] + 1;
+    const int64_t pad = std::max<int64_t>(2 * m->B, (int64_t)ceil(margin * ext));
+    wlo[a] = (int32_t)std::max<int64_t>(m->last_vlo[a] - pad, -SMKI_COORD_LIM);
+    whi[a] = (int32_t)std::min<int64_t>(m->last_vhi[a] + pad, SMKI_COORD_LIM - 1);
+    maxabs = std::max<int64_t>(maxabs, std::max(std::abs((int64_t)wlo[a]), std::abs((int64_t)whi[a])));
+  }
+  b->g = make_geom(m, wlo, whi, m->K);
+  const BucketGeom& g = b->g;
+  b->n_ext = 1;
+  for (int a = 0; a < 3; ++a) {
+    b->eblo[a] = g.blo[a] - 1;
+    b->enb[a] = g.nb[a] + 2;
+    b->n_ext *= b->enb[a];
+  }
+  const double lv = (double)max_class_l(m) / (double)m->res;
+  const double smargin = std::max(1e-4, 4.0 * ldexp((double)maxabs + 1.0, -23));
+  b->sten = make_stencil(lv, smargin);
+  // 3. capacities
+  b->cap_rows = std::max<int64_t>(n, (int64_t)ceil((double)(st.n_hits + st.n_free) * grow)) + 4096;
+  b->cap_slots = std::min<int64_t>(b->cap_rows, g.n_blocks * m->K);
+  b->cap_units = (int64_t)ceil((double)st.n_units * grow) + 1024;
+  const int64_t DR = m->B + 2 * b->sten.R;
+  if (g.n_blocks * m->K > (int64_t(1) << 30) || b->n_ext > (int64_t(1) << 30) ||
+      b->n_ext * m->K > (int64_t)INT32_MAX / 2 || b->cap_rows > (int64_t)INT32_MAX - 1 ||
+      b->sten.R > SMKI_MAX_REACH || b->sten.R > m->B ||
+      (double)b->cap_units * DR * DR * DR * sizeof(float) > 64.0 * (1ull << 30)) {
+    delete b;
+    return SMKI_E_CAPACITY;
+  }
+  // room in the map for the replays: the blocks and class blocks of this
+  // insert again, plus margin, on top of what the map holds now
+  rc = ensure_pool(m, (int64_t)ceil((double)(m->n_blocks + st.n_new_blocks) * grow) + 64);
+  if (rc == SMKI_OK)
+    rc = ensure_cpool(m, (int64_t)ceil((double)(m->n_cblocks + st.n_new_class_blocks) * grow) + 64);
+  if (rc == SMKI_OK) rc = ensure_hash(m, m->pool_cap);
+  if (rc != SMKI_OK) {
+    delete b;
+    return rc;
+  }
+  b->pool_cap = m->pool_cap;
+  b->cpool_cap = m->cpool_cap;
+  b->hcap = m->dev.hcap;
+  // 4. buffers, stencil, header
+  b->in_bytes = kBTail + sizeof(int64_t) * (S + 1) + sizeof(float) * 3 * S;
+  const size_t dbytes = carve_batch(b, nullptr) + kAlign;
+  hipError_t e = hipMalloc((void**)&b->dbuf, dbytes);
+  if (e == hipSuccess)
+    e = hipMalloc((void**)&b->d_offs, sizeof(StencilOff) * std::max<size_t>(b->sten.offs.size(), 1));
+  if (e == hipSuccess) e = hipHostMalloc((void**)&b->h_in, b->in_bytes, hipHostMallocDefault);
+  if (e == hipSuccess)
+    e = hipHostMalloc((void**)&b->h_out, sizeof(int64_t) * (kBOut + 4 * SMKI_STAT_COPIES),
+                      hipHostMallocDefault);
+  if (e == hipSuccess) e = hipStreamCreateWithFlags(&b->cs, hipStreamNonBlocking);
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&b->done, hipEventDisableTiming);
+  if (e == hipSuccess)
+    e = hipMemcpy(b->d_offs, b->sten.offs.data(), sizeof(StencilOff) * b->sten.offs.size(),
+                  hipMemcpyHostToDevice);
+  if (e != hipSuccess) {
+    batch_release(b);
+    return smki_hip_error(e);
+  }
+  carve_batch(b, (char*)(((uintptr_t)b->dbuf + kAlign - 1) / kAlign * kAlign));
+  batch_header(b, offsets, origins);
+  // 5. record the insert (nothing runs now)
+  e = hipStreamBeginCapture(b->cs, hipStreamCaptureModeThreadLocal);
+  if (e != hipSuccess) {
+    batch_release(b);
+    return smki_hip_error(e);
+  }
+  rc = batch_enqueue(b, b->cs);
+  hipGraph_t graph = nullptr;
+  e = hipStreamEndCapture(b->cs, &graph);
+  b->graph = graph;
+  if (rc == SMKI_OK && e != hipSuccess) rc = smki_hip_error(e);
+  if (rc == SMKI_OK) {
+    e = hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0);
+    if (e != hipSuccess) rc = smki_hip_error(e);
+  }
+  if (rc != SMKI_OK) {
+    batch_release(b);
+    return rc;
+  }
+  b->epoch = m->epoch;
+  *out = b;
+  return SMKI_OK;
+}
+
+smki_status smki_batch_replay(smki_batch* b, const int64_t* offsets, const float* origins) {
+  if (!b || !offsets || !origins) return SMKI_E_INVALID_ARG;
+  smki_map* m = b->m;
+  if (!batch_inputs_ok(m, b->n, offsets, origins, b->S)) return SMKI_E_INVALID_ARG;
+  if (m->epoch != b->epoch) return SMKI_E_CAPACITY;   // the map's storage moved: capture again
+  SMKI_HIP_TRY(hipSetDevice(m->device));
+  // the previous replay has read its header before this one is written
+  if (b->launched) SMKI_HIP_TRY(hipEventSynchronize(b->done));
+  batch_header(b, offsets, origins);
+  SMKI_HIP_TRY(hipGraphLaunch(b->exec, m->stream));
+  SMKI_HIP_TRY(hipEventRecord(b->done, m->stream));
+  b->launched = true;
+  m->host_counts_valid = false;
+  m->stats_batch = b;
+  m->stats_pending = true;
+  return SMKI_OK;
+}
+
+smki_status smki_batch_destroy(smki_batch* b) {
+  if (!b) return SMKI_E_INVALID_ARG;
+  batch_release(b);
+  return SMKI_OK;
+}
 
 }  // extern "C"

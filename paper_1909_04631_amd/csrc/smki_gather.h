@@ -30,6 +30,8 @@ struct MapDev {
   float* calpha;        // [cpool_cap][B^3] concentrations of the allocated class blocks
   int32_t K, B, log2B;
   float alpha0;
+  int64_t* counts;      // [2] blocks and class blocks in use, kept on the device for
+                        // inserts whose launches do not know them when enqueued
 };
 
 // Voxel offset (relative to a row's cell) that can lie within l of a point of
@@ -82,6 +84,14 @@ struct SplatArgs {
   float alpha0;               // prior concentration written to fresh class blocks
   unsigned long long* stats;  // [SMKI_STAT_COPIES][4]: [0] updated voxels, [1] in-support pairs;
                               // workgroup b adds to copy b % SMKI_STAT_COPIES
+  // Device-resident counts (captured inserts, whose launches are sized for
+  // capacities); all null for an insert sized on the host.
+  const int32_t* dn_slots;    // slots (n_slots is then a capacity)
+  const int32_t* dn_targets;  // active-target candidates (the n_targets argument: a capacity)
+  const int32_t* dn_units;    // work units (the launch: a capacity)
+  const uint32_t* abort_word; // non-zero: an error or a capacity overflow; nothing is written
+                              // to the map (allocation and merge return at once)
+  int32_t cap_units;          // work units the unit table may hold
 };
 
 hipError_t launch_mark_targets(const int32_t* slot_lin, const int32_t* d_nslots, int32_t max_slots,
@@ -95,7 +105,8 @@ hipError_t launch_slot_units(const int32_t* head, const int32_t* d_nslots, int32
 hipError_t launch_unit_table(const int32_t* nunits, const int32_t* ustart, const int32_t* head,
                              const int32_t* slot_lin, int64_t n_blocks, int32_t chunk,
                              int32_t max_slots, const int32_t* d_nslots, const int32_t* d_nunits,
-                             int4* units, int32_t* order, hipStream_t st);
+                             int4* units, int32_t* order, hipStream_t st,
+                             int32_t cap_units = INT32_MAX);
 hipError_t launch_splat(const SplatArgs& a, int64_t n_units, hipStream_t st);
 hipError_t launch_merge(const SplatArgs& a, int32_t n_targets, hipStream_t st);
 // class blocks: which (target, class) pairs receive rows, which need a new
@@ -104,7 +115,7 @@ hipError_t launch_contrib(const SplatArgs& a, bool own_block_only, int32_t* cont
                           hipStream_t st);
 hipError_t launch_need(const MapDev& m, int32_t n_targets, const int32_t* contrib,
                        const int32_t* is_new, const int32_t* tgt_slot, int32_t* need,
-                       hipStream_t st);
+                       hipStream_t st, const int32_t* dn_targets = nullptr);
 hipError_t launch_slot_info(const SplatArgs& a, hipStream_t st);
 hipError_t launch_map_lookup(const MapDev& m, const SplatArgs& a, int32_t n_targets,
                              int32_t* tgt_slot, int32_t* is_new, hipStream_t st);
@@ -113,6 +124,30 @@ hipError_t launch_assign(const MapDev& m, const SplatArgs& a, int32_t n_targets,
                          const int32_t* is_new, const int32_t* new_rank, int64_t n_old,
                          int32_t* tgt_slot, const int32_t* need, const int32_t* cpos,
                          int64_t n_cold, uint32_t* err, hipStream_t st);
+
+// Captured (graph) inserts: the steps that replace the host's reads of counts.
+// hdr (device): [0] 1 if the map's counts below are to be installed, [1] blocks,
+// [2] class blocks; the map's counts are set from it, the insert counters cleared.
+hipError_t launch_batch_start(const int64_t* hdr, int64_t* counts, unsigned long long* stats,
+                              hipStream_t st);
+// sc: phase-one totals (int64 free samples, then int32 hit rows); pc <- [rows,
+// hit rows, free samples] clamped to cap_rows (overflow: DEVERR_CAPACITY in err).
+hipError_t launch_batch_rows(const int64_t* sc, int64_t cap_rows, int64_t* pc, uint32_t* err,
+                             hipStream_t st);
+// DEVERR_CAPACITY if the work units exceed cap_units
+hipError_t launch_batch_units(const int32_t* d_nunits, int64_t cap_units, uint32_t* err,
+                              hipStream_t st);
+// DEVERR_CAPACITY if the new blocks / class blocks (cnt[0], cnt[1]) do not fit the
+// map's pools (blocks, class blocks; the hash at most half full)
+hipError_t launch_batch_alloc_check(const int32_t* cnt, const int64_t* counts, int64_t pool_cap,
+                                    int64_t cpool_cap, int64_t hcap, uint32_t* err,
+                                    hipStream_t st);
+// without an error: counts += (cnt[0], cnt[1]); with one: OR it into the map's
+// sticky error word.  out (int64 [8]): error, new blocks, new class blocks,
+// rows, hit rows, free samples, slots, targets, units (read by the host later)
+hipError_t launch_batch_commit(const int32_t* cnt, int64_t* counts, const uint32_t* err,
+                               uint32_t* map_err, const int64_t* pc, const int32_t* si,
+                               int64_t* out, hipStream_t st);
 
 // csm.hip: counting-model inserts
 hipError_t launch_csm_counts(const SplatArgs& a, const void* keys, bool wide_keys, int64_t n,

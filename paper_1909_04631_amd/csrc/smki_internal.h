@@ -26,6 +26,7 @@ enum : uint32_t {
   DEVERR_RANGE = 1u << 3,      // voxel index outside [-2^20, 2^20)
   DEVERR_HASH = 1u << 4,       // block hash full
   DEVERR_DUP = 1u << 5,        // the same block twice in an import
+  DEVERR_CAPACITY = 1u << 6,   // a captured insert outgrew a capacity fixed at capture
 };
 
 // ---------------------------------------------------------------------------
@@ -59,16 +60,26 @@ struct SortPayload {
 };
 size_t radix_tmp_bytes(int64_t n);
 // vals_iota: vals holds nothing on entry; element i's value is i.
+// dn (device, nullable): the element count, read by the kernels; n is then a
+// capacity (buffers, tiles and launches are sized for n elements).
 hipError_t radix_sort_u32(uint32_t* keys, uint32_t* vals, uint32_t* alt_keys, uint32_t* alt_vals,
                           int64_t n, int bits, void* tmp, hipStream_t st,
-                          const SortPayload* payload = nullptr, bool vals_iota = false);
+                          const SortPayload* payload = nullptr, bool vals_iota = false,
+                          const int64_t* dn = nullptr);
 hipError_t radix_sort_u64(uint64_t* keys, uint32_t* vals, uint64_t* alt_keys, uint32_t* alt_vals,
                           int64_t n, int bits, void* tmp, hipStream_t st,
-                          const SortPayload* payload = nullptr, bool vals_iota = false);
+                          const SortPayload* payload = nullptr, bool vals_iota = false,
+                          const int64_t* dn = nullptr);
 
 // ---------------------------------------------------------------------------
 // small device helpers
 // ---------------------------------------------------------------------------
+// Element count of a launch sized for capacity n: the device count *dn when
+// given (the launch does not know it when it is enqueued), else n.
+__device__ __forceinline__ int64_t eff_n(int64_t n, const int64_t* dn) {
+  return dn ? min(n, *dn) : n;
+}
+
 __device__ __forceinline__ int64_t floordiv_i64(int64_t a, int64_t b) {
   int64_t q = a / b;
   return (a % b != 0 && ((a < 0) != (b < 0))) ? q - 1 : q;

@@ -99,13 +99,16 @@ __global__ void k_unit_table(const int32_t* __restrict__ nunits, const int32_t* 
                              int64_t n_blocks, int32_t chunk, int32_t max_slots,
                              const int32_t* __restrict__ d_nslots,
                              const int32_t* __restrict__ d_nunits, int4* __restrict__ units,
-                             int32_t* __restrict__ order) {
+                             int32_t* __restrict__ order, int32_t cap_units) {
   // eight threads per slot, taking its units k = j, j + 8, ...
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int32_t s = (int32_t)(t >> 3);
   if (s >= max_slots) return;
   const int32_t n = nunits[s];
   if (n == 0) return;
+  // (a captured insert whose units outgrow the table stores none of the rest;
+  // its abort word is set and the map is left unchanged)
+  if (*d_nunits > cap_units) return;
   const int32_t b = ustart[s], h0 = head[s], h1 = head[s + 1];
   const int32_t plane = (int32_t)(slot_lin[s] / n_blocks);
   for (int32_t k = (int32_t)(t & 7); k < n; k += 8) {
@@ -174,6 +177,8 @@ __global__ void __launch_bounds__(SMKI_WAVE) k_splat(SplatArgs a) {
   __shared__ float4 acc4[NACC4];   // the region + a dummy slot for pad lanes
   float* acc = (float*)acc4;
   const int lane = threadIdx.x;
+  if (a.dn_units && (int32_t)blockIdx.x >= *a.dn_units) return;   // capacity launch
+  if (a.abort_word && *a.abort_word) return;   // (a failed captured insert: the units may be stale)
   const int32_t uid = a.uorder ? a.uorder[blockIdx.x] : (int32_t)blockIdx.x;
   const int4 u = a.units[uid];   // (first row, end row, slot, class)
   const int32_t r0 = u.x, r1 = u.y;
@@ -380,7 +385,7 @@ __global__ void __launch_bounds__(SMKI_WAVE) k_splat(SplatArgs a) {
 __global__ void k_slot_info(SplatArgs a) {
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int32_t s = (int32_t)(t >> 3), j = (int32_t)(t & 7);
-  if (s >= a.n_slots) return;
+  if (s >= (a.dn_slots ? min(a.n_slots, *a.dn_slots) : a.n_slots)) return;
   const int32_t u0 = a.ustart[s], nu = a.nunits[s];
   uint32_t m = 0;
   for (int32_t w = u0 + j; w < u0 + nu; w += 8) m |= a.umask[w];
@@ -481,7 +486,10 @@ k_merge(SplatArgs a, int32_t n_targets) {
   __shared__ int32_t cflag[CPG], clist[CPG], cblk[CPG], ncls_s;
   __shared__ int32_t red[NT / SMKI_WAVE];
   const int32_t t = blockIdx.x;
+  if (a.dn_targets) n_targets = min(n_targets, *a.dn_targets);
   if (t >= n_targets || !a.tgt_active[t]) return;
+  if (a.abort_word && *a.abort_word) return;   // nothing is written to the map
+  const int64_t n_cold = a.dn_targets ? a.map.counts[1] : a.n_cold;
   const int tid = threadIdx.x;
   const int32_t mslot = a.tgt_slot[t];
   int32_t bt[3];
@@ -598,7 +606,7 @@ k_merge(SplatArgs a, int32_t n_targets) {
       }
       const int32_t cb = cblk[yc];   // allocated for every class with rows reaching here
       float* dst = a.map.calpha + (int64_t)cb * B3 + tid;
-      if (cb >= a.n_cold) {
+      if (cb >= n_cold) {
         *dst = a.alpha0 + sm;   // class block allocated by this insert: written whole
       } else if (sm != 0.0f) {
         *dst += sm;
@@ -622,7 +630,7 @@ k_merge(SplatArgs a, int32_t n_targets) {
 // thread per (slot, piece).
 __global__ void k_contrib(SplatArgs a, int32_t own_block_only, int32_t* __restrict__ contrib) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= (int64_t)a.n_slots * 27) return;
+  if (i >= (int64_t)(a.dn_slots ? min(a.n_slots, *a.dn_slots) : a.n_slots) * 27) return;
   const int32_t s = (int32_t)(i / 27), p = (int32_t)(i % 27);
   const uint32_t m = own_block_only ? (1u << 13) : (uint32_t)a.sinfo[s].z;
   if (!((m >> p) & 1u)) return;
@@ -642,14 +650,17 @@ __global__ void k_contrib(SplatArgs a, int32_t own_block_only, int32_t* __restri
 }
 
 // a class block is needed where rows arrive and the block has none for the class
+// (dnt: the device count of targets, n_targets then a capacity whose tail is
+// written 0 for the scan that follows)
 __global__ void k_need(MapDev m, int32_t n_targets, const int32_t* __restrict__ contrib,
                        const int32_t* __restrict__ is_new, const int32_t* __restrict__ tgt_slot,
-                       int32_t* __restrict__ need) {
+                       int32_t* __restrict__ need, const int32_t* __restrict__ dnt) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= (int64_t)n_targets * m.K) return;
   const int32_t t = (int32_t)(i / m.K), k = (int32_t)(i % m.K);
   int32_t v = 0;
-  if (contrib[i]) v = (is_new[t] || m.cslot[(int64_t)tgt_slot[t] * m.K + k] < 0) ? 1 : 0;
+  if ((!dnt || t < *dnt) && contrib[i])
+    v = (is_new[t] || m.cslot[(int64_t)tgt_slot[t] * m.K + k] < 0) ? 1 : 0;
   need[i] = v;
 }
 
@@ -658,7 +669,7 @@ __global__ void k_map_lookup(MapDev m, SplatArgs a, int32_t n_targets,
                              int32_t* __restrict__ tgt_slot, int32_t* __restrict__ is_new) {
   const int32_t t = blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= n_targets) return;
-  if (!a.tgt_active[t]) {
+  if ((a.dn_targets && t >= *a.dn_targets) || !a.tgt_active[t]) {
     tgt_slot[t] = -1;
     is_new[t] = 0;
     return;
@@ -688,7 +699,13 @@ __global__ void k_assign(MapDev m, SplatArgs a, int32_t n_targets,
                          const int32_t* __restrict__ need, const int32_t* __restrict__ cpos,
                          int64_t n_cold, uint32_t* __restrict__ err) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (a.dn_targets) n_targets = min(n_targets, *a.dn_targets);
   if (i >= (int64_t)n_targets * m.K) return;
+  if (a.abort_word && *a.abort_word) return;   // nothing is written to the map
+  if (a.dn_targets) {   // the map's counts before this insert, from the device
+    n_old = m.counts[0];
+    n_cold = m.counts[1];
+  }
   const int32_t t = (int32_t)(i / m.K), k = (int32_t)(i % m.K);
   const bool fresh = is_new[t] != 0;
   const int32_t slot = fresh ? (int32_t)(n_old + rank[t]) : tgt_slot[t];
@@ -810,11 +827,11 @@ hipError_t launch_slot_units(const int32_t* head, const int32_t* d_nslots, int32
 hipError_t launch_unit_table(const int32_t* nunits, const int32_t* ustart, const int32_t* head,
                              const int32_t* slot_lin, int64_t n_blocks, int32_t chunk,
                              int32_t max_slots, const int32_t* d_nslots, const int32_t* d_nunits,
-                             int4* units, int32_t* order, hipStream_t st) {
+                             int4* units, int32_t* order, hipStream_t st, int32_t cap_units) {
   if (max_slots <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_unit_table, dim3(nblk((int64_t)max_slots * 8, 256)), dim3(256), 0, st,
                      nunits, ustart, head, slot_lin, n_blocks, chunk, max_slots, d_nslots, d_nunits,
-                     units, order);
+                     units, order, cap_units);
   return hipGetLastError();
 }
 
@@ -861,11 +878,11 @@ hipError_t launch_contrib(const SplatArgs& a, bool own_block_only, int32_t* cont
 
 hipError_t launch_need(const MapDev& m, int32_t n_targets, const int32_t* contrib,
                        const int32_t* is_new, const int32_t* tgt_slot, int32_t* need,
-                       hipStream_t st) {
+                       hipStream_t st, const int32_t* dn_targets) {
   const int64_t n = (int64_t)n_targets * m.K;
   if (n <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_need, dim3(nblk(n, 256)), dim3(256), 0, st, m, n_targets, contrib, is_new,
-                     tgt_slot, need);
+                     tgt_slot, need, dn_targets);
   return hipGetLastError();
 }
 
