@@ -29,20 +29,33 @@ def _rows(xyz, lab, name):
     return xyz.contiguous(), lab.contiguous()
 
 
-def loss_forward(train_xyz, train_label, query_xyz, query_label, l, sigma0, alpha0, K):
-    """(loss float32 [1], alpha_q float32 [H, K])."""
+def workspace(n_train, n_query, K, device=None):
+    """A device workspace (uint8 tensor) for loss_forward / loss_backward of these
+    sizes (smki_loss_workspace_bytes); without one, every call allocates its own."""
+    nb = int(lib().smki_loss_workspace_bytes(int(n_train), int(n_query), int(K)))
+    return torch.empty((nb,), dtype=torch.uint8, device=device or torch.cuda.current_device())
+
+
+def _ws(ws):
+    return (_ptr(ws), ws.numel()) if ws is not None else (None, 0)
+
+
+def loss_forward(train_xyz, train_label, query_xyz, query_label, l, sigma0, alpha0, K,
+                 keep_alpha=True, ws=None):
+    """(loss float32 [1], alpha_q float32 [H, K] or None when keep_alpha is False)."""
     tx, ty = _rows(train_xyz, train_label, "train")
     qx, qy = _rows(query_xyz, query_label, "query")
     loss = torch.empty((1,), dtype=torch.float32, device=qx.device)
-    aq = torch.empty((qx.shape[0], int(K)), dtype=torch.float32, device=qx.device)
+    aq = (torch.empty((qx.shape[0], int(K)), dtype=torch.float32, device=qx.device)
+          if keep_alpha else None)
     check(lib().smki_loss_forward(_ptr(tx), _ptr(ty), tx.shape[0], _ptr(qx), _ptr(qy), qx.shape[0],
-                                  float(l), float(sigma0), float(alpha0), int(K), _stream(), None, 0,
-                                  _ptr(loss), _ptr(aq)), "smki_loss_forward")
+                                  float(l), float(sigma0), float(alpha0), int(K), _stream(),
+                                  *_ws(ws), _ptr(loss), _ptr(aq)), "smki_loss_forward")
     return loss, aq
 
 
 def loss_backward(train_xyz, train_label, query_xyz, query_label, l, sigma0, alpha0, K, alpha_q,
-                  grad_loss, need_train=True, need_query=True):
+                  grad_loss, need_train=True, need_query=True, ws=None):
     """(grad_l [1], grad_sigma0 [1], grad_train [N,3] or None, grad_query [H,3] or None)."""
     tx, ty = _rows(train_xyz, train_label, "train")
     qx, qy = _rows(query_xyz, query_label, "query")
@@ -54,7 +67,7 @@ def loss_backward(train_xyz, train_label, query_xyz, query_label, l, sigma0, alp
     g = grad_loss.reshape(1).to(torch.float32).contiguous()
     check(lib().smki_loss_backward(_ptr(tx), _ptr(ty), tx.shape[0], _ptr(qx), _ptr(qy),
                                    qx.shape[0], float(l), float(sigma0), float(alpha0), int(K),
-                                   _stream(), None, 0, _ptr(alpha_q.contiguous()), _ptr(g),
+                                   _stream(), *_ws(ws), _ptr(alpha_q.contiguous()), _ptr(g),
                                    _ptr(gl), _ptr(gs), _ptr(gt), _ptr(gq)), "smki_loss_backward")
     return gl, gs, gt, gq
 

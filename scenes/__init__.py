@@ -516,12 +516,13 @@ def batched_town_scene(seed: int = 3, n_scans: int = 64, n_lo: int = 10_000,
     return Scene("batched", params, scans, info={"seed": seed})
 
 
-def differentiable_scene(seed: int = 4, holdout: float = 0.2) -> Scene:
-    """The tiny scene with a seeded 20 % of its labelled hits held out.
+def differentiable_scene(seed: int = 4, holdout: float = 0.2, base: Scene = None) -> Scene:
+    """The tiny scene (or `base`, e.g. the LiDAR scan) with a seeded 20 % of its
+    labelled hits held out.
 
     The held-out hits (and their beams) are removed from the training scan and
     returned as `holdout`: they are the query points of the predictive loss."""
-    base = tiny_scene(seed=0)
+    base = tiny_scene(seed=0) if base is None else base
     rng = np.random.default_rng(seed)
     s = base.scans[0]
     n = s.xyz.shape[0]
@@ -532,7 +533,7 @@ def differentiable_scene(seed: int = 4, holdout: float = 0.2) -> Scene:
     train = Scan(s.xyz[keep].copy(), s.label[keep].copy(), s.origin.copy())
     hold = Scan(s.xyz[held].copy(), s.label[held].copy(), s.origin.copy())
     return Scene("differentiable", base.params, [train], holdout=hold,
-                 info={"seed": seed, "base_seed": 0})
+                 info={"seed": seed, "base": base.name})
 
 
 def random_points_scene(seed: int, n: int, K: int = 4, extent: float = 1.0,
