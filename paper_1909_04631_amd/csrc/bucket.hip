@@ -405,13 +405,16 @@ __global__ void __launch_bounds__(HT_THREADS) k_slot_heads(const KeyT* __restric
                                                            int32_t* __restrict__ dense,
                                                            int32_t* __restrict__ slot_lin,
                                                            int32_t* __restrict__ head,
-                                                           const int32_t* __restrict__ d_nslots) {
+                                                           const int32_t* __restrict__ d_nslots,
+                                                           int32_t cap_slots) {
+  // (slots past cap_slots are not stored: a captured insert whose rows make
+  // more slots than it was sized for is failed by its capacity check)
   const int64_t n = eff_n(ncap, dn);
   __shared__ int32_t wc[HT_THREADS / SMKI_WAVE];
   const int lane = threadIdx.x & (SMKI_WAVE - 1), w = threadIdx.x / SMKI_WAVE;
   const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (SMKI_WAVE - lane));
   const int64_t base = (int64_t)blockIdx.x * HT + (int64_t)w * HS + lane;
-  if (blockIdx.x == 0 && threadIdx.x == 0) head[*d_nslots] = (int32_t)n;
+  if (blockIdx.x == 0 && threadIdx.x == 0 && *d_nslots <= cap_slots) head[*d_nslots] = (int32_t)n;
   uint64_t hb[HT_ROUNDS];
   int32_t c = 0;
 #pragma unroll
@@ -429,9 +432,11 @@ __global__ void __launch_bounds__(HT_THREADS) k_slot_heads(const KeyT* __restric
       const int64_t i = base + r * SMKI_WAVE;
       const int64_t blk = (int64_t)((uint64_t)keys[i] >> log2B3);   // plane * n_blocks + block
       const int32_t sl = slot + (int32_t)__popcll(hb[r] & lt_mask);
-      dense[(blk % n_blocks) * planes + blk / n_blocks] = sl;
-      slot_lin[sl] = (int32_t)blk;
-      head[sl] = (int32_t)i;
+      if (sl < cap_slots) {
+        dense[(blk % n_blocks) * planes + blk / n_blocks] = sl;
+        slot_lin[sl] = (int32_t)blk;
+        head[sl] = (int32_t)i;
+      }
     }
     slot += (int32_t)__popcll(hb[r]);
   }
@@ -547,7 +552,7 @@ template <typename KeyT>
 static hipError_t finish_set(PointSet& ps, KeyT* keys, uint32_t* idx, KeyT* akeys, uint32_t* aidx,
                              float4* rec_unsorted, const BucketGeom& g, int key_bits,
                              BucketScratch& scr, hipStream_t st, bool idx_iota = false,
-                             const int64_t* dn = nullptr) {
+                             const int64_t* dn = nullptr, int32_t cap_slots = INT32_MAX) {
   const int64_t n = ps.n;
   if (n <= 0) return hipSuccess;
   hipError_t e;
@@ -579,7 +584,7 @@ static hipError_t finish_set(PointSet& ps, KeyT* keys, uint32_t* idx, KeyT* akey
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_slot_heads<KeyT>, dim3((unsigned)ntiles), dim3(HT_THREADS), 0, st, keys, n,
                      dn, log2B3, g.n_blocks, g.planes, scr.slot_excl, ps.dense, ps.slot_lin,
-                     ps.head, ps.d_nslots);
+                     ps.head, ps.d_nslots, cap_slots);
   if (!ps.prefix) return hipGetLastError();
   if (dn) return hipErrorInvalidValue;   // (per-cell tables are built for host counts only)
   const unsigned grid = (unsigned)std::min<int64_t>(n, 8192);
@@ -605,7 +610,7 @@ static hipError_t bucket_scan_t(const float* xyz, const int32_t* label, const fl
                                 const int64_t* scan_off, const float* origins, int32_t S,
                                 float step, int32_t free_class, const BucketGeom& g, PointSet& ps,
                                 BucketScratch& scr, uint32_t* err, hipStream_t st,
-                                const int64_t* dcnt) {
+                                const int64_t* dcnt, int32_t cap_slots) {
   if (nk > 0 || dcnt)
     hipLaunchKernelGGL(k_hit_keys<KeyT>, dim3(nblk(n, 256)), dim3(256), 0, st, xyz, label, probs,
                        K, n, kept, kpos, off, nf, dcnt, wgbeam, g, (KeyT*)scr.keys, scr.rec,
@@ -615,7 +620,7 @@ static hipError_t bucket_scan_t(const float* xyz, const int32_t* label, const fl
                        off, nf, dcnt, scan_off, origins, S, step, free_class, g, nk,
                        (KeyT*)scr.keys, scr.rec, scr.wt, (const int32_t*)wgbeam, err);
   return finish_set<KeyT>(ps, (KeyT*)scr.keys, scr.idx, (KeyT*)scr.akeys, scr.aidx, scr.rec, g,
-                          g.key_bits, scr, st, true, dcnt);
+                          g.key_bits, scr, st, true, dcnt, cap_slots);
 }
 
 // All training rows of an insert in one sorted set: kept hits at [0, nk), free
@@ -626,15 +631,15 @@ hipError_t bucket_scan(const float* xyz, const int32_t* label, const float* prob
                        const int64_t* off, int64_t nf, int32_t* wgbeam, const int64_t* scan_off,
                        const float* origins, int32_t S, float step, int32_t free_class,
                        const BucketGeom& g, PointSet& ps, BucketScratch& scr, uint32_t* err,
-                       hipStream_t st, const int64_t* dcnt) {
+                       hipStream_t st, const int64_t* dcnt, int32_t cap_slots) {
   if (ps.n <= 0) return hipSuccess;
   if (g.key_bits <= 32)
     return bucket_scan_t<uint32_t>(xyz, label, probs, K, n, kept, kpos, nk, off, nf, wgbeam,
                                    scan_off, origins, S, step, free_class, g, ps, scr, err, st,
-                                   dcnt);
+                                   dcnt, cap_slots);
   return bucket_scan_t<uint64_t>(xyz, label, probs, K, n, kept, kpos, nk, off, nf, wgbeam,
                                  scan_off, origins, S, step, free_class, g, ps, scr, err, st,
-                                 dcnt);
+                                 dcnt, cap_slots);
 }
 
 int64_t free_sample_workgroups(int64_t nf) { return nf > 0 ? ceil_div_i64(nf, FREE_WG) : 1; }

@@ -220,9 +220,9 @@ __global__ void k_batch_rows(const int64_t* __restrict__ sc, int64_t cap_rows,
   pc[2] = nt - nk;
 }
 
-__global__ void k_batch_units(const int32_t* __restrict__ d_nunits, int64_t cap_units,
-                              uint32_t* __restrict__ err) {
-  if (*d_nunits > cap_units) atomicOr(err, DEVERR_CAPACITY);
+__global__ void k_batch_units(const int32_t* __restrict__ si, int64_t cap_slots,
+                              int64_t cap_units, uint32_t* __restrict__ err) {
+  if (si[0] > cap_slots || si[2] > cap_units) atomicOr(err, DEVERR_CAPACITY);
 }
 
 __global__ void k_batch_alloc_check(const int32_t* __restrict__ cnt,
@@ -268,9 +268,9 @@ hipError_t launch_batch_rows(const int64_t* sc, int64_t cap_rows, int64_t* pc, u
   return hipGetLastError();
 }
 
-hipError_t launch_batch_units(const int32_t* d_nunits, int64_t cap_units, uint32_t* err,
-                              hipStream_t st) {
-  hipLaunchKernelGGL(k_batch_units, dim3(1), dim3(1), 0, st, d_nunits, cap_units, err);
+hipError_t launch_batch_units(const int32_t* si, int64_t cap_slots, int64_t cap_units,
+                              uint32_t* err, hipStream_t st) {
+  hipLaunchKernelGGL(k_batch_units, dim3(1), dim3(1), 0, st, si, cap_slots, cap_units, err);
   return hipGetLastError();
 }
 

@@ -643,7 +643,8 @@ smki_status insert_impl(smki_map* m, const float* xyz, const int32_t* label, con
   m->last.n_units = n_units;
   if ((double)n_units * (double)DR3 * sizeof(float) > 64.0 * (1ull << 30)) return SMKI_E_CAPACITY;
   m->last.n_candidates = nt * (int64_t)sten.offs.size();
-  m->last.n_lane_slots = nt * (int64_t)SMKI_WAVE * ((int64_t)(sten.offs.size() + SMKI_WAVE - 1) / SMKI_WAVE);
+  m->last.n_lane_slots =
+      sten.offs.empty() ? 0 : nt * splat_lane_slots_per_row((int32_t)sten.offs.size());
 
   // ---- phase C: splat, allocate, merge ----
   if (csm)
@@ -968,13 +969,13 @@ smki_status batch_enqueue(smki_batch* b, hipStream_t q) {
   scr.scan_tmp = d.scan_tmp;
   SMKI_HIP_TRY(bucket_scan(b->xyz, b->label, nullptr, m->K, n, d.kept, d.kpos, n, d.off,
                            b->cap_rows, d.wgbeam, d.soff, d.org, b->S, b->step, m->free_class, g,
-                           ps, scr, d.err, q, d.pc));
+                           ps, scr, d.err, q, d.pc, (int32_t)b->cap_slots));
   SMKI_HIP_TRY(launch_mark_targets(ps.slot_lin, ps.d_nslots, (int32_t)b->cap_slots, g, b->eblo,
                                    b->enb, 1, d.mark, q));
   SMKI_HIP_TRY(launch_slot_units(ps.head, ps.d_nslots, (int32_t)b->cap_slots, m->chunk, d.nun, q));
   SMKI_HIP_TRY(scan_excl_pair_i32(d.mark, d.mpos, ne, d.si + 1, d.nun, d.ust, b->cap_slots,
                                   d.si + 2, d.scan_tmp, q));
-  SMKI_HIP_TRY(launch_batch_units(d.si + 2, b->cap_units, d.err, q));
+  SMKI_HIP_TRY(launch_batch_units(d.si, b->cap_slots, b->cap_units, d.err, q));
   // splat, allocation, merge
   const Stencil& sten = b->sten;
   const int64_t DR = m->B + 2 * sten.R;
@@ -1371,8 +1372,7 @@ smki_status smki_last_scan_stats(smki_map* m, smki_scan_stats* out) {
     st.n_updated_voxels = o[0] ? 0 : (int64_t)s[0];
     st.n_pairs = (int64_t)s[1];
     st.n_candidates = o[3] * (int64_t)b->sten.offs.size();
-    st.n_lane_slots =
-        o[3] * (int64_t)SMKI_WAVE * ((int64_t)(b->sten.offs.size() + SMKI_WAVE - 1) / SMKI_WAVE);
+    st.n_lane_slots = o[3] * splat_lane_slots_per_row((int32_t)b->sten.offs.size());
     m->last = st;
     m->stats_pending = false;
   }
@@ -1622,17 +1622,30 @@ smki_status smki_batch_capture(smki_map* m, const float* xyz, const int32_t* lab
   b->S = S;
   b->step = free_step;
   const double grow = 1.0 + (double)margin;
-  // 2. the window: the voxel box of that insert, grown by margin of its extent per side
-  int32_t wlo[3], whi[3];
-  int64_t maxabs = 0;
+  // 2. the window: the voxel box of that insert grown by margin of its extent per
+  // side (at least two blocks), narrowed while that would widen the row keys
+  // past 32 bits (or past the insert's own key width)
+  const int kb0 = make_geom(m, m->last_vlo, m->last_vhi, m->K).key_bits;
+  int64_t pad[3];
   for (int a = 0; a < 3; ++a) {
     const int64_t ext = (int64_t)m->last_vhi[a] - m->last_vlo[a] + 1;
-    const int64_t pad = std::max<int64_t>(2 * m->B, (int64_t)ceil(margin * ext));
-    wlo[a] = (int32_t)std::max<int64_t>(m->last_vlo[a] - pad, -SMKI_COORD_LIM);
-    whi[a] = (int32_t)std::min<int64_t>(m->last_vhi[a] + pad, SMKI_COORD_LIM - 1);
-    maxabs = std::max<int64_t>(maxabs, std::max(std::abs((int64_t)wlo[a]), std::abs((int64_t)whi[a])));
+    pad[a] = std::max<int64_t>(2 * m->B, (int64_t)ceil(margin * ext));
   }
-  b->g = make_geom(m, wlo, whi, m->K);
+  int32_t wlo[3], whi[3];
+  int64_t maxabs = 0;
+  for (;;) {
+    maxabs = 0;
+    for (int a = 0; a < 3; ++a) {
+      wlo[a] = (int32_t)std::max<int64_t>(m->last_vlo[a] - pad[a], -SMKI_COORD_LIM);
+      whi[a] = (int32_t)std::min<int64_t>(m->last_vhi[a] + pad[a], SMKI_COORD_LIM - 1);
+      maxabs = std::max<int64_t>(maxabs, std::max(std::abs((int64_t)wlo[a]), std::abs((int64_t)whi[a])));
+    }
+    b->g = make_geom(m, wlo, whi, m->K);
+    bool shrink = false;
+    for (int a = 0; a < 3; ++a) shrink = shrink || pad[a] > 2 * m->B;
+    if (b->g.key_bits <= std::max(32, kb0) || !shrink) break;
+    for (int a = 0; a < 3; ++a) pad[a] = std::max<int64_t>(2 * m->B, pad[a] / 2);
+  }
   const BucketGeom& g = b->g;
   b->n_ext = 1;
   for (int a = 0; a < 3; ++a) {
@@ -1645,9 +1658,15 @@ smki_status smki_batch_capture(smki_map* m, const float* xyz, const int32_t* lab
   b->sten = make_stencil(lv, smargin);
   // 3. capacities
   b->cap_rows = std::max<int64_t>(n, (int64_t)ceil((double)(st.n_hits + st.n_free) * grow)) + 4096;
-  b->cap_slots = std::min<int64_t>(b->cap_rows, g.n_blocks * m->K);
+  b->cap_slots = std::min<int64_t>(std::min<int64_t>(b->cap_rows, g.n_blocks * m->K),
+                                   (int64_t)ceil((double)st.n_point_blocks * grow) + 1024);
   b->cap_units = (int64_t)ceil((double)st.n_units * grow) + 1024;
   const int64_t DR = m->B + 2 * b->sten.R;
+  // keep the partial sums under 4 GiB (32-bit offsets in the merge) when the
+  // sizing insert's fitted
+  const int64_t narrow_units = (int64_t(1) << 32) / (int64_t)(sizeof(float) * DR * DR * DR);
+  if (st.n_units <= narrow_units && !(m->flags & SMKI_FLAG_WIDE_OFFSETS))
+    b->cap_units = std::min(b->cap_units, narrow_units);
   if (g.n_blocks * m->K > (int64_t(1) << 30) || b->n_ext > (int64_t(1) << 30) ||
       b->n_ext * m->K > (int64_t)INT32_MAX / 2 || b->cap_rows > (int64_t)INT32_MAX - 1 ||
       b->sten.R > SMKI_MAX_REACH || b->sten.R > m->B ||

@@ -62,13 +62,14 @@ hipError_t launch_clear3(int32_t* z0, int64_t n0, int32_t* z1, int64_t n1, int32
 // hold -1 on entry (the caller clears it with its other buffers).
 // dcnt (device, nullable): [rows, hit rows, free samples] of the insert, read
 // by the kernels; nk, nf and ps.n are then capacities (launch sizes) and the
-// free samples start at row dcnt[1].
+// free samples start at row dcnt[1].  Slots past cap_slots are not stored.
 hipError_t bucket_scan(const float* xyz, const int32_t* label, const float* probs, int32_t K,
                        int64_t n, const int32_t* kept, const int32_t* kpos, int64_t nk,
                        const int64_t* off, int64_t nf, int32_t* wgbeam, const int64_t* scan_off,
                        const float* origins, int32_t S, float step, int32_t free_class,
                        const BucketGeom& g, PointSet& ps, BucketScratch& scr, uint32_t* err,
-                       hipStream_t st, const int64_t* dcnt = nullptr);
+                       hipStream_t st, const int64_t* dcnt = nullptr,
+                       int32_t cap_slots = INT32_MAX);
 // entries of bucket_scan's wgbeam scratch for nf free samples
 int64_t free_sample_workgroups(int64_t nf);
 hipError_t bucket_rows(const float* xyz, const int32_t* label, int64_t n, const BucketGeom& g,

@@ -18,6 +18,17 @@ static constexpr double kSmkiQ[SMKI_POLY_N] = {
     0.04696689938778598, -0.41528081234338315, 1.9962683906096352, -6.394682424213184,
     13.385465187748379,  -16.277320609426397,  8.658583627197082};
 
+// The splat's last 64-lane step is shared by two consecutive rows when it
+// holds at most 32 of the stencil's noff (>= 1) offsets; lane-iterations a row
+// then costs (a shared step counts half).
+__host__ __device__ inline bool splat_half_step(int32_t noff) {
+  return noff - SMKI_WAVE * ((noff - 1) / SMKI_WAVE) <= SMKI_WAVE / 2;
+}
+inline int64_t splat_lane_slots_per_row(int32_t noff) {
+  const int64_t ns = (noff + SMKI_WAVE - 1) / SMKI_WAVE;
+  return SMKI_WAVE * ns - (splat_half_step(noff) ? SMKI_WAVE / 2 : 0);
+}
+
 // Block hash and pools of the persistent map.  A block holds, per class, either
 // nothing (every voxel at the prior alpha0) or one class block of B^3
 // concentrations: only classes that some row ever reached take memory.
@@ -134,9 +145,10 @@ hipError_t launch_batch_start(const int64_t* hdr, int64_t* counts, unsigned long
 // hit rows, free samples] clamped to cap_rows (overflow: DEVERR_CAPACITY in err).
 hipError_t launch_batch_rows(const int64_t* sc, int64_t cap_rows, int64_t* pc, uint32_t* err,
                              hipStream_t st);
-// DEVERR_CAPACITY if the work units exceed cap_units
-hipError_t launch_batch_units(const int32_t* d_nunits, int64_t cap_units, uint32_t* err,
-                              hipStream_t st);
+// DEVERR_CAPACITY if the slots (si[0]) exceed cap_slots or the work units (si[2])
+// exceed cap_units
+hipError_t launch_batch_units(const int32_t* si, int64_t cap_slots, int64_t cap_units,
+                              uint32_t* err, hipStream_t st);
 // DEVERR_CAPACITY if the new blocks / class blocks (cnt[0], cnt[1]) do not fit the
 // map's pools (blocks, class blocks; the hash at most half full)
 hipError_t launch_batch_alloc_check(const int32_t* cnt, const int64_t* counts, int64_t pool_cap,
