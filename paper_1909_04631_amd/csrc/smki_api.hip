@@ -643,8 +643,7 @@ smki_status insert_impl(smki_map* m, const float* xyz, const int32_t* label, con
   m->last.n_units = n_units;
   if ((double)n_units * (double)DR3 * sizeof(float) > 64.0 * (1ull << 30)) return SMKI_E_CAPACITY;
   m->last.n_candidates = nt * (int64_t)sten.offs.size();
-  m->last.n_lane_slots =
-      sten.offs.empty() ? 0 : nt * splat_lane_slots_per_row((int32_t)sten.offs.size());
+  m->last.n_lane_slots = nt * (int64_t)SMKI_WAVE * ((int64_t)(sten.offs.size() + SMKI_WAVE - 1) / SMKI_WAVE);
 
   // ---- phase C: splat, allocate, merge ----
   if (csm)
@@ -1372,7 +1371,8 @@ smki_status smki_last_scan_stats(smki_map* m, smki_scan_stats* out) {
     st.n_updated_voxels = o[0] ? 0 : (int64_t)s[0];
     st.n_pairs = (int64_t)s[1];
     st.n_candidates = o[3] * (int64_t)b->sten.offs.size();
-    st.n_lane_slots = o[3] * splat_lane_slots_per_row((int32_t)b->sten.offs.size());
+    st.n_lane_slots =
+        o[3] * (int64_t)SMKI_WAVE * ((int64_t)(b->sten.offs.size() + SMKI_WAVE - 1) / SMKI_WAVE);
     m->last = st;
     m->stats_pending = false;
   }

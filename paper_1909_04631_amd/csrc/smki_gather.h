@@ -18,17 +18,6 @@ static constexpr double kSmkiQ[SMKI_POLY_N] = {
     0.04696689938778598, -0.41528081234338315, 1.9962683906096352, -6.394682424213184,
     13.385465187748379,  -16.277320609426397,  8.658583627197082};
 
-// The splat's last 64-lane step is shared by two consecutive rows when it
-// holds at most 32 of the stencil's noff (>= 1) offsets; lane-iterations a row
-// then costs (a shared step counts half).
-__host__ __device__ inline bool splat_half_step(int32_t noff) {
-  return noff - SMKI_WAVE * ((noff - 1) / SMKI_WAVE) <= SMKI_WAVE / 2;
-}
-inline int64_t splat_lane_slots_per_row(int32_t noff) {
-  const int64_t ns = (noff + SMKI_WAVE - 1) / SMKI_WAVE;
-  return SMKI_WAVE * ns - (splat_half_step(noff) ? SMKI_WAVE / 2 : 0);
-}
-
 // Block hash and pools of the persistent map.  A block holds, per class, either
 // nothing (every voxel at the prior alpha0) or one class block of B^3
 // concentrations: only classes that some row ever reached take memory.

@@ -168,16 +168,12 @@ __device__ __forceinline__ int pbase(int p) {
 
 // NS = ceil(stencil size / 64), the steps each row takes (compiled per value
 // so that the steps of a row are independent straight-line code).  W: rows carry
-// a weight (soft measurements) that scales their kernel values.  HALF: the
-// stencil's last step holds at most 32 offsets, and two consecutive rows share
-// it (lanes 0-31 take the first row's last offsets, lanes 32-63 the second's),
-// so a row costs NS - 1/2 steps instead of NS.
-template <int B, int R, int NS, bool W, bool HALF>
+// a weight (soft measurements) that scales their kernel values.
+template <int B, int R, int NS, bool W>
 __global__ void __launch_bounds__(SMKI_WAVE) k_splat(SplatArgs a) {
   constexpr int DR = B + 2 * R;                 // region edge (voxels)
   constexpr int DR3 = DR * DR * DR;
   constexpr int NACC4 = (DR3 + 1 + 3) / 4;
-  constexpr int NF = HALF ? NS - 1 : NS;        // steps a row takes on its own
   __shared__ float4 acc4[NACC4];   // the region + a dummy slot for pad lanes
   float* acc = (float*)acc4;
   const int lane = threadIdx.x;
@@ -196,18 +192,13 @@ __global__ void __launch_bounds__(SMKI_WAVE) k_splat(SplatArgs a) {
   // cell + (sx ox, sy oy, sz oz), at the distance from |u| to o.
   // The squared distance is evaluated as |q|^2 + |w|^2 - 2 q.w (q: the row's
   // |u|, at most res sqrt(3)/2; w: the offset's centre): nw = -2 w, w2 = |w|^2.
-  // The shared step (HALF) maps lane i to offset (NS-1) 64 + (i mod 32) and
-  // keeps the offset itself (hx, hy, hz): its rows differ between the halves,
-  // so the octant mirror is applied per lane.
   float nwx[NS], nwy[NS], nwz[NS], w2[NS];
   int32_t wl[8][NS];
   bool pad[NS];
-  int32_t hx = 0, hy = 0, hz = 0;
   const double res = (double)a.g.res;
 #pragma unroll
   for (int s = 0; s < NS; ++s) {
-    const bool shared_step = HALF && s == NS - 1;
-    const int o = s * SMKI_WAVE + (shared_step ? (lane & 31) : lane);
+    const int o = s * SMKI_WAVE + lane;
     pad[s] = o >= a.noff;
     int4 off = a.offs[min(o, a.noff - 1)];   // unconditional load, pad lanes reset below
     if (pad[s]) off = make_int4(0, 0, 0, 0);
@@ -217,11 +208,6 @@ __global__ void __launch_bounds__(SMKI_WAVE) k_splat(SplatArgs a) {
       nwy[s] = (float)(-2.0 * y);
       nwz[s] = (float)(-2.0 * z);
       w2[s] = pad[s] ? 1.0e30f : (float)(x * x + y * y + z * z);   // pad: never within l
-    }
-    if (shared_step) {
-      hx = off.x;
-      hy = off.y;
-      hz = off.z;
     }
 #pragma unroll
     for (int oc = 0; oc < 8; ++oc)
@@ -240,7 +226,7 @@ __global__ void __launch_bounds__(SMKI_WAVE) k_splat(SplatArgs a) {
   // offset) use a dummy slot past the region.  Within one flush the lanes'
   // addresses are distinct; the LDS executes one wavefront's reads and writes
   // in issue order and the compiler keeps flushes in program order (signal
-  // fence), so every voxel sums its rows in a fixed order.
+  // fence), so every voxel sums its rows in row order.
   auto flush = [&]() {
     const int oc = gkey & 7;
     int32_t base[NS];
@@ -252,9 +238,9 @@ __global__ void __launch_bounds__(SMKI_WAVE) k_splat(SplatArgs a) {
 #define SMKI_FLUSH_CASE(OC)                                                  \
   case OC: {                                                                 \
     float old[NS];                                                           \
-    _Pragma("unroll") for (int s = 0; s < NF; ++s)                           \
+    _Pragma("unroll") for (int s = 0; s < NS; ++s)                           \
         old[s] = acc[base[s] + wl[OC][s]];                                   \
-    _Pragma("unroll") for (int s = 0; s < NF; ++s)                           \
+    _Pragma("unroll") for (int s = 0; s < NS; ++s)                           \
         acc[base[s] + wl[OC][s]] = fmaf(cscale, sum[s], old[s]);             \
     break;                                                                   \
   }
@@ -264,20 +250,6 @@ __global__ void __launch_bounds__(SMKI_WAVE) k_splat(SplatArgs a) {
     }
 #pragma unroll
     for (int s = 0; s < NS; ++s) sum[s] = 0.0f;
-  };
-  // Kernel weight of one lane's pair: s = 1 - d/l clamped to [0, 1] (the clamp
-  // is free on the fused multiply-add) is 0 out of support, which zeroes the
-  // weight s^5 Q(s^2).  |d2| only guards rounding below 0 when the row sits on
-  // the voxel centre.
-  // Returns acc + that weight (one fused multiply-add).
-  auto add_weight = [&](float d2, float wr, float acc_in) {
-    const float d = __builtin_amdgcn_sqrtf(fabsf(d2));
-    const float sv = __builtin_amdgcn_fmed3f(fmaf(-d, inv_l, 1.0f), 0.0f, 1.0f);
-    const float uu = sv * sv;
-    float qq = uu + a.mcoef[1];
-#pragma unroll
-    for (int i = 2; i < SMKI_POLY_N; ++i) qq = fmaf(qq, uu, a.mcoef[i]);
-    return W ? fmaf(uu * uu, (sv * wr) * qq, acc_in) : fmaf(uu * uu, sv * qq, acc_in);
   };
   // Rows are staged 64 at a time in registers (lane i holds row base + i) and
   // broadcast with v_readlane; two batches alternate so that one loads while
@@ -309,9 +281,7 @@ __global__ void __launch_bounds__(SMKI_WAVE) k_splat(SplatArgs a) {
     if (W) asm volatile("" ::"v"(bt.w));
     // |q|^2 of every row of the batch, once per lane
     const float q2l = fmaf(cur.x, cur.x, fmaf(cur.y, cur.y, cur.z * cur.z));
-    // the steps row j takes on its own, its sums kept per lane in registers
-    // while consecutive rows share a (cell, octant) group
-    auto own_steps = [&](int j) {
+    for (int j = 0; j < nb; ++j) {
       const float qx = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(cur.x), j));
       const float qy = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(cur.y), j));
       const float qz = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(cur.z), j));
@@ -324,60 +294,30 @@ __global__ void __launch_bounds__(SMKI_WAVE) k_splat(SplatArgs a) {
         gcb = ((c / (B * B) + R) * DR + ((c / B) % B + R)) * DR + (c % B + R);
       }
       const float q2 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(q2l), j));
+      // Branch-free: every lane evaluates its pair; s = 1 - d/l clamped to [0, 1]
+      // (the clamp is free on the fused multiply-add) is 0 out of support, which
+      // zeroes the weight s^5 Q(s^2).
 #pragma unroll
-      for (int s = 0; s < NF; ++s) {
+      for (int s = 0; s < NS; ++s) {
+        // |d2| only guards rounding below 0 when the row sits on the voxel centre
         const float d2 = fmaf(qz, nwz[s], fmaf(qy, nwy[s], fmaf(qx, nwx[s], q2 + w2[s])));
         const bool in = d2 < l2;
         const uint64_t inm = __ballot(in);
         npair += (uint32_t)__popcll(inm);
         // the last step holds the farthest offsets (the stencil is ordered by
         // distance): a row that reaches none of them skips it
-        if (!HALF && NS > 1 && s == NS - 1 && inm == 0) continue;
-        sum[s] = add_weight(d2, wr, sum[s]);
+        if (NS > 1 && s == NS - 1 && inm == 0) continue;
+        const float d = __builtin_amdgcn_sqrtf(fabsf(d2));
+        const float sv = __builtin_amdgcn_fmed3f(fmaf(-d, inv_l, 1.0f), 0.0f, 1.0f);
+        const float uu = sv * sv;
+        float qq = uu + a.mcoef[1];
+#pragma unroll
+        for (int i = 2; i < SMKI_POLY_N; ++i) qq = fmaf(qq, uu, a.mcoef[i]);
+        if (W)
+          sum[s] = fmaf(uu * uu, (sv * wr) * qq, sum[s]);
+        else
+          sum[s] = fmaf(uu * uu, sv * qq, sum[s]);
       }
-    };
-    if (!HALF) {
-      for (int j = 0; j < nb; ++j) own_steps(j);
-      return;
-    }
-    for (int j = 0; j < nb; j += 2) {
-      const bool has2 = j + 1 < nb;   // (uniform)
-      if (NF > 0) {
-        own_steps(j);
-        if (has2) own_steps(j + 1);
-      }
-      // The shared step: lanes 0-31 row j, lanes 32-63 row j + 1.
-      const int j2 = has2 ? j + 1 : j;
-      const bool upper = lane >= 32;
-      const bool live = !upper || has2;
-      // both rows broadcast, each half selects its own
-      auto pick = [&](float v) {
-        const float va = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), j));
-        const float vb = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), j2));
-        return upper ? vb : va;
-      };
-      const float qx = pick(cur.x), qy = pick(cur.y), qz = pick(cur.z), q2 = pick(q2l);
-      const int32_t key = __float_as_int(pick(cur.w));
-      const float wr = W ? pick(bt.w) : 1.0f;
-      constexpr int S = NS - 1;
-      const float d2 = fmaf(qz, nwz[S], fmaf(qy, nwy[S], fmaf(qx, nwx[S], q2 + w2[S])));
-      const bool in = live && d2 < l2;
-      const uint64_t inm = __ballot(in);
-      npair += (uint32_t)__popcll(inm);
-      if (inm == 0) continue;   // neither row reaches its far offsets
-      const float v = live ? add_weight(d2, wr, 0.0f) : 0.0f;
-      // the lane's voxel: its row's cell, its offset mirrored into the row's octant
-      const int c = key >> 3, oc = key & 7;
-      int32_t idx = ((c / (B * B) + R) * DR + ((c / B) % B + R)) * DR + (c % B + R) +
-                    ((oc & 1) ? -hx : hx) * (DR * DR) + ((oc & 2) ? -hy : hy) * DR +
-                    ((oc & 4) ? -hz : hz);
-      if (pad[S] || !live) idx = DR3;   // dummy slot
-      // the two halves add in turn: their voxels may coincide
-      __atomic_signal_fence(__ATOMIC_SEQ_CST);
-      if (!upper) acc[idx] = fmaf(cscale, v, acc[idx]);
-      __atomic_signal_fence(__ATOMIC_SEQ_CST);
-      if (upper) acc[idx] = fmaf(cscale, v, acc[idx]);
-      __atomic_signal_fence(__ATOMIC_SEQ_CST);
     }
   };
   Batch ba = load_batch(load_index(r0));
@@ -792,25 +732,16 @@ __global__ void k_assign(MapDev m, SplatArgs a, int32_t n_targets,
   atomicOr(err, DEVERR_HASH);
 }
 
-template <int B, int R, int NSV, bool HALF>
-void launch_splat_w(const SplatArgs& a, int64_t n_units, hipStream_t st) {
-  if (a.wts)
-    hipLaunchKernelGGL((k_splat<B, R, NSV, true, HALF>), dim3((unsigned)n_units), dim3(SMKI_WAVE),
-                       0, st, a);
-  else
-    hipLaunchKernelGGL((k_splat<B, R, NSV, false, HALF>), dim3((unsigned)n_units),
-                       dim3(SMKI_WAVE), 0, st, a);
-}
-
 template <int B, int R, int NSV>
 hipError_t launch_splat_ns(const SplatArgs& a, int64_t n_units, int ns, hipStream_t st) {
   if constexpr (NSV >= Steps<R>::NSMIN) {
     if (ns == NSV) {
-      // a last step of at most 32 offsets is shared by two rows
-      if (splat_half_step(a.noff))
-        launch_splat_w<B, R, NSV, true>(a, n_units, st);
+      if (a.wts)
+        hipLaunchKernelGGL((k_splat<B, R, NSV, true>), dim3((unsigned)n_units), dim3(SMKI_WAVE), 0,
+                           st, a);
       else
-        launch_splat_w<B, R, NSV, false>(a, n_units, st);
+        hipLaunchKernelGGL((k_splat<B, R, NSV, false>), dim3((unsigned)n_units), dim3(SMKI_WAVE),
+                           0, st, a);
       return hipGetLastError();
     }
     return launch_splat_ns<B, R, NSV - 1>(a, n_units, ns, st);
