@@ -104,8 +104,12 @@ const char *smki_status_string(smki_status s);
  *   res         voxel edge in metres (> 0); voxel (i,j,k) has its centroid at
  *               ((i+1/2) res, (j+1/2) res, (k+1/2) res) -- the query points of
  *               Eq. (7) are the grid centroids (Sec. IV, after Eq. (8)).
- *   block_size  voxels per block edge: 4 or 8 (blocks group the grid
- *               as in Sec. IV; allocation granularity).
+ *   block_size  voxels per block edge, a power of two in [1, 32]: the block of
+ *               Sec. IV, an octree of grids of depth d holds 2^(d-1) voxels per
+ *               edge (depth 1: one voxel).  The counting model serves every
+ *               size; S-BKI inserts need B in {2, 4, 8, 16} and a kernel reach
+ *               of at most B voxels (else SMKI_E_CAPACITY; see
+ *               smki_insert_scan).
  *   l, sigma0   length-scale (> 0) and scale (> 0) of the sparse kernel, Eq. (8).
  *   K           classes (2..255), free class included.
  *   alpha0      Dirichlet prior concentration of every class (> 0), Sec. III.
@@ -144,6 +148,24 @@ smki_status smki_kernel_times(smki_map *m, int32_t max, float *splat_ms, float *
 smki_status smki_set_stream(smki_map *m, void *hip_stream);
 
 /*
+ * Device memory of the map's growable buffers (block hash, block and class-
+ * block pools, insert workspaces, recorded batches): alloc(bytes, ctx) returns
+ * device memory of the map's device (aligned to at least 256 bytes) or NULL
+ * on failure (the call needing it then returns SMKI_E_OOM); release(ptr, ctx)
+ * gives back memory alloc returned.  Buffers are released by the allocator
+ * that made them, once the map's stream no longer uses them (the map
+ * synchronises before it releases).  Both NULL: hipMalloc / hipFree (the
+ * default).  Applies to allocations after the call; a few small fixed
+ * buffers made at creation always use hipMalloc.  The callbacks run on the
+ * thread that calls into the map.  Errors: SMKI_E_INVALID_ARG (exactly one
+ * of alloc, release NULL).
+ */
+typedef void *(*smki_alloc_fn)(size_t bytes, void *ctx);
+typedef void (*smki_release_fn)(void *ptr, void *ctx);
+smki_status smki_set_allocator(smki_map *m, smki_alloc_fn alloc, smki_release_fn release,
+                               void *ctx);
+
+/*
  * Insert one labelled scan: Eq. (7) with the kernel of Eq. (8), applied at
  * every voxel centroid and added to the map (the recursive update of Sec. IV).
  * The training rows are the hits with label != -1 and, for each of them, the
@@ -155,9 +177,11 @@ smki_status smki_set_stream(smki_map *m, void *hip_stream);
  * to size its launches).  Errors: SMKI_E_BAD_INPUT for a label outside
  * {-1..K-1} or a non-finite kept coordinate, SMKI_E_RANGE for a voxel index
  * outside [-2^20, 2^20) or a beam with more than 2^20 samples, SMKI_E_CAPACITY
- * when l / res >= 4.5 voxels (the kernel support reaches at most 4 voxels past
- * a row's own voxel) or the scan's bounding box spans more than 2^30 / K
- * blocks; on any error the map is left unchanged.
+ * when the kernel's reach R (the voxels a row's support extends past its own
+ * voxel: R = ceil(l / res + 1/2) - 1, at most 4, so l / res < 4.5) exceeds 4 or
+ * the block size B, when B is not 2, 4, 8 or 16 (S-BKI), or when the scan's
+ * bounding box spans more than 2^30 / K blocks; on any error the map is left
+ * unchanged.
  */
 smki_status smki_insert_scan(smki_map *m, const float *xyz, const int32_t *label, int64_t n,
                              const float *origin, float free_step);

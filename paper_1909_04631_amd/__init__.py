@@ -13,7 +13,8 @@ import ctypes as C
 
 import torch
 
-from ._lib import FLAG_WIDE_OFFSETS, MODELS, SELECTIONS, SmkiError, ScanStats, Options, check, lib
+from ._lib import (ALLOC_FN, FLAG_WIDE_OFFSETS, MODELS, RELEASE_FN, SELECTIONS, SmkiError,
+                   ScanStats, Options, check, lib)
 
 __all__ = ["SemanticMap", "SmkiError", "free_samples", "bucket_cells", "loss_forward",
            "loss_backward", "PredictiveLoss", "predictive_loss", "loss_forward_classes",
@@ -84,12 +85,16 @@ class SemanticMap:
 
     def __init__(self, res, block_size, l, sigma0, K, alpha0=1e-3, free_class=0,
                  unit_budget=0, initial_blocks=0, model="sbki", selection="exact",
-                 wide_offsets=False):
+                 wide_offsets=False, allocator="torch"):
         """model: "sbki" (Eq. 7-8, the default) or "scsm" (counting model, Eq. 2).
         selection: "exact" (every row within l) or "face_blocks" (rows of the
         voxel's block and its six face neighbours, the paper's extended block).
         wide_offsets: address partial sums with 64-bit offsets at any size
-        (SMKI_FLAG_WIDE_OFFSETS)."""
+        (SMKI_FLAG_WIDE_OFFSETS).  allocator: "torch" (the map's growable
+        buffers come from torch's caching allocator, smki_set_allocator) or
+        None (hipMalloc)."""
+        if allocator not in ("torch", None):
+            raise ValueError('allocator must be "torch" or None')
         if model not in MODELS:
             raise ValueError(f"model must be one of {sorted(MODELS)}")
         if selection not in SELECTIONS:
@@ -105,6 +110,27 @@ class SemanticMap:
         check(lib().smki_create_map(res, block_size, l, sigma0, K, alpha0, free_class,
                                     C.byref(opt), C.byref(h)), "smki_create_map")
         self._h = h
+        self._alloc = None
+        if allocator == "torch":
+            dev = self.device
+
+            def _alloc(nbytes, ctx):
+                try:
+                    return torch.cuda.caching_allocator_alloc(
+                        int(nbytes), dev, torch.cuda.current_stream(dev))
+                except Exception:
+                    return None
+
+            def _release(ptr, ctx):
+                try:
+                    torch.cuda.caching_allocator_delete(int(ptr))
+                except Exception:
+                    pass
+
+            # (the callback objects must outlive the map)
+            self._alloc = (ALLOC_FN(_alloc), RELEASE_FN(_release))
+            check(lib().smki_set_allocator(self._h, self._alloc[0], self._alloc[1], None),
+                  "smki_set_allocator")
 
     @classmethod
     def from_params(cls, p, **kw):

@@ -19,7 +19,7 @@ STATUS_NAMES = {
 # every symbol include/smki.h declares
 EXPORTED = [
     "smki_status_string", "smki_create_map", "smki_destroy_map", "smki_set_class_params",
-    "smki_set_stream", "smki_insert_scan", "smki_insert_scan_soft", "smki_insert_scans",
+    "smki_set_stream", "smki_set_allocator", "smki_insert_scan", "smki_insert_scan_soft", "smki_insert_scans",
     "smki_query", "smki_num_blocks", "smki_export", "smki_import", "smki_kernel_times", "smki_last_scan_stats", "smki_sync", "smki_free_samples", "smki_bucket_cells",
     "smki_loss_workspace_bytes", "smki_loss_forward", "smki_loss_backward",
     "smki_loss_forward_classes", "smki_loss_backward_classes", "smki_loss_forward_noalloc",
@@ -45,6 +45,10 @@ class Options(C.Structure):
 
 
 FLAG_WIDE_OFFSETS = 1
+
+# smki_alloc_fn / smki_release_fn
+ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p)
+RELEASE_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_void_p)
 
 
 MODELS = {"sbki": 0, "scsm": 1}
@@ -83,6 +87,8 @@ def lib():
     L.smki_destroy_map.argtypes = [vp]
     L.smki_set_stream.restype = st
     L.smki_set_stream.argtypes = [vp, vp]
+    L.smki_set_allocator.restype = st
+    L.smki_set_allocator.argtypes = [vp, ALLOC_FN, RELEASE_FN, vp]
     L.smki_kernel_times.restype = st
     L.smki_kernel_times.argtypes = [vp, i32, C.POINTER(C.c_float), C.POINTER(C.c_float),
                                     C.POINTER(C.c_int32)]

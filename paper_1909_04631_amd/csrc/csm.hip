@@ -18,11 +18,14 @@ inline unsigned nblk(int64_t n, int t) { return (unsigned)ceil_div_i64(n > 0 ? n
 // One thread per row; the last row of each run of equal keys (one class in one
 // voxel: keys are sorted by (class, block, voxel)) finds the run's first row by
 // binary search and adds the run length to that voxel's class.
+// Words of voxel bits per target block.
+constexpr int vbit_words(int B) { return (B * B * B + 31) / 32; }
+
 template <typename KeyT, int B>
 __global__ void k_csm_counts(SplatArgs a, const KeyT* __restrict__ keys, int64_t n,
                              uint32_t* __restrict__ vbits) {
   constexpr int B3 = B * B * B;
-  constexpr int L3 = B == 8 ? 9 : 6;   // bits of the voxel cell in the key
+  constexpr int L3 = B == 1 ? 0 : B == 2 ? 3 : B == 4 ? 6 : B == 8 ? 9 : B == 16 ? 12 : 15;   // cell bits
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   const KeyT k = keys[i];
@@ -51,7 +54,7 @@ __global__ void k_csm_counts(SplatArgs a, const KeyT* __restrict__ keys, int64_t
     add = (float)sw;
   }
   a.map.calpha[(int64_t)cb * B3 + c] += add;
-  atomicOr(&vbits[(int64_t)t * (B3 / 32) + (c >> 5)], 1u << (c & 31));
+  atomicOr(&vbits[(int64_t)t * vbit_words(B) + (c >> 5)], 1u << (c & 31));
 }
 
 // voxels with at least one row: popcount of the per-target voxel bits
@@ -77,17 +80,22 @@ hipError_t launch_csm_counts(const SplatArgs& a, const void* keys, bool wide_key
                              uint32_t* vbits, int64_t n_targets, hipStream_t st) {
   if (n <= 0) return hipSuccess;
   const dim3 grid(nblk(n, 256)), block(256);
-  if (a.g.B == 8 && !wide_keys)
-    hipLaunchKernelGGL((k_csm_counts<uint32_t, 8>), grid, block, 0, st, a, (const uint32_t*)keys, n, vbits);
-  else if (a.g.B == 8)
-    hipLaunchKernelGGL((k_csm_counts<uint64_t, 8>), grid, block, 0, st, a, (const uint64_t*)keys, n, vbits);
-  else if (a.g.B == 4 && !wide_keys)
-    hipLaunchKernelGGL((k_csm_counts<uint32_t, 4>), grid, block, 0, st, a, (const uint32_t*)keys, n, vbits);
-  else if (a.g.B == 4)
-    hipLaunchKernelGGL((k_csm_counts<uint64_t, 4>), grid, block, 0, st, a, (const uint64_t*)keys, n, vbits);
-  else
-    return hipErrorInvalidValue;
-  const int64_t nwords = n_targets * (int64_t)(a.g.B * a.g.B * a.g.B / 32);
+#define SMKI_CSM_CASE(BB)                                                                    \
+  case BB:                                                                                  \
+    if (wide_keys)                                                                          \
+      hipLaunchKernelGGL((k_csm_counts<uint64_t, BB>), grid, block, 0, st, a,               \
+                         (const uint64_t*)keys, n, vbits);                                  \
+    else                                                                                    \
+      hipLaunchKernelGGL((k_csm_counts<uint32_t, BB>), grid, block, 0, st, a,               \
+                         (const uint32_t*)keys, n, vbits);                                  \
+    break;
+  switch (a.g.B) {
+    SMKI_CSM_CASE(1) SMKI_CSM_CASE(2) SMKI_CSM_CASE(4) SMKI_CSM_CASE(8) SMKI_CSM_CASE(16)
+    SMKI_CSM_CASE(32)
+    default: return hipErrorInvalidValue;
+  }
+#undef SMKI_CSM_CASE
+  const int64_t nwords = n_targets * (int64_t)((a.g.B * a.g.B * a.g.B + 31) / 32);
   hipLaunchKernelGGL(k_csm_voxels, dim3(nblk(nwords, 256)), dim3(256), 0, st, vbits, nwords,
                      &a.stats[0]);
   return hipGetLastError();

@@ -32,26 +32,50 @@ namespace {
 
 constexpr size_t kAlign = 256;
 
+// Device memory of a map's growable buffers: the caller's allocator
+// (smki_set_allocator) or hipMalloc / hipFree.  Every buffer is released by
+// the allocator that made it.
+struct Allocator {
+  smki_alloc_fn alloc = nullptr;
+  smki_release_fn release = nullptr;
+  void* ctx = nullptr;
+};
+
+hipError_t dev_alloc(const Allocator& A, void** p, size_t bytes) {
+  if (!A.alloc) return hipMalloc(p, bytes);
+  *p = A.alloc(bytes, A.ctx);
+  return *p ? hipSuccess : hipErrorOutOfMemory;
+}
+
+void dev_release(const Allocator& A, void* p) {
+  if (!p) return;
+  if (A.release)
+    A.release(p, A.ctx);
+  else
+    (void)hipFree(p);
+}
+
 // A growable device region carved into aligned sub-buffers per phase.
 struct Arena {
   char* base = nullptr;
   size_t cap = 0;
   size_t used = 0;
-  hipError_t reserve(size_t bytes) {
+  Allocator by;   // the allocator of base
+  hipError_t reserve(size_t bytes, const Allocator& now = Allocator{}) {
     used = 0;
     if (bytes <= cap) return hipSuccess;
     if (base) {
       // work queued on any stream may still read the old region
       hipError_t e = hipDeviceSynchronize();
       if (e != hipSuccess) return e;
-      e = hipFree(base);
-      if (e != hipSuccess) return e;
+      dev_release(by, base);
       base = nullptr;
       cap = 0;
     }
     const size_t want = bytes + bytes / 4 + (1 << 20);
-    hipError_t e = hipMalloc((void**)&base, want);
+    hipError_t e = dev_alloc(now, (void**)&base, want);
     if (e != hipSuccess) return e;
+    by = now;
     cap = want;
     return hipSuccess;
   }
@@ -62,7 +86,7 @@ struct Arena {
     return (T*)(base + off);
   }
   void release() {
-    if (base) (void)hipFree(base);
+    dev_release(by, base);
     base = nullptr;
     cap = used = 0;
   }
@@ -158,6 +182,8 @@ struct smki_map {
   bool host_counts_valid = true;
   int64_t epoch = 0;
   smki_batch* stats_batch = nullptr;   // the replay whose counters smki_last_scan_stats reports
+  // allocator of new growable buffers, and the one that made each current buffer
+  Allocator alloc_now, by_hash, by_pool, by_cpool;
   int32_t last_vlo[3] = {0, 0, 0}, last_vhi[3] = {0, 0, 0};   // voxel box of the last insert
 };
 
@@ -206,6 +232,14 @@ Stencil make_stencil(double lv, double margin) {
   return s;
 }
 
+// Block sizes and reaches the S-BKI kernels serve: B in {2, 4, 8, 16}, reach
+// R <= B (a row's region covers its own block and the 26 around it) and at
+// most SMKI_MAX_REACH; the splat's LDS region (B + 2R)^3 floats stays under
+// 64 KiB for all of them.
+bool sbki_shape_ok(int32_t B, int32_t R) {
+  return (B == 2 || B == 4 || B == 8 || B == 16) && R <= B && R <= SMKI_MAX_REACH;
+}
+
 hipError_t sync_read(smki_map* m, const void* dev, size_t bytes, void* host) {
   hipError_t e = hipMemcpyAsync(host, dev, bytes, hipMemcpyDeviceToHost, m->stream);
   if (e != hipSuccess) return e;
@@ -218,10 +252,10 @@ smki_status ensure_pool(smki_map* m, int64_t need) {
   const int64_t cap = std::max<int64_t>(need, m->pool_cap * 2);
   int32_t* ncs = nullptr;
   uint64_t* nk = nullptr;
-  SMKI_HIP_TRY(hipMalloc((void**)&ncs, sizeof(int32_t) * m->K * cap));
-  hipError_t e = hipMalloc((void**)&nk, sizeof(uint64_t) * cap);
+  SMKI_HIP_TRY(dev_alloc(m->alloc_now, (void**)&ncs, sizeof(int32_t) * m->K * cap));
+  hipError_t e = dev_alloc(m->alloc_now, (void**)&nk, sizeof(uint64_t) * cap);
   if (e != hipSuccess) {
-    (void)hipFree(ncs);
+    dev_release(m->alloc_now, ncs);
     return smki_hip_error(e);
   }
   if (m->n_blocks > 0) {
@@ -231,8 +265,9 @@ smki_status ensure_pool(smki_map* m, int64_t need) {
                                 hipMemcpyDeviceToDevice, m->stream));
   }
   SMKI_HIP_TRY(hipStreamSynchronize(m->stream));
-  if (m->dev.cslot) (void)hipFree(m->dev.cslot);
-  if (m->dev.bkeys) (void)hipFree(m->dev.bkeys);
+  dev_release(m->by_pool, m->dev.cslot);
+  dev_release(m->by_pool, m->dev.bkeys);
+  m->by_pool = m->alloc_now;
   m->dev.cslot = ncs;
   m->dev.bkeys = nk;
   m->pool_cap = cap;
@@ -246,12 +281,13 @@ smki_status ensure_cpool(smki_map* m, int64_t need) {
   const int64_t cap = std::max<int64_t>(need, m->cpool_cap * 2);
   const size_t per = (size_t)m->B * m->B * m->B;
   float* na = nullptr;
-  SMKI_HIP_TRY(hipMalloc((void**)&na, sizeof(float) * per * cap));
+  SMKI_HIP_TRY(dev_alloc(m->alloc_now, (void**)&na, sizeof(float) * per * cap));
   if (m->n_cblocks > 0)
     SMKI_HIP_TRY(hipMemcpyAsync(na, m->dev.calpha, sizeof(float) * per * m->n_cblocks,
                                 hipMemcpyDeviceToDevice, m->stream));
   SMKI_HIP_TRY(hipStreamSynchronize(m->stream));
-  if (m->dev.calpha) (void)hipFree(m->dev.calpha);
+  dev_release(m->by_cpool, m->dev.calpha);
+  m->by_cpool = m->alloc_now;
   m->dev.calpha = na;
   m->cpool_cap = cap;
   ++m->epoch;
@@ -265,15 +301,16 @@ smki_status ensure_hash(smki_map* m, int64_t blocks) {
   while (cap < 2 * blocks) cap *= 2;
   uint64_t* hk = nullptr;
   int32_t* hv = nullptr;
-  SMKI_HIP_TRY(hipMalloc((void**)&hk, sizeof(uint64_t) * cap));
-  hipError_t e = hipMalloc((void**)&hv, sizeof(int32_t) * cap);
+  SMKI_HIP_TRY(dev_alloc(m->alloc_now, (void**)&hk, sizeof(uint64_t) * cap));
+  hipError_t e = dev_alloc(m->alloc_now, (void**)&hv, sizeof(int32_t) * cap);
   if (e != hipSuccess) {
-    (void)hipFree(hk);
+    dev_release(m->alloc_now, hk);
     return smki_hip_error(e);
   }
   SMKI_HIP_TRY(hipStreamSynchronize(m->stream));
-  if (m->dev.hkeys) (void)hipFree(m->dev.hkeys);
-  if (m->dev.hvals) (void)hipFree(m->dev.hvals);
+  dev_release(m->by_hash, m->dev.hkeys);
+  dev_release(m->by_hash, m->dev.hvals);
+  m->by_hash = m->alloc_now;
   m->dev.hkeys = hk;
   m->dev.hvals = hv;
   m->dev.hcap = cap;
@@ -373,13 +410,14 @@ smki_status insert_csm(smki_map* m, const BucketGeom& g, const PointSet& ps,
   for (int i = 0; i < 5; ++i) zc.add<int32_t>(n_t);
   zc.add<int32_t>(8);
   zc.add<char>(scan_tmp_bytes(std::max<int64_t>(ntk, 1)));
-  zc.add<uint32_t>((size_t)n_t * (B3 / 32));
+  const int64_t vwords = (B3 + 31) / 32;   // voxel bits per target block
+  zc.add<uint32_t>((size_t)n_t * vwords);
   for (int i = 0; i < 3; ++i) zc.add<int32_t>(ntk);
-  SMKI_HIP_TRY(m->a_tgts.reserve(zc.total));
+  SMKI_HIP_TRY(m->a_tgts.reserve(zc.total, m->alloc_now));
   Arena& C = m->a_tgts;
   // cleared together: counts, voxel bits, contribution flags
   int32_t* d_cnt = C.take<int32_t>(8);
-  uint32_t* d_vbits = C.take<uint32_t>((size_t)n_t * (B3 / 32));
+  uint32_t* d_vbits = C.take<uint32_t>((size_t)n_t * vwords);
   int32_t* d_contrib = C.take<int32_t>(ntk);
   int32_t* d_tgt = C.take<int32_t>(n_t);
   int32_t* d_active = C.take<int32_t>(n_t);
@@ -497,7 +535,7 @@ smki_status insert_impl(smki_map* m, const float* xyz, const int32_t* label, con
   za.add<int32_t>(n);        // kept
   za.add<int32_t>(n);        // kpos
   za.add<char>(scan_tmp_bytes(n));
-  SMKI_HIP_TRY(m->a_hits.reserve(za.total));
+  SMKI_HIP_TRY(m->a_hits.reserve(za.total, m->alloc_now));
   Arena& A = m->a_hits;
   char* d_hdr = A.take<char>(hdr_bytes);
   int64_t* d_sc = (int64_t*)d_hdr;
@@ -549,7 +587,7 @@ smki_status insert_impl(smki_map* m, const float* xyz, const int32_t* label, con
   const double lv = (double)max_class_l(m) / (double)m->res;   // the stencil of the widest kernel
   const double margin = std::max(1e-4, 4.0 * ldexp((double)maxabs + 1.0, -23));
   const Stencil sten = csm ? Stencil{} : make_stencil(lv, margin);
-  if (!csm && (sten.R > SMKI_MAX_REACH || sten.R > m->B)) return SMKI_E_CAPACITY;
+  if (!csm && !sbki_shape_ok(m->B, sten.R)) return SMKI_E_CAPACITY;
   // target blocks: the row blocks and their neighbours (S-BKI), the row blocks (S-CSM)
   const int32_t DB = csm ? 0 : 1;
   int32_t eblo[3], enb[3];
@@ -586,7 +624,7 @@ smki_status insert_impl(smki_map* m, const float* xyz, const int32_t* label, con
   zb.add<int32_t>(max_slots);
   if (probs) zb.add<float>(nt);   // row weights (read through the permutation)
   zb.add<int32_t>(free_sample_workgroups(nf));
-  SMKI_HIP_TRY(m->a_sets.reserve(zb.total));
+  SMKI_HIP_TRY(m->a_sets.reserve(zb.total, m->alloc_now));
   Arena& Bz = m->a_sets;
   PointSet ps{};
   ps.n = nt;
@@ -702,7 +740,7 @@ smki_status insert_impl(smki_map* m, const float* xyz, const int32_t* label, con
   zc.add<int32_t>(n_units);   // splat launch order
   zc.add<int4>(n_slots);
   for (int i = 0; i < 3; ++i) zc.add<int32_t>(ntk);
-  SMKI_HIP_TRY(m->a_tgts.reserve(zc.total));
+  SMKI_HIP_TRY(m->a_tgts.reserve(zc.total, m->alloc_now));
   Arena& C = m->a_tgts;
   // cleared together: counts, active flags, contribution flags
   int32_t* d_cnt = C.take<int32_t>(8);
@@ -833,6 +871,7 @@ struct smki_batch {
   int64_t pool_cap = 0, cpool_cap = 0, hcap = 0;
   size_t in_bytes = 0;
   char* dbuf = nullptr;
+  Allocator by;              // the allocator of dbuf
   char* h_in = nullptr;      // pinned input header
   int64_t* h_out = nullptr;  // pinned results: kBOut int64, then the counter copies
   StencilOff* d_offs = nullptr;
@@ -1054,7 +1093,7 @@ void batch_release(smki_batch* b) {
   if (b->graph) (void)hipGraphDestroy(b->graph);
   if (b->cs) (void)hipStreamDestroy(b->cs);
   if (b->done) (void)hipEventDestroy(b->done);
-  if (b->dbuf) (void)hipFree(b->dbuf);
+  dev_release(b->by, b->dbuf);
   if (b->d_offs) (void)hipFree(b->d_offs);
   if (b->h_in) (void)hipHostFree(b->h_in);
   if (b->h_out) (void)hipHostFree(b->h_out);
@@ -1103,7 +1142,8 @@ smki_status smki_create_map(float res, int32_t block_size, float l, float sigma0
   if (!finite_pos(res) || !finite_pos(l) || !finite_pos(sigma0) || !finite_pos(alpha0))
     return SMKI_E_INVALID_ARG;
   if (K < 2 || K > 255 || free_class < 0 || free_class >= K) return SMKI_E_INVALID_ARG;
-  if (block_size != 4 && block_size != 8) return SMKI_E_INVALID_ARG;
+  if (block_size < 1 || block_size > 32 || (block_size & (block_size - 1)) != 0)
+    return SMKI_E_INVALID_ARG;
   if (opt && (opt->initial_blocks < 0 || opt->unit_budget < 0 || opt->unit_budget > (1 << 24) ||
               (opt->model != SMKI_MODEL_SBKI && opt->model != SMKI_MODEL_SCSM) ||
               (opt->selection != SMKI_SELECT_EXACT && opt->selection != SMKI_SELECT_FACE_BLOCKS) ||
@@ -1165,11 +1205,11 @@ smki_status smki_create_map(float res, int32_t block_size, float l, float sigma0
 smki_status smki_destroy_map(smki_map* m) {
   if (!m) return SMKI_E_INVALID_ARG;
   (void)hipStreamSynchronize(m->stream);
-  if (m->dev.hkeys) (void)hipFree(m->dev.hkeys);
-  if (m->dev.hvals) (void)hipFree(m->dev.hvals);
-  if (m->dev.bkeys) (void)hipFree(m->dev.bkeys);
-  if (m->dev.cslot) (void)hipFree(m->dev.cslot);
-  if (m->dev.calpha) (void)hipFree(m->dev.calpha);
+  dev_release(m->by_hash, m->dev.hkeys);
+  dev_release(m->by_hash, m->dev.hvals);
+  dev_release(m->by_pool, m->dev.bkeys);
+  dev_release(m->by_pool, m->dev.cslot);
+  dev_release(m->by_cpool, m->dev.calpha);
   if (m->d_err) (void)hipFree(m->d_err);
   if (m->d_stats) (void)hipFree(m->d_stats);
   if (m->d_offs) (void)hipFree(m->d_offs);
@@ -1197,6 +1237,15 @@ smki_status smki_set_class_params(smki_map* m, const float* l, const float* sigm
   m->s0k.assign(sigma0, sigma0 + m->K);
   ++m->epoch;   // a captured insert was sized for the old kernels
   return upload_class_params(m);
+}
+
+smki_status smki_set_allocator(smki_map* m, smki_alloc_fn alloc, smki_release_fn release,
+                               void* ctx) {
+  if (!m || (alloc == nullptr) != (release == nullptr)) return SMKI_E_INVALID_ARG;
+  m->alloc_now.alloc = alloc;
+  m->alloc_now.release = release;
+  m->alloc_now.ctx = ctx;
+  return SMKI_OK;
 }
 
 smki_status smki_set_stream(smki_map* m, void* hip_stream) {
@@ -1258,7 +1307,7 @@ smki_status smki_export(smki_map* m, int64_t capacity, int64_t* n_blocks, int32_
   z.add<uint32_t>(n);
   z.add<uint32_t>(n);
   z.add<char>(radix_tmp_bytes(n));
-  SMKI_HIP_TRY(m->a_misc.reserve(z.total));
+  SMKI_HIP_TRY(m->a_misc.reserve(z.total, m->alloc_now));
   uint64_t* k = m->a_misc.take<uint64_t>(n);
   uint64_t* k2 = m->a_misc.take<uint64_t>(n);
   uint32_t* o = m->a_misc.take<uint32_t>(n);
@@ -1305,7 +1354,7 @@ smki_status smki_import(smki_map* m, int64_t n, const int32_t* block_ijk, const 
   z.add<int32_t>(nk);
   z.add<int32_t>(nk);
   z.add<char>(scan_tmp_bytes(nk));
-  SMKI_HIP_TRY(m->a_misc.reserve(z.total));
+  SMKI_HIP_TRY(m->a_misc.reserve(z.total, m->alloc_now));
   Arena& Z = m->a_misc;
   int32_t* hdr = Z.take<int32_t>(4);   // [0] error word, [1] class blocks
   uint64_t* keys = Z.take<uint64_t>(n);
@@ -1669,7 +1718,7 @@ smki_status smki_batch_capture(smki_map* m, const float* xyz, const int32_t* lab
     b->cap_units = std::min(b->cap_units, narrow_units);
   if (g.n_blocks * m->K > (int64_t(1) << 30) || b->n_ext > (int64_t(1) << 30) ||
       b->n_ext * m->K > (int64_t)INT32_MAX / 2 || b->cap_rows > (int64_t)INT32_MAX - 1 ||
-      b->sten.R > SMKI_MAX_REACH || b->sten.R > m->B ||
+      !sbki_shape_ok(m->B, b->sten.R) ||
       (double)b->cap_units * DR * DR * DR * sizeof(float) > 64.0 * (1ull << 30)) {
     delete b;
     return SMKI_E_CAPACITY;
@@ -1690,7 +1739,8 @@ smki_status smki_batch_capture(smki_map* m, const float* xyz, const int32_t* lab
   // 4. buffers, stencil, header
   b->in_bytes = kBTail + sizeof(int64_t) * (S + 1) + sizeof(float) * 3 * S;
   const size_t dbytes = carve_batch(b, nullptr) + kAlign;
-  hipError_t e = hipMalloc((void**)&b->dbuf, dbytes);
+  hipError_t e = dev_alloc(m->alloc_now, (void**)&b->dbuf, dbytes);
+  b->by = m->alloc_now;
   if (e == hipSuccess)
     e = hipMalloc((void**)&b->d_offs, sizeof(StencilOff) * std::max<size_t>(b->sten.offs.size(), 1));
   if (e == hipSuccess) e = hipHostMalloc((void**)&b->h_in, b->in_bytes, hipHostMallocDefault);

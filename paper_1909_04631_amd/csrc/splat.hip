@@ -35,12 +35,6 @@ namespace {
 
 inline unsigned nblk(int64_t n, int t) { return (unsigned)ceil_div_i64(n > 0 ? n : 1, t); }
 
-__device__ __forceinline__ int64_t wave_sum_i64(int64_t v) {
-#pragma unroll
-  for (int o = SMKI_WAVE / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, SMKI_WAVE);
-  return v;
-}
-
 __device__ __forceinline__ void unlin3(int64_t lin, const int32_t n[3], int32_t out[3]) {
   out[2] = (int32_t)(lin % n[2]);
   lin /= n[2];
@@ -350,24 +344,40 @@ __global__ void __launch_bounds__(SMKI_WAVE) k_splat(SplatArgs a) {
               sz = PC::rstart(p % 3 - 1);
     const int n = ex * ey * ez, b = PC::base(p);
     const int per = (n + SMKI_WAVE - 1) / SMKI_WAVE;
-    float v[MAXPER];
-    bool nz = false;
-#pragma unroll
-    for (int k = 0; k < MAXPER; ++k) {
-      v[k] = 0.0f;
-      const int i = lane + k * SMKI_WAVE;
-      if (k < per && i < n) {
+    if constexpr (MAXPER > 8) {
+      // large blocks: vote while reading, then read again to store (no
+      // register copy of the piece)
+      bool nz = false;
+      for (int i = lane; i < n; i += SMKI_WAVE) {
         const int lx = i / (ey * ez), ly = (i / ez) % ey, lz = i % ez;
-        v[k] = acc[((sx + lx) * DR + (sy + ly)) * DR + (sz + lz)];
-        nz = nz || v[k] != 0.0f;
+        nz = nz || acc[((sx + lx) * DR + (sy + ly)) * DR + (sz + lz)] != 0.0f;
       }
-    }
-    if (__ballot(nz) == 0) continue;
-    touched |= 1u << p;
+      if (__ballot(nz) == 0) continue;
+      touched |= 1u << p;
+      for (int i = lane; i < n; i += SMKI_WAVE) {
+        const int lx = i / (ey * ez), ly = (i / ez) % ey, lz = i % ez;
+        out[b + i] = acc[((sx + lx) * DR + (sy + ly)) * DR + (sz + lz)];
+      }
+    } else {
+      float v[MAXPER];
+      bool nz = false;
 #pragma unroll
-    for (int k = 0; k < MAXPER; ++k) {
-      const int i = lane + k * SMKI_WAVE;
-      if (k < per && i < n) out[b + i] = v[k];
+      for (int k = 0; k < MAXPER; ++k) {
+        v[k] = 0.0f;
+        const int i = lane + k * SMKI_WAVE;
+        if (k < per && i < n) {
+          const int lx = i / (ey * ez), ly = (i / ez) % ey, lz = i % ez;
+          v[k] = acc[((sx + lx) * DR + (sy + ly)) * DR + (sz + lz)];
+          nz = nz || v[k] != 0.0f;
+        }
+      }
+      if (__ballot(nz) == 0) continue;
+      touched |= 1u << p;
+#pragma unroll
+      for (int k = 0; k < MAXPER; ++k) {
+        const int i = lane + k * SMKI_WAVE;
+        if (k < per && i < n) out[b + i] = v[k];
+      }
     }
   }
   if (lane == 0) a.umask[uid] = touched;
@@ -412,8 +422,10 @@ __global__ void k_slot_info(SplatArgs a) {
 template <int B, int R>
 struct MergeShape {
   static constexpr int B3 = B * B * B;
-  static constexpr int NT = B3;                       // threads per workgroup
-  static constexpr int CPG = 32;                      // classes per lookup group
+  static constexpr int NT = B3 < 1024 ? B3 : 1024;    // threads per workgroup
+  static constexpr int VPT = B3 / NT;                 // voxels per thread
+  static constexpr int CPG = NT < 32 ? NT : 32;       // classes per lookup group (<= threads)
+  static constexpr int RW = NT < SMKI_WAVE ? NT : SMKI_WAVE;   // lanes of one wavefront in use
   // neighbours whose region can cover one voxel: per axis 1, 2 (R > 0), or 3 (2R > B)
   static constexpr int AX = R == 0 ? 1 : (2 * R > B ? 3 : 2);
   static constexpr int MAXC = AX * AX * AX;
@@ -474,18 +486,18 @@ __device__ __forceinline__ void kahan_add(float& sm, float& comp, float v) {
 
 // (B = 8 up to reach 3: at most 64 registers, eight wavefronts per SIMD)
 template <int B, int R, bool WIDE>
-__global__ void __launch_bounds__(B * B * B, (B == 8 && R <= 3 && !WIDE) ? 8 : 1)
+__global__ void __launch_bounds__((B * B * B < 1024 ? B * B * B : 1024), (B == 8 && R <= 3 && !WIDE) ? 8 : 1)
 k_merge(SplatArgs a, int32_t n_targets) {
   using S = MergeShape<B, R>;
   constexpr int DR = B + 2 * R;
   constexpr int DR3 = DR * DR * DR;
-  constexpr int B3 = S::B3, NT = S::NT, CPG = S::CPG, MAXC = S::MAXC;
+  constexpr int B3 = S::B3, NT = S::NT, CPG = S::CPG, MAXC = S::MAXC, VPT = S::VPT;
   // [class][neighbour d]: (first unit, units) of the neighbour's slot if some
   // unit of it wrote piece 26 - d (the part of its region inside this block),
   // else (0, 0); units negated when the first unit did not write the piece
   __shared__ int2 ent[CPG * 27];
   __shared__ int32_t cflag[CPG], clist[CPG], cblk[CPG], ncls_s;
-  __shared__ int32_t red[NT / SMKI_WAVE];
+  __shared__ int32_t red[(NT + SMKI_WAVE - 1) / SMKI_WAVE];
   const int32_t t = blockIdx.x;
   if (a.dn_targets) n_targets = min(n_targets, *a.dn_targets);
   if (t >= n_targets || !a.tgt_active[t]) return;
@@ -497,11 +509,17 @@ k_merge(SplatArgs a, int32_t n_targets) {
   unlin3(a.tgt_elin[t], a.enb, bt);
   int32_t pt[3];   // target block on the point grid
   for (int q = 0; q < 3; ++q) pt[q] = bt[q] + a.eblo[q] - a.g.blo[q];
-  const int vv[3] = {tid / (B * B), (tid / B) % B, tid % B};
-  int pk[MAXC];   // candidates, in a fixed order
+  // Thread tid serves voxels tid + i NT, i < VPT (one voxel up to B = 8);
+  // its candidates (a fixed order) are kept for one voxel and recomputed
+  // per voxel otherwise.
+  int pk[MAXC];
+  auto candidates = [&](int vox) {
+    const int vv[3] = {vox / (B * B), (vox / B) % B, vox % B};
 #pragma unroll
-  for (int k = 0; k < MAXC; ++k) pk[k] = merge_candidate<B, R>(vv, k);
-  bool upd = false;
+    for (int k = 0; k < MAXC; ++k) pk[k] = merge_candidate<B, R>(vv, k);
+  };
+  if (VPT == 1) candidates(tid);
+  uint32_t upd = 0;   // bit i: voxel tid + i NT received a non-zero sum
   for (int y0 = 0; y0 < a.K; y0 += CPG) {
     const int ny = min(CPG, a.K - y0);
     // classes whose rows reach this block, and their class blocks
@@ -546,8 +564,11 @@ k_merge(SplatArgs a, int32_t n_targets) {
     __syncthreads();
     const int ncls = ncls_s;
     for (int ic = 0; ic < ncls; ++ic) {
-      const int yc = clist[ic];
-      const int2* E = ent + yc * 27;
+     const int yc = clist[ic];
+     const int2* E = ent + yc * 27;
+     for (int vi = 0; vi < VPT; ++vi) {
+      const int vox = tid + vi * NT;
+      if (VPT > 1) candidates(vox);
       float sm = 0.0f, comp = 0.0f;
       if constexpr (MAXC > 8) {
         // 2R > B (B = 4 with a reach of 3 or 4 voxels): up to 27 candidates,
@@ -606,22 +627,25 @@ k_merge(SplatArgs a, int32_t n_targets) {
         sm = (float)sd;
       }
       const int32_t cb = cblk[yc];   // allocated for every class with rows reaching here
-      float* dst = a.map.calpha + (int64_t)cb * B3 + tid;
+      float* dst = a.map.calpha + (int64_t)cb * B3 + vox;
       if (cb >= n_cold) {
         *dst = a.alpha0 + sm;   // class block allocated by this insert: written whole
       } else if (sm != 0.0f) {
         *dst += sm;
       }
-      upd = upd || sm != 0.0f;
+      if (sm != 0.0f) upd |= 1u << vi;
+     }
     }
     __syncthreads();
   }
-  const int64_t wsum = wave_sum_i64(upd ? 1 : 0);
-  if ((tid & (SMKI_WAVE - 1)) == 0) red[tid / SMKI_WAVE] = (int32_t)wsum;
+  int32_t wsum = __popc(upd);
+#pragma unroll
+  for (int o = S::RW / 2; o > 0; o >>= 1) wsum += __shfl_xor(wsum, o, S::RW);
+  if ((tid & (SMKI_WAVE - 1)) == 0) red[tid / SMKI_WAVE] = wsum;
   __syncthreads();
   if (tid == 0) {
     int32_t tot = 0;
-    for (int i = 0; i < NT / SMKI_WAVE; ++i) tot += red[i];
+    for (int i = 0; i < (NT + SMKI_WAVE - 1) / SMKI_WAVE; ++i) tot += red[i];
     atomicAdd(&a.stats[(blockIdx.x % SMKI_STAT_COPIES) * 4], (unsigned long long)tot);
   }
 }
@@ -770,15 +794,17 @@ hipError_t launch_splat_br(const SplatArgs& a, int64_t n_units, int32_t n_target
   return hipGetLastError();
 }
 
+// reach R <= B (a row's region covers its own block and the 26 around it)
 template <int B>
 hipError_t launch_splat_b(const SplatArgs& a, int64_t n_units, int32_t n_targets, bool merge,
                           hipStream_t st) {
+  if (a.R > B) return hipErrorInvalidValue;
   switch (a.R) {
     case 0: return launch_splat_br<B, 0>(a, n_units, n_targets, merge, st);
-    case 1: return launch_splat_br<B, 1>(a, n_units, n_targets, merge, st);
-    case 2: return launch_splat_br<B, 2>(a, n_units, n_targets, merge, st);
-    case 3: return launch_splat_br<B, 3>(a, n_units, n_targets, merge, st);
-    case 4: return launch_splat_br<B, 4>(a, n_units, n_targets, merge, st);
+    case 1: return launch_splat_br<B, (B >= 1 ? 1 : 0)>(a, n_units, n_targets, merge, st);
+    case 2: return launch_splat_br<B, (B >= 2 ? 2 : 0)>(a, n_units, n_targets, merge, st);
+    case 3: return launch_splat_br<B, (B >= 3 ? 3 : 0)>(a, n_units, n_targets, merge, st);
+    case 4: return launch_splat_br<B, (B >= 4 ? 4 : 0)>(a, n_units, n_targets, merge, st);
     default: return hipErrorInvalidValue;
   }
 }
@@ -791,8 +817,10 @@ hipError_t launch_splat_any(const SplatArgs& a, int64_t n_units, int32_t n_targe
   if (a.R < 0 || a.R > SMKI_MAX_REACH || a.noff < 1 || a.noff > kMaxOff[a.R])
     return hipErrorInvalidValue;
   switch (a.g.B) {
+    case 2: return launch_splat_b<2>(a, n_units, n_targets, merge, st);
     case 4: return launch_splat_b<4>(a, n_units, n_targets, merge, st);
     case 8: return launch_splat_b<8>(a, n_units, n_targets, merge, st);
+    case 16: return launch_splat_b<16>(a, n_units, n_targets, merge, st);
     default: return hipErrorInvalidValue;
   }
 }

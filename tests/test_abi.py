@@ -46,13 +46,21 @@ def test_host_argument_checks_need_no_gpu(lib):
     # non-positive resolution, K out of range, block size not supported, bad free class
     assert lib.smki_create_map(0.0, 8, 0.3, 0.1, 4, 1e-3, 0, None, C.byref(h)) == -1
     assert lib.smki_create_map(0.1, 8, 0.3, 0.1, 1, 1e-3, 0, None, C.byref(h)) == -1
-    assert lib.smki_create_map(0.1, 6, 0.3, 0.1, 4, 1e-3, 0, None, C.byref(h)) == -1
-    assert lib.smki_create_map(0.1, 16, 0.3, 0.1, 4, 1e-3, 0, None, C.byref(h)) == -1
+    # block sizes: powers of two in [1, 32]
+    for bad_b in (0, 3, 6, 12, 64, -8):
+        assert lib.smki_create_map(0.1, bad_b, 0.3, 0.1, 4, 1e-3, 0, None, C.byref(h)) == -1
     assert lib.smki_create_map(0.1, 8, 0.3, 0.1, 4, 1e-3, 4, None, C.byref(h)) == -1
     assert lib.smki_create_map(0.1, 8, float("nan"), 0.1, 4, 1e-3, 0, None, C.byref(h)) == -1
-    for bad in (Options(-1, 0), Options(0, -1), Options(0, (1 << 24) + 1), Options(0, 0, 2), Options(0, 0, 0, 2)):
+    for bad in (Options(-1, 0), Options(0, -1), Options(0, (1 << 24) + 1), Options(0, 0, 2),
+                Options(0, 0, 0, 2), Options(0, 0, 0, 0, 2)):
         assert lib.smki_create_map(0.1, 8, 0.3, 0.1, 4, 1e-3, 0, C.byref(bad), C.byref(h)) == -1
     assert lib.smki_insert_scan(None, None, None, 0, None, 0.3) == -1
+    from paper_1909_04631_amd._lib import ALLOC_FN, RELEASE_FN
+    assert lib.smki_set_allocator(None, ALLOC_FN(), RELEASE_FN(), None) == -1
+    assert lib.smki_batch_replay(None, None, None) == -1
+    assert lib.smki_batch_destroy(None) == -1
+    hb = C.c_void_p()
+    assert lib.smki_batch_capture(None, None, None, None, None, 1, 0.3, 0.25, C.byref(hb)) == -1
     assert lib.smki_query(None, None, 0, None, None, None, None, None) == -1
     n = C.c_int64()
     o = (C.c_float * 3)(0, 0, 0)

@@ -69,3 +69,18 @@ def test_counting_model_lidar_scan_full_size():
     om = oracle_map_of(sc, scsm=True)
     ijk, _ = _compare_counts(gm, om, p)
     print(f"lidar S-CSM: {ijk.shape[0]} voxels, stats {gm.stats()}", flush=True)
+
+
+@pytest.mark.parametrize("B", [1, 2, 16, 32])
+def test_counting_model_at_every_block_depth(B):
+    # block depth d: 2^(d-1) voxels per block edge (depth 1: a block is one
+    # voxel, the setting the paper runs the counting model at); counts exact
+    sc = scenes.make_config(0)
+    sc.params.block_size = B
+    p = sc.params
+    print(f"[case] S-CSM block size {B}", flush=True)
+    gm = gpu_map_of(sc, model="scsm")
+    om = oracle_map_of(sc, scsm=True)
+    _compare_counts(gm, om, p)
+    ijk, alpha = gm.export()
+    assert alpha.shape[2:] == (B, B, B)

@@ -321,10 +321,12 @@ def test_split_work_units_agree(chunk):
     check_counts(st, nv, nb)
 
 
-@pytest.mark.parametrize("B,l", [(4, 0.3), (8, 0.3), (4, 0.89), (8, 0.89)])
+@pytest.mark.parametrize("B,l", [(2, 0.3), (4, 0.3), (8, 0.3), (16, 0.3), (4, 0.89), (8, 0.89),
+                                 (16, 0.89)])
 def test_block_sizes_and_reach(B, l):
     # res 0.2: l = 0.3 reaches 2 voxels past a row's voxel, l = 0.89 reaches 4,
-    # the largest supported reach (equal to the block edge for B = 4)
+    # the largest supported reach (equal to the block edge for B = 4, as 2 is
+    # for B = 2); B = 16 merges four voxels per thread
     sc = scenes.random_points_scene(5, 3000, K=5, extent=1.3, centre=(-7.3, 12.9, -0.4),
                                     res=0.2, l=l, sigma0=0.4, free_step=0.25,
                                     origin=(-6.0, 11.0, 0.5))
@@ -339,6 +341,12 @@ def test_reach_beyond_limit_is_rejected_and_map_unchanged():
     sc = scenes.random_points_scene(6, 500, K=3, extent=0.5, res=0.1, l=0.3)
     p = sc.params
     s = sc.scans[0]
+    # reach 3 > B = 2; and S-BKI at block sizes 1 and 32
+    for B, l in ((2, 0.3), (1, 0.3), (32, 0.3), (1, 0.04)):
+        m = SemanticMap(p.res, B, l, p.sigma0, p.K, p.alpha0)
+        with pytest.raises(SmkiError, match="CAPACITY"):
+            m.insert_scan(cuda(s.xyz), cuda(s.label), s.origin, 0.0)
+        assert m.num_blocks() == 0
     m = SemanticMap(p.res, 8, 0.46, p.sigma0, p.K, p.alpha0)   # l / res = 4.6 voxels
     with pytest.raises(SmkiError, match="CAPACITY"):
         m.insert_scan(cuda(s.xyz), cuda(s.label), s.origin, 0.0)
