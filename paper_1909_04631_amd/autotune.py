@@ -1,0 +1,155 @@
+"""Autotuner of the map update's launch shape, per workload.
+
+Two settings decide how the S-BKI update maps onto the GPU and neither changes
+what it computes (Eq. (7)-(8) at the grid centroids; only the float32
+summation order of a voxel's partial sums moves):
+
+  block_size   voxels per block edge B (2, 4, 8, 16): the splat keeps one
+               (B + 2R)^3 region per work unit in LDS, so B sets the waves a
+               compute unit holds and how many neighbouring regions the merge
+               adds per voxel;
+  unit_budget  rows of one (class, block) per splat work unit: longer units
+               amortise the region's clearing and write-out, shorter ones
+               spread dense blocks over more compute units.
+
+For each workload the tuner times the insert (map reset + insert, HIP events on
+the stream) at every combination and keeps the fastest.  Workloads:
+
+  lidar    one LiDAR-shaped scan (scenes.make_config(1))
+  stereo   the first scans of the stereo sequence, one map (make_config(2))
+  town     the 64-scan batched insert (make_config(3))
+
+    python -m paper_1909_04631_amd.autotune [--out tuned.json] [--workloads lidar,town]
+
+The result (tuned.json beside this file by default) holds, per workload, the
+chosen settings, the time of every combination tried, and the device name.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+DEFAULT_OUT = os.path.join(HERE, "tuned.json")
+BLOCK_SIZES = (4, 8, 16)
+UNIT_BUDGETS = (256, 512, 1024, 2048)
+
+
+def load(path=DEFAULT_OUT):
+    """Tuned settings per workload ({} when the file is absent)."""
+    if not os.path.exists(path):
+        return {}
+    with open(path) as f:
+        return json.load(f).get("workloads", {})
+
+
+def settings(workload, path=DEFAULT_OUT):
+    """(block_size, unit_budget) chosen for a workload, or None."""
+    w = load(path).get(workload)
+    return (w["block_size"], w["unit_budget"]) if w else None
+
+
+def _time_inserts(torch, step, reps):
+    step()
+    torch.cuda.synchronize()
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record()
+    for _ in range(reps):
+        step()
+    b.record()
+    torch.cuda.synchronize()
+    return a.elapsed_time(b) / reps
+
+
+def tune_workload(name, scene, reps, log):
+    import torch
+    from . import SemanticMap, SmkiError
+    dev = torch.device("cuda", 0)
+    p = scene.params
+    if name == "town":
+        xyz, lab, offs, org = scene.concat()
+        tx, tl = torch.from_numpy(xyz).to(dev), torch.from_numpy(lab).to(dev)
+        offs, org = [int(o) for o in offs], [tuple(o) for o in org]
+    else:
+        tx = [torch.from_numpy(s.xyz).to(dev) for s in scene.scans]
+        tl = [torch.from_numpy(s.label).to(dev) for s in scene.scans]
+    tried = []
+    for B in BLOCK_SIZES:
+        for ub in UNIT_BUDGETS:
+            m = SemanticMap(p.res, B, p.l, p.sigma0, p.K, p.alpha0, p.free_class,
+                            unit_budget=ub, initial_blocks=1 << 16)
+            if name == "town":
+                def step():
+                    m.reset()
+                    m.insert_scans(tx, tl, offs, org, p.free_step)
+            else:
+                def step():
+                    m.reset()
+                    for i, s in enumerate(scene.scans):
+                        m.insert_scan(tx[i], tl[i], s.origin, p.free_step)
+            try:
+                ms = _time_inserts(torch, step, reps)
+            except SmkiError as e:   # (a shape the kernels do not serve)
+                log(f"[autotune] {name} B={B} unit_budget={ub}: {e}")
+                continue
+            if name == "stereo":
+                ms /= len(scene.scans)
+            tried.append({"block_size": B, "unit_budget": ub, "ms": ms})
+            log(f"[autotune] {name} B={B} unit_budget={ub}: {ms:.3f} ms")
+            del m
+            torch.cuda.empty_cache()
+    best = min(tried, key=lambda t: t["ms"])
+    return {"block_size": best["block_size"], "unit_budget": best["unit_budget"],
+            "ms": best["ms"], "unit": "ms per scan" if name == "stereo" else "ms per insert",
+            "tried": tried}
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--out", default=DEFAULT_OUT)
+    ap.add_argument("--workloads", default="lidar,stereo,town")
+    ap.add_argument("--reps", type=int, default=5)
+    ap.add_argument("--stereo-scans", type=int, default=10)
+    args = ap.parse_args(argv)
+    root = os.path.dirname(HERE)
+    if root not in sys.path:
+        sys.path.insert(0, root)
+    import scenes
+
+    def log(*a):
+        print(*a, file=sys.stderr, flush=True)
+
+    names = [w for w in args.workloads.split(",") if w]
+    made = {}
+    t0 = time.time()
+    for w in names:   # generated before the GPU is touched
+        if w == "lidar":
+            made[w] = scenes.make_config(1)
+        elif w == "stereo":
+            made[w] = scenes.make_config(2, first=args.stereo_scans,
+                                         workers=min(16, os.cpu_count() or 1))
+        elif w == "town":
+            made[w] = scenes.make_config(3)
+        else:
+            raise SystemExit(f"unknown workload {w}")
+    log(f"[autotune] workloads generated in {time.time() - t0:.1f}s")
+    import torch
+    torch.cuda.init()
+    out = {"device": torch.cuda.get_device_name(0), "block_sizes": list(BLOCK_SIZES),
+           "unit_budgets": list(UNIT_BUDGETS), "reps": args.reps, "workloads": {}}
+    if os.path.exists(args.out):   # keep the workloads not tuned now
+        with open(args.out) as f:
+            out["workloads"].update(json.load(f).get("workloads", {}))
+    for w in names:
+        out["workloads"][w] = tune_workload(w, made[w], args.reps, log)
+        log(f"[autotune] {w}: B={out['workloads'][w]['block_size']} "
+            f"unit_budget={out['workloads'][w]['unit_budget']}")
+    with open(args.out, "w") as f:
+        json.dump(out, f, indent=1)
+    print(json.dumps({w: {k: v for k, v in out["workloads"][w].items() if k != "tried"}
+                      for w in names}))
+
+
+if __name__ == "__main__":
+    main()
