@@ -117,8 +117,9 @@ def main():
     xyz = torch.from_numpy(s.xyz).to(dev)
     lab = torch.from_numpy(s.label).to(dev)
     vox = torch.from_numpy(np.floor(s.xyz / np.float32(p.res)).astype(np.int32)).to(dev)
-    m = SemanticMap.from_params(p, initial_blocks=1 << 15,
-                                unit_budget=int(os.environ.get("SMKI_CHUNK", "0")))
+    B_l, ub_l = tuned("lidar", p)
+    m = SemanticMap(p.res, B_l, p.l, p.sigma0, p.K, p.alpha0, p.free_class,
+                    initial_blocks=1 << 15, unit_budget=ub_l)
     stream = torch.cuda.current_stream()
 
     def step():
@@ -175,6 +176,7 @@ def main():
         "data": "synthetic (seeded ray-cast street scene, LiDAR-shaped)",
         "config": {
             "workload": "lidar_scan_64x2048_K20_res0.1_B8_l0.3_s0.1_step0.3",
+            "block_size": B_l, "unit_budget": ub_l,
             "hits": st["n_hits"], "free_samples": st["n_free"], "voxels_updated": V,
             "pairs_in_support": P, "blocks_allocated": st["n_new_blocks"],
             "splat_units": st["n_units"], "stencil_lane_util": st["n_candidates"] / max(st["n_lane_slots"], 1),
@@ -219,6 +221,15 @@ def main():
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(sc, V)
     print(json.dumps(out), flush=True)
+
+
+def tuned(workload, p):
+    """(block size, unit budget) the autotuner chose for a workload
+    (paper_1909_04631_amd/tuned.json), else the workload's own block size and
+    the library's default unit budget."""
+    from paper_1909_04631_amd import autotune
+    s = autotune.settings(workload)
+    return (int(s[0]), int(s[1])) if s else (int(p.block_size), 0)
 
 
 def copy_bandwidth(torch, dev, mib=1024, reps=10):
@@ -290,12 +301,15 @@ def bench_stereo(torch, dev, SemanticMap, stereo):
     """The stereo sequence: every scan inserted into one persistent map, each
     insert timed with events on the stream (its host waits included)."""
     p = stereo.params
-    m = SemanticMap.from_params(p, initial_blocks=1 << 17)
+    B_s, ub_s = tuned("stereo", p)
+    m = SemanticMap(p.res, B_s, p.l, p.sigma0, p.K, p.alpha0, p.free_class,
+                    initial_blocks=1 << 17, unit_budget=ub_s)
     stream = torch.cuda.current_stream()
     xyz = [torch.from_numpy(x.xyz).to(dev) for x in stereo.scans]
     lab = [torch.from_numpy(x.label).to(dev) for x in stereo.scans]
     # warm-up on a separate map (same shapes)
-    w = SemanticMap.from_params(p, initial_blocks=1 << 17)
+    w = SemanticMap(p.res, B_s, p.l, p.sigma0, p.K, p.alpha0, p.free_class,
+                    initial_blocks=1 << 17, unit_budget=ub_s)
     for i in range(2):
         w.insert_scan(xyz[i], lab[i], stereo.scans[i].origin, p.free_step)
     torch.cuda.synchronize()
@@ -315,7 +329,8 @@ def bench_stereo(torch, dev, SemanticMap, stereo):
     splat_ms, _ = m.kernel_times(64)
     tot = ms.sum() * 1e-3
     log(f"[bench] stereo: {len(ms)} scans, median {np.median(ms):.2f} ms, max {ms.max():.2f} ms")
-    return {"workload": "stereo_1242x375_100scans_K11_res0.1_B8_l0.3_s0.1_step0.3",
+    return {"workload": "stereo_1242x375_100scans_K11_res0.1_l0.3_s0.1_step0.3",
+            "block_size": B_s, "unit_budget": ub_s,
             "scans": len(ms), "hits_per_scan_mean": float(np.mean(H)),
             "ms_per_scan_median": float(np.median(ms)), "ms_per_scan_max": float(ms.max()),
             "ms_per_scan_mean": float(ms.mean()),
@@ -524,7 +539,9 @@ def bench_batched(torch, dev, SemanticMap, town, reps=3):
     for s in sc.scans:
         offs.append(offs[-1] + s.xyz.shape[0])
     origins = [s.origin for s in sc.scans]
-    m = SemanticMap.from_params(p, initial_blocks=1 << 18)
+    B_t, ub_t = tuned("town", p)
+    m = SemanticMap(p.res, B_t, p.l, p.sigma0, p.K, p.alpha0, p.free_class,
+                    initial_blocks=1 << 18, unit_budget=ub_t)
 
     def sequential():
         m.reset()
@@ -572,7 +589,8 @@ def bench_batched(torch, dev, SemanticMap, town, reps=3):
     sp = float(np.mean(splat_ms))
     log(f"[bench] batched: graph {t_graph * 1e3:.1f} ms, batched {t_bat * 1e3:.1f} ms, "
         f"sequential {t_seq * 1e3:.1f} ms")
-    return {"workload": "town_64_scans_K20_res0.2_B8_l0.3_s0.1_step0.3",
+    return {"workload": "town_64_scans_K20_res0.2_l0.3_s0.1_step0.3",
+            "block_size": B_t, "unit_budget": ub_t,
             "hits": int(offs[-1]), "rows": int(st["n_hits"] + st["n_free"]),
             "voxel_updates_sum_over_scans": int(V), "voxels_updated_union": int(st["n_updated_voxels"]),
             "t_graph_replay_ms": t_graph * 1e3, "t_batched_ms": t_bat * 1e3,

@@ -30,6 +30,13 @@ def _print_case(name):
     print(f"[case] {name}", flush=True)
 
 
+def _tuned(workload):
+    """The autotuner's (block size, unit budget) for a workload (defaults when untuned)."""
+    from paper_1909_04631_amd import autotune
+    s = autotune.settings(workload)
+    return {"block_size": s[0], "unit_budget": s[1]} if s else {"block_size": 8, "unit_budget": 0}
+
+
 def _counts_agree(gpu_stats, ora, what):
     """V and P of one insert: exact up to band pairs."""
     dv = abs(gpu_stats["n_updated_voxels"] - ora["V"])
@@ -57,7 +64,9 @@ def test_lidar_scan_whole_map():
     _print_case(f"lidar whole map n={s.xyz.shape[0]}")
     om = oracle_map_of(sc)
     ora = om.last_insert()
-    gm = SemanticMap.from_params(p)
+    t = _tuned("lidar")   # the settings the benchmark runs at
+    gm = SemanticMap(p.res, t["block_size"], p.l, p.sigma0, p.K, p.alpha0, p.free_class,
+                     unit_budget=t["unit_budget"])
     gm.insert_scan(cuda(s.xyz), cuda(s.label), s.origin, p.free_step)
     torch.cuda.synchronize()
     st = gm.stats()
@@ -91,7 +100,9 @@ def test_batched_town_counts_and_sampled_alpha():
     xyz = np.concatenate([s.xyz for s in sc.scans])
     lab = np.concatenate([s.label for s in sc.scans])
     offs = np.concatenate([[0], np.cumsum([s.xyz.shape[0] for s in sc.scans])])
-    gb = SemanticMap.from_params(p, initial_blocks=1 << 18)
+    t = _tuned("town")   # the batched insert at the settings the benchmark runs at
+    gb = SemanticMap(p.res, t["block_size"], p.l, p.sigma0, p.K, p.alpha0, p.free_class,
+                     unit_budget=t["unit_budget"], initial_blocks=1 << 18)
     gb.insert_scans(cuda(xyz), cuda(lab), [int(o) for o in offs], [s.origin for s in sc.scans],
                     p.free_step)
     torch.cuda.synchronize()
@@ -123,7 +134,9 @@ def test_stereo_scans_into_one_map():
     p = sc.params
     _print_case(f"stereo: {len(sc.scans)} scans of {[s.xyz.shape[0] for s in sc.scans]} hits")
     om = oracle.OracleMap.from_params(p.f32())
-    gm = SemanticMap.from_params(p, initial_blocks=1 << 15)
+    t = _tuned("stereo")
+    gm = SemanticMap(p.res, t["block_size"], p.l, p.sigma0, p.K, p.alpha0, p.free_class,
+                     unit_budget=t["unit_budget"], initial_blocks=1 << 15)
     pf = p.f32()
     for i, s in enumerate(sc.scans):
         om.insert_scan(s.xyz, s.label, s.origin, pf.free_step, pf.free_class)
