@@ -28,13 +28,14 @@ constexpr int LB = 4;       // cells per block edge of the loss grid
 constexpr int LLOG2B = 2;
 constexpr int64_t kMaxLossBlocks = int64_t(1) << 22;
 
-// f'(r)/r = s^4 P(s), s = 1 - r: weighted least-squares degree-10 fit on [0, 1]
-// (relative error 2e-8) to the series f'(1 - s) = sum_{n>=2} (-1)^(n+1) (2n-2)
-// (2 pi)^(2n) s^(2n) / (3 (2n)!) divided by r; highest degree first.
-__constant__ float kG[11] = {0.8349097349647332f,  0.8454704795995118f,  -18.5857978887505f,
-                             33.497402687692315f,  12.910037904193086f,  -46.956133599204506f,
-                             -50.499994537936374f, 70.73669937252042f,   70.6436413248805f,
-                             -43.29277781556012f,  -43.29292998698858f};
+// f'(r)/r = s^4 P(s), s = 1 - r: P is a relative degree-10 fit on s in [0, 1]
+// (error 1.5e-8) of [f'(1 - s)/s^4]/(1 - s), the series f'(1 - s) = sum_{n>=2}
+// (-1)^(n+1) (2n-2) (2 pi)^(2n) s^(2n) / (3 (2n)!) divided by s^4 r;
+// kernel_poly.py derives it.  Highest degree first.
+__constant__ float kG[11] = {0.826695529413764f,  0.8883087167660566f, -18.68107694361095f,
+                             33.6151725453642f,   12.821709617420272f, -46.914955742370914f,
+                             -50.511732012322824f, 70.73862871627226f, 70.64347982896255f,
+                             -43.2927725732048f,  -43.292930014879026f};
 
 struct LossArgs {
   BucketGeom g;

@@ -30,6 +30,7 @@
 // formula cancels.  The splat evaluates Q divided by its leading coefficient
 // (monic) and applies sigma0 times that coefficient once per flushed sum.
 #include "smki_gather.h"
+#include "smki_pieces.h"
 
 namespace {
 
@@ -125,40 +126,6 @@ struct Steps {
   // fewest steps a reach-R stencil can need (its size at l / res -> R - 1/2)
   static constexpr int NSMIN = R <= 2 ? 1 : R == 3 ? 2 : 4;
 };
-
-// The region of a (class, block) work unit, (B + 2R)^3 voxels, split into 27
-// pieces: piece p = (dx+1)*9 + (dy+1)*3 + (dz+1) holds the voxels that lie in
-// the block at offset (dx, dy, dz) from the unit's block.  Per axis a piece
-// spans R voxels (d = -1, region coordinates [0, R)), B (d = 0, [R, R+B)) or
-// R (d = +1, [R+B, 2R+B)).  Partial sums are stored piece after piece, each
-// piece contiguous with z fastest.
-template <int B, int R>
-struct Pieces {
-  static constexpr int ext(int d) { return d == 0 ? B : R; }
-  static constexpr int rstart(int d) { return d < 0 ? 0 : (d == 0 ? R : R + B); }
-  static constexpr int size(int p) { return ext(p / 9 - 1) * ext((p / 3) % 3 - 1) * ext(p % 3 - 1); }
-  static constexpr int base(int p) {
-    int b = 0;
-    for (int q = 0; q < p; ++q) b += size(q);
-    return b;
-  }
-};
-
-// Start of piece p inside a unit's partial sums (p known at run time).
-template <int B, int R>
-__device__ __forceinline__ int pbase(int p) {
-  const int px = p / 9, py = (p / 3) % 3, pz = p % 3;
-  // pieces before p: full x-layers, then y-rows of this layer, then z-cells of this row
-  constexpr int E[3] = {R, B, R};
-  constexpr int S2 = (2 * R + B) * (2 * R + B);   // one x-layer spans all (y, z): sum ey * ez
-  int b = 0;
-  for (int i = 0; i < px; ++i) b += E[i] * S2;
-  const int ex = E[px];
-  for (int i = 0; i < py; ++i) b += ex * E[i] * (2 * R + B);
-  const int ey = E[py];
-  for (int i = 0; i < pz; ++i) b += ex * ey * E[i];
-  return b;
-}
 
 // NS = ceil(stencil size / 64), the steps each row takes (compiled per value
 // so that the steps of a row are independent straight-line code).  W: rows carry
@@ -406,8 +373,19 @@ __global__ void k_slot_info(SplatArgs a) {
   if (j == 0) a.sinfo[s] = make_int4(u0, nu, (int32_t)m, nu > 0 ? (int32_t)a.umask[u0] : 0);
 }
 
-// One workgroup per active target block, one thread per voxel.  Each thread
-// first lists, once, the neighbours whose regions cover its voxel and the
+// Partial sum at element off of unit w's region.  Below 4 GiB of partial sums
+// (WIDE false) the address is a 32-bit byte offset from the buffer base, so
+// that a load takes one address register instead of two.
+template <int DR3, bool WIDE>
+__device__ __forceinline__ float part_at(const float* part, int32_t w, int32_t off) {
+  if (WIDE) return part[(int64_t)w * DR3 + off];
+  const uint32_t byte = ((uint32_t)w * (uint32_t)DR3 + (uint32_t)off) * 4u;
+  return *(const float*)((const char*)part + byte);
+}
+
+// (B = 8 up to reach 3: at most 64 registers, eight wavefronts per SIMD)
+// One workgroup per active target block, one thread per voxel (blocks of more
+// than 1024 voxels: several voxels per thread).  Each thread first lists, the neighbours whose regions cover its voxel and the
 // offset of its voxel in the corresponding piece.  The workgroup then looks up
 // the slots of the 27 neighbouring blocks for a group of classes into LDS (all
 // lookups in flight together), keeping for each neighbour only whether its
@@ -419,72 +397,6 @@ __global__ void k_slot_info(SplatArgs a) {
 // allocated by this insert are written alpha0 + sum, older blocks updated in
 // place where the sum is non-zero.  The per-thread state is kept small (packed
 // candidates, slot entries re-read from LDS) so that 8 wavefronts fit per SIMD.
-template <int B, int R>
-struct MergeShape {
-  static constexpr int B3 = B * B * B;
-  static constexpr int NT = B3 < 1024 ? B3 : 1024;    // threads per workgroup
-  static constexpr int VPT = B3 / NT;                 // voxels per thread
-  static constexpr int CPG = NT < 32 ? NT : 32;       // classes per lookup group (<= threads)
-  static constexpr int RW = NT < SMKI_WAVE ? NT : SMKI_WAVE;   // lanes of one wavefront in use
-  // neighbours whose region can cover one voxel: per axis 1, 2 (R > 0), or 3 (2R > B)
-  static constexpr int AX = R == 0 ? 1 : (2 * R > B ? 3 : 2);
-  static constexpr int MAXC = AX * AX * AX;
-};
-
-// Candidate k of voxel vv (coordinates in the target block): the neighbour c
-// (per axis 0, -1 if v < R, +1 if v >= B - R; both only when 2R > B) whose
-// region covers the voxel, which lies in piece 26 - c of that region.  Packed
-// as (neighbour index << 16) | offset of the voxel in the region's pieces, or
-// -1 when the candidate does not apply to this voxel.
-template <int B, int R>
-__device__ __forceinline__ int merge_candidate(const int vv[3], int k) {
-  constexpr int AX = MergeShape<B, R>::AX;
-  const int kk[3] = {k / (AX * AX), (k / AX) % AX, k % AX};
-  int c3[3], l3[3];
-  bool valid = true;
-#pragma unroll
-  for (int q = 0; q < 3; ++q) {
-    int c = 0;
-    if (kk[q] == 1) {
-      if (AX == 2) {
-        c = vv[q] < R ? -1 : (vv[q] >= B - R ? 1 : 0);
-        valid = valid && c != 0;
-      } else {
-        c = -1;
-        valid = valid && vv[q] < R;
-      }
-    } else if (kk[q] == 2) {
-      c = 1;
-      valid = valid && vv[q] >= B - R;
-    }
-    c3[q] = c;
-    l3[q] = c > 0 ? vv[q] - (B - R) : vv[q];
-  }
-  const int ci = (c3[0] + 1) * 9 + (c3[1] + 1) * 3 + (c3[2] + 1);
-  const int ey = c3[1] == 0 ? B : R, ez = c3[2] == 0 ? B : R;
-  const int off = pbase<B, R>(26 - ci) + (l3[0] * ey + l3[1]) * ez + l3[2];
-  return valid ? (ci << 16) | off : -1;
-}
-
-// Partial sum at element off of unit w's region.  Below 4 GiB of partial sums
-// (WIDE false) the address is a 32-bit byte offset from the buffer base, so
-// that a load takes one address register instead of two.
-template <int DR3, bool WIDE>
-__device__ __forceinline__ float part_at(const float* part, int32_t w, int32_t off) {
-  if (WIDE) return part[(int64_t)w * DR3 + off];
-  const uint32_t byte = ((uint32_t)w * (uint32_t)DR3 + (uint32_t)off) * 4u;
-  return *(const float*)((const char*)part + byte);
-}
-
-// Compensated (Kahan) step.
-__device__ __forceinline__ void kahan_add(float& sm, float& comp, float v) {
-  const float yv = v - comp;
-  const float tv = sm + yv;
-  comp = (tv - sm) - yv;
-  sm = tv;
-}
-
-// (B = 8 up to reach 3: at most 64 registers, eight wavefronts per SIMD)
 template <int B, int R, bool WIDE>
 __global__ void __launch_bounds__((B * B * B < 1024 ? B * B * B : 1024), (B == 8 && R <= 3 && !WIDE) ? 8 : 1)
 k_merge(SplatArgs a, int32_t n_targets) {
@@ -569,19 +481,20 @@ k_merge(SplatArgs a, int32_t n_targets) {
      for (int vi = 0; vi < VPT; ++vi) {
       const int vox = tid + vi * NT;
       if (VPT > 1) candidates(vox);
-      float sm = 0.0f, comp = 0.0f;
+      float sm = 0.0f;
       if constexpr (MAXC > 8) {
-        // 2R > B (B = 4 with a reach of 3 or 4 voxels): up to 27 candidates,
-        // summed one at a time
+        // 2R > B (a reach of more than half the block edge): up to 27
+        // candidates, summed one at a time in double
+        double sd = 0.0;
         for (int k = 0; k < MAXC; ++k) {
           if (pk[k] < 0) continue;
           const int ci = pk[k] >> 16;
           const int2 e = E[ci];
           const int p = 26 - ci;
           for (int32_t w = e.x; w < e.x + abs(e.y); ++w)
-            if ((a.umask[w] >> p) & 1u)
-              kahan_add(sm, comp, part_at<DR3, WIDE>(a.part, w, pk[k] & 0xffff));
+            if ((a.umask[w] >> p) & 1u) sd += (double)part_at<DR3, WIDE>(a.part, w, pk[k] & 0xffff);
         }
+        sm = (float)sd;
       } else {
         // Branch-free over the candidates: every candidate loads (an absent one
         // reads element 0 of the buffer and discards it) and the sum is kept in
