@@ -3,19 +3,22 @@
 //
 //   alpha_v^k += sum over rows t with |x_t - c_v| < l of  sigma0 f(|x_t - c_v| / l) [y_t = k]
 //
-// Organisation (deterministic, no floating-point atomics):
+// Organisation (deterministic: no floating-point atomics across wavefronts):
 //
 //   splat   Rows are sorted by (class, block, voxel cell).  One wavefront takes
 //           a chunk of at most `chunk` rows of one (class, block) and keeps,
 //           in LDS, the partial sums of the region that those rows can reach:
-//           the block grown by the stencil reach R on every side.  For each
-//           row (taken in sorted order, uniform across the wavefront), lane i
-//           handles the voxel offsets i, i + 64, ... of the list of voxels that
-//           can lie within l of a point of the row's cell; lanes accumulate in
-//           registers while consecutive rows share a cell and add to LDS when
-//           the cell changes.  Every lane owns distinct LDS addresses, so the
-//           sum order of every voxel is the row order: run-to-run identical.
-//           The region is written out as the chunk's partial sums.
+//           the block grown by the stencil reach R on every side.  Rows are
+//           taken 64 at a time, octant by octant of their position in their
+//           cell, each octant's rows in sorted order; for each row (uniform
+//           across the wavefront), lane i handles the voxel offsets i, i + 64,
+//           ... of the list of voxels that can lie within l of a point of that
+//           octant of the row's cell.  Lanes accumulate in registers while
+//           consecutive rows share a cell and octant, and add to LDS when it
+//           changes.  Every lane owns distinct LDS addresses and the LDS runs a
+//           wavefront's adds in issue order, so the sum order of every voxel is
+//           fixed: run-to-run identical.  The region is written out as the
+//           chunk's partial sums.
 //   merge   One workgroup per target block: for every class, add in double
 //           the partial sums that the neighbouring (class, block) regions
 //           covering a voxel hold for it (first chunks in a fixed neighbour
@@ -27,8 +30,9 @@
 // series of the sparse kernel about r = 1 has only odd powers from s^5 on);
 // Q is a degree-6 polynomial fit (kernel_poly.py), which keeps f relatively
 // accurate (about 1.3e-6 in binary32) up to the support edge, where the direct
-// formula cancels.  The splat evaluates Q divided by its leading coefficient
-// (monic) and applies sigma0 times that coefficient once per flushed sum.
+// formula cancels.  The splat evaluates sigma0 Q, whose coefficients it forms
+// once per work unit from Q divided by its leading coefficient (monic) and
+// sigma0 times that coefficient.
 #include "smki_gather.h"
 #include "smki_pieces.h"
 
@@ -134,8 +138,9 @@ template <int B, int R, int NS, bool W>
 __global__ void __launch_bounds__(SMKI_WAVE) k_splat(SplatArgs a) {
   constexpr int DR = B + 2 * R;                 // region edge (voxels)
   constexpr int DR3 = DR * DR * DR;
-  constexpr int NACC4 = (DR3 + 1 + 3) / 4;
-  __shared__ float4 acc4[NACC4];   // the region + a dummy slot for pad lanes
+  constexpr int NACC4 = (DR3 + 3) / 4;
+  __shared__ float4 acc4[NACC4];   // the region
+  __shared__ float4 rowq[SMKI_WAVE];   // the batch being processed: (|u| per axis, |u|^2) per row
   float* acc = (float*)acc4;
   const int lane = threadIdx.x;
   if (a.dn_units && (int32_t)blockIdx.x >= *a.dn_units) return;   // capacity launch
@@ -145,6 +150,12 @@ __global__ void __launch_bounds__(SMKI_WAVE) k_splat(SplatArgs a) {
   const int32_t r0 = u.x, r1 = u.y;
   const float4 kc = a.cls[u.w];         // the kernel of the unit's class
   const float l2 = kc.x, inv_l = kc.y, cscale = kc.z;
+  // sigma0 Q (the class's scale times the monic fit), highest degree first: the
+  // sums of kernel values go to LDS as they are
+  float cq[SMKI_POLY_N];
+  cq[0] = cscale;
+#pragma unroll
+  for (int i = 1; i < SMKI_POLY_N; ++i) cq[i] = cscale * a.mcoef[i];
   for (int i = lane; i < NACC4; i += SMKI_WAVE) acc4[i] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
   // Per lane, for each step: one voxel offset o of the first-octant stencil
   // (offsets whose centre can lie within l of a point in the (+,+,+) octant of
@@ -178,43 +189,40 @@ __global__ void __launch_bounds__(SMKI_WAVE) k_splat(SplatArgs a) {
   __syncthreads();
   const float4* __restrict__ pts = a.pts;
   uint32_t npair = 0;
-  int32_t gkey = -1, gcb = 0;   // current (cell, octant) group and its region index
+  // The open group: rows of one (cell, octant), whose sums the lanes hold in
+  // registers; its region index and the region-index offsets of its octant.
+  int32_t gkey = -1, gcb = 0, goc = -1;
+  int32_t cw[NS];
   float sum[NS];
 #pragma unroll
-  for (int s = 0; s < NS; ++s) sum[s] = 0.0f;
+  for (int s = 0; s < NS; ++s) {
+    sum[s] = 0.0f;
+    cw[s] = 0;
+  }
   // Flush: every lane adds its group sum (0 included) to its voxel of the
   // region, all reads of a flush first, then all writes; pad lanes (no stencil
-  // offset) use a dummy slot past the region.  Within one flush the lanes'
-  // addresses are distinct; the LDS executes one wavefront's reads and writes
-  // in issue order and the compiler keeps flushes in program order (signal
-  // fence), so every voxel sums its rows in row order.
+  // offset) touch nothing.  Within one flush the lanes' addresses are distinct;
+  // the LDS executes one wavefront's reads and writes in issue order and the
+  // compiler keeps flushes in program order (signal fence), so every voxel
+  // sums its groups in processing order: run-to-run identical.
   auto flush = [&]() {
-    const int oc = gkey & 7;
-    int32_t base[NS];
-#pragma unroll
-    // only the last step has pad lanes (NS = ceil(stencil size / 64))
-    for (int s = 0; s < NS; ++s) base[s] = (s == NS - 1 && pad[s]) ? DR3 : gcb;
+    int32_t fa[NS];
+    float fo[NS];
     __atomic_signal_fence(__ATOMIC_SEQ_CST);
-    switch (oc) {
-#define SMKI_FLUSH_CASE(OC)                                                  \
-  case OC: {                                                                 \
-    float old[NS];                                                           \
-    _Pragma("unroll") for (int s = 0; s < NS; ++s)                           \
-        old[s] = acc[base[s] + wl[OC][s]];                                   \
-    _Pragma("unroll") for (int s = 0; s < NS; ++s)                           \
-        acc[base[s] + wl[OC][s]] = fmaf(cscale, sum[s], old[s]);             \
-    break;                                                                   \
-  }
-      SMKI_FLUSH_CASE(0) SMKI_FLUSH_CASE(1) SMKI_FLUSH_CASE(2) SMKI_FLUSH_CASE(3)
-      SMKI_FLUSH_CASE(4) SMKI_FLUSH_CASE(5) SMKI_FLUSH_CASE(6) SMKI_FLUSH_CASE(7)
-#undef SMKI_FLUSH_CASE
+#pragma unroll
+    for (int s = 0; s < NS; ++s) {
+      fa[s] = gcb + cw[s];
+      // only the last step has pad lanes (NS = ceil(stencil size / 64))
+      if (!(s == NS - 1 && pad[s])) fo[s] = acc[fa[s]];
     }
 #pragma unroll
-    for (int s = 0; s < NS; ++s) sum[s] = 0.0f;
+    for (int s = 0; s < NS; ++s) {
+      if (!(s == NS - 1 && pad[s])) acc[fa[s]] = fo[s] + sum[s];
+      sum[s] = 0.0f;
+    }
   };
-  // Rows are staged 64 at a time in registers (lane i holds row base + i) and
-  // broadcast with v_readlane; two batches alternate so that one loads while
-  // the other is processed.
+  // Rows are staged 64 at a time in registers (lane i holds row base + i); two
+  // batches alternate so that one loads while the other is processed.
   // A batch: the rows' records and (W) their weights.
   struct Batch {
     float4 r;
@@ -233,51 +241,93 @@ __global__ void __launch_bounds__(SMKI_WAVE) k_splat(SplatArgs a) {
     b.w = W ? a.wts[v] : 1.0f;
     return b;
   };
+  // One row (j of the batch, its |u| and |u|^2 in q, read from LDS one row
+  // earlier): group change, the read of the next row (jn, into qn), then the
+  // row's contribution to every stencil offset.  The wait for q sits first, so
+  // that no wait for the next read stalls the arithmetic.
+  auto row = [&](const Batch& bt, int32_t keyl, int j, const float4& q, int jn, float4& qn) {
+    asm volatile("" ::"v"(q.x), "v"(q.y), "v"(q.z), "v"(q.w));
+    const int32_t key = __builtin_amdgcn_readlane(keyl, j);
+    const float wr = W ? __int_as_float(__builtin_amdgcn_readlane(__float_as_int(bt.w), j)) : 1.0f;
+    if (key != gkey) {
+      if (gkey >= 0) flush();
+      gkey = key;
+      const uint32_t c = (uint32_t)key >> 3;   // the cell: x, y, z of log2(B) bits each
+      gcb = (int32_t)(((c / (B * B) + R) * DR + ((c / B) % B + R)) * DR + (c % B + R));
+    }
+    qn = rowq[jn];
+    // Branch-free: every lane evaluates its pair; s = 1 - d/l clamped to [0, 1]
+    // (the clamp is free on the fused multiply-add) is 0 out of support, which
+    // zeroes the weight s^5 Q(s^2).
+#pragma unroll
+    for (int s = 0; s < NS; ++s) {
+      // |d2| only guards rounding below 0 when the row sits on the voxel centre
+      const float d2 = fmaf(q.z, nwz[s], fmaf(q.y, nwy[s], fmaf(q.x, nwx[s], q.w + w2[s])));
+      const bool in = d2 < l2;
+      const uint64_t inm = __ballot(in);
+      npair += (uint32_t)__popcll(inm);
+      // the last step holds the farthest offsets (the stencil is ordered by
+      // distance): a row that reaches none of them skips it
+      if (NS > 1 && s == NS - 1 && inm == 0) continue;
+      const float d = __builtin_amdgcn_sqrtf(fabsf(d2));
+      const float sv = __builtin_amdgcn_fmed3f(fmaf(-d, inv_l, 1.0f), 0.0f, 1.0f);
+      const float uu = sv * sv;
+      float qq = fmaf(uu, cq[0], cq[1]);
+#pragma unroll
+      for (int i = 2; i < SMKI_POLY_N; ++i) qq = fmaf(qq, uu, cq[i]);
+      if (W)
+        sum[s] = fmaf(uu * uu, (sv * wr) * qq, sum[s]);
+      else
+        sum[s] = fmaf(uu * uu, sv * qq, sum[s]);
+    }
+  };
+  // One batch: its rows go to LDS (read back by every lane, one row at a time)
+  // and are taken octant by octant, each octant's rows in sorted order, so that
+  // the region-index offsets change at most eight times per batch.
   auto process = [&](const Batch& bt, int32_t base) {
     const int nb = min(SMKI_WAVE, r1 - base);
     const float4& cur = bt.r;
-    // Consume the batch once here, so that the only wait for its load (and not
-    // for the other batch's, issued later) sits before the row loop.
-    asm volatile("" ::"v"(cur.x), "v"(cur.y), "v"(cur.z), "v"(cur.w));
+    // (consume the weights here, so that no wait for their load sits in the row loop)
     if (W) asm volatile("" ::"v"(bt.w));
-    // |q|^2 of every row of the batch, once per lane
     const float q2l = fmaf(cur.x, cur.x, fmaf(cur.y, cur.y, cur.z * cur.z));
-    for (int j = 0; j < nb; ++j) {
-      const float qx = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(cur.x), j));
-      const float qy = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(cur.y), j));
-      const float qz = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(cur.z), j));
-      const int32_t key = __builtin_amdgcn_readlane(__float_as_int(cur.w), j);
-      const float wr = W ? __int_as_float(__builtin_amdgcn_readlane(__float_as_int(bt.w), j)) : 1.0f;
-      if (key != gkey) {
+    // (the previous batch's reads of rowq were issued before this write)
+    rowq[lane] = make_float4(cur.x, cur.y, cur.z, q2l);
+    const int32_t keyl = __float_as_int(cur.w);
+    const bool valid = lane < nb;
+#pragma unroll 1
+    for (int oc = 0; oc < 8; ++oc) {
+      uint64_t mask = __ballot(valid && (keyl & 7) == oc);
+      if (mask == 0) continue;
+      if (oc != goc) {
         if (gkey >= 0) flush();
-        gkey = key;
-        const int c = key >> 3;
-        gcb = ((c / (B * B) + R) * DR + ((c / B) % B + R)) * DR + (c % B + R);
+        gkey = -1;
+        goc = oc;
+        switch (oc) {
+#define SMKI_OCT_CASE(OC)                                        \
+  case OC:                                                       \
+    _Pragma("unroll") for (int s = 0; s < NS; ++s) cw[s] = wl[OC][s]; \
+    break;
+          SMKI_OCT_CASE(0) SMKI_OCT_CASE(1) SMKI_OCT_CASE(2) SMKI_OCT_CASE(3)
+          SMKI_OCT_CASE(4) SMKI_OCT_CASE(5) SMKI_OCT_CASE(6) SMKI_OCT_CASE(7)
+#undef SMKI_OCT_CASE
+        }
       }
-      const float q2 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(q2l), j));
-      // Branch-free: every lane evaluates its pair; s = 1 - d/l clamped to [0, 1]
-      // (the clamp is free on the fused multiply-add) is 0 out of support, which
-      // zeroes the weight s^5 Q(s^2).
-#pragma unroll
-      for (int s = 0; s < NS; ++s) {
-        // |d2| only guards rounding below 0 when the row sits on the voxel centre
-        const float d2 = fmaf(qz, nwz[s], fmaf(qy, nwy[s], fmaf(qx, nwx[s], q2 + w2[s])));
-        const bool in = d2 < l2;
-        const uint64_t inm = __ballot(in);
-        npair += (uint32_t)__popcll(inm);
-        // the last step holds the farthest offsets (the stencil is ordered by
-        // distance): a row that reaches none of them skips it
-        if (NS > 1 && s == NS - 1 && inm == 0) continue;
-        const float d = __builtin_amdgcn_sqrtf(fabsf(d2));
-        const float sv = __builtin_amdgcn_fmed3f(fmaf(-d, inv_l, 1.0f), 0.0f, 1.0f);
-        const float uu = sv * sv;
-        float qq = uu + a.mcoef[1];
-#pragma unroll
-        for (int i = 2; i < SMKI_POLY_N; ++i) qq = fmaf(qq, uu, a.mcoef[i]);
-        if (W)
-          sum[s] = fmaf(uu * uu, (sv * wr) * qq, sum[s]);
-        else
-          sum[s] = fmaf(uu * uu, sv * qq, sum[s]);
+      // Rows of this octant, two at a time through two row registers: the next
+      // row is read while this one is processed.
+      int j = (int)__builtin_ctzll(mask);
+      mask &= mask - 1;
+      float4 qa = rowq[j], qb;
+      while (true) {
+        int jn = mask ? (int)__builtin_ctzll(mask) : j;
+        row(bt, keyl, j, qa, jn, qb);
+        if (!mask) break;
+        mask &= mask - 1;
+        j = jn;
+        jn = mask ? (int)__builtin_ctzll(mask) : j;
+        row(bt, keyl, j, qb, jn, qa);
+        if (!mask) break;
+        mask &= mask - 1;
+        j = jn;
       }
     }
   };
@@ -303,15 +353,14 @@ __global__ void __launch_bounds__(SMKI_WAVE) k_splat(SplatArgs a) {
   float* out = a.part + (int64_t)uid * DR3;
   constexpr int MAXPER = (B * B * B + SMKI_WAVE - 1) / SMKI_WAVE;   // the largest piece is the block
   uint32_t touched = 0;
+  if constexpr (MAXPER > 8) {
 #pragma unroll
-  for (int p = 0; p < 27; ++p) {
-    if (!((a.piece_mask >> p) & 1u)) continue;
-    const int ex = PC::ext(p / 9 - 1), ey = PC::ext((p / 3) % 3 - 1), ez = PC::ext(p % 3 - 1);
-    const int sx = PC::rstart(p / 9 - 1), sy = PC::rstart((p / 3) % 3 - 1),
-              sz = PC::rstart(p % 3 - 1);
-    const int n = ex * ey * ez, b = PC::base(p);
-    const int per = (n + SMKI_WAVE - 1) / SMKI_WAVE;
-    if constexpr (MAXPER > 8) {
+    for (int p = 0; p < 27; ++p) {
+      if (!((a.piece_mask >> p) & 1u)) continue;
+      const int ey = PC::ext((p / 3) % 3 - 1), ez = PC::ext(p % 3 - 1);
+      const int sx = PC::rstart(p / 9 - 1), sy = PC::rstart((p / 3) % 3 - 1),
+                sz = PC::rstart(p % 3 - 1);
+      const int n = PC::size(p), b = PC::base(p);
       // large blocks: vote while reading, then read again to store (no
       // register copy of the piece)
       bool nz = false;
@@ -325,26 +374,52 @@ __global__ void __launch_bounds__(SMKI_WAVE) k_splat(SplatArgs a) {
         const int lx = i / (ey * ez), ly = (i / ez) % ey, lz = i % ez;
         out[b + i] = acc[((sx + lx) * DR + (sy + ly)) * DR + (sz + lz)];
       }
-    } else {
+    }
+  } else {
+    // Region index of element i = lane + 64 k of a piece, relative to the
+    // piece's first voxel, for each pair of (y, z) extents in {R, B}: computed
+    // once here (the x extent only bounds i).
+    constexpr int KRR = (B * R * R + SMKI_WAVE - 1) / SMKI_WAVE,
+                  KRB = (B * R * B + SMKI_WAVE - 1) / SMKI_WAVE;
+    int32_t lRR[KRR > 0 ? KRR : 1], lRB[KRB > 0 ? KRB : 1], lBR[KRB > 0 ? KRB : 1], lBB[MAXPER];
+    auto rel = [&](int ey, int ez, int i) { return ((i / (ey * ez)) * DR + (i / ez) % ey) * DR + i % ez; };
+#pragma unroll
+    for (int k = 0; k < MAXPER; ++k) {
+      const int i = lane + k * SMKI_WAVE;
+      if (k < KRR) lRR[k] = rel(R, R, i);
+      if (k < KRB) {
+        lRB[k] = rel(R, B, i);
+        lBR[k] = rel(B, R, i);
+      }
+      lBB[k] = rel(B, B, i);
+    }
+#pragma unroll
+    for (int p = 0; p < 27; ++p) {
+      if (!((a.piece_mask >> p) & 1u)) continue;
+      const bool yr = (p / 3) % 3 != 1, zr = p % 3 != 1;   // y / z extent R (else B)
+      const int sx = PC::rstart(p / 9 - 1), sy = PC::rstart((p / 3) % 3 - 1),
+                sz = PC::rstart(p % 3 - 1);
+      const int n = PC::size(p), b = PC::base(p);
+      const int per = (n + SMKI_WAVE - 1) / SMKI_WAVE;
+      const int S = (sx * DR + sy) * DR + sz;
       float v[MAXPER];
       bool nz = false;
 #pragma unroll
       for (int k = 0; k < MAXPER; ++k) {
         v[k] = 0.0f;
-        const int i = lane + k * SMKI_WAVE;
-        if (k < per && i < n) {
-          const int lx = i / (ey * ez), ly = (i / ez) % ey, lz = i % ez;
-          v[k] = acc[((sx + lx) * DR + (sy + ly)) * DR + (sz + lz)];
+        if (k < per && lane + k * SMKI_WAVE < n) {
+          const int r = yr ? (zr ? lRR[k < KRR ? k : 0] : lRB[k < KRB ? k : 0])
+                           : (zr ? lBR[k < KRB ? k : 0] : lBB[k]);
+          v[k] = acc[S + r];
           nz = nz || v[k] != 0.0f;
         }
       }
       if (__ballot(nz) == 0) continue;
       touched |= 1u << p;
+      float* ob = out + b;
 #pragma unroll
-      for (int k = 0; k < MAXPER; ++k) {
-        const int i = lane + k * SMKI_WAVE;
-        if (k < per && i < n) out[b + i] = v[k];
-      }
+      for (int k = 0; k < MAXPER; ++k)
+        if (k < per && lane + k * SMKI_WAVE < n) ob[lane + k * SMKI_WAVE] = v[k];
     }
   }
   if (lane == 0) a.umask[uid] = touched;
