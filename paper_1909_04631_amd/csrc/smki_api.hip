@@ -735,7 +735,7 @@ smki_status insert_impl(smki_map* m, const float* xyz, const int32_t* label, con
   const int64_t ntk = (int64_t)n_t * m->K;
   zc.add<char>(scan_tmp_bytes(std::max<int64_t>(ntk, 1)));
   zc.add<int4>(n_units);
-  zc.add<float>((size_t)n_units * DR3);
+  zc.add<float>(SMKI_PART_HEAD + (size_t)n_units * DR3);
   zc.add<uint32_t>(n_units);
   zc.add<int32_t>(n_units);   // splat launch order
   zc.add<int4>(n_slots);
@@ -752,7 +752,7 @@ smki_status insert_impl(smki_map* m, const float* xyz, const int32_t* label, con
   int32_t* d_rank = C.take<int32_t>(n_t);
   void* d_ctmp = C.take<char>(scan_tmp_bytes(std::max<int64_t>(ntk, 1)));
   int4* d_units = C.take<int4>(n_units);
-  float* d_part = C.take<float>((size_t)n_units * DR3);
+  float* d_part = C.take<float>(SMKI_PART_HEAD + (size_t)n_units * DR3);
   uint32_t* d_umask = C.take<uint32_t>(n_units);
   int32_t* d_uorder = C.take<int32_t>(n_units);
   int4* d_sinfo = C.take<int4>(n_slots);
@@ -764,7 +764,7 @@ smki_status insert_impl(smki_map* m, const float* xyz, const int32_t* label, con
   sa.units = d_units;
   sa.uorder = d_uorder;
   sa.part = d_part;
-  sa.part_elems = n_units * DR3;
+  sa.part_elems = SMKI_PART_HEAD + n_units * DR3;
   sa.wide = (m->flags & SMKI_FLAG_WIDE_OFFSETS) ? 1 : 0;
   sa.umask = d_umask;
   sa.sinfo = d_sinfo;
@@ -948,7 +948,7 @@ size_t carve_batch(smki_batch* b, char* base) {
   d.rank = c.take<int32_t>(ne);
   d.ctmp = c.take<char>(scan_tmp_bytes(std::max<int64_t>(ntk, 1)));
   d.units = c.take<int4>(NU);
-  d.part = c.take<float>((size_t)NU * DR3);
+  d.part = c.take<float>(SMKI_PART_HEAD + (size_t)NU * DR3);
   d.umask = c.take<uint32_t>(NU);
   d.uorder = c.take<int32_t>(NU);
   d.sinfo = c.take<int4>(NS);
@@ -1051,7 +1051,7 @@ smki_status batch_enqueue(smki_batch* b, hipStream_t q) {
   sa.units = d.units;
   sa.uorder = d.uorder;
   sa.part = d.part;
-  sa.part_elems = b->cap_units * DR * DR * DR;
+  sa.part_elems = SMKI_PART_HEAD + (int64_t)b->cap_units * DR * DR * DR;
   sa.wide = (m->flags & SMKI_FLAG_WIDE_OFFSETS) ? 1 : 0;
   sa.umask = d.umask;
   sa.sinfo = d.sinfo;
@@ -1711,9 +1711,11 @@ smki_status smki_batch_capture(smki_map* m, const float* xyz, const int32_t* lab
                                    (int64_t)ceil((double)st.n_point_blocks * grow) + 1024);
   b->cap_units = (int64_t)ceil((double)st.n_units * grow) + 1024;
   const int64_t DR = m->B + 2 * b->sten.R;
-  // keep the partial sums under 4 GiB (32-bit offsets in the merge) when the
-  // sizing insert's fitted
-  const int64_t narrow_units = (int64_t(1) << 32) / (int64_t)(sizeof(float) * DR * DR * DR);
+  // keep the partial sums under 4 GiB and 2^24 units (32-bit offsets in the
+  // merge) when the sizing insert's fitted
+  const int64_t narrow_units =
+      std::min<int64_t>(((int64_t(1) << 32) - 4 * SMKI_PART_HEAD) / (int64_t)(sizeof(float) * DR * DR * DR),
+                        (int64_t(1) << 24) - 1);
   if (st.n_units <= narrow_units && !(m->flags & SMKI_FLAG_WIDE_OFFSETS))
     b->cap_units = std::min(b->cap_units, narrow_units);
   if (g.n_blocks * m->K > (int64_t(1) << 30) || b->n_ext > (int64_t(1) << 30) ||

@@ -8,6 +8,7 @@
 #define SMKI_CHUNK 512              // default rows of one (class, block) per splat work unit
 #define SMKI_STAT_COPIES 64         // copies of the insert counters (spread the atomics)
 #define SMKI_TIMING_RING 64         // inserts whose kernel times are kept
+#define SMKI_PART_HEAD 64           // zero words heading the partial sums (read for absent pieces)
 
 // Sparse kernel of Eq. (8): f(1 - s) = s^5 Q(s^2) with s = 1 - d/l.  Q below is a
 // degree-6 relative least-squares fit in u = s^2 on [0, 1] to the series
@@ -61,9 +62,10 @@ struct SplatArgs {
   const int32_t* ustart;      // [slots] first unit of the slot
   const int4* units;          // [n_units] (first row, end row, slot, class)
   const int32_t* uorder;      // [n_units] unit of splat workgroup b (nullable: b itself)
-  int64_t part_elems;         // n_units (B + 2R)^3
+  int64_t part_elems;         // SMKI_PART_HEAD + n_units (B + 2R)^3
   int32_t wide;               // 1: 64-bit offsets into part even below 4 GiB
-  float* part;                // [n_units][(B + 2R)^3] partial sums of each unit's region, by
+  float* part;                // SMKI_PART_HEAD zeros (written by the splat), then
+                              // [n_units][(B + 2R)^3] partial sums of each unit's region, by
                               // piece: the region split into the 27 parts that fall in the
                               // unit's block and its neighbours, each contiguous (x, y, z)
   uint32_t* umask;            // [n_units] bit d: piece d is non-zero (and written)

@@ -143,6 +143,8 @@ __global__ void __launch_bounds__(SMKI_WAVE) k_splat(SplatArgs a) {
   __shared__ float4 rowq[SMKI_WAVE];   // the batch being processed: (|u| per axis, |u|^2) per row
   float* acc = (float*)acc4;
   const int lane = threadIdx.x;
+  // the zero words that the merge reads for absent pieces
+  if (blockIdx.x == 0 && lane < SMKI_PART_HEAD) a.part[lane] = 0.0f;
   if (a.dn_units && (int32_t)blockIdx.x >= *a.dn_units) return;   // capacity launch
   if (a.abort_word && *a.abort_word) return;   // (a failed captured insert: the units may be stale)
   const int32_t uid = a.uorder ? a.uorder[blockIdx.x] : (int32_t)blockIdx.x;
@@ -350,7 +352,7 @@ __global__ void __launch_bounds__(SMKI_WAVE) k_splat(SplatArgs a) {
   // contiguously.  Piece geometry is compile-time, so the index arithmetic
   // folds to constants.
   using PC = Pieces<B, R>;
-  float* out = a.part + (int64_t)uid * DR3;
+  float* out = a.part + SMKI_PART_HEAD + (int64_t)uid * DR3;
   constexpr int MAXPER = (B * B * B + SMKI_WAVE - 1) / SMKI_WAVE;   // the largest piece is the block
   uint32_t touched = 0;
   if constexpr (MAXPER > 8) {
@@ -448,30 +450,34 @@ __global__ void k_slot_info(SplatArgs a) {
   if (j == 0) a.sinfo[s] = make_int4(u0, nu, (int32_t)m, nu > 0 ? (int32_t)a.umask[u0] : 0);
 }
 
-// Partial sum at element off of unit w's region.  Below 4 GiB of partial sums
-// (WIDE false) the address is a 32-bit byte offset from the buffer base, so
-// that a load takes one address register instead of two.
+// Partial sum at element off of unit w's region; unit w < 0 reads the zero
+// word at the head of the buffer.  Below 4 GiB of partial sums (WIDE false) the
+// address is a 32-bit byte offset from the buffer base (unit times region size
+// in a 24-bit multiply: fewer than 2^24 units fit there), so that a load takes
+// one address register instead of two.
 template <int DR3, bool WIDE>
 __device__ __forceinline__ float part_at(const float* part, int32_t w, int32_t off) {
-  if (WIDE) return part[(int64_t)w * DR3 + off];
-  const uint32_t byte = ((uint32_t)w * (uint32_t)DR3 + (uint32_t)off) * 4u;
-  return *(const float*)((const char*)part + byte);
+  if (WIDE) return part[w < 0 ? (int64_t)0 : SMKI_PART_HEAD + (int64_t)w * DR3 + off];
+  const uint32_t e = ((uint32_t)SMKI_PART_HEAD + __umul24((uint32_t)w & 0xffffffu, (uint32_t)DR3) +
+                      (uint32_t)off) * 4u;
+  return *(const float*)((const char*)part + (w < 0 ? 0u : e));
 }
 
 // (B = 8 up to reach 3: at most 64 registers, eight wavefronts per SIMD)
 // One workgroup per active target block, one thread per voxel (blocks of more
-// than 1024 voxels: several voxels per thread).  Each thread first lists, the neighbours whose regions cover its voxel and the
-// offset of its voxel in the corresponding piece.  The workgroup then looks up
-// the slots of the 27 neighbouring blocks for a group of classes into LDS (all
-// lookups in flight together), keeping for each neighbour only whether its
-// units wrote the piece that lies in this block, and lists the classes that
-// have any.  For every listed class, each thread adds, in double, the pieces
-// that cover its voxel: the first chunks of all its candidates (loads issued
-// together, in the fixed neighbour order), then the later chunks of multi-chunk
-// slots eight at a time; blocks
-// allocated by this insert are written alpha0 + sum, older blocks updated in
-// place where the sum is non-zero.  The per-thread state is kept small (packed
-// candidates, slot entries re-read from LDS) so that 8 wavefronts fit per SIMD.
+// than 1024 voxels: several voxels per thread).  Each thread first lists the
+// neighbours whose regions cover its voxel and the offset of its voxel in the
+// corresponding piece.  For a group of classes, the workgroup lists the classes
+// whose rows reach this block and looks up the slots of the 27 neighbouring
+// blocks into LDS (for all classes of the group at once when one round of
+// lookups covers them, else for the listed classes), keeping for each neighbour
+// only whether its units wrote the piece that lies in this block.  For every listed class, each thread adds, in double, the pieces that
+// cover its voxel: the first chunks of all its candidates (loads issued
+// together, in the fixed neighbour order; an absent one reads a zero word),
+// then the later chunks of multi-chunk slots eight at a time; blocks allocated
+// by this insert are written alpha0 + sum, older blocks updated in place where
+// the sum is non-zero.  The per-thread state is kept small (packed candidates,
+// slot entries re-read from LDS) so that 8 wavefronts fit per SIMD.
 template <int B, int R, bool WIDE>
 __global__ void __launch_bounds__((B * B * B < 1024 ? B * B * B : 1024), (B == 8 && R <= 3 && !WIDE) ? 8 : 1)
 k_merge(SplatArgs a, int32_t n_targets) {
@@ -479,9 +485,10 @@ k_merge(SplatArgs a, int32_t n_targets) {
   constexpr int DR = B + 2 * R;
   constexpr int DR3 = DR * DR * DR;
   constexpr int B3 = S::B3, NT = S::NT, CPG = S::CPG, MAXC = S::MAXC, VPT = S::VPT;
-  // [class][neighbour d]: (first unit, units) of the neighbour's slot if some
-  // unit of it wrote piece 26 - d (the part of its region inside this block),
-  // else (0, 0); units negated when the first unit did not write the piece
+  // [class (or listed class)][neighbour d]: (first unit, units) of the
+  // neighbour's slot if some unit of it wrote piece 26 - d (the part of its
+  // region inside this block), else (0, 0); units negated when the first unit
+  // did not write it
   __shared__ int2 ent[CPG * 27];
   __shared__ int32_t cflag[CPG], clist[CPG], cblk[CPG], ncls_s;
   __shared__ int32_t red[(NT + SMKI_WAVE - 1) / SMKI_WAVE];
@@ -509,50 +516,84 @@ k_merge(SplatArgs a, int32_t n_targets) {
   uint32_t upd = 0;   // bit i: voxel tid + i NT received a non-zero sum
   for (int y0 = 0; y0 < a.K; y0 += CPG) {
     const int ny = min(CPG, a.K - y0);
+    // Slots of the 27 neighbouring blocks, entry i = class * 27 + neighbour,
+    // two per thread and round, their loads in flight together: for every
+    // class of the group when that takes one round (issued with the class
+    // flags), else only for the classes listed as reaching this block.
+    // (compile-time: one round covers a whole group for blocks of 8^3 and more)
+    constexpr bool all = 27 * CPG <= 2 * NT;
+    auto list_classes = [&]() {   // the classes with contributions, in class order
+      if (tid < SMKI_WAVE) {
+        const bool f = tid < ny && cflag[tid] != 0;
+        const uint64_t m = __ballot(f);
+        if (f) clist[__popcll(m & ((1ull << tid) - 1ull))] = tid;
+        if (tid == 0) ncls_s = __popcll(m);
+      }
+    };
     // classes whose rows reach this block, and their class blocks
     if (tid < ny) {
       cflag[tid] = a.contrib[(int64_t)t * a.K + y0 + tid];
       cblk[tid] = a.map.cslot[(int64_t)mslot * a.K + y0 + tid];
     }
-    // two lookups per thread and round, their loads in flight together
-    for (int i0 = tid; i0 < 27 * ny; i0 += 2 * NT) {
+    if constexpr (!all) {
+      __syncthreads();
+      list_classes();
+      __syncthreads();
+      if (ncls_s == 0) continue;   // (uniform; nothing below reads this group's tables)
+    }
+    // lookup i of this round: class yc, neighbour d
+    auto lookup = [&](int yc, int d) {
+      const int px = pt[0] + d / 9 - 1, py = pt[1] + (d / 3) % 3 - 1, pz = pt[2] + d % 3 - 1;
+      if (px >= 0 && py >= 0 && pz >= 0 && px < a.g.nb[0] && py < a.g.nb[1] && pz < a.g.nb[2])
+        return a.dense[(((int64_t)px * a.g.nb[1] + py) * a.g.nb[2] + pz) * a.K + y0 + yc];
+      return -1;
+    };
+    auto entry = [&](int32_t sl, int d) {
+      int2 e2 = make_int2(0, 0);
+      if (sl >= 0) {
+        const int4 e = a.sinfo[sl];
+        if ((e.z >> (26 - d)) & 1) e2 = make_int2(e.x, ((e.w >> (26 - d)) & 1) ? e.y : -e.y);
+      }
+      return e2;
+    };
+    const int nl = all ? ny : ncls_s;
+    for (int i0 = tid; i0 < 27 * nl; i0 += 2 * NT) {
       int32_t sl[2];
 #pragma unroll
       for (int j = 0; j < 2; ++j) {
         const int i = i0 + j * NT;
         sl[j] = -1;
-        if (i < 27 * ny) {
-          const int d = i / ny, yc = i - d * ny;
-          const int px = pt[0] + d / 9 - 1, py = pt[1] + (d / 3) % 3 - 1, pz = pt[2] + d % 3 - 1;
-          if (px >= 0 && py >= 0 && pz >= 0 && px < a.g.nb[0] && py < a.g.nb[1] && pz < a.g.nb[2])
-            sl[j] = a.dense[(((int64_t)px * a.g.nb[1] + py) * a.g.nb[2] + pz) * a.K + y0 + yc];
+        if (i < 27 * nl) {
+          if constexpr (all) {   // i = d * ny + class
+            const int d = i / ny;
+            sl[j] = lookup(i - d * ny, d);
+          } else {               // i = listed class * 27 + d
+            const int c = i / 27;
+            sl[j] = lookup(clist[c], i - 27 * c);
+          }
         }
       }
 #pragma unroll
       for (int j = 0; j < 2; ++j) {
         const int i = i0 + j * NT;
-        if (i >= 27 * ny) continue;
-        const int d = i / ny, yc = i - d * ny;
-        int2 e2 = make_int2(0, 0);
-        if (sl[j] >= 0) {
-          const int4 e = a.sinfo[sl[j]];
-          if ((e.z >> (26 - d)) & 1) e2 = make_int2(e.x, ((e.w >> (26 - d)) & 1) ? e.y : -e.y);
+        if (i >= 27 * nl) continue;
+        if constexpr (all) {
+          const int d = i / ny, yc = i - d * ny;
+          ent[yc * 27 + d] = entry(sl[j], d);
+        } else {
+          ent[i] = entry(sl[j], i % 27);
         }
-        ent[yc * 27 + d] = e2;
       }
     }
     __syncthreads();
-    if (tid < SMKI_WAVE) {   // list the classes with contributions, in class order
-      const bool f = tid < ny && cflag[tid] != 0;
-      const uint64_t m = __ballot(f);
-      if (f) clist[__popcll(m & ((1ull << tid) - 1ull))] = tid;
-      if (tid == 0) ncls_s = __popcll(m);
+    if constexpr (all) {
+      list_classes();
+      __syncthreads();
     }
-    __syncthreads();
     const int ncls = ncls_s;
     for (int ic = 0; ic < ncls; ++ic) {
      const int yc = clist[ic];
-     const int2* E = ent + yc * 27;
+     const int2* E = ent + (all ? yc : ic) * 27;
      for (int vi = 0; vi < VPT; ++vi) {
       const int vox = tid + vi * NT;
       if (VPT > 1) candidates(vox);
@@ -572,9 +613,9 @@ k_merge(SplatArgs a, int32_t n_targets) {
         sm = (float)sd;
       } else {
         // Branch-free over the candidates: every candidate loads (an absent one
-        // reads element 0 of the buffer and discards it) and the sum is kept in
-        // double; then the later units of multi-unit slots, eight at a time
-        // (their masks, then their pieces, each set of loads in flight together).
+        // reads a zero word) and the sum is kept in double; then the later units
+        // of multi-unit slots, eight at a time (their masks, then their pieces,
+        // each set of loads in flight together).
         float first[MAXC];
         bool more = false;
 #pragma unroll
@@ -582,8 +623,7 @@ k_merge(SplatArgs a, int32_t n_targets) {
           const int pkk = pk[k];
           const int2 e = E[pkk >= 0 ? (pkk >> 16) : 13];
           const bool ld = pkk >= 0 && e.y > 0;
-          const float v = part_at<DR3, WIDE>(a.part, ld ? e.x : 0, ld ? (pkk & 0xffff) : 0);
-          first[k] = ld ? v : 0.0f;
+          first[k] = part_at<DR3, WIDE>(a.part, ld ? e.x : -1, pkk & 0xffff);
           more = more || (pkk >= 0 && (e.y > 1 || e.y < -1));
         }
         double sd = 0.0;
@@ -604,8 +644,7 @@ k_merge(SplatArgs a, int32_t n_targets) {
 #pragma unroll
               for (int j = 0; j < 8; ++j) {
                 const bool has = (mk[j] >> (26 - ci)) & 1u;
-                const float x = part_at<DR3, WIDE>(a.part, has ? w0 + j : 0, has ? (pk[k] & 0xffff) : 0);
-                v[j] = has ? x : 0.0f;
+                v[j] = part_at<DR3, WIDE>(a.part, has ? w0 + j : -1, pk[k] & 0xffff);
               }
 #pragma unroll
               for (int j = 0; j < 8; ++j) sd += (double)v[j];
@@ -771,7 +810,9 @@ hipError_t launch_splat_br(const SplatArgs& a, int64_t n_units, int32_t n_target
                                                  st);
   } else {
     if (n_targets > 0) {
-      if (!a.wide && a.part_elems * sizeof(float) <= (int64_t(1) << 32))
+      constexpr int64_t DR3 = (int64_t)(B + 2 * R) * (B + 2 * R) * (B + 2 * R);
+      if (!a.wide && a.part_elems * sizeof(float) <= (int64_t(1) << 32) &&
+          (a.part_elems - SMKI_PART_HEAD) / DR3 < (int64_t(1) << 24))
         hipLaunchKernelGGL((k_merge<B, R, false>), dim3((unsigned)n_targets),
                            dim3(MergeShape<B, R>::NT), 0, st, a, n_targets);
       else
