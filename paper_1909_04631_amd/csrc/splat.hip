@@ -597,62 +597,46 @@ k_merge(SplatArgs a, int32_t n_targets) {
      for (int vi = 0; vi < VPT; ++vi) {
       const int vox = tid + vi * NT;
       if (VPT > 1) candidates(vox);
-      float sm = 0.0f;
-      if constexpr (MAXC > 8) {
-        // 2R > B (a reach of more than half the block edge): up to 27
-        // candidates, summed one at a time in double
-        double sd = 0.0;
+      // Branch-free over the candidates (up to 27 when 2R > B): every candidate
+      // loads (an absent one reads a zero word) and the sum is kept in double;
+      // then the later units of multi-unit slots, eight at a time (their masks,
+      // then their pieces, each set of loads in flight together).
+      float first[MAXC];
+      bool more = false;
+#pragma unroll
+      for (int k = 0; k < MAXC; ++k) {
+        const int pkk = pk[k];
+        const int2 e = E[pkk >= 0 ? (pkk >> 16) : 13];
+        const bool ld = pkk >= 0 && e.y > 0;
+        first[k] = part_at<DR3, WIDE>(a.part, ld ? e.x : -1, pkk & 0xffff);
+        more = more || (pkk >= 0 && (e.y > 1 || e.y < -1));
+      }
+      double sd = 0.0;
+#pragma unroll
+      for (int k = 0; k < MAXC; ++k) sd += (double)first[k];
+      if (more) {
+#pragma unroll
         for (int k = 0; k < MAXC; ++k) {
           if (pk[k] < 0) continue;
           const int ci = pk[k] >> 16;
           const int2 e = E[ci];
-          const int p = 26 - ci;
-          for (int32_t w = e.x; w < e.x + abs(e.y); ++w)
-            if ((a.umask[w] >> p) & 1u) sd += (double)part_at<DR3, WIDE>(a.part, w, pk[k] & 0xffff);
-        }
-        sm = (float)sd;
-      } else {
-        // Branch-free over the candidates: every candidate loads (an absent one
-        // reads a zero word) and the sum is kept in double; then the later units
-        // of multi-unit slots, eight at a time (their masks, then their pieces,
-        // each set of loads in flight together).
-        float first[MAXC];
-        bool more = false;
+          const int32_t w1 = e.x + abs(e.y);
+          for (int32_t w0 = e.x + 1; w0 < w1; w0 += 8) {
+            uint32_t mk[8];
 #pragma unroll
-        for (int k = 0; k < MAXC; ++k) {
-          const int pkk = pk[k];
-          const int2 e = E[pkk >= 0 ? (pkk >> 16) : 13];
-          const bool ld = pkk >= 0 && e.y > 0;
-          first[k] = part_at<DR3, WIDE>(a.part, ld ? e.x : -1, pkk & 0xffff);
-          more = more || (pkk >= 0 && (e.y > 1 || e.y < -1));
-        }
-        double sd = 0.0;
+            for (int j = 0; j < 8; ++j) mk[j] = w0 + j < w1 ? a.umask[w0 + j] : 0u;
+            float v[8];
 #pragma unroll
-        for (int k = 0; k < MAXC; ++k) sd += (double)first[k];
-        if (more) {
-#pragma unroll
-          for (int k = 0; k < MAXC; ++k) {
-            if (pk[k] < 0) continue;
-            const int ci = pk[k] >> 16;
-            const int2 e = E[ci];
-            const int32_t w1 = e.x + abs(e.y);
-            for (int32_t w0 = e.x + 1; w0 < w1; w0 += 8) {
-              uint32_t mk[8];
-#pragma unroll
-              for (int j = 0; j < 8; ++j) mk[j] = w0 + j < w1 ? a.umask[w0 + j] : 0u;
-              float v[8];
-#pragma unroll
-              for (int j = 0; j < 8; ++j) {
-                const bool has = (mk[j] >> (26 - ci)) & 1u;
-                v[j] = part_at<DR3, WIDE>(a.part, has ? w0 + j : -1, pk[k] & 0xffff);
-              }
-#pragma unroll
-              for (int j = 0; j < 8; ++j) sd += (double)v[j];
+            for (int j = 0; j < 8; ++j) {
+              const bool has = (mk[j] >> (26 - ci)) & 1u;
+              v[j] = part_at<DR3, WIDE>(a.part, has ? w0 + j : -1, pk[k] & 0xffff);
             }
+#pragma unroll
+            for (int j = 0; j < 8; ++j) sd += (double)v[j];
           }
         }
-        sm = (float)sd;
       }
+      const float sm = (float)sd;
       const int32_t cb = cblk[yc];   // allocated for every class with rows reaching here
       float* dst = a.map.calpha + (int64_t)cb * B3 + vox;
       if (cb >= n_cold) {
