@@ -133,9 +133,12 @@ struct Steps {
 
 // NS = ceil(stencil size / 64), the steps each row takes (compiled per value
 // so that the steps of a row are independent straight-line code).  W: rows carry
-// a weight (soft measurements) that scales their kernel values.
-template <int B, int R, int NS, bool W>
+// a weight (soft measurements) that scales their kernel values.  RPS: rows per
+// step; 2 for a stencil of at most 32 offsets (one step), whose two halves of
+// the wavefront then take two rows at once.
+template <int B, int R, int NS, bool W, int RPS>
 __global__ void __launch_bounds__(SMKI_WAVE) k_splat(SplatArgs a) {
+  static_assert(RPS == 1 || (RPS == 2 && NS == 1), "two rows per step only for a one-step stencil");
   constexpr int DR = B + 2 * R;                 // region edge (voxels)
   constexpr int DR3 = DR * DR * DR;
   constexpr int NACC4 = (DR3 + 3) / 4;
@@ -172,7 +175,7 @@ __global__ void __launch_bounds__(SMKI_WAVE) k_splat(SplatArgs a) {
   const double res = (double)a.g.res;
 #pragma unroll
   for (int s = 0; s < NS; ++s) {
-    const int o = s * SMKI_WAVE + lane;
+    const int o = s * SMKI_WAVE + (RPS == 2 ? (lane & 31) : lane);
     pad[s] = o >= a.noff;
     int4 off = a.offs[min(o, a.noff - 1)];   // unconditional load, pad lanes reset below
     if (pad[s]) off = make_int4(0, 0, 0, 0);
@@ -208,6 +211,16 @@ __global__ void __launch_bounds__(SMKI_WAVE) k_splat(SplatArgs a) {
   // compiler keeps flushes in program order (signal fence), so every voxel
   // sums its groups in processing order: run-to-run identical.
   auto flush = [&]() {
+    if constexpr (RPS == 2) {
+      // both halves hold sums of the same group for the same offsets: the
+      // lower half adds their total
+      const float tot = sum[0] + __shfl_xor(sum[0], 32);
+      const int32_t fa0 = gcb + cw[0];
+      __atomic_signal_fence(__ATOMIC_SEQ_CST);
+      if (lane < 32 && !pad[0]) acc[fa0] = acc[fa0] + tot;
+      sum[0] = 0.0f;
+      return;
+    }
     int32_t fa[NS];
     float fo[NS];
     __atomic_signal_fence(__ATOMIC_SEQ_CST);
@@ -283,6 +296,56 @@ __global__ void __launch_bounds__(SMKI_WAVE) k_splat(SplatArgs a) {
         sum[s] = fmaf(uu * uu, sv * qq, sum[s]);
     }
   };
+  // Two rows at once (RPS == 2): j in the lower half of the wavefront, jh (-1:
+  // none) in the upper, their |u| and |u|^2 in q (per half); the next pair's
+  // rows (jn, jnh) are read into qn.  A half's sums join the open group when
+  // its row belongs to it; a pair that spans two groups flushes in between.
+  auto cell_base = [&](int32_t key) {
+    const uint32_t c = (uint32_t)key >> 3;   // the cell: x, y, z of log2(B) bits each
+    return (int32_t)(((c / (B * B) + R) * DR + ((c / B) % B + R)) * DR + (c % B + R));
+  };
+  auto pair = [&](const Batch& bt, int32_t keyl, int j, int jh, const float4& q, int jn, int jnh,
+                  float4& qn) {
+    asm volatile("" ::"v"(q.x), "v"(q.y), "v"(q.z), "v"(q.w));
+    const bool hi = lane >= 32;
+    qn = rowq[(hi && jnh >= 0) ? jnh : jn];
+    const int32_t klo = __builtin_amdgcn_readlane(keyl, j);
+    const int32_t khi = jh >= 0 ? __builtin_amdgcn_readlane(keyl, jh) : -1;
+    const bool act = !hi || jh >= 0;   // this half has a row
+    float wr = 1.0f;
+    if (W) {
+      const float wlo = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(bt.w), j));
+      const float whi = jh >= 0 ? __int_as_float(__builtin_amdgcn_readlane(__float_as_int(bt.w), jh)) : 0.0f;
+      wr = hi ? whi : wlo;
+    }
+    const float d2 = fmaf(q.z, nwz[0], fmaf(q.y, nwy[0], fmaf(q.x, nwx[0], q.w + w2[0])));
+    const bool in = act && d2 < l2;
+    npair += (uint32_t)__popcll(__ballot(in));
+    const float d = __builtin_amdgcn_sqrtf(fabsf(d2));
+    const float sv = __builtin_amdgcn_fmed3f(fmaf(-d, inv_l, 1.0f), 0.0f, 1.0f);
+    const float uu = sv * sv;
+    float qq = fmaf(uu, cq[0], cq[1]);
+#pragma unroll
+    for (int i = 2; i < SMKI_POLY_N; ++i) qq = fmaf(qq, uu, cq[i]);
+    float v = W ? (uu * uu) * ((sv * wr) * qq) : (uu * uu) * (sv * qq);
+    if (!act) v = 0.0f;
+    if (klo != gkey) {
+      if (gkey >= 0) flush();
+      gkey = klo;
+      gcb = cell_base(klo);
+    }
+    if (khi == gkey) {
+      sum[0] += v;
+    } else {
+      sum[0] += hi ? 0.0f : v;
+      if (jh >= 0) {
+        flush();
+        gkey = khi;
+        gcb = cell_base(khi);
+        sum[0] = hi ? v : 0.0f;
+      }
+    }
+  };
   // One batch: its rows go to LDS (read back by every lane, one row at a time)
   // and are taken octant by octant, each octant's rows in sorted order, so that
   // the region-index offsets change at most eight times per batch.
@@ -313,6 +376,32 @@ __global__ void __launch_bounds__(SMKI_WAVE) k_splat(SplatArgs a) {
           SMKI_OCT_CASE(4) SMKI_OCT_CASE(5) SMKI_OCT_CASE(6) SMKI_OCT_CASE(7)
 #undef SMKI_OCT_CASE
         }
+      }
+      if constexpr (RPS == 2) {
+        // Pairs of rows of this octant, through two row registers: the next
+        // pair is read while this one is processed.
+        auto pop = [&](int& x, int& xh) {
+          x = mask ? (int)__builtin_ctzll(mask) : -1;
+          if (x >= 0) mask &= mask - 1;
+          xh = mask ? (int)__builtin_ctzll(mask) : -1;
+          if (xh >= 0) mask &= mask - 1;
+        };
+        int j, jh, jn, jnh;
+        pop(j, jh);
+        float4 qa = rowq[(lane >= 32 && jh >= 0) ? jh : j], qb;
+        while (true) {
+          pop(jn, jnh);
+          pair(bt, keyl, j, jh, qa, jn >= 0 ? jn : j, jnh, qb);
+          if (jn < 0) break;
+          j = jn;
+          jh = jnh;
+          pop(jn, jnh);
+          pair(bt, keyl, j, jh, qb, jn >= 0 ? jn : j, jnh, qa);
+          if (jn < 0) break;
+          j = jn;
+          jh = jnh;
+        }
+        continue;
       }
       // Rows of this octant, two at a time through two row registers: the next
       // row is read while this one is processed.
@@ -771,12 +860,20 @@ template <int B, int R, int NSV>
 hipError_t launch_splat_ns(const SplatArgs& a, int64_t n_units, int ns, hipStream_t st) {
   if constexpr (NSV >= Steps<R>::NSMIN) {
     if (ns == NSV) {
+      const dim3 grid((unsigned)n_units), block(SMKI_WAVE);
+      if constexpr (NSV == 1) {
+        if (a.noff <= 32) {   // two rows per step
+          if (a.wts)
+            hipLaunchKernelGGL((k_splat<B, R, 1, true, 2>), grid, block, 0, st, a);
+          else
+            hipLaunchKernelGGL((k_splat<B, R, 1, false, 2>), grid, block, 0, st, a);
+          return hipGetLastError();
+        }
+      }
       if (a.wts)
-        hipLaunchKernelGGL((k_splat<B, R, NSV, true>), dim3((unsigned)n_units), dim3(SMKI_WAVE), 0,
-                           st, a);
+        hipLaunchKernelGGL((k_splat<B, R, NSV, true, 1>), grid, block, 0, st, a);
       else
-        hipLaunchKernelGGL((k_splat<B, R, NSV, false>), dim3((unsigned)n_units), dim3(SMKI_WAVE),
-                           0, st, a);
+        hipLaunchKernelGGL((k_splat<B, R, NSV, false, 1>), grid, block, 0, st, a);
       return hipGetLastError();
     }
     return launch_splat_ns<B, R, NSV - 1>(a, n_units, ns, st);
