@@ -321,12 +321,13 @@ def test_split_work_units_agree(chunk):
     check_counts(st, nv, nb)
 
 
-@pytest.mark.parametrize("B,l", [(2, 0.3), (4, 0.3), (8, 0.3), (16, 0.3), (4, 0.89), (8, 0.89),
-                                 (16, 0.89)])
+@pytest.mark.parametrize("B,l", [(2, 0.3), (4, 0.3), (8, 0.3), (16, 0.3), (4, 0.6), (4, 0.89),
+                                 (8, 0.89), (16, 0.89)])
 def test_block_sizes_and_reach(B, l):
-    # res 0.2: l = 0.3 reaches 2 voxels past a row's voxel, l = 0.89 reaches 4,
-    # the largest supported reach (equal to the block edge for B = 4, as 2 is
-    # for B = 2); B = 16 merges four voxels per thread
+    # res 0.2: l = 0.3 reaches 2 voxels past a row's voxel, l = 0.6 reaches 3,
+    # l = 0.89 reaches 4, the largest supported reach (equal to the block edge
+    # for B = 4, as 2 is for B = 2; 2R > B puts up to 27 regions over a voxel);
+    # B = 16 merges four voxels per thread
     sc = scenes.random_points_scene(5, 3000, K=5, extent=1.3, centre=(-7.3, 12.9, -0.4),
                                     res=0.2, l=l, sigma0=0.4, free_step=0.25,
                                     origin=(-6.0, 11.0, 0.5))
