@@ -200,7 +200,7 @@ def main():
     }
 
     out["roofline"]["traffic"] = splat_traffic()
-    kt = kernel_table(st, p)
+    kt = kernel_table(st, p, copy_bw)
     if kt is not None:
         out["kernels"] = kt
     if not args.no_variants:
@@ -606,11 +606,12 @@ def bench_batched(torch, dev, SemanticMap, town, reps=3):
                                "pairs_in_support": int(st["n_pairs"])}}
 
 
-def kernel_table(st, p):
+def kernel_table(st, p, copy_bw):
     """Per-kernel achieved HBM bandwidth of the LiDAR step's bucketing, merge and
     readout kernels: algorithmic bytes per launch (from this run's counts) over
-    the mean durations of the committed kernel trace of the same workload; None
-    when the trace is missing or older than the sources it names."""
+    the mean durations of the committed kernel trace of the same workload, as a
+    fraction of the 8 TB/s peak and of the measured copy bandwidth; None when
+    the trace is missing or older than the sources it names."""
     import hashlib
     import re
     prof = os.path.join(HERE, "profiles", "lidar_scan_kernel_trace.txt")
@@ -655,7 +656,8 @@ def kernel_table(st, p):
         us = dur.get(k)
         if us:
             out[k] = {"algorithmic_bytes": b, "mean_us": us, "GBps": b / (us * 1e-6) / 1e9,
-                      "frac_of_peak": b / (us * 1e-6) / HBM_PEAK}
+                      "frac_of_peak": b / (us * 1e-6) / HBM_PEAK,
+                      "frac_of_copy": b / (us * 1e-6) / copy_bw}
     return {"source": "profiles/lidar_scan_kernel_trace.txt", "per_kernel": out}
 
 
