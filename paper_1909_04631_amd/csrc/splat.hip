@@ -329,6 +329,8 @@ __global__ void __launch_bounds__(SMKI_WAVE) k_splat(SplatArgs a) {
     for (int i = 2; i < SMKI_POLY_N; ++i) qq = fmaf(qq, uu, cq[i]);
     float v = W ? (uu * uu) * ((sv * wr) * qq) : (uu * uu) * (sv * qq);
     if (!act) v = 0.0f;
+    // (the value is complete before any flush's LDS traffic is issued)
+    asm volatile("" ::"v"(v) : "memory");
     if (klo != gkey) {
       if (gkey >= 0) flush();
       gkey = klo;
