@@ -175,7 +175,7 @@ def main():
         "dtype": "f32",
         "data": "synthetic (seeded ray-cast street scene, LiDAR-shaped)",
         "config": {
-            "workload": "lidar_scan_64x2048_K20_res0.1_B8_l0.3_s0.1_step0.3",
+            "workload": f"lidar_scan_64x2048_K20_res0.1_B{B_l}_l0.3_s0.1_step0.3",
             "block_size": B_l, "unit_budget": ub_l,
             "hits": st["n_hits"], "free_samples": st["n_free"], "voxels_updated": V,
             "pairs_in_support": P, "blocks_allocated": st["n_new_blocks"],
