@@ -706,10 +706,15 @@ k_merge(SplatArgs a, int32_t n_targets) {
 #pragma unroll
       for (int k = 0; k < MAXC; ++k) sd += (double)first[k];
       if (more) {
-#pragma unroll
+        // (up to 27 candidates: a runtime loop, the candidates recomputed, so
+        // that this path adds no registers to the common one)
+        const int vv[3] = {vox / (B * B), (vox / B) % B, vox % B};
+        constexpr int MU = MAXC > 8 ? 1 : MAXC;
+#pragma unroll MU
         for (int k = 0; k < MAXC; ++k) {
-          if (pk[k] < 0) continue;
-          const int ci = pk[k] >> 16;
+          const int pkk = MAXC > 8 ? merge_candidate<B, R>(vv, k) : pk[k];
+          if (pkk < 0) continue;
+          const int ci = pkk >> 16;
           const int2 e = E[ci];
           const int32_t w1 = e.x + abs(e.y);
           for (int32_t w0 = e.x + 1; w0 < w1; w0 += 8) {
@@ -720,7 +725,7 @@ k_merge(SplatArgs a, int32_t n_targets) {
 #pragma unroll
             for (int j = 0; j < 8; ++j) {
               const bool has = (mk[j] >> (26 - ci)) & 1u;
-              v[j] = part_at<DR3, WIDE>(a.part, has ? w0 + j : -1, pk[k] & 0xffff);
+              v[j] = part_at<DR3, WIDE>(a.part, has ? w0 + j : -1, pkk & 0xffff);
             }
 #pragma unroll
             for (int j = 0; j < 8; ++j) sd += (double)v[j];

@@ -307,12 +307,14 @@ def test_single_class_scene_and_k2_reduction():
                                atol=1e-7)
 
 
-@pytest.mark.parametrize("chunk", [64, 300])
-def test_split_work_units_agree(chunk):
+@pytest.mark.parametrize("chunk,B", [(64, 8), (300, 8), (64, 4), (300, 4)])
+def test_split_work_units_agree(chunk, B):
     # small chunks split every busy (class, block) into several splat units whose
-    # partial sums the merge adds in chunk order
+    # partial sums the merge adds in chunk order (at B = 4 the reach of 3
+    # exceeds half the block: up to 27 regions over a voxel)
     sc = scenes.make_config(0)
-    _print_case(f"chunk {chunk}")
+    sc.params.block_size = B
+    _print_case(f"chunk {chunk} B {B}")
     gm = gpu_map_of(sc, unit_budget=chunk)
     om = oracle_map_of(sc)
     worst, (ijk, a_ref, nv, nb) = compare_map(gm, om, sc.params.K)
