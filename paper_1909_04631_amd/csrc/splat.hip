@@ -143,7 +143,11 @@ __global__ void __launch_bounds__(SMKI_WAVE) k_splat(SplatArgs a) {
   constexpr int DR3 = DR * DR * DR;
   constexpr int NACC4 = (DR3 + 3) / 4;
   __shared__ float4 acc4[NACC4];   // the region
-  __shared__ float4 rowq[SMKI_WAVE];   // the batch being processed: (|u| per axis, |u|^2) per row
+  // the batch being processed, its rows in octant-major order: (|u| per axis,
+  // |u|^2), keys and (W) weights
+  __shared__ float4 rowq[SMKI_WAVE];
+  __shared__ int32_t keyq[SMKI_WAVE];
+  __shared__ float wq[W ? SMKI_WAVE : 1];
   float* acc = (float*)acc4;
   const int lane = threadIdx.x;
   // the zero words that the merge reads for absent pieces
@@ -204,6 +208,7 @@ __global__ void __launch_bounds__(SMKI_WAVE) k_splat(SplatArgs a) {
     sum[s] = 0.0f;
     cw[s] = 0;
   }
+  const int xlane4 = (lane ^ 32) << 2;   // byte address of the other half's lane (RPS == 2)
   // Flush: every lane adds its group sum (0 included) to its voxel of the
   // region, all reads of a flush first, then all writes; pad lanes (no stencil
   // offset) touch nothing.  Within one flush the lanes' addresses are distinct;
@@ -214,7 +219,8 @@ __global__ void __launch_bounds__(SMKI_WAVE) k_splat(SplatArgs a) {
     if constexpr (RPS == 2) {
       // both halves hold sums of the same group for the same offsets: the
       // lower half adds their total
-      const float tot = sum[0] + __shfl_xor(sum[0], 32);
+      const float tot =
+          sum[0] + __int_as_float(__builtin_amdgcn_ds_bpermute(xlane4, __float_as_int(sum[0])));
       const int32_t fa0 = gcb + cw[0];
       __atomic_signal_fence(__ATOMIC_SEQ_CST);
       if (lane < 32 && !pad[0]) acc[fa0] = acc[fa0] + tot;
@@ -256,19 +262,42 @@ __global__ void __launch_bounds__(SMKI_WAVE) k_splat(SplatArgs a) {
     b.w = W ? a.wts[v] : 1.0f;
     return b;
   };
+  // A row's octant selects the mirrored region offsets; rows come octant by
+  // octant, so this changes at most eight times per batch (the open group is
+  // flushed first).
+  auto octant = [&](int32_t key) {
+    const int oc = key & 7;
+    if (oc == goc) return;
+    if (gkey >= 0) flush();
+    gkey = -1;
+    goc = oc;
+    switch (oc) {
+#define SMKI_OCT_CASE(OC)                                             \
+  case OC:                                                            \
+    _Pragma("unroll") for (int s = 0; s < NS; ++s) cw[s] = wl[OC][s]; \
+    break;
+      SMKI_OCT_CASE(0) SMKI_OCT_CASE(1) SMKI_OCT_CASE(2) SMKI_OCT_CASE(3)
+      SMKI_OCT_CASE(4) SMKI_OCT_CASE(5) SMKI_OCT_CASE(6) SMKI_OCT_CASE(7)
+#undef SMKI_OCT_CASE
+    }
+  };
+  auto cell_base = [&](int32_t key) {
+    const uint32_t c = (uint32_t)key >> 3;   // the cell: x, y, z of log2(B) bits each
+    return (int32_t)(((c / (B * B) + R) * DR + ((c / B) % B + R)) * DR + (c % B + R));
+  };
   // One row (j of the batch, its |u| and |u|^2 in q, read from LDS one row
-  // earlier): group change, the read of the next row (jn, into qn), then the
-  // row's contribution to every stencil offset.  The wait for q sits first, so
-  // that no wait for the next read stalls the arithmetic.
-  auto row = [&](const Batch& bt, int32_t keyl, int j, const float4& q, int jn, float4& qn) {
+  // earlier): octant and group change, the read of the next row (jn, into qn),
+  // then the row's contribution to every stencil offset.  The wait for q sits
+  // first, so that no wait for the next read stalls the arithmetic.
+  auto row = [&](int32_t keyp, float wp, int j, const float4& q, int jn, float4& qn) {
     asm volatile("" ::"v"(q.x), "v"(q.y), "v"(q.z), "v"(q.w));
-    const int32_t key = __builtin_amdgcn_readlane(keyl, j);
-    const float wr = W ? __int_as_float(__builtin_amdgcn_readlane(__float_as_int(bt.w), j)) : 1.0f;
+    const int32_t key = __builtin_amdgcn_readlane(keyp, j);
+    const float wr = W ? __int_as_float(__builtin_amdgcn_readlane(__float_as_int(wp), j)) : 1.0f;
+    octant(key);
     if (key != gkey) {
       if (gkey >= 0) flush();
       gkey = key;
-      const uint32_t c = (uint32_t)key >> 3;   // the cell: x, y, z of log2(B) bits each
-      gcb = (int32_t)(((c / (B * B) + R) * DR + ((c / B) % B + R)) * DR + (c % B + R));
+      gcb = cell_base(key);
     }
     qn = rowq[jn];
     // Branch-free: every lane evaluates its pair; s = 1 - d/l clamped to [0, 1]
@@ -297,25 +326,16 @@ __global__ void __launch_bounds__(SMKI_WAVE) k_splat(SplatArgs a) {
     }
   };
   // Two rows at once (RPS == 2): j in the lower half of the wavefront, jh (-1:
-  // none) in the upper, their |u| and |u|^2 in q (per half); the next pair's
-  // rows (jn, jnh) are read into qn.  A half's sums join the open group when
-  // its row belongs to it; a pair that spans two groups flushes in between.
-  auto cell_base = [&](int32_t key) {
-    const uint32_t c = (uint32_t)key >> 3;   // the cell: x, y, z of log2(B) bits each
-    return (int32_t)(((c / (B * B) + R) * DR + ((c / B) % B + R)) * DR + (c % B + R));
-  };
-  auto pair = [&](const Batch& bt, int32_t keyl, int j, int jh, const float4& q, int jn, int jnh,
-                  float4& qn) {
-    asm volatile("" ::"v"(q.x), "v"(q.y), "v"(q.z), "v"(q.w));
+  // none) in the upper, of one octant, keys klo and khi, their |u| and |u|^2 in
+  // q (per half).  A half's sums join the open group when its row belongs to
+  // it; a pair that spans two groups flushes in between.
+  auto pair = [&](float wp, int j, int jh, int32_t klo, int32_t khi, const float4& q) {
     const bool hi = lane >= 32;
-    qn = rowq[(hi && jnh >= 0) ? jnh : jn];
-    const int32_t klo = __builtin_amdgcn_readlane(keyl, j);
-    const int32_t khi = jh >= 0 ? __builtin_amdgcn_readlane(keyl, jh) : -1;
     const bool act = !hi || jh >= 0;   // this half has a row
     float wr = 1.0f;
     if (W) {
-      const float wlo = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(bt.w), j));
-      const float whi = jh >= 0 ? __int_as_float(__builtin_amdgcn_readlane(__float_as_int(bt.w), jh)) : 0.0f;
+      const float wlo = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(wp), j));
+      const float whi = jh >= 0 ? __int_as_float(__builtin_amdgcn_readlane(__float_as_int(wp), jh)) : 0.0f;
       wr = hi ? whi : wlo;
     }
     const float d2 = fmaf(q.z, nwz[0], fmaf(q.y, nwy[0], fmaf(q.x, nwx[0], q.w + w2[0])));
@@ -331,6 +351,7 @@ __global__ void __launch_bounds__(SMKI_WAVE) k_splat(SplatArgs a) {
     if (!act) v = 0.0f;
     // (the value is complete before any flush's LDS traffic is issued)
     asm volatile("" ::"v"(v) : "memory");
+    octant(klo);
     if (klo != gkey) {
       if (gkey >= 0) flush();
       gkey = klo;
@@ -348,79 +369,62 @@ __global__ void __launch_bounds__(SMKI_WAVE) k_splat(SplatArgs a) {
       }
     }
   };
-  // One batch: its rows go to LDS (read back by every lane, one row at a time)
-  // and are taken octant by octant, each octant's rows in sorted order, so that
-  // the region-index offsets change at most eight times per batch.
+  // One batch: its rows go to LDS in octant-major order (each octant's rows in
+  // sorted order) and are read back by every lane, one row (or pair) at a time.
   auto process = [&](const Batch& bt, int32_t base) {
     const int nb = min(SMKI_WAVE, r1 - base);
     const float4& cur = bt.r;
     // (consume the weights here, so that no wait for their load sits in the row loop)
     if (W) asm volatile("" ::"v"(bt.w));
     const float q2l = fmaf(cur.x, cur.x, fmaf(cur.y, cur.y, cur.z * cur.z));
-    // (the previous batch's reads of rowq were issued before this write)
-    rowq[lane] = make_float4(cur.x, cur.y, cur.z, q2l);
     const int32_t keyl = __float_as_int(cur.w);
     const bool valid = lane < nb;
-#pragma unroll 1
+    // slot of each row: the rows of smaller octants, then its rank in its own
+    // (lanes past the batch keep slots past it, never read)
+    int slot = lane;
+    uint32_t run = 0;
+#pragma unroll
     for (int oc = 0; oc < 8; ++oc) {
-      uint64_t mask = __ballot(valid && (keyl & 7) == oc);
-      if (mask == 0) continue;
-      if (oc != goc) {
-        if (gkey >= 0) flush();
-        gkey = -1;
-        goc = oc;
-        switch (oc) {
-#define SMKI_OCT_CASE(OC)                                        \
-  case OC:                                                       \
-    _Pragma("unroll") for (int s = 0; s < NS; ++s) cw[s] = wl[OC][s]; \
-    break;
-          SMKI_OCT_CASE(0) SMKI_OCT_CASE(1) SMKI_OCT_CASE(2) SMKI_OCT_CASE(3)
-          SMKI_OCT_CASE(4) SMKI_OCT_CASE(5) SMKI_OCT_CASE(6) SMKI_OCT_CASE(7)
-#undef SMKI_OCT_CASE
+      const bool mine = valid && (keyl & 7) == oc;
+      const uint64_t m = __ballot(mine);
+      if (mine)
+        slot = (int)(run + __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32),
+                                                     __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u)));
+      run += (uint32_t)__popcll(m);
+    }
+    // (the previous batch's reads of these arrays were issued before the writes)
+    rowq[slot] = make_float4(cur.x, cur.y, cur.z, q2l);
+    keyq[slot] = keyl;
+    if (W) wq[slot] = bt.w;
+    const int32_t keyp = keyq[lane];
+    const float wp = W ? wq[lane] : 1.0f;
+    if constexpr (RPS == 2) {
+      // pairs of consecutive rows of one octant (a row whose successor lies in
+      // another octant, or the last row, goes alone)
+      int j = 0;
+      while (j < nb) {
+        const int32_t klo = __builtin_amdgcn_readlane(keyp, j);
+        int jh = -1;
+        int32_t khi = -1;
+        if (j + 1 < nb) {
+          const int32_t k1 = __builtin_amdgcn_readlane(keyp, j + 1);
+          if (((k1 ^ klo) & 7) == 0) {
+            jh = j + 1;
+            khi = k1;
+          }
         }
+        const float4 q = rowq[(lane >= 32 && jh >= 0) ? jh : j];
+        pair(wp, j, jh, klo, khi, q);
+        j = (jh >= 0 ? jh : j) + 1;
       }
-      if constexpr (RPS == 2) {
-        // Pairs of rows of this octant, through two row registers: the next
-        // pair is read while this one is processed.
-        auto pop = [&](int& x, int& xh) {
-          x = mask ? (int)__builtin_ctzll(mask) : -1;
-          if (x >= 0) mask &= mask - 1;
-          xh = mask ? (int)__builtin_ctzll(mask) : -1;
-          if (xh >= 0) mask &= mask - 1;
-        };
-        int j, jh, jn, jnh;
-        pop(j, jh);
-        float4 qa = rowq[(lane >= 32 && jh >= 0) ? jh : j], qb;
-        while (true) {
-          pop(jn, jnh);
-          pair(bt, keyl, j, jh, qa, jn >= 0 ? jn : j, jnh, qb);
-          if (jn < 0) break;
-          j = jn;
-          jh = jnh;
-          pop(jn, jnh);
-          pair(bt, keyl, j, jh, qb, jn >= 0 ? jn : j, jnh, qa);
-          if (jn < 0) break;
-          j = jn;
-          jh = jnh;
-        }
-        continue;
-      }
-      // Rows of this octant, two at a time through two row registers: the next
-      // row is read while this one is processed.
-      int j = (int)__builtin_ctzll(mask);
-      mask &= mask - 1;
-      float4 qa = rowq[j], qb;
-      while (true) {
-        int jn = mask ? (int)__builtin_ctzll(mask) : j;
-        row(bt, keyl, j, qa, jn, qb);
-        if (!mask) break;
-        mask &= mask - 1;
-        j = jn;
-        jn = mask ? (int)__builtin_ctzll(mask) : j;
-        row(bt, keyl, j, qb, jn, qa);
-        if (!mask) break;
-        mask &= mask - 1;
-        j = jn;
+    } else {
+      // rows in order, through two row registers: the next row is read while
+      // this one is processed
+      float4 qa = rowq[0], qb;
+      for (int j = 0; j < nb; j += 2) {
+        row(keyp, wp, j, qa, min(j + 1, nb - 1), qb);
+        if (j + 1 >= nb) break;
+        row(keyp, wp, j + 1, qb, min(j + 2, nb - 1), qa);
       }
     }
   };
