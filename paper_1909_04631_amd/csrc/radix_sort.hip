@@ -88,34 +88,57 @@ __global__ void __launch_bounds__(RS_THREADS) k_hist(const K* __restrict__ keys,
 
 // Per digit (one workgroup each): exclusive scan, in place, of the digit's
 // row of the digit-major table (its count in every tile), and the digit's
-// total.  Thread i takes a run of consecutive tiles: its sum, a scan of the
-// sums over the workgroup, then the run is rewritten as running prefixes.
+// total.
 __global__ void __launch_bounds__(RS_THREADS) k_digit_scan(uint32_t* __restrict__ hist,
                                                            int64_t ntiles,
                                                            uint32_t* __restrict__ total) {
-  __shared__ uint32_t wsum[RS_WAVES];
+  // The digit's row of tile counts, scanned in chunks of RS_THREADS * 4 counts
+  // (thread t takes four consecutive ones): per chunk a workgroup scan, carried
+  // into the next chunk, whose counts are loaded while this one is scanned.
+  constexpr int V = 4, CH = RS_THREADS * V;
+  __shared__ uint32_t wsum[2][RS_WAVES];
   const int tid = threadIdx.x, lane = tid & (SMKI_WAVE - 1), w = tid / SMKI_WAVE;
   uint32_t* row = hist + (int64_t)blockIdx.x * ntiles;
-  const int64_t run_len = (ntiles + RS_THREADS - 1) / RS_THREADS;
-  const int64_t b0 = min((int64_t)tid * run_len, ntiles), b1 = min(b0 + run_len, ntiles);
-  uint32_t sum = 0;
-  for (int64_t i = b0; i < b1; ++i) sum += row[i];
-  uint32_t inc = sum;
+  auto load = [&](int64_t c0, uint32_t* v) {
 #pragma unroll
-  for (int o = 1; o < SMKI_WAVE; o <<= 1) {
-    const uint32_t u = __shfl_up(inc, o, SMKI_WAVE);
-    if (lane >= o) inc += u;
+    for (int j = 0; j < V; ++j) {
+      const int64_t i = c0 + (int64_t)tid * V + j;
+      v[j] = i < ntiles ? row[i] : 0u;
+    }
+  };
+  uint32_t cur[V], nxt[V];
+  load(0, cur);
+  uint32_t carry = 0;
+  int par = 0;
+  for (int64_t c0 = 0; c0 < ntiles; c0 += CH, par ^= 1) {
+    load(c0 + CH, nxt);
+    const uint32_t s = cur[0] + cur[1] + cur[2] + cur[3];
+    uint32_t inc = s;
+#pragma unroll
+    for (int o = 1; o < SMKI_WAVE; o <<= 1) {
+      const uint32_t u = __shfl_up(inc, o, SMKI_WAVE);
+      if (lane >= o) inc += u;
+    }
+    if (lane == SMKI_WAVE - 1) wsum[par][w] = inc;
+    __syncthreads();   // (two copies of wsum: a chunk's writes never meet the previous chunk's reads)
+    uint32_t run = carry + inc - s;
+    uint32_t tot = 0;
+#pragma unroll
+    for (int q = 0; q < RS_WAVES; ++q) {
+      run += q < w ? wsum[par][q] : 0u;
+      tot += wsum[par][q];
+    }
+#pragma unroll
+    for (int j = 0; j < V; ++j) {
+      const int64_t i = c0 + (int64_t)tid * V + j;
+      if (i < ntiles) row[i] = run;
+      run += cur[j];
+    }
+    carry += tot;
+#pragma unroll
+    for (int j = 0; j < V; ++j) cur[j] = nxt[j];
   }
-  if (lane == SMKI_WAVE - 1) wsum[w] = inc;
-  __syncthreads();
-  uint32_t run = inc - sum;
-  for (int q = 0; q < w; ++q) run += wsum[q];
-  for (int64_t i = b0; i < b1; ++i) {
-    const uint32_t c = row[i];
-    row[i] = run;
-    run += c;
-  }
-  if (tid == RS_THREADS - 1) total[blockIdx.x] = run;
+  if (tid == 0) total[blockIdx.x] = carry;
 }
 
 // Last pass with records: a thread gathers the records (and weights) of eight
