@@ -108,6 +108,22 @@ def test_soft_recursive_update_and_reach():
                 sc.params.K)
 
 
+def test_soft_small_stencil_two_rows_per_step():
+    # l / res = 1.5: a stencil of 29 offsets, so the splat takes two rows per
+    # step, each half with its own row's weight; two scans, several classes per hit
+    sc = scenes.random_points_scene(7, 3000, K=6, extent=1.3, centre=(3.1, -2.2, 0.6),
+                                    res=0.2, l=0.3, sigma0=0.7, free_step=0.25,
+                                    origin=(1.5, -1.0, 1.2))
+    sc.params.block_size = 4
+    s = sc.scans[0]
+    A = scenes.Scan(s.xyz[:1300], s.label[:1300], s.origin)
+    B = scenes.Scan(s.xyz[1300:], s.label[1300:], s.origin)
+    probs = [scenes.soft_measurements(x.label, 6, seed=21 + i, top=3) for i, x in enumerate((A, B))]
+    _print_case("soft two rows per step")
+    compare_map(gpu_soft_map(sc, probs, scans=[A, B]), oracle_soft_map(sc, probs, scans=[A, B]),
+                sc.params.K)
+
+
 def test_soft_counting_model_and_extended_block_selection():
     sc = scenes.make_config(0)
     p = sc.params
