@@ -42,9 +42,17 @@ __device__ __forceinline__ T block_excl_scan(T v, T* block_total) {
   return off + inc - v;
 }
 
+// Elements of an array of capacity n whose count (dn, nullable) is read on
+// the device: tiles past the count read and write nothing, and add zero.
+__device__ __forceinline__ int64_t count_of(int64_t n, const int32_t* dn) {
+  return dn ? min(n, (int64_t)max(*dn, 0)) : n;
+}
+
 template <typename T>
 __global__ void __launch_bounds__(SCAN_THREADS) k_tile_sums(const T* __restrict__ in, int64_t n,
-                                                            T* __restrict__ sums) {
+                                                            T* __restrict__ sums,
+                                                            const int32_t* dn) {
+  n = count_of(n, dn);
   const int64_t base = (int64_t)blockIdx.x * SCAN_TILE + (int64_t)threadIdx.x * SCAN_ITEMS;
   T s = 0;
 #pragma unroll
@@ -58,7 +66,8 @@ __global__ void __launch_bounds__(SCAN_THREADS) k_tile_sums(const T* __restrict_
 template <typename T>
 __global__ void __launch_bounds__(SCAN_THREADS) k_tile_scan(const T* in, T* out, int64_t n,
                                                             const T* __restrict__ tile_off,
-                                                            T* total) {
+                                                            T* total, const int32_t* dn) {
+  n = count_of(n, dn);
   const int64_t base = (int64_t)blockIdx.x * SCAN_TILE + (int64_t)threadIdx.x * SCAN_ITEMS;
   T v[SCAN_ITEMS];
   T s = 0;
@@ -82,7 +91,8 @@ __global__ void __launch_bounds__(SCAN_THREADS) k_tile_scan(const T* in, T* out,
 template <typename T>
 __global__ void __launch_bounds__(SCAN_THREADS) k_tile_scan_direct(const T* in, T* out, int64_t n,
                                                                    const T* __restrict__ sums,
-                                                                   T* total) {
+                                                                   T* total, const int32_t* dn) {
+  n = count_of(n, dn);
   __shared__ T part[SCAN_THREADS / SMKI_WAVE];
   T pre = 0;
   for (int64_t i = threadIdx.x; i < (int64_t)blockIdx.x; i += SCAN_THREADS) pre += sums[i];
@@ -163,21 +173,23 @@ __global__ void __launch_bounds__(SCAN_THREADS) k_tile_sums_pair(const TA* __res
                                                                  int64_t na, TA* __restrict__ sa,
                                                                  int64_t ta,
                                                                  const TB* __restrict__ inb,
-                                                                 int64_t nb, TB* __restrict__ sb) {
+                                                                 int64_t nb, TB* __restrict__ sb,
+                                                                 const int32_t* dnb) {
   if ((int64_t)blockIdx.x < ta)
     tile_sum<TA>(ina, na, sa, blockIdx.x);
   else
-    tile_sum<TB>(inb, nb, sb, (int64_t)blockIdx.x - ta);
+    tile_sum<TB>(inb, count_of(nb, dnb), sb, (int64_t)blockIdx.x - ta);
 }
 
 template <typename TA, typename TB>
 __global__ void __launch_bounds__(SCAN_THREADS) k_tile_scan_direct_pair(
     const TA* ina, TA* outa, int64_t na, const TA* __restrict__ sa, TA* tota, int64_t ta,
-    const TB* inb, TB* outb, int64_t nb, const TB* __restrict__ sb, TB* totb, int64_t tb) {
+    const TB* inb, TB* outb, int64_t nb, const TB* __restrict__ sb, TB* totb, int64_t tb,
+    const int32_t* dnb) {
   if ((int64_t)blockIdx.x < ta)
     tile_scan_direct<TA>(ina, outa, na, sa, tota, blockIdx.x, ta);
   else
-    tile_scan_direct<TB>(inb, outb, nb, sb, totb, (int64_t)blockIdx.x - ta, tb);
+    tile_scan_direct<TB>(inb, outb, count_of(nb, dnb), sb, totb, (int64_t)blockIdx.x - ta, tb);
 }
 
 template <typename T>
@@ -194,8 +206,10 @@ size_t tmp_elems(int64_t n) {
   return e + 1;
 }
 
+// dn (device, nullable): the element count, n then being the capacity
 template <typename T>
-hipError_t scan_impl(const T* in, T* out, int64_t n, T* total, T* tmp, hipStream_t st) {
+hipError_t scan_impl(const T* in, T* out, int64_t n, T* total, T* tmp, hipStream_t st,
+                     const int32_t* dn = nullptr) {
   if (n <= 0) {
     if (total) hipLaunchKernelGGL(k_zero_total<T>, dim3(1), dim3(1), 0, st, total);
     return hipGetLastError();
@@ -203,22 +217,22 @@ hipError_t scan_impl(const T* in, T* out, int64_t n, T* total, T* tmp, hipStream
   const int64_t tiles = ceil_div_i64(n, SCAN_TILE);
   if (tiles == 1) {
     hipLaunchKernelGGL(k_tile_scan<T>, dim3(1), dim3(SCAN_THREADS), 0, st, in, out, n,
-                       (const T*)nullptr, total);
+                       (const T*)nullptr, total, dn);
     return hipGetLastError();
   }
   T* sums = tmp;
   T* rest = tmp + tiles + 1;
   hipLaunchKernelGGL(k_tile_sums<T>, dim3((unsigned)tiles), dim3(SCAN_THREADS), 0, st, in, n,
-                     sums);
+                     sums, dn);
   if (tiles <= 512) {   // up to 512 tile sums: every workgroup adds its predecessors' itself
     hipLaunchKernelGGL(k_tile_scan_direct<T>, dim3((unsigned)tiles), dim3(SCAN_THREADS), 0, st, in,
-                       out, n, (const T*)sums, total);
+                       out, n, (const T*)sums, total, dn);
     return hipGetLastError();
   }
   hipError_t e = scan_impl<T>(sums, sums, tiles, (T*)nullptr, rest, st);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_tile_scan<T>, dim3((unsigned)tiles), dim3(SCAN_THREADS), 0, st, in, out,
-                     n, (const T*)sums, total);
+                     n, (const T*)sums, total, dn);
   return hipGetLastError();
 }
 
@@ -226,20 +240,20 @@ constexpr int64_t kPairTiles = 512;   // per array, for the two-launch pair scan
 
 template <typename TA, typename TB>
 hipError_t scan_pair_impl(const TA* ina, TA* outa, int64_t na, TA* tota, const TB* inb, TB* outb,
-                          int64_t nb, TB* totb, void* tmp, hipStream_t st) {
+                          int64_t nb, TB* totb, void* tmp, hipStream_t st, const int32_t* dnb) {
   const int64_t ta = ceil_div_i64(na, SCAN_TILE), tb = ceil_div_i64(nb, SCAN_TILE);
   if (na <= 0 || nb <= 0 || ta > kPairTiles || tb > kPairTiles) {
     hipError_t e = scan_impl<TA>(ina, outa, na, tota, (TA*)tmp, st);
     if (e != hipSuccess) return e;
-    return scan_impl<TB>(inb, outb, nb, totb, (TB*)tmp, st);
+    return scan_impl<TB>(inb, outb, nb, totb, (TB*)tmp, st, dnb);
   }
   TA* sa = (TA*)tmp;
   TB* sb = (TB*)((char*)tmp + kPairTiles * sizeof(int64_t));
   hipLaunchKernelGGL((k_tile_sums_pair<TA, TB>), dim3((unsigned)(ta + tb)), dim3(SCAN_THREADS), 0,
-                     st, ina, na, sa, ta, inb, nb, sb);
+                     st, ina, na, sa, ta, inb, nb, sb, dnb);
   hipLaunchKernelGGL((k_tile_scan_direct_pair<TA, TB>), dim3((unsigned)(ta + tb)),
                      dim3(SCAN_THREADS), 0, st, ina, outa, na, (const TA*)sa, tota, ta, inb, outb,
-                     nb, (const TB*)sb, totb, tb);
+                     nb, (const TB*)sb, totb, tb, dnb);
   return hipGetLastError();
 }
 
@@ -252,13 +266,14 @@ size_t scan_tmp_bytes(int64_t n) {
 hipError_t scan_excl_pair_i64_i32(const int64_t* ina, int64_t* outa, int64_t na, int64_t* tota,
                                   const int32_t* inb, int32_t* outb, int64_t nb, int32_t* totb,
                                   void* tmp, hipStream_t st) {
-  return scan_pair_impl<int64_t, int32_t>(ina, outa, na, tota, inb, outb, nb, totb, tmp, st);
+  return scan_pair_impl<int64_t, int32_t>(ina, outa, na, tota, inb, outb, nb, totb, tmp, st,
+                                          nullptr);
 }
 
 hipError_t scan_excl_pair_i32(const int32_t* ina, int32_t* outa, int64_t na, int32_t* tota,
                               const int32_t* inb, int32_t* outb, int64_t nb, int32_t* totb,
-                              void* tmp, hipStream_t st) {
-  return scan_pair_impl<int32_t, int32_t>(ina, outa, na, tota, inb, outb, nb, totb, tmp, st);
+                              void* tmp, hipStream_t st, const int32_t* dnb) {
+  return scan_pair_impl<int32_t, int32_t>(ina, outa, na, tota, inb, outb, nb, totb, tmp, st, dnb);
 }
 
 hipError_t scan_excl_i64(const int64_t* in, int64_t* out, int64_t n, int64_t* total, void* tmp,

@@ -134,6 +134,11 @@ void bbox_reduce(const int32_t* h, int32_t out[6]) {
 }
 constexpr size_t kBboxInts = 8 * SMKI_BBOX_COPIES;
 constexpr size_t kStatBytes = sizeof(unsigned long long) * 4 * SMKI_STAT_COPIES;
+// pinned staging (h_pin, 8 KiB, int64 words): [20] the counting model's row
+// count, [256, 512) the insert counters, [704, 706) the map's block counts read
+// back with an insert's first copy, [720] an insert's new block and class
+// block counts (two int32)
+constexpr int kPinCounts = 704, kPinNew = 720;
 // Pinned staging (int64 words): [0, 2) counts, [6] error word, [20] row count,
 // [128, 256) bounding-box copies, [256, 512) counter copies.
 
@@ -180,6 +185,7 @@ struct smki_map {
   // until then; epoch changes whenever the map's storage moves (a captured
   // graph holds its addresses).
   bool host_counts_valid = true;
+  bool new_pending = false;   // the last insert's new (class) block counts are in h_pin[kPinNew]
   int64_t epoch = 0;
   smki_batch* stats_batch = nullptr;   // the replay whose counters smki_last_scan_stats reports
   // allocator of new growable buffers, and the one that made each current buffer
@@ -500,11 +506,13 @@ smki_status insert_impl(smki_map* m, const float* xyz, const int32_t* label, con
   // soft: up to K hit rows per hit, counted in int32
   if (probs && n * (int64_t)m->K > (int64_t)INT32_MAX / 2) return SMKI_E_CAPACITY;
   SMKI_HIP_TRY(hipSetDevice(m->device));
-  smki_status rc0 = refresh_counts(m);
-  if (rc0 != SMKI_OK) return rc0;
+  // block counts still on the device (after an insert or a replay) come back
+  // with this insert's first copy
+  const bool counts_on_device = !m->host_counts_valid;
   smki_scan_stats st{};
   m->last = st;
   m->stats_pending = false;
+  m->new_pending = false;
   m->stats_batch = nullptr;
   if (n == 0) return SMKI_OK;
   hipStream_t q = m->stream;
@@ -553,9 +561,17 @@ smki_status insert_impl(smki_map* m, const float* xyz, const int32_t* label, con
                             d_kept, d_bbox, d_err0, q));
   SMKI_HIP_TRY(scan_excl_pair_i64_i32(d_nfree, d_off, n, d_sc, d_kept, d_kpos, n,
                                       (int32_t*)(d_sc + 1), d_stmp, q));
-  // sync 1: counts, error word and box in one copy
+  // sync 1: counts, error word and box in one copy (and the map's block counts)
   SMKI_HIP_TRY(hipMemcpyAsync(hh, d_hdr, kHdrTail, hipMemcpyDeviceToHost, q));
+  if (counts_on_device)
+    SMKI_HIP_TRY(hipMemcpyAsync(m->h_pin + kPinCounts, m->dev.counts, 2 * sizeof(int64_t),
+                                hipMemcpyDeviceToHost, q));
   SMKI_HIP_TRY(stream_wait(q));
+  if (counts_on_device) {
+    m->n_blocks = m->h_pin[kPinCounts];
+    m->n_cblocks = m->h_pin[kPinCounts + 1];
+    m->host_counts_valid = true;
+  }
   const int64_t nf = ((const int64_t*)hh)[0];
   const int64_t nk = (int64_t)((const int32_t*)hh)[2];
   int32_t bb[6];
@@ -607,6 +623,7 @@ smki_status insert_impl(smki_map* m, const float* xyz, const int32_t* label, con
   zb.add<int32_t>(g.n_blocks * m->K);
   zb.add<int32_t>(max_slots);
   zb.add<int32_t>(8);
+  zb.add<int32_t>(m->K);
   zb.add<uint64_t>(nt);
   zb.add<uint64_t>(nt);
   zb.add<uint32_t>(nt);
@@ -644,6 +661,7 @@ smki_status insert_impl(smki_map* m, const float* xyz, const int32_t* label, con
   scr.sort_tmp = Bz.take<char>(radix_tmp_bytes(nt));
   scr.scan_tmp = Bz.take<char>(scan_tmp_bytes(std::max(nt, n_ext)));
   int32_t* d_si = Bz.take<int32_t>(8);   // counts; cleared with the target marks below
+  int32_t* d_cfirst = Bz.take<int32_t>(m->K);   // first slot of each class (cleared too)
   ps.d_nslots = d_si;
   int32_t* d_ntgt = d_si + 1;
   int32_t* d_nunits = d_si + 2;
@@ -667,12 +685,16 @@ smki_status insert_impl(smki_map* m, const float* xyz, const int32_t* label, con
                            (uint32_t*)(d_si + 3), q));
   SMKI_HIP_TRY(launch_mark_targets(ps.slot_lin, ps.d_nslots, (int32_t)max_slots, g, eblo, enb, DB,
                                    d_mark, q));
-  SMKI_HIP_TRY(launch_slot_units(ps.head, ps.d_nslots, (int32_t)max_slots, m->chunk, d_nun, q));
+  SMKI_HIP_TRY(launch_slot_units(ps.head, ps.d_nslots, (int32_t)max_slots, m->chunk, d_nun, q,
+                                 ps.slot_lin, g.n_blocks, d_cfirst));
   SMKI_HIP_TRY(scan_excl_pair_i32(d_mark, d_mpos, n_ext, d_ntgt, d_nun, d_ust, max_slots, d_nunits,
-                                  scr.scan_tmp, q));
-  // sync 2: slots, targets, work units, the bucketing's error word
-  int32_t si[4];
-  SMKI_HIP_TRY(sync_read(m, d_si, sizeof(si), si));
+                                  scr.scan_tmp, q, ps.d_nslots));
+  // sync 2: slots, targets, work units, the bucketing's error word, each
+  // class's first slot
+  std::vector<int32_t> sih((size_t)(d_cfirst + m->K - d_si));
+  SMKI_HIP_TRY(sync_read(m, d_si, sizeof(int32_t) * sih.size(), sih.data()));
+  const int32_t* si = sih.data();
+  const int32_t* cfirst = si + (d_cfirst - d_si);
   if (si[3]) return status_of_err((uint32_t)si[3]);
   const int32_t n_slots = si[0], n_t = si[1];
   const int64_t n_units = si[2];
@@ -687,6 +709,24 @@ smki_status insert_impl(smki_map* m, const float* xyz, const int32_t* label, con
   if (csm)
     return insert_csm(m, g, ps, scr.wt, scr.keys, n_slots, n_t, n_ext, eblo, enb, d_mark, d_mpos,
                       d_ext2t, q);
+  // Room in the map for what this insert can allocate, by bounds known now, so
+  // that the allocation needs no further synchronisation: at most one new block
+  // per target, and per class at most min(targets, 27 x its slots) new class
+  // blocks (a slot's rows reach its own block and the 26 around it).
+  {
+    int64_t new_cb = 0, prev = -1, prev_first = 0;
+    for (int32_t c = 0; c < m->K; ++c) {
+      if (cfirst[c] <= 0) continue;
+      if (prev >= 0) new_cb += std::min<int64_t>(n_t, 27 * (int64_t)(cfirst[c] - 1 - prev_first));
+      prev = c;
+      prev_first = cfirst[c] - 1;
+    }
+    if (prev >= 0) new_cb += std::min<int64_t>(n_t, 27 * (int64_t)(n_slots - prev_first));
+    smki_status rc = ensure_pool(m, m->n_blocks + n_t);
+    if (rc == SMKI_OK) rc = ensure_hash(m, m->n_blocks + n_t);
+    if (rc == SMKI_OK) rc = ensure_cpool(m, m->n_cblocks + new_cb);
+    if (rc != SMKI_OK) return rc;
+  }
   SplatArgs sa{};
   sa.g = g;
   sa.R = sten.R;
@@ -772,8 +812,8 @@ smki_status insert_impl(smki_map* m, const float* xyz, const int32_t* label, con
   sa.contrib = d_contrib;
   // the splat first (its counters were cleared before the bucketing); what
   // only the later kernels read is prepared while it runs
-  SMKI_HIP_TRY(launch_unit_table(d_nun, d_ust, ps.head, ps.slot_lin, g.n_blocks, m->chunk,
-                                 (int32_t)max_slots, ps.d_nslots, d_nunits, d_units, d_uorder, q));
+  SMKI_HIP_TRY(launch_unit_table(d_nun, d_ust, ps.head, ps.slot_lin, g.n_blocks, m->chunk, n_slots,
+                                 ps.d_nslots, d_nunits, d_units, d_uorder, q));
   m->ev = m->evr[m->n_timed++ % SMKI_TIMING_RING];
   SMKI_HIP_TRY(hipEventRecord(m->ev[0], q));
   SMKI_HIP_TRY(launch_splat(sa, n_units, q));
@@ -788,17 +828,9 @@ smki_status insert_impl(smki_map* m, const float* xyz, const int32_t* label, con
   SMKI_HIP_TRY(launch_need(m->dev, n_t, d_contrib, d_isnew, d_tslot, d_need, q));
   SMKI_HIP_TRY(scan_excl_pair_i32(d_isnew, d_rank, n_t, d_cnt, d_need, d_cpos, ntk, d_cnt + 1,
                                   d_ctmp, q));
-  // sync 3: new blocks and class blocks
-  int32_t cnt[2];
-  SMKI_HIP_TRY(sync_read(m, d_cnt, sizeof(cnt), cnt));
-  const int64_t n_new = cnt[0], n_cnew = cnt[1];
-  m->last.n_new_blocks = n_new;
-  smki_status rc = ensure_pool(m, m->n_blocks + n_new);
-  if (rc != SMKI_OK) return rc;
-  rc = ensure_hash(m, m->n_blocks + n_new);
-  if (rc != SMKI_OK) return rc;
-  rc = ensure_cpool(m, m->n_cblocks + n_cnew);
-  if (rc != SMKI_OK) return rc;
+  // no synchronisation here: the map has room for the bounds above; the
+  // numbers of new blocks and class blocks stay on the device, which updates
+  // the map's counts there (the host reads them back at its next synchronisation)
   SMKI_HIP_TRY(hipEventRecord(m->ev[2], q));
   SMKI_HIP_TRY(launch_assign(m->dev, sa, n_t, d_isnew, d_rank, m->n_blocks, d_tslot, d_need,
                              d_cpos, m->n_cblocks, m->d_err, q));
@@ -807,11 +839,13 @@ smki_status insert_impl(smki_map* m, const float* xyz, const int32_t* label, con
   sa.alpha0 = m->alpha0;
   SMKI_HIP_TRY(launch_merge(sa, n_t, q));
   SMKI_HIP_TRY(hipEventRecord(m->ev[3], q));
+  SMKI_HIP_TRY(launch_commit_counts(d_cnt, m->dev.counts, m->n_blocks, m->n_cblocks, q));
   SMKI_HIP_TRY(hipMemcpyAsync(m->h_pin + 256, m->d_stats, kStatBytes,
                               hipMemcpyDeviceToHost, q));
-  m->n_blocks += n_new;
-  m->n_cblocks += n_cnew;
-  m->last.n_new_class_blocks = n_cnew;
+  SMKI_HIP_TRY(hipMemcpyAsync(m->h_pin + kPinNew, d_cnt, 2 * sizeof(int32_t),
+                              hipMemcpyDeviceToHost, q));
+  m->host_counts_valid = false;
+  m->new_pending = true;
   m->stats_pending = true;
   return SMKI_OK;
 }
@@ -1012,7 +1046,7 @@ smki_status batch_enqueue(smki_batch* b, hipStream_t q) {
                                    b->enb, 1, d.mark, q));
   SMKI_HIP_TRY(launch_slot_units(ps.head, ps.d_nslots, (int32_t)b->cap_slots, m->chunk, d.nun, q));
   SMKI_HIP_TRY(scan_excl_pair_i32(d.mark, d.mpos, ne, d.si + 1, d.nun, d.ust, b->cap_slots,
-                                  d.si + 2, d.scan_tmp, q));
+                                  d.si + 2, d.scan_tmp, q, ps.d_nslots));
   SMKI_HIP_TRY(launch_batch_units(d.si, b->cap_slots, b->cap_units, d.err, q));
   // splat, allocation, merge
   const Stencil& sten = b->sten;
@@ -1434,6 +1468,12 @@ smki_status smki_last_scan_stats(smki_map* m, smki_scan_stats* out) {
       for (int i = 0; i < 4; ++i) s[i] += c[k * 4 + i];
     m->last.n_updated_voxels = (int64_t)s[0];
     m->last.n_pairs = (int64_t)s[1];
+    if (m->new_pending) {
+      const int32_t* nc = (const int32_t*)(m->h_pin + kPinNew);
+      m->last.n_new_blocks = nc[0];
+      m->last.n_new_class_blocks = nc[1];
+      m->new_pending = false;
+    }
     float ms = 0.0f;
     if (hipEventElapsedTime(&ms, m->ev[0], m->ev[1]) == hipSuccess) m->last.splat_ms = ms;
     if (hipEventElapsedTime(&ms, m->ev[2], m->ev[3]) == hipSuccess) m->last.merge_ms = ms;
@@ -1659,8 +1699,10 @@ smki_status smki_batch_capture(smki_map* m, const float* xyz, const int32_t* lab
   if (!batch_inputs_ok(m, n, offsets, origins, S)) return SMKI_E_INVALID_ARG;
   // 1. the ordinary insert of these scans (it sizes everything)
   smki_status rc = insert_impl(m, xyz, label, nullptr, n, offsets, origins, S, free_step);
+  if (rc == SMKI_OK) rc = refresh_counts(m);   // (the insert leaves them on the device)
+  smki_scan_stats st{};
+  if (rc == SMKI_OK) rc = smki_last_scan_stats(m, &st);
   if (rc != SMKI_OK) return rc;
-  const smki_scan_stats st = m->last;
   if (st.n_hits == 0) return SMKI_E_INVALID_ARG;   // nothing to size the capture by
   smki_batch* b = new (std::nothrow) smki_batch();
   if (!b) return SMKI_E_OOM;

@@ -101,8 +101,11 @@ hipError_t launch_mark_targets(const int32_t* slot_lin, const int32_t* d_nslots,
                                int32_t DB, int32_t* mark, hipStream_t st);
 hipError_t launch_list_targets(const int32_t* mark, const int32_t* mpos, int64_t n_ext,
                                int32_t* tgt_elin, int32_t* ext2t, hipStream_t st);
+// cfirst (nullable, [K], zeroed): 1 + the first slot of each class that has one
 hipError_t launch_slot_units(const int32_t* head, const int32_t* d_nslots, int32_t max_slots,
-                             int32_t chunk, int32_t* nunits, hipStream_t st);
+                             int32_t chunk, int32_t* nunits, hipStream_t st,
+                             const int32_t* slot_lin = nullptr, int64_t n_blocks = 1,
+                             int32_t* cfirst = nullptr);
 // units of every slot, and (order, nullable) the splat's launch order
 hipError_t launch_unit_table(const int32_t* nunits, const int32_t* ustart, const int32_t* head,
                              const int32_t* slot_lin, int64_t n_blocks, int32_t chunk,
@@ -130,6 +133,9 @@ hipError_t launch_assign(const MapDev& m, const SplatArgs& a, int32_t n_targets,
 // Captured (graph) inserts: the steps that replace the host's reads of counts.
 // hdr (device): [0] 1 if the map's counts below are to be installed, [1] blocks,
 // [2] class blocks; the map's counts are set from it, the insert counters cleared.
+// counts = (n_blocks + cnt[0], n_cblocks + cnt[1]) on the stream (one thread)
+hipError_t launch_commit_counts(const int32_t* cnt, int64_t* counts, int64_t n_blocks,
+                                int64_t n_cblocks, hipStream_t st);
 hipError_t launch_batch_start(const int64_t* hdr, int64_t* counts, unsigned long long* stats,
                               hipStream_t st);
 // sc: phase-one totals (int64 free samples, then int32 hit rows); pc <- [rows,

@@ -44,9 +44,11 @@ hipError_t scan_excl_i32(const int32_t* in, int32_t* out, int64_t n, int32_t* to
 hipError_t scan_excl_pair_i64_i32(const int64_t* ina, int64_t* outa, int64_t na, int64_t* tota,
                                   const int32_t* inb, int32_t* outb, int64_t nb, int32_t* totb,
                                   void* tmp, hipStream_t st);
+// dnb (device, nullable): the second array's element count, nb then being its
+// capacity; entries past the count are neither read nor written
 hipError_t scan_excl_pair_i32(const int32_t* ina, int32_t* outa, int64_t na, int32_t* tota,
                               const int32_t* inb, int32_t* outb, int64_t nb, int32_t* totb,
-                              void* tmp, hipStream_t st);
+                              void* tmp, hipStream_t st, const int32_t* dnb = nullptr);
 
 // stable LSD radix sort of (key, value) pairs on the low `bits` bits of the
 // keys.  keys/vals are sorted in place; alt_* are scratch of the same size.

@@ -25,20 +25,17 @@ struct Pieces {
   }
 };
 
-// Start of piece p inside a unit's partial sums (p known at run time).
+// Start of piece p inside a unit's partial sums (p known at run time): the
+// x-layers before it (each spans all (y, z)), then the y-rows of its layer
+// before it, then the z-cells of its row before it.  Per axis the extents are
+// (R, B, R), and the extent before index i is 0, R or R + B.
 template <int B, int R>
 __host__ __device__ inline int pbase(int p) {
+  constexpr int DR = 2 * R + B;
   const int px = p / 9, py = (p / 3) % 3, pz = p % 3;
-  // pieces before p: full x-layers, then y-rows of this layer, then z-cells of this row
-  constexpr int E[3] = {R, B, R};
-  constexpr int S2 = (2 * R + B) * (2 * R + B);   // one x-layer spans all (y, z): sum ey * ez
-  int b = 0;
-  for (int i = 0; i < px; ++i) b += E[i] * S2;
-  const int ex = E[px];
-  for (int i = 0; i < py; ++i) b += ex * E[i] * (2 * R + B);
-  const int ey = E[py];
-  for (int i = 0; i < pz; ++i) b += ex * ey * E[i];
-  return b;
+  auto ext = [](int i) { return i == 1 ? B : R; };
+  auto before = [](int i) { return i == 0 ? 0 : (i == 1 ? R : R + B); };
+  return before(px) * DR * DR + ext(px) * before(py) * DR + ext(px) * ext(py) * before(pz);
 }
 
 template <int B, int R>

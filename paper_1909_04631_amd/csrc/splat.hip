@@ -50,20 +50,26 @@ __device__ __forceinline__ void unlin3(int64_t lin, const int32_t n[3], int32_t 
 // ---------------------------------------------------------------------------
 // target blocks and work units
 // ---------------------------------------------------------------------------
+// The per-slot kernels that run before the slot count reaches the host take a
+// grid of at most this many workgroups and stride over the count read on the
+// device (a grid sized for the capacity would mostly start workgroups that exit).
+constexpr int kSlotGrid = 1024;
+
 __global__ void k_mark_targets(const int32_t* __restrict__ slot_lin,
                                const int32_t* __restrict__ d_nslots, int32_t max_slots,
                                BucketGeom g, int3 eblo, int3 enb, int32_t DB,
                                int32_t* __restrict__ mark) {
-  const int32_t s = blockIdx.x * blockDim.x + threadIdx.x;
-  if (s >= max_slots || s >= *d_nslots) return;
-  int32_t p[3];
-  unlin3(slot_lin[s] % g.n_blocks, g.nb, p);
-  const int32_t ex = p[0] + (g.blo[0] - eblo.x), ey = p[1] + (g.blo[1] - eblo.y),
-                ez = p[2] + (g.blo[2] - eblo.z);
-  for (int dx = -DB; dx <= DB; ++dx)
-    for (int dy = -DB; dy <= DB; ++dy)
-      for (int dz = -DB; dz <= DB; ++dz)
-        mark[((int64_t)(ex + dx) * enb.y + (ey + dy)) * enb.z + (ez + dz)] = 1;
+  const int32_t n = min(max_slots, *d_nslots);
+  for (int32_t s = blockIdx.x * blockDim.x + threadIdx.x; s < n; s += gridDim.x * blockDim.x) {
+    int32_t p[3];
+    unlin3(slot_lin[s] % g.n_blocks, g.nb, p);
+    const int32_t ex = p[0] + (g.blo[0] - eblo.x), ey = p[1] + (g.blo[1] - eblo.y),
+                  ez = p[2] + (g.blo[2] - eblo.z);
+    for (int dx = -DB; dx <= DB; ++dx)
+      for (int dy = -DB; dy <= DB; ++dy)
+        for (int dz = -DB; dz <= DB; ++dz)
+          mark[((int64_t)(ex + dx) * enb.y + (ey + dy)) * enb.z + (ez + dz)] = 1;
+  }
 }
 
 __global__ void k_list_targets(const int32_t* __restrict__ mark, const int32_t* __restrict__ mpos,
@@ -78,14 +84,21 @@ __global__ void k_list_targets(const int32_t* __restrict__ mark, const int32_t* 
   }
 }
 
-// chunks of every (class, block) slot
+// chunks of every (class, block) slot (entries past the slot count are not
+// written); cfirst (nullable): 1 + the first slot of each class with slots
+// (slots are in class-major order)
 __global__ void k_slot_units(const int32_t* __restrict__ head, const int32_t* __restrict__ d_nslots,
-                             int32_t max_slots, int32_t chunk, int32_t* __restrict__ nunits) {
-  const int32_t s = blockIdx.x * blockDim.x + threadIdx.x;
-  if (s >= max_slots) return;
-  int32_t u = 0;
-  if (s < *d_nslots) u = max(0, (head[s + 1] - head[s] + chunk - 1) / chunk);
-  nunits[s] = u;
+                             int32_t max_slots, int32_t chunk, int32_t* __restrict__ nunits,
+                             const int32_t* __restrict__ slot_lin, int64_t n_blocks,
+                             int32_t* __restrict__ cfirst) {
+  const int32_t n = min(max_slots, *d_nslots);
+  for (int32_t s = blockIdx.x * blockDim.x + threadIdx.x; s < n; s += gridDim.x * blockDim.x) {
+    nunits[s] = max(0, (head[s + 1] - head[s] + chunk - 1) / chunk);
+    if (cfirst) {
+      const int32_t c = (int32_t)(slot_lin[s] / n_blocks);
+      if (s == 0 || (int32_t)(slot_lin[s - 1] / n_blocks) != c) cfirst[c] = s + 1;
+    }
+  }
 }
 
 // Work units of every slot: (first row, end row, slot, class), chunk rows each.
@@ -103,11 +116,12 @@ __global__ void k_unit_table(const int32_t* __restrict__ nunits, const int32_t* 
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int32_t s = (int32_t)(t >> 3);
   if (s >= max_slots) return;
-  const int32_t n = nunits[s];
-  if (n == 0) return;
   // (a captured insert whose slots or units outgrow their tables stores no
   // unit; its abort word is set and the map is left unchanged)
   if (*d_nslots > max_slots || *d_nunits > cap_units || *d_nunits < 0) return;
+  if (s >= *d_nslots) return;
+  const int32_t n = nunits[s];
+  if (n == 0) return;
   const int32_t b = ustart[s], h0 = head[s], h1 = head[s + 1];
   const int32_t plane = (int32_t)(slot_lin[s] / n_blocks);
   for (int32_t k = (int32_t)(t & 7); k < n; k += 8) {
@@ -952,7 +966,8 @@ hipError_t launch_mark_targets(const int32_t* slot_lin, const int32_t* d_nslots,
                                const BucketGeom& g, const int32_t eblo[3], const int32_t enb[3],
                                int32_t DB, int32_t* mark, hipStream_t st) {
   if (max_slots <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_mark_targets, dim3(nblk(max_slots, 256)), dim3(256), 0, st, slot_lin,
+  hipLaunchKernelGGL(k_mark_targets, dim3(std::min<unsigned>(nblk(max_slots, 256), kSlotGrid)),
+                     dim3(256), 0, st, slot_lin,
                      d_nslots, max_slots, g, make_int3(eblo[0], eblo[1], eblo[2]),
                      make_int3(enb[0], enb[1], enb[2]), DB, mark);
   return hipGetLastError();
@@ -967,11 +982,13 @@ hipError_t launch_list_targets(const int32_t* mark, const int32_t* mpos, int64_t
 }
 
 hipError_t launch_slot_units(const int32_t* head, const int32_t* d_nslots, int32_t max_slots,
-                             int32_t chunk, int32_t* nunits, hipStream_t st) {
+                             int32_t chunk, int32_t* nunits, hipStream_t st,
+                             const int32_t* slot_lin, int64_t n_blocks, int32_t* cfirst) {
   if (max_slots <= 0) return hipSuccess;
-  if (chunk <= 0) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(k_slot_units, dim3(nblk(max_slots, 256)), dim3(256), 0, st, head, d_nslots,
-                     max_slots, chunk, nunits);
+  if (chunk <= 0 || n_blocks <= 0 || (cfirst && !slot_lin)) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_slot_units, dim3(std::min<unsigned>(nblk(max_slots, 256), kSlotGrid)),
+                     dim3(256), 0, st, head, d_nslots, max_slots, chunk, nunits, slot_lin,
+                     n_blocks, cfirst);
   return hipGetLastError();
 }
 
