@@ -448,8 +448,8 @@ smki_status insert_csm(smki_map* m, const BucketGeom& g, const PointSet& ps,
   SMKI_HIP_TRY(hipEventRecord(m->ev[0], q));
   SMKI_HIP_TRY(hipEventRecord(m->ev[1], q));
   SMKI_HIP_TRY(launch_map_lookup(m->dev, sa, n_t, d_tslot, d_isnew, q));
-  SMKI_HIP_TRY(launch_need(m->dev, n_t, d_contrib, d_isnew, d_tslot, d_need, q));
-  SMKI_HIP_TRY(scan_excl_pair_i32(d_isnew, d_rank, n_t, d_cnt, d_need, d_cpos, ntk, d_cnt + 1,
+  SMKI_HIP_TRY(launch_need(m->dev, n_t, d_contrib, d_isnew, d_tslot, d_need, d_cpos, q));
+  SMKI_HIP_TRY(scan_excl_pair_i32(d_isnew, d_rank, n_t, d_cnt, d_cpos, d_cpos, n_t, d_cnt + 1,
                                   d_ctmp, q));
   int32_t cnt[2];
   SMKI_HIP_TRY(sync_read(m, d_cnt, sizeof(cnt), cnt));
@@ -825,8 +825,8 @@ smki_status insert_impl(smki_map* m, const float* xyz, const int32_t* label, con
   SMKI_HIP_TRY(launch_slot_info(sa, q));
   SMKI_HIP_TRY(launch_contrib(sa, false, d_contrib, q));
   SMKI_HIP_TRY(launch_map_lookup(m->dev, sa, n_t, d_tslot, d_isnew, q));
-  SMKI_HIP_TRY(launch_need(m->dev, n_t, d_contrib, d_isnew, d_tslot, d_need, q));
-  SMKI_HIP_TRY(scan_excl_pair_i32(d_isnew, d_rank, n_t, d_cnt, d_need, d_cpos, ntk, d_cnt + 1,
+  SMKI_HIP_TRY(launch_need(m->dev, n_t, d_contrib, d_isnew, d_tslot, d_need, d_cpos, q));
+  SMKI_HIP_TRY(scan_excl_pair_i32(d_isnew, d_rank, n_t, d_cnt, d_cpos, d_cpos, n_t, d_cnt + 1,
                                   d_ctmp, q));
   // no synchronisation here: the map has room for the bounds above; the
   // numbers of new blocks and class blocks stay on the device, which updates
@@ -1104,8 +1104,9 @@ smki_status batch_enqueue(smki_batch* b, hipStream_t q) {
   SMKI_HIP_TRY(launch_slot_info(sa, q));
   SMKI_HIP_TRY(launch_contrib(sa, false, d.contrib, q));
   SMKI_HIP_TRY(launch_map_lookup(m->dev, sa, (int32_t)ne, d.tslot, d.isnew, q));
-  SMKI_HIP_TRY(launch_need(m->dev, (int32_t)ne, d.contrib, d.isnew, d.tslot, d.need, q, d.si + 1));
-  SMKI_HIP_TRY(scan_excl_pair_i32(d.isnew, d.rank, ne, d.cnt, d.need, d.cpos, ntk, d.cnt + 1,
+  SMKI_HIP_TRY(launch_need(m->dev, (int32_t)ne, d.contrib, d.isnew, d.tslot, d.need, d.cpos, q,
+                           d.si + 1));
+  SMKI_HIP_TRY(scan_excl_pair_i32(d.isnew, d.rank, ne, d.cnt, d.cpos, d.cpos, ne, d.cnt + 1,
                                   d.ctmp, q));
   SMKI_HIP_TRY(launch_batch_alloc_check(d.cnt, m->dev.counts, b->pool_cap, b->cpool_cap, b->hcap,
                                         d.err, q));

@@ -118,13 +118,16 @@ hipError_t launch_merge(const SplatArgs& a, int32_t n_targets, hipStream_t st);
 // class block, and their allocation (splat.hip)
 hipError_t launch_contrib(const SplatArgs& a, bool own_block_only, int32_t* contrib,
                           hipStream_t st);
+// need [targets][K]: 1 + the rank of a class needing a class block among the
+// target's (0: none); need_t [targets]: their number
 hipError_t launch_need(const MapDev& m, int32_t n_targets, const int32_t* contrib,
                        const int32_t* is_new, const int32_t* tgt_slot, int32_t* need,
-                       hipStream_t st, const int32_t* dn_targets = nullptr);
+                       int32_t* need_t, hipStream_t st, const int32_t* dn_targets = nullptr);
 hipError_t launch_slot_info(const SplatArgs& a, hipStream_t st);
 hipError_t launch_map_lookup(const MapDev& m, const SplatArgs& a, int32_t n_targets,
                              int32_t* tgt_slot, int32_t* is_new, hipStream_t st);
 // new map blocks (slot, key, hash entry) and class blocks, in one launch
+// cpos [targets]: the exclusive scan of need_t
 hipError_t launch_assign(const MapDev& m, const SplatArgs& a, int32_t n_targets,
                          const int32_t* is_new, const int32_t* new_rank, int64_t n_old,
                          int32_t* tgt_slot, const int32_t* need, const int32_t* cpos,

@@ -40,11 +40,13 @@ namespace {
 
 inline unsigned nblk(int64_t n, int t) { return (unsigned)ceil_div_i64(n > 0 ? n : 1, t); }
 
-__device__ __forceinline__ void unlin3(int64_t lin, const int32_t n[3], int32_t out[3]) {
-  out[2] = (int32_t)(lin % n[2]);
+// Grid coordinates of a linear block index.  Every grid here has at most 2^30
+// blocks (the insert refuses larger ones), so 32-bit arithmetic suffices.
+__device__ __forceinline__ void unlin3(int32_t lin, const int32_t n[3], int32_t out[3]) {
+  out[2] = lin % n[2];
   lin /= n[2];
-  out[1] = (int32_t)(lin % n[1]);
-  out[0] = (int32_t)(lin / n[1]);
+  out[1] = lin % n[1];
+  out[0] = lin / n[1];
 }
 
 // ---------------------------------------------------------------------------
@@ -62,7 +64,7 @@ __global__ void k_mark_targets(const int32_t* __restrict__ slot_lin,
   const int32_t n = min(max_slots, *d_nslots);
   for (int32_t s = blockIdx.x * blockDim.x + threadIdx.x; s < n; s += gridDim.x * blockDim.x) {
     int32_t p[3];
-    unlin3(slot_lin[s] % g.n_blocks, g.nb, p);
+    unlin3(slot_lin[s] % (int32_t)g.n_blocks, g.nb, p);
     const int32_t ex = p[0] + (g.blo[0] - eblo.x), ey = p[1] + (g.blo[1] - eblo.y),
                   ez = p[2] + (g.blo[2] - eblo.z);
     for (int dx = -DB; dx <= DB; ++dx)
@@ -95,8 +97,8 @@ __global__ void k_slot_units(const int32_t* __restrict__ head, const int32_t* __
   for (int32_t s = blockIdx.x * blockDim.x + threadIdx.x; s < n; s += gridDim.x * blockDim.x) {
     nunits[s] = max(0, (head[s + 1] - head[s] + chunk - 1) / chunk);
     if (cfirst) {
-      const int32_t c = (int32_t)(slot_lin[s] / n_blocks);
-      if (s == 0 || (int32_t)(slot_lin[s - 1] / n_blocks) != c) cfirst[c] = s + 1;
+      const int32_t nb = (int32_t)n_blocks, c = slot_lin[s] / nb;
+      if (s == 0 || slot_lin[s - 1] / nb != c) cfirst[c] = s + 1;
     }
   }
 }
@@ -123,7 +125,7 @@ __global__ void k_unit_table(const int32_t* __restrict__ nunits, const int32_t* 
   const int32_t n = nunits[s];
   if (n == 0) return;
   const int32_t b = ustart[s], h0 = head[s], h1 = head[s + 1];
-  const int32_t plane = (int32_t)(slot_lin[s] / n_blocks);
+  const int32_t plane = slot_lin[s] / (int32_t)n_blocks;
   for (int32_t k = (int32_t)(t & 7); k < n; k += 8) {
     const int32_t r0 = h0 + k * chunk;
     units[b + k] = make_int4(r0, min(h1, r0 + chunk), s, plane);
@@ -786,9 +788,9 @@ __global__ void k_contrib(SplatArgs a, int32_t own_block_only, int32_t* __restri
   const uint32_t m = own_block_only ? (1u << 13) : (uint32_t)a.sinfo[s].z;
   if (!((m >> p) & 1u)) return;
   const int32_t plane_lin = a.slot_lin[s];
-  const int32_t y = (int32_t)(plane_lin / a.g.n_blocks);
+  const int32_t nb = (int32_t)a.g.n_blocks, y = plane_lin / nb;
   int32_t pb[3];
-  unlin3(plane_lin % a.g.n_blocks, a.g.nb, pb);
+  unlin3(plane_lin - y * nb, a.g.nb, pb);
   const int dx = p / 9 - 1, dy = (p / 3) % 3 - 1, dz = p % 3 - 1;
   const int64_t e = ((int64_t)(pb[0] + a.g.blo[0] - a.eblo[0] + dx) * a.enb[1] +
                      (pb[1] + a.g.blo[1] - a.eblo[1] + dy)) * a.enb[2] +
@@ -803,16 +805,28 @@ __global__ void k_contrib(SplatArgs a, int32_t own_block_only, int32_t* __restri
 // a class block is needed where rows arrive and the block has none for the class
 // (dnt: the device count of targets, n_targets then a capacity whose tail is
 // written 0 for the scan that follows)
+// Per target, one thread: for each class, whether it needs a class block (rows
+// reach the block and it has none yet) as need = 1 + its rank among the
+// target's classes that do (0: no), and the target's number of them in
+// need_t, whose exclusive scan places the target's class blocks.
 __global__ void k_need(MapDev m, int32_t n_targets, const int32_t* __restrict__ contrib,
                        const int32_t* __restrict__ is_new, const int32_t* __restrict__ tgt_slot,
-                       int32_t* __restrict__ need, const int32_t* __restrict__ dnt) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= (int64_t)n_targets * m.K) return;
-  const int32_t t = (int32_t)(i / m.K), k = (int32_t)(i % m.K);
-  int32_t v = 0;
-  if ((!dnt || t < *dnt) && contrib[i])
-    v = (is_new[t] || m.cslot[(int64_t)tgt_slot[t] * m.K + k] < 0) ? 1 : 0;
-  need[i] = v;
+                       int32_t* __restrict__ need, int32_t* __restrict__ need_t,
+                       const int32_t* __restrict__ dnt) {
+  const int32_t t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= n_targets) return;
+  const bool live = !dnt || t < *dnt;
+  const bool fresh = live && is_new[t] != 0;
+  const int64_t base = (int64_t)t * m.K;
+  int32_t r = 0;
+  for (int32_t k = 0; k < m.K; ++k) {
+    int32_t v = 0;
+    if (live && contrib[base + k])
+      v = (fresh || m.cslot[(int64_t)tgt_slot[t] * m.K + k] < 0) ? 1 : 0;
+    need[base + k] = v ? r + 1 : 0;
+    r += v;
+  }
+  need_t[t] = r;
 }
 
 // map-slot lookup of the active targets; new blocks are marked for allocation
@@ -843,7 +857,8 @@ __global__ void k_map_lookup(MapDev m, SplatArgs a, int32_t n_targets,
 // Allocation, one thread per (target, class): a new target block takes map
 // slot n_old + its rank (the class-0 thread records its key and inserts it in
 // the hash), and its class slots start empty; a (target, class) pair that
-// needs a class block takes class block n_cold + its rank.
+// needs a class block takes class block n_cold + cpos[t] + its rank among the
+// target's (cpos: the exclusive scan of the per-target counts).
 __global__ void k_assign(MapDev m, SplatArgs a, int32_t n_targets,
                          const int32_t* __restrict__ is_new, const int32_t* __restrict__ rank,
                          int64_t n_old, int32_t* __restrict__ tgt_slot,
@@ -860,8 +875,9 @@ __global__ void k_assign(MapDev m, SplatArgs a, int32_t n_targets,
   const int32_t t = (int32_t)(i / m.K), k = (int32_t)(i % m.K);
   const bool fresh = is_new[t] != 0;
   const int32_t slot = fresh ? (int32_t)(n_old + rank[t]) : tgt_slot[t];
-  if (fresh || need[i])
-    m.cslot[(int64_t)slot * m.K + k] = need[i] ? (int32_t)(n_cold + cpos[i]) : -1;
+  const int32_t nd = need[i];   // 1 + rank among the target's new class blocks, 0: none
+  if (fresh || nd)
+    m.cslot[(int64_t)slot * m.K + k] = nd ? (int32_t)(n_cold + cpos[t] + nd - 1) : -1;
   if (!fresh || k != 0) return;
   int32_t bt[3];
   unlin3(a.tgt_elin[t], a.enb, bt);
@@ -1046,11 +1062,10 @@ hipError_t launch_contrib(const SplatArgs& a, bool own_block_only, int32_t* cont
 
 hipError_t launch_need(const MapDev& m, int32_t n_targets, const int32_t* contrib,
                        const int32_t* is_new, const int32_t* tgt_slot, int32_t* need,
-                       hipStream_t st, const int32_t* dn_targets) {
-  const int64_t n = (int64_t)n_targets * m.K;
-  if (n <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_need, dim3(nblk(n, 256)), dim3(256), 0, st, m, n_targets, contrib, is_new,
-                     tgt_slot, need, dn_targets);
+                       int32_t* need_t, hipStream_t st, const int32_t* dn_targets) {
+  if (n_targets <= 0 || m.K <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_need, dim3(nblk(n_targets, 256)), dim3(256), 0, st, m, n_targets, contrib,
+                     is_new, tgt_slot, need, need_t, dn_targets);
   return hipGetLastError();
 }
 
