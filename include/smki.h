@@ -143,6 +143,15 @@ smki_status smki_set_class_params(smki_map *m, const float *l, const float *sigm
 smki_status smki_kernel_times(smki_map *m, int32_t max, float *splat_ms, float *merge_ms,
                               int32_t *count);
 
+/*
+ * Whether inserts record the HIP events behind smki_kernel_times and the
+ * splat / merge times of smki_last_scan_stats (on when a map is created).  Off,
+ * an insert enqueues no event (four fewer stream markers per insert); the times
+ * then cover only the inserts made while it was on.  No synchronisation.
+ * Errors: SMKI_E_INVALID_ARG (m null).
+ */
+smki_status smki_set_kernel_timing(smki_map *m, int32_t enable);
+
 /* Stream (a hipStream_t, e.g. torch.cuda.current_stream().cuda_stream) on which
  * the map enqueues its work; NULL = the default stream. */
 smki_status smki_set_stream(smki_map *m, void *hip_stream);

@@ -262,6 +262,10 @@ class SemanticMap:
         check(lib().smki_kernel_times(self._h, int(last), sp, mg, C.byref(n)), "smki_kernel_times")
         return list(sp[:n.value]), list(mg[:n.value])
 
+    def set_kernel_timing(self, on=True):
+        """Record (or not) the HIP events behind kernel_times() in later inserts."""
+        check(lib().smki_set_kernel_timing(self._h, 1 if on else 0), "smki_set_kernel_timing")
+
     def sync(self):
         check(lib().smki_sync(self._h), "smki_sync")
 

@@ -20,7 +20,7 @@ STATUS_NAMES = {
 EXPORTED = [
     "smki_status_string", "smki_create_map", "smki_destroy_map", "smki_set_class_params",
     "smki_set_stream", "smki_set_allocator", "smki_insert_scan", "smki_insert_scan_soft", "smki_insert_scans",
-    "smki_query", "smki_num_blocks", "smki_export", "smki_import", "smki_kernel_times", "smki_last_scan_stats", "smki_sync", "smki_free_samples", "smki_bucket_cells",
+    "smki_query", "smki_num_blocks", "smki_export", "smki_import", "smki_kernel_times", "smki_set_kernel_timing", "smki_last_scan_stats", "smki_sync", "smki_free_samples", "smki_bucket_cells",
     "smki_loss_workspace_bytes", "smki_loss_forward", "smki_loss_backward",
     "smki_loss_forward_classes", "smki_loss_backward_classes", "smki_loss_forward_noalloc",
     "smki_batch_capture", "smki_batch_replay", "smki_batch_destroy",
@@ -112,6 +112,8 @@ def lib():
     L.smki_last_scan_stats.argtypes = [vp, C.POINTER(ScanStats)]
     L.smki_sync.restype = st
     L.smki_sync.argtypes = [vp]
+    L.smki_set_kernel_timing.restype = st
+    L.smki_set_kernel_timing.argtypes = [vp, i32]
     L.smki_free_samples.restype = st
     L.smki_free_samples.argtypes = [vp, vp, i64, C.POINTER(C.c_float), f, i32, vp,
                                     C.POINTER(C.c_int64), vp, vp]

@@ -255,18 +255,22 @@ __global__ void k_batch_commit(const int32_t* __restrict__ cnt, int64_t* __restr
 }
 
 // An ordinary insert's new block counts, added on the device to the counts the
-// host held before it (the host reads them back at its next synchronisation).
+// host held before it (the host reads them back at its next synchronisation),
+// and copied to out (read back with the insert counters).
 __global__ void k_commit_counts(const int32_t* __restrict__ cnt, int64_t* __restrict__ counts,
-                                int64_t n_blocks, int64_t n_cblocks) {
+                                int64_t n_blocks, int64_t n_cblocks, int32_t* __restrict__ out) {
   counts[0] = n_blocks + cnt[0];
   counts[1] = n_cblocks + cnt[1];
+  out[0] = cnt[0];
+  out[1] = cnt[1];
 }
 
 }  // namespace
 
 hipError_t launch_commit_counts(const int32_t* cnt, int64_t* counts, int64_t n_blocks,
-                                int64_t n_cblocks, hipStream_t st) {
-  hipLaunchKernelGGL(k_commit_counts, dim3(1), dim3(1), 0, st, cnt, counts, n_blocks, n_cblocks);
+                                int64_t n_cblocks, int32_t* out, hipStream_t st) {
+  hipLaunchKernelGGL(k_commit_counts, dim3(1), dim3(1), 0, st, cnt, counts, n_blocks, n_cblocks,
+                     out);
   return hipGetLastError();
 }
 

@@ -134,11 +134,14 @@ void bbox_reduce(const int32_t* h, int32_t out[6]) {
 }
 constexpr size_t kBboxInts = 8 * SMKI_BBOX_COPIES;
 constexpr size_t kStatBytes = sizeof(unsigned long long) * 4 * SMKI_STAT_COPIES;
+// The device's insert counters (d_stats) are followed by one word holding an
+// insert's new block and class block counts (two int32), read back with them.
+constexpr size_t kStatAlloc = kStatBytes + sizeof(int64_t);
 // pinned staging (h_pin, 8 KiB, int64 words): [20] the counting model's row
-// count, [256, 512) the insert counters, [704, 706) the map's block counts read
-// back with an insert's first copy, [720] an insert's new block and class
-// block counts (two int32)
-constexpr int kPinCounts = 704, kPinNew = 720;
+// count, [256, 512) the insert counters and [512] the new block counts (one
+// copy of d_stats), [704, 706) the map's block counts read back with an
+// insert's first copy
+constexpr int kPinNew = 512, kPinCounts = 704;
 // Pinned staging (int64 words): [0, 2) counts, [6] error word, [20] row count,
 // [128, 256) bounding-box copies, [256, 512) counter copies.
 
@@ -180,6 +183,8 @@ struct smki_map {
   hipEvent_t evr[SMKI_TIMING_RING][4] = {};
   hipEvent_t* ev = evr[0];
   int64_t n_timed = 0;    // inserts that recorded a set
+  bool timing = true;     // inserts record the events (smki_set_kernel_timing)
+  bool last_timed = false;   // the last insert recorded a set
   // Captured inserts (smki_batch_*): the device copy of the block counts
   // (dev.counts) is current after a replay, the host's (n_blocks, n_cblocks)
   // until then; epoch changes whenever the map's storage moves (a captured
@@ -356,6 +361,19 @@ smki_status refresh_counts(smki_map* m) {
   return SMKI_OK;
 }
 
+// The HIP events around an insert's splat [0, 1] and allocation + merge [2, 3],
+// when the map records them: begin takes the next set of the ring and marks 0.
+hipError_t timing_begin(smki_map* m, hipStream_t q) {
+  if (!m->timing) return hipSuccess;
+  m->ev = m->evr[m->n_timed++ % SMKI_TIMING_RING];
+  m->last_timed = true;
+  return hipEventRecord(m->ev[0], q);
+}
+
+hipError_t timing_mark(smki_map* m, int i, hipStream_t q) {
+  return m->last_timed ? hipEventRecord(m->ev[i], q) : hipSuccess;
+}
+
 smki_status take_device_error(smki_map* m) {
   uint32_t e = 0;
   SMKI_HIP_TRY(sync_read(m, m->d_err, sizeof(uint32_t), &e));
@@ -444,9 +462,8 @@ smki_status insert_csm(smki_map* m, const BucketGeom& g, const PointSet& ps,
   SMKI_HIP_TRY(launch_list_targets(d_mark, d_mpos, n_ext, d_tgt, d_ext2t, q));
   SMKI_HIP_TRY(launch_fill_i32(d_active, n_t, 1, q));   // every row block is updated
   SMKI_HIP_TRY(launch_contrib(sa, true, d_contrib, q));
-  m->ev = m->evr[m->n_timed++ % SMKI_TIMING_RING];
-  SMKI_HIP_TRY(hipEventRecord(m->ev[0], q));
-  SMKI_HIP_TRY(hipEventRecord(m->ev[1], q));
+  SMKI_HIP_TRY(timing_begin(m, q));
+  SMKI_HIP_TRY(timing_mark(m, 1, q));
   SMKI_HIP_TRY(launch_map_lookup(m->dev, sa, n_t, d_tslot, d_isnew, q));
   SMKI_HIP_TRY(launch_need(m->dev, n_t, d_contrib, d_isnew, d_tslot, d_need, d_cpos, q));
   SMKI_HIP_TRY(scan_excl_pair_i32(d_isnew, d_rank, n_t, d_cnt, d_cpos, d_cpos, n_t, d_cnt + 1,
@@ -461,13 +478,13 @@ smki_status insert_csm(smki_map* m, const BucketGeom& g, const PointSet& ps,
   if (rc != SMKI_OK) return rc;
   rc = ensure_cpool(m, m->n_cblocks + n_cnew);
   if (rc != SMKI_OK) return rc;
-  SMKI_HIP_TRY(hipEventRecord(m->ev[2], q));
+  SMKI_HIP_TRY(timing_mark(m, 2, q));
   SMKI_HIP_TRY(launch_assign(m->dev, sa, n_t, d_isnew, d_rank, m->n_blocks, d_tslot, d_need,
                              d_cpos, m->n_cblocks, m->d_err, q));
   SMKI_HIP_TRY(launch_fill_calpha0(m->dev, m->n_cblocks, n_cnew, q));
   sa.map = m->dev;
   SMKI_HIP_TRY(launch_csm_counts(sa, keys, g.key_bits > 32, ps.n, d_vbits, n_t, q));
-  SMKI_HIP_TRY(hipEventRecord(m->ev[3], q));
+  SMKI_HIP_TRY(timing_mark(m, 3, q));
   // in-support pairs of the counting model: every row counts once (staged in
   // pinned memory, which no later insert touches before this one has synchronised)
   unsigned long long* h_rows = (unsigned long long*)(m->h_pin + 20);
@@ -513,6 +530,7 @@ smki_status insert_impl(smki_map* m, const float* xyz, const int32_t* label, con
   m->last = st;
   m->stats_pending = false;
   m->new_pending = false;
+  m->last_timed = false;
   m->stats_batch = nullptr;
   if (n == 0) return SMKI_OK;
   hipStream_t q = m->stream;
@@ -814,10 +832,9 @@ smki_status insert_impl(smki_map* m, const float* xyz, const int32_t* label, con
   // only the later kernels read is prepared while it runs
   SMKI_HIP_TRY(launch_unit_table(d_nun, d_ust, ps.head, ps.slot_lin, g.n_blocks, m->chunk, n_slots,
                                  ps.d_nslots, d_nunits, d_units, d_uorder, q));
-  m->ev = m->evr[m->n_timed++ % SMKI_TIMING_RING];
-  SMKI_HIP_TRY(hipEventRecord(m->ev[0], q));
+  SMKI_HIP_TRY(timing_begin(m, q));
   SMKI_HIP_TRY(launch_splat(sa, n_units, q));
-  SMKI_HIP_TRY(hipEventRecord(m->ev[1], q));
+  SMKI_HIP_TRY(timing_mark(m, 1, q));
   SMKI_HIP_TRY(hipMemsetAsync(d_cnt, 0,
                               (size_t)((char*)(d_contrib + std::max<int64_t>(ntk, 1)) - (char*)d_cnt),
                               q));
@@ -831,19 +848,17 @@ smki_status insert_impl(smki_map* m, const float* xyz, const int32_t* label, con
   // no synchronisation here: the map has room for the bounds above; the
   // numbers of new blocks and class blocks stay on the device, which updates
   // the map's counts there (the host reads them back at its next synchronisation)
-  SMKI_HIP_TRY(hipEventRecord(m->ev[2], q));
+  SMKI_HIP_TRY(timing_mark(m, 2, q));
   SMKI_HIP_TRY(launch_assign(m->dev, sa, n_t, d_isnew, d_rank, m->n_blocks, d_tslot, d_need,
                              d_cpos, m->n_cblocks, m->d_err, q));
   sa.map = m->dev;
   sa.n_cold = m->n_cblocks;
   sa.alpha0 = m->alpha0;
   SMKI_HIP_TRY(launch_merge(sa, n_t, q));
-  SMKI_HIP_TRY(hipEventRecord(m->ev[3], q));
-  SMKI_HIP_TRY(launch_commit_counts(d_cnt, m->dev.counts, m->n_blocks, m->n_cblocks, q));
-  SMKI_HIP_TRY(hipMemcpyAsync(m->h_pin + 256, m->d_stats, kStatBytes,
-                              hipMemcpyDeviceToHost, q));
-  SMKI_HIP_TRY(hipMemcpyAsync(m->h_pin + kPinNew, d_cnt, 2 * sizeof(int32_t),
-                              hipMemcpyDeviceToHost, q));
+  SMKI_HIP_TRY(timing_mark(m, 3, q));
+  SMKI_HIP_TRY(launch_commit_counts(d_cnt, m->dev.counts, m->n_blocks, m->n_cblocks,
+                                    (int32_t*)((char*)m->d_stats + kStatBytes), q));
+  SMKI_HIP_TRY(hipMemcpyAsync(m->h_pin + 256, m->d_stats, kStatAlloc, hipMemcpyDeviceToHost, q));
   m->host_counts_valid = false;
   m->new_pending = true;
   m->stats_pending = true;
@@ -1207,7 +1222,7 @@ smki_status smki_create_map(float res, int32_t block_size, float l, float sigma0
   m->dev.alpha0 = alpha0;
   smki_status rc = SMKI_OK;
   if (hipMalloc((void**)&m->d_err, 64) != hipSuccess ||
-      hipMalloc((void**)&m->d_stats, kStatBytes) != hipSuccess ||
+      hipMalloc((void**)&m->d_stats, kStatAlloc) != hipSuccess ||
       hipMalloc((void**)&m->d_offs, sizeof(StencilOff) * SMKI_MAX_OFFS) != hipSuccess ||
       hipMalloc((void**)&m->d_cls, sizeof(float4) * K) != hipSuccess ||
       hipMalloc((void**)&m->dev.counts, sizeof(int64_t) * 2) != hipSuccess ||
@@ -1476,8 +1491,10 @@ smki_status smki_last_scan_stats(smki_map* m, smki_scan_stats* out) {
       m->new_pending = false;
     }
     float ms = 0.0f;
-    if (hipEventElapsedTime(&ms, m->ev[0], m->ev[1]) == hipSuccess) m->last.splat_ms = ms;
-    if (hipEventElapsedTime(&ms, m->ev[2], m->ev[3]) == hipSuccess) m->last.merge_ms = ms;
+    if (m->last_timed) {
+      if (hipEventElapsedTime(&ms, m->ev[0], m->ev[1]) == hipSuccess) m->last.splat_ms = ms;
+      if (hipEventElapsedTime(&ms, m->ev[2], m->ev[3]) == hipSuccess) m->last.merge_ms = ms;
+    }
     m->stats_pending = false;
   }
   *out = m->last;
@@ -1496,6 +1513,12 @@ smki_status smki_kernel_times(smki_map* m, int32_t max, float* splat_ms, float* 
     SMKI_HIP_TRY(hipEventElapsedTime(&merge_ms[i], e[2], e[3]));
   }
   *count = (int32_t)k;
+  return SMKI_OK;
+}
+
+smki_status smki_set_kernel_timing(smki_map* m, int32_t enable) {
+  if (!m) return SMKI_E_INVALID_ARG;
+  m->timing = enable != 0;
   return SMKI_OK;
 }
 

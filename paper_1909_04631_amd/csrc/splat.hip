@@ -805,28 +805,44 @@ __global__ void k_contrib(SplatArgs a, int32_t own_block_only, int32_t* __restri
 // a class block is needed where rows arrive and the block has none for the class
 // (dnt: the device count of targets, n_targets then a capacity whose tail is
 // written 0 for the scan that follows)
-// Per target, one thread: for each class, whether it needs a class block (rows
-// reach the block and it has none yet) as need = 1 + its rank among the
-// target's classes that do (0: no), and the target's number of them in
-// need_t, whose exclusive scan places the target's class blocks.
+// Per target: for each class, whether it needs a class block (rows reach the
+// block and it has none yet) as need = 1 + its rank among the target's classes
+// that do (0: no), and the target's number of them in need_t, whose exclusive
+// scan places the target's class blocks.  G lanes per target (G >= K, a power
+// of two up to 64; the ranks from a wave ballot), else one thread per target.
+template <int G>
 __global__ void k_need(MapDev m, int32_t n_targets, const int32_t* __restrict__ contrib,
                        const int32_t* __restrict__ is_new, const int32_t* __restrict__ tgt_slot,
                        int32_t* __restrict__ need, int32_t* __restrict__ need_t,
                        const int32_t* __restrict__ dnt) {
-  const int32_t t = blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= n_targets) return;
-  const bool live = !dnt || t < *dnt;
+  const int64_t gi = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int32_t t = (int32_t)(gi / G), k = (int32_t)(gi % G);
+  const bool in = t < n_targets;                      // (uniform per group of G lanes)
+  const bool live = in && (!dnt || t < *dnt);
   const bool fresh = live && is_new[t] != 0;
   const int64_t base = (int64_t)t * m.K;
-  int32_t r = 0;
-  for (int32_t k = 0; k < m.K; ++k) {
-    int32_t v = 0;
-    if (live && contrib[base + k])
-      v = (fresh || m.cslot[(int64_t)tgt_slot[t] * m.K + k] < 0) ? 1 : 0;
-    need[base + k] = v ? r + 1 : 0;
-    r += v;
+  if (G == 1) {
+    if (!in) return;
+    int32_t r = 0;
+    for (int32_t c = 0; c < m.K; ++c) {
+      int32_t v = 0;
+      if (live && contrib[base + c])
+        v = (fresh || m.cslot[(int64_t)tgt_slot[t] * m.K + c] < 0) ? 1 : 0;
+      need[base + c] = v ? r + 1 : 0;
+      r += v;
+    }
+    need_t[t] = r;
+    return;
   }
-  need_t[t] = r;
+  bool v = false;
+  if (live && k < m.K && contrib[base + k])
+    v = fresh || m.cslot[(int64_t)tgt_slot[t] * m.K + k] < 0;
+  const int lane = threadIdx.x & (SMKI_WAVE - 1);
+  const uint64_t grp = (G == SMKI_WAVE ? ~0ull : ((1ull << G) - 1ull)) << (lane & ~(G - 1));
+  const uint64_t mk = __ballot(v) & grp;
+  if (!in) return;
+  if (k < m.K) need[base + k] = v ? __popcll(mk & ((1ull << lane) - 1ull)) + 1 : 0;
+  if (k == 0) need_t[t] = __popcll(mk);
 }
 
 // map-slot lookup of the active targets; new blocks are marked for allocation
@@ -1064,8 +1080,15 @@ hipError_t launch_need(const MapDev& m, int32_t n_targets, const int32_t* contri
                        const int32_t* is_new, const int32_t* tgt_slot, int32_t* need,
                        int32_t* need_t, hipStream_t st, const int32_t* dn_targets) {
   if (n_targets <= 0 || m.K <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_need, dim3(nblk(n_targets, 256)), dim3(256), 0, st, m, n_targets, contrib,
-                     is_new, tgt_slot, need, need_t, dn_targets);
+  if (m.K <= 32)
+    hipLaunchKernelGGL(k_need<32>, dim3(nblk((int64_t)n_targets * 32, 256)), dim3(256), 0, st, m,
+                       n_targets, contrib, is_new, tgt_slot, need, need_t, dn_targets);
+  else if (m.K <= 64)
+    hipLaunchKernelGGL(k_need<64>, dim3(nblk((int64_t)n_targets * 64, 256)), dim3(256), 0, st, m,
+                       n_targets, contrib, is_new, tgt_slot, need, need_t, dn_targets);
+  else
+    hipLaunchKernelGGL(k_need<1>, dim3(nblk(n_targets, 256)), dim3(256), 0, st, m, n_targets,
+                       contrib, is_new, tgt_slot, need, need_t, dn_targets);
   return hipGetLastError();
 }
 

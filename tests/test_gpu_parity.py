@@ -434,6 +434,14 @@ def test_kernel_times_and_reset():
     assert len(gm.kernel_times(2)[0]) == 2
     gm.reset()                      # empties the map without synchronising
     assert gm.num_blocks() == 0
+    gm.set_kernel_timing(False)     # an insert without events: same map, no new times
     gm.insert_scan(cuda(s.xyz), cuda(s.label), s.origin, p.free_step)
     torch.cuda.synchronize()
+    assert gm.kernel_times(10)[0] == sp
+    st = gm.stats()
+    assert st["n_new_blocks"] == gm.num_blocks() > 0 and st["splat_ms"] == 0.0
     compare_map(gm, oracle_map_of(sc), p.K)
+    gm.set_kernel_timing(True)
+    gm.reset()
+    gm.insert_scan(cuda(s.xyz), cuda(s.label), s.origin, p.free_step)
+    assert len(gm.kernel_times(10)[0]) == 4 and gm.stats()["splat_ms"] > 0
