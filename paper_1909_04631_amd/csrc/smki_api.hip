@@ -135,7 +135,8 @@ void bbox_reduce(const int32_t* h, int32_t out[6]) {
 constexpr size_t kBboxInts = 8 * SMKI_BBOX_COPIES;
 constexpr size_t kStatBytes = sizeof(unsigned long long) * 4 * SMKI_STAT_COPIES;
 // The device's insert counters (d_stats) are followed by one word holding an
-// insert's new block and class block counts (two int32), read back with them.
+// insert's new block and class block counts (two int32); both stay on the
+// device until smki_last_scan_stats reads them (the next insert clears them).
 constexpr size_t kStatAlloc = kStatBytes + sizeof(int64_t);
 // pinned staging (h_pin, 8 KiB, int64 words): [20] the counting model's row
 // count, [256, 512) the insert counters and [512] the new block counts (one
@@ -490,8 +491,6 @@ smki_status insert_csm(smki_map* m, const BucketGeom& g, const PointSet& ps,
   unsigned long long* h_rows = (unsigned long long*)(m->h_pin + 20);
   *h_rows = (unsigned long long)ps.n;
   SMKI_HIP_TRY(hipMemcpyAsync(m->d_stats + 1, h_rows, sizeof(*h_rows), hipMemcpyHostToDevice, q));
-  SMKI_HIP_TRY(hipMemcpyAsync(m->h_pin + 256, m->d_stats, kStatBytes,
-                              hipMemcpyDeviceToHost, q));
   m->n_blocks += n_new;
   m->n_cblocks += n_cnew;
   m->last.n_new_class_blocks = n_cnew;
@@ -858,7 +857,6 @@ smki_status insert_impl(smki_map* m, const float* xyz, const int32_t* label, con
   SMKI_HIP_TRY(timing_mark(m, 3, q));
   SMKI_HIP_TRY(launch_commit_counts(d_cnt, m->dev.counts, m->n_blocks, m->n_cblocks,
                                     (int32_t*)((char*)m->d_stats + kStatBytes), q));
-  SMKI_HIP_TRY(hipMemcpyAsync(m->h_pin + 256, m->d_stats, kStatAlloc, hipMemcpyDeviceToHost, q));
   m->host_counts_valid = false;
   m->new_pending = true;
   m->stats_pending = true;
@@ -1476,8 +1474,8 @@ smki_status smki_last_scan_stats(smki_map* m, smki_scan_stats* out) {
     m->stats_pending = false;
   }
   if (m->stats_pending) {
-    SMKI_HIP_TRY(hipStreamSynchronize(m->stream));
-    // the counters' copies, summed
+    // the last insert's counters (left on the device: no insert since), summed
+    SMKI_HIP_TRY(sync_read(m, m->d_stats, kStatAlloc, m->h_pin + 256));
     const unsigned long long* c = (const unsigned long long*)(m->h_pin + 256);
     unsigned long long s[4] = {0, 0, 0, 0};
     for (int k = 0; k < SMKI_STAT_COPIES; ++k)

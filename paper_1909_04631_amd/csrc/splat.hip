@@ -779,26 +779,31 @@ k_merge(SplatArgs a, int32_t n_targets) {
 
 // (target, class) pairs that receive rows: from each slot's non-zero pieces (or
 // the slot's own block for the counting model); idempotent flag stores.  One
-// thread per (slot, piece).
+// thread per slot: its block's coordinates once, then the targets of its
+// pieces (their lookups in flight together).
 __global__ void k_contrib(SplatArgs a, int32_t own_block_only, int32_t* __restrict__ contrib) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= (int64_t)(a.dn_slots ? min(a.n_slots, *a.dn_slots) : a.n_slots) * 27) return;
+  const int32_t s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= (a.dn_slots ? min(a.n_slots, *a.dn_slots) : a.n_slots)) return;
   if (a.abort_word && *a.abort_word) return;
-  const int32_t s = (int32_t)(i / 27), p = (int32_t)(i % 27);
-  const uint32_t m = own_block_only ? (1u << 13) : (uint32_t)a.sinfo[s].z;
-  if (!((m >> p) & 1u)) return;
+  const uint32_t mk = own_block_only ? (1u << 13) : (uint32_t)a.sinfo[s].z;
+  if (mk == 0) return;
   const int32_t plane_lin = a.slot_lin[s];
   const int32_t nb = (int32_t)a.g.n_blocks, y = plane_lin / nb;
   int32_t pb[3];
   unlin3(plane_lin - y * nb, a.g.nb, pb);
-  const int dx = p / 9 - 1, dy = (p / 3) % 3 - 1, dz = p % 3 - 1;
-  const int64_t e = ((int64_t)(pb[0] + a.g.blo[0] - a.eblo[0] + dx) * a.enb[1] +
-                     (pb[1] + a.g.blo[1] - a.eblo[1] + dy)) * a.enb[2] +
-                    (pb[2] + a.g.blo[2] - a.eblo[2] + dz);
-  const int32_t t = a.ext2t[e];
-  if (t >= 0) {
-    contrib[(int64_t)t * a.K + y] = 1;
-    a.tgt_active[t] = 1;   // some row reaches the block
+  const int32_t e0 = ((pb[0] + a.g.blo[0] - a.eblo[0]) * a.enb[1] + (pb[1] + a.g.blo[1] - a.eblo[1])) *
+                         a.enb[2] + (pb[2] + a.g.blo[2] - a.eblo[2]);
+  int32_t tt[27];
+#pragma unroll
+  for (int p = 0; p < 27; ++p) {
+    const int dx = p / 9 - 1, dy = (p / 3) % 3 - 1, dz = p % 3 - 1;
+    tt[p] = ((mk >> p) & 1u) ? a.ext2t[e0 + (dx * a.enb[1] + dy) * a.enb[2] + dz] : -1;
+  }
+#pragma unroll
+  for (int p = 0; p < 27; ++p) {
+    if (tt[p] < 0) continue;
+    contrib[(int64_t)tt[p] * a.K + y] = 1;
+    a.tgt_active[tt[p]] = 1;   // some row reaches the block
   }
 }
 
@@ -1071,7 +1076,7 @@ hipError_t launch_slot_info(const SplatArgs& a, hipStream_t st) {
 hipError_t launch_contrib(const SplatArgs& a, bool own_block_only, int32_t* contrib,
                           hipStream_t st) {
   if (a.n_slots <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_contrib, dim3(nblk((int64_t)a.n_slots * 27, 256)), dim3(256), 0, st, a,
+  hipLaunchKernelGGL(k_contrib, dim3(nblk(a.n_slots, 256)), dim3(256), 0, st, a,
                      own_block_only ? 1 : 0, contrib);
   return hipGetLastError();
 }
