@@ -143,10 +143,15 @@ constexpr size_t kStatAlloc = kStatBytes + sizeof(int64_t);
 // copy of d_stats), [704, 706) the map's block counts read back with an
 // insert's first copy
 constexpr int kPinNew = 512, kPinCounts = 704;
-// Pinned staging (int64 words): [0, 2) counts, [6] error word, [20] row count,
-// [128, 256) bounding-box copies, [256, 512) counter copies.
 
 }  // namespace
+
+// Voxel offsets that a row of a cell can reach (first octant of the cell:
+// mirrored per octant by the splat), nearest first, and their reach R.
+struct Stencil {
+  int32_t R = 0;
+  std::vector<StencilOff> offs;
+};
 
 struct smki_map {
   float res, l, sigma0, alpha0;
@@ -168,6 +173,9 @@ struct smki_map {
   StencilOff* d_offs = nullptr;
   std::vector<StencilOff> dev_offs;      // the stencil now in d_offs
   int32_t dev_R = -1;
+  // the last insert's stencil and the (l / res, rounding margin) it was built for
+  Stencil sten_cache;
+  double sten_lv = -1.0, sten_margin = -1.0;
   // kernel of each class (l_k, sigma0_k; all l and sigma0 unless set per class)
   std::vector<float> lk, s0k;
   float4* d_cls = nullptr;  // [K] (l^2, 1/l, sigma0 * Q's leading coefficient, l)
@@ -217,11 +225,6 @@ smki_status status_of_err(uint32_t e) {
 // sum_a dist(o_a, [0, 1/2])^2 < (l/res + margin)^2.  The margin covers a point
 // assigned to the neighbouring cell by the rounding of floor(x / res).  A point
 // in another octant uses the mirrored offsets.  Ordered by that distance.
-struct Stencil {
-  int32_t R = 0;
-  std::vector<StencilOff> offs;
-};
-
 Stencil make_stencil(double lv, double margin) {
   Stencil s;
   const double L = lv + margin;
@@ -619,7 +622,13 @@ smki_status insert_impl(smki_map* m, const float* xyz, const int32_t* label, con
   const bool csm = m->model == SMKI_MODEL_SCSM;
   const double lv = (double)max_class_l(m) / (double)m->res;   // the stencil of the widest kernel
   const double margin = std::max(1e-4, 4.0 * ldexp((double)maxabs + 1.0, -23));
-  const Stencil sten = csm ? Stencil{} : make_stencil(lv, margin);
+  if (!csm && (lv != m->sten_lv || margin != m->sten_margin)) {   // (rebuilt when they change)
+    m->sten_cache = make_stencil(lv, margin);
+    m->sten_lv = lv;
+    m->sten_margin = margin;
+  }
+  const Stencil empty_sten{};
+  const Stencil& sten = csm ? empty_sten : m->sten_cache;
   if (!csm && !sbki_shape_ok(m->B, sten.R)) return SMKI_E_CAPACITY;
   // target blocks: the row blocks and their neighbours (S-BKI), the row blocks (S-CSM)
   const int32_t DB = csm ? 0 : 1;
@@ -849,14 +858,13 @@ smki_status insert_impl(smki_map* m, const float* xyz, const int32_t* label, con
   // the map's counts there (the host reads them back at its next synchronisation)
   SMKI_HIP_TRY(timing_mark(m, 2, q));
   SMKI_HIP_TRY(launch_assign(m->dev, sa, n_t, d_isnew, d_rank, m->n_blocks, d_tslot, d_need,
-                             d_cpos, m->n_cblocks, m->d_err, q));
+                             d_cpos, m->n_cblocks, m->d_err, q, d_cnt,
+                             (int32_t*)((char*)m->d_stats + kStatBytes)));
   sa.map = m->dev;
   sa.n_cold = m->n_cblocks;
   sa.alpha0 = m->alpha0;
   SMKI_HIP_TRY(launch_merge(sa, n_t, q));
   SMKI_HIP_TRY(timing_mark(m, 3, q));
-  SMKI_HIP_TRY(launch_commit_counts(d_cnt, m->dev.counts, m->n_blocks, m->n_cblocks,
-                                    (int32_t*)((char*)m->d_stats + kStatBytes), q));
   m->host_counts_valid = false;
   m->new_pending = true;
   m->stats_pending = true;

@@ -127,11 +127,14 @@ hipError_t launch_slot_info(const SplatArgs& a, hipStream_t st);
 hipError_t launch_map_lookup(const MapDev& m, const SplatArgs& a, int32_t n_targets,
                              int32_t* tgt_slot, int32_t* is_new, hipStream_t st);
 // new map blocks (slot, key, hash entry) and class blocks, in one launch
-// cpos [targets]: the exclusive scan of need_t
+// cpos [targets]: the exclusive scan of need_t.  cnt (nullable, an ordinary
+// insert's new block and class block counts): also sets the map's device
+// counts to (n_old + cnt[0], n_cold + cnt[1]) and copies cnt to cnt_copy.
 hipError_t launch_assign(const MapDev& m, const SplatArgs& a, int32_t n_targets,
                          const int32_t* is_new, const int32_t* new_rank, int64_t n_old,
                          int32_t* tgt_slot, const int32_t* need, const int32_t* cpos,
-                         int64_t n_cold, uint32_t* err, hipStream_t st);
+                         int64_t n_cold, uint32_t* err, hipStream_t st,
+                         const int32_t* cnt = nullptr, int32_t* cnt_copy = nullptr);
 
 // Captured (graph) inserts: the steps that replace the host's reads of counts.
 // hdr (device): [0] 1 if the map's counts below are to be installed, [1] blocks,

@@ -884,11 +884,18 @@ __global__ void k_assign(MapDev m, SplatArgs a, int32_t n_targets,
                          const int32_t* __restrict__ is_new, const int32_t* __restrict__ rank,
                          int64_t n_old, int32_t* __restrict__ tgt_slot,
                          const int32_t* __restrict__ need, const int32_t* __restrict__ cpos,
-                         int64_t n_cold, uint32_t* __restrict__ err) {
+                         int64_t n_cold, uint32_t* __restrict__ err,
+                         const int32_t* __restrict__ cnt, int32_t* __restrict__ cnt_copy) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (a.dn_targets) n_targets = min(n_targets, *a.dn_targets);
   if (i >= (int64_t)n_targets * m.K) return;
   if (a.abort_word && *a.abort_word) return;   // nothing is written to the map
+  if (cnt && i == 0) {   // an ordinary insert: the map's counts after it, on the device
+    m.counts[0] = n_old + cnt[0];
+    m.counts[1] = n_cold + cnt[1];
+    cnt_copy[0] = cnt[0];
+    cnt_copy[1] = cnt[1];
+  }
   if (a.dn_targets) {   // the map's counts before this insert, from the device
     n_old = m.counts[0];
     n_cold = m.counts[1];
@@ -1059,11 +1066,13 @@ hipError_t launch_map_lookup(const MapDev& m, const SplatArgs& a, int32_t n_targ
 hipError_t launch_assign(const MapDev& m, const SplatArgs& a, int32_t n_targets,
                          const int32_t* is_new, const int32_t* new_rank, int64_t n_old,
                          int32_t* tgt_slot, const int32_t* need, const int32_t* cpos,
-                         int64_t n_cold, uint32_t* err, hipStream_t st) {
+                         int64_t n_cold, uint32_t* err, hipStream_t st, const int32_t* cnt,
+                         int32_t* cnt_copy) {
   const int64_t n = (int64_t)n_targets * m.K;
-  if (n <= 0) return hipSuccess;
+  if (n <= 0)
+    return cnt ? launch_commit_counts(cnt, m.counts, n_old, n_cold, cnt_copy, st) : hipSuccess;
   hipLaunchKernelGGL(k_assign, dim3(nblk(n, 256)), dim3(256), 0, st, m, a, n_targets, is_new,
-                     new_rank, n_old, tgt_slot, need, cpos, n_cold, err);
+                     new_rank, n_old, tgt_slot, need, cpos, n_cold, err, cnt, cnt_copy);
   return hipGetLastError();
 }
 
