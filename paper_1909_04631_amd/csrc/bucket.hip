@@ -274,17 +274,33 @@ __global__ void k_free_keys(const float* __restrict__ xyz, int64_t n,
   // The beams of this workgroup's samples lie between the beam of its first
   // sample and the beam of the next workgroup's first sample (wgbeam, written
   // by k_hit_keys); every sample searches only between them.
+  // The beam offsets of that range go to LDS first when they fit (one round of
+  // global loads instead of a chain of them per search).
+  constexpr int MAXB = FREE_WG;
+  __shared__ int64_t soff[MAXB];
   const int64_t nf = dcnt ? dcnt[2] : nf_cap;             // (launch sized for nf_cap)
   const int64_t out_base = dcnt ? dcnt[1] : out_base_h;   // free samples follow the hits
   const int64_t nwg = (nf + FREE_WG - 1) / FREE_WG;
+  if ((int64_t)blockIdx.x >= nwg) return;   // (the whole workgroup)
   const int64_t f = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (f >= nf) return;
   int64_t lo = wgbeam[blockIdx.x];
   int64_t hi = (int64_t)blockIdx.x + 1 < nwg ? wgbeam[blockIdx.x + 1] : n - 1;
-  while (lo < hi) {
-    const int64_t mid = (lo + hi + 1) >> 1;
-    if (off[mid] <= f) lo = mid; else hi = mid - 1;
+  if (hi - lo < MAXB) {   // (the same range for the whole workgroup)
+    if (threadIdx.x <= hi - lo) soff[threadIdx.x] = off[lo + threadIdx.x];
+    __syncthreads();
+    int32_t a = 0, c = (int32_t)(hi - lo);
+    while (a < c) {
+      const int32_t mid = (a + c + 1) >> 1;
+      if (soff[mid] <= f) a = mid; else c = mid - 1;
+    }
+    lo += a;
+  } else {
+    while (lo < hi) {
+      const int64_t mid = (lo + hi + 1) >> 1;
+      if (off[mid] <= f) lo = mid; else hi = mid - 1;
+    }
   }
+  if (f >= nf) return;
   const int64_t i = lo;
   const int64_t j = f - off[i] + 1;
   const int32_t s = scan_of(scan_off, S, i);
