@@ -62,6 +62,7 @@ def test_host_argument_checks_need_no_gpu(lib):
     hb = C.c_void_p()
     assert lib.smki_batch_capture(None, None, None, None, None, 1, 0.3, 0.25, C.byref(hb)) == -1
     assert lib.smki_query(None, None, 0, None, None, None, None, None) == -1
+    assert lib.smki_set_kernel_timing(None, 0) == -1
     n = C.c_int64()
     o = (C.c_float * 3)(0, 0, 0)
     assert lib.smki_free_samples(None, None, -1, o, 0.3, 4, None, C.byref(n), None, None) == -1
