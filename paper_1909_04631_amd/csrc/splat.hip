@@ -114,22 +114,24 @@ __global__ void k_unit_table(const int32_t* __restrict__ nunits, const int32_t* 
                              const int32_t* __restrict__ d_nslots,
                              const int32_t* __restrict__ d_nunits, int4* __restrict__ units,
                              int32_t* __restrict__ order, int32_t cap_units) {
-  // eight threads per slot, taking its units k = j, j + 8, ...
-  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const int32_t s = (int32_t)(t >> 3);
-  if (s >= max_slots) return;
+  // eight threads per slot, taking its units k = j, j + 8, ...; the grid
+  // strides over the slots (a multiple of eight threads)
   // (a captured insert whose slots or units outgrow their tables stores no
   // unit; its abort word is set and the map is left unchanged)
   if (*d_nslots > max_slots || *d_nunits > cap_units || *d_nunits < 0) return;
-  if (s >= *d_nslots) return;
-  const int32_t n = nunits[s];
-  if (n == 0) return;
-  const int32_t b = ustart[s], h0 = head[s], h1 = head[s + 1];
-  const int32_t plane = slot_lin[s] / (int32_t)n_blocks;
-  for (int32_t k = (int32_t)(t & 7); k < n; k += 8) {
-    const int32_t r0 = h0 + k * chunk;
-    units[b + k] = make_int4(r0, min(h1, r0 + chunk), s, plane);
-    if (order) order[k + 1 < n ? b - s + k : (*d_nunits - *d_nslots) + s] = b + k;
+  const int32_t ns = *d_nslots;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; (t >> 3) < ns; t += stride) {
+    const int32_t s = (int32_t)(t >> 3);
+    const int32_t n = nunits[s];
+    if (n == 0) continue;
+    const int32_t b = ustart[s], h0 = head[s], h1 = head[s + 1];
+    const int32_t plane = slot_lin[s] / (int32_t)n_blocks;
+    for (int32_t k = (int32_t)(t & 7); k < n; k += 8) {
+      const int32_t r0 = h0 + k * chunk;
+      units[b + k] = make_int4(r0, min(h1, r0 + chunk), s, plane);
+      if (order) order[k + 1 < n ? b - s + k : (*d_nunits - *d_nslots) + s] = b + k;
+    }
   }
 }
 
@@ -1041,7 +1043,9 @@ hipError_t launch_unit_table(const int32_t* nunits, const int32_t* ustart, const
                              int32_t max_slots, const int32_t* d_nslots, const int32_t* d_nunits,
                              int4* units, int32_t* order, hipStream_t st, int32_t cap_units) {
   if (max_slots <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_unit_table, dim3(nblk((int64_t)max_slots * 8, 256)), dim3(256), 0, st,
+  hipLaunchKernelGGL(k_unit_table,
+                     dim3(std::min<unsigned>(nblk((int64_t)max_slots * 8, 256), 8 * kSlotGrid)),
+                     dim3(256), 0, st,
                      nunits, ustart, head, slot_lin, n_blocks, chunk, max_slots, d_nslots, d_nunits,
                      units, order, cap_units);
   return hipGetLastError();
