@@ -291,6 +291,9 @@ smki_status smki_export(smki_map *m, int64_t capacity, int64_t *n_blocks, int32_
  * if n * K > 2^30, SMKI_E_OOM; on any error the map is left unchanged. */
 smki_status smki_import(smki_map *m, int64_t n, const int32_t *block_ijk, const float *alpha);
 
+/* The counters of the last insert or replay (smki_scan_stats).  They stay on
+ * the device until asked for: the first call after an insert synchronises the
+ * map's stream and reads them back.  Errors: SMKI_E_INVALID_ARG. */
 smki_status smki_last_scan_stats(smki_map *m, smki_scan_stats *out);
 
 /* Wait for the map's stream; returns a deferred device error if one occurred. */
