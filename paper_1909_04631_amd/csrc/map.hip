@@ -256,7 +256,8 @@ __global__ void k_batch_commit(const int32_t* __restrict__ cnt, int64_t* __restr
 
 // An ordinary insert's new block counts, added on the device to the counts the
 // host held before it (the host reads them back at its next synchronisation),
-// and copied to out (read back with the insert counters).
+// and copied to out (read back with the insert counters).  The allocation
+// kernel does the same when it runs; this serves an insert with no targets.
 __global__ void k_commit_counts(const int32_t* __restrict__ cnt, int64_t* __restrict__ counts,
                                 int64_t n_blocks, int64_t n_cblocks, int32_t* __restrict__ out) {
   counts[0] = n_blocks + cnt[0];

@@ -135,13 +135,14 @@ hipError_t launch_assign(const MapDev& m, const SplatArgs& a, int32_t n_targets,
                          int32_t* tgt_slot, const int32_t* need, const int32_t* cpos,
                          int64_t n_cold, uint32_t* err, hipStream_t st,
                          const int32_t* cnt = nullptr, int32_t* cnt_copy = nullptr);
+// An ordinary insert without allocations: counts = (n_blocks + cnt[0],
+// n_cblocks + cnt[1]), out = cnt[0, 2) (one thread)
+hipError_t launch_commit_counts(const int32_t* cnt, int64_t* counts, int64_t n_blocks,
+                                int64_t n_cblocks, int32_t* out, hipStream_t st);
 
 // Captured (graph) inserts: the steps that replace the host's reads of counts.
 // hdr (device): [0] 1 if the map's counts below are to be installed, [1] blocks,
 // [2] class blocks; the map's counts are set from it, the insert counters cleared.
-// counts = (n_blocks + cnt[0], n_cblocks + cnt[1]), out = cnt[0, 2) (one thread)
-hipError_t launch_commit_counts(const int32_t* cnt, int64_t* counts, int64_t n_blocks,
-                                int64_t n_cblocks, int32_t* out, hipStream_t st);
 hipError_t launch_batch_start(const int64_t* hdr, int64_t* counts, unsigned long long* stats,
                               hipStream_t st);
 // sc: phase-one totals (int64 free samples, then int32 hit rows); pc <- [rows,

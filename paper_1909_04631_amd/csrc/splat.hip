@@ -809,14 +809,13 @@ __global__ void k_contrib(SplatArgs a, int32_t own_block_only, int32_t* __restri
   }
 }
 
-// a class block is needed where rows arrive and the block has none for the class
-// (dnt: the device count of targets, n_targets then a capacity whose tail is
-// written 0 for the scan that follows)
 // Per target: for each class, whether it needs a class block (rows reach the
 // block and it has none yet) as need = 1 + its rank among the target's classes
 // that do (0: no), and the target's number of them in need_t, whose exclusive
 // scan places the target's class blocks.  G lanes per target (G >= K, a power
 // of two up to 64; the ranks from a wave ballot), else one thread per target.
+// (dnt: the device count of targets, n_targets then a capacity whose tail is
+// written 0 for the scan that follows)
 template <int G>
 __global__ void k_need(MapDev m, int32_t n_targets, const int32_t* __restrict__ contrib,
                        const int32_t* __restrict__ is_new, const int32_t* __restrict__ tgt_slot,
