@@ -843,11 +843,10 @@ smki_status insert_impl(smki_map* m, const float* xyz, const int32_t* label, con
   SMKI_HIP_TRY(timing_begin(m, q));
   SMKI_HIP_TRY(launch_splat(sa, n_units, q));
   SMKI_HIP_TRY(timing_mark(m, 1, q));
-  SMKI_HIP_TRY(hipMemsetAsync(d_cnt, 0,
-                              (size_t)((char*)(d_contrib + std::max<int64_t>(ntk, 1)) - (char*)d_cnt),
-                              q));
-  SMKI_HIP_TRY(launch_list_targets(d_mark, d_mpos, n_ext, d_tgt, d_ext2t, q));
-  SMKI_HIP_TRY(launch_slot_info(sa, q));
+  // the counts, active flags and contribution flags cleared, the targets
+  // listed and the slots summarised, in one launch
+  SMKI_HIP_TRY(launch_after_splat(sa, d_cnt, (int64_t)(d_contrib + std::max<int64_t>(ntk, 1) - d_cnt),
+                                  d_mark, d_mpos, n_ext, d_tgt, d_ext2t, q));
   SMKI_HIP_TRY(launch_contrib(sa, false, d_contrib, q));
   SMKI_HIP_TRY(launch_map_lookup(m->dev, sa, n_t, d_tslot, d_isnew, q));
   SMKI_HIP_TRY(launch_need(m->dev, n_t, d_contrib, d_isnew, d_tslot, d_need, d_cpos, q));

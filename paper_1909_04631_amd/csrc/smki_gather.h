@@ -124,6 +124,11 @@ hipError_t launch_need(const MapDev& m, int32_t n_targets, const int32_t* contri
                        const int32_t* is_new, const int32_t* tgt_slot, int32_t* need,
                        int32_t* need_t, hipStream_t st, const int32_t* dn_targets = nullptr);
 hipError_t launch_slot_info(const SplatArgs& a, hipStream_t st);
+// one launch: clear nclear words from clr, then (independently) the target list
+// of launch_list_targets and the slot summaries of launch_slot_info
+hipError_t launch_after_splat(const SplatArgs& a, int32_t* clr, int64_t nclear,
+                              const int32_t* mark, const int32_t* mpos, int64_t n_ext,
+                              int32_t* tgt_elin, int32_t* ext2t, hipStream_t st);
 hipError_t launch_map_lookup(const MapDev& m, const SplatArgs& a, int32_t n_targets,
                              int32_t* tgt_slot, int32_t* is_new, hipStream_t st);
 // new map blocks (slot, key, hash entry) and class blocks, in one launch

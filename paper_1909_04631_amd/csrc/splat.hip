@@ -74,16 +74,22 @@ __global__ void k_mark_targets(const int32_t* __restrict__ slot_lin,
   }
 }
 
-__global__ void k_list_targets(const int32_t* __restrict__ mark, const int32_t* __restrict__ mpos,
-                               int64_t n, int32_t* __restrict__ tgt, int32_t* __restrict__ ext2t) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
+// entry i of the extended grid: its target index, and the target's grid index
+__device__ __forceinline__ void list_target(const int32_t* __restrict__ mark,
+                                            const int32_t* __restrict__ mpos, int64_t i,
+                                            int32_t* __restrict__ tgt, int32_t* __restrict__ ext2t) {
   if (mark[i]) {
     tgt[mpos[i]] = (int32_t)i;
     ext2t[i] = mpos[i];
   } else {
     ext2t[i] = -1;
   }
+}
+
+__global__ void k_list_targets(const int32_t* __restrict__ mark, const int32_t* __restrict__ mpos,
+                               int64_t n, int32_t* __restrict__ tgt, int32_t* __restrict__ ext2t) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) list_target(mark, mpos, i, tgt, ext2t);
 }
 
 // chunks of every (class, block) slot (entries past the slot count are not
@@ -549,8 +555,7 @@ __global__ void __launch_bounds__(SMKI_WAVE) k_splat(SplatArgs a) {
 // unit's own pieces.
 // Eight threads per slot (one 8-lane group of a wavefront, active or exited
 // together) OR the masks of units j, j + 8, ...
-__global__ void k_slot_info(SplatArgs a) {
-  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+__device__ __forceinline__ void slot_info(const SplatArgs& a, int64_t t) {
   const int32_t s = (int32_t)(t >> 3), j = (int32_t)(t & 7);
   if (s >= (a.dn_slots ? min(a.n_slots, *a.dn_slots) : a.n_slots)) return;
   if (a.abort_word && *a.abort_word) return;   // (the unit tables may be stale)
@@ -561,6 +566,29 @@ __global__ void k_slot_info(SplatArgs a) {
   m |= __shfl_xor(m, 2, 8);
   m |= __shfl_xor(m, 4, 8);
   if (j == 0) a.sinfo[s] = make_int4(u0, nu, (int32_t)m, nu > 0 ? (int32_t)a.umask[u0] : 0);
+}
+
+__global__ void k_slot_info(SplatArgs a) {
+  slot_info(a, (int64_t)blockIdx.x * blockDim.x + threadIdx.x);
+}
+
+// After the splat of an ordinary insert, three independent steps in one
+// launch: workgroups [0, gc) clear nclear words from clr (the allocation's
+// counts and flags), [gc, gc + gl) list the targets (k_list_targets), the rest
+// summarise the slots' pieces (k_slot_info).  (Whole workgroups take one step.)
+__global__ void k_after_splat(SplatArgs a, int32_t* __restrict__ clr, int64_t nclear, int64_t gc,
+                              const int32_t* __restrict__ mark, const int32_t* __restrict__ mpos,
+                              int64_t n_ext, int64_t gl, int32_t* __restrict__ tgt,
+                              int32_t* __restrict__ ext2t) {
+  const int64_t b = blockIdx.x;
+  if (b < gc) {
+    for (int64_t i = b * blockDim.x + threadIdx.x; i < nclear; i += gc * blockDim.x) clr[i] = 0;
+  } else if (b < gc + gl) {
+    const int64_t i = (b - gc) * blockDim.x + threadIdx.x;
+    if (i < n_ext) list_target(mark, mpos, i, tgt, ext2t);
+  } else {
+    slot_info(a, (b - gc - gl) * blockDim.x + threadIdx.x);
+  }
 }
 
 // Partial sum at element off of unit w's region; unit w < 0 reads the zero
@@ -1076,6 +1104,17 @@ hipError_t launch_assign(const MapDev& m, const SplatArgs& a, int32_t n_targets,
     return cnt ? launch_commit_counts(cnt, m.counts, n_old, n_cold, cnt_copy, st) : hipSuccess;
   hipLaunchKernelGGL(k_assign, dim3(nblk(n, 256)), dim3(256), 0, st, m, a, n_targets, is_new,
                      new_rank, n_old, tgt_slot, need, cpos, n_cold, err, cnt, cnt_copy);
+  return hipGetLastError();
+}
+
+hipError_t launch_after_splat(const SplatArgs& a, int32_t* clr, int64_t nclear,
+                              const int32_t* mark, const int32_t* mpos, int64_t n_ext,
+                              int32_t* tgt_elin, int32_t* ext2t, hipStream_t st) {
+  const int64_t gc = std::min<int64_t>(nblk(nclear, 256), 2048);
+  const int64_t gl = n_ext > 0 ? nblk(n_ext, 256) : 0;
+  const int64_t gs = a.n_slots > 0 ? nblk((int64_t)a.n_slots * 8, 256) : 0;
+  hipLaunchKernelGGL(k_after_splat, dim3((unsigned)(gc + gl + gs)), dim3(256), 0, st, a, clr,
+                     nclear, gc, mark, mpos, n_ext, gl, tgt_elin, ext2t);
   return hipGetLastError();
 }
 
