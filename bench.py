@@ -68,7 +68,8 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-extras", action="store_true", help="skip the differentiable-form lines")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the differentiable-form lines and the steps without timing events")
     ap.add_argument("--no-variants", action="store_true",
                     help="skip the S-CSM, extended-block and soft-measurement lines")
     ap.add_argument("--no-batched", action="store_true", help="skip the 64-scan batched line")
@@ -149,6 +150,21 @@ def main():
     assert len(splat_ms) == min(args.steps, 64)
     ev_ms = e0.elapsed_time(e1)
     ms = max(ev_ms, 1e3 * wall) / args.steps
+    # the same steps without the insert's timing events (outside the timed
+    # region; what an insert costs when nobody asks for kernel times; not in
+    # the profiling runs, which trace the timed steps only)
+    ms_no_events = None
+    if not args.no_extras:
+        m.set_kernel_timing(False)
+        f0, f1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        f0.record(stream)
+        for i in range(args.steps):
+            step()
+        f1.record(stream)
+        torch.cuda.synchronize()
+        m.set_kernel_timing(True)
+        ms_no_events = f0.elapsed_time(f1) / args.steps
     log(f"[bench] {args.steps} steps: {ms:.3f} ms/step (events {ev_ms / args.steps:.3f}, "
         f"wall {1e3 * wall / args.steps:.3f}); splat {np.mean(splat_ms):.3f} ms, "
         f"alloc+merge {np.mean(merge_ms):.3f} ms")
@@ -197,6 +213,7 @@ def main():
         "step_roofline": {"t_roof_ms": 1e3 * t_roof, "t_step_ms": ms, "frac": 1e3 * t_roof / ms,
                           "algorithmic_bytes": b_alg, "algorithmic_valu_ops": OPS_PER_PAIR * P},
         "hbm": {"peak_GBps": HBM_PEAK / 1e9, "copy_GBps": copy_bw / 1e9},
+        "ms_per_step_without_timing_events": ms_no_events,
     }
 
     out["roofline"]["traffic"] = splat_traffic()
